@@ -1,0 +1,501 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test targets a part of the oracle that a plausible mistake would break:
+closed forms (one isotropic Gaussian, two stacked Gaussians), a Monte-Carlo
+check of the projected covariance, invariants of front-to-back compositing
+(Alg. 1 stage 3), symmetry under a rotation about the vertical axis, a dense
+twin written differently, special MLP weights that reduce the network to known
+functions of the Fourier encoding (Sec. 4.3.2 eq. rx_enc), and central finite
+differences of the forward for the reverse mode.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+from oracle import oracle as O
+from oracle import twin
+from paper_2605_24290_amd import scenes as S
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ALPHA = 1.0 / 255.0
+
+
+def one_scene(means, ls, quats, logits, radiance=None, features=None):
+    return S.Scene(np.asarray(means, dtype=np.float64).reshape(-1, 3),
+                   np.asarray(ls, dtype=np.float64).reshape(-1, 3),
+                   np.asarray(quats, dtype=np.float64).reshape(-1, 4),
+                   np.asarray(logits, dtype=np.float64).reshape(-1),
+                   None if radiance is None else np.asarray(radiance, dtype=np.float64).reshape(-1, 2),
+                   None if features is None else np.asarray(features, dtype=np.float64).reshape(-1, 32))
+
+
+# ---------------------------------------------------------------- Pin-1
+def test_isotropic_gaussian_closed_form(oracle_lib):
+    """One isotropic Gaussian: the projected covariance is diagonal,
+    sigma^2 / (h^2 daz^2) + 0.3 and sigma^2 / (rho^2 del^2) + 0.3, and every
+    pixel holds min(0.99, o exp(-q/2)) s when that weight is at least 1/255."""
+    grid = S.Grid(18, 36, -math.pi / 2, math.pi / 18)
+    p = np.array([1.3, 0.8, 0.6])
+    sig = 0.35
+    logit = 0.7
+    s = np.array([0.8, -0.3])
+    sc = one_scene(p, [math.log(sig)] * 3, [1, 0, 0, 0], [logit], radiance=s)
+    out = O.render(sc, grid, np.zeros((1, 3)), np.zeros((1, 3)), [0])
+    h = math.hypot(p[0], p[1])
+    rho2 = float(p @ p)
+    az = math.atan2(p[1], p[0])
+    el = math.atan2(p[2], h)
+    u = az / grid.del_az - 0.5
+    v = (el - grid.el0) / grid.del_el - 0.5
+    A = sig ** 2 / (h ** 2 * grid.del_az ** 2) + 0.3
+    Cc = sig ** 2 / (rho2 * grid.del_el ** 2) + 0.3
+    o = 1.0 / (1.0 + math.exp(-logit))
+    exp_C = np.zeros((2, grid.H, grid.W))
+    for i in range(grid.H):
+        for c in range(grid.W):
+            du = (c - u + grid.W / 2) % grid.W - grid.W / 2
+            dv = i - v
+            w = min(0.99, o * math.exp(-0.5 * (du * du / A + dv * dv / Cc)))
+            if w >= ALPHA:
+                exp_C[:, i, c] = w * s
+    assert np.abs(out["C"][0] - exp_C).max() < 1e-12
+    assert (out["C"][0, 0] != 0).sum() > 10
+    assert abs(out["power"][0] - (exp_C ** 2).sum()) < 1e-11
+    kb, near, pr = O.project(sc, grid, np.zeros((1, 3)))
+    assert abs(pr[0, 0, 6] - A) < 1e-12 and abs(pr[0, 0, 8] - Cc) < 1e-12 and abs(pr[0, 0, 7]) < 1e-12
+
+
+# ---------------------------------------------------------------- Pin-1b
+def test_projected_covariance_monte_carlo(oracle_lib):
+    """Anisotropic, rotated Gaussians: the projected pixel covariance minus the
+    0.3 px^2 dilation matches the covariance of (u, v) over samples drawn from
+    the 3-D Gaussian and mapped through the exact angle map.  This fixes the
+    Jacobian's signs and layout, the (w,x,y,z) quaternion convention (scipy's
+    rotation builds the samples) and the daz / del scaling."""
+    rng = np.random.default_rng(11)
+    grid = S.Grid(90, 360, 0.0, math.pi / 180)
+    c = np.array([0.2, -0.1, 0.3])
+    for trial in range(4):
+        p = c + rng.uniform(-3, 3, 3)
+        p[2] = c[2] + abs(p[2] - c[2]) + 0.5
+        ls = np.log(rng.uniform(0.004, 0.02, 3))
+        q = rng.normal(size=4)
+        q /= np.linalg.norm(q)
+        sc = one_scene(p, ls, q, [0.0], radiance=[1, 0])
+        _, _, pr = O.project(sc, grid, c[None])
+        R = Rotation.from_quat(q[[1, 2, 3, 0]]).as_matrix()
+        n = 400_000
+        x = p + (rng.normal(size=(n, 3)) * np.exp(ls)) @ R.T
+        d = x - c
+        az = np.mod(np.arctan2(d[:, 1], d[:, 0]), 2 * math.pi)
+        el = np.arctan2(d[:, 2], np.hypot(d[:, 0], d[:, 1]))
+        uv = np.stack([az / grid.del_az, el / grid.del_el], 1)
+        cov = np.cov(uv.T)
+        A, B, Cc = pr[0, 0, 6] - 0.3, pr[0, 0, 7], pr[0, 0, 8] - 0.3
+        scale = math.sqrt(A * Cc)
+        assert abs(cov[0, 0] - A) < 0.02 * A
+        assert abs(cov[1, 1] - Cc) < 0.02 * Cc
+        assert abs(cov[0, 1] - B) < 0.02 * scale
+        # conic is the inverse of the dilated covariance
+        con = np.array([[pr[0, 0, 2], pr[0, 0, 3]], [pr[0, 0, 3], pr[0, 0, 4]]])
+        cv = np.array([[pr[0, 0, 6], pr[0, 0, 7]], [pr[0, 0, 7], pr[0, 0, 8]]])
+        assert np.abs(con @ cv - np.eye(2)).max() < 1e-12
+
+
+# ---------------------------------------------------------------- Pin-2
+def test_two_gaussians_order(oracle_lib):
+    """Two Gaussians on one line of sight: the pixel holds
+    w1 s1 + (1 - w1) w2 s2 with 1 the nearer; moving the near one behind the
+    far one swaps the roles."""
+    grid = S.Grid(18, 36, -math.pi / 2, math.pi / 18)
+    d = np.array([1.0, 0.7, 0.4])
+    d /= np.linalg.norm(d)
+    s1, s2 = np.array([1.0, 0.5]), np.array([-0.4, 0.9])
+    for near_first in (True, False):
+        r1, r2 = (1.5, 2.5) if near_first else (3.5, 2.5)
+        sc = one_scene([r1 * d, r2 * d], [[-1.2] * 3] * 2, [[1, 0, 0, 0]] * 2, [0.5, 1.0],
+                       radiance=[s1, s2])
+        out = O.render(sc, grid, np.zeros((1, 3)), np.zeros((1, 3)), [0])
+        _, _, pr = O.project(sc, grid, np.zeros((1, 3)))
+        i, c = int(round(pr[0, 0, 1])), int(round(pr[0, 0, 0]))
+
+        def wgt(k):
+            du = c - pr[0, k, 0]
+            dv = i - pr[0, k, 1]
+            q = pr[0, k, 2] * du * du + 2 * pr[0, k, 3] * du * dv + pr[0, k, 4] * dv * dv
+            return min(0.99, pr[0, k, 5] * math.exp(-0.5 * q))
+        w1, w2 = wgt(0), wgt(1)
+        assert w1 > ALPHA and w2 > ALPHA
+        if near_first:
+            expect = w1 * s1 + (1 - w1) * w2 * s2
+        else:
+            expect = w2 * s2 + (1 - w2) * w1 * s1
+        assert np.abs(out["C"][0, :, i, c] - expect).max() < 1e-13
+
+
+# ---------------------------------------------------------------- Pin-3 / Pin-4
+def _random_scene(seed, K, box=(3.0, 3.0, 2.0), mlp=False, ls_mu=-1.2):
+    wl = S.make_workload(S.Preset("t", K, 3, box, ls_mu, 0.3, S.GRID_90x180, mlp), seed=seed)
+    return wl
+
+
+def test_telescoping_and_transmittance_bounds(oracle_lib):
+    """With s = (1, 0) for every Gaussian, Re C = 1 - T_final exactly (the
+    weights T_k w_k telescope); T_final lies in (0, 1]; |C| <= max|s| (1 - T);
+    a pixel composited at least once has T_final < 1."""
+    grid = S.Grid(18, 36, -math.pi / 2, math.pi / 18)
+    wl = _random_scene(3, 60)
+    sc = wl.scene
+    ones = S.Scene(sc.means, sc.log_scales, sc.quats, sc.logits,
+                   radiance=np.tile(np.array([[1.0, 0.0]], np.float32), (sc.K, 1)))
+    cen, rv = O.views_for("rx", wl.tx, wl.rx)
+    out = O.render(ones, grid, cen, wl.rx, rv)
+    assert np.abs(out["C"][:, 0] - (1 - out["T_final"])).max() < 1e-12
+    assert np.abs(out["C"][:, 1]).max() == 0.0
+    T = out["T_final"]
+    assert (T > 0).all() and (T <= 1).all()
+    assert out["ncomp"].max() > 3
+    out2 = O.render(sc, grid, cen, wl.rx, rv)
+    smax = np.abs(sc.radiance.astype(np.float64)).max() * math.sqrt(2)
+    mag = np.hypot(out2["C"][:, 0], out2["C"][:, 1])
+    assert (mag <= smax * (1 - out2["T_final"]) + 1e-12).all()
+    assert ((out2["ncomp"] > 0) == (out2["T_final"] < 1)).all()
+
+
+# ---------------------------------------------------------------- Pin-5
+def test_zero_opacity_gaussians_change_nothing(oracle_lib):
+    wl = _random_scene(4, 40)
+    sc = wl.scene
+    grid = S.Grid(18, 36, -math.pi / 2, math.pi / 18)
+    rng = np.random.default_rng(1)
+    extra = 25
+    sc2 = S.Scene(np.concatenate([sc.means, rng.uniform(0, 3, (extra, 3)).astype(np.float32)]),
+                  np.concatenate([sc.log_scales, np.full((extra, 3), -0.5, np.float32)]),
+                  np.concatenate([sc.quats, np.tile([[1, 0, 0, 0]], (extra, 1)).astype(np.float32)]),
+                  np.concatenate([sc.logits, np.full(extra, -30.0, np.float32)]),
+                  radiance=np.concatenate([sc.radiance, rng.normal(size=(extra, 2)).astype(np.float32)]))
+    for mode in ("tx", "rx"):
+        cen, rv = O.views_for(mode, wl.tx, wl.rx)
+        a = O.render(sc, grid, cen, wl.rx, rv)
+        b = O.render(sc2, grid, cen, wl.rx, rv)
+        assert np.array_equal(a["C"], b["C"]) and np.array_equal(a["T_final"], b["T_final"])
+
+
+# ---------------------------------------------------------------- Pin-6
+def test_linear_in_radiance(oracle_lib):
+    wl = _random_scene(5, 40)
+    sc = wl.scene
+    grid = S.Grid(18, 36, -math.pi / 2, math.pi / 18)
+    rng = np.random.default_rng(2)
+    s1 = rng.normal(size=(sc.K, 2))
+    s2 = rng.normal(size=(sc.K, 2))
+    cen, rv = O.views_for("rx", wl.tx, wl.rx)
+
+    def run(s):
+        return O.render(S.Scene(sc.means, sc.log_scales, sc.quats, sc.logits, radiance=s),
+                        grid, cen, wl.rx, rv)["C"]
+    a, b = 0.7, -1.9
+    lhs = run(a * s1 + b * s2)
+    rhs = a * run(s1) + b * run(s2)
+    assert np.abs(lhs - rhs).max() < 1e-12
+
+
+# ---------------------------------------------------------------- Pin-7 / Pin-8
+def test_tx_mode_receiver_independent_radiance_gives_equal_outputs(oracle_lib):
+    """Receiver-independent radiance under one transmitter-centred view makes
+    every receiver's spectrum the same (Alg. 1 shares stages 1-2 across
+    receivers; only the radiance differs)."""
+    wl = _random_scene(6, 50)
+    grid = S.Grid(18, 36, -math.pi / 2, math.pi / 18)
+    cen, rv = O.views_for("tx", wl.tx, wl.rx)
+    out = O.render(wl.scene, grid, cen, wl.rx, rv)
+    for j in range(1, wl.rx.shape[0]):
+        assert np.array_equal(out["C"][j], out["C"][0])
+
+
+def test_receiver_permutation(oracle_lib):
+    wl = S.make_workload(S.Preset("t", 30, 5, (3, 3, 2), -1.2, 0.3, S.GRID_90x180, True), seed=8)
+    grid = S.Grid(18, 36, -math.pi / 2, math.pi / 18)
+    perm = np.array([3, 0, 4, 2, 1])
+    for mode in ("tx", "rx"):
+        cen, rv = O.views_for(mode, wl.tx, wl.rx)
+        a = O.render(wl.scene, grid, cen, wl.rx, rv, mlp=wl.mlp)
+        cen2, rv2 = O.views_for(mode, wl.tx, wl.rx[perm])
+        b = O.render(wl.scene, grid, cen2, wl.rx[perm], rv2, mlp=wl.mlp)
+        assert np.array_equal(a["C"][perm], b["C"])
+        assert np.array_equal(a["power"][perm], b["power"])
+
+
+# ---------------------------------------------------------------- Pin-9
+def test_rotation_about_vertical_axis_shifts_columns(oracle_lib):
+    """Rotating the scene by 90 degrees about the vertical axis through the
+    view centre shifts every spectrum by a quarter of the columns, across the
+    azimuth seam."""
+    grid = S.Grid(18, 36, -math.pi / 2, math.pi / 18)
+    wl = _random_scene(9, 50, box=(3.0, 3.0, 2.0))
+    sc = wl.scene
+    m = sc.means.astype(np.float64) - np.array([1.5, 1.5, 0.0])
+    m = m.astype(np.float32).astype(np.float64)
+    rot_m = np.stack([-m[:, 1], m[:, 0], m[:, 2]], 1)
+    qz = np.array([math.cos(math.pi / 4), 0, 0, math.sin(math.pi / 4)])
+    q = sc.quats.astype(np.float64)
+    qr = np.stack([qz[0] * q[:, 0] - qz[3] * q[:, 3],
+                   qz[0] * q[:, 1] - qz[3] * q[:, 2],
+                   qz[0] * q[:, 2] + qz[3] * q[:, 1],
+                   qz[0] * q[:, 3] + qz[3] * q[:, 0]], 1)
+    a_sc = one_scene(m, sc.log_scales, q, sc.logits, radiance=sc.radiance)
+    b_sc = one_scene(rot_m, sc.log_scales, qr, sc.logits, radiance=sc.radiance)
+    a = O.render(a_sc, grid, np.zeros((1, 3)), np.zeros((1, 3)), [0])
+    b = O.render(b_sc, grid, np.zeros((1, 3)), np.zeros((1, 3)), [0])
+    shift = grid.W // 4
+    assert np.abs(np.roll(a["C"], shift, axis=-1) - b["C"]).max() < 1e-9
+    assert np.abs(a["C"]).max() > 0.1
+    # the seam is crossed: some composited pixel sits in the first or last column
+    assert np.abs(b["C"][..., :2]).max() > 1e-3 or np.abs(b["C"][..., -2:]).max() > 1e-3
+
+
+# ---------------------------------------------------------------- Pin-10
+@pytest.mark.parametrize("seed,mode,mlp", [(21, "rx", False), (22, "tx", False),
+                                           (23, "rx", True), (24, "tx", True)])
+def test_dense_twin_agrees(oracle_lib, seed, mode, mlp):
+    grid = S.Grid(9, 18, -math.pi / 2, math.pi / 9)
+    wl = S.make_workload(S.Preset("t", 8, 3, (2.5, 2.5, 2.0), -1.0, 0.3, S.GRID_90x180, mlp), seed=seed)
+    cen, rv = O.views_for(mode, wl.tx, wl.rx)
+    a = O.render(wl.scene, grid, cen, wl.rx, rv, mlp=wl.mlp)
+    b = twin.render(wl.scene, grid, cen, wl.rx, rv, mlp=wl.mlp)
+    assert np.abs(a["C"]).max() > 1e-2
+    assert np.abs(a["C"] - b["C"]).max() < 1e-8 * max(1.0, np.abs(a["C"]).max())
+    assert np.abs(a["T_final"] - b["T_final"]).max() < 1e-8
+
+
+def test_dense_twin_agrees_90x360(oracle_lib):
+    grid = S.Grid(30, 120, 0.0, math.pi / 60)
+    wl = S.make_workload(S.Preset("t", 24, 2, (4.0, 4.0, 3.0), -1.0, 0.3, S.GRID_90x360, True), seed=31)
+    cen, rv = O.views_for("rx", wl.tx, wl.rx)
+    a = O.render(wl.scene, grid, cen, wl.rx, rv, mlp=wl.mlp)
+    b = twin.render(wl.scene, grid, cen, wl.rx, rv, mlp=wl.mlp)
+    assert np.abs(a["C"]).max() > 1e-2
+    assert np.abs(a["C"] - b["C"]).max() < 1e-8 * max(1.0, np.abs(a["C"]).max())
+
+
+# ---------------------------------------------------------------- Pin-11
+def test_mlp_special_weights_select_encoding_and_features(oracle_lib):
+    """Weights with a single 1 per row turn the MLP into a selector:
+    s = (relu(gamma_a), relu(f_b)) with gamma[12 d + 2 f] = sin(2^f r_d) and
+    gamma[12 d + 2 f + 1] = cos(2^f r_d); W is (out x in), row-major."""
+    W1 = np.zeros((64, 68)); b1 = np.zeros(64)
+    W2 = np.eye(64); b2 = np.zeros(64)
+    W3 = np.zeros((2, 64)); b3 = np.array([0.25, -0.5])
+    d, f = 1, 4                       # y axis, band 2^4, sine
+    W1[0, 12 * d + 2 * f] = 1.0
+    W1[1, 36 + 7] = 1.0               # feature 7
+    W3[0, 0] = 1.0
+    W3[1, 1] = 1.0
+    rng = np.random.default_rng(3)
+    feats = rng.normal(size=(5, 32))
+    sc = one_scene(rng.uniform(0, 1, (5, 3)), np.zeros((5, 3)), np.tile([1, 0, 0, 0], (5, 1)),
+                   np.zeros(5), features=feats)
+    rx = np.array([[0.3, 1.7, 0.2], [2.0, -0.9, 1.0]])
+    rad = O.radiance(sc, rx, mlp=[W1, b1, W2, b2, W3, b3])
+    for j in range(2):
+        g = math.sin(rx[j, d] * 2 ** f)
+        assert np.abs(rad[j, :, 0] - (max(g, 0.0) + 0.25)).max() < 1e-15
+        assert np.abs(rad[j, :, 1] - (np.maximum(feats[:, 7], 0.0) - 0.5)).max() < 1e-15
+    W1[0] = 0.0
+    W1[0, 12 * 2 + 2 * 5 + 1] = 1.0   # z axis, band 2^5, cosine
+    rad = O.radiance(sc, rx, mlp=[W1, b1, W2, b2, W3, b3])
+    for j in range(2):
+        g = math.cos(rx[j, 2] * 32.0)
+        assert np.abs(rad[j, :, 0] - (max(g, 0.0) + 0.25)).max() < 1e-15
+
+
+def test_mlp_matches_factorised_twin(oracle_lib):
+    wl = S.make_workload(S.Preset("t", 50, 4, (5, 5, 3), -1.2, 0.3, S.GRID_90x360, True), seed=12)
+    a = O.radiance(wl.scene, wl.rx, mlp=wl.mlp)
+    b = twin.radiance(wl.scene, wl.rx, mlp=wl.mlp)
+    assert np.abs(a - b).max() < 1e-12 * max(1.0, np.abs(a).max())
+
+
+# ---------------------------------------------------------------- Pin-12
+def test_projection_jacobian_matches_central_differences(oracle_lib):
+    grid = S.Grid(90, 360, 0.0, math.pi / 180)
+    rng = np.random.default_rng(4)
+    c = np.array([0.5, 0.4, 0.3])
+    for _ in range(5):
+        p = c + rng.uniform(-2, 2, 3)
+        ls = rng.normal(-1.2, 0.3, 3)
+        q = rng.normal(size=4)
+        lg = rng.normal()
+        jac = O.project_jacobian(p, ls, q, lg, c, grid)
+        x0 = np.concatenate([p, ls, q, [lg]])
+        for i in range(11):
+            h = 1e-6
+            outs = []
+            for sgn in (1, -1):
+                x = x0.copy()
+                x[i] += sgn * h
+                sc = one_scene(x[:3], x[3:6], x[6:10], [x[10]], radiance=[1, 0])
+                _, _, pr = O.project(sc, grid, c[None])
+                outs.append(pr[0, 0, :6])
+            fd = (outs[0] - outs[1]) / (2 * h)
+            scale = np.abs(jac[:, i]) + 1e-6 * np.abs(outs[0]) + 1e-7
+            assert (np.abs(fd - jac[:, i]) <= 1e-5 * scale + 1e-6).all(), (i, fd, jac[:, i])
+
+
+def _loss_and_hash(sc, grid, cen, rx, rv, mlp, Y, lam):
+    out = O.render(sc, grid, cen, rx, rv, mlp=mlp, want_hash=True)
+    L = float(((out["C"] - Y) ** 2).sum() + lam * out["power"].sum())
+    return L, out
+
+
+@pytest.mark.parametrize("mode,use_mlp", [("tx", True), ("rx", True), ("rx", False)])
+def test_gradient_matches_central_differences(oracle_lib, mode, use_mlp):
+    """FP64 central differences (step 1e-6) of L = sum (C - Y)^2 + 0.3 sum P on
+    random parameters match the reverse mode.  Parameters whose +-h steps change
+    any discrete decision (skip, clamp, stop, order) are redrawn."""
+    grid = S.Grid(12, 24, -math.pi / 2, math.pi / 12)
+    wl = S.make_workload(S.Preset("t", 12, 2, (2.0, 2.0, 1.5), -0.9, 0.3, S.GRID_90x180, use_mlp),
+                         seed=41 + (mode == "rx") + 2 * use_mlp)
+    s0 = wl.scene
+    sc = S.Scene(*[None if a is None else np.asarray(a, dtype=np.float64)
+                   for a in (s0.means, s0.log_scales, s0.quats, s0.logits, s0.radiance, s0.features)])
+    mlp = [np.asarray(a, dtype=np.float64) for a in wl.mlp] if use_mlp else None
+    if mlp is not None:
+        mlp[1] = np.random.default_rng(5).normal(0, 0.1, 64)
+        mlp[3] = np.random.default_rng(6).normal(0, 0.1, 64)
+        mlp[5] = np.array([0.05, -0.02])
+    cen, rv = O.views_for(mode, wl.tx, wl.rx)
+    rx = wl.rx.astype(np.float64)
+    rng = np.random.default_rng(7)
+    Y = 0.3 * rng.normal(size=(rx.shape[0], 2, grid.H, grid.W))
+    lam = 0.3
+    L0, out0 = _loss_and_hash(sc, grid, cen, rx, rv, mlp, Y, lam)
+    assert out0["ncomp"].max() >= 2
+    g = O.backward(sc, grid, cen, rx, rv, 2.0 * (out0["C"] - Y), np.full(rx.shape[0], lam), mlp=mlp)
+
+    fields = ["means", "log_scales", "quats", "logits"] + (["features", "mlp"] if use_mlp else ["radiance"])
+    checked = 0
+    tries = 0
+    while checked < 48 and tries < 400:
+        tries += 1
+        f = fields[rng.integers(len(fields))]
+        if f == "mlp":
+            flat = np.concatenate([a.ravel() for a in mlp])
+            i = int(rng.integers(flat.size))
+            gval = g["mlp"][i]
+        else:
+            arr = getattr(sc, f)
+            i = int(rng.integers(arr.size))
+            gval = g[f].ravel()[i]
+        h = 1e-6
+        Ls, hashes = [], []
+        for sgn in (1, -1):
+            if f == "mlp":
+                fl = flat.copy()
+                fl[i] += sgn * h
+                m2 = S.unflat_mlp(fl)
+                sc2 = sc
+            else:
+                a2 = getattr(sc, f).copy().ravel()
+                a2[i] += sgn * h
+                sc2 = S.Scene(**{**sc.__dict__, f: a2.reshape(getattr(sc, f).shape)})
+                m2 = mlp
+            L, o = _loss_and_hash(sc2, grid, cen, rx, rv, m2, Y, lam)
+            Ls.append(L)
+            hashes.append(o["rowhash"])
+        if not (np.array_equal(hashes[0], hashes[1]) and np.array_equal(hashes[0], out0["rowhash"])):
+            continue
+        fd = (Ls[0] - Ls[1]) / (2 * h)
+        assert abs(fd - gval) <= 1e-6 * abs(gval) + 2e-8 * max(1.0, abs(L0)), (f, i, fd, gval)
+        checked += 1
+    assert checked >= 40
+
+
+# ---------------------------------------------------------------- binning reference
+def _bin(u, v, rup, rvp, o=1.0, key=0x40000000, grid=S.Grid(90, 360, 0.0, math.pi / 180)):
+    arr = lambda x: np.array([[x]], dtype=np.float32)
+    return O.bin_records(arr(u), arr(v), arr(rup), arr(rvp), arr(o),
+                         np.array([[key]], dtype=np.uint32), grid)
+
+
+def test_binning_hand_cases(oracle_lib):
+    # interior: rows 10..14 -> tile row 0, cols 30..37 -> tile cols 1, 2  (23 tile columns)
+    seg, k = _bin(33.6, 12.0, 3.9, 2.5)
+    assert list(seg) == [1, 2]
+    # spans two tile rows: rows 13..18 -> tile rows 0 and 1
+    seg, _ = _bin(40.0, 15.5, 1.0, 2.6)
+    assert list(seg) == [2, 23 + 2]
+    # azimuth seam: cols 357..361 -> 357..359 (tile 22) and 0..1 (tile 0), in segment order
+    seg, _ = _bin(359.0, 5.0, 2.2, 1.0)
+    assert list(seg) == [0, 22]
+    # left of column 0: cols -3..2 -> 357..359 and 0..2
+    seg, _ = _bin(-0.4, 5.0, 2.9, 1.0)
+    assert list(seg) == [0, 22]
+    # nearly the full circle: every tile column once
+    seg, _ = _bin(100.0, 5.0, 180.0, 1.0)
+    assert list(seg) == list(range(23))
+    # entirely below the grid, entirely between two columns, near-culled, transparent
+    assert _bin(100.0, -5.0, 3.0, 2.0)[0].size == 0
+    assert _bin(100.4, 5.0, 0.05, 2.0)[0].size == 0
+    assert _bin(100.0, 5.0, 3.0, 2.0, key=np.float32(0.03).view(np.uint32))[0].size == 0
+    assert _bin(100.0, 5.0, 3.0, 2.0, o=np.float32(1.0 / 255.0) * np.float32(0.999))[0].size == 0
+    # rows 76..85 straddle tile rows 4 and 5 (the ragged last row of tiles, rows 80..89);
+    # columns 354..356 sit in the last, partial tile column (352..359)
+    seg, _ = _bin(355.0, 80.5, 1.0, 5.0)
+    assert list(seg) == [4 * 23 + 22, 5 * 23 + 22]
+
+
+def test_binning_covers_every_pixel_in_the_padded_box(oracle_lib):
+    """Brute force: the binned tiles are exactly the tiles holding a pixel inside
+    the padded box (wrapped in azimuth), except that a box spanning nearly the
+    whole circle takes every tile column."""
+    grid = S.Grid(20, 40, 0.0, math.pi / 20)
+    rng = np.random.default_rng(9)
+    V, K = 2, 60
+    u = rng.uniform(-0.5, 39.5, (V, K)).astype(np.float32)
+    v = rng.uniform(-4, 24, (V, K)).astype(np.float32)
+    rup = np.exp(rng.uniform(-3, 3.3, (V, K))).astype(np.float32)
+    rvp = np.exp(rng.uniform(-3, 2.5, (V, K))).astype(np.float32)
+    o = rng.uniform(0.001, 1, (V, K)).astype(np.float32)
+    key = rng.uniform(0.01, 30, (V, K)).astype(np.float32).view(np.uint32)
+    seg, kk = O.bin_records(u, v, rup, rvp, o, key, grid)
+    nTx, nTy = 3, 2
+    got = {}
+    for s_, k_ in zip(seg, kk):
+        got.setdefault((int(s_) // (nTx * nTy), int(k_)), set()).add(int(s_) % (nTx * nTy))
+    for vv in range(V):
+        for k in range(K):
+            exp_tiles = set()
+            if key[vv, k] >= np.float32(0.04).view(np.uint32) and o[vv, k] >= np.float32(1 / 255):
+                for i in range(grid.H):
+                    if abs(i - float(v[vv, k])) > rvp[vv, k]:
+                        continue
+                    for c in range(grid.W):
+                        du = c - float(u[vv, k])
+                        dus = [du, du - grid.W, du + grid.W]
+                        if min(abs(x) for x in dus) <= rup[vv, k]:
+                            exp_tiles.add((i // 16) * nTx + c // 16)
+            t = got.get((vv, k), set())
+            if rup[vv, k] >= 0.5 * (grid.W - 16 - 2):
+                assert exp_tiles <= t
+            else:
+                assert t == exp_tiles, (vv, k, t, exp_tiles)
+    # sorted by (segment, key, index)
+    order = np.lexsort((kk, key.reshape(-1)[(seg // (nTx * nTy)) * K + kk], seg))
+    assert np.array_equal(order, np.arange(seg.size))
+
+
+# ---------------------------------------------------------------- golden
+def test_table4_hyperparameters_fixture():
+    """The encoding width, hidden size and spectrum grid follow the paper's
+    hyperparameter table (App. E, Table 4, RFID spectrum column)."""
+    with open(os.path.join(HERE, "golden", "table4_rfid.json")) as fh:
+        t4 = json.load(fh)
+    assert S.ENC_DIM == 3 * 2 * t4["fourier_bands"]
+    assert S.HIDDEN == t4["mlp_hidden"]
+    assert (S.GRID_90x360.W, S.GRID_90x360.H) == tuple(t4["ray_directions_phi_theta"])
+    assert abs(S.GRID_90x360.del_az - 2 * math.pi / t4["ray_directions_phi_theta"][0]) < 1e-15
