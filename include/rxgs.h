@@ -1,0 +1,218 @@
+/*
+ * rxgs.h -- C ABI of the MI355X multi-receiver Gaussian rasterizer.
+ *
+ * The library renders, for a batch of receivers, the spectrum that a set of
+ * frozen 3-D Gaussians produces on an angular (azimuth x elevation) grid, as
+ * RxGS (arXiv 2605.24290) defines it: Alg. 1 ("Multi-Receiver Spectrum
+ * Rendering for One Transmitter") with its three stages -- projection and a
+ * depth sort over (tile, depth) keys shared by the receivers of a view, one
+ * batched radiance evaluation per (receiver, Gaussian), and front-to-back
+ * alpha compositing per (tile, receiver) -- plus the backward pass of
+ * App. D ("the backward kernel runs with the same gridDim.z = N") and a
+ * continuous-batching server.
+ *
+ * Conventions shared by every entry point:
+ *   - All functions return rxgs_status; no C++ exception crosses the ABI.
+ *     On failure rxgs_last_error(ctx) returns a message valid until the next
+ *     call on that context.
+ *   - "device" pointers are HIP device memory on the context's device, owned
+ *     by the caller; "host" pointers are ordinary host memory.
+ *   - Work is enqueued on the caller's HIP stream (a hipStream_t passed as
+ *     void*, NULL = the null stream).  rxgs_render waits once, after the
+ *     projection, to size its buffers; every other device step is
+ *     asynchronous.  Outputs are valid once the stream reaches that point.
+ *   - A context is used by one host thread at a time; the server's submit,
+ *     poll and cancel calls are thread-safe.
+ *   - Arrays are row-major FP32 unless stated.
+ *
+ * Angular grid: row i is centred at elevation el0 + (i + 1/2) del_el,
+ * column c at azimuth (c + 1/2) 2 pi / W, azimuth atan2(y, x) in [0, 2 pi)
+ * and elevation measured from the horizontal plane (+z up).  The paper's
+ * spatial-spectrum grid is 360 x 90 at 1 degree (App. E, Table 4).
+ */
+#ifndef RXGS_H
+#define RXGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RXGS_OK = 0,
+    RXGS_E_INVALID = 1,    /* bad argument: null pointer, size, non-finite value */
+    RXGS_E_OOM = 2,        /* device or pinned host allocation failed */
+    RXGS_E_DEVICE = 3,     /* a HIP call failed; the context should be destroyed */
+    RXGS_E_STATE = 4,      /* call out of order (no scene, no MLP, stale saved state) */
+    RXGS_E_BUSY = 5,       /* server queue full */
+    RXGS_E_TIMEOUT = 6,    /* poll timed out; the ticket is still pending */
+    RXGS_E_CANCELLED = 7   /* ticket was cancelled */
+} rxgs_status;
+
+typedef struct rxgs_ctx rxgs_ctx;
+typedef struct rxgs_saved rxgs_saved;
+typedef struct rxgs_server rxgs_server;
+
+typedef struct {
+    int32_t H;        /* rows (elevation), >= 1 */
+    int32_t W;        /* columns (azimuth), >= 2, even */
+    int32_t reserved; /* must be 0 */
+    double el0;       /* elevation of the lower edge of row 0, radians */
+    double del_el;    /* row pitch, radians (> 0) */
+} rxgs_grid;
+
+/* View modes.  TX: each transmitter is one view centred at it, shared by its
+ * receivers (Alg. 1 stage 1 "computed once"; App. D "Transmitter-Side
+ * Preprocessing").  RX: each receiver is its own view centred at its
+ * position; keys are then (receiver, tile, depth). */
+enum { RXGS_MODE_TX = 0, RXGS_MODE_RX = 1 };
+
+/* Number of MLP parameters: W1 (64 x 68), b1 (64), W2 (64 x 64), b2 (64),
+ * W3 (2 x 64), b3 (2), concatenated in that order, each row-major (out x in). */
+#define RXGS_MLP_NPARAM 8706
+#define RXGS_FEAT_DIM 32
+#define RXGS_TILE 16
+
+/* Create a context on HIP device `device` for one angular grid.
+ * Errors: E_INVALID (grid), E_DEVICE. */
+rxgs_status rxgs_create(int device, const rxgs_grid *grid, rxgs_ctx **out);
+
+/* Destroy a context, its scene, MLP and internal workspaces.  Saved states
+ * created from it must be destroyed first.  NULL is ignored. */
+void rxgs_destroy(rxgs_ctx *ctx);
+
+/* Last error message of the context ("" when none).  NULL ctx: the message
+ * of the last failed rxgs_create on this thread. */
+const char *rxgs_last_error(const rxgs_ctx *ctx);
+
+/*
+ * Upload the Gaussian scene (Sec. 2 eq. (1); App. E.1): K Gaussians with
+ * means (K x 3, metres), log-space scales (K x 3), rotation quaternions
+ * (K x 4, (w, x, y, z), normalised inside the renderer) and opacity logits
+ * (K; opacity = sigmoid(logit)).  Radiance is either direct, radiance
+ * (K x 2, Re/Im, the same for every receiver), or per-Gaussian features
+ * (K x 32) fed to the conditioning MLP; exactly one of the two is non-NULL
+ * (with K = 0 both may be NULL: an empty direct-radiance scene).
+ * The library copies everything into its own device buffers (the scene stays
+ * resident for serving).  src_on_device: 1 if the pointers are device memory,
+ * 0 for host memory.  Validates that every value is finite (E_INVALID).
+ * K may be 0.  Invalidates earlier saved states (E_STATE on their backward).
+ */
+rxgs_status rxgs_scene_upload(rxgs_ctx *ctx, int64_t K, const float *means, const float *log_scales,
+                              const float *quats, const float *logits, const float *radiance,
+                              const float *features, int src_on_device, void *stream);
+
+/*
+ * Upload the receiver-conditioning MLP (RXGS_MLP_NPARAM floats, layout
+ * above).  Its input is [gamma(r); f_k] where gamma(r)[12 d + 2 f] =
+ * sin(2^f r_d) and gamma(r)[12 d + 2 f + 1] = cos(2^f r_d), d in {x, y, z},
+ * f = 0..5 (the Fourier receiver encoding of Sec. 4.3.2 eq. rx_enc with the
+ * 6 bands of App. E Table 4); hidden layers ReLU; output (Re, Im).
+ * Layer 1 is evaluated as W1[:, :36] gamma(r_j) once per receiver plus
+ * W1[:, 36:] f_k + b1 once per Gaussian (the global and local branches).
+ */
+rxgs_status rxgs_mlp_upload(rxgs_ctx *ctx, const float *params, int src_on_device, void *stream);
+
+/* Saved forward state for the backward pass.  Buffers grow on demand and are
+ * kept until rxgs_saved_destroy. */
+rxgs_status rxgs_saved_create(rxgs_ctx *ctx, rxgs_saved **out);
+void rxgs_saved_destroy(rxgs_saved *s);
+
+/*
+ * Render N receivers in one pass (Alg. 1; Sec. 4.4).
+ *   mode    RXGS_MODE_TX or RXGS_MODE_RX.
+ *   Q, tx   TX mode: Q >= 1 transmitters, tx device Q x 3; receivers
+ *           rx_off[q] .. rx_off[q+1]-1 use transmitter q.  RX mode: tx and
+ *           rx_off are ignored (may be NULL) and Q is ignored.
+ *   rx_off  host, Q + 1 non-decreasing offsets, rx_off[0] = 0, rx_off[Q] = N.
+ *   N, rx   N >= 0 receivers, device N x 3 (metres).
+ *   C       device N x 2 x H x W output spectrum (Re plane, then Im plane).
+ *   power   device N output, received power sum_p |C_p|^2 (App. A Def. 2
+ *           aggregates over rays; here over the grid's pixels), or NULL.
+ *   csum    device N x 2 output, coherent sum sum_p C_p, or NULL.
+ *   saved   state for rxgs_render_backward, or NULL (an internal workspace is
+ *           used and nothing is kept).
+ * Compositing per pixel (Alg. 1 stage 3): Gaussians of the view in ascending
+ * (FP32 squared distance to the view centre, index) order; w = min(0.99,
+ * o exp(-q/2)) with q the Mahalanobis distance of the pixel under the
+ * projected covariance (+0.3 px^2); skipped when w < 1/255; C += T w s;
+ * T <- T (1 - w); stop after the Gaussian that takes T below 1e-4.
+ * Gaussians closer than 0.2 m to the view centre are culled.
+ * Errors: E_INVALID, E_STATE (no scene, or MLP scene without an MLP), E_OOM,
+ * E_DEVICE.  The call synchronises the stream once.
+ */
+rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off,
+                        int N, const float *rx, float *C, float *power, float *csum,
+                        rxgs_saved *saved, void *stream);
+
+/* Gradient outputs of rxgs_render_backward (device pointers, caller-owned,
+ * overwritten).  Any may be NULL to skip it; radiance is used for direct
+ * radiance scenes, features and mlp for MLP scenes. */
+typedef struct {
+    float *means;        /* K x 3 */
+    float *log_scales;   /* K x 3 */
+    float *quats;        /* K x 4, gradient w.r.t. the raw (unnormalised) quaternion */
+    float *logits;       /* K */
+    float *radiance;     /* K x 2 */
+    float *features;     /* K x 32 */
+    float *mlp;          /* RXGS_MLP_NPARAM */
+} rxgs_grads;
+
+/*
+ * Backward pass of the last rxgs_render into `saved` (App. D: per-receiver
+ * dL/ds, Gaussian-level gradients accumulated over receivers and pixels).
+ *   C    device N x 2 x H x W, the forward's output (used for dL/dP).
+ *   dC   device N x 2 x H x W, dL/dC.
+ *   dP   device N, dL/dpower, or NULL.
+ * Gradients flow through w = o exp(-q/2) when it is not clamped at 0.99, the
+ * projected mean and covariance, the quaternion normalisation and the MLP
+ * (ReLU derivative 0 at 0).  Float atomics make results vary in the last
+ * bits from run to run.  Errors: E_INVALID, E_STATE, E_OOM, E_DEVICE.
+ */
+rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *saved, const float *C,
+                                 const float *dC, const float *dP, const rxgs_grads *grads,
+                                 void *stream);
+
+/* Sizes of a saved forward state. */
+typedef struct {
+    int64_t K;          /* Gaussians */
+    int64_t K_pad;      /* per-view stride of record arrays (multiple of 4096) */
+    int64_t V;          /* views */
+    int64_t N;          /* receivers */
+    int64_t D;          /* (view, tile, Gaussian) pairs */
+    int64_t n_visible;  /* sum over views of Gaussians with a non-empty tile set */
+    int64_t tiles;      /* tiles per view */
+    int64_t tiles_x;    /* tile columns */
+} rxgs_saved_info_t;
+
+rxgs_status rxgs_saved_info(const rxgs_saved *s, rxgs_saved_info_t *out);
+
+/* Copy an internal array of a saved state to a caller device or host buffer
+ * (hipMemcpy semantics: the copy completes before return).  `what`:
+ *   RXGS_EXPORT_BIN       V x K_pad x 4 f32: u, v, padded half-extents rup, rvp
+ *   RXGS_EXPORT_KEYS      V x K_pad u32: FP32 depth-key bits (0xFFFFFFFF if culled)
+ *   RXGS_EXPORT_OPACITY   V x K_pad f32: opacity used for culling
+ *   RXGS_EXPORT_ORDER     V x K_pad i32: Gaussian index at each sorted position
+ *   RXGS_EXPORT_NVIS      V i32: visible Gaussians per view
+ *   RXGS_EXPORT_PAIRS     D i32: sorted position (v * K_pad + s) of each pair
+ *   RXGS_EXPORT_RANGES    V x tiles x 2 i32: [start, end) of each tile's pairs
+ *   RXGS_EXPORT_RADIANCE  N x K_pad x 2 f32: radiance at each sorted position
+ *   RXGS_EXPORT_TFINAL    S x H x W f32: final transmittance (S = V in TX mode, N in RX)
+ *   RXGS_EXPORT_NLAST     S x H x W i32: entries of the tile list consumed
+ * `bytes` must be at least the size above; E_INVALID otherwise. */
+enum {
+    RXGS_EXPORT_BIN = 0, RXGS_EXPORT_KEYS = 1, RXGS_EXPORT_OPACITY = 2, RXGS_EXPORT_ORDER = 3,
+    RXGS_EXPORT_NVIS = 4, RXGS_EXPORT_PAIRS = 5, RXGS_EXPORT_RANGES = 6,
+    RXGS_EXPORT_RADIANCE = 7, RXGS_EXPORT_TFINAL = 8, RXGS_EXPORT_NLAST = 9
+};
+rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *dst, int64_t bytes, int dst_on_device);
+
+/* Library version string. */
+const char *rxgs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RXGS_H */

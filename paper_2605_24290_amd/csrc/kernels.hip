@@ -1,0 +1,907 @@
+// Forward kernels of librxgs for gfx950 (CDNA4, wave64).
+//
+// Pipeline of one render (Alg. 1 of RxGS, arXiv 2605.24290, with the view
+// index added to the sort key):
+//   k_project      stage 1: per (view, Gaussian) projection onto the angular
+//                  grid, FP32 depth key, conservative tile count.   [HBM]
+//   radix sort     stage 1: per-view stable sort of the depth keys (one
+//                  segment per view), 4 passes of 8 bits.          [HBM]
+//   k_gather       records into depth order, tile counts in depth order.
+//   scan + k_emit  one (segment, position) pair per covered tile, emitted in
+//                  depth order.                                      [HBM]
+//   radix sort     stable sort of the pairs by segment = view x tiles + tile,
+//                  so each tile's list stays in depth order.        [HBM]
+//   k_ranges       [start, end) of each tile's list.
+//   k_mlp_*        stage 2: receiver term and Gaussian term of the MLP's first
+//                  layer, then the per-(receiver, Gaussian) layers on FP32
+//                  MFMA.                                            [MFMA]
+//   k_blend_fwd    stage 3: per (tile, receiver chunk) front-to-back
+//                  compositing from LDS-staged batches.             [VALU]
+//   k_reduce_out   per-receiver power and coherent sum, fixed order.
+#include "rxgs_internal.h"
+
+#include <cmath>
+
+namespace rxgs {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int count_below(uint64_t m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x)
+{
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+__device__ __forceinline__ float wave_sum_f32(float x)
+{
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+// FP32 squared distance, each product and sum rounded on its own (no FMA)
+__device__ __forceinline__ float depth_key(float dx, float dy, float dz)
+{
+#pragma clang fp contract(off)
+    const float xx = dx * dx;
+    const float yy = dy * dy;
+    const float zz = dz * dz;
+    return (xx + yy) + zz;
+}
+
+// ----------------------------------------------------------------------------
+// tile coverage of one record, FP32 rules (rows clamped to the grid, columns
+// modulo W; a box spanning nearly the full circle takes every tile column)
+__device__ __forceinline__ int tile_rows(float v, float rvp, int H, int &ty0, int &ty1)
+{
+    float lo = fmaxf(__fsub_rn(v, rvp), 0.0f);
+    float hi = fminf(__fadd_rn(v, rvp), (float)(H - 1));
+    int i0 = (int)ceilf(lo), i1 = (int)floorf(hi);
+    if (i0 > i1) return 0;
+    ty0 = i0 / TILE;
+    ty1 = i1 / TILE;
+    return ty1 - ty0 + 1;
+}
+
+__device__ __forceinline__ int tile_cols(float u, float rup, int W, int tiles_x, int &a0, int &a1, int &b0,
+                                         int &b1)
+{
+    b0 = 0;
+    b1 = -1;
+    if (rup >= 0.5f * (float)(W - TILE - 2)) {
+        a0 = 0;
+        a1 = tiles_x - 1;
+        return tiles_x;
+    }
+    int c0 = (int)ceilf(__fsub_rn(u, rup)), c1 = (int)floorf(__fadd_rn(u, rup));
+    if (c0 > c1) return 0;
+    int m = ((c0 % W) + W) % W;
+    int e = m + (c1 - c0);
+    a0 = m / TILE;
+    if (e < W) {
+        a1 = e / TILE;
+    } else {
+        a1 = (W - 1) / TILE;
+        b1 = (e - W) / TILE;
+    }
+    return (a1 - a0 + 1) + (b1 - b0 + 1);
+}
+
+// ----------------------------------------------------------------------------
+// Stage 1: projection.  One thread per Gaussian (coalesced SoA loads), looping
+// over a chunk of views.  Geometry in FP64 (exact differences of the FP32
+// inputs), stored as FP32.  The depth key is the FP32 squared distance
+// computed with rounded, unfused operations.
+__global__ __launch_bounds__(BLOCK) void k_project(
+    const float *__restrict__ soa, int64_t K, int64_t Kp, const float *__restrict__ centres, int V,
+    int vchunk, DevGrid g, float4 *__restrict__ rec, float4 *__restrict__ ext, uint32_t *__restrict__ rawkey,
+    float *__restrict__ opac, uint32_t *__restrict__ ntl, uint32_t *__restrict__ skey,
+    uint32_t *__restrict__ sval, unsigned long long *__restrict__ counters)
+{
+    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int v0 = blockIdx.y * vchunk;
+    const int v1 = min(V, v0 + vchunk);
+    const bool real = k < K;
+    const int lane = threadIdx.x & 63;
+    float px = 0.f, py = 0.f, pz = 0.f, o32 = 0.f;
+    double S00 = 0, S01 = 0, S02 = 0, S11 = 0, S12 = 0, S22 = 0;
+    if (real) {
+        px = soa[k];
+        py = soa[K + k];
+        pz = soa[2 * K + k];
+        const double s0 = exp(2.0 * (double)soa[3 * K + k]);
+        const double s1 = exp(2.0 * (double)soa[4 * K + k]);
+        const double s2 = exp(2.0 * (double)soa[5 * K + k]);
+        double qw = soa[6 * K + k], qx = soa[7 * K + k], qy = soa[8 * K + k], qz = soa[9 * K + k];
+        const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+        qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+        const double R00 = 1.0 - 2.0 * (qy * qy + qz * qz), R01 = 2.0 * (qx * qy - qw * qz),
+                     R02 = 2.0 * (qx * qz + qw * qy);
+        const double R10 = 2.0 * (qx * qy + qw * qz), R11 = 1.0 - 2.0 * (qx * qx + qz * qz),
+                     R12 = 2.0 * (qy * qz - qw * qx);
+        const double R20 = 2.0 * (qx * qz - qw * qy), R21 = 2.0 * (qy * qz + qw * qx),
+                     R22 = 1.0 - 2.0 * (qx * qx + qy * qy);
+        S00 = R00 * R00 * s0 + R01 * R01 * s1 + R02 * R02 * s2;
+        S01 = R00 * R10 * s0 + R01 * R11 * s1 + R02 * R12 * s2;
+        S02 = R00 * R20 * s0 + R01 * R21 * s1 + R02 * R22 * s2;
+        S11 = R10 * R10 * s0 + R11 * R11 * s1 + R12 * R12 * s2;
+        S12 = R10 * R20 * s0 + R11 * R21 * s1 + R12 * R22 * s2;
+        S22 = R20 * R20 * s0 + R21 * R21 * s1 + R22 * R22 * s2;
+        o32 = (float)(1.0 / (1.0 + exp(-(double)soa[10 * K + k])));
+    }
+    for (int v = v0; v < v1; v++) {
+        const size_t i = (size_t)v * Kp + k;
+        uint32_t key = 0xFFFFFFFFu, kb = 0xFFFFFFFFu, nt = 0;
+        float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+        bool vis = false;
+        if (real) {
+            const float cx = centres[3 * v], cy = centres[3 * v + 1], cz = centres[3 * v + 2];
+            const float dxf = __fsub_rn(px, cx), dyf = __fsub_rn(py, cy), dzf = __fsub_rn(pz, cz);
+            const float kf = depth_key(dxf, dyf, dzf);
+            kb = __float_as_uint(kf);
+            if (!(kf < NEAR2)) {
+                const double dx = (double)px - (double)cx, dy = (double)py - (double)cy,
+                             dz = (double)pz - (double)cz;
+                double h = sqrt(dx * dx + dy * dy);
+                if (!(h >= H_MIN)) h = H_MIN;
+                double az = atan2(dy, dx);
+                if (az < 0.0) az += 2.0 * M_PI;
+                const double el = atan2(dz, h);
+                const double u = az / g.daz - 0.5;
+                const double vv = (el - g.el0) / g.del - 0.5;
+                const double hh = h * h, rh2 = hh + dz * dz, rh2h = rh2 * h;
+                const double mu0 = -dy / hh / g.daz, mu1 = dx / hh / g.daz;
+                const double mv0 = -dx * dz / rh2h / g.del, mv1 = -dy * dz / rh2h / g.del, mv2 = h / rh2 / g.del;
+                const double Smv0 = S00 * mv0 + S01 * mv1 + S02 * mv2;
+                const double Smv1 = S01 * mv0 + S11 * mv1 + S12 * mv2;
+                const double Smv2 = S02 * mv0 + S12 * mv1 + S22 * mv2;
+                const double A = S00 * mu0 * mu0 + 2.0 * S01 * mu0 * mu1 + S11 * mu1 * mu1 + DILATE;
+                const double B = mu0 * Smv0 + mu1 * Smv1;
+                const double Cc = mv0 * Smv0 + mv1 * Smv1 + mv2 * Smv2 + DILATE;
+                const float u32 = (float)u, v32 = (float)vv;
+                e = make_float4(u32, v32, 0.f, 0.f);
+                if (o32 >= ALPHA_MIN) {
+                    const double qmax = 2.0 * log((double)o32 / (double)ALPHA_MIN);
+                    const float rup = (float)(sqrt(qmax * A) * (1.0 + PAD_REL) + PAD_ABS);
+                    const float rvp = (float)(sqrt(qmax * Cc) * (1.0 + PAD_REL) + PAD_ABS);
+                    e.z = rup;
+                    e.w = rvp;
+                    int ty0, ty1, a0, a1, b0, b1;
+                    const int nr = tile_rows(v32, rvp, g.H, ty0, ty1);
+                    const int nc = nr ? tile_cols(u32, rup, g.W, g.tiles_x, a0, a1, b0, b1) : 0;
+                    nt = (uint32_t)(nr * nc);
+                }
+                vis = nt > 0;
+                if (vis) {
+                    const double det = A * Cc - B * B;
+                    const double ca = Cc / det, cb = -B / det, cc = A / det;
+                    const double uf = floor(u), vf = floor(vv);
+                    constexpr double L2E = 1.4426950408889634;
+                    rec[2 * i] = make_float4((float)uf, (float)(u - uf), (float)vf, (float)(vv - vf));
+                    rec[2 * i + 1] = make_float4((float)(-0.5 * L2E * ca), (float)(-L2E * cb),
+                                                 (float)(-0.5 * L2E * cc), (float)log2((double)o32));
+                    key = kb;
+                }
+            }
+        }
+        ext[i] = e;
+        rawkey[i] = kb;
+        opac[i] = o32;
+        ntl[i] = nt;
+        skey[i] = key;
+        sval[i] = (uint32_t)k;
+        const uint64_t bal = __ballot(vis);
+        const uint32_t tsum = wave_sum_u32(nt);
+        if (lane == 0) {
+            if (bal) atomicAdd(&counters[1 + v], (unsigned long long)__popcll(bal));
+            if (tsum) atomicAdd(&counters[0], (unsigned long long)tsum);
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// fills
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * BLOCK;
+    for (; i < n; i += stride) p[i] = value;
+}
+
+// ----------------------------------------------------------------------------
+// exclusive scan of u32 (three kernels: block sums, scan of block sums,
+// block-local scan plus offset); blocks of 4096, 16 consecutive items per thread
+__device__ uint32_t block_exclusive_scan(uint32_t x, uint32_t &total, uint32_t *s_w)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t v = x;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(v, off);
+        if (lane >= off) v += y;
+    }
+    if (lane == 63) s_w[w] = v;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int i = 0; i < w; i++) pre += s_w[i];
+    total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    __syncthreads();
+    return pre + v - x;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t *__restrict__ in, uint32_t n,
+                                                       uint32_t *__restrict__ bsum)
+{
+    __shared__ uint32_t s_w[4];
+    const size_t base = (size_t)blockIdx.x * SORT_TILE + (size_t)threadIdx.x * SORT_ITEMS;
+    uint32_t s = 0;
+    for (int i = 0; i < SORT_ITEMS; i++)
+        if (base + i < n) s += in[base + i];
+    s = wave_sum_u32(s);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+}
+
+// single workgroup: exclusive scan of nb block sums in place
+__global__ __launch_bounds__(BLOCK) void k_scan_top(uint32_t *__restrict__ bsum, uint32_t nb)
+{
+    __shared__ uint32_t s_w[4];
+    uint32_t carry = 0;
+    for (uint32_t c = 0; c < nb; c += SORT_TILE) {
+        const uint32_t base = c + threadIdx.x * SORT_ITEMS;
+        uint32_t loc[SORT_ITEMS];
+        uint32_t s = 0;
+        for (int i = 0; i < SORT_ITEMS; i++) {
+            loc[i] = (base + i < nb) ? bsum[base + i] : 0u;
+            s += loc[i];
+        }
+        uint32_t tot;
+        uint32_t pre = block_exclusive_scan(s, tot, s_w) + carry;
+        for (int i = 0; i < SORT_ITEMS; i++) {
+            if (base + i < nb) bsum[base + i] = pre;
+            pre += loc[i];
+        }
+        carry += tot;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t *__restrict__ in, uint32_t n,
+                                                     const uint32_t *__restrict__ bsum,
+                                                     uint32_t *__restrict__ out)
+{
+    __shared__ uint32_t s_w[4];
+    const size_t base = (size_t)blockIdx.x * SORT_TILE + (size_t)threadIdx.x * SORT_ITEMS;
+    uint32_t loc[SORT_ITEMS];
+    uint32_t s = 0;
+    for (int i = 0; i < SORT_ITEMS; i++) {
+        loc[i] = (base + i < n) ? in[base + i] : 0u;
+        s += loc[i];
+    }
+    uint32_t tot;
+    uint32_t pre = block_exclusive_scan(s, tot, s_w) + bsum[blockIdx.x];
+    for (int i = 0; i < SORT_ITEMS; i++) {
+        if (base + i < n) out[base + i] = pre;
+        pre += loc[i];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Stable LSD radix sort, 8-bit digits.  A pass is a per-block digit histogram,
+// an exclusive scan over (segment, digit, block), and a stable scatter that
+// ranks equal digits inside each wave with 8 ballots.  With seg_blocks > 0 the
+// key space is cut into segments of seg_blocks blocks that are sorted
+// independently (one segment per view).
+__device__ __forceinline__ size_t hist_index(uint32_t d, uint32_t blk, uint32_t nblocks, uint32_t seg_blocks)
+{
+    if (seg_blocks) {
+        const uint32_t seg = blk / seg_blocks, b = blk % seg_blocks;
+        return ((size_t)seg * 256 + d) * seg_blocks + b;
+    }
+    return (size_t)d * nblocks + blk;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint32_t *__restrict__ keys, uint32_t n, int shift,
+                                                      uint32_t *__restrict__ hist, uint32_t nblocks,
+                                                      uint32_t seg_blocks)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const size_t base = (size_t)blockIdx.x * SORT_TILE;
+    for (int i = 0; i < SORT_ITEMS; i++) {
+        const size_t idx = base + (size_t)i * BLOCK + threadIdx.x;
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[hist_index(threadIdx.x, blockIdx.x, nblocks, seg_blocks)] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_radix_scatter(const uint32_t *__restrict__ kin,
+                                                         const uint32_t *__restrict__ vin,
+                                                         uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                         uint32_t n, int shift, const uint32_t *__restrict__ offs,
+                                                         uint32_t nblocks, uint32_t seg_blocks)
+{
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wc[4][256];
+    const int t = threadIdx.x, w = t >> 6;
+    run[t] = offs[hist_index(t, blockIdx.x, nblocks, seg_blocks)];
+    wc[0][t] = 0;
+    wc[1][t] = 0;
+    wc[2][t] = 0;
+    wc[3][t] = 0;
+    __syncthreads();
+    const size_t base = (size_t)blockIdx.x * SORT_TILE;
+    for (int r = 0; r < SORT_ITEMS; r++) {
+        if (base + (size_t)r * BLOCK >= n) break;   // uniform across the block
+        const size_t idx = base + (size_t)r * BLOCK + t;
+        const bool valid = idx < n;
+        const uint32_t key = valid ? kin[idx] : 0u;
+        const uint32_t val = valid ? vin[idx] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            const uint32_t bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        const int rank = count_below(m);
+        if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(m);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + (uint32_t)rank;
+            for (int ww = 0; ww < w; ww++) pos += wc[ww][d];
+            if (pos < n) {
+                kout[pos] = key;
+                vout[pos] = val;
+            }
+        }
+        __syncthreads();
+        run[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
+        wc[0][t] = 0;
+        wc[1][t] = 0;
+        wc[2][t] = 0;
+        wc[3][t] = 0;
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
+// records into depth order; tile counts in depth order
+__global__ __launch_bounds__(BLOCK) void k_gather(const float4 *__restrict__ rec, const uint32_t *__restrict__ ntl,
+                                                  const uint32_t *__restrict__ order,
+                                                  const unsigned long long *__restrict__ counters, int64_t Kp,
+                                                  int64_t total, float4 *__restrict__ srec,
+                                                  uint32_t *__restrict__ ntl_s)
+{
+    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= total) return;
+    const int64_t v = p / Kp, s = p - v * Kp;
+    if (s < (int64_t)counters[1 + v]) {
+        const size_t i = (size_t)v * Kp + min((int64_t)order[p], Kp - 1);
+        srec[2 * p] = rec[2 * i];
+        srec[2 * p + 1] = rec[2 * i + 1];
+        ntl_s[p] = ntl[i];
+    } else {
+        ntl_s[p] = 0;
+    }
+}
+
+// one pair per covered tile, in depth order within the view
+__global__ __launch_bounds__(BLOCK) void k_emit(const float4 *__restrict__ ext, const uint32_t *__restrict__ order,
+                                                const unsigned long long *__restrict__ counters,
+                                                const uint32_t *__restrict__ poff, int64_t Kp, int64_t total,
+                                                DevGrid g, uint32_t D, uint32_t *__restrict__ pkey,
+                                                uint32_t *__restrict__ pval)
+{
+    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= total) return;
+    const int64_t v = p / Kp, s = p - v * Kp;
+    if (s >= (int64_t)counters[1 + v]) return;
+    const float4 e = ext[(size_t)v * Kp + min((int64_t)order[p], Kp - 1)];
+    int ty0, ty1, a0, a1, b0, b1;
+    if (!tile_rows(e.y, e.w, g.H, ty0, ty1)) return;
+    if (!tile_cols(e.x, e.z, g.W, g.tiles_x, a0, a1, b0, b1)) return;
+    uint32_t o = poff[p];
+    const uint32_t seg0 = (uint32_t)v * (uint32_t)g.tiles;
+    for (int ty = ty0; ty <= ty1; ty++) {
+        for (int tx = a0; tx <= a1; tx++, o++) {
+            if (o >= D) return;
+            pkey[o] = seg0 + (uint32_t)(ty * g.tiles_x + tx);
+            pval[o] = (uint32_t)p;
+        }
+        for (int tx = b0; tx <= b1; tx++, o++) {
+            if (o >= D) return;
+            pkey[o] = seg0 + (uint32_t)(ty * g.tiles_x + tx);
+            pval[o] = (uint32_t)p;
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_ranges(const uint32_t *__restrict__ skey, uint32_t D, uint32_t nseg,
+                                                  uint2 *__restrict__ ranges)
+{
+    const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= D) return;
+    const uint32_t s = skey[i];
+    if (s >= nseg) return;
+    if (i == 0 || skey[i - 1] != s) ranges[s].x = i;
+    if (i == D - 1 || skey[i + 1] != s) ranges[s].y = i + 1;
+}
+
+// ----------------------------------------------------------------------------
+// Stage 2: radiance per (receiver, sorted position)
+__global__ __launch_bounds__(BLOCK) void k_rad_direct(const float2 *__restrict__ radiance,
+                                                      const uint32_t *__restrict__ order,
+                                                      const unsigned long long *__restrict__ counters,
+                                                      const int *__restrict__ rxview, int N, int64_t Kp,
+                                                      int64_t K, float2 *__restrict__ rad)
+{
+    const int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= (int64_t)N * Kp) return;
+    const int64_t j = idx / Kp, s = idx - j * Kp;
+    const int v = rxview[j];
+    if (s < (int64_t)counters[1 + v]) rad[idx] = radiance[min((int64_t)order[(size_t)v * Kp + s], K - 1)];
+}
+
+__device__ __forceinline__ int hperm(int d) { return (d & 1) * 32 + (d >> 1); }
+
+// receiver ("global") term of layer 1: W1[:, :36] gamma(r_j), stored permuted
+__global__ __launch_bounds__(BLOCK) void k_mlp_global(const float *__restrict__ W1, const float *__restrict__ rx,
+                                                      int N, float *__restrict__ Gp)
+{
+    const int idx = blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= N * HID) return;
+    const int j = idx / HID, d = idx % HID;
+    float acc = 0.f;
+    for (int a = 0; a < 3; a++) {
+        const float r = rx[3 * j + a];
+        for (int f = 0; f < 6; f++) {
+            float sn, cs;
+            sincosf(ldexpf(r, f), &sn, &cs);
+            acc = fmaf(W1[d * MLP_IN + 12 * a + 2 * f], sn, acc);
+            acc = fmaf(W1[d * MLP_IN + 12 * a + 2 * f + 1], cs, acc);
+        }
+    }
+    Gp[(size_t)j * HID + hperm(d)] = acc;
+}
+
+// Gaussian ("local") term of layer 1: W1[:, 36:] f_k + b1, stored permuted
+__global__ __launch_bounds__(BLOCK) void k_mlp_local(const float *__restrict__ W1, const float *__restrict__ b1,
+                                                     const float *__restrict__ feat, int64_t K,
+                                                     float *__restrict__ Lp)
+{
+    const int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= K * HID) return;
+    const int64_t k = idx / HID;
+    const int d = (int)(idx % HID);
+    float acc = b1[d];
+    const float *f = feat + k * FEAT;
+    const float *w = W1 + d * MLP_IN + ENC;
+#pragma unroll
+    for (int i = 0; i < FEAT; i++) acc = fmaf(w[i], f[i], acc);
+    Lp[k * HID + hperm(d)] = acc;
+}
+
+// Per-(receiver, Gaussian) layers 2 and 3 on FP32 MFMA (v_mfma_f32_32x32x2f32).
+// One wave per work item = (view, 32 consecutive sorted positions, up to 16
+// receivers of that view).  The wave computes H2^T = W2 X1^T for its 32
+// pairs: A = W2 rows from LDS, B = X1 = relu(local + global), one pair per
+// lane pair (lane l and l + 32 hold even / odd hidden indices), so the
+// accumulator leaves each lane with 32 of the 64 hidden outputs of its own
+// pair.  Layer 3 (64 -> 2) is then a per-lane dot product plus one exchange
+// between the two lane halves.
+__global__ __launch_bounds__(BLOCK) void k_mlp_pairs(const float *__restrict__ Lp, const float *__restrict__ Gp,
+                                                     const float *__restrict__ w2a,
+                                                     const float4 *__restrict__ tab, const float *__restrict__ b3,
+                                                     const uint32_t *__restrict__ order,
+                                                     const int4 *__restrict__ items, int nitems, int64_t Kp,
+                                                     int64_t K, const unsigned long long *__restrict__ counters,
+                                                     float2 *__restrict__ rad)
+{
+    __shared__ float s_w2a[2 * 32 * 64];
+    __shared__ float4 s_tab[2 * 2 * 16];
+    for (int i = threadIdx.x; i < 2 * 32 * 64; i += BLOCK) s_w2a[i] = w2a[i];
+    if (threadIdx.x < 64) s_tab[threadIdx.x] = tab[threadIdx.x];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, h = lane >> 5, pl = lane & 31;
+    const int item = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    if (item >= nitems) return;
+    const int4 it = items[item];
+    const int view = it.x, s0 = it.y, j0 = it.z, nj = it.w;
+    const int64_t nv = (int64_t)counters[1 + view];
+    const int64_t s = s0 + pl;
+    const bool valid = s < nv;
+    const uint32_t k = (uint32_t)min((int64_t)order[(size_t)view * Kp + (valid ? s : s0)], K - 1);
+    float l[32];
+    {
+        const float4 *src = reinterpret_cast<const float4 *>(Lp + (size_t)k * HID + h * 32);
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const float4 x = src[q];
+            l[4 * q] = x.x; l[4 * q + 1] = x.y; l[4 * q + 2] = x.z; l[4 * q + 3] = x.w;
+        }
+    }
+    const float b30 = b3[0], b31 = b3[1];
+    for (int jj = 0; jj < nj; jj++) {
+        const int j = j0 + jj;
+        float x1[32];
+        const float4 *gs = reinterpret_cast<const float4 *>(Gp + (size_t)j * HID + h * 32);
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const float4 gv = gs[q];
+            x1[4 * q] = fmaxf(l[4 * q] + gv.x, 0.f);
+            x1[4 * q + 1] = fmaxf(l[4 * q + 1] + gv.y, 0.f);
+            x1[4 * q + 2] = fmaxf(l[4 * q + 2] + gv.z, 0.f);
+            x1[4 * q + 3] = fmaxf(l[4 * q + 3] + gv.w, 0.f);
+        }
+        floatx16 acc0, acc1;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            acc0[r] = s_tab[(h * 2 + 0) * 16 + r].z;
+            acc1[r] = s_tab[(h * 2 + 1) * 16 + r].z;
+        }
+#pragma unroll
+        for (int t = 0; t < 32; t++) {
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(s_w2a[(0 * 32 + t) * 64 + lane], x1[t], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(s_w2a[(1 * 32 + t) * 64 + lane], x1[t], acc1, 0, 0, 0);
+        }
+        float o0 = 0.f, o1 = 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const float4 ta = s_tab[(h * 2 + 0) * 16 + r];
+            const float4 tb = s_tab[(h * 2 + 1) * 16 + r];
+            const float ha = fmaxf(acc0[r], 0.f), hb = fmaxf(acc1[r], 0.f);
+            o0 = fmaf(ta.x, ha, o0);
+            o1 = fmaf(ta.y, ha, o1);
+            o0 = fmaf(tb.x, hb, o0);
+            o1 = fmaf(tb.y, hb, o1);
+        }
+        o0 += __shfl_xor(o0, 32);
+        o1 += __shfl_xor(o1, 32);
+        if (h == 0 && valid) rad[(size_t)j * Kp + s] = make_float2(o0 + b30, o1 + b31);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Stage 3: front-to-back compositing.  One workgroup per (tile, chunk of R
+// receivers of one view); one pixel per thread.  Batches of 256 list entries
+// (record + R radiance values) are staged in LDS; every lane walks the batch
+// with its own transmittance.  A wave stops walking once all its lanes have
+// terminated; the workgroup stops loading once all its waves have.
+template <int R>
+__global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ srec,
+                                                     const uint32_t *__restrict__ pval,
+                                                     const uint2 *__restrict__ ranges,
+                                                     const float2 *__restrict__ rad,
+                                                     const int4 *__restrict__ chunks, int64_t Kp, DevGrid g,
+                                                     float *__restrict__ C, float *__restrict__ Tfin,
+                                                     int *__restrict__ nlast, float *__restrict__ part)
+{
+    __shared__ float4 s_r0[BLOCK];
+    __shared__ float4 s_r1[BLOCK];
+    __shared__ float2 s_rad[R][BLOCK];
+    __shared__ int s_wide[BLOCK];
+    __shared__ float s_red[4][R][3];
+
+    const int tile = blockIdx.x;
+    const int4 ch = chunks[blockIdx.y];
+    const int view = ch.x, j0 = ch.y, nrx = ch.z, tslot = ch.w;
+    const int ty = tile / g.tiles_x, tx = tile - ty * g.tiles_x;
+    const int t = threadIdx.x;
+    const int row = ty * TILE + (t >> 4), col = tx * TILE + (t & 15);
+    const bool inside = row < g.H && col < g.W;
+    const float rowf = (float)row, colf = (float)col;
+    const float Wf = (float)g.W, halfW = 0.5f * (float)g.W;
+    const float tcol = (float)(tx * TILE) + 7.5f;
+    const uint2 rg = ranges[(size_t)view * g.tiles + tile];
+    const int64_t view_end = ((int64_t)view + 1) * Kp;   // pair values of this view lie below
+
+    float T = 1.f;
+    float2 acc[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) acc[r] = make_float2(0.f, 0.f);
+    int last = 0;
+    bool done = !inside;
+
+    for (uint32_t base = rg.x; base < rg.y; base += BLOCK) {
+        const uint32_t cnt = min((uint32_t)BLOCK, rg.y - base);
+        __syncthreads();
+        if ((uint32_t)t < cnt) {
+            const uint32_t p = min(pval[base + t], (uint32_t)(view_end - 1));
+            float4 r0 = srec[2 * (size_t)p];
+            const float4 r1 = srec[2 * (size_t)p + 1];
+            // representative of the azimuth closest to this tile's centre
+            const float sh = rintf((tcol - r0.x) / Wf);
+            r0.x = fmaf(sh, Wf, r0.x);
+            s_wide[t] = fabsf(tcol - (r0.x + r0.y)) >= halfW - 9.0f;
+            s_r0[t] = r0;
+            s_r1[t] = r1;
+            const int64_t s = max((int64_t)p - (int64_t)view * Kp, (int64_t)0);
+#pragma unroll
+            for (int r = 0; r < R; r++)
+                s_rad[r][t] = (r < nrx) ? rad[(size_t)(j0 + r) * Kp + s] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        if (!done) {
+            for (uint32_t e = 0; e < cnt; e++) {
+                const float4 r0 = s_r0[e];
+                const float4 r1 = s_r1[e];
+                float du = (colf - r0.x) - r0.y;
+                if (s_wide[e]) {
+                    if (du >= halfW) du -= Wf;
+                    else if (du < -halfW) du += Wf;
+                }
+                const float dv = (rowf - r0.z) - r0.w;
+                const float ex = r1.w + du * (r1.x * du + r1.y * dv) + r1.z * (dv * dv);
+                const float w = fminf(W_MAX, __builtin_amdgcn_exp2f(ex));
+                if (w < ALPHA_MIN) continue;
+                const float tw = T * w;
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const float2 sv = s_rad[r][e];
+                    acc[r].x = fmaf(tw, sv.x, acc[r].x);
+                    acc[r].y = fmaf(tw, sv.y, acc[r].y);
+                }
+                T = T * (1.f - w);
+                last = (int)(base - rg.x + e + 1);
+                if (T < T_EPS) {
+                    done = true;
+                    break;
+                }
+            }
+        }
+        if (__syncthreads_and(done ? 1 : 0)) break;
+    }
+
+    const size_t P = (size_t)g.H * g.W;
+    const size_t pix = (size_t)row * g.W + col;
+    if (inside) {
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            if (r < nrx) {
+                C[((size_t)(j0 + r) * 2) * P + pix] = acc[r].x;
+                C[((size_t)(j0 + r) * 2 + 1) * P + pix] = acc[r].y;
+            }
+        }
+        if (tslot >= 0) {
+            Tfin[(size_t)tslot * P + pix] = T;
+            nlast[(size_t)tslot * P + pix] = last;
+        }
+    }
+    // per-tile partial sums: power, Re, Im (fixed-order reduction)
+    const int lane = t & 63, w = t >> 6;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const float pw = wave_sum_f32(acc[r].x * acc[r].x + acc[r].y * acc[r].y);
+        const float sr = wave_sum_f32(acc[r].x);
+        const float si = wave_sum_f32(acc[r].y);
+        if (lane == 0) {
+            s_red[w][r][0] = pw;
+            s_red[w][r][1] = sr;
+            s_red[w][r][2] = si;
+        }
+    }
+    __syncthreads();
+    if (t < R * 3) {
+        const int r = t / 3, c = t % 3;
+        if (r < nrx) {
+            const float v = ((s_red[0][r][c] + s_red[1][r][c]) + s_red[2][r][c]) + s_red[3][r][c];
+            part[((size_t)(j0 + r) * g.tiles + tile) * 3 + c] = v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_reduce_out(const float *__restrict__ part, int N, int tiles,
+                                                      float *__restrict__ power, float *__restrict__ csum)
+{
+    const int j = blockIdx.x * BLOCK + threadIdx.x;
+    if (j >= N) return;
+    double pw = 0, sr = 0, si = 0;
+    for (int t = 0; t < tiles; t++) {
+        const float *p = part + ((size_t)j * tiles + t) * 3;
+        pw += p[0];
+        sr += p[1];
+        si += p[2];
+    }
+    if (power) power[j] = (float)pw;
+    if (csum) {
+        csum[2 * j] = (float)sr;
+        csum[2 * j + 1] = (float)si;
+    }
+}
+
+// ============================================================================
+// host-side launch wrappers
+static inline unsigned nblk(size_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
+
+bool grow(DevBuf &b, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (b.cap >= bytes) return true;
+    if (b.p) {
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        if (hipMalloc(&b.p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            b.p = nullptr;
+            return false;
+        }
+        want = bytes;
+    }
+    b.cap = want;
+    return true;
+}
+
+void release(DevBuf &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    unsigned blocks = (unsigned)std::min<size_t>(nblk(n), 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(BLOCK), 0, st, p, value, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t Kp, const DevGrid &g,
+                          Workspace &ws, hipStream_t st)
+{
+    const int vchunk = V <= 4 ? 1 : 4;
+    dim3 grid((unsigned)(Kp / BLOCK), (unsigned)((V + vchunk - 1) / vchunk));
+    hipLaunchKernelGGL(k_project, grid, dim3(BLOCK), 0, st, sc.soa.as<float>(), sc.K, Kp, centres, V, vchunk, g,
+                       ws.rec.as<float4>(), ws.ext.as<float4>(), ws.rawkey.as<uint32_t>(), ws.opac.as<float>(),
+                       ws.ntl.as<uint32_t>(), ws.skey[0].as<uint32_t>(), ws.sval[0].as<uint32_t>(),
+                       ws.counters.as<unsigned long long>());
+    return hipGetLastError();
+}
+
+// The buffers are sized by the caller before any work that may still be in
+// flight uses them (grow() frees the old buffer).
+hipError_t scan_exclusive_u32(DevBuf &scan_tmp, const uint32_t *in, uint32_t *out, uint32_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
+    if (scan_tmp.cap < (size_t)nb * 4) return hipErrorOutOfMemory;
+    uint32_t *bs = scan_tmp.as<uint32_t>();
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(BLOCK), 0, st, in, n, bs);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, st, bs, nb);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(BLOCK), 0, st, in, n, bs, out);
+    return hipGetLastError();
+}
+
+// Sort n (key, value) pairs by the low `bits` bits of the key, stably.
+// seg_len > 0: independent segments of seg_len (a multiple of SORT_TILE).
+hipError_t sort_pairs_u32(Workspace &ws, DevBuf *keys, DevBuf *vals, DevBuf &histb, DevBuf &scan_tmp, int &cur,
+                          uint32_t n, int bits, int64_t seg_len, hipStream_t st)
+{
+    (void)ws;
+    if (n == 0 || bits <= 0) return hipSuccess;
+    const uint32_t nblocks = (n + SORT_TILE - 1) / SORT_TILE;
+    const uint32_t seg_blocks = seg_len > 0 ? (uint32_t)(seg_len / SORT_TILE) : 0u;
+    const size_t nh = (size_t)nblocks * 256;
+    if (histb.cap < nh * 4) return hipErrorOutOfMemory;
+    uint32_t *hist = histb.as<uint32_t>();
+    for (int shift = 0; shift < bits; shift += 8) {
+        const uint32_t *kin = keys[cur].as<uint32_t>();
+        const uint32_t *vin = vals[cur].as<uint32_t>();
+        uint32_t *kout = keys[cur ^ 1].as<uint32_t>();
+        uint32_t *vout = vals[cur ^ 1].as<uint32_t>();
+        hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(BLOCK), 0, st, kin, n, shift, hist, nblocks,
+                           seg_blocks);
+        hipError_t e = scan_exclusive_u32(scan_tmp, hist, hist, (uint32_t)nh, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(BLOCK), 0, st, kin, vin, kout, vout, n, shift, hist,
+                           nblocks, seg_blocks);
+        cur ^= 1;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(Workspace &ws, int V, int64_t Kp, hipStream_t st)
+{
+    const int64_t total = (int64_t)V * Kp;
+    hipLaunchKernelGGL(k_gather, dim3(nblk(total)), dim3(BLOCK), 0, st, ws.rec.as<float4>(), ws.ntl.as<uint32_t>(),
+                       ws.sval[ws.sorted_buf].as<uint32_t>(), ws.counters.as<unsigned long long>(), Kp, total,
+                       ws.srec.as<float4>(), ws.ntl_s.as<uint32_t>());
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(Workspace &ws, int V, int64_t Kp, const DevGrid &g, hipStream_t st)
+{
+    const int64_t total = (int64_t)V * Kp;
+    hipLaunchKernelGGL(k_emit, dim3(nblk(total)), dim3(BLOCK), 0, st, ws.ext.as<float4>(),
+                       ws.sval[ws.sorted_buf].as<uint32_t>(), ws.counters.as<unsigned long long>(),
+                       ws.poff.as<uint32_t>(), Kp, total, g, (uint32_t)ws.D, ws.pkey[0].as<uint32_t>(),
+                       ws.pval[0].as<uint32_t>());
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st)
+{
+    const size_t nr = (size_t)ws.V * g.tiles;
+    hipError_t e = launch_fill_u32(ws.ranges.as<uint32_t>(), 0u, nr * 2, st);
+    if (e != hipSuccess || ws.D == 0) return e;
+    hipLaunchKernelGGL(k_ranges, dim3(nblk((size_t)ws.D)), dim3(BLOCK), 0, st, ws.pkey[ws.pairs_buf].as<uint32_t>(),
+                       (uint32_t)ws.D, (uint32_t)nr, ws.ranges.as<uint2>());
+    return hipGetLastError();
+}
+
+hipError_t launch_rad_direct(const Scene &sc, Workspace &ws, hipStream_t st)
+{
+    const int64_t n = (int64_t)ws.N * ws.Kp;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rad_direct, dim3(nblk(n)), dim3(BLOCK), 0, st, sc.rad.as<float2>(),
+                       ws.sval[ws.sorted_buf].as<uint32_t>(), ws.counters.as<unsigned long long>(),
+                       ws.rxview.as<int>(), ws.N, ws.Kp, ws.K, ws.rad.as<float2>());
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st)
+{
+    const float *raw = m.raw.as<float>();
+    const float *W1 = raw, *b1 = raw + HID * MLP_IN;
+    const float *b3 = raw + HID * MLP_IN + HID + HID * HID + HID + 2 * HID;
+    if (ws.N > 0)
+        hipLaunchKernelGGL(k_mlp_global, dim3(nblk((size_t)ws.N * HID)), dim3(BLOCK), 0, st, W1,
+                           ws.rxpos.as<float>(), ws.N, ws.Gp.as<float>());
+    if (sc.K > 0)
+        hipLaunchKernelGGL(k_mlp_local, dim3(nblk((size_t)sc.K * HID)), dim3(BLOCK), 0, st, W1, b1,
+                           sc.feat.as<float>(), sc.K, ws.Lp.as<float>());
+    if (ws.n_items > 0) {
+        const unsigned blocks = (unsigned)((ws.n_items + 3) / 4);
+        hipLaunchKernelGGL(k_mlp_pairs, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(), ws.Gp.as<float>(),
+                           m.w2a.as<float>(), m.tab.as<float4>(), b3, ws.sval[ws.sorted_buf].as<uint32_t>(),
+                           ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K, ws.counters.as<unsigned long long>(),
+                           ws.rad.as<float2>());
+    }
+    return hipGetLastError();
+}
+
+template <int R>
+static void blend_launch(Workspace &ws, float *C, hipStream_t st)
+{
+    dim3 grid((unsigned)ws.g.tiles, (unsigned)ws.n_chunks);
+    hipLaunchKernelGGL(k_blend_fwd<R>, grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
+                       ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
+                       ws.chunks.as<int4>(), ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
+                       ws.part.as<float>());
+}
+
+hipError_t launch_blend_fwd(Workspace &ws, float *C, hipStream_t st)
+{
+    if (ws.n_chunks == 0) return hipSuccess;
+    switch (ws.R) {
+    case 1: blend_launch<1>(ws, C, st); break;
+    case 2: blend_launch<2>(ws, C, st); break;
+    case 4: blend_launch<4>(ws, C, st); break;
+    case 8: blend_launch<8>(ws, C, st); break;
+    default: blend_launch<16>(ws, C, st); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_outputs(Workspace &ws, float *power, float *csum, hipStream_t st)
+{
+    if (ws.N == 0 || (!power && !csum)) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_out, dim3(nblk((size_t)ws.N)), dim3(BLOCK), 0, st, ws.part.as<float>(), ws.N,
+                       ws.g.tiles, power, csum);
+    return hipGetLastError();
+}
+
+}  // namespace rxgs

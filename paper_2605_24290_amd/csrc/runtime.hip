@@ -1,0 +1,575 @@
+// C-ABI entry points of librxgs: context, scene and MLP upload, the render
+// pipeline (Alg. 1 of RxGS with a view index in the sort key), exports.
+#include "rxgs_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+using namespace rxgs;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+rxgs_status fail(rxgs_ctx *ctx, rxgs_status st, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+rxgs_status hip_fail(rxgs_ctx *ctx, hipError_t e, const char *what)
+{
+    (void)hipGetLastError();
+    const rxgs_status st = (e == hipErrorOutOfMemory) ? RXGS_E_OOM : RXGS_E_DEVICE;
+    return fail(ctx, st, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, expr)                                   \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+#define GROW(ctx, buf, bytes)                                                     \
+    do {                                                                          \
+        if (!grow((buf), (bytes))) return fail(ctx, RXGS_E_OOM, "device allocation failed: " #buf); \
+    } while (0)
+
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int d)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != d) (void)hipSetDevice(d);
+    }
+    ~DeviceScope()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+__global__ void k_count_nonfinite(const float *__restrict__ p, size_t n, unsigned *__restrict__ cnt)
+{
+    size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * BLOCK;
+    unsigned c = 0;
+    for (; i < n; i += stride) c += !isfinite(p[i]);
+    if (c) atomicAdd(cnt, c);
+}
+
+// AoS inputs -> SoA planes (x, y, z, ls0, ls1, ls2, qw, qx, qy, qz, logit)
+__global__ void k_to_soa(const float *__restrict__ means, const float *__restrict__ ls,
+                         const float *__restrict__ q, const float *__restrict__ lg, int64_t K,
+                         float *__restrict__ soa)
+{
+    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= K) return;
+    for (int a = 0; a < 3; a++) soa[a * K + k] = means[3 * k + a];
+    for (int a = 0; a < 3; a++) soa[(3 + a) * K + k] = ls[3 * k + a];
+    for (int a = 0; a < 4; a++) soa[(6 + a) * K + k] = q[4 * k + a];
+    soa[10 * K + k] = lg[k];
+}
+
+bool all_finite_host(const float *p, size_t n)
+{
+    for (size_t i = 0; i < n; i++)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+int bits_for(uint64_t n)
+{
+    int b = 0;
+    while ((1ull << b) < n) b++;
+    return b;
+}
+
+// pinned host staging of the workspace (grow-only)
+bool ensure_pinned(Workspace &ws, size_t bytes)
+{
+    if (ws.h_pinned_cap >= bytes) return true;
+    if (ws.h_pinned) (void)hipHostFree(ws.h_pinned);
+    ws.h_pinned = nullptr;
+    ws.h_pinned_cap = 0;
+    size_t want = std::max<size_t>(bytes + bytes / 4, 4096);
+    if (hipHostMalloc(&ws.h_pinned, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        ws.h_pinned = nullptr;
+        return false;
+    }
+    ws.h_pinned_cap = want;
+    return true;
+}
+
+void free_workspace(Workspace &ws)
+{
+    DevBuf *bufs[] = {&ws.centres, &ws.rxpos,   &ws.rxview, &ws.rec,   &ws.ext,     &ws.rawkey, &ws.opac,
+                      &ws.ntl,     &ws.skey[0], &ws.skey[1], &ws.sval[0], &ws.sval[1], &ws.srec, &ws.ntl_s,
+                      &ws.poff,    &ws.pkey[0], &ws.pkey[1], &ws.pval[0], &ws.pval[1], &ws.ranges, &ws.rad,
+                      &ws.Lp,      &ws.Gp,      &ws.Tfin,   &ws.nlast,  &ws.part,    &ws.chunks, &ws.items,
+                      &ws.counters, &ws.hist,   &ws.scan_tmp, &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
+                      &ws.dG,      &ws.dmlp,    &ws.hist_b,  &ws.scan_b};
+    for (DevBuf *b : bufs) release(*b);
+    if (ws.staged) (void)hipEventDestroy(ws.staged);
+    if (ws.counted) (void)hipEventDestroy(ws.counted);
+    ws.staged = nullptr;
+    ws.counted = nullptr;
+    if (ws.h_pinned) (void)hipHostFree(ws.h_pinned);
+    ws.h_pinned = nullptr;
+    ws.h_pinned_cap = 0;
+    ws.valid = false;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" const char *rxgs_version(void) { return "rxgs 0.1 (gfx950)"; }
+
+extern "C" const char *rxgs_last_error(const rxgs_ctx *ctx)
+{
+    if (!ctx) return g_create_err.c_str();
+    return ctx->err.c_str();
+}
+
+extern "C" rxgs_status rxgs_create(int device, const rxgs_grid *grid, rxgs_ctx **out)
+{
+    if (!out) {
+        g_create_err = "out is NULL";
+        return RXGS_E_INVALID;
+    }
+    *out = nullptr;
+    if (!grid || grid->H < 1 || grid->W < 2 || (grid->W & 1) || grid->reserved != 0 ||
+        !std::isfinite(grid->el0) || !std::isfinite(grid->del_el) || !(grid->del_el > 0.0) ||
+        (int64_t)grid->H * grid->W > (1ll << 28)) {
+        g_create_err = "invalid grid (H >= 1, even W >= 2, finite el0, del_el > 0)";
+        return RXGS_E_INVALID;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        (void)hipGetLastError();
+        g_create_err = "no such HIP device";
+        return RXGS_E_DEVICE;
+    }
+    rxgs_ctx *ctx = new (std::nothrow) rxgs_ctx();
+    if (!ctx) {
+        g_create_err = "out of host memory";
+        return RXGS_E_OOM;
+    }
+    ctx->device = device;
+    ctx->grid = *grid;
+    DevGrid &g = ctx->g;
+    g.H = grid->H;
+    g.W = grid->W;
+    g.tiles_x = (grid->W + TILE - 1) / TILE;
+    g.tiles_y = (grid->H + TILE - 1) / TILE;
+    g.tiles = g.tiles_x * g.tiles_y;
+    g.el0 = grid->el0;
+    g.del = grid->del_el;
+    g.daz = 2.0 * M_PI / (double)grid->W;
+    *out = ctx;
+    return RXGS_OK;
+}
+
+extern "C" void rxgs_destroy(rxgs_ctx *ctx)
+{
+    if (!ctx) return;
+    DeviceScope ds(ctx->device);
+    (void)hipDeviceSynchronize();
+    free_workspace(ctx->ws);
+    release(ctx->scene.soa);
+    release(ctx->scene.rad);
+    release(ctx->scene.feat);
+    release(ctx->mlp.raw);
+    release(ctx->mlp.w2a);
+    release(ctx->mlp.tab);
+    release(ctx->stage);
+    delete ctx;
+}
+
+extern "C" rxgs_status rxgs_saved_create(rxgs_ctx *ctx, rxgs_saved **out)
+{
+    if (!ctx || !out) return fail(ctx, RXGS_E_INVALID, "NULL argument");
+    rxgs_saved *s = new (std::nothrow) rxgs_saved();
+    if (!s) return fail(ctx, RXGS_E_OOM, "out of host memory");
+    s->ctx = ctx;
+    ctx->saved.push_back(s);
+    *out = s;
+    return RXGS_OK;
+}
+
+extern "C" void rxgs_saved_destroy(rxgs_saved *s)
+{
+    if (!s) return;
+    rxgs_ctx *ctx = s->ctx;
+    DeviceScope ds(ctx->device);
+    (void)hipDeviceSynchronize();
+    free_workspace(s->ws);
+    auto &v = ctx->saved;
+    v.erase(std::remove(v.begin(), v.end(), s), v.end());
+    delete s;
+}
+
+extern "C" rxgs_status rxgs_scene_upload(rxgs_ctx *ctx, int64_t K, const float *means, const float *log_scales,
+                                         const float *quats, const float *logits, const float *radiance,
+                                         const float *features, int src_on_device, void *stream)
+{
+    if (!ctx) return RXGS_E_INVALID;
+    if (K < 0 || K > (1ll << 27)) return fail(ctx, RXGS_E_INVALID, "K out of range [0, 2^27]");
+    if (K > 0 && (radiance == nullptr) == (features == nullptr))
+        return fail(ctx, RXGS_E_INVALID, "exactly one of radiance and features must be given");
+    if (K > 0 && (!means || !log_scales || !quats || !logits))
+        return fail(ctx, RXGS_E_INVALID, "NULL scene array");
+    DeviceScope ds(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    Scene &sc = ctx->scene;
+    sc.valid = false;
+    const bool feat = features != nullptr;
+    const size_t nrad = (size_t)K * (feat ? FEAT : 2);
+    const float *radsrc = feat ? features : radiance;
+    const hipMemcpyKind kind = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (!src_on_device) {
+        if (!all_finite_host(means, 3 * K) || !all_finite_host(log_scales, 3 * K) ||
+            !all_finite_host(quats, 4 * K) || !all_finite_host(logits, K) || !all_finite_host(radsrc, nrad))
+            return fail(ctx, RXGS_E_INVALID, "non-finite value in the scene");
+        for (int64_t k = 0; k < K; k++) {
+            const float *q = quats + 4 * k;
+            if (q[0] == 0.f && q[1] == 0.f && q[2] == 0.f && q[3] == 0.f)
+                return fail(ctx, RXGS_E_INVALID, "zero quaternion");
+        }
+    }
+    GROW(ctx, sc.soa, (size_t)11 * std::max<int64_t>(K, 1) * 4);
+    GROW(ctx, ctx->stage, (size_t)12 * std::max<int64_t>(K, 1) * 4 + 256);
+    float *stg = ctx->stage.as<float>();
+    if (K > 0) {
+        HIPCHK(ctx, hipMemcpyAsync(stg, means, 12 * K, kind, st));
+        HIPCHK(ctx, hipMemcpyAsync(stg + 3 * K, log_scales, 12 * K, kind, st));
+        HIPCHK(ctx, hipMemcpyAsync(stg + 6 * K, quats, 16 * K, kind, st));
+        HIPCHK(ctx, hipMemcpyAsync(stg + 10 * K, logits, 4 * K, kind, st));
+        hipLaunchKernelGGL(k_to_soa, dim3((unsigned)((K + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, stg, stg + 3 * K,
+                           stg + 6 * K, stg + 10 * K, K, sc.soa.as<float>());
+        HIPCHK(ctx, hipGetLastError());
+    }
+    DevBuf &dst = feat ? sc.feat : sc.rad;
+    GROW(ctx, dst, std::max<size_t>(nrad, 1) * 4);
+    if (K > 0) HIPCHK(ctx, hipMemcpyAsync(dst.p, radsrc, nrad * 4, kind, st));
+    if (src_on_device && K > 0) {
+        unsigned *cnt = reinterpret_cast<unsigned *>(stg + 11 * K);
+        HIPCHK(ctx, hipMemsetAsync(cnt, 0, 4, st));
+        const unsigned blocks = (unsigned)std::min<int64_t>((11 * K + BLOCK - 1) / BLOCK, 2048);
+        hipLaunchKernelGGL(k_count_nonfinite, dim3(blocks), dim3(BLOCK), 0, st, sc.soa.as<float>(), (size_t)11 * K,
+                           cnt);
+        hipLaunchKernelGGL(k_count_nonfinite, dim3(blocks), dim3(BLOCK), 0, st, dst.as<float>(), nrad, cnt);
+        HIPCHK(ctx, hipGetLastError());
+        unsigned h = 0;
+        HIPCHK(ctx, hipMemcpyAsync(&h, cnt, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        if (h) return fail(ctx, RXGS_E_INVALID, "non-finite value in the scene");
+    }
+    sc.K = K;
+    sc.has_features = feat;
+    sc.version = ++ctx->version_counter;
+    sc.valid = true;
+    return RXGS_OK;
+}
+
+extern "C" rxgs_status rxgs_mlp_upload(rxgs_ctx *ctx, const float *params, int src_on_device, void *stream)
+{
+    if (!ctx) return RXGS_E_INVALID;
+    if (!params) return fail(ctx, RXGS_E_INVALID, "params is NULL");
+    DeviceScope ds(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<float> h(RXGS_MLP_NPARAM);
+    if (src_on_device) {
+        HIPCHK(ctx, hipMemcpyAsync(h.data(), params, sizeof(float) * h.size(), hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+    } else {
+        std::memcpy(h.data(), params, sizeof(float) * h.size());
+    }
+    if (!all_finite_host(h.data(), h.size())) return fail(ctx, RXGS_E_INVALID, "non-finite MLP parameter");
+    const float *W2 = h.data() + HID * MLP_IN + HID;
+    const float *b2 = W2 + HID * HID;
+    const float *W3 = b2 + HID;
+    // MFMA A-operand layout of W2: [mb][t][lane] = W2[32 mb + lane % 32][2 t + lane / 32]
+    std::vector<float> w2a(2 * 32 * 64);
+    for (int mb = 0; mb < 2; mb++)
+        for (int t = 0; t < 32; t++)
+            for (int l = 0; l < 64; l++) w2a[(mb * 32 + t) * 64 + l] = W2[(32 * mb + (l & 31)) * HID + 2 * t + (l >> 5)];
+    // per (lane half h, block mb, accumulator register r): hidden index d and
+    // its layer-3 weights and layer-2 bias
+    std::vector<float> tab(2 * 2 * 16 * 4, 0.f);
+    for (int hh = 0; hh < 2; hh++)
+        for (int mb = 0; mb < 2; mb++)
+            for (int r = 0; r < 16; r++) {
+                const int d = 32 * mb + 8 * (r / 4) + 4 * hh + (r % 4);
+                float *e = &tab[((hh * 2 + mb) * 16 + r) * 4];
+                e[0] = W3[d];
+                e[1] = W3[HID + d];
+                e[2] = b2[d];
+            }
+    Mlp &m = ctx->mlp;
+    m.valid = false;
+    GROW(ctx, m.raw, sizeof(float) * RXGS_MLP_NPARAM);
+    GROW(ctx, m.w2a, sizeof(float) * w2a.size());
+    GROW(ctx, m.tab, sizeof(float) * tab.size());
+    HIPCHK(ctx, hipMemcpy(m.raw.p, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(m.w2a.p, w2a.data(), sizeof(float) * w2a.size(), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(m.tab.p, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice));
+    m.version = ++ctx->version_counter;
+    m.valid = true;
+    return RXGS_OK;
+}
+
+// ============================================================================
+extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off, int N,
+                                   const float *rx, float *C, float *power, float *csum, rxgs_saved *saved,
+                                   void *stream)
+{
+    if (!ctx) return RXGS_E_INVALID;
+    if (mode != RXGS_MODE_TX && mode != RXGS_MODE_RX) return fail(ctx, RXGS_E_INVALID, "unknown mode");
+    if (N < 0) return fail(ctx, RXGS_E_INVALID, "N < 0");
+    if (N > 0 && (!rx || !C)) return fail(ctx, RXGS_E_INVALID, "rx or C is NULL");
+    if (saved && saved->ctx != ctx) return fail(ctx, RXGS_E_INVALID, "saved state of another context");
+    const Scene &sc = ctx->scene;
+    if (!sc.valid) return fail(ctx, RXGS_E_STATE, "no scene uploaded");
+    if (sc.has_features && !ctx->mlp.valid) return fail(ctx, RXGS_E_STATE, "MLP scene without an uploaded MLP");
+    std::vector<int> rxview(N);
+    int V = 0;
+    if (mode == RXGS_MODE_TX) {
+        if (Q < 1 || !tx || !rx_off) return fail(ctx, RXGS_E_INVALID, "TX mode needs Q >= 1, tx and rx_off");
+        if (rx_off[0] != 0 || rx_off[Q] != N) return fail(ctx, RXGS_E_INVALID, "rx_off must run from 0 to N");
+        for (int q = 0; q < Q; q++) {
+            if (rx_off[q + 1] < rx_off[q]) return fail(ctx, RXGS_E_INVALID, "rx_off must be non-decreasing");
+            for (int j = rx_off[q]; j < rx_off[q + 1]; j++) rxview[j] = q;
+        }
+        V = Q;
+    } else {
+        for (int j = 0; j < N; j++) rxview[j] = j;
+        V = N;
+    }
+    if (N == 0) return RXGS_OK;
+    const DevGrid &g = ctx->g;
+    const int64_t K = sc.K;
+    const int64_t Kp = round_up(std::max<int64_t>(K, 1), SORT_TILE);
+    if ((uint64_t)V * (uint64_t)Kp >= (1ull << 32) || (uint64_t)V * (uint64_t)g.tiles >= (1ull << 32))
+        return fail(ctx, RXGS_E_INVALID, "views x Gaussians exceeds 2^32; split the receivers");
+    DeviceScope ds(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    Workspace &ws = saved ? saved->ws : ctx->ws;
+    ws.valid = false;
+    if (!ws.staged) {
+        HIPCHK(ctx, hipEventCreateWithFlags(&ws.staged, hipEventDisableTiming));
+        HIPCHK(ctx, hipEventCreateWithFlags(&ws.counted, hipEventDisableTiming));
+    } else {
+        // the previous render's host-to-device copies out of the staging buffer
+        HIPCHK(ctx, hipEventSynchronize(ws.staged));
+    }
+    const size_t VK = (size_t)V * Kp;
+    ws.mode = mode;
+    ws.V = V;
+    ws.N = N;
+    ws.Q = Q;
+    ws.K = K;
+    ws.Kp = Kp;
+    ws.g = g;
+    ws.use_mlp = sc.has_features;
+    ws.h_rxview = rxview;
+
+    GROW(ctx, ws.centres, (size_t)V * 12);
+    GROW(ctx, ws.rxpos, (size_t)N * 12);
+    GROW(ctx, ws.rxview, (size_t)N * 4);
+    GROW(ctx, ws.rec, VK * 32);
+    GROW(ctx, ws.ext, VK * 16);
+    GROW(ctx, ws.rawkey, VK * 4);
+    GROW(ctx, ws.opac, VK * 4);
+    GROW(ctx, ws.ntl, VK * 4);
+    for (int b = 0; b < 2; b++) {
+        GROW(ctx, ws.skey[b], VK * 4);
+        GROW(ctx, ws.sval[b], VK * 4);
+    }
+    GROW(ctx, ws.srec, VK * 32);
+    GROW(ctx, ws.ntl_s, VK * 4);
+    GROW(ctx, ws.poff, VK * 4);
+    GROW(ctx, ws.counters, (size_t)(1 + V) * 8);
+    GROW(ctx, ws.hist, (VK / SORT_TILE) * 256 * 4);
+    // block sums of two scans: the sort histograms (VK / 16 entries) and the
+    // emission offsets (VK entries), 4096 entries per block
+    GROW(ctx, ws.scan_tmp, (std::max(VK / SORT_TILE, (VK / SORT_TILE) * 256 / SORT_TILE) + 2) * 4);
+
+    HIPCHK(ctx, hipMemcpyAsync(ws.centres.p, mode == RXGS_MODE_TX ? tx : rx, (size_t)V * 12,
+                               hipMemcpyDeviceToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(ws.rxpos.p, rx, (size_t)N * 12, hipMemcpyDeviceToDevice, st));
+    HIPCHK(ctx, launch_fill_u32(ws.counters.as<uint32_t>(), 0u, (size_t)(1 + V) * 2, st));
+
+    // stage 1: projection, then the per-view depth sort; the host waits only
+    // for the counters (visible Gaussians per view, pair count) while the sort runs
+    HIPCHK(ctx, launch_project(sc, ws.centres.as<float>(), V, Kp, g, ws, st));
+    if (!ensure_pinned(ws, (size_t)(1 + V) * 8 + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
+    unsigned long long *h_cnt = static_cast<unsigned long long *>(ws.h_pinned);
+    HIPCHK(ctx, hipMemcpyAsync(h_cnt, ws.counters.p, (size_t)(1 + V) * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipEventRecord(ws.counted, st));
+    int cur = 0;
+    HIPCHK(ctx, sort_pairs_u32(ws, ws.skey, ws.sval, ws.hist, ws.scan_tmp, cur, (uint32_t)VK, 32, Kp, st));
+    ws.sorted_buf = cur;
+    HIPCHK(ctx, launch_gather(ws, V, Kp, st));
+    HIPCHK(ctx, scan_exclusive_u32(ws.scan_tmp, ws.ntl_s.as<uint32_t>(), ws.poff.as<uint32_t>(), (uint32_t)VK, st));
+    HIPCHK(ctx, hipEventSynchronize(ws.counted));
+
+    const uint64_t D = h_cnt[0];
+    if (D >= (1ull << 32) - 1) return fail(ctx, RXGS_E_INVALID, "more than 2^32 pairs; split the receivers");
+    ws.D = (int64_t)D;
+    ws.h_nvis.assign(V, 0);
+    ws.nvis_total = 0;
+    for (int v = 0; v < V; v++) {
+        ws.h_nvis[v] = (int)h_cnt[1 + v];
+        ws.nvis_total += ws.h_nvis[v];
+    }
+
+    // receiver chunks of the blend and work items of the MLP
+    std::vector<std::vector<int>> vrx(V);
+    for (int j = 0; j < N; j++) vrx[rxview[j]].push_back(j);
+    int maxr = 1;
+    for (int v = 0; v < V; v++) maxr = std::max<int>(maxr, (int)vrx[v].size());
+    int R = 1;
+    if (mode == RXGS_MODE_TX)
+        while (R < 16 && R < maxr) R *= 2;
+    ws.R = R;
+    std::vector<int4> chunks, items;
+    for (int v = 0; v < V; v++) {
+        const auto &js = vrx[v];
+        for (size_t a = 0; a < js.size(); a += R) {
+            const int n = (int)std::min<size_t>(R, js.size() - a);
+            const int tslot = (mode == RXGS_MODE_TX) ? (a == 0 ? v : -1) : js[a];
+            chunks.push_back(make_int4(v, js[a], n, tslot));
+        }
+        if (ws.use_mlp)
+            for (int s0 = 0; s0 < ws.h_nvis[v]; s0 += MLP_PAIRS)
+                for (size_t a = 0; a < js.size(); a += MLP_RG)
+                    items.push_back(make_int4(v, s0, js[a], (int)std::min<size_t>(MLP_RG, js.size() - a)));
+    }
+    ws.n_chunks = (int)chunks.size();
+    ws.n_items = (int)items.size();
+    ws.n_tslots = (mode == RXGS_MODE_TX) ? V : N;
+
+    const size_t P = (size_t)g.H * g.W;
+    GROW(ctx, ws.pkey[0], std::max<uint64_t>(D, 1) * 4);
+    GROW(ctx, ws.pkey[1], std::max<uint64_t>(D, 1) * 4);
+    GROW(ctx, ws.pval[0], std::max<uint64_t>(D, 1) * 4);
+    GROW(ctx, ws.pval[1], std::max<uint64_t>(D, 1) * 4);
+    GROW(ctx, ws.hist_b, ((D + SORT_TILE - 1) / SORT_TILE) * 256 * 4);
+    GROW(ctx, ws.scan_b, (((D + SORT_TILE - 1) / SORT_TILE) * 256 / SORT_TILE + 2) * 4);
+    GROW(ctx, ws.ranges, (size_t)V * g.tiles * 8);
+    GROW(ctx, ws.rad, (size_t)N * Kp * 8);
+    GROW(ctx, ws.Tfin, (size_t)ws.n_tslots * P * 4);
+    GROW(ctx, ws.nlast, (size_t)ws.n_tslots * P * 4);
+    GROW(ctx, ws.part, (size_t)N * g.tiles * 12);
+    GROW(ctx, ws.chunks, std::max<size_t>(chunks.size(), 1) * 16);
+    GROW(ctx, ws.items, std::max<size_t>(items.size(), 1) * 16);
+    if (ws.use_mlp) {
+        GROW(ctx, ws.Lp, (size_t)std::max<int64_t>(K, 1) * HID * 4);
+        GROW(ctx, ws.Gp, (size_t)N * HID * 4);
+    }
+
+    // one host-to-device copy of the small descriptors
+    const size_t stage_bytes = (size_t)N * 4 + chunks.size() * 16 + items.size() * 16;
+    const size_t cnt_bytes = (size_t)(1 + V) * 8;
+    const size_t off0 = (cnt_bytes + 63) / 64 * 64;
+    if (!ensure_pinned(ws, off0 + stage_bytes + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
+    char *hp = static_cast<char *>(ws.h_pinned) + off0;
+    std::memcpy(hp, rxview.data(), (size_t)N * 4);
+    std::memcpy(hp + (size_t)N * 4, chunks.data(), chunks.size() * 16);
+    std::memcpy(hp + (size_t)N * 4 + chunks.size() * 16, items.data(), items.size() * 16);
+    HIPCHK(ctx, hipMemcpyAsync(ws.rxview.p, hp, (size_t)N * 4, hipMemcpyHostToDevice, st));
+    if (!chunks.empty())
+        HIPCHK(ctx, hipMemcpyAsync(ws.chunks.p, hp + (size_t)N * 4, chunks.size() * 16, hipMemcpyHostToDevice, st));
+    if (!items.empty())
+        HIPCHK(ctx, hipMemcpyAsync(ws.items.p, hp + (size_t)N * 4 + chunks.size() * 16, items.size() * 16,
+                                   hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipEventRecord(ws.staged, st));
+
+    // pairs: emit in depth order, stable sort by (view, tile), tile ranges
+    int pcur = 0;
+    if (D > 0) {
+        HIPCHK(ctx, launch_emit(ws, V, Kp, g, st));
+        const int sbits = bits_for((uint64_t)V * g.tiles);
+        HIPCHK(ctx, sort_pairs_u32(ws, ws.pkey, ws.pval, ws.hist_b, ws.scan_b, pcur, (uint32_t)D, sbits, 0, st));
+    }
+    ws.pairs_buf = pcur;
+    HIPCHK(ctx, launch_ranges(ws, g, st));
+
+    // stage 2: radiance per (receiver, sorted position)
+    if (ws.use_mlp)
+        HIPCHK(ctx, launch_mlp(sc, ctx->mlp, ws, st));
+    else
+        HIPCHK(ctx, launch_rad_direct(sc, ws, st));
+
+    // stage 3: compositing, then the per-receiver reductions
+    HIPCHK(ctx, launch_blend_fwd(ws, C, st));
+    HIPCHK(ctx, launch_reduce_outputs(ws, power, csum, st));
+    ws.scene_version = sc.version;
+    ws.mlp_version = ctx->mlp.version;
+    ws.valid = true;
+    return RXGS_OK;
+}
+
+// ============================================================================
+extern "C" rxgs_status rxgs_saved_info(const rxgs_saved *s, rxgs_saved_info_t *out)
+{
+    if (!s || !out) return RXGS_E_INVALID;
+    const Workspace &ws = s->ws;
+    if (!ws.valid) return RXGS_E_STATE;
+    out->K = ws.K;
+    out->K_pad = ws.Kp;
+    out->V = ws.V;
+    out->N = ws.N;
+    out->D = ws.D;
+    out->n_visible = ws.nvis_total;
+    out->tiles = ws.g.tiles;
+    out->tiles_x = ws.g.tiles_x;
+    return RXGS_OK;
+}
+
+extern "C" rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *dst, int64_t bytes, int dst_on_device)
+{
+    if (!s || !dst || bytes < 0) return RXGS_E_INVALID;
+    const Workspace &ws = s->ws;
+    rxgs_ctx *ctx = s->ctx;
+    if (!ws.valid) return fail(ctx, RXGS_E_STATE, "no forward state");
+    const size_t VK = (size_t)ws.V * ws.Kp;
+    const size_t P = (size_t)ws.g.H * ws.g.W;
+    const void *src = nullptr;
+    size_t n = 0;
+    std::vector<int> tmp;
+    switch (what) {
+    case RXGS_EXPORT_BIN: src = ws.ext.p; n = VK * 16; break;
+    case RXGS_EXPORT_KEYS: src = ws.rawkey.p; n = VK * 4; break;
+    case RXGS_EXPORT_OPACITY: src = ws.opac.p; n = VK * 4; break;
+    case RXGS_EXPORT_ORDER: src = ws.sval[ws.sorted_buf].p; n = VK * 4; break;
+    case RXGS_EXPORT_NVIS:
+        tmp = ws.h_nvis;
+        src = tmp.data();
+        n = tmp.size() * 4;
+        break;
+    case RXGS_EXPORT_PAIRS: src = ws.pval[ws.pairs_buf].p; n = (size_t)ws.D * 4; break;
+    case RXGS_EXPORT_RANGES: src = ws.ranges.p; n = (size_t)ws.V * ws.g.tiles * 8; break;
+    case RXGS_EXPORT_RADIANCE: src = ws.rad.p; n = (size_t)ws.N * ws.Kp * 8; break;
+    case RXGS_EXPORT_TFINAL: src = ws.Tfin.p; n = (size_t)ws.n_tslots * P * 4; break;
+    case RXGS_EXPORT_NLAST: src = ws.nlast.p; n = (size_t)ws.n_tslots * P * 4; break;
+    default: return fail(ctx, RXGS_E_INVALID, "unknown export");
+    }
+    if ((size_t)bytes < n) return fail(ctx, RXGS_E_INVALID, "destination too small");
+    if (n == 0) return RXGS_OK;
+    DeviceScope ds(ctx->device);
+    HIPCHK(ctx, hipDeviceSynchronize());
+    if (what == RXGS_EXPORT_NVIS) {
+        if (dst_on_device)
+            HIPCHK(ctx, hipMemcpy(dst, src, n, hipMemcpyHostToDevice));
+        else
+            std::memcpy(dst, src, n);
+        return RXGS_OK;
+    }
+    HIPCHK(ctx, hipMemcpy(dst, src, n, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    return RXGS_OK;
+}

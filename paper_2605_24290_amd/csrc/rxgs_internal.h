@@ -1,0 +1,166 @@
+// Internal declarations of librxgs (MI355X / gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rxgs.h"
+
+namespace rxgs {
+
+constexpr int TILE = RXGS_TILE;          // 16 x 16 pixel tiles, one pixel per thread
+constexpr int BLOCK = 256;               // threads per workgroup (4 wave64)
+constexpr int SORT_ITEMS = 16;           // keys per thread in the radix sort
+constexpr int SORT_TILE = BLOCK * SORT_ITEMS;  // 4096 keys per sort block
+constexpr int FEAT = RXGS_FEAT_DIM;
+constexpr int ENC = 36;
+constexpr int HID = 64;
+constexpr int MLP_IN = ENC + FEAT;
+constexpr int MLP_RG = 16;               // receivers per MLP work item
+constexpr int MLP_PAIRS = 32;            // sorted positions per MLP work item
+
+// Method constants (Alg. 1 compositing and the readings of its unstated values).
+constexpr float ALPHA_MIN = 1.0f / 255.0f;   // skip threshold on the blend weight
+constexpr float W_MAX = 0.99f;               // blend weight clamp
+constexpr float T_EPS = 1e-4f;               // early-termination transmittance
+constexpr double DILATE = 0.3;               // px^2 added to the projected covariance
+constexpr float NEAR2 = 0.04f;               // cull Gaussians closer than 0.2 m
+constexpr double H_MIN = 1e-6;               // horizontal distance floor (poles)
+constexpr double PAD_REL = 1e-4;             // conservative padding of the
+constexpr double PAD_ABS = 0.01;             //   binning ellipse box, px
+
+struct DevGrid {
+    int H, W, tiles_x, tiles_y, tiles;
+    double el0, del, daz;
+};
+
+// grow-only device buffer
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+struct Scene {
+    int64_t K = 0;
+    bool has_features = false;
+    bool valid = false;
+    uint64_t version = 0;
+    DevBuf soa;    // 11 x K: x, y, z, ls0, ls1, ls2, qw, qx, qy, qz, logit
+    DevBuf rad;    // K x 2
+    DevBuf feat;   // K x 32
+};
+
+struct Mlp {
+    bool valid = false;
+    uint64_t version = 0;
+    DevBuf raw;    // RXGS_MLP_NPARAM
+    DevBuf w2a;    // [2][32][64]  W2[32 mb + l % 32][2 t + l / 32]
+    DevBuf tab;    // [2 h][2 mb][16 r] float4 (W3[0][d], W3[1][d], b2[d], 0)
+};
+
+struct Workspace {
+    // sizes of the last render
+    int mode = 0, V = 0, N = 0, Q = 0, R = 1;
+    int64_t K = 0, Kp = 0, D = 0, nvis_total = 0;
+    uint64_t scene_version = 0, mlp_version = 0;
+    bool valid = false;
+    bool use_mlp = false;
+    DevGrid g{};
+    std::vector<int> h_nvis;          // V
+    std::vector<int> h_rxview;        // N
+    int n_chunks = 0, n_items = 0, n_tslots = 0;
+
+    DevBuf centres;   // V x 3
+    DevBuf rxpos;     // N x 3
+    DevBuf rxview;    // N int
+    DevBuf rec;       // V x Kp x 2 float4 (blend record, unsorted)
+    DevBuf ext;       // V x Kp float4 (u, v, rup, rvp)
+    DevBuf rawkey;    // V x Kp u32
+    DevBuf opac;      // V x Kp f32
+    DevBuf ntl;       // V x Kp u32 tiles per record
+    DevBuf skey[2];   // V x Kp u32 sort keys (ping-pong)
+    DevBuf sval[2];   // V x Kp u32 sort values
+    int sorted_buf = 0;
+    DevBuf srec;      // V x Kp x 2 float4 (sorted order)
+    DevBuf ntl_s;     // V x Kp u32 (sorted order)
+    DevBuf poff;      // V x Kp u32 emission offsets
+    DevBuf pkey[2];   // D u32
+    DevBuf pval[2];   // D u32
+    int pairs_buf = 0;
+    DevBuf ranges;    // V x tiles uint2
+    DevBuf rad;       // N x Kp float2
+    DevBuf Lp;        // K x 64
+    DevBuf Gp;        // N x 64
+    DevBuf Tfin;      // S x H x W
+    DevBuf nlast;     // S x H x W
+    DevBuf part;      // N x tiles x 3
+    DevBuf chunks;    // int4
+    DevBuf items;     // int4
+    DevBuf counters;  // u64: [0] D, [1..V] nvis
+    DevBuf hist;      // radix histograms (depth sort)
+    DevBuf scan_tmp;  // scan block sums (depth sort, emission offsets)
+    DevBuf hist_b;    // radix histograms (pair sort)
+    DevBuf scan_b;    // scan block sums (pair sort)
+    DevBuf nvis_d;    // V int
+    // backward scratch
+    DevBuf dS;        // N x Kp float2
+    DevBuf g2d;       // V x Kp x 8 (u, v, a, b, c, o partials)
+    DevBuf dL;        // K x 64
+    DevBuf dG;        // N x 64
+    DevBuf dmlp;      // RXGS_MLP_NPARAM f32 accumulators
+    // host staging (pinned) and the events guarding it
+    void *h_pinned = nullptr;
+    size_t h_pinned_cap = 0;
+    hipEvent_t staged = nullptr;   // last host-to-device copy out of h_pinned
+    hipEvent_t counted = nullptr;  // counters copied to h_pinned
+};
+
+}  // namespace rxgs
+
+struct rxgs_ctx {
+    int device = 0;
+    rxgs::DevGrid g{};
+    rxgs_grid grid{};
+    rxgs::Scene scene;
+    rxgs::Mlp mlp;
+    rxgs::Workspace ws;     // used when the caller passes no saved state
+    rxgs::DevBuf stage;     // scene upload staging
+    std::string err;
+    uint64_t version_counter = 0;
+    std::vector<rxgs_saved *> saved;   // live saved states
+};
+
+struct rxgs_saved {
+    rxgs_ctx *ctx = nullptr;
+    rxgs::Workspace ws;
+};
+
+namespace rxgs {
+
+// ---- launch wrappers (kernels.hip) ----
+hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t Kp, const DevGrid &g,
+                          Workspace &ws, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st);
+hipError_t sort_pairs_u32(Workspace &ws, DevBuf *keys, DevBuf *vals, DevBuf &hist, DevBuf &scan_tmp, int &cur,
+                          uint32_t n, int bits, int64_t seg_len, hipStream_t st);
+hipError_t scan_exclusive_u32(DevBuf &scan_tmp, const uint32_t *in, uint32_t *out, uint32_t n, hipStream_t st);
+hipError_t launch_gather(Workspace &ws, int V, int64_t Kp, hipStream_t st);
+hipError_t launch_emit(Workspace &ws, int V, int64_t Kp, const DevGrid &g, hipStream_t st);
+hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st);
+hipError_t launch_rad_direct(const Scene &sc, Workspace &ws, hipStream_t st);
+hipError_t launch_mlp(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st);
+hipError_t launch_blend_fwd(Workspace &ws, float *C, hipStream_t st);
+hipError_t launch_reduce_outputs(Workspace &ws, float *power, float *csum, hipStream_t st);
+hipError_t launch_backward(const Scene &sc, const Mlp &m, Workspace &ws, const float *C, const float *dC,
+                           const float *dP, const rxgs_grads &gr, hipStream_t st);
+
+bool grow(DevBuf &b, size_t bytes);
+void release(DevBuf &b);
+
+}  // namespace rxgs

@@ -1,0 +1,257 @@
+"""Python binding of librxgs (ctypes).  Argument marshalling only: every step
+of the render and its backward runs in the library's HIP kernels; PyTorch only
+provides device memory (tensors) and the current stream.
+
+The library must be built (``python -m paper_2605_24290_amd.build``); there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_int, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librxgs.so")
+
+MODE_TX = 0
+MODE_RX = 1
+MLP_NPARAM = 8706
+FEAT_DIM = 32
+TILE = 16
+
+EXPORT_BIN, EXPORT_KEYS, EXPORT_OPACITY, EXPORT_ORDER, EXPORT_NVIS, EXPORT_PAIRS, \
+    EXPORT_RANGES, EXPORT_RADIANCE, EXPORT_TFINAL, EXPORT_NLAST = range(10)
+
+STATUS = {0: "OK", 1: "E_INVALID", 2: "E_OOM", 3: "E_DEVICE", 4: "E_STATE", 5: "E_BUSY",
+          6: "E_TIMEOUT", 7: "E_CANCELLED"}
+
+
+class RxgsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class CGrid(ctypes.Structure):
+    _fields_ = [("H", c_int32), ("W", c_int32), ("reserved", c_int32),
+                ("el0", c_double), ("del_el", c_double)]
+
+
+class CGrads(ctypes.Structure):
+    _fields_ = [("means", c_void_p), ("log_scales", c_void_p), ("quats", c_void_p),
+                ("logits", c_void_p), ("radiance", c_void_p), ("features", c_void_p),
+                ("mlp", c_void_p)]
+
+
+class CSavedInfo(ctypes.Structure):
+    _fields_ = [("K", c_int64), ("K_pad", c_int64), ("V", c_int64), ("N", c_int64),
+                ("D", c_int64), ("n_visible", c_int64), ("tiles", c_int64), ("tiles_x", c_int64)]
+
+
+EXPORTED = ("rxgs_create", "rxgs_destroy", "rxgs_last_error", "rxgs_scene_upload", "rxgs_mlp_upload",
+            "rxgs_saved_create", "rxgs_saved_destroy", "rxgs_render", "rxgs_render_backward",
+            "rxgs_saved_info", "rxgs_saved_export", "rxgs_version")
+
+_lib = None
+
+
+def lib():
+    """Load librxgs.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2605_24290_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = c_void_p
+    L.rxgs_create.argtypes = [c_int, POINTER(CGrid), POINTER(vp)]
+    L.rxgs_destroy.argtypes = [vp]
+    L.rxgs_destroy.restype = None
+    L.rxgs_last_error.argtypes = [vp]
+    L.rxgs_last_error.restype = ctypes.c_char_p
+    L.rxgs_version.restype = ctypes.c_char_p
+    L.rxgs_scene_upload.argtypes = [vp, c_int64, vp, vp, vp, vp, vp, vp, c_int, vp]
+    L.rxgs_mlp_upload.argtypes = [vp, vp, c_int, vp]
+    L.rxgs_saved_create.argtypes = [vp, POINTER(vp)]
+    L.rxgs_saved_destroy.argtypes = [vp]
+    L.rxgs_saved_destroy.restype = None
+    L.rxgs_render.argtypes = [vp, c_int, c_int, vp, POINTER(c_int32), c_int, vp, vp, vp, vp, vp, vp]
+    if hasattr(L, "rxgs_render_backward"):
+        L.rxgs_render_backward.argtypes = [vp, vp, vp, vp, vp, POINTER(CGrads), vp]
+    L.rxgs_saved_info.argtypes = [vp, POINTER(CSavedInfo)]
+    L.rxgs_saved_export.argtypes = [vp, c_int, vp, c_int64, c_int]
+    for name in ("rxgs_create", "rxgs_scene_upload", "rxgs_mlp_upload", "rxgs_saved_create", "rxgs_render",
+                 "rxgs_saved_info", "rxgs_saved_export"):
+        getattr(L, name).restype = c_int
+    if hasattr(L, "rxgs_render_backward"):
+        L.rxgs_render_backward.restype = c_int
+    _lib = L
+    return L
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check(status: int, ctx=None):
+    if status != 0:
+        msg = lib().rxgs_last_error(ctx)
+        raise RxgsError(status, msg.decode() if msg else "")
+
+
+def _dev_f32(t, device):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.asarray(t, dtype=np.float32))
+    return t.to(device=device, dtype=torch.float32).contiguous()
+
+
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+class Saved:
+    """Forward state kept for the backward pass (rxgs_saved)."""
+
+    def __init__(self, renderer: "Renderer"):
+        self.renderer = renderer
+        h = c_void_p()
+        _check(lib().rxgs_saved_create(renderer._ctx, byref(h)), renderer._ctx)
+        self._h = h
+
+    def info(self) -> dict:
+        i = CSavedInfo()
+        _check(lib().rxgs_saved_info(self._h, byref(i)), self.renderer._ctx)
+        return {f: getattr(i, f) for f, _ in CSavedInfo._fields_}
+
+    def export(self, what: int, dtype, shape) -> np.ndarray:
+        out = np.zeros(shape, dtype=dtype)
+        if out.size:
+            _check(lib().rxgs_saved_export(self._h, what, out.ctypes.data_as(c_void_p), out.nbytes, 0),
+                   self.renderer._ctx)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self.renderer._ctx is not None:
+            lib().rxgs_saved_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Renderer:
+    """One librxgs context on a device, for one angular grid."""
+
+    def __init__(self, grid, device: int = 0):
+        torch = _torch()
+        self.device = torch.device("cuda", device)
+        self.grid = grid
+        self._cgrid = CGrid(int(grid.H), int(grid.W), 0, float(grid.el0), float(grid.del_el))
+        ctx = c_void_p()
+        _check(lib().rxgs_create(device, byref(self._cgrid), byref(ctx)), None)
+        self._ctx = ctx
+        self.K = 0
+        self.use_mlp = False
+
+    def _stream(self):
+        return c_void_p(_torch().cuda.current_stream(self.device).cuda_stream)
+
+    def upload_scene(self, means, log_scales, quats, logits, radiance=None, features=None):
+        ts = [_dev_f32(x, self.device) for x in (means, log_scales, quats, logits, radiance, features)]
+        K = int(ts[0].shape[0])
+        self._scene_keep = ts
+        _check(lib().rxgs_scene_upload(self._ctx, K, *[_ptr(t) for t in ts], 1, self._stream()), self._ctx)
+        self.K = K
+        self.use_mlp = features is not None
+
+    def upload_mlp(self, params):
+        if isinstance(params, (list, tuple)):
+            params = np.concatenate([np.asarray(p, dtype=np.float32).ravel() for p in params])
+        t = _dev_f32(params, self.device).reshape(-1)
+        if t.numel() != MLP_NPARAM:
+            raise ValueError(f"MLP needs {MLP_NPARAM} parameters")
+        _check(lib().rxgs_mlp_upload(self._ctx, _ptr(t), 1, self._stream()), self._ctx)
+
+    def render(self, rx, tx=None, rx_off=None, mode: str = "tx", saved: Saved | None = None,
+               want_csum: bool = False, out=None):
+        """Render receivers rx (N x 3).  Returns (C (N,2,H,W), power (N), csum or None)."""
+        torch = _torch()
+        rx_t = _dev_f32(rx, self.device).reshape(-1, 3)
+        N = int(rx_t.shape[0])
+        m = MODE_TX if mode == "tx" else MODE_RX
+        if mode not in ("tx", "rx"):
+            raise ValueError("mode must be 'tx' or 'rx'")
+        tx_t = None
+        Q = 0
+        off_arr = None
+        if m == MODE_TX:
+            tx_t = _dev_f32(tx, self.device).reshape(-1, 3)
+            Q = int(tx_t.shape[0])
+            if rx_off is None:
+                if Q != 1:
+                    raise ValueError("rx_off is needed with several transmitters")
+                rx_off = [0, N]
+            off_arr = (c_int32 * (Q + 1))(*[int(x) for x in rx_off])
+        H, W = self.grid.H, self.grid.W
+        if out is None:
+            C = torch.empty((N, 2, H, W), device=self.device, dtype=torch.float32)
+            P = torch.empty((N,), device=self.device, dtype=torch.float32)
+        else:
+            C, P = out
+        S = torch.empty((N, 2), device=self.device, dtype=torch.float32) if want_csum else None
+        _check(lib().rxgs_render(self._ctx, m, Q, _ptr(tx_t), off_arr, N, _ptr(rx_t), _ptr(C), _ptr(P), _ptr(S),
+                                 None if saved is None else saved._h, self._stream()), self._ctx)
+        return C, P, S
+
+    def backward(self, saved: Saved, C, dC, dP=None, grads: dict | None = None) -> dict:
+        """Gradients w.r.t. the scene (and MLP) given dL/dC and dL/dpower."""
+        torch = _torch()
+        K = self.K
+        dev = self.device
+        if grads is None:
+            grads = dict(means=torch.empty((K, 3), device=dev), log_scales=torch.empty((K, 3), device=dev),
+                         quats=torch.empty((K, 4), device=dev), logits=torch.empty((K,), device=dev))
+            if self.use_mlp:
+                grads["features"] = torch.empty((K, FEAT_DIM), device=dev)
+                grads["mlp"] = torch.empty((MLP_NPARAM,), device=dev)
+            else:
+                grads["radiance"] = torch.empty((K, 2), device=dev)
+        cg = CGrads(*[None if grads.get(f) is None else grads[f].data_ptr() for f, _ in CGrads._fields_])
+        dC = dC.contiguous()
+        dP_t = None if dP is None else _dev_f32(dP, dev)
+        _check(lib().rxgs_render_backward(self._ctx, saved._h, _ptr(C.contiguous()), _ptr(dC), _ptr(dP_t),
+                                          byref(cg), self._stream()), self._ctx)
+        return grads
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None:
+            lib().rxgs_destroy(self._ctx)
+        self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def grid_from(H: int, W: int, el0: float, del_el: float):
+    """Plain grid record with the attributes the Renderer needs."""
+    from .scenes import Grid
+    return Grid(H, W, el0, del_el)
+
+
+def version() -> str:
+    return lib().rxgs_version().decode()
+
+
+__all__ = ["Renderer", "Saved", "RxgsError", "lib", "version", "MODE_TX", "MODE_RX", "EXPORTED"]
