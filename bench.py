@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark of the multi-receiver Gaussian rasterizer on one MI355X.
+
+Metric: receiver-views per second on the 90 x 360 grid for one fused render
+of all receivers, beside a per-receiver launch loop (the same library called
+once per receiver) on the same GPU, as in the paper's inference comparison
+(Table 2; App. G.3).  Workload: 50,000 seeded synthetic Gaussians in a
+10 x 10 x 3 m box, 64 receivers, conditioning-MLP radiance, one transmitter.
+
+One step = one pass of the whole hot path over all receivers: projection,
+per-view depth sort, binning, pair sort, MLP radiance, compositing and the
+power reduction.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  Per-stage times come from HIP events recorded by the
+library on the launch stream during a second, profiled pass of the same
+steps; the roofline entry is for the stage with the largest share.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+METRIC = "receiver-views/s (90x360 grid) multi-rx fused vs per-rx loop; serve p50/p99"
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP32_VALU_TFLOPS = 157.3
+MLP_FLOP_PER_PAIR = 2 * 64 * 64 + 2 * 64 * 2     # layers 2 and 3 per (receiver, visible Gaussian)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c1", help="workload preset (c1 = 50k Gaussians, 64 receivers)")
+    ap.add_argument("--mode", default="rx", choices=["rx", "tx"],
+                    help="rx: each receiver is its own view; tx: receivers share the transmitter's view")
+    ap.add_argument("--loop-steps", type=int, default=3)
+    ap.add_argument("--no-loop", action="store_true")
+    ap.add_argument("--no-other-mode", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the oracle sample")
+    return ap.parse_args()
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / max(steps, 1)
+
+
+def gpu_part(args):
+    import torch
+    from paper_2605_24290_amd import rxgs
+    from paper_2605_24290_amd import scenes as S
+
+    wl = S.make_workload(args.config)
+    sc = wl.scene
+    dev = torch.device("cuda", 0)
+    r = rxgs.Renderer(wl.grid)
+    r.upload_scene(sc.means, sc.log_scales, sc.quats, sc.logits, radiance=sc.radiance, features=sc.features)
+    if sc.features is not None:
+        r.upload_mlp(S.flat_mlp(wl.mlp))
+    rx = torch.as_tensor(wl.rx, device=dev)
+    tx = torch.as_tensor(wl.tx, device=dev)
+    N = rx.shape[0]
+    H, W = wl.grid.H, wl.grid.W
+    C = torch.empty((N, 2, H, W), device=dev)
+    P = torch.empty((N,), device=dev)
+
+    def fused(mode):
+        return lambda: r.render(rx, tx=tx, mode=mode, out=(C, P))
+
+    def loop(mode):
+        def f():
+            for j in range(N):
+                r.render(rx[j:j + 1], tx=tx, mode=mode, out=(C[j:j + 1], P[j:j + 1]))
+        return f
+
+    res = {}
+    modes = [args.mode] + ([] if args.no_other_mode else [m for m in ("rx", "tx") if m != args.mode])
+    for mode in modes:
+        ms = timed(fused(mode), args.steps, args.warmup)
+        entry = {"ms_per_step": ms, "rx_views_per_s": N * 1000.0 / ms}
+        # profiled pass: per-stage event times over the same number of steps
+        r.profile(True)
+        r.profile_read(reset=True)
+        ms_prof = timed(fused(mode), args.steps, 0)
+        stages = r.profile_read(reset=True)
+        r.profile(False)
+        entry["ms_per_step_profiled"] = ms_prof
+        entry["stages_ms_per_step"] = {k: v[1] / args.steps for k, v in stages.items()}
+        entry["stage_launches"] = {k: v[0] for k, v in stages.items()}
+        # sizes of one render (visible Gaussians per view, pairs)
+        saved = rxgs.Saved(r)
+        r.render(rx, tx=tx, mode=mode, saved=saved, out=(C, P))
+        torch.cuda.synchronize()
+        info = saved.info()
+        nvis = saved.export(rxgs.EXPORT_NVIS, "int32", (info["V"],))
+        pairs_mlp = int(nvis.sum()) if mode == "rx" else int(nvis[0]) * N
+        entry["sizes"] = {"views": info["V"], "visible_total": int(nvis.sum()), "tile_pairs": info["D"],
+                          "mlp_pairs": pairs_mlp}
+        saved.close()
+        if not args.no_loop:
+            ms_loop = timed(loop(mode), args.loop_steps, 1)
+            entry["per_rx_loop"] = {"ms_per_step": ms_loop, "rx_views_per_s": N * 1000.0 / ms_loop,
+                                    "fused_speedup": ms_loop / ms}
+        res[mode] = entry
+    r.close()
+    return wl, res
+
+
+def roofline_for(entry):
+    """Roofline entry for the stage with the largest time share."""
+    st = entry["stages_ms_per_step"]
+    top = max(st, key=st.get)
+    t_s = st[top] / 1000.0
+    sz = entry["sizes"]
+    if top == "mlp_pairs":
+        flop = MLP_FLOP_PER_PAIR * sz["mlp_pairs"]
+        ach = flop / t_s / 1e12
+        return {"kernel": "k_mlp_pairs", "bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
+                "work": f"{MLP_FLOP_PER_PAIR} FLOP x {sz['mlp_pairs']} (receiver, visible Gaussian) pairs"}
+    return {"kernel": top, "bound": "unknown", "achieved": None, "peak": None, "unit": None, "frac": None,
+            "traffic": None}
+
+
+def cpu_baseline(args, wl, mode):
+    import numpy as np
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from oracle import oracle as O
+    threads = len(os.sched_getaffinity(0))
+    # calibrate on one receiver, then run a sample sized to the target time
+    rx1 = wl.rx[:1]
+    cen, rv = O.views_for(mode, wl.tx, rx1)
+    t0 = time.perf_counter()
+    O.render(wl.scene, wl.grid, cen, rx1, rv, mlp=wl.mlp, nthreads=threads)
+    t1 = time.perf_counter() - t0
+    n = int(max(1, min(wl.rx.shape[0], math.floor(args.cpu_seconds / max(t1, 1e-3)))))
+    rxs = wl.rx[:n]
+    cen, rv = O.views_for(mode, wl.tx, rxs)
+    t0 = time.perf_counter()
+    O.render(wl.scene, wl.grid, cen, rxs, rv, mlp=wl.mlp, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "receiver-views/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of {wl.rx.shape[0]} receivers, full grid, {mode} mode, FP64 C oracle, "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the receiver-sharded "
+              "multi-GPU layout is a design note, not a measured path", file=sys.stderr)
+        sys.exit(2)
+    wl, res = gpu_part(args)
+    head = res[args.mode]
+    out = {
+        "metric": METRIC,
+        "value": head["rx_views_per_s"],
+        "unit": "receiver-views/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {wl.scene.K} Gaussians, {wl.rx.shape[0]} receivers, "
+                               f"{wl.grid.H}x{wl.grid.W} grid, MLP radiance, {args.mode.upper()}-mode views",
+                   "gaussians": wl.scene.K, "receivers": int(wl.rx.shape[0]), "grid": [wl.grid.H, wl.grid.W],
+                   "mode": args.mode},
+        "fused": head,
+        "other_modes": {k: v for k, v in res.items() if k != args.mode},
+        "roofline": roofline_for(head),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, wl, args.mode)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

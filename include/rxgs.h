@@ -208,6 +208,25 @@ enum {
 };
 rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *dst, int64_t bytes, int dst_on_device);
 
+/*
+ * Stage timing.  While enabled, every pipeline stage of rxgs_render and
+ * rxgs_render_backward is bracketed by HIP events recorded on the caller's
+ * stream; rxgs_profile_read synchronises on them and returns, per stage,
+ * the number of launches and the summed event-to-event time (ms).  Stage
+ * names: project, sort_depth, gather, scan, emit, sort_pairs, ranges,
+ * mlp_global, mlp_local, mlp_pairs, rad_direct, blend_fwd, reduce, and the
+ * backward stages blend_bwd, mlp_bwd, project_bwd, bwd_misc.  `reset` clears the
+ * totals after reading.  Errors: E_INVALID, E_DEVICE.
+ */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+} rxgs_stage_time;
+
+rxgs_status rxgs_profile_enable(rxgs_ctx *ctx, int on);
+rxgs_status rxgs_profile_read(rxgs_ctx *ctx, rxgs_stage_time *out, int max_entries, int *n_entries, int reset);
+
 /* Library version string. */
 const char *rxgs_version(void);
 

@@ -852,17 +852,27 @@ hipError_t launch_rad_direct(const Scene &sc, Workspace &ws, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_mlp(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st)
+hipError_t launch_mlp_global(const Mlp &m, Workspace &ws, hipStream_t st)
+{
+    if (ws.N > 0)
+        hipLaunchKernelGGL(k_mlp_global, dim3(nblk((size_t)ws.N * HID)), dim3(BLOCK), 0, st, m.raw.as<float>(),
+                           ws.rxpos.as<float>(), ws.N, ws.Gp.as<float>());
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_local(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st)
 {
     const float *raw = m.raw.as<float>();
-    const float *W1 = raw, *b1 = raw + HID * MLP_IN;
-    const float *b3 = raw + HID * MLP_IN + HID + HID * HID + HID + 2 * HID;
-    if (ws.N > 0)
-        hipLaunchKernelGGL(k_mlp_global, dim3(nblk((size_t)ws.N * HID)), dim3(BLOCK), 0, st, W1,
-                           ws.rxpos.as<float>(), ws.N, ws.Gp.as<float>());
     if (sc.K > 0)
-        hipLaunchKernelGGL(k_mlp_local, dim3(nblk((size_t)sc.K * HID)), dim3(BLOCK), 0, st, W1, b1,
-                           sc.feat.as<float>(), sc.K, ws.Lp.as<float>());
+        hipLaunchKernelGGL(k_mlp_local, dim3(nblk((size_t)sc.K * HID)), dim3(BLOCK), 0, st, raw,
+                           raw + HID * MLP_IN, sc.feat.as<float>(), sc.K, ws.Lp.as<float>());
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_pairs(const Mlp &m, Workspace &ws, hipStream_t st)
+{
+    const float *raw = m.raw.as<float>();
+    const float *b3 = raw + HID * MLP_IN + HID + HID * HID + HID + 2 * HID;
     if (ws.n_items > 0) {
         const unsigned blocks = (unsigned)((ws.n_items + 3) / 4);
         hipLaunchKernelGGL(k_mlp_pairs, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(), ws.Gp.as<float>(),

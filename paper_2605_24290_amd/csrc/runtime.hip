@@ -126,6 +126,122 @@ void free_workspace(Workspace &ws)
 }  // namespace
 
 // ============================================================================
+// stage timing
+namespace rxgs {
+
+int Profiler::stage_id(const char *name)
+{
+    for (size_t i = 0; i < names.size(); i++)
+        if (names[i] == name) return (int)i;
+    names.emplace_back(name);
+    launches.push_back(0);
+    ms.push_back(0.0);
+    return (int)names.size() - 1;
+}
+
+hipEvent_t Profiler::take()
+{
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+void Profiler::flush()
+{
+    for (const Pending &q : pending) {
+        float t = 0.f;
+        if (hipEventSynchronize(q.b) == hipSuccess && hipEventElapsedTime(&t, q.a, q.b) == hipSuccess) {
+            launches[q.stage] += 1;
+            ms[q.stage] += t;
+        } else {
+            (void)hipGetLastError();
+        }
+        pool.push_back(q.a);
+        pool.push_back(q.b);
+    }
+    pending.clear();
+}
+
+void Profiler::release_all()
+{
+    flush();
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+}
+
+StageMark::StageMark(Profiler &prof, const char *name, hipStream_t s) : p(&prof), st(s)
+{
+    if (!p->on) return;
+    if (p->pending.size() > 65536) p->flush();
+    stage = p->stage_id(name);
+    a = p->take();
+    if (a && hipEventRecord(a, st) != hipSuccess) {
+        (void)hipGetLastError();
+        p->pool.push_back(a);
+        a = nullptr;
+    }
+}
+
+StageMark::~StageMark()
+{
+    if (!a) return;
+    hipEvent_t b = p->take();
+    if (!b || hipEventRecord(b, st) != hipSuccess) {
+        (void)hipGetLastError();
+        p->pool.push_back(a);
+        if (b) p->pool.push_back(b);
+        return;
+    }
+    p->pending.push_back({stage, a, b});
+}
+
+}  // namespace rxgs
+
+#define STAGE(ctx, name, expr)                              \
+    do {                                                    \
+        rxgs::StageMark sm_((ctx)->prof, name, st);         \
+        HIPCHK(ctx, (expr));                                \
+    } while (0)
+
+extern "C" rxgs_status rxgs_profile_enable(rxgs_ctx *ctx, int on)
+{
+    if (!ctx) return RXGS_E_INVALID;
+    DeviceScope ds(ctx->device);
+    ctx->prof.on = on != 0;
+    return RXGS_OK;
+}
+
+extern "C" rxgs_status rxgs_profile_read(rxgs_ctx *ctx, rxgs_stage_time *out, int max_entries, int *n_entries,
+                                         int reset)
+{
+    if (!ctx || max_entries < 0 || (max_entries > 0 && !out)) return RXGS_E_INVALID;
+    DeviceScope ds(ctx->device);
+    Profiler &p = ctx->prof;
+    p.flush();
+    const int n = (int)p.names.size();
+    for (int i = 0; i < n && i < max_entries; i++) {
+        std::memset(out[i].name, 0, sizeof out[i].name);
+        std::strncpy(out[i].name, p.names[i].c_str(), sizeof out[i].name - 1);
+        out[i].launches = p.launches[i];
+        out[i].total_ms = p.ms[i];
+    }
+    if (n_entries) *n_entries = n;
+    if (reset)
+        for (int i = 0; i < n; i++) {
+            p.launches[i] = 0;
+            p.ms[i] = 0.0;
+        }
+    return RXGS_OK;
+}
+
 extern "C" const char *rxgs_version(void) { return "rxgs 0.1 (gfx950)"; }
 
 extern "C" const char *rxgs_last_error(const rxgs_ctx *ctx)
@@ -178,6 +294,7 @@ extern "C" void rxgs_destroy(rxgs_ctx *ctx)
     if (!ctx) return;
     DeviceScope ds(ctx->device);
     (void)hipDeviceSynchronize();
+    ctx->prof.release_all();
     free_workspace(ctx->ws);
     release(ctx->scene.soa);
     release(ctx->scene.rad);
@@ -405,16 +522,16 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
 
     // stage 1: projection, then the per-view depth sort; the host waits only
     // for the counters (visible Gaussians per view, pair count) while the sort runs
-    HIPCHK(ctx, launch_project(sc, ws.centres.as<float>(), V, Kp, g, ws, st));
+    STAGE(ctx, "project", launch_project(sc, ws.centres.as<float>(), V, Kp, g, ws, st));
     if (!ensure_pinned(ws, (size_t)(1 + V) * 8 + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
     unsigned long long *h_cnt = static_cast<unsigned long long *>(ws.h_pinned);
     HIPCHK(ctx, hipMemcpyAsync(h_cnt, ws.counters.p, (size_t)(1 + V) * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(ctx, hipEventRecord(ws.counted, st));
     int cur = 0;
-    HIPCHK(ctx, sort_pairs_u32(ws, ws.skey, ws.sval, ws.hist, ws.scan_tmp, cur, (uint32_t)VK, 32, Kp, st));
+    STAGE(ctx, "sort_depth", sort_pairs_u32(ws, ws.skey, ws.sval, ws.hist, ws.scan_tmp, cur, (uint32_t)VK, 32, Kp, st));
     ws.sorted_buf = cur;
-    HIPCHK(ctx, launch_gather(ws, V, Kp, st));
-    HIPCHK(ctx, scan_exclusive_u32(ws.scan_tmp, ws.ntl_s.as<uint32_t>(), ws.poff.as<uint32_t>(), (uint32_t)VK, st));
+    STAGE(ctx, "gather", launch_gather(ws, V, Kp, st));
+    STAGE(ctx, "scan", scan_exclusive_u32(ws.scan_tmp, ws.ntl_s.as<uint32_t>(), ws.poff.as<uint32_t>(), (uint32_t)VK, st));
     HIPCHK(ctx, hipEventSynchronize(ws.counted));
 
     const uint64_t D = h_cnt[0];
@@ -492,22 +609,25 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     // pairs: emit in depth order, stable sort by (view, tile), tile ranges
     int pcur = 0;
     if (D > 0) {
-        HIPCHK(ctx, launch_emit(ws, V, Kp, g, st));
+        STAGE(ctx, "emit", launch_emit(ws, V, Kp, g, st));
         const int sbits = bits_for((uint64_t)V * g.tiles);
-        HIPCHK(ctx, sort_pairs_u32(ws, ws.pkey, ws.pval, ws.hist_b, ws.scan_b, pcur, (uint32_t)D, sbits, 0, st));
+        STAGE(ctx, "sort_pairs", sort_pairs_u32(ws, ws.pkey, ws.pval, ws.hist_b, ws.scan_b, pcur, (uint32_t)D, sbits, 0, st));
     }
     ws.pairs_buf = pcur;
-    HIPCHK(ctx, launch_ranges(ws, g, st));
+    STAGE(ctx, "ranges", launch_ranges(ws, g, st));
 
     // stage 2: radiance per (receiver, sorted position)
-    if (ws.use_mlp)
-        HIPCHK(ctx, launch_mlp(sc, ctx->mlp, ws, st));
-    else
-        HIPCHK(ctx, launch_rad_direct(sc, ws, st));
+    if (ws.use_mlp) {
+        STAGE(ctx, "mlp_global", launch_mlp_global(ctx->mlp, ws, st));
+        STAGE(ctx, "mlp_local", launch_mlp_local(sc, ctx->mlp, ws, st));
+        STAGE(ctx, "mlp_pairs", launch_mlp_pairs(ctx->mlp, ws, st));
+    } else {
+        STAGE(ctx, "rad_direct", launch_rad_direct(sc, ws, st));
+    }
 
     // stage 3: compositing, then the per-receiver reductions
-    HIPCHK(ctx, launch_blend_fwd(ws, C, st));
-    HIPCHK(ctx, launch_reduce_outputs(ws, power, csum, st));
+    STAGE(ctx, "blend_fwd", launch_blend_fwd(ws, C, st));
+    STAGE(ctx, "reduce", launch_reduce_outputs(ws, power, csum, st));
     ws.scene_version = sc.version;
     ws.mlp_version = ctx->mlp.version;
     ws.valid = true;

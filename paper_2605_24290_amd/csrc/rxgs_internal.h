@@ -121,6 +121,34 @@ struct Workspace {
     hipEvent_t counted = nullptr;  // counters copied to h_pinned
 };
 
+// Per-stage event timing (rxgs_profile_enable / rxgs_profile_read).
+struct Profiler {
+    bool on = false;
+    struct Pending {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::string> names;
+    std::vector<int64_t> launches;
+    std::vector<double> ms;
+    int stage_id(const char *name);
+    hipEvent_t take();
+    void flush();
+    void release_all();
+};
+
+// Records an event pair around one stage when profiling is on.
+struct StageMark {
+    Profiler *p;
+    int stage = -1;
+    hipEvent_t a = nullptr;
+    hipStream_t st;
+    StageMark(Profiler &prof, const char *name, hipStream_t s);
+    ~StageMark();
+};
+
 }  // namespace rxgs
 
 struct rxgs_ctx {
@@ -134,6 +162,7 @@ struct rxgs_ctx {
     std::string err;
     uint64_t version_counter = 0;
     std::vector<rxgs_saved *> saved;   // live saved states
+    rxgs::Profiler prof;
 };
 
 struct rxgs_saved {
@@ -154,7 +183,9 @@ hipError_t launch_gather(Workspace &ws, int V, int64_t Kp, hipStream_t st);
 hipError_t launch_emit(Workspace &ws, int V, int64_t Kp, const DevGrid &g, hipStream_t st);
 hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st);
 hipError_t launch_rad_direct(const Scene &sc, Workspace &ws, hipStream_t st);
-hipError_t launch_mlp(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st);
+hipError_t launch_mlp_global(const Mlp &m, Workspace &ws, hipStream_t st);
+hipError_t launch_mlp_local(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st);
+hipError_t launch_mlp_pairs(const Mlp &m, Workspace &ws, hipStream_t st);
 hipError_t launch_blend_fwd(Workspace &ws, float *C, hipStream_t st);
 hipError_t launch_reduce_outputs(Workspace &ws, float *power, float *csum, hipStream_t st);
 hipError_t launch_backward(const Scene &sc, const Mlp &m, Workspace &ws, const float *C, const float *dC,

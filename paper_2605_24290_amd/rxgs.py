@@ -50,9 +50,14 @@ class CSavedInfo(ctypes.Structure):
                 ("D", c_int64), ("n_visible", c_int64), ("tiles", c_int64), ("tiles_x", c_int64)]
 
 
+class CStageTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", c_int64), ("total_ms", c_double)]
+
+
 EXPORTED = ("rxgs_create", "rxgs_destroy", "rxgs_last_error", "rxgs_scene_upload", "rxgs_mlp_upload",
             "rxgs_saved_create", "rxgs_saved_destroy", "rxgs_render", "rxgs_render_backward",
-            "rxgs_saved_info", "rxgs_saved_export", "rxgs_version")
+            "rxgs_saved_info", "rxgs_saved_export", "rxgs_version", "rxgs_profile_enable",
+            "rxgs_profile_read")
 
 _lib = None
 
@@ -82,8 +87,10 @@ def lib():
         L.rxgs_render_backward.argtypes = [vp, vp, vp, vp, vp, POINTER(CGrads), vp]
     L.rxgs_saved_info.argtypes = [vp, POINTER(CSavedInfo)]
     L.rxgs_saved_export.argtypes = [vp, c_int, vp, c_int64, c_int]
+    L.rxgs_profile_enable.argtypes = [vp, c_int]
+    L.rxgs_profile_read.argtypes = [vp, POINTER(CStageTime), c_int, POINTER(c_int), c_int]
     for name in ("rxgs_create", "rxgs_scene_upload", "rxgs_mlp_upload", "rxgs_saved_create", "rxgs_render",
-                 "rxgs_saved_info", "rxgs_saved_export"):
+                 "rxgs_saved_info", "rxgs_saved_export", "rxgs_profile_enable", "rxgs_profile_read"):
         getattr(L, name).restype = c_int
     if hasattr(L, "rxgs_render_backward"):
         L.rxgs_render_backward.restype = c_int
@@ -231,6 +238,17 @@ class Renderer:
         _check(lib().rxgs_render_backward(self._ctx, saved._h, _ptr(C.contiguous()), _ptr(dC), _ptr(dP_t),
                                           byref(cg), self._stream()), self._ctx)
         return grads
+
+    def profile(self, on: bool = True):
+        """Turn per-stage event timing on or off."""
+        _check(lib().rxgs_profile_enable(self._ctx, 1 if on else 0), self._ctx)
+
+    def profile_read(self, reset: bool = True) -> dict:
+        """{stage: (launches, total_ms)} accumulated since the last reset."""
+        buf = (CStageTime * 64)()
+        n = c_int(0)
+        _check(lib().rxgs_profile_read(self._ctx, buf, 64, byref(n), 1 if reset else 0), self._ctx)
+        return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(min(n.value, 64))}
 
     def close(self):
         if getattr(self, "_ctx", None) is not None:
