@@ -1,0 +1,727 @@
+// Backward kernels of librxgs for gfx950 (App. D of RxGS: the backward runs on
+// the same (tile, receiver) grid as the forward and accumulates Gaussian-level
+// gradients over receivers and directions with atomics).
+//
+//   k_blend_bwd     reverse walk of each tile list from the last composited
+//                   entry: T_before = T_after / (1 - w) from the saved final
+//                   transmittance; per entry dL/ds (per receiver) and dL/d(u,
+//                   v, conic, opacity) summed over the wave (DPP), one atomic
+//                   per wave.                                        [VALU]
+//   k_mlp_bwd       persistent FP32-MFMA backward of layers 2 and 3 over the
+//                   same work items as the forward (recompute, dz2, dx1 =
+//                   W2^T dz2, dW2 = dz2^T x1), per-wave partial sums. [MFMA]
+//   k_mlp_*_w1      layer-1 weights (receiver and Gaussian parts), bias and
+//                   feature gradients.
+//   k_project_bwd   per (view, visible Gaussian): projected-record gradients
+//                   to mean, log-scale, quaternion and opacity logit (FP64).
+#include "device_common.h"
+
+#include <cmath>
+
+namespace rxgs {
+
+constexpr int MLPB_PART = 4096 + 64 + 128 + 2 + 62;   // dW2, db2, dW3, db3, pad
+constexpr int W1B_CHUNK = 128;                        // Gaussians per dW1b partial
+constexpr float LN2F = 0.69314718055994531f;
+
+// ----------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(BLOCK) void k_blend_bwd(
+    const float4 *__restrict__ srec, const uint32_t *__restrict__ pval, const uint2 *__restrict__ ranges,
+    const float2 *__restrict__ rad, const int4 *__restrict__ chunks, int64_t Kp, DevGrid g, int tx_mode,
+    const float *__restrict__ C, const float *__restrict__ dC, const float *__restrict__ dP,
+    const float *__restrict__ Tfin, const int *__restrict__ nlast, float *__restrict__ dS,
+    float *__restrict__ g2d)
+{
+    __shared__ float4 s_r0[BLOCK];
+    __shared__ float4 s_r1[BLOCK];
+    __shared__ float2 s_rad[R][BLOCK];
+    __shared__ int s_wide[BLOCK];
+    __shared__ uint32_t s_p[BLOCK];
+    __shared__ int s_max[4];
+
+    const int tile = blockIdx.x;
+    const int4 ch = chunks[blockIdx.y];
+    const int view = ch.x, j0 = ch.y, nrx = ch.z;
+    const int tread = tx_mode ? view : j0;
+    const int ty = tile / g.tiles_x, tx = tile - ty * g.tiles_x;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int row = ty * TILE + (t >> 4), col = tx * TILE + (t & 15);
+    const bool inside = row < g.H && col < g.W;
+    const float rowf = (float)row, colf = (float)col;
+    const float Wf = (float)g.W, halfW = 0.5f * (float)g.W;
+    const float tcol = (float)(tx * TILE) + 7.5f;
+    const uint2 rg = ranges[(size_t)view * g.tiles + tile];
+    const int64_t view_end = ((int64_t)view + 1) * Kp;
+    const size_t P = (size_t)g.H * g.W;
+    const size_t pix = (size_t)row * g.W + col;
+
+    float T = 1.f;
+    int last = 0;
+    if (inside) {
+        T = Tfin[(size_t)tread * P + pix];
+        last = nlast[(size_t)tread * P + pix];
+    }
+    float2 G[R], A[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        G[r] = make_float2(0.f, 0.f);
+        A[r] = make_float2(0.f, 0.f);
+        if (inside && r < nrx) {
+            const size_t j = (size_t)(j0 + r);
+            const float gp = dP ? 2.f * dP[j] : 0.f;
+            G[r].x = dC[(j * 2) * P + pix] + gp * C[(j * 2) * P + pix];
+            G[r].y = dC[(j * 2 + 1) * P + pix] + gp * C[(j * 2 + 1) * P + pix];
+        }
+    }
+    int m = last;
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+    if (lane == 0) s_max[wv] = m;
+    __syncthreads();
+    const int maxlast = max(max(s_max[0], s_max[1]), max(s_max[2], s_max[3]));
+
+    for (int end = maxlast; end > 0; end -= BLOCK) {
+        const int start = max(0, end - BLOCK);
+        const int cnt = end - start;
+        __syncthreads();
+        if (t < cnt) {
+            const uint32_t p = (uint32_t)min((int64_t)pval[rg.x + start + t], view_end - 1);
+            float4 r0 = srec[2 * (size_t)p];
+            const float4 r1 = srec[2 * (size_t)p + 1];
+            const float sh = rintf((tcol - r0.x) / Wf);
+            r0.x = fmaf(sh, Wf, r0.x);
+            s_wide[t] = fabsf(tcol - (r0.x + r0.y)) >= halfW - 9.0f;
+            s_r0[t] = r0;
+            s_r1[t] = r1;
+            s_p[t] = p;
+            const int64_t s = max((int64_t)p - (int64_t)view * Kp, (int64_t)0);
+#pragma unroll
+            for (int r = 0; r < R; r++)
+                s_rad[r][t] = (r < nrx) ? rad[(size_t)(j0 + r) * Kp + s] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        for (int e = cnt - 1; e >= 0; e--) {
+            bool act = inside && (start + e) < last;
+            float gu = 0.f, gv = 0.f, gca = 0.f, gcb = 0.f, gcc = 0.f, glo = 0.f;
+            float2 dsr[R];
+#pragma unroll
+            for (int r = 0; r < R; r++) dsr[r] = make_float2(0.f, 0.f);
+            if (act) {
+                const float4 r0 = s_r0[e];
+                const float4 r1 = s_r1[e];
+                float du = (colf - r0.x) - r0.y;
+                if (s_wide[e]) {
+                    if (du >= halfW) du -= Wf;
+                    else if (du < -halfW) du += Wf;
+                }
+                const float dv = (rowf - r0.z) - r0.w;
+                const float ex = blend_exponent(du, dv, r1);
+                const float wr = __builtin_amdgcn_exp2f(ex);
+                const float w = fminf(W_MAX, wr);
+                if (w >= ALPHA_MIN) {
+                    const float omw = 1.f - w;
+                    const float Tb = T / omw;
+                    const float tw = Tb * w;
+                    float dw = 0.f;
+#pragma unroll
+                    for (int r = 0; r < R; r++) {
+                        const float2 sv = s_rad[r][e];
+                        dsr[r] = make_float2(tw * G[r].x, tw * G[r].y);
+                        dw += G[r].x * (Tb * sv.x - A[r].x / omw) + G[r].y * (Tb * sv.y - A[r].y / omw);
+                        A[r].x = fmaf(tw, sv.x, A[r].x);
+                        A[r].y = fmaf(tw, sv.y, A[r].y);
+                    }
+                    if (wr < W_MAX) {
+                        const float gex = dw * w * LN2F;
+                        gu = -gex * (2.f * r1.x * du + r1.y * dv);
+                        gv = -gex * (r1.y * du + 2.f * r1.z * dv);
+                        gca = gex * du * du;
+                        gcb = gex * du * dv;
+                        gcc = gex * dv * dv;
+                        glo = gex;
+                    }
+                    T = Tb;
+                } else {
+                    act = false;
+                }
+            }
+            if (__ballot(act) == 0) continue;   // uniform across the wave
+            const uint32_t p = s_p[e];
+            float vals[6] = {gu, gv, gca, gcb, gcc, glo};
+#pragma unroll
+            for (int c = 0; c < 6; c++) {
+                const float v = wave_sum_last(vals[c]);
+                if (lane == 63 && v != 0.f) atomicAdd(&g2d[(size_t)p * 8 + c], v);
+            }
+            const int64_t s = (int64_t)p - (int64_t)view * Kp;
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                if (r < nrx) {
+                    const float vx = wave_sum_last(dsr[r].x);
+                    const float vy = wave_sum_last(dsr[r].y);
+                    if (lane == 63) {
+                        float *d = dS + ((size_t)(j0 + r) * Kp + s) * 2;
+                        if (vx != 0.f) atomicAdd(d, vx);
+                        if (vy != 0.f) atomicAdd(d + 1, vy);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// direct radiance: dL/d radiance_k = sum over receivers of dL/ds at k's positions
+__global__ __launch_bounds__(BLOCK) void k_rad_direct_bwd(const float2 *__restrict__ dS,
+                                                          const uint32_t *__restrict__ order,
+                                                          const unsigned long long *__restrict__ counters,
+                                                          const int *__restrict__ rxview, int N, int64_t Kp,
+                                                          int64_t K, float *__restrict__ grad)
+{
+    const int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= (int64_t)N * Kp) return;
+    const int64_t j = idx / Kp, s = idx - j * Kp;
+    const int v = rxview[j];
+    if (s >= (int64_t)counters[1 + v]) return;
+    const float2 d = dS[idx];
+    if (d.x == 0.f && d.y == 0.f) return;
+    const int64_t k = min((int64_t)order[(size_t)v * Kp + s], K - 1);
+    atomicAdd(&grad[2 * k], d.x);
+    atomicAdd(&grad[2 * k + 1], d.y);
+}
+
+// ----------------------------------------------------------------------------
+// MLP backward, layers 2 and 3, persistent waves.  Per work item (view, 32
+// sorted positions, receivers) and receiver:
+//   x1 = relu(L_k + G_j)                     lane = pair, hid_of order
+//   z2 = b2 + W2 x1          (MFMA, A = w2a)   lane = pair
+//   dz2 = (W3^T ds) * [z2 > 0]
+//   dx1 = (W2^T dz2) * [x1 > 0]  (MFMA, A = w2b, B = dz2 registers)
+//   dL_k += dx1 (registers), dG_j += sum over pairs of dx1 (DPP, atomics)
+//   z2 transposed through LDS to lane = hidden unit, then
+//   dW2 += dz2^T x1 over the 32 pairs (MFMA), db2, dW3, db3 (VALU)
+__global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
+    const float *__restrict__ Lp, const float *__restrict__ Gp, const float *__restrict__ w2a,
+    const float *__restrict__ w2b, const float4 *__restrict__ tab, const float *__restrict__ W3,
+    const uint32_t *__restrict__ order, const int4 *__restrict__ items, int nitems, int64_t Kp, int64_t K,
+    const unsigned long long *__restrict__ counters, const float2 *__restrict__ dS, float *__restrict__ dL,
+    float *__restrict__ dG, float *__restrict__ part)
+{
+    __shared__ float s_w2a[2 * 32 * 64];
+    __shared__ float s_w2b[2 * 32 * 64];
+    __shared__ float4 s_tab[64];
+    __shared__ float s_z2[4][32][65];
+    __shared__ float2 s_ds[4][32];
+    for (int i = threadIdx.x; i < 2 * 32 * 64; i += BLOCK) {
+        s_w2a[i] = w2a[i];
+        s_w2b[i] = w2b[i];
+    }
+    if (threadIdx.x < 64) s_tab[threadIdx.x] = tab[threadIdx.x];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, h = lane >> 5, pl = lane & 31, wv = threadIdx.x >> 6;
+    const int gw = blockIdx.x * (BLOCK / 64) + wv, nw = gridDim.x * (BLOCK / 64);
+    floatx16 dw2[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) dw2[a][b][r] = 0.f;
+    float db2a[2] = {0.f, 0.f}, dw3a[2][2] = {{0.f, 0.f}, {0.f, 0.f}}, db3a[2] = {0.f, 0.f};
+    float w3o[2][2];
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int ob = 0; ob < 2; ob++) w3o[c][ob] = W3[c * HID + pl + 32 * ob];
+    const int pos_i0 = hid_pos(pl), pos_i1 = hid_pos(pl + 32);
+
+    for (int item = gw; item < nitems; item += nw) {
+        const int4 it = items[item];
+        const int view = it.x, s0 = it.y, j0 = it.z, nj = it.w;
+        const int64_t nv = (int64_t)counters[1 + view];
+        const int64_t s = s0 + pl;
+        const bool valid = s < nv;
+        const size_t obase = (size_t)view * Kp;
+        const uint32_t k = (uint32_t)min((int64_t)order[obase + (valid ? s : s0)], K - 1);
+        float l[32];
+        {
+            const float4 *src = reinterpret_cast<const float4 *>(Lp + (size_t)k * HID + h * 32);
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const float4 x = src[q];
+                l[4 * q] = x.x; l[4 * q + 1] = x.y; l[4 * q + 2] = x.z; l[4 * q + 3] = x.w;
+            }
+        }
+        // Gaussians of the pairs 2 t + h, for the lane = hidden-unit layout
+        float lt0[16], lt1[16];
+#pragma unroll
+        for (int tt = 0; tt < 16; tt++) {
+            const int64_t sp = min((int64_t)(s0 + 2 * tt + h), nv - 1);
+            const uint32_t kp = (uint32_t)min((int64_t)order[obase + sp], K - 1);
+            lt0[tt] = Lp[(size_t)kp * HID + pos_i0];
+            lt1[tt] = Lp[(size_t)kp * HID + pos_i1];
+        }
+        float dl[32];
+#pragma unroll
+        for (int q = 0; q < 32; q++) dl[q] = 0.f;
+
+        for (int jj = 0; jj < nj; jj++) {
+            const int j = j0 + jj;
+            const float2 dsv = valid ? dS[(size_t)j * Kp + s] : make_float2(0.f, 0.f);
+            float x1[32];
+            {
+                const float4 *gs = reinterpret_cast<const float4 *>(Gp + (size_t)j * HID + h * 32);
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    const float4 gv = gs[q];
+                    x1[4 * q] = fmaxf(l[4 * q] + gv.x, 0.f);
+                    x1[4 * q + 1] = fmaxf(l[4 * q + 1] + gv.y, 0.f);
+                    x1[4 * q + 2] = fmaxf(l[4 * q + 2] + gv.z, 0.f);
+                    x1[4 * q + 3] = fmaxf(l[4 * q + 3] + gv.w, 0.f);
+                }
+            }
+            floatx16 a0, a1;
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                a0[r] = s_tab[(h * 2 + 0) * 16 + r].z;
+                a1[r] = s_tab[(h * 2 + 1) * 16 + r].z;
+            }
+#pragma unroll
+            for (int tt = 0; tt < 32; tt++) {
+                a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(s_w2a[(0 * 32 + tt) * 64 + lane], x1[tt], a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f32_32x32x2f32(s_w2a[(1 * 32 + tt) * 64 + lane], x1[tt], a1, 0, 0, 0);
+            }
+            float dz[32];
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const float4 ta = s_tab[(h * 2 + 0) * 16 + r];
+                const float4 tb = s_tab[(h * 2 + 1) * 16 + r];
+                dz[r] = a0[r] > 0.f ? ta.x * dsv.x + ta.y * dsv.y : 0.f;
+                dz[16 + r] = a1[r] > 0.f ? tb.x * dsv.x + tb.y * dsv.y : 0.f;
+                s_z2[wv][pl][hid_of(h, r)] = a0[r];
+                s_z2[wv][pl][hid_of(h, 16 + r)] = a1[r];
+            }
+            if (h == 0) s_ds[wv][pl] = dsv;
+            floatx16 c0, c1;
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                c0[r] = 0.f;
+                c1[r] = 0.f;
+            }
+#pragma unroll
+            for (int tt = 0; tt < 32; tt++) {
+                c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(s_w2b[(0 * 32 + tt) * 64 + lane], dz[tt], c0, 0, 0, 0);
+                c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(s_w2b[(1 * 32 + tt) * 64 + lane], dz[tt], c1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const float d0 = x1[r] > 0.f ? c0[r] : 0.f;
+                const float d1 = x1[16 + r] > 0.f ? c1[r] : 0.f;
+                dl[r] += d0;
+                dl[16 + r] += d1;
+                const float s0v = half_wave_sum(d0);
+                const float s1v = half_wave_sum(d1);
+                if (pl == 31) {
+                    if (s0v != 0.f) atomicAdd(&dG[(size_t)j * HID + h * 32 + r], s0v);
+                    if (s1v != 0.f) atomicAdd(&dG[(size_t)j * HID + h * 32 + 16 + r], s1v);
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            const float g_i0 = Gp[(size_t)j * HID + pos_i0], g_i1 = Gp[(size_t)j * HID + pos_i1];
+#pragma unroll
+            for (int tt = 0; tt < 16; tt++) {
+                const int pr = 2 * tt + h;
+                const float2 d = s_ds[wv][pr];
+                const float z0 = s_z2[wv][pr][pl], z1 = s_z2[wv][pr][pl + 32];
+                const float m0 = z0 > 0.f ? 1.f : 0.f, m1 = z1 > 0.f ? 1.f : 0.f;
+                const float dzt0 = m0 * (w3o[0][0] * d.x + w3o[1][0] * d.y);
+                const float dzt1 = m1 * (w3o[0][1] * d.x + w3o[1][1] * d.y);
+                db2a[0] += dzt0;
+                db2a[1] += dzt1;
+                dw3a[0][0] = fmaf(d.x, m0 * z0, dw3a[0][0]);
+                dw3a[1][0] = fmaf(d.y, m0 * z0, dw3a[1][0]);
+                dw3a[0][1] = fmaf(d.x, m1 * z1, dw3a[0][1]);
+                dw3a[1][1] = fmaf(d.y, m1 * z1, dw3a[1][1]);
+                const float xb0 = fmaxf(lt0[tt] + g_i0, 0.f), xb1 = fmaxf(lt1[tt] + g_i1, 0.f);
+                dw2[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(dzt0, xb0, dw2[0][0], 0, 0, 0);
+                dw2[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(dzt0, xb1, dw2[0][1], 0, 0, 0);
+                dw2[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(dzt1, xb0, dw2[1][0], 0, 0, 0);
+                dw2[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(dzt1, xb1, dw2[1][1], 0, 0, 0);
+            }
+            if (lane == 0)
+                for (int q = 0; q < 32; q++) {
+                    db3a[0] += s_ds[wv][q].x;
+                    db3a[1] += s_ds[wv][q].y;
+                }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (valid)
+#pragma unroll
+            for (int q = 0; q < 32; q++)
+                if (dl[q] != 0.f) atomicAdd(&dL[(size_t)k * HID + h * 32 + q], dl[q]);
+    }
+    // per-wave partial sums (natural layouts), reduced in a fixed order later
+    float *pw = part + (size_t)gw * MLPB_PART;
+#pragma unroll
+    for (int ob = 0; ob < 2; ob++)
+#pragma unroll
+        for (int ib = 0; ib < 2; ib++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const int o = 32 * ob + 8 * (r >> 2) + 4 * h + (r & 3);
+                const int i = 32 * ib + pl;
+                pw[o * HID + i] = dw2[ob][ib][r];
+            }
+#pragma unroll
+    for (int ob = 0; ob < 2; ob++) {
+        const float b = db2a[ob] + __shfl_xor(db2a[ob], 32);
+        const float w0 = dw3a[0][ob] + __shfl_xor(dw3a[0][ob], 32);
+        const float w1 = dw3a[1][ob] + __shfl_xor(dw3a[1][ob], 32);
+        if (h == 0) {
+            pw[4096 + pl + 32 * ob] = b;
+            pw[4096 + 64 + pl + 32 * ob] = w0;
+            pw[4096 + 64 + 64 + pl + 32 * ob] = w1;
+        }
+    }
+    if (lane == 0) {
+        pw[4096 + 192] = db3a[0];
+        pw[4096 + 193] = db3a[1];
+    }
+}
+
+// fixed-order sum of the per-wave partials into the flat MLP gradient
+__global__ __launch_bounds__(BLOCK) void k_mlp_bwd_reduce(const float *__restrict__ part, int nwaves,
+                                                          float *__restrict__ gmlp)
+{
+    const int e = blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= 4096 + 194) return;
+    double acc = 0.0;
+    for (int w = 0; w < nwaves; w++) acc += part[(size_t)w * MLPB_PART + e];
+    const int W2OFF = HID * MLP_IN + HID, B2OFF = W2OFF + HID * HID, W3OFF = B2OFF + HID, B3OFF = W3OFF + 2 * HID;
+    int dst;
+    if (e < 4096) dst = W2OFF + e;
+    else if (e < 4096 + 64) dst = B2OFF + (e - 4096);
+    else if (e < 4096 + 192) dst = W3OFF + (e - 4096 - 64);
+    else dst = B3OFF + (e - 4096 - 192);
+    gmlp[dst] = (float)acc;
+}
+
+// layer 1, receiver part and bias: dW1[:, :36] = sum_j dG_j gamma(r_j)^T, db1 = sum_j dG_j
+__global__ __launch_bounds__(BLOCK) void k_mlp_w1a(const float *__restrict__ dG, const float *__restrict__ rx, int N,
+                                                   float *__restrict__ gmlp)
+{
+    const int idx = blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= HID * (ENC + 1)) return;
+    const int d = idx / (ENC + 1), e = idx % (ENC + 1);
+    const int pos = hid_pos(d);
+    double acc = 0.0;
+    if (e == ENC) {
+        for (int j = 0; j < N; j++) acc += dG[(size_t)j * HID + pos];
+        gmlp[HID * MLP_IN + d] = (float)acc;
+        return;
+    }
+    const int a = e / 12, f = (e % 12) / 2, cs = e & 1;
+    for (int j = 0; j < N; j++) {
+        float sn, cn;
+        sincosf(ldexpf(rx[3 * j + a], f), &sn, &cn);
+        acc += (double)dG[(size_t)j * HID + pos] * (double)(cs ? cn : sn);
+    }
+    gmlp[d * MLP_IN + e] = (float)acc;
+}
+
+// layer 1, Gaussian part: partial sums of dL_k f_k^T over chunks of Gaussians
+__global__ __launch_bounds__(BLOCK) void k_mlp_w1b_part(const float *__restrict__ dL, const float *__restrict__ feat,
+                                                        int64_t K, float *__restrict__ part)
+{
+    __shared__ float s_dl[W1B_CHUNK][HID + 1];
+    __shared__ float s_f[W1B_CHUNK][FEAT + 1];
+    const int64_t k0 = (int64_t)blockIdx.x * W1B_CHUNK;
+    const int n = (int)min((int64_t)W1B_CHUNK, K - k0);
+    for (int i = threadIdx.x; i < W1B_CHUNK * HID; i += BLOCK) {
+        const int kk = i / HID, d = i % HID;
+        s_dl[kk][d] = kk < n ? dL[(size_t)(k0 + kk) * HID + hid_pos(d)] : 0.f;
+    }
+    for (int i = threadIdx.x; i < W1B_CHUNK * FEAT; i += BLOCK) {
+        const int kk = i / FEAT, c = i % FEAT;
+        s_f[kk][c] = kk < n ? feat[(size_t)(k0 + kk) * FEAT + c] : 0.f;
+    }
+    __syncthreads();
+    // 2048 outputs (64 x 32), 8 per thread
+    for (int o = threadIdx.x; o < HID * FEAT; o += BLOCK) {
+        const int d = o / FEAT, c = o % FEAT;
+        float acc = 0.f;
+        for (int kk = 0; kk < n; kk++) acc = fmaf(s_dl[kk][d], s_f[kk][c], acc);
+        part[(size_t)blockIdx.x * HID * FEAT + o] = acc;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_mlp_w1b_reduce(const float *__restrict__ part, int nchunks,
+                                                          float *__restrict__ gmlp)
+{
+    const int o = blockIdx.x * BLOCK + threadIdx.x;
+    if (o >= HID * FEAT) return;
+    double acc = 0.0;
+    for (int c = 0; c < nchunks; c++) acc += part[(size_t)c * HID * FEAT + o];
+    const int d = o / FEAT, c = o % FEAT;
+    gmlp[d * MLP_IN + ENC + c] = (float)acc;
+}
+
+// feature gradients: df_k = W1[:, 36:]^T dL_k
+__global__ __launch_bounds__(BLOCK) void k_mlp_dfeat(const float *__restrict__ dL, const float *__restrict__ W1,
+                                                     int64_t K, float *__restrict__ gfeat)
+{
+    const int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= K * FEAT) return;
+    const int64_t k = idx / FEAT;
+    const int c = (int)(idx % FEAT);
+    float acc = 0.f;
+    for (int d = 0; d < HID; d++) acc = fmaf(W1[d * MLP_IN + ENC + c], dL[(size_t)k * HID + hid_pos(d)], acc);
+    gfeat[idx] = acc;
+}
+
+// ----------------------------------------------------------------------------
+// projection backward (FP64), one thread per (view, visible sorted position)
+struct d3 {
+    double v, x, y, z;
+};
+__device__ __forceinline__ d3 D3(double v, double x, double y, double z) { return {v, x, y, z}; }
+__device__ __forceinline__ d3 operator+(d3 a, d3 b) { return {a.v + b.v, a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ d3 operator-(d3 a, d3 b) { return {a.v - b.v, a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ d3 operator*(d3 a, d3 b)
+{
+    return {a.v * b.v, a.x * b.v + a.v * b.x, a.y * b.v + a.v * b.y, a.z * b.v + a.v * b.z};
+}
+__device__ __forceinline__ d3 operator*(d3 a, double s) { return {a.v * s, a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ d3 operator-(d3 a) { return {-a.v, -a.x, -a.y, -a.z}; }
+__device__ __forceinline__ d3 inv(d3 a)
+{
+    const double r = 1.0 / a.v, r2 = -r * r;
+    return {r, a.x * r2, a.y * r2, a.z * r2};
+}
+__device__ __forceinline__ d3 dsqrt3(d3 a)
+{
+    const double s = sqrt(a.v), k = 0.5 / s;
+    return {s, a.x * k, a.y * k, a.z * k};
+}
+
+__global__ __launch_bounds__(BLOCK) void k_project_bwd(
+    const float *__restrict__ soa, int64_t K, int64_t Kp, const float *__restrict__ centres, int V, DevGrid g,
+    const uint32_t *__restrict__ order, const unsigned long long *__restrict__ counters,
+    const float *__restrict__ g2d, float *__restrict__ gmeans, float *__restrict__ gls, float *__restrict__ gq,
+    float *__restrict__ glogit)
+{
+    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= (int64_t)V * Kp) return;
+    const int64_t v = p / Kp, s = p - v * Kp;
+    if (s >= (int64_t)counters[1 + v]) return;
+    const float *gg = g2d + (size_t)p * 8;
+    const double g_u = gg[0], g_v = gg[1], g_ca = gg[2], g_cb = gg[3], g_cc = gg[4], g_lo = gg[5];
+    if (g_u == 0 && g_v == 0 && g_ca == 0 && g_cb == 0 && g_cc == 0 && g_lo == 0) return;
+    const int64_t k = min((int64_t)order[p], K - 1);
+
+    const double px = soa[k], py = soa[K + k], pz = soa[2 * K + k];
+    double s2[3];
+    for (int a = 0; a < 3; a++) s2[a] = exp(2.0 * (double)soa[(3 + a) * K + k]);
+    const double q0 = soa[6 * K + k], q1 = soa[7 * K + k], q2 = soa[8 * K + k], q3 = soa[9 * K + k];
+    const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    const double w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
+    double R[3][3];
+    R[0][0] = 1.0 - 2.0 * (y * y + z * z); R[0][1] = 2.0 * (x * y - w * z); R[0][2] = 2.0 * (x * z + w * y);
+    R[1][0] = 2.0 * (x * y + w * z); R[1][1] = 1.0 - 2.0 * (x * x + z * z); R[1][2] = 2.0 * (y * z - w * x);
+    R[2][0] = 2.0 * (x * z - w * y); R[2][1] = 2.0 * (y * z + w * x); R[2][2] = 1.0 - 2.0 * (x * x + y * y);
+    double S[3][3];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) S[a][b] = R[a][0] * s2[0] * R[b][0] + R[a][1] * s2[1] * R[b][1] + R[a][2] * s2[2] * R[b][2];
+    const double o = 1.0 / (1.0 + exp(-(double)soa[10 * K + k]));
+
+    const double cx = centres[3 * v], cy = centres[3 * v + 1], cz = centres[3 * v + 2];
+    const d3 dx = D3(px - cx, 1, 0, 0), dy = D3(py - cy, 0, 1, 0), dz = D3(pz - cz, 0, 0, 1);
+    d3 hh = dx * dx + dy * dy;
+    d3 h = dsqrt3(hh);
+    if (!(h.v >= H_MIN)) {
+        h = D3(H_MIN, 0, 0, 0);
+        hh = h * h;
+    }
+    const d3 rh2 = hh + dz * dz;
+    const d3 ihh = inv(hh), irh2h = inv(rh2 * h);
+    const double idaz = 1.0 / g.daz, idel = 1.0 / g.del;
+    d3 mu[3], mv[3];
+    mu[0] = (-dy) * ihh * idaz;
+    mu[1] = dx * ihh * idaz;
+    mu[2] = D3(0, 0, 0, 0);
+    mv[0] = (-(dx * dz)) * irh2h * idel;
+    mv[1] = (-(dy * dz)) * irh2h * idel;
+    mv[2] = h * inv(rh2) * idel;
+    double Smu[3], Smv[3];
+    for (int a = 0; a < 3; a++) {
+        Smu[a] = S[a][0] * mu[0].v + S[a][1] * mu[1].v + S[a][2] * mu[2].v;
+        Smv[a] = S[a][0] * mv[0].v + S[a][1] * mv[1].v + S[a][2] * mv[2].v;
+    }
+    const double A = mu[0].v * Smu[0] + mu[1].v * Smu[1] + DILATE;
+    const double B = mu[0].v * Smv[0] + mu[1].v * Smv[1] + mu[2].v * Smv[2];
+    const double Cc = mv[0].v * Smv[0] + mv[1].v * Smv[1] + mv[2].v * Smv[2] + DILATE;
+    const double det = A * Cc - B * B, id2 = 1.0 / (det * det);
+
+    // record parameters (ca, cb, cc, lo) -> conic (a, b, c) and opacity
+    constexpr double L2E = 1.4426950408889634;
+    const double g_a = -0.5 * L2E * g_ca, g_b = -L2E * g_cb, g_c = -0.5 * L2E * g_cc;
+    const double g_o = g_lo / (o * 0.69314718055994531);
+    // conic = inverse of [[A, B], [B, Cc]]
+    const double g_A = (-Cc * Cc * g_a + B * Cc * g_b - B * B * g_c) * id2;
+    const double g_B = (2.0 * B * Cc * g_a - (A * Cc + B * B) * g_b + 2.0 * A * B * g_c) * id2;
+    const double g_C = (-B * B * g_a + A * B * g_b - A * A * g_c) * id2;
+    // Jacobian rows
+    double g_mu[3], g_mv[3];
+    for (int a = 0; a < 3; a++) {
+        g_mu[a] = 2.0 * g_A * Smu[a] + g_B * Smv[a];
+        g_mv[a] = 2.0 * g_C * Smv[a] + g_B * Smu[a];
+    }
+    double gp[3] = {0, 0, 0};
+    for (int a = 0; a < 3; a++) {
+        const double wu = g_mu[a], wvv = g_mv[a];
+        gp[0] += wu * mu[a].x + wvv * mv[a].x;
+        gp[1] += wu * mu[a].y + wvv * mv[a].y;
+        gp[2] += wu * mu[a].z + wvv * mv[a].z;
+    }
+    for (int a = 0; a < 3; a++) gp[a] += g_u * mu[a].v + g_v * mv[a].v;
+    // covariance: gS = g_A mu mu^T + g_B mu mv^T + g_C mv mv^T
+    double gS[3][3];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++)
+            gS[a][b] = g_A * mu[a].v * mu[b].v + g_B * mu[a].v * mv[b].v + g_C * mv[a].v * mv[b].v;
+    // Sigma = R diag(s2) R^T
+    double gR[3][3];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            double acc = 0.0;
+            for (int c = 0; c < 3; c++) acc += (gS[a][c] + gS[c][a]) * R[c][b];
+            gR[a][b] = acc * s2[b];
+        }
+    double gls_[3];
+    for (int b = 0; b < 3; b++) {
+        double acc = 0.0;
+        for (int a = 0; a < 3; a++)
+            for (int c = 0; c < 3; c++) acc += R[a][b] * gS[a][c] * R[c][b];
+        gls_[b] = acc * 2.0 * s2[b];
+    }
+    // rotation from the normalised quaternion (w, x, y, z)
+    const double gw = 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
+    const double gx = 2.0 * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2.0 * x * gR[1][1] - w * gR[1][2] +
+                             z * gR[2][0] + w * gR[2][1] - 2.0 * x * gR[2][2]);
+    const double gy = 2.0 * (-2.0 * y * gR[0][0] + x * gR[0][1] + w * gR[0][2] + x * gR[1][0] + z * gR[1][2] -
+                             w * gR[2][0] + z * gR[2][1] - 2.0 * y * gR[2][2]);
+    const double gz = 2.0 * (-2.0 * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.0 * z * gR[1][1] +
+                             y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
+    const double dotq = w * gw + x * gx + y * gy + z * gz;
+    const double gq4[4] = {(gw - w * dotq) / qn, (gx - x * dotq) / qn, (gy - y * dotq) / qn, (gz - z * dotq) / qn};
+
+    if (gmeans)
+        for (int a = 0; a < 3; a++) atomicAdd(&gmeans[3 * k + a], (float)gp[a]);
+    if (gls)
+        for (int a = 0; a < 3; a++) atomicAdd(&gls[3 * k + a], (float)gls_[a]);
+    if (gq)
+        for (int a = 0; a < 4; a++) atomicAdd(&gq[4 * k + a], (float)gq4[a]);
+    if (glogit) atomicAdd(&glogit[k], (float)(g_o * o * (1.0 - o)));
+}
+
+// ============================================================================
+static inline unsigned nblk(size_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
+
+template <int R>
+static void blend_bwd_launch(Workspace &ws, const float *C, const float *dC, const float *dP, hipStream_t st)
+{
+    dim3 grid((unsigned)ws.g.tiles, (unsigned)ws.n_chunks);
+    hipLaunchKernelGGL(k_blend_bwd<R>, grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
+                       ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
+                       ws.chunks.as<int4>(), ws.Kp, ws.g, ws.mode == RXGS_MODE_TX ? 1 : 0, C, dC, dP,
+                       ws.Tfin.as<float>(), ws.nlast.as<int>(), ws.dS.as<float>(), ws.g2d.as<float>());
+}
+
+hipError_t launch_blend_bwd(Workspace &ws, const float *C, const float *dC, const float *dP, hipStream_t st)
+{
+    if (ws.n_chunks == 0) return hipSuccess;
+    switch (ws.R) {
+    case 1: blend_bwd_launch<1>(ws, C, dC, dP, st); break;
+    case 2: blend_bwd_launch<2>(ws, C, dC, dP, st); break;
+    case 4: blend_bwd_launch<4>(ws, C, dC, dP, st); break;
+    case 8: blend_bwd_launch<8>(ws, C, dC, dP, st); break;
+    default: blend_bwd_launch<16>(ws, C, dC, dP, st); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rad_bwd(const Scene &sc, Workspace &ws, float *grad, hipStream_t st)
+{
+    const int64_t n = (int64_t)ws.N * ws.Kp;
+    if (n == 0 || !grad || sc.K == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rad_direct_bwd, dim3(nblk(n)), dim3(BLOCK), 0, st, ws.dS.as<float2>(),
+                       ws.sval[ws.sorted_buf].as<uint32_t>(), ws.counters.as<unsigned long long>(),
+                       ws.rxview.as<int>(), ws.N, ws.Kp, sc.K, grad);
+    return hipGetLastError();
+}
+
+int mlp_bwd_waves(const Workspace &ws)
+{
+    const int want = (ws.n_items + 3) / 4;
+    return 4 * std::max(1, std::min(want, 1024));
+}
+
+hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *gfeat, float *gmlp, hipStream_t st)
+{
+    const float *raw = m.raw.as<float>();
+    const float *W1 = raw;
+    const float *W3 = raw + HID * MLP_IN + HID + HID * HID + HID;
+    const int nwaves = mlp_bwd_waves(ws);
+    if (ws.n_items > 0)
+        hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)(nwaves / 4)), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
+                           ws.Gp.as<float>(), m.w2a.as<float>(), m.w2b.as<float>(), m.tab.as<float4>(), W3,
+                           ws.sval[ws.sorted_buf].as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, sc.K,
+                           ws.counters.as<unsigned long long>(), ws.dS.as<float2>(), ws.dL.as<float>(),
+                           ws.dG.as<float>(), ws.mpart.as<float>());
+    if (gmlp) {
+        if (ws.n_items > 0) {
+            hipLaunchKernelGGL(k_mlp_bwd_reduce, dim3(nblk(4096 + 194)), dim3(BLOCK), 0, st, ws.mpart.as<float>(),
+                               nwaves, gmlp);
+        } else {
+            hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(gmlp), 0u, RXGS_MLP_NPARAM, st);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_mlp_w1a, dim3(nblk(HID * (ENC + 1))), dim3(BLOCK), 0, st, ws.dG.as<float>(),
+                           ws.rxpos.as<float>(), ws.N, gmlp);
+        const int nchunks = (int)((sc.K + W1B_CHUNK - 1) / W1B_CHUNK);
+        if (nchunks > 0) {
+            hipLaunchKernelGGL(k_mlp_w1b_part, dim3((unsigned)nchunks), dim3(BLOCK), 0, st, ws.dL.as<float>(),
+                               sc.feat.as<float>(), sc.K, ws.w1part.as<float>());
+            hipLaunchKernelGGL(k_mlp_w1b_reduce, dim3(nblk(HID * FEAT)), dim3(BLOCK), 0, st, ws.w1part.as<float>(),
+                               nchunks, gmlp);
+        } else {
+            hipError_t e = hipSuccess;
+            for (int d = 0; d < HID && e == hipSuccess; d++)
+                e = launch_fill_u32(reinterpret_cast<uint32_t *>(gmlp + d * MLP_IN + ENC), 0u, FEAT, st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    if (gfeat && sc.K > 0)
+        hipLaunchKernelGGL(k_mlp_dfeat, dim3(nblk((size_t)sc.K * FEAT)), dim3(BLOCK), 0, st, ws.dL.as<float>(), W1,
+                           sc.K, gfeat);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const Scene &sc, Workspace &ws, const rxgs_grads &gr, hipStream_t st)
+{
+    const int64_t n = (int64_t)ws.V * ws.Kp;
+    if (sc.K == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project_bwd, dim3(nblk(n)), dim3(BLOCK), 0, st, sc.soa.as<float>(), sc.K, ws.Kp,
+                       ws.centres.as<float>(), ws.V, ws.g, ws.sval[ws.sorted_buf].as<uint32_t>(),
+                       ws.counters.as<unsigned long long>(), ws.g2d.as<float>(), gr.means, gr.log_scales, gr.quats,
+                       gr.logits);
+    return hipGetLastError();
+}
+
+size_t mlp_part_bytes(const Workspace &ws) { return (size_t)mlp_bwd_waves(ws) * MLPB_PART * 4; }
+size_t w1b_part_bytes(int64_t K) { return (size_t)std::max<int64_t>((K + W1B_CHUNK - 1) / W1B_CHUNK, 1) * HID * FEAT * 4; }
+
+}  // namespace rxgs

@@ -18,13 +18,11 @@
 //   k_blend_fwd    stage 3: per (tile, receiver chunk) front-to-back
 //                  compositing from LDS-staged batches.             [VALU]
 //   k_reduce_out   per-receiver power and coherent sum, fixed order.
-#include "rxgs_internal.h"
+#include "device_common.h"
 
 #include <cmath>
 
 namespace rxgs {
-
-typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ int count_below(uint64_t m)
 {
@@ -450,9 +448,7 @@ __global__ __launch_bounds__(BLOCK) void k_rad_direct(const float2 *__restrict__
     if (s < (int64_t)counters[1 + v]) rad[idx] = radiance[min((int64_t)order[(size_t)v * Kp + s], K - 1)];
 }
 
-__device__ __forceinline__ int hperm(int d) { return (d & 1) * 32 + (d >> 1); }
-
-// receiver ("global") term of layer 1: W1[:, :36] gamma(r_j), stored permuted
+// receiver ("global") term of layer 1: W1[:, :36] gamma(r_j), stored in hid_pos order
 __global__ __launch_bounds__(BLOCK) void k_mlp_global(const float *__restrict__ W1, const float *__restrict__ rx,
                                                       int N, float *__restrict__ Gp)
 {
@@ -469,10 +465,10 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_global(const float *__restrict__ 
             acc = fmaf(W1[d * MLP_IN + 12 * a + 2 * f + 1], cs, acc);
         }
     }
-    Gp[(size_t)j * HID + hperm(d)] = acc;
+    Gp[(size_t)j * HID + hid_pos(d)] = acc;
 }
 
-// Gaussian ("local") term of layer 1: W1[:, 36:] f_k + b1, stored permuted
+// Gaussian ("local") term of layer 1: W1[:, 36:] f_k + b1, stored in hid_pos order
 __global__ __launch_bounds__(BLOCK) void k_mlp_local(const float *__restrict__ W1, const float *__restrict__ b1,
                                                      const float *__restrict__ feat, int64_t K,
                                                      float *__restrict__ Lp)
@@ -486,17 +482,17 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_local(const float *__restrict__ W
     const float *w = W1 + d * MLP_IN + ENC;
 #pragma unroll
     for (int i = 0; i < FEAT; i++) acc = fmaf(w[i], f[i], acc);
-    Lp[k * HID + hperm(d)] = acc;
+    Lp[k * HID + hid_pos(d)] = acc;
 }
 
 // Per-(receiver, Gaussian) layers 2 and 3 on FP32 MFMA (v_mfma_f32_32x32x2f32).
 // One wave per work item = (view, 32 consecutive sorted positions, up to 16
 // receivers of that view).  The wave computes H2^T = W2 X1^T for its 32
 // pairs: A = W2 rows from LDS, B = X1 = relu(local + global), one pair per
-// lane pair (lane l and l + 32 hold even / odd hidden indices), so the
-// accumulator leaves each lane with 32 of the 64 hidden outputs of its own
-// pair.  Layer 3 (64 -> 2) is then a per-lane dot product plus one exchange
-// between the two lane halves.
+// lane pair (lane l and l + 32 hold the two halves of the hidden units, in
+// hid_of order), so the accumulator leaves each lane with 32 of the 64 hidden
+// outputs of its own pair.  Layer 3 (64 -> 2) is then a per-lane dot product
+// plus one exchange between the two lane halves.
 __global__ __launch_bounds__(BLOCK) void k_mlp_pairs(const float *__restrict__ Lp, const float *__restrict__ Gp,
                                                      const float *__restrict__ w2a,
                                                      const float4 *__restrict__ tab, const float *__restrict__ b3,
@@ -639,7 +635,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
                     else if (du < -halfW) du += Wf;
                 }
                 const float dv = (rowf - r0.z) - r0.w;
-                const float ex = r1.w + du * (r1.x * du + r1.y * dv) + r1.z * (dv * dv);
+                const float ex = blend_exponent(du, dv, r1);
                 const float w = fminf(W_MAX, __builtin_amdgcn_exp2f(ex));
                 if (w < ALPHA_MIN) continue;
                 const float tw = T * w;

@@ -1,6 +1,6 @@
 // C-ABI entry points of librxgs: context, scene and MLP upload, the render
 // pipeline (Alg. 1 of RxGS with a view index in the sort key), exports.
-#include "rxgs_internal.h"
+#include "device_common.h"
 
 #include <algorithm>
 #include <cmath>
@@ -111,7 +111,7 @@ void free_workspace(Workspace &ws)
                       &ws.poff,    &ws.pkey[0], &ws.pkey[1], &ws.pval[0], &ws.pval[1], &ws.ranges, &ws.rad,
                       &ws.Lp,      &ws.Gp,      &ws.Tfin,   &ws.nlast,  &ws.part,    &ws.chunks, &ws.items,
                       &ws.counters, &ws.hist,   &ws.scan_tmp, &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
-                      &ws.dG,      &ws.dmlp,    &ws.hist_b,  &ws.scan_b};
+                      &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.hist_b,  &ws.scan_b};
     for (DevBuf *b : bufs) release(*b);
     if (ws.staged) (void)hipEventDestroy(ws.staged);
     if (ws.counted) (void)hipEventDestroy(ws.counted);
@@ -301,6 +301,7 @@ extern "C" void rxgs_destroy(rxgs_ctx *ctx)
     release(ctx->scene.feat);
     release(ctx->mlp.raw);
     release(ctx->mlp.w2a);
+    release(ctx->mlp.w2b);
     release(ctx->mlp.tab);
     release(ctx->stage);
     delete ctx;
@@ -409,11 +410,16 @@ extern "C" rxgs_status rxgs_mlp_upload(rxgs_ctx *ctx, const float *params, int s
     const float *W2 = h.data() + HID * MLP_IN + HID;
     const float *b2 = W2 + HID * HID;
     const float *W3 = b2 + HID;
-    // MFMA A-operand layout of W2: [mb][t][lane] = W2[32 mb + lane % 32][2 t + lane / 32]
-    std::vector<float> w2a(2 * 32 * 64);
+    // MFMA A-operand layouts of W2 (forward) and W2^T (backward):
+    //   w2a[mb][t][lane] = W2[32 mb + lane % 32][hid_of(lane / 32, t)]
+    //   w2b[ib][t][lane] = W2[hid_of(lane / 32, t)][32 ib + lane % 32]
+    std::vector<float> w2a(2 * 32 * 64), w2b(2 * 32 * 64);
     for (int mb = 0; mb < 2; mb++)
         for (int t = 0; t < 32; t++)
-            for (int l = 0; l < 64; l++) w2a[(mb * 32 + t) * 64 + l] = W2[(32 * mb + (l & 31)) * HID + 2 * t + (l >> 5)];
+            for (int l = 0; l < 64; l++) {
+                w2a[(mb * 32 + t) * 64 + l] = W2[(32 * mb + (l & 31)) * HID + hid_of(l >> 5, t)];
+                w2b[(mb * 32 + t) * 64 + l] = W2[hid_of(l >> 5, t) * HID + 32 * mb + (l & 31)];
+            }
     // per (lane half h, block mb, accumulator register r): hidden index d and
     // its layer-3 weights and layer-2 bias
     std::vector<float> tab(2 * 2 * 16 * 4, 0.f);
@@ -430,9 +436,11 @@ extern "C" rxgs_status rxgs_mlp_upload(rxgs_ctx *ctx, const float *params, int s
     m.valid = false;
     GROW(ctx, m.raw, sizeof(float) * RXGS_MLP_NPARAM);
     GROW(ctx, m.w2a, sizeof(float) * w2a.size());
+    GROW(ctx, m.w2b, sizeof(float) * w2b.size());
     GROW(ctx, m.tab, sizeof(float) * tab.size());
     HIPCHK(ctx, hipMemcpy(m.raw.p, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMemcpy(m.w2a.p, w2a.data(), sizeof(float) * w2a.size(), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(m.w2b.p, w2b.data(), sizeof(float) * w2b.size(), hipMemcpyHostToDevice));
     HIPCHK(ctx, hipMemcpy(m.tab.p, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice));
     m.version = ++ctx->version_counter;
     m.valid = true;
@@ -631,6 +639,59 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     ws.scene_version = sc.version;
     ws.mlp_version = ctx->mlp.version;
     ws.valid = true;
+    return RXGS_OK;
+}
+
+// ============================================================================
+extern "C" rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *saved, const float *C, const float *dC,
+                                            const float *dP, const rxgs_grads *grads, void *stream)
+{
+    if (!ctx) return RXGS_E_INVALID;
+    if (!saved || !grads) return fail(ctx, RXGS_E_INVALID, "saved or grads is NULL");
+    if (saved->ctx != ctx) return fail(ctx, RXGS_E_INVALID, "saved state of another context");
+    // the backward uses scratch buffers of the saved state: calls on one saved state must not overlap
+    Workspace &ws = const_cast<rxgs_saved *>(saved)->ws;
+    const Scene &sc = ctx->scene;
+    if (!ws.valid) return fail(ctx, RXGS_E_STATE, "no forward state in saved");
+    if (ws.scene_version != sc.version || (ws.use_mlp && ws.mlp_version != ctx->mlp.version))
+        return fail(ctx, RXGS_E_STATE, "scene or MLP changed since the forward");
+    if (ws.N > 0 && (!C || !dC)) return fail(ctx, RXGS_E_INVALID, "C or dC is NULL");
+    DeviceScope ds(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const rxgs_grads &gr = *grads;
+    const int64_t K = ws.K;
+    // gradients accumulate with atomics: clear them first
+    struct {
+        float *p;
+        size_t n;
+    } outs[] = {{gr.means, (size_t)K * 3}, {gr.log_scales, (size_t)K * 3}, {gr.quats, (size_t)K * 4},
+                {gr.logits, (size_t)K},   {ws.use_mlp ? nullptr : gr.radiance, (size_t)K * 2}};
+    for (auto &o : outs)
+        if (o.p) HIPCHK(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(o.p), 0u, o.n, st));
+    if (ws.N == 0 || K == 0) {
+        if (ws.use_mlp && gr.features) HIPCHK(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(gr.features), 0u, (size_t)K * FEAT, st));
+        if (ws.use_mlp && gr.mlp) HIPCHK(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(gr.mlp), 0u, RXGS_MLP_NPARAM, st));
+        return RXGS_OK;
+    }
+    const size_t VK = (size_t)ws.V * ws.Kp;
+    GROW(ctx, ws.dS, (size_t)ws.N * ws.Kp * 8);
+    GROW(ctx, ws.g2d, VK * 32);
+    HIPCHK(ctx, launch_fill_u32(ws.dS.as<uint32_t>(), 0u, (size_t)ws.N * ws.Kp * 2, st));
+    HIPCHK(ctx, launch_fill_u32(ws.g2d.as<uint32_t>(), 0u, VK * 8, st));
+    if (ws.use_mlp) {
+        GROW(ctx, ws.dL, (size_t)K * HID * 4);
+        GROW(ctx, ws.dG, (size_t)ws.N * HID * 4);
+        GROW(ctx, ws.mpart, mlp_part_bytes(ws));
+        GROW(ctx, ws.w1part, w1b_part_bytes(K));
+        HIPCHK(ctx, launch_fill_u32(ws.dL.as<uint32_t>(), 0u, (size_t)K * HID, st));
+        HIPCHK(ctx, launch_fill_u32(ws.dG.as<uint32_t>(), 0u, (size_t)ws.N * HID, st));
+    }
+    STAGE(ctx, "blend_bwd", launch_blend_bwd(ws, C, dC, dP, st));
+    if (ws.use_mlp)
+        STAGE(ctx, "mlp_bwd", launch_mlp_bwd(sc, ctx->mlp, ws, gr.features, gr.mlp, st));
+    else
+        STAGE(ctx, "bwd_misc", launch_rad_bwd(sc, ws, gr.radiance, st));
+    STAGE(ctx, "project_bwd", launch_project_bwd(sc, ws, gr, st));
     return RXGS_OK;
 }
 

@@ -60,7 +60,8 @@ struct Mlp {
     bool valid = false;
     uint64_t version = 0;
     DevBuf raw;    // RXGS_MLP_NPARAM
-    DevBuf w2a;    // [2][32][64]  W2[32 mb + l % 32][2 t + l / 32]
+    DevBuf w2a;    // [2][32][64]  W2[32 mb + l % 32][hid_of(l / 32, t)]
+    DevBuf w2b;    // [2][32][64]  W2[hid_of(l / 32, t)][32 ib + l % 32]
     DevBuf tab;    // [2 h][2 mb][16 r] float4 (W3[0][d], W3[1][d], b2[d], 0)
 };
 
@@ -113,7 +114,8 @@ struct Workspace {
     DevBuf g2d;       // V x Kp x 8 (u, v, a, b, c, o partials)
     DevBuf dL;        // K x 64
     DevBuf dG;        // N x 64
-    DevBuf dmlp;      // RXGS_MLP_NPARAM f32 accumulators
+    DevBuf mpart;     // per-wave partial sums of the MLP backward
+    DevBuf w1part;    // per-chunk partial sums of dW1 (Gaussian part)
     // host staging (pinned) and the events guarding it
     void *h_pinned = nullptr;
     size_t h_pinned_cap = 0;
@@ -188,8 +190,13 @@ hipError_t launch_mlp_local(const Scene &sc, const Mlp &m, Workspace &ws, hipStr
 hipError_t launch_mlp_pairs(const Mlp &m, Workspace &ws, hipStream_t st);
 hipError_t launch_blend_fwd(Workspace &ws, float *C, hipStream_t st);
 hipError_t launch_reduce_outputs(Workspace &ws, float *power, float *csum, hipStream_t st);
-hipError_t launch_backward(const Scene &sc, const Mlp &m, Workspace &ws, const float *C, const float *dC,
-                           const float *dP, const rxgs_grads &gr, hipStream_t st);
+// backward (backward.hip)
+hipError_t launch_blend_bwd(Workspace &ws, const float *C, const float *dC, const float *dP, hipStream_t st);
+hipError_t launch_rad_bwd(const Scene &sc, Workspace &ws, float *grad, hipStream_t st);
+hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *gfeat, float *gmlp, hipStream_t st);
+hipError_t launch_project_bwd(const Scene &sc, Workspace &ws, const rxgs_grads &gr, hipStream_t st);
+size_t mlp_part_bytes(const Workspace &ws);
+size_t w1b_part_bytes(int64_t K);
 
 bool grow(DevBuf &b, size_t bytes);
 void release(DevBuf &b);

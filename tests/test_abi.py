@@ -1,0 +1,62 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function the header declares, and rejects bad arguments before touching
+a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rxgs.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rxgs_\w+)\s*\(", text)))
+
+
+def test_header_and_library_agree():
+    from paper_2605_24290_amd import rxgs
+    L = rxgs.lib()
+    names = declared_functions()
+    assert "rxgs_render" in names and "rxgs_render_backward" in names
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, f"declared but not exported: {missing}"
+    for n in rxgs.EXPORTED:
+        assert n in names, f"binding names {n}, header does not declare it"
+
+
+def test_version_and_create_rejects_bad_grid():
+    from paper_2605_24290_amd import rxgs
+    L = rxgs.lib()
+    assert L.rxgs_version().decode().startswith("rxgs")
+    ctx = ctypes.c_void_p()
+    bad = rxgs.CGrid(0, 360, 0, 0.0, 0.01)
+    assert L.rxgs_create(0, ctypes.byref(bad), ctypes.byref(ctx)) == 1
+    assert b"grid" in L.rxgs_last_error(None)
+    odd = rxgs.CGrid(90, 361, 0, 0.0, 0.01)
+    assert L.rxgs_create(0, ctypes.byref(odd), ctypes.byref(ctx)) == 1
+    neg = rxgs.CGrid(90, 360, 0, 0.0, -0.01)
+    assert L.rxgs_create(0, ctypes.byref(neg), ctypes.byref(ctx)) == 1
+    assert L.rxgs_create(0, ctypes.byref(neg), None) == 1
+
+
+def test_null_context_calls_are_rejected():
+    from paper_2605_24290_amd import rxgs
+    L = rxgs.lib()
+    assert L.rxgs_render(None, 0, 1, None, None, 1, None, None, None, None, None, None) == 1
+    assert L.rxgs_scene_upload(None, 0, None, None, None, None, None, None, 0, None) == 1
+    assert L.rxgs_mlp_upload(None, None, 0, None) == 1
+    assert L.rxgs_saved_info(None, None) == 1
+    L.rxgs_destroy(None)
+    L.rxgs_saved_destroy(None)
+
+
+def test_package_import_does_not_load_the_oracle():
+    import subprocess
+    import sys
+    code = ("import sys; import paper_2605_24290_amd.rxgs, paper_2605_24290_amd.scenes; "
+            "assert not any(m.startswith('oracle') for m in sys.modules), 'oracle imported'")
+    subprocess.run([sys.executable, "-c", code], check=True, cwd=ROOT)

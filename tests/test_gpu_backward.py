@@ -1,0 +1,156 @@
+"""GPU backward against the FP64 oracle's reverse mode and against FP64 central
+finite differences of the oracle's forward.
+
+Metric (per gradient tensor): max |g_gpu - g_oracle| / max |g_oracle| <= 1e-4.
+The loss is L = sum(dC * C) + sum(dP * power) with fixed random dC, dP (its
+gradient is the vector-Jacobian product both sides compute), and the L2 loss
+of the training step, sum (C - Y)^2, with seeded targets Y.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2605_24290_amd import scenes as S
+
+from .parity import gpu, needs_gpu, renderer_for
+
+pytestmark = [gpu, needs_gpu]
+
+TOL = 1e-4
+FIELDS_MLP = ["means", "log_scales", "quats", "logits", "features", "mlp"]
+FIELDS_DIRECT = ["means", "log_scales", "quats", "logits", "radiance"]
+
+
+def _gpu_grads(wl, mode, dC=None, dP=None, l2_targets=None, rx_off=None):
+    import torch
+    from paper_2605_24290_amd import rxgs
+    r = renderer_for(wl)
+    saved = rxgs.Saved(r)
+    C, P, _ = r.render(wl.rx, tx=wl.tx, rx_off=rx_off, mode=mode, saved=saved)
+    if l2_targets is not None:
+        Y = torch.as_tensor(l2_targets, device=C.device)
+        dC_t = 2.0 * (C - Y)
+        dP_t = None
+    else:
+        dC_t = torch.as_tensor(dC, dtype=torch.float32, device=C.device)
+        dP_t = None if dP is None else torch.as_tensor(dP, dtype=torch.float32, device=C.device)
+    g = r.backward(saved, C, dC_t, dP_t)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
+    Cn = C.cpu().numpy()
+    saved.close()
+    r.close()
+    return out, Cn
+
+
+def _compare(gg, go, fields, tol=TOL):
+    worst = {}
+    for f in fields:
+        a, b = gg[f].ravel(), go[f].ravel()
+        scale = np.abs(b).max()
+        assert scale > 0, f
+        err = np.abs(a - b).max() / scale
+        worst[f] = err
+        assert err <= tol, f"{f}: {err:.3e}"
+    print("[grad parity]", {k: f"{v:.2e}" for k, v in worst.items()})
+    return worst
+
+
+@pytest.mark.parametrize("mode", ["tx", "rx"])
+def test_backward_direct_radiance(mode):
+    wl = S.make_workload("c0", K=300, N=4)
+    rng = np.random.default_rng(5)
+    dC = rng.normal(size=(4, 2, wl.grid.H, wl.grid.W)).astype(np.float32)
+    dP = rng.normal(size=(4,)).astype(np.float32)
+    gg, _ = _gpu_grads(wl, mode, dC=dC, dP=dP)
+    cen, rv = O.views_for(mode, wl.tx, wl.rx)
+    go = O.backward(wl.scene, wl.grid, cen, wl.rx, rv, dC, dP)
+    _compare(gg, go, FIELDS_DIRECT)
+
+
+@pytest.mark.parametrize("mode", ["tx", "rx"])
+def test_backward_mlp_subset_l2(mode):
+    """The training-step loss on the 256-Gaussian, 8-receiver subset of the
+    100k-Gaussian, 32-receiver workload, 90 x 360 grid."""
+    full = S.make_workload("c2", K=100_000, N=32)
+    sc = full.scene
+    sub = S.Scene(sc.means[:256], sc.log_scales[:256], sc.quats[:256], sc.logits[:256], features=sc.features[:256])
+    wl = S.Workload(sub, full.tx, full.rx[:8], full.grid, full.mlp, full.targets[:8], name="c2-subset")
+    gg, Cg = _gpu_grads(wl, mode, l2_targets=wl.targets)
+    cen, rv = O.views_for(mode, wl.tx, wl.rx)
+    ora = O.render(wl.scene, wl.grid, cen, wl.rx, rv, mlp=wl.mlp)
+    dC = 2.0 * (ora["C"] - wl.targets)
+    go = O.backward(wl.scene, wl.grid, cen, wl.rx, rv, dC, None, mlp=wl.mlp)
+    _compare(gg, go, FIELDS_MLP)
+
+
+def test_backward_mlp_several_transmitters():
+    grid = S.Grid(45, 90, -math.pi / 2, math.pi / 45)
+    wl = S.make_workload("c1", K=500, N=7, Q=2, grid=grid)
+    rng = np.random.default_rng(6)
+    dC = rng.normal(size=(7, 2, grid.H, grid.W)).astype(np.float32)
+    dP = rng.normal(size=(7,)).astype(np.float32)
+    gg, _ = _gpu_grads(wl, "tx", dC=dC, dP=dP, rx_off=[0, 4, 7])
+    cen = wl.tx.astype(np.float64)
+    rv = np.array([0, 0, 0, 0, 1, 1, 1], dtype=np.int32)
+    go = O.backward(wl.scene, wl.grid, cen, wl.rx, rv, dC, dP, mlp=wl.mlp)
+    _compare(gg, go, FIELDS_MLP)
+
+
+def test_gpu_gradient_matches_fp64_central_differences():
+    """GPU gradient of L = sum(dC * C) against FP64 central differences (step
+    1e-6) of the oracle's forward on 64 random parameters; parameters whose
+    +-h steps change a discrete decision of the oracle are redrawn."""
+    grid = S.Grid(30, 60, -math.pi / 2, math.pi / 30)
+    wl = S.make_workload(S.Preset("t", 40, 3, (3.0, 3.0, 2.0), -1.0, 0.3, S.GRID_90x180, True), seed=77, grid=grid)
+    rng = np.random.default_rng(8)
+    dC = rng.normal(size=(3, 2, grid.H, grid.W)).astype(np.float32)
+    mode = "rx"
+    gg, _ = _gpu_grads(wl, mode, dC=dC)
+    sc = wl.scene
+    sc64 = S.Scene(*[np.asarray(a, dtype=np.float64) for a in (sc.means, sc.log_scales, sc.quats, sc.logits)],
+                   None, np.asarray(sc.features, dtype=np.float64))
+    mlp = [np.asarray(a, dtype=np.float64) for a in wl.mlp]
+    flat = np.concatenate([a.ravel() for a in mlp])
+    cen, rv = O.views_for(mode, wl.tx, wl.rx)
+    rx = wl.rx.astype(np.float64)
+    dC64 = dC.astype(np.float64)
+
+    def loss(scn, m):
+        o = O.render(scn, grid, cen, rx, rv, mlp=m, want_hash=True)
+        return float((dC64 * o["C"]).sum()), o["rowhash"]
+    L0, h0 = loss(sc64, mlp)
+    scale = {f: np.abs(gg[f]).max() for f in FIELDS_MLP}
+    checked = tries = 0
+    while checked < 64 and tries < 400:
+        tries += 1
+        f = FIELDS_MLP[rng.integers(len(FIELDS_MLP))]
+        h = 1e-6
+        vals = []
+        hs = []
+        if f == "mlp":
+            i = int(rng.integers(flat.size))
+            for sgn in (1, -1):
+                fl = flat.copy()
+                fl[i] += sgn * h
+                L, hh = loss(sc64, S.unflat_mlp(fl))
+                vals.append(L)
+                hs.append(hh)
+        else:
+            arr = getattr(sc64, f)
+            i = int(rng.integers(arr.size))
+            for sgn in (1, -1):
+                a2 = arr.copy().ravel()
+                a2[i] += sgn * h
+                L, hh = loss(S.Scene(**{**sc64.__dict__, f: a2.reshape(arr.shape)}), mlp)
+                vals.append(L)
+                hs.append(hh)
+        if not (np.array_equal(hs[0], h0) and np.array_equal(hs[1], h0)):
+            continue
+        fd = (vals[0] - vals[1]) / (2 * h)
+        g = gg[f].ravel()[i]
+        assert abs(g - fd) <= TOL * scale[f] + 1e-6 * abs(fd), (f, i, g, fd, scale[f])
+        checked += 1
+    assert checked >= 48
