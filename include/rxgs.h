@@ -209,6 +209,75 @@ enum {
 rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *dst, int64_t bytes, int dst_on_device);
 
 /*
+ * Serving: a persistent request loop on one context (the use the paper
+ * motivates with coverage maps, App. G.3 "Asymptotic scaling").  Each query is
+ * one transmitter and n receivers; queries are rendered by a worker thread in
+ * batches (several queries, each its own view in TX mode, fused into one
+ * render) on `slots` HIP streams, so a batch is formed whenever a slot frees
+ * up, from whatever has arrived (continuous batching), and batches on
+ * different slots overlap on the device.  A batch takes queued queries in
+ * arrival order while the receiver count, the query count and the estimated
+ * device workspace stay within the limits; a query that alone exceeds them is
+ * rejected at submit.  While a server runs, the context's scene and MLP must
+ * not change and the context must not render from other threads.
+ */
+typedef struct {
+    int64_t mem_budget_bytes;  /* device workspace for all slots; 0 = half of the free memory */
+    int32_t max_rx_per_batch;  /* receivers fused into one render (>= 1) */
+    int32_t max_queries_per_batch;
+    int32_t slots;             /* batches in flight, 1..8 */
+    int32_t mode;              /* RXGS_MODE_TX or RXGS_MODE_RX */
+    int32_t queue_capacity;    /* queued queries; submit returns E_BUSY beyond */
+    int32_t want_spectra;      /* 1: results include the N x 2 x H x W spectra */
+} rxgs_server_opts;
+
+typedef struct {
+    double t_submit;           /* seconds, host monotonic clock */
+    double t_start;            /* batch launched */
+    double t_done;             /* results copied to host */
+    int32_t batch_queries;     /* queries in the batch that carried it */
+    int32_t batch_receivers;
+} rxgs_ticket_info;
+
+typedef struct {
+    int64_t submitted, completed, cancelled, rejected, failed, batches, receivers;
+    int64_t queued, in_flight;
+    double busy_s;             /* summed wall time of batches on the device */
+} rxgs_server_stats_t;
+
+/* Start the worker on a context with an uploaded scene (and MLP).
+ * Errors: E_INVALID (options), E_STATE (no scene / MLP), E_OOM, E_DEVICE. */
+rxgs_status rxgs_server_start(rxgs_ctx *ctx, const rxgs_server_opts *opts, rxgs_server **out);
+/* Queue one query: tx host 3 floats, rx_host n x 3 floats (copied).  Returns
+ * a ticket.  Errors: E_INVALID (n < 1, n > max_rx_per_batch, non-finite,
+ * workspace estimate above the per-slot budget), E_BUSY (queue full), E_STATE (stopped). */
+rxgs_status rxgs_server_submit(rxgs_server *srv, const float *tx, int32_t n, const float *rx_host,
+                               uint64_t *ticket);
+/* Wait up to timeout_ms (< 0: forever) for a ticket; on success copy power
+ * (n floats) and, if the server keeps spectra and C_host is not NULL, the
+ * n x 2 x H x W spectra, fill info (may be NULL) and retire the ticket.
+ * Errors: E_TIMEOUT (still pending), E_CANCELLED, E_INVALID (unknown ticket),
+ * E_DEVICE (its batch failed). */
+rxgs_status rxgs_server_poll(rxgs_server *srv, uint64_t ticket, float *power_host, float *C_host,
+                             rxgs_ticket_info *info, int32_t timeout_ms);
+/* Cancel a queued ticket (a ticket already on the device completes). */
+rxgs_status rxgs_server_cancel(rxgs_server *srv, uint64_t ticket);
+rxgs_status rxgs_server_stats(rxgs_server *srv, rxgs_server_stats_t *out);
+/* Finish in-flight batches, cancel queued tickets, join the worker, free. */
+rxgs_status rxgs_server_stop(rxgs_server *srv);
+
+/*
+ * Batch planning rule of the server, as a host function: given the receiver
+ * counts of the queued queries in arrival order, return how many of them
+ * (a prefix) the next batch takes and its workspace estimate.  Pure host
+ * logic, no device access.
+ */
+int32_t rxgs_plan_batch(const int32_t *n_rx, int32_t n_queued, int32_t mode, int64_t K, int32_t H, int32_t W,
+                        int64_t budget_bytes, int32_t max_rx, int32_t max_queries, int64_t *bytes_out);
+/* Workspace estimate of one render (bytes) for Q queries and N receivers. */
+int64_t rxgs_workspace_estimate(int32_t mode, int32_t Q, int32_t N, int64_t K, int32_t H, int32_t W);
+
+/*
  * Stage timing.  While enabled, every pipeline stage of rxgs_render and
  * rxgs_render_backward is bracketed by HIP events recorded on the caller's
  * stream; rxgs_profile_read synchronises on them and returns, per stage,

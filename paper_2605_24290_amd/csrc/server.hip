@@ -1,0 +1,484 @@
+// Continuous-batching server of librxgs: a worker thread keeps the scene on
+// the device, forms a batch from the queued queries whenever one of its slots
+// (stream + workspace + pinned staging) is free, fuses the batch into one
+// render (each query's transmitter is one view in TX mode) and retires the
+// tickets when the slot's completion event fires.
+#include "rxgs_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <thread>
+#include <unordered_map>
+
+using namespace rxgs;
+
+namespace {
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+int64_t round_up64(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+enum TicketState { T_QUEUED = 0, T_RUNNING = 1, T_DONE = 2, T_CANCELLED = 3, T_FAILED = 4 };
+
+struct Ticket {
+    uint64_t id = 0;
+    float tx[3] = {0, 0, 0};
+    std::vector<float> rx;
+    int n = 0;
+    int state = T_QUEUED;
+    double t_submit = 0, t_start = 0, t_done = 0;
+    int batch_q = 0, batch_n = 0;
+    std::vector<float> power;
+    std::vector<float> C;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    rxgs_saved *saved = nullptr;
+    DevBuf d_tx, d_rx, d_C, d_P;
+    float *h_in = nullptr;   // pinned: tx (Q x 3) then rx (N x 3)
+    size_t h_in_cap = 0;
+    float *h_P = nullptr;    // pinned: N
+    size_t h_P_cap = 0;
+    float *h_C = nullptr;    // pinned: N x 2 x H x W
+    size_t h_C_cap = 0;
+    bool busy = false;
+    double t_launch = 0;
+    std::vector<uint64_t> tickets;
+    std::vector<int> offs;   // receiver offset of each ticket in the batch
+    int N = 0;
+};
+
+bool pinned_grow(float *&p, size_t &cap, size_t n)
+{
+    if (cap >= n) return true;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    const size_t want = std::max<size_t>(n + n / 4, 1024);
+    if (hipHostMalloc((void **)&p, want * sizeof(float), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+        return false;
+    }
+    cap = want;
+    return true;
+}
+
+}  // namespace
+
+struct rxgs_server {
+    rxgs_ctx *ctx = nullptr;
+    rxgs_server_opts opts{};
+    int64_t slot_budget = 0;
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<uint64_t> queue;
+    std::unordered_map<uint64_t, Ticket> tickets;
+    std::vector<Slot> slots;
+    uint64_t next_id = 1;
+    bool stopping = false;
+    bool running = false;
+    rxgs_server_stats_t st{};
+    std::string err;
+};
+
+// ---------------------------------------------------------------------------
+extern "C" int64_t rxgs_workspace_estimate(int32_t mode, int32_t Q, int32_t N, int64_t K, int32_t H, int32_t W)
+{
+    if (N <= 0) return 0;
+    const int64_t V = (mode == RXGS_MODE_TX) ? std::max(Q, 1) : N;
+    const int64_t Kp = round_up64(std::max<int64_t>(K, 1), SORT_TILE);
+    const int64_t VK = V * Kp;
+    const int64_t P = (int64_t)H * W;
+    const int64_t tiles = (int64_t)((H + TILE - 1) / TILE) * ((W + TILE - 1) / TILE);
+    const int64_t D_est = 6 * V * std::max<int64_t>(K, 1);
+    int64_t b = VK * 117;               // records, keys, values, sorted records, offsets, histograms
+    b += D_est * 16;                    // pair keys and values, ping-pong
+    b += (int64_t)N * Kp * 8;           // radiance
+    b += (int64_t)N * P * 8;            // spectra
+    b += (mode == RXGS_MODE_TX ? V : N) * P * 8;   // final transmittance, stop index
+    b += (int64_t)N * tiles * 12 + V * tiles * 8;  // partial sums, ranges
+    b += std::max<int64_t>(K, 1) * 256 + (int64_t)N * 256;  // MLP layer-1 terms
+    return b;
+}
+
+extern "C" int32_t rxgs_plan_batch(const int32_t *n_rx, int32_t n_queued, int32_t mode, int64_t K, int32_t H,
+                                   int32_t W, int64_t budget_bytes, int32_t max_rx, int32_t max_queries,
+                                   int64_t *bytes_out)
+{
+    int32_t take = 0;
+    int64_t total = 0, bytes = 0;
+    if (n_rx && n_queued > 0)
+        for (int32_t i = 0; i < n_queued && i < max_queries; i++) {
+            const int64_t t2 = total + n_rx[i];
+            if (n_rx[i] < 1 || t2 > max_rx) break;
+            const int64_t b = rxgs_workspace_estimate(mode, i + 1, (int32_t)t2, K, H, W);
+            if (b > budget_bytes) break;
+            take = i + 1;
+            total = t2;
+            bytes = b;
+        }
+    if (bytes_out) *bytes_out = bytes;
+    return take;
+}
+
+// ---------------------------------------------------------------------------
+namespace {
+
+// launch one batch on a free slot (called by the worker with the lock released)
+rxgs_status launch_batch(rxgs_server *s, Slot &sl, std::vector<Ticket *> &batch)
+{
+    rxgs_ctx *ctx = s->ctx;
+    const int mode = s->opts.mode;
+    const int Q = (int)batch.size();
+    int N = 0;
+    sl.offs.clear();
+    for (Ticket *t : batch) {
+        sl.offs.push_back(N);
+        N += t->n;
+    }
+    sl.N = N;
+    const size_t P = (size_t)ctx->g.H * ctx->g.W;
+    if (!pinned_grow(sl.h_in, sl.h_in_cap, (size_t)(Q + N) * 3) || !pinned_grow(sl.h_P, sl.h_P_cap, (size_t)N))
+        return RXGS_E_OOM;
+    if (s->opts.want_spectra && !pinned_grow(sl.h_C, sl.h_C_cap, (size_t)N * 2 * P)) return RXGS_E_OOM;
+    std::vector<int32_t> rx_off(Q + 1, 0);
+    for (int q = 0; q < Q; q++) {
+        std::memcpy(sl.h_in + 3 * q, batch[q]->tx, 12);
+        std::memcpy(sl.h_in + 3 * Q + 3 * sl.offs[q], batch[q]->rx.data(), (size_t)batch[q]->n * 12);
+        rx_off[q + 1] = rx_off[q] + batch[q]->n;
+    }
+    if (!grow(sl.d_tx, (size_t)Q * 12) || !grow(sl.d_rx, (size_t)N * 12) || !grow(sl.d_P, (size_t)N * 4) ||
+        !grow(sl.d_C, (size_t)N * 2 * P * 4))
+        return RXGS_E_OOM;
+    if (hipMemcpyAsync(sl.d_tx.p, sl.h_in, (size_t)Q * 12, hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
+        hipMemcpyAsync(sl.d_rx.p, sl.h_in + 3 * Q, (size_t)N * 12, hipMemcpyHostToDevice, sl.stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return RXGS_E_DEVICE;
+    }
+    rxgs_status rs = rxgs_render(ctx, mode, Q, sl.d_tx.as<float>(), rx_off.data(), N, sl.d_rx.as<float>(),
+                                 sl.d_C.as<float>(), sl.d_P.as<float>(), nullptr, sl.saved, sl.stream);
+    if (rs != RXGS_OK) return rs;
+    if (hipMemcpyAsync(sl.h_P, sl.d_P.p, (size_t)N * 4, hipMemcpyDeviceToHost, sl.stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return RXGS_E_DEVICE;
+    }
+    if (s->opts.want_spectra &&
+        hipMemcpyAsync(sl.h_C, sl.d_C.p, (size_t)N * 2 * P * 4, hipMemcpyDeviceToHost, sl.stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return RXGS_E_DEVICE;
+    }
+    if (hipEventRecord(sl.done, sl.stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return RXGS_E_DEVICE;
+    }
+    return RXGS_OK;
+}
+
+void worker_main(rxgs_server *s)
+{
+    (void)hipSetDevice(s->ctx->device);
+    const size_t P = (size_t)s->ctx->g.H * s->ctx->g.W;
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        // retire finished batches
+        bool any_busy = false;
+        for (Slot &sl : s->slots) {
+            if (!sl.busy) continue;
+            const hipError_t q = hipEventQuery(sl.done);
+            if (q == hipErrorNotReady) {
+                any_busy = true;
+                continue;
+            }
+            const double t = now_s();
+            const bool ok = q == hipSuccess;
+            if (!ok) (void)hipGetLastError();
+            for (size_t b = 0; b < sl.tickets.size(); b++) {
+                auto it = s->tickets.find(sl.tickets[b]);
+                if (it == s->tickets.end()) continue;
+                Ticket &tk = it->second;
+                if (ok) {
+                    tk.power.assign(sl.h_P + sl.offs[b], sl.h_P + sl.offs[b] + tk.n);
+                    if (s->opts.want_spectra)
+                        tk.C.assign(sl.h_C + (size_t)sl.offs[b] * 2 * P, sl.h_C + (size_t)(sl.offs[b] + tk.n) * 2 * P);
+                    tk.state = T_DONE;
+                    s->st.completed++;
+                } else {
+                    tk.state = T_FAILED;
+                    s->st.failed++;
+                }
+                tk.t_done = t;
+            }
+            s->st.busy_s += t - sl.t_launch;
+            s->st.in_flight -= (int64_t)sl.tickets.size();
+            sl.tickets.clear();
+            sl.busy = false;
+            s->cv_done.notify_all();
+        }
+        if (s->stopping && !any_busy) break;
+        // launch batches on free slots (continuous batching)
+        bool launched = false;
+        if (!s->stopping) {
+            for (Slot &sl : s->slots) {
+                if (sl.busy || s->queue.empty()) continue;
+                std::vector<int32_t> ns;
+                for (size_t i = 0; i < s->queue.size() && (int)i < s->opts.max_queries_per_batch; i++)
+                    ns.push_back(s->tickets[s->queue[i]].n);
+                int64_t bytes = 0;
+                const int take = rxgs_plan_batch(ns.data(), (int32_t)ns.size(), s->opts.mode, s->ctx->scene.K,
+                                                 s->ctx->g.H, s->ctx->g.W, s->slot_budget,
+                                                 s->opts.max_rx_per_batch, s->opts.max_queries_per_batch, &bytes);
+                if (take < 1) break;
+                std::vector<Ticket *> batch;
+                sl.tickets.clear();
+                int nrx = 0;
+                const double t = now_s();
+                for (int i = 0; i < take; i++) {
+                    Ticket &tk = s->tickets[s->queue.front()];
+                    s->queue.pop_front();
+                    tk.state = T_RUNNING;
+                    tk.t_start = t;
+                    batch.push_back(&tk);
+                    sl.tickets.push_back(tk.id);
+                    nrx += tk.n;
+                }
+                for (Ticket *tk : batch) {
+                    tk->batch_q = take;
+                    tk->batch_n = nrx;
+                }
+                s->st.queued -= take;
+                s->st.in_flight += take;
+                s->st.batches++;
+                s->st.receivers += nrx;
+                sl.busy = true;
+                sl.t_launch = t;
+                // ticket storage is stable while running (only this thread erases running tickets)
+                lk.unlock();
+                const rxgs_status rs = launch_batch(s, sl, batch);
+                lk.lock();
+                if (rs != RXGS_OK) {
+                    s->err = s->ctx->err;
+                    for (uint64_t id : sl.tickets) {
+                        auto it = s->tickets.find(id);
+                        if (it != s->tickets.end()) {
+                            it->second.state = T_FAILED;
+                            it->second.t_done = now_s();
+                        }
+                        s->st.failed++;
+                    }
+                    s->st.in_flight -= (int64_t)sl.tickets.size();
+                    sl.tickets.clear();
+                    sl.busy = false;
+                    (void)hipStreamSynchronize(sl.stream);
+                    (void)hipGetLastError();
+                    s->cv_done.notify_all();
+                }
+                launched = true;
+            }
+        }
+        if (launched) continue;
+        bool busy_now = false;
+        for (Slot &sl : s->slots) busy_now |= sl.busy;
+        if (busy_now)
+            s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+        else
+            s->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+    }
+    s->running = false;
+}
+
+}  // namespace
+
+extern "C" rxgs_status rxgs_server_start(rxgs_ctx *ctx, const rxgs_server_opts *opts, rxgs_server **out)
+{
+    if (!ctx || !opts || !out) return RXGS_E_INVALID;
+    *out = nullptr;
+    if (opts->max_rx_per_batch < 1 || opts->max_queries_per_batch < 1 || opts->slots < 1 || opts->slots > 8 ||
+        (opts->mode != RXGS_MODE_TX && opts->mode != RXGS_MODE_RX) || opts->queue_capacity < 1 ||
+        opts->mem_budget_bytes < 0) {
+        ctx->err = "invalid server options";
+        return RXGS_E_INVALID;
+    }
+    if (!ctx->scene.valid || (ctx->scene.has_features && !ctx->mlp.valid)) {
+        ctx->err = "server needs an uploaded scene (and MLP)";
+        return RXGS_E_STATE;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        (void)hipGetLastError();
+        return RXGS_E_DEVICE;
+    }
+    rxgs_server *s = new (std::nothrow) rxgs_server();
+    if (!s) return RXGS_E_OOM;
+    s->ctx = ctx;
+    s->opts = *opts;
+    int64_t budget = opts->mem_budget_bytes;
+    if (budget == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            (void)hipGetLastError();
+            fr = (size_t)8 << 30;
+        }
+        budget = (int64_t)(fr / 2);
+    }
+    s->slot_budget = budget / opts->slots;
+    s->slots.resize(opts->slots);
+    for (Slot &sl : s->slots) {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+            rxgs_saved_create(ctx, &sl.saved) != RXGS_OK) {
+            (void)hipGetLastError();
+            ctx->err = "server slot creation failed";
+            rxgs_server_stop(s);
+            return RXGS_E_DEVICE;
+        }
+    }
+    s->running = true;
+    s->worker = std::thread(worker_main, s);
+    *out = s;
+    return RXGS_OK;
+}
+
+extern "C" rxgs_status rxgs_server_submit(rxgs_server *s, const float *tx, int32_t n, const float *rx_host,
+                                          uint64_t *ticket)
+{
+    if (!s || !tx || !rx_host || !ticket || n < 1) return RXGS_E_INVALID;
+    if (n > s->opts.max_rx_per_batch) return RXGS_E_INVALID;
+    for (int i = 0; i < 3; i++)
+        if (!std::isfinite(tx[i])) return RXGS_E_INVALID;
+    for (int64_t i = 0; i < 3 * (int64_t)n; i++)
+        if (!std::isfinite(rx_host[i])) return RXGS_E_INVALID;
+    if (rxgs_workspace_estimate(s->opts.mode, 1, n, s->ctx->scene.K, s->ctx->g.H, s->ctx->g.W) > s->slot_budget) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->st.rejected++;
+        return RXGS_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping || !s->running) return RXGS_E_STATE;
+    if ((int64_t)s->queue.size() >= s->opts.queue_capacity) {
+        s->st.rejected++;
+        return RXGS_E_BUSY;
+    }
+    Ticket tk;
+    tk.id = s->next_id++;
+    std::memcpy(tk.tx, tx, 12);
+    tk.rx.assign(rx_host, rx_host + 3 * (size_t)n);
+    tk.n = n;
+    tk.t_submit = now_s();
+    const uint64_t id = tk.id;
+    s->tickets.emplace(id, std::move(tk));
+    s->queue.push_back(id);
+    s->st.submitted++;
+    s->st.queued++;
+    *ticket = id;
+    s->cv_work.notify_one();
+    return RXGS_OK;
+}
+
+extern "C" rxgs_status rxgs_server_poll(rxgs_server *s, uint64_t ticket, float *power_host, float *C_host,
+                                        rxgs_ticket_info *info, int32_t timeout_ms)
+{
+    if (!s) return RXGS_E_INVALID;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return RXGS_E_INVALID;
+    auto ready = [&] {
+        auto i2 = s->tickets.find(ticket);
+        return i2 == s->tickets.end() || i2->second.state >= T_DONE;
+    };
+    if (timeout_ms < 0)
+        s->cv_done.wait(lk, ready);
+    else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
+        return RXGS_E_TIMEOUT;
+    it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return RXGS_E_INVALID;
+    Ticket &tk = it->second;
+    rxgs_status rs = RXGS_OK;
+    if (tk.state == T_CANCELLED) rs = RXGS_E_CANCELLED;
+    else if (tk.state == T_FAILED) rs = RXGS_E_DEVICE;
+    else {
+        if (power_host) std::memcpy(power_host, tk.power.data(), tk.power.size() * 4);
+        if (C_host && !tk.C.empty()) std::memcpy(C_host, tk.C.data(), tk.C.size() * 4);
+    }
+    if (info) {
+        info->t_submit = tk.t_submit;
+        info->t_start = tk.t_start;
+        info->t_done = tk.t_done;
+        info->batch_queries = tk.batch_q;
+        info->batch_receivers = tk.batch_n;
+    }
+    s->tickets.erase(it);
+    return rs;
+}
+
+extern "C" rxgs_status rxgs_server_cancel(rxgs_server *s, uint64_t ticket)
+{
+    if (!s) return RXGS_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return RXGS_E_INVALID;
+    if (it->second.state != T_QUEUED) return RXGS_E_STATE;
+    auto q = std::find(s->queue.begin(), s->queue.end(), ticket);
+    if (q != s->queue.end()) s->queue.erase(q);
+    it->second.state = T_CANCELLED;
+    it->second.t_done = now_s();
+    s->st.cancelled++;
+    s->st.queued--;
+    s->cv_done.notify_all();
+    return RXGS_OK;
+}
+
+extern "C" rxgs_status rxgs_server_stats(rxgs_server *s, rxgs_server_stats_t *out)
+{
+    if (!s || !out) return RXGS_E_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->st;
+    return RXGS_OK;
+}
+
+extern "C" rxgs_status rxgs_server_stop(rxgs_server *s)
+{
+    if (!s) return RXGS_E_INVALID;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+        for (uint64_t id : s->queue) {
+            auto it = s->tickets.find(id);
+            if (it != s->tickets.end()) {
+                it->second.state = T_CANCELLED;
+                s->st.cancelled++;
+            }
+        }
+        s->queue.clear();
+        s->st.queued = 0;
+        s->cv_work.notify_all();
+        s->cv_done.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipSetDevice(s->ctx->device);
+    for (Slot &sl : s->slots) {
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.saved) rxgs_saved_destroy(sl.saved);
+        release(sl.d_tx);
+        release(sl.d_rx);
+        release(sl.d_C);
+        release(sl.d_P);
+        if (sl.h_in) (void)hipHostFree(sl.h_in);
+        if (sl.h_P) (void)hipHostFree(sl.h_P);
+        if (sl.h_C) (void)hipHostFree(sl.h_C);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
+    delete s;
+    return RXGS_OK;
+}

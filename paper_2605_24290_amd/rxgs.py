@@ -50,6 +50,22 @@ class CSavedInfo(ctypes.Structure):
                 ("D", c_int64), ("n_visible", c_int64), ("tiles", c_int64), ("tiles_x", c_int64)]
 
 
+class CServerOpts(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", c_int64), ("max_rx_per_batch", c_int32), ("max_queries_per_batch", c_int32),
+                ("slots", c_int32), ("mode", c_int32), ("queue_capacity", c_int32), ("want_spectra", c_int32)]
+
+
+class CTicketInfo(ctypes.Structure):
+    _fields_ = [("t_submit", c_double), ("t_start", c_double), ("t_done", c_double),
+                ("batch_queries", c_int32), ("batch_receivers", c_int32)]
+
+
+class CServerStats(ctypes.Structure):
+    _fields_ = [("submitted", c_int64), ("completed", c_int64), ("cancelled", c_int64), ("rejected", c_int64),
+                ("failed", c_int64), ("batches", c_int64), ("receivers", c_int64), ("queued", c_int64),
+                ("in_flight", c_int64), ("busy_s", c_double)]
+
+
 class CStageTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", c_int64), ("total_ms", c_double)]
 
@@ -57,7 +73,9 @@ class CStageTime(ctypes.Structure):
 EXPORTED = ("rxgs_create", "rxgs_destroy", "rxgs_last_error", "rxgs_scene_upload", "rxgs_mlp_upload",
             "rxgs_saved_create", "rxgs_saved_destroy", "rxgs_render", "rxgs_render_backward",
             "rxgs_saved_info", "rxgs_saved_export", "rxgs_version", "rxgs_profile_enable",
-            "rxgs_profile_read")
+            "rxgs_profile_read", "rxgs_server_start", "rxgs_server_submit", "rxgs_server_poll",
+            "rxgs_server_cancel", "rxgs_server_stats", "rxgs_server_stop", "rxgs_plan_batch",
+            "rxgs_workspace_estimate")
 
 _lib = None
 
@@ -87,6 +105,20 @@ def lib():
         L.rxgs_render_backward.argtypes = [vp, vp, vp, vp, vp, POINTER(CGrads), vp]
     L.rxgs_saved_info.argtypes = [vp, POINTER(CSavedInfo)]
     L.rxgs_saved_export.argtypes = [vp, c_int, vp, c_int64, c_int]
+    L.rxgs_server_start.argtypes = [vp, POINTER(CServerOpts), POINTER(vp)]
+    L.rxgs_server_submit.argtypes = [vp, vp, c_int32, vp, POINTER(ctypes.c_uint64)]
+    L.rxgs_server_poll.argtypes = [vp, ctypes.c_uint64, vp, vp, POINTER(CTicketInfo), c_int32]
+    L.rxgs_server_cancel.argtypes = [vp, ctypes.c_uint64]
+    L.rxgs_server_stats.argtypes = [vp, POINTER(CServerStats)]
+    L.rxgs_server_stop.argtypes = [vp]
+    L.rxgs_plan_batch.argtypes = [POINTER(c_int32), c_int32, c_int32, c_int64, c_int32, c_int32, c_int64, c_int32,
+                                  c_int32, POINTER(c_int64)]
+    L.rxgs_plan_batch.restype = c_int32
+    L.rxgs_workspace_estimate.argtypes = [c_int32, c_int32, c_int32, c_int64, c_int32, c_int32]
+    L.rxgs_workspace_estimate.restype = c_int64
+    for name in ("rxgs_server_start", "rxgs_server_submit", "rxgs_server_poll", "rxgs_server_cancel",
+                 "rxgs_server_stats", "rxgs_server_stop"):
+        getattr(L, name).restype = c_int
     L.rxgs_profile_enable.argtypes = [vp, c_int]
     L.rxgs_profile_read.argtypes = [vp, POINTER(CStageTime), c_int, POINTER(c_int), c_int]
     for name in ("rxgs_create", "rxgs_scene_upload", "rxgs_mlp_upload", "rxgs_saved_create", "rxgs_render",
@@ -262,6 +294,83 @@ class Renderer:
             pass
 
 
+class Server:
+    """Continuous-batching server on a Renderer (rxgs_server_*)."""
+
+    def __init__(self, renderer: Renderer, mode: str = "tx", max_rx_per_batch: int = 2048,
+                 max_queries_per_batch: int = 64, slots: int = 2, queue_capacity: int = 1 << 20,
+                 want_spectra: bool = False, mem_budget_bytes: int = 0):
+        self.renderer = renderer
+        self.want_spectra = want_spectra
+        o = CServerOpts(mem_budget_bytes, max_rx_per_batch, max_queries_per_batch, slots,
+                        MODE_TX if mode == "tx" else MODE_RX, queue_capacity, 1 if want_spectra else 0)
+        h = c_void_p()
+        _check(lib().rxgs_server_start(renderer._ctx, byref(o), byref(h)), renderer._ctx)
+        self._h = h
+        self._n = {}
+
+    def submit(self, tx, rx) -> int:
+        tx = np.ascontiguousarray(np.asarray(tx, dtype=np.float32).reshape(3))
+        rx = np.ascontiguousarray(np.asarray(rx, dtype=np.float32).reshape(-1, 3))
+        t = ctypes.c_uint64()
+        st = lib().rxgs_server_submit(self._h, tx.ctypes.data_as(c_void_p), rx.shape[0],
+                                      rx.ctypes.data_as(c_void_p), byref(t))
+        if st != 0:
+            raise RxgsError(st, "submit rejected")
+        self._n[t.value] = rx.shape[0]
+        return t.value
+
+    def poll(self, ticket: int, timeout_ms: int = -1):
+        """(power (n,), spectra (n,2,H,W) or None, info dict); raises RxgsError on timeout/failure."""
+        n = self._n[ticket]
+        power = np.zeros(n, dtype=np.float32)
+        C = None
+        if self.want_spectra:
+            g = self.renderer.grid
+            C = np.zeros((n, 2, g.H, g.W), dtype=np.float32)
+        info = CTicketInfo()
+        st = lib().rxgs_server_poll(self._h, ticket, power.ctypes.data_as(c_void_p),
+                                    None if C is None else C.ctypes.data_as(c_void_p), byref(info), timeout_ms)
+        if st != 0:
+            if st != 6:
+                self._n.pop(ticket, None)
+            raise RxgsError(st, f"ticket {ticket}")
+        self._n.pop(ticket, None)
+        return power, C, {f: getattr(info, f) for f, _ in CTicketInfo._fields_}
+
+    def cancel(self, ticket: int) -> int:
+        return lib().rxgs_server_cancel(self._h, ticket)
+
+    def stats(self) -> dict:
+        s = CServerStats()
+        _check(lib().rxgs_server_stats(self._h, byref(s)))
+        return {f: getattr(s, f) for f, _ in CServerStats._fields_}
+
+    def stop(self):
+        if getattr(self, "_h", None) is not None:
+            lib().rxgs_server_stop(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
+
+
+def plan_batch(n_rx, mode: str, K: int, H: int, W: int, budget: int, max_rx: int, max_queries: int):
+    """Host batch planner of the server: (queries taken, workspace bytes)."""
+    arr = (c_int32 * max(len(n_rx), 1))(*[int(x) for x in n_rx])
+    b = c_int64(0)
+    take = lib().rxgs_plan_batch(arr, len(n_rx), MODE_TX if mode == "tx" else MODE_RX, K, H, W, budget, max_rx,
+                                 max_queries, byref(b))
+    return int(take), int(b.value)
+
+
+def workspace_estimate(mode: str, Q: int, N: int, K: int, H: int, W: int) -> int:
+    return int(lib().rxgs_workspace_estimate(MODE_TX if mode == "tx" else MODE_RX, Q, N, K, H, W))
+
+
 def grid_from(H: int, W: int, el0: float, del_el: float):
     """Plain grid record with the attributes the Renderer needs."""
     from .scenes import Grid
@@ -272,4 +381,5 @@ def version() -> str:
     return lib().rxgs_version().decode()
 
 
-__all__ = ["Renderer", "Saved", "RxgsError", "lib", "version", "MODE_TX", "MODE_RX", "EXPORTED"]
+__all__ = ["Renderer", "Saved", "Server", "RxgsError", "lib", "version", "plan_batch", "workspace_estimate",
+           "MODE_TX", "MODE_RX", "EXPORTED"]

@@ -201,3 +201,19 @@ def poisson_queries(rng: np.random.Generator, rate: float, count: int, box,
         rxq = _uniform_box(rng, n, box).astype(np.float32)
         out.append((t, txq, rxq))
     return out
+
+
+def serving_queries(seed: int, count: int, box, max_rx: int = 256):
+    """Seeded serving queries at unit rate: Exp(1) inter-arrival gaps (scale by
+    1 / rate), receiver counts floor(exp(U(0, ln(max_rx + 1)))) clipped to
+    [1, max_rx], transmitter and receivers uniform in the box."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gaps = rng.exponential(1.0, size=count)
+    out = []
+    for i in range(count):
+        n = int(math.floor(math.exp(rng.uniform(0.0, math.log(max_rx + 1)))))
+        n = min(max(n, 1), max_rx)
+        txq = _uniform_box(rng, 1, box).astype(np.float32)[0]
+        rxq = _uniform_box(rng, n, box).astype(np.float32)
+        out.append((float(gaps[i]), txq, rxq))
+    return out
