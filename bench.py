@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--no-other-mode", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the oracle sample")
+    ap.add_argument("--no-train", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-queries", type=int, default=400)
     return ap.parse_args()
 
 
@@ -125,6 +128,73 @@ def gpu_part(args):
     return wl, res
 
 
+def train_step_part(args):
+    """Forward + L2 loss gradient + hand-written backward on the 100k-Gaussian,
+    32-receiver workload (gradients for every scene and MLP parameter; no
+    optimizer update)."""
+    import torch
+    from paper_2605_24290_amd import rxgs
+    from paper_2605_24290_amd import scenes as S
+
+    wl = S.make_workload("c2")
+    sc = wl.scene
+    dev = torch.device("cuda", 0)
+    r = rxgs.Renderer(wl.grid)
+    r.upload_scene(sc.means, sc.log_scales, sc.quats, sc.logits, features=sc.features)
+    r.upload_mlp(S.flat_mlp(wl.mlp))
+    rx = torch.as_tensor(wl.rx, device=dev)
+    tx = torch.as_tensor(wl.tx, device=dev)
+    Y = torch.as_tensor(wl.targets, device=dev)
+    saved = rxgs.Saved(r)
+    grads = None
+    out = {}
+    for mode in ("rx", "tx"):
+        def step():
+            nonlocal grads
+            C, P, _ = r.render(rx, tx=tx, mode=mode, saved=saved)
+            grads = r.backward(saved, C, 2.0 * (C - Y), None, grads)
+        ms = timed(step, max(3, args.steps // 4), 2)
+        r.profile(True)
+        r.profile_read(reset=True)
+        timed(step, 3, 0)
+        stages = r.profile_read(reset=True)
+        r.profile(False)
+        out[mode] = {"ms_per_step": ms, "rx_views_per_s": wl.rx.shape[0] * 1000.0 / ms,
+                     "stages_ms_per_step": {k: v[1] / 3 for k, v in stages.items()}}
+    saved.close()
+    r.close()
+    return {"workload": f"c2: {sc.K} Gaussians, {wl.rx.shape[0]} receivers, 90x360, MLP, L2 loss, forward + "
+                        "backward to all parameters (no optimizer update)", **out}
+
+
+def serving_part(args):
+    """Continuous batching on the 200k-Gaussian scene: saturation throughput of
+    a burst, then open-loop Poisson arrivals at 0.3 / 0.6 / 0.9 of it."""
+    from paper_2605_24290_amd import rxgs, serving
+    from paper_2605_24290_amd import scenes as S
+
+    wl = S.make_workload("c3", N=1)
+    sc = wl.scene
+    r = rxgs.Renderer(wl.grid)
+    r.upload_scene(sc.means, sc.log_scales, sc.quats, sc.logits, features=sc.features)
+    r.upload_mlp(S.flat_mlp(wl.mlp))
+    box = S.PRESETS["c3"].box
+    srv = rxgs.Server(r, mode="tx", slots=2, max_rx_per_batch=4096, max_queries_per_batch=64)
+    warm = S.serving_queries(1, 64, box)
+    serving.run_burst(srv, warm)
+    qs = S.serving_queries(S.BASE_SEED + 3000, args.serve_queries, box)
+    sat = serving.run_burst(srv, qs)
+    rates = {}
+    for f in (0.3, 0.6, 0.9):
+        rates[str(f)] = serving.run_open_loop(srv, qs, rate=f * sat["achieved_qps"])
+    st = srv.stats()
+    srv.stop()
+    r.close()
+    return {"workload": f"c3: {sc.K} Gaussians resident, TX mode, queries of 1-256 receivers (log-uniform), "
+                        f"{args.serve_queries} queries per rate, 2 slots", "saturation": sat,
+            "rates_x_saturation": rates, "server_stats": st}
+
+
 def roofline_for(entry):
     """Roofline entry for the stage with the largest time share."""
     st = entry["stages_ms_per_step"]
@@ -192,6 +262,10 @@ def main():
         "other_modes": {k: v for k, v in res.items() if k != args.mode},
         "roofline": roofline_for(head),
     }
+    if not args.no_train:
+        out["train_step"] = train_step_part(args)
+    if not args.no_serve:
+        out["serving"] = serving_part(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, wl, args.mode)
     print(json.dumps(out), flush=True)
