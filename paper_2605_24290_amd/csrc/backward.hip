@@ -25,6 +25,9 @@ constexpr int W1B_CHUNK = 128;                        // Gaussians per dW1b part
 constexpr float LN2F = 0.69314718055994531f;
 
 // ----------------------------------------------------------------------------
+// Same (tile, receiver chunk) grid, pixel mapping, LDS staging and per-wave
+// entry lists as the forward; batches are staged from the end of the consumed
+// part of the tile list towards its start and walked in reverse.
 template <int R>
 __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
     const float4 *__restrict__ srec, const uint32_t *__restrict__ pval, const uint2 *__restrict__ ranges,
@@ -33,11 +36,8 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
     const float *__restrict__ Tfin, const int *__restrict__ nlast, float *__restrict__ dS,
     float *__restrict__ g2d)
 {
-    __shared__ float4 s_r0[BLOCK];
-    __shared__ float4 s_r1[BLOCK];
+    __shared__ BlendStage st;
     __shared__ float2 s_rad[R][BLOCK];
-    __shared__ int s_wide[BLOCK];
-    __shared__ uint32_t s_p[BLOCK];
     __shared__ int s_max[4];
 
     const int tile = blockIdx.x;
@@ -46,11 +46,10 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
     const int tread = tx_mode ? view : j0;
     const int ty = tile / g.tiles_x, tx = tile - ty * g.tiles_x;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int row = ty * TILE + (t >> 4), col = tx * TILE + (t & 15);
+    const int row = ty * TILE + 8 * (wv >> 1) + (lane >> 3), col = tx * TILE + 8 * (wv & 1) + (lane & 7);
     const bool inside = row < g.H && col < g.W;
     const float rowf = (float)row, colf = (float)col;
     const float Wf = (float)g.W, halfW = 0.5f * (float)g.W;
-    const float tcol = (float)(tx * TILE) + 7.5f;
     const uint2 rg = ranges[(size_t)view * g.tiles + tile];
     const int64_t view_end = ((int64_t)view + 1) * Kp;
     const size_t P = (size_t)g.H * g.W;
@@ -84,33 +83,28 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
         const int start = max(0, end - BLOCK);
         const int cnt = end - start;
         __syncthreads();
+        uint32_t p = 0;
         if (t < cnt) {
-            const uint32_t p = (uint32_t)min((int64_t)pval[rg.x + start + t], view_end - 1);
-            float4 r0 = srec[2 * (size_t)p];
-            const float4 r1 = srec[2 * (size_t)p + 1];
-            const float sh = rintf((tcol - r0.x) / Wf);
-            r0.x = fmaf(sh, Wf, r0.x);
-            s_wide[t] = fabsf(tcol - (r0.x + r0.y)) >= halfW - 9.0f;
-            s_r0[t] = r0;
-            s_r1[t] = r1;
-            s_p[t] = p;
+            p = (uint32_t)min((int64_t)pval[rg.x + start + t], view_end - 1);
             const int64_t s = max((int64_t)p - (int64_t)view * Kp, (int64_t)0);
 #pragma unroll
             for (int r = 0; r < R; r++)
                 s_rad[r][t] = (r < nrx) ? rad[(size_t)(j0 + r) * Kp + s] : make_float2(0.f, 0.f);
         }
-        __syncthreads();
-        for (int e = cnt - 1; e >= 0; e--) {
+        stage_batch(st, srec, p, t < cnt, tx, ty, g);
+        const int n = st.len[wv];
+        for (int i = n - 1; i >= 0; i--) {
+            const int e = st.list[wv][i];
             bool act = inside && (start + e) < last;
             float gu = 0.f, gv = 0.f, gca = 0.f, gcb = 0.f, gcc = 0.f, glo = 0.f;
             float2 dsr[R];
 #pragma unroll
             for (int r = 0; r < R; r++) dsr[r] = make_float2(0.f, 0.f);
             if (act) {
-                const float4 r0 = s_r0[e];
-                const float4 r1 = s_r1[e];
+                const float4 r0 = st.r0[e];
+                const float4 r1 = st.r1[e];
                 float du = (colf - r0.x) - r0.y;
-                if (s_wide[e]) {
+                if (st.wide[e]) {
                     if (du >= halfW) du -= Wf;
                     else if (du < -halfW) du += Wf;
                 }
@@ -146,14 +140,14 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
                 }
             }
             if (__ballot(act) == 0) continue;   // uniform across the wave
-            const uint32_t p = s_p[e];
+            const uint32_t pe = st.p[e];
             float vals[6] = {gu, gv, gca, gcb, gcc, glo};
 #pragma unroll
             for (int c = 0; c < 6; c++) {
                 const float v = wave_sum_last(vals[c]);
-                if (lane == 63 && v != 0.f) atomicAdd(&g2d[(size_t)p * 8 + c], v);
+                if (lane == 63 && v != 0.f) atomicAdd(&g2d[(size_t)pe * 8 + c], v);
             }
-            const int64_t s = (int64_t)p - (int64_t)view * Kp;
+            const int64_t s = (int64_t)pe - (int64_t)view * Kp;
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 if (r < nrx) {
@@ -182,7 +176,7 @@ __global__ __launch_bounds__(BLOCK) void k_rad_direct_bwd(const float2 *__restri
     if (idx >= (int64_t)N * Kp) return;
     const int64_t j = idx / Kp, s = idx - j * Kp;
     const int v = rxview[j];
-    if (s >= (int64_t)counters[1 + v]) return;
+    if (s >= (int64_t)counters[2 * (size_t)v]) return;
     const float2 d = dS[idx];
     if (d.x == 0.f && d.y == 0.f) return;
     const int64_t k = min((int64_t)order[(size_t)v * Kp + s], K - 1);
@@ -239,7 +233,7 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
     for (int item = gw; item < nitems; item += nw) {
         const int4 it = items[item];
         const int view = it.x, s0 = it.y, j0 = it.z, nj = it.w;
-        const int64_t nv = (int64_t)counters[1 + view];
+        const int64_t nv = (int64_t)counters[2 * (size_t)view];
         const int64_t s = s0 + pl;
         const bool valid = s < nv;
         const size_t obase = (size_t)view * Kp;
@@ -516,7 +510,7 @@ __global__ __launch_bounds__(BLOCK) void k_project_bwd(
     const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (p >= (int64_t)V * Kp) return;
     const int64_t v = p / Kp, s = p - v * Kp;
-    if (s >= (int64_t)counters[1 + v]) return;
+    if (s >= (int64_t)counters[2 * (size_t)v]) return;
     const float *gg = g2d + (size_t)p * 8;
     const double g_u = gg[0], g_v = gg[1], g_ca = gg[2], g_cb = gg[3], g_cc = gg[4], g_lo = gg[5];
     if (g_u == 0 && g_v == 0 && g_ca == 0 && g_cb == 0 && g_cc == 0 && g_lo == 0) return;

@@ -7,6 +7,11 @@ namespace rxgs {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+__device__ __forceinline__ int count_below(uint64_t m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Blend exponent of one (pixel, record): log2 of o exp(-q/2), with the record
 // holding (-a/2, -b, -c/2) log2(e) and log2(o).  Written with explicit fmaf so
 // that the forward and the backward evaluate bit-identical weights.
@@ -57,6 +62,84 @@ __device__ __forceinline__ float wave_sum_last(float x)
     x = half_wave_sum(x);
     x += dpp_shift<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
     return x;
+}
+
+// ---------------------------------------------------------------------------
+// LDS staging of one batch of a tile's list for the blend kernels.
+struct BlendStage {
+    float4 r0[BLOCK];            // (floor u shifted near the tile, frac u, floor v, frac v)
+    float4 r1[BLOCK];            // exponent coefficients and log2 opacity
+    uint32_t p[BLOCK];           // sorted position of the entry
+    int wide[BLOCK];             // azimuth offsets inside the tile may need wrapping
+    unsigned short list[4][BLOCK];  // per wave: entries (in list order) that can reach its sub-tile
+    int len[4];
+    int wcnt[4][4];
+};
+
+// Conservative sub-tile mask of one record: bit w set when the box around the
+// ellipse {ex >= log2(1/255)} meets wave w's 8 x 8 sub-tile.
+__device__ __forceinline__ int subtile_mask(const float4 &r0, const float4 &r1, int wide, int tx, int ty)
+{
+    if (wide) return 0xF;
+    float lo = r1.w - (-7.99435343685886f);   // log2 o - log2(1/255)
+    if (!(lo >= -1e-3f)) return 0;
+    lo = fmaxf(lo, 0.f) + 1e-3f;
+    const float muu = -r1.x, muv = -0.5f * r1.y, mvv = -r1.z;
+    const float det = muu * mvv - muv * muv;
+    if (!(det > 0.f)) return 0xF;
+    const float ru = sqrtf(lo * mvv / det) * 1.001f + 0.05f;
+    const float rv = sqrtf(lo * muu / det) * 1.001f + 0.05f;
+    const float u = r0.x + r0.y, v = r0.z + r0.w;
+    const float c0 = (float)(tx * TILE), r0f = (float)(ty * TILE);
+    int m = 0;
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+        const float cl = c0 + 8.f * (float)(w & 1), rl = r0f + 8.f * (float)(w >> 1);
+        const bool hit = (u + ru >= cl) && (u - ru <= cl + 7.f) && (v + rv >= rl) && (v - rv <= rl + 7.f);
+        m |= hit ? (1 << w) : 0;
+    }
+    return m;
+}
+
+// Stage the batch entry of this thread (if `has`) and build the per-wave lists.
+// All threads of the block must call it.
+__device__ __forceinline__ void stage_batch(BlendStage &st, const float4 *__restrict__ srec, uint32_t p, bool has,
+                                            int tx, int ty, const DevGrid &g)
+{
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    int m = 0;
+    if (has) {
+        float4 r0 = srec[2 * (size_t)p];
+        const float4 r1 = srec[2 * (size_t)p + 1];
+        const float Wf = (float)g.W, halfW = 0.5f * (float)g.W;
+        const float tcol = (float)(tx * TILE) + 7.5f;
+        // representative of the azimuth closest to this tile's centre
+        const float sh = rintf((tcol - r0.x) / Wf);
+        r0.x = fmaf(sh, Wf, r0.x);
+        const int wide = fabsf(tcol - (r0.x + r0.y)) >= halfW - 9.0f;
+        st.r0[t] = r0;
+        st.r1[t] = r1;
+        st.p[t] = p;
+        st.wide[t] = wide;
+        m = subtile_mask(r0, r1, wide, tx, ty);
+    }
+    uint64_t bal[4];
+#pragma unroll
+    for (int b = 0; b < 4; b++) bal[b] = __ballot((m >> b) & 1);
+    if (lane == 0)
+#pragma unroll
+        for (int b = 0; b < 4; b++) st.wcnt[w][b] = (int)__popcll(bal[b]);
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 4; b++) {
+        if ((m >> b) & 1) {
+            int pos = count_below(bal[b]);
+            for (int ww = 0; ww < w; ww++) pos += st.wcnt[ww][b];
+            st.list[b][pos] = (unsigned short)t;
+        }
+    }
+    if (t < 4) st.len[t] = st.wcnt[0][t] + st.wcnt[1][t] + st.wcnt[2][t] + st.wcnt[3][t];
+    __syncthreads();
 }
 
 }  // namespace rxgs

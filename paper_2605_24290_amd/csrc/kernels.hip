@@ -24,11 +24,6 @@
 
 namespace rxgs {
 
-__device__ __forceinline__ int count_below(uint64_t m)
-{
-    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x)
 {
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
@@ -104,8 +99,10 @@ __global__ __launch_bounds__(BLOCK) void k_project(
     const int v0 = blockIdx.y * vchunk;
     const int v1 = min(V, v0 + vchunk);
     const bool real = k < K;
+    __shared__ uint32_t s_cnt[4][2];
     const int lane = threadIdx.x & 63;
     float px = 0.f, py = 0.f, pz = 0.f, o32 = 0.f;
+    double qmax = 0.0, lo2 = 0.0;
     double S00 = 0, S01 = 0, S02 = 0, S11 = 0, S12 = 0, S22 = 0;
     if (real) {
         px = soa[k];
@@ -130,6 +127,10 @@ __global__ __launch_bounds__(BLOCK) void k_project(
         S12 = R10 * R20 * s0 + R11 * R21 * s1 + R12 * R22 * s2;
         S22 = R20 * R20 * s0 + R21 * R21 * s1 + R22 * R22 * s2;
         o32 = (float)(1.0 / (1.0 + exp(-(double)soa[10 * K + k])));
+        if (o32 >= ALPHA_MIN) {
+            qmax = 2.0 * log((double)o32 / (double)ALPHA_MIN);
+            lo2 = log2((double)o32);
+        }
     }
     for (int v = v0; v < v1; v++) {
         const size_t i = (size_t)v * Kp + k;
@@ -149,11 +150,13 @@ __global__ __launch_bounds__(BLOCK) void k_project(
                 double az = atan2(dy, dx);
                 if (az < 0.0) az += 2.0 * M_PI;
                 const double el = atan2(dz, h);
-                const double u = az / g.daz - 0.5;
-                const double vv = (el - g.el0) / g.del - 0.5;
-                const double hh = h * h, rh2 = hh + dz * dz, rh2h = rh2 * h;
-                const double mu0 = -dy / hh / g.daz, mu1 = dx / hh / g.daz;
-                const double mv0 = -dx * dz / rh2h / g.del, mv1 = -dy * dz / rh2h / g.del, mv2 = h / rh2 / g.del;
+                const double u = az * g.idaz - 0.5;
+                const double vv = (el - g.el0) * g.idel - 0.5;
+                const double hh = h * h, rh2 = hh + dz * dz;
+                const double ihh = g.idaz / hh;               // 1 / (h^2 daz)
+                const double irh = g.idel / (rh2 * h);        // 1 / (rho^2 h del)
+                const double mu0 = -dy * ihh, mu1 = dx * ihh;
+                const double mv0 = -dx * dz * irh, mv1 = -dy * dz * irh, mv2 = hh * irh;
                 const double Smv0 = S00 * mv0 + S01 * mv1 + S02 * mv2;
                 const double Smv1 = S01 * mv0 + S11 * mv1 + S12 * mv2;
                 const double Smv2 = S02 * mv0 + S12 * mv1 + S22 * mv2;
@@ -163,7 +166,6 @@ __global__ __launch_bounds__(BLOCK) void k_project(
                 const float u32 = (float)u, v32 = (float)vv;
                 e = make_float4(u32, v32, 0.f, 0.f);
                 if (o32 >= ALPHA_MIN) {
-                    const double qmax = 2.0 * log((double)o32 / (double)ALPHA_MIN);
                     const float rup = (float)(sqrt(qmax * A) * (1.0 + PAD_REL) + PAD_ABS);
                     const float rvp = (float)(sqrt(qmax * Cc) * (1.0 + PAD_REL) + PAD_ABS);
                     e.z = rup;
@@ -175,13 +177,13 @@ __global__ __launch_bounds__(BLOCK) void k_project(
                 }
                 vis = nt > 0;
                 if (vis) {
-                    const double det = A * Cc - B * B;
-                    const double ca = Cc / det, cb = -B / det, cc = A / det;
+                    const double idet = 1.0 / (A * Cc - B * B);
+                    const double ca = Cc * idet, cb = -B * idet, cc = A * idet;
                     const double uf = floor(u), vf = floor(vv);
                     constexpr double L2E = 1.4426950408889634;
                     rec[2 * i] = make_float4((float)uf, (float)(u - uf), (float)vf, (float)(vv - vf));
                     rec[2 * i + 1] = make_float4((float)(-0.5 * L2E * ca), (float)(-L2E * cb),
-                                                 (float)(-0.5 * L2E * cc), (float)log2((double)o32));
+                                                 (float)(-0.5 * L2E * cc), (float)lo2);
                     key = kb;
                 }
             }
@@ -195,9 +197,17 @@ __global__ __launch_bounds__(BLOCK) void k_project(
         const uint64_t bal = __ballot(vis);
         const uint32_t tsum = wave_sum_u32(nt);
         if (lane == 0) {
-            if (bal) atomicAdd(&counters[1 + v], (unsigned long long)__popcll(bal));
-            if (tsum) atomicAdd(&counters[0], (unsigned long long)tsum);
+            s_cnt[threadIdx.x >> 6][0] = (uint32_t)__popcll(bal);
+            s_cnt[threadIdx.x >> 6][1] = tsum;
         }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t nv = s_cnt[0][0] + s_cnt[1][0] + s_cnt[2][0] + s_cnt[3][0];
+            const uint32_t nd = s_cnt[0][1] + s_cnt[1][1] + s_cnt[2][1] + s_cnt[3][1];
+            if (nv) atomicAdd(&counters[2 * (size_t)v], (unsigned long long)nv);
+            if (nd) atomicAdd(&counters[2 * (size_t)v + 1], (unsigned long long)nd);
+        }
+        __syncthreads();
     }
 }
 
@@ -381,7 +391,7 @@ __global__ __launch_bounds__(BLOCK) void k_gather(const float4 *__restrict__ rec
     const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (p >= total) return;
     const int64_t v = p / Kp, s = p - v * Kp;
-    if (s < (int64_t)counters[1 + v]) {
+    if (s < (int64_t)counters[2 * (size_t)v]) {
         const size_t i = (size_t)v * Kp + min((int64_t)order[p], Kp - 1);
         srec[2 * p] = rec[2 * i];
         srec[2 * p + 1] = rec[2 * i + 1];
@@ -401,7 +411,7 @@ __global__ __launch_bounds__(BLOCK) void k_emit(const float4 *__restrict__ ext, 
     const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (p >= total) return;
     const int64_t v = p / Kp, s = p - v * Kp;
-    if (s >= (int64_t)counters[1 + v]) return;
+    if (s >= (int64_t)counters[2 * (size_t)v]) return;
     const float4 e = ext[(size_t)v * Kp + min((int64_t)order[p], Kp - 1)];
     int ty0, ty1, a0, a1, b0, b1;
     if (!tile_rows(e.y, e.w, g.H, ty0, ty1)) return;
@@ -445,7 +455,7 @@ __global__ __launch_bounds__(BLOCK) void k_rad_direct(const float2 *__restrict__
     if (idx >= (int64_t)N * Kp) return;
     const int64_t j = idx / Kp, s = idx - j * Kp;
     const int v = rxview[j];
-    if (s < (int64_t)counters[1 + v]) rad[idx] = radiance[min((int64_t)order[(size_t)v * Kp + s], K - 1)];
+    if (s < (int64_t)counters[2 * (size_t)v]) rad[idx] = radiance[min((int64_t)order[(size_t)v * Kp + s], K - 1)];
 }
 
 // receiver ("global") term of layer 1: W1[:, :36] gamma(r_j), stored in hid_pos order
@@ -469,20 +479,32 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_global(const float *__restrict__ 
 }
 
 // Gaussian ("local") term of layer 1: W1[:, 36:] f_k + b1, stored in hid_pos order
+// 64 Gaussians per workgroup, W1[:, 36:] and the features staged in LDS
 __global__ __launch_bounds__(BLOCK) void k_mlp_local(const float *__restrict__ W1, const float *__restrict__ b1,
                                                      const float *__restrict__ feat, int64_t K,
                                                      float *__restrict__ Lp)
 {
-    const int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (idx >= K * HID) return;
-    const int64_t k = idx / HID;
-    const int d = (int)(idx % HID);
-    float acc = b1[d];
-    const float *f = feat + k * FEAT;
-    const float *w = W1 + d * MLP_IN + ENC;
+    __shared__ float s_w[FEAT][HID + 1];
+    __shared__ float s_f[64][FEAT + 1];
+    const int64_t k0 = (int64_t)blockIdx.x * 64;
+    for (int i = threadIdx.x; i < HID * FEAT; i += BLOCK) {
+        const int d = i / FEAT, c = i % FEAT;
+        s_w[c][d] = W1[d * MLP_IN + ENC + c];
+    }
+    for (int i = threadIdx.x; i < 64 * FEAT; i += BLOCK) {
+        const int kk = i / FEAT, c = i % FEAT;
+        s_f[kk][c] = (k0 + kk < K) ? feat[(size_t)(k0 + kk) * FEAT + c] : 0.f;
+    }
+    __syncthreads();
+    const int d = threadIdx.x & 63;
+    const float bias = b1[d];
+    for (int kk = threadIdx.x >> 6; kk < 64; kk += BLOCK / 64) {
+        if (k0 + kk >= K) break;
+        float acc = bias;
 #pragma unroll
-    for (int i = 0; i < FEAT; i++) acc = fmaf(w[i], f[i], acc);
-    Lp[k * HID + hid_pos(d)] = acc;
+        for (int c = 0; c < FEAT; c++) acc = fmaf(s_w[c][d], s_f[kk][c], acc);
+        Lp[(size_t)(k0 + kk) * HID + hid_pos(d)] = acc;
+    }
 }
 
 // Per-(receiver, Gaussian) layers 2 and 3 on FP32 MFMA (v_mfma_f32_32x32x2f32).
@@ -507,11 +529,12 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_pairs(const float *__restrict__ L
     if (threadIdx.x < 64) s_tab[threadIdx.x] = tab[threadIdx.x];
     __syncthreads();
     const int lane = threadIdx.x & 63, h = lane >> 5, pl = lane & 31;
-    const int item = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
-    if (item >= nitems) return;
+    const float b30 = b3[0], b31 = b3[1];
+    // persistent waves: the workgroup stages W2 once and walks many work items
+    for (int item = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); item < nitems; item += gridDim.x * (BLOCK / 64)) {
     const int4 it = items[item];
     const int view = it.x, s0 = it.y, j0 = it.z, nj = it.w;
-    const int64_t nv = (int64_t)counters[1 + view];
+    const int64_t nv = (int64_t)counters[2 * (size_t)view];
     const int64_t s = s0 + pl;
     const bool valid = s < nv;
     const uint32_t k = (uint32_t)min((int64_t)order[(size_t)view * Kp + (valid ? s : s0)], K - 1);
@@ -524,9 +547,13 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_pairs(const float *__restrict__ L
             l[4 * q] = x.x; l[4 * q + 1] = x.y; l[4 * q + 2] = x.z; l[4 * q + 3] = x.w;
         }
     }
-    const float b30 = b3[0], b31 = b3[1];
     for (int jj = 0; jj < nj; jj++) {
         const int j = j0 + jj;
+        // an index the compiler cannot prove loop-invariant: keeps the layer-3
+        // and bias constants in LDS instead of ~100 hoisted registers
+        int z0 = 0;
+        asm volatile("" : "+v"(z0));
+        const float4 *tabh = s_tab + h * 32 + z0;
         float x1[32];
         const float4 *gs = reinterpret_cast<const float4 *>(Gp + (size_t)j * HID + h * 32);
 #pragma unroll
@@ -540,8 +567,8 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_pairs(const float *__restrict__ L
         floatx16 acc0, acc1;
 #pragma unroll
         for (int r = 0; r < 16; r++) {
-            acc0[r] = s_tab[(h * 2 + 0) * 16 + r].z;
-            acc1[r] = s_tab[(h * 2 + 1) * 16 + r].z;
+            acc0[r] = tabh[r].z;
+            acc1[r] = tabh[16 + r].z;
         }
 #pragma unroll
         for (int t = 0; t < 32; t++) {
@@ -551,8 +578,8 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_pairs(const float *__restrict__ L
         float o0 = 0.f, o1 = 0.f;
 #pragma unroll
         for (int r = 0; r < 16; r++) {
-            const float4 ta = s_tab[(h * 2 + 0) * 16 + r];
-            const float4 tb = s_tab[(h * 2 + 1) * 16 + r];
+            const float4 ta = tabh[r];
+            const float4 tb = tabh[16 + r];
             const float ha = fmaxf(acc0[r], 0.f), hb = fmaxf(acc1[r], 0.f);
             o0 = fmaf(ta.x, ha, o0);
             o1 = fmaf(ta.y, ha, o1);
@@ -563,14 +590,18 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_pairs(const float *__restrict__ L
         o1 += __shfl_xor(o1, 32);
         if (h == 0 && valid) rad[(size_t)j * Kp + s] = make_float2(o0 + b30, o1 + b31);
     }
+    }
 }
 
 // ----------------------------------------------------------------------------
 // Stage 3: front-to-back compositing.  One workgroup per (tile, chunk of R
-// receivers of one view); one pixel per thread.  Batches of 256 list entries
-// (record + R radiance values) are staged in LDS; every lane walks the batch
-// with its own transmittance.  A wave stops walking once all its lanes have
-// terminated; the workgroup stops loading once all its waves have.
+// receivers of one view); one pixel per thread, each wave an 8 x 8 sub-tile.
+// Batches of 256 list entries (record + R radiance values) are staged in LDS;
+// while staging, each entry's conservative support box is tested against the
+// four sub-tiles and a ballot/prefix pass builds, per wave, the ordered list of
+// entries that can reach it, so a wave walks only those.  Every lane keeps its
+// own transmittance; a wave stops once all its lanes have terminated and the
+// workgroup stops staging once all its waves have.
 template <int R>
 __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ srec,
                                                      const uint32_t *__restrict__ pval,
@@ -580,24 +611,21 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
                                                      float *__restrict__ C, float *__restrict__ Tfin,
                                                      int *__restrict__ nlast, float *__restrict__ part)
 {
-    __shared__ float4 s_r0[BLOCK];
-    __shared__ float4 s_r1[BLOCK];
+    __shared__ BlendStage st;
     __shared__ float2 s_rad[R][BLOCK];
-    __shared__ int s_wide[BLOCK];
     __shared__ float s_red[4][R][3];
 
     const int tile = blockIdx.x;
     const int4 ch = chunks[blockIdx.y];
     const int view = ch.x, j0 = ch.y, nrx = ch.z, tslot = ch.w;
     const int ty = tile / g.tiles_x, tx = tile - ty * g.tiles_x;
-    const int t = threadIdx.x;
-    const int row = ty * TILE + (t >> 4), col = tx * TILE + (t & 15);
+    const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+    const int row = ty * TILE + 8 * (wv >> 1) + (lane >> 3), col = tx * TILE + 8 * (wv & 1) + (lane & 7);
     const bool inside = row < g.H && col < g.W;
     const float rowf = (float)row, colf = (float)col;
     const float Wf = (float)g.W, halfW = 0.5f * (float)g.W;
-    const float tcol = (float)(tx * TILE) + 7.5f;
     const uint2 rg = ranges[(size_t)view * g.tiles + tile];
-    const int64_t view_end = ((int64_t)view + 1) * Kp;   // pair values of this view lie below
+    const int64_t view_end = ((int64_t)view + 1) * Kp;
 
     float T = 1.f;
     float2 acc[R];
@@ -609,34 +637,28 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
     for (uint32_t base = rg.x; base < rg.y; base += BLOCK) {
         const uint32_t cnt = min((uint32_t)BLOCK, rg.y - base);
         __syncthreads();
+        uint32_t p = 0;
         if ((uint32_t)t < cnt) {
-            const uint32_t p = min(pval[base + t], (uint32_t)(view_end - 1));
-            float4 r0 = srec[2 * (size_t)p];
-            const float4 r1 = srec[2 * (size_t)p + 1];
-            // representative of the azimuth closest to this tile's centre
-            const float sh = rintf((tcol - r0.x) / Wf);
-            r0.x = fmaf(sh, Wf, r0.x);
-            s_wide[t] = fabsf(tcol - (r0.x + r0.y)) >= halfW - 9.0f;
-            s_r0[t] = r0;
-            s_r1[t] = r1;
+            p = min(pval[base + t], (uint32_t)(view_end - 1));
             const int64_t s = max((int64_t)p - (int64_t)view * Kp, (int64_t)0);
 #pragma unroll
             for (int r = 0; r < R; r++)
                 s_rad[r][t] = (r < nrx) ? rad[(size_t)(j0 + r) * Kp + s] : make_float2(0.f, 0.f);
         }
-        __syncthreads();
+        stage_batch(st, srec, p, (uint32_t)t < cnt, tx, ty, g);
         if (!done) {
-            for (uint32_t e = 0; e < cnt; e++) {
-                const float4 r0 = s_r0[e];
-                const float4 r1 = s_r1[e];
+            const int n = st.len[wv];
+            for (int i = 0; i < n; i++) {
+                const int e = st.list[wv][i];
+                const float4 r0 = st.r0[e];
+                const float4 r1 = st.r1[e];
                 float du = (colf - r0.x) - r0.y;
-                if (s_wide[e]) {
+                if (st.wide[e]) {
                     if (du >= halfW) du -= Wf;
                     else if (du < -halfW) du += Wf;
                 }
                 const float dv = (rowf - r0.z) - r0.w;
-                const float ex = blend_exponent(du, dv, r1);
-                const float w = fminf(W_MAX, __builtin_amdgcn_exp2f(ex));
+                const float w = fminf(W_MAX, __builtin_amdgcn_exp2f(blend_exponent(du, dv, r1)));
                 if (w < ALPHA_MIN) continue;
                 const float tw = T * w;
 #pragma unroll
@@ -646,7 +668,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
                     acc[r].y = fmaf(tw, sv.y, acc[r].y);
                 }
                 T = T * (1.f - w);
-                last = (int)(base - rg.x + e + 1);
+                last = (int)(base - rg.x) + e + 1;
                 if (T < T_EPS) {
                     done = true;
                     break;
@@ -672,16 +694,15 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
         }
     }
     // per-tile partial sums: power, Re, Im (fixed-order reduction)
-    const int lane = t & 63, w = t >> 6;
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const float pw = wave_sum_f32(acc[r].x * acc[r].x + acc[r].y * acc[r].y);
         const float sr = wave_sum_f32(acc[r].x);
         const float si = wave_sum_f32(acc[r].y);
         if (lane == 0) {
-            s_red[w][r][0] = pw;
-            s_red[w][r][1] = sr;
-            s_red[w][r][2] = si;
+            s_red[wv][r][0] = pw;
+            s_red[wv][r][1] = sr;
+            s_red[wv][r][2] = si;
         }
     }
     __syncthreads();
@@ -694,22 +715,32 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
     }
 }
 
+// one wave per receiver; lanes take tiles in a fixed stride, then a fixed
+// butterfly, so the result does not depend on scheduling
 __global__ __launch_bounds__(BLOCK) void k_reduce_out(const float *__restrict__ part, int N, int tiles,
                                                       float *__restrict__ power, float *__restrict__ csum)
 {
-    const int j = blockIdx.x * BLOCK + threadIdx.x;
+    const int j = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (j >= N) return;
     double pw = 0, sr = 0, si = 0;
-    for (int t = 0; t < tiles; t++) {
+    for (int t = lane; t < tiles; t += 64) {
         const float *p = part + ((size_t)j * tiles + t) * 3;
         pw += p[0];
         sr += p[1];
         si += p[2];
     }
-    if (power) power[j] = (float)pw;
-    if (csum) {
-        csum[2 * j] = (float)sr;
-        csum[2 * j + 1] = (float)si;
+    for (int off = 32; off > 0; off >>= 1) {
+        pw += __shfl_xor(pw, off);
+        sr += __shfl_xor(sr, off);
+        si += __shfl_xor(si, off);
+    }
+    if (lane == 0) {
+        if (power) power[j] = (float)pw;
+        if (csum) {
+            csum[2 * j] = (float)sr;
+            csum[2 * j + 1] = (float)si;
+        }
     }
 }
 
@@ -860,7 +891,7 @@ hipError_t launch_mlp_local(const Scene &sc, const Mlp &m, Workspace &ws, hipStr
 {
     const float *raw = m.raw.as<float>();
     if (sc.K > 0)
-        hipLaunchKernelGGL(k_mlp_local, dim3(nblk((size_t)sc.K * HID)), dim3(BLOCK), 0, st, raw,
+        hipLaunchKernelGGL(k_mlp_local, dim3((unsigned)((sc.K + 63) / 64)), dim3(BLOCK), 0, st, raw,
                            raw + HID * MLP_IN, sc.feat.as<float>(), sc.K, ws.Lp.as<float>());
     return hipGetLastError();
 }
@@ -870,7 +901,7 @@ hipError_t launch_mlp_pairs(const Mlp &m, Workspace &ws, hipStream_t st)
     const float *raw = m.raw.as<float>();
     const float *b3 = raw + HID * MLP_IN + HID + HID * HID + HID + 2 * HID;
     if (ws.n_items > 0) {
-        const unsigned blocks = (unsigned)((ws.n_items + 3) / 4);
+        const unsigned blocks = (unsigned)std::min((ws.n_items + 3) / 4, 256 * 8);
         hipLaunchKernelGGL(k_mlp_pairs, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(), ws.Gp.as<float>(),
                            m.w2a.as<float>(), m.tab.as<float4>(), b3, ws.sval[ws.sorted_buf].as<uint32_t>(),
                            ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K, ws.counters.as<unsigned long long>(),
@@ -905,7 +936,7 @@ hipError_t launch_blend_fwd(Workspace &ws, float *C, hipStream_t st)
 hipError_t launch_reduce_outputs(Workspace &ws, float *power, float *csum, hipStream_t st)
 {
     if (ws.N == 0 || (!power && !csum)) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_out, dim3(nblk((size_t)ws.N)), dim3(BLOCK), 0, st, ws.part.as<float>(), ws.N,
+    hipLaunchKernelGGL(k_reduce_out, dim3((unsigned)((ws.N + 3) / 4)), dim3(BLOCK), 0, st, ws.part.as<float>(), ws.N,
                        ws.g.tiles, power, csum);
     return hipGetLastError();
 }

@@ -285,6 +285,8 @@ extern "C" rxgs_status rxgs_create(int device, const rxgs_grid *grid, rxgs_ctx *
     g.el0 = grid->el0;
     g.del = grid->del_el;
     g.daz = 2.0 * M_PI / (double)grid->W;
+    g.idaz = (double)grid->W / (2.0 * M_PI);
+    g.idel = 1.0 / grid->del_el;
     *out = ctx;
     return RXGS_OK;
 }
@@ -517,7 +519,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     GROW(ctx, ws.srec, VK * 32);
     GROW(ctx, ws.ntl_s, VK * 4);
     GROW(ctx, ws.poff, VK * 4);
-    GROW(ctx, ws.counters, (size_t)(1 + V) * 8);
+    GROW(ctx, ws.counters, (size_t)2 * V * 8);
     GROW(ctx, ws.hist, (VK / SORT_TILE) * 256 * 4);
     // block sums of two scans: the sort histograms (VK / 16 entries) and the
     // emission offsets (VK entries), 4096 entries per block
@@ -526,14 +528,14 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     HIPCHK(ctx, hipMemcpyAsync(ws.centres.p, mode == RXGS_MODE_TX ? tx : rx, (size_t)V * 12,
                                hipMemcpyDeviceToDevice, st));
     HIPCHK(ctx, hipMemcpyAsync(ws.rxpos.p, rx, (size_t)N * 12, hipMemcpyDeviceToDevice, st));
-    HIPCHK(ctx, launch_fill_u32(ws.counters.as<uint32_t>(), 0u, (size_t)(1 + V) * 2, st));
+    HIPCHK(ctx, launch_fill_u32(ws.counters.as<uint32_t>(), 0u, (size_t)V * 4, st));
 
     // stage 1: projection, then the per-view depth sort; the host waits only
     // for the counters (visible Gaussians per view, pair count) while the sort runs
     STAGE(ctx, "project", launch_project(sc, ws.centres.as<float>(), V, Kp, g, ws, st));
-    if (!ensure_pinned(ws, (size_t)(1 + V) * 8 + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
+    if (!ensure_pinned(ws, (size_t)2 * V * 8 + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
     unsigned long long *h_cnt = static_cast<unsigned long long *>(ws.h_pinned);
-    HIPCHK(ctx, hipMemcpyAsync(h_cnt, ws.counters.p, (size_t)(1 + V) * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipMemcpyAsync(h_cnt, ws.counters.p, (size_t)2 * V * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(ctx, hipEventRecord(ws.counted, st));
     int cur = 0;
     STAGE(ctx, "sort_depth", sort_pairs_u32(ws, ws.skey, ws.sval, ws.hist, ws.scan_tmp, cur, (uint32_t)VK, 32, Kp, st));
@@ -542,13 +544,14 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     STAGE(ctx, "scan", scan_exclusive_u32(ws.scan_tmp, ws.ntl_s.as<uint32_t>(), ws.poff.as<uint32_t>(), (uint32_t)VK, st));
     HIPCHK(ctx, hipEventSynchronize(ws.counted));
 
-    const uint64_t D = h_cnt[0];
+    uint64_t D = 0;
+    for (int v = 0; v < V; v++) D += h_cnt[2 * v + 1];
     if (D >= (1ull << 32) - 1) return fail(ctx, RXGS_E_INVALID, "more than 2^32 pairs; split the receivers");
     ws.D = (int64_t)D;
     ws.h_nvis.assign(V, 0);
     ws.nvis_total = 0;
     for (int v = 0; v < V; v++) {
-        ws.h_nvis[v] = (int)h_cnt[1 + v];
+        ws.h_nvis[v] = (int)h_cnt[2 * v];
         ws.nvis_total += ws.h_nvis[v];
     }
 
@@ -599,7 +602,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
 
     // one host-to-device copy of the small descriptors
     const size_t stage_bytes = (size_t)N * 4 + chunks.size() * 16 + items.size() * 16;
-    const size_t cnt_bytes = (size_t)(1 + V) * 8;
+    const size_t cnt_bytes = (size_t)2 * V * 8;
     const size_t off0 = (cnt_bytes + 63) / 64 * 64;
     if (!ensure_pinned(ws, off0 + stage_bytes + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
     char *hp = static_cast<char *>(ws.h_pinned) + off0;

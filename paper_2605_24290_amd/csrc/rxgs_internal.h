@@ -36,7 +36,7 @@ constexpr double PAD_ABS = 0.01;             //   binning ellipse box, px
 
 struct DevGrid {
     int H, W, tiles_x, tiles_y, tiles;
-    double el0, del, daz;
+    double el0, del, daz, idel, idaz;
 };
 
 // grow-only device buffer
@@ -103,7 +103,7 @@ struct Workspace {
     DevBuf part;      // N x tiles x 3
     DevBuf chunks;    // int4
     DevBuf items;     // int4
-    DevBuf counters;  // u64: [0] D, [1..V] nvis
+    DevBuf counters;  // u64 per view: [2 v] visible Gaussians, [2 v + 1] pairs
     DevBuf hist;      // radix histograms (depth sort)
     DevBuf scan_tmp;  // scan block sums (depth sort, emission offsets)
     DevBuf hist_b;    // radix histograms (pair sort)
