@@ -299,58 +299,92 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t *__restrict_
 }
 
 // ----------------------------------------------------------------------------
-// Stable LSD radix sort, 8-bit digits.  A pass is a per-block digit histogram,
-// an exclusive scan over (segment, digit, block), and a stable scatter that
-// ranks equal digits inside each wave with 8 ballots.  With seg_blocks > 0 the
-// key space is cut into segments of seg_blocks blocks that are sorted
-// independently (one segment per view).
-__device__ __forceinline__ size_t hist_index(uint32_t d, uint32_t blk, uint32_t nblocks, uint32_t seg_blocks)
+// Stable LSD radix sort, 8-bit digits, 4096 keys per block.  A pass is a
+// per-block digit histogram, an exclusive scan over (segment, digit, block),
+// and a stable scatter.  Segments are runs of whole blocks sorted
+// independently: either uniform (seg_blocks blocks each) or given per block by
+// a table (first block, block count) for segments of different lengths.
+struct SegMap {
+    uint32_t seg_blocks;          // uniform segment length in blocks (0: use tab or none)
+    const int4 *tab;              // per block: (first block of its segment, blocks in it, view, 0)
+};
+
+__device__ __forceinline__ size_t hist_index(uint32_t d, uint32_t blk, uint32_t nblocks, const SegMap &sm)
 {
-    if (seg_blocks) {
-        const uint32_t seg = blk / seg_blocks, b = blk % seg_blocks;
-        return ((size_t)seg * 256 + d) * seg_blocks + b;
+    if (sm.tab) {
+        const int4 e = sm.tab[blk];
+        return (size_t)e.x * 256 + (size_t)d * (uint32_t)e.y + (blk - (uint32_t)e.x);
+    }
+    if (sm.seg_blocks) {
+        const uint32_t seg = blk / sm.seg_blocks, b = blk % sm.seg_blocks;
+        return ((size_t)seg * 256 + d) * sm.seg_blocks + b;
     }
     return (size_t)d * nblocks + blk;
 }
 
+// per-wave LDS histograms (less same-address contention), summed per digit
 __global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint32_t *__restrict__ keys, uint32_t n, int shift,
-                                                      uint32_t *__restrict__ hist, uint32_t nblocks,
-                                                      uint32_t seg_blocks)
+                                                      uint32_t *__restrict__ hist, uint32_t nblocks, SegMap sm)
 {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    __shared__ uint32_t h[4][256];
+    const int t = threadIdx.x, w = t >> 6;
+    h[0][t] = 0;
+    h[1][t] = 0;
+    h[2][t] = 0;
+    h[3][t] = 0;
     __syncthreads();
     const size_t base = (size_t)blockIdx.x * SORT_TILE;
+#pragma unroll 4
     for (int i = 0; i < SORT_ITEMS; i++) {
-        const size_t idx = base + (size_t)i * BLOCK + threadIdx.x;
-        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+        const size_t idx = base + (size_t)i * BLOCK + t;
+        if (idx < n) atomicAdd(&h[w][(keys[idx] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[hist_index(threadIdx.x, blockIdx.x, nblocks, seg_blocks)] = h[threadIdx.x];
+    hist[hist_index(t, blockIdx.x, nblocks, sm)] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
 }
 
+// Stable scatter.  Keys are ranked in 16 rounds of 256 (wave match by 8
+// ballots, prefix over waves, running count per digit) into an LDS copy of the
+// block sorted by digit; the block is then written out digit run by digit run,
+// so consecutive threads store to consecutive addresses.
 __global__ __launch_bounds__(BLOCK) void k_radix_scatter(const uint32_t *__restrict__ kin,
                                                          const uint32_t *__restrict__ vin,
                                                          uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                          uint32_t n, int shift, const uint32_t *__restrict__ offs,
-                                                         uint32_t nblocks, uint32_t seg_blocks)
+                                                         uint32_t nblocks, SegMap sm)
 {
+    __shared__ uint32_t s_key[SORT_TILE];
+    __shared__ uint32_t s_val[SORT_TILE];
+    __shared__ uint32_t s_loc[256];     // block-local start of each digit
+    __shared__ uint32_t s_glob[256];    // global start of each digit for this block
     __shared__ uint32_t run[256];
     __shared__ uint32_t wc[4][256];
+    __shared__ uint32_t s_w[4];
     const int t = threadIdx.x, w = t >> 6;
-    run[t] = offs[hist_index(t, blockIdx.x, nblocks, seg_blocks)];
+    const size_t base = (size_t)blockIdx.x * SORT_TILE;
+    const uint32_t cnt = (uint32_t)min((size_t)SORT_TILE, (size_t)n - base);
+    // block histogram and its exclusive scan
+    wc[0][t] = 0;
+    __syncthreads();
+    for (uint32_t i = t; i < cnt; i += BLOCK) atomicAdd(&wc[0][(kin[base + i] >> shift) & 255u], 1u);
+    __syncthreads();
+    uint32_t tot;
+    const uint32_t myc = wc[0][t];
+    const uint32_t loc = block_exclusive_scan(myc, tot, s_w);
+    s_loc[t] = loc;
+    s_glob[t] = offs[hist_index(t, blockIdx.x, nblocks, sm)];
+    run[t] = loc;
     wc[0][t] = 0;
     wc[1][t] = 0;
     wc[2][t] = 0;
     wc[3][t] = 0;
     __syncthreads();
-    const size_t base = (size_t)blockIdx.x * SORT_TILE;
     for (int r = 0; r < SORT_ITEMS; r++) {
-        if (base + (size_t)r * BLOCK >= n) break;   // uniform across the block
-        const size_t idx = base + (size_t)r * BLOCK + t;
-        const bool valid = idx < n;
-        const uint32_t key = valid ? kin[idx] : 0u;
-        const uint32_t val = valid ? vin[idx] : 0u;
+        if ((uint32_t)r * BLOCK >= cnt) break;   // uniform across the block
+        const uint32_t li = (uint32_t)r * BLOCK + t;
+        const bool valid = li < cnt;
+        const uint32_t key = valid ? kin[base + li] : 0u;
+        const uint32_t val = valid ? vin[base + li] : 0u;
         const uint32_t d = (key >> shift) & 255u;
         uint64_t m = __ballot(valid);
 #pragma unroll
@@ -365,9 +399,9 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(const uint32_t *__restr
         if (valid) {
             uint32_t pos = run[d] + (uint32_t)rank;
             for (int ww = 0; ww < w; ww++) pos += wc[ww][d];
-            if (pos < n) {
-                kout[pos] = key;
-                vout[pos] = val;
+            if (pos < SORT_TILE) {
+                s_key[pos] = key;
+                s_val[pos] = val;
             }
         }
         __syncthreads();
@@ -377,6 +411,16 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(const uint32_t *__restr
         wc[2][t] = 0;
         wc[3][t] = 0;
         __syncthreads();
+    }
+    // write out: LDS slot i holds digit d = key's digit; destination = global start + (i - local start)
+    for (uint32_t i = t; i < cnt; i += BLOCK) {
+        const uint32_t key = s_key[i];
+        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t pos = s_glob[d] + (i - s_loc[d]);
+        if (pos < n) {
+            kout[pos] = key;
+            vout[pos] = s_val[i];
+        }
     }
 }
 
@@ -401,46 +445,87 @@ __global__ __launch_bounds__(BLOCK) void k_gather(const float4 *__restrict__ rec
     }
 }
 
-// one pair per covered tile, in depth order within the view
+// One pair (local tile id, sorted position) per covered tile, in depth order
+// within the view, into the view's segment of the pair arrays (segments start
+// at multiples of 4096 so the pair sort can treat each view on its own).  A
+// workgroup takes 256 consecutive sorted positions (always inside one view),
+// flattens their pairs with a block scan and writes them with consecutive
+// threads on consecutive slots; each thread finds its record by binary search.
 __global__ __launch_bounds__(BLOCK) void k_emit(const float4 *__restrict__ ext, const uint32_t *__restrict__ order,
                                                 const unsigned long long *__restrict__ counters,
-                                                const uint32_t *__restrict__ poff, int64_t Kp, int64_t total,
-                                                DevGrid g, uint32_t D, uint32_t *__restrict__ pkey,
+                                                const uint32_t *__restrict__ poff, const uint32_t *__restrict__ ntl_s,
+                                                const uint32_t *__restrict__ pbase, int64_t Kp, DevGrid g,
+                                                uint32_t Dpad, uint32_t *__restrict__ pkey,
                                                 uint32_t *__restrict__ pval)
 {
-    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (p >= total) return;
-    const int64_t v = p / Kp, s = p - v * Kp;
-    if (s >= (int64_t)counters[2 * (size_t)v]) return;
-    const float4 e = ext[(size_t)v * Kp + min((int64_t)order[p], Kp - 1)];
-    int ty0, ty1, a0, a1, b0, b1;
-    if (!tile_rows(e.y, e.w, g.H, ty0, ty1)) return;
-    if (!tile_cols(e.x, e.z, g.W, g.tiles_x, a0, a1, b0, b1)) return;
-    uint32_t o = poff[p];
-    const uint32_t seg0 = (uint32_t)v * (uint32_t)g.tiles;
-    for (int ty = ty0; ty <= ty1; ty++) {
-        for (int tx = a0; tx <= a1; tx++, o++) {
-            if (o >= D) return;
-            pkey[o] = seg0 + (uint32_t)(ty * g.tiles_x + tx);
-            pval[o] = (uint32_t)p;
+    __shared__ uint32_t s_pre[BLOCK];
+    __shared__ int4 s_tp[BLOCK];     // ty0, a0, columns in range a, b0
+    __shared__ int s_ncol[BLOCK];
+    __shared__ uint32_t s_w[4];
+    const int t = threadIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.x * BLOCK;
+    const int64_t v = p0 / Kp, s0 = p0 - v * Kp;
+    const int64_t nv = (int64_t)counters[2 * (size_t)v];
+    if (s0 >= nv) return;   // uniform across the block
+    const int64_t p = p0 + t;
+    uint32_t nt = 0;
+    int4 tp = make_int4(0, 0, 0, 0);
+    int ncol = 1;
+    if (s0 + t < nv) {
+        nt = ntl_s[p];
+        if (nt) {
+            const float4 e = ext[(size_t)v * Kp + min((int64_t)order[p], Kp - 1)];
+            int ty0, ty1, a0, a1, b0, b1;
+            tile_rows(e.y, e.w, g.H, ty0, ty1);
+            ncol = tile_cols(e.x, e.z, g.W, g.tiles_x, a0, a1, b0, b1);
+            tp = make_int4(ty0, a0, a1 - a0 + 1, b0);
+            if (ncol < 1) {
+                ncol = 1;
+                nt = 0;
+            }
         }
-        for (int tx = b0; tx <= b1; tx++, o++) {
-            if (o >= D) return;
-            pkey[o] = seg0 + (uint32_t)(ty * g.tiles_x + tx);
-            pval[o] = (uint32_t)p;
+    }
+    uint32_t tot;
+    const uint32_t pre = block_exclusive_scan(nt, tot, s_w);
+    s_pre[t] = pre;
+    s_tp[t] = tp;
+    s_ncol[t] = ncol;
+    __syncthreads();
+    const uint32_t out0 = pbase[v] + (poff[p0] - poff[(size_t)v * Kp]);
+    for (uint32_t i = t; i < tot; i += BLOCK) {
+        int lo = 0, hi = BLOCK - 1;   // last record with s_pre <= i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_pre[mid] <= i) lo = mid;
+            else hi = mid - 1;
+        }
+        const int4 q = s_tp[lo];
+        const int nc = s_ncol[lo];
+        const int j = (int)(i - s_pre[lo]);
+        const int ty = q.x + j / nc, c = j % nc;
+        const int tx = c < q.z ? q.y + c : q.w + (c - q.z);
+        const uint32_t o = out0 + i;
+        if (o < Dpad) {
+            pkey[o] = (uint32_t)(ty * g.tiles_x + tx);
+            pval[o] = (uint32_t)(p0 + lo);
         }
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_ranges(const uint32_t *__restrict__ skey, uint32_t D, uint32_t nseg,
+// [start, end) of each (view, tile) list in the padded pair array
+__global__ __launch_bounds__(BLOCK) void k_ranges(const uint32_t *__restrict__ skey, uint32_t Dpad,
+                                                  const int4 *__restrict__ segtab, int tiles,
                                                   uint2 *__restrict__ ranges)
 {
     const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
-    if (i >= D) return;
-    const uint32_t s = skey[i];
-    if (s >= nseg) return;
-    if (i == 0 || skey[i - 1] != s) ranges[s].x = i;
-    if (i == D - 1 || skey[i + 1] != s) ranges[s].y = i + 1;
+    if (i >= Dpad) return;
+    const uint32_t key = skey[i];
+    if (key >= (uint32_t)tiles) return;   // padding
+    const int4 e = segtab[i / SORT_TILE];
+    const uint32_t first = (uint32_t)e.x * SORT_TILE, end = first + (uint32_t)e.y * SORT_TILE;
+    const size_t seg = (size_t)e.z * tiles + key;
+    if (i == first || skey[i - 1] != key) ranges[seg].x = i;
+    if (i + 1 == end || skey[i + 1] != key) ranges[seg].y = i + 1;
 }
 
 // ----------------------------------------------------------------------------
@@ -815,12 +900,14 @@ hipError_t scan_exclusive_u32(DevBuf &scan_tmp, const uint32_t *in, uint32_t *ou
 // Sort n (key, value) pairs by the low `bits` bits of the key, stably.
 // seg_len > 0: independent segments of seg_len (a multiple of SORT_TILE).
 hipError_t sort_pairs_u32(Workspace &ws, DevBuf *keys, DevBuf *vals, DevBuf &histb, DevBuf &scan_tmp, int &cur,
-                          uint32_t n, int bits, int64_t seg_len, hipStream_t st)
+                          uint32_t n, int bits, int64_t seg_len, const int4 *segtab, hipStream_t st)
 {
     (void)ws;
     if (n == 0 || bits <= 0) return hipSuccess;
     const uint32_t nblocks = (n + SORT_TILE - 1) / SORT_TILE;
-    const uint32_t seg_blocks = seg_len > 0 ? (uint32_t)(seg_len / SORT_TILE) : 0u;
+    SegMap sm;
+    sm.seg_blocks = seg_len > 0 ? (uint32_t)(seg_len / SORT_TILE) : 0u;
+    sm.tab = segtab;
     const size_t nh = (size_t)nblocks * 256;
     if (histb.cap < nh * 4) return hipErrorOutOfMemory;
     uint32_t *hist = histb.as<uint32_t>();
@@ -829,12 +916,11 @@ hipError_t sort_pairs_u32(Workspace &ws, DevBuf *keys, DevBuf *vals, DevBuf &his
         const uint32_t *vin = vals[cur].as<uint32_t>();
         uint32_t *kout = keys[cur ^ 1].as<uint32_t>();
         uint32_t *vout = vals[cur ^ 1].as<uint32_t>();
-        hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(BLOCK), 0, st, kin, n, shift, hist, nblocks,
-                           seg_blocks);
+        hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(BLOCK), 0, st, kin, n, shift, hist, nblocks, sm);
         hipError_t e = scan_exclusive_u32(scan_tmp, hist, hist, (uint32_t)nh, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(BLOCK), 0, st, kin, vin, kout, vout, n, shift, hist,
-                           nblocks, seg_blocks);
+                           nblocks, sm);
         cur ^= 1;
     }
     return hipGetLastError();
@@ -852,10 +938,12 @@ hipError_t launch_gather(Workspace &ws, int V, int64_t Kp, hipStream_t st)
 hipError_t launch_emit(Workspace &ws, int V, int64_t Kp, const DevGrid &g, hipStream_t st)
 {
     const int64_t total = (int64_t)V * Kp;
-    hipLaunchKernelGGL(k_emit, dim3(nblk(total)), dim3(BLOCK), 0, st, ws.ext.as<float4>(),
+    hipError_t e = launch_fill_u32(ws.pkey[0].as<uint32_t>(), 0xFFFFFFFFu, (size_t)ws.Dpad, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)(total / BLOCK)), dim3(BLOCK), 0, st, ws.ext.as<float4>(),
                        ws.sval[ws.sorted_buf].as<uint32_t>(), ws.counters.as<unsigned long long>(),
-                       ws.poff.as<uint32_t>(), Kp, total, g, (uint32_t)ws.D, ws.pkey[0].as<uint32_t>(),
-                       ws.pval[0].as<uint32_t>());
+                       ws.poff.as<uint32_t>(), ws.ntl_s.as<uint32_t>(), ws.pbase.as<uint32_t>(), Kp, g,
+                       (uint32_t)ws.Dpad, ws.pkey[0].as<uint32_t>(), ws.pval[0].as<uint32_t>());
     return hipGetLastError();
 }
 
@@ -863,9 +951,10 @@ hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st)
 {
     const size_t nr = (size_t)ws.V * g.tiles;
     hipError_t e = launch_fill_u32(ws.ranges.as<uint32_t>(), 0u, nr * 2, st);
-    if (e != hipSuccess || ws.D == 0) return e;
-    hipLaunchKernelGGL(k_ranges, dim3(nblk((size_t)ws.D)), dim3(BLOCK), 0, st, ws.pkey[ws.pairs_buf].as<uint32_t>(),
-                       (uint32_t)ws.D, (uint32_t)nr, ws.ranges.as<uint2>());
+    if (e != hipSuccess || ws.Dpad == 0) return e;
+    hipLaunchKernelGGL(k_ranges, dim3(nblk((size_t)ws.Dpad)), dim3(BLOCK), 0, st,
+                       ws.pkey[ws.pairs_buf].as<uint32_t>(), (uint32_t)ws.Dpad, ws.segtab.as<int4>(), g.tiles,
+                       ws.ranges.as<uint2>());
     return hipGetLastError();
 }
 

@@ -111,7 +111,7 @@ void free_workspace(Workspace &ws)
                       &ws.poff,    &ws.pkey[0], &ws.pkey[1], &ws.pval[0], &ws.pval[1], &ws.ranges, &ws.rad,
                       &ws.Lp,      &ws.Gp,      &ws.Tfin,   &ws.nlast,  &ws.part,    &ws.chunks, &ws.items,
                       &ws.counters, &ws.hist,   &ws.scan_tmp, &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
-                      &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.hist_b,  &ws.scan_b};
+                      &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.hist_b,  &ws.scan_b, &ws.pbase,  &ws.segtab};
     for (DevBuf *b : bufs) release(*b);
     if (ws.staged) (void)hipEventDestroy(ws.staged);
     if (ws.counted) (void)hipEventDestroy(ws.counted);
@@ -538,16 +538,30 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     HIPCHK(ctx, hipMemcpyAsync(h_cnt, ws.counters.p, (size_t)2 * V * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(ctx, hipEventRecord(ws.counted, st));
     int cur = 0;
-    STAGE(ctx, "sort_depth", sort_pairs_u32(ws, ws.skey, ws.sval, ws.hist, ws.scan_tmp, cur, (uint32_t)VK, 32, Kp, st));
+    STAGE(ctx, "sort_depth", sort_pairs_u32(ws, ws.skey, ws.sval, ws.hist, ws.scan_tmp, cur, (uint32_t)VK, 32, Kp, nullptr, st));
     ws.sorted_buf = cur;
     STAGE(ctx, "gather", launch_gather(ws, V, Kp, st));
     STAGE(ctx, "scan", scan_exclusive_u32(ws.scan_tmp, ws.ntl_s.as<uint32_t>(), ws.poff.as<uint32_t>(), (uint32_t)VK, st));
     HIPCHK(ctx, hipEventSynchronize(ws.counted));
 
-    uint64_t D = 0;
-    for (int v = 0; v < V; v++) D += h_cnt[2 * v + 1];
-    if (D >= (1ull << 32) - 1) return fail(ctx, RXGS_E_INVALID, "more than 2^32 pairs; split the receivers");
+    // pairs per view; each view's pairs get a segment padded to whole sort blocks
+    uint64_t D = 0, Dpad = 0;
+    ws.h_pbase.assign(V, 0);
+    ws.h_pcount.assign(V, 0);
+    std::vector<int4> segtab;
+    for (int v = 0; v < V; v++) {
+        const uint64_t dv = h_cnt[2 * v + 1];
+        ws.h_pbase[v] = (uint32_t)Dpad;
+        ws.h_pcount[v] = (uint32_t)dv;
+        const uint64_t nb = (dv + SORT_TILE - 1) / SORT_TILE;
+        for (uint64_t b = 0; b < nb; b++)
+            segtab.push_back(make_int4((int)(Dpad / SORT_TILE), (int)nb, v, 0));
+        D += dv;
+        Dpad += nb * SORT_TILE;
+        if (Dpad >= (1ull << 32) - SORT_TILE) return fail(ctx, RXGS_E_INVALID, "more than 2^32 pairs; split the receivers");
+    }
     ws.D = (int64_t)D;
+    ws.Dpad = (int64_t)Dpad;
     ws.h_nvis.assign(V, 0);
     ws.nvis_total = 0;
     for (int v = 0; v < V; v++) {
@@ -582,12 +596,14 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     ws.n_tslots = (mode == RXGS_MODE_TX) ? V : N;
 
     const size_t P = (size_t)g.H * g.W;
-    GROW(ctx, ws.pkey[0], std::max<uint64_t>(D, 1) * 4);
-    GROW(ctx, ws.pkey[1], std::max<uint64_t>(D, 1) * 4);
-    GROW(ctx, ws.pval[0], std::max<uint64_t>(D, 1) * 4);
-    GROW(ctx, ws.pval[1], std::max<uint64_t>(D, 1) * 4);
-    GROW(ctx, ws.hist_b, ((D + SORT_TILE - 1) / SORT_TILE) * 256 * 4);
-    GROW(ctx, ws.scan_b, (((D + SORT_TILE - 1) / SORT_TILE) * 256 / SORT_TILE + 2) * 4);
+    GROW(ctx, ws.pkey[0], std::max<uint64_t>(Dpad, 1) * 4);
+    GROW(ctx, ws.pkey[1], std::max<uint64_t>(Dpad, 1) * 4);
+    GROW(ctx, ws.pval[0], std::max<uint64_t>(Dpad, 1) * 4);
+    GROW(ctx, ws.pval[1], std::max<uint64_t>(Dpad, 1) * 4);
+    GROW(ctx, ws.hist_b, (Dpad / SORT_TILE) * 256 * 4);
+    GROW(ctx, ws.scan_b, ((Dpad / SORT_TILE) * 256 / SORT_TILE + 2) * 4);
+    GROW(ctx, ws.pbase, (size_t)V * 4);
+    GROW(ctx, ws.segtab, std::max<size_t>(segtab.size(), 1) * 16);
     GROW(ctx, ws.ranges, (size_t)V * g.tiles * 8);
     GROW(ctx, ws.rad, (size_t)N * Kp * 8);
     GROW(ctx, ws.Tfin, (size_t)ws.n_tslots * P * 4);
@@ -600,8 +616,9 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         GROW(ctx, ws.Gp, (size_t)N * HID * 4);
     }
 
-    // one host-to-device copy of the small descriptors
-    const size_t stage_bytes = (size_t)N * 4 + chunks.size() * 16 + items.size() * 16;
+    // host-to-device copies of the small descriptors
+    const size_t stage_bytes =
+        (size_t)N * 4 + chunks.size() * 16 + items.size() * 16 + (size_t)V * 4 + segtab.size() * 16;
     const size_t cnt_bytes = (size_t)2 * V * 8;
     const size_t off0 = (cnt_bytes + 63) / 64 * 64;
     if (!ensure_pinned(ws, off0 + stage_bytes + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
@@ -609,20 +626,27 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     std::memcpy(hp, rxview.data(), (size_t)N * 4);
     std::memcpy(hp + (size_t)N * 4, chunks.data(), chunks.size() * 16);
     std::memcpy(hp + (size_t)N * 4 + chunks.size() * 16, items.data(), items.size() * 16);
+    char *hp2 = hp + (size_t)N * 4 + chunks.size() * 16 + items.size() * 16;
+    std::memcpy(hp2, ws.h_pbase.data(), (size_t)V * 4);
+    std::memcpy(hp2 + (size_t)V * 4, segtab.data(), segtab.size() * 16);
     HIPCHK(ctx, hipMemcpyAsync(ws.rxview.p, hp, (size_t)N * 4, hipMemcpyHostToDevice, st));
     if (!chunks.empty())
         HIPCHK(ctx, hipMemcpyAsync(ws.chunks.p, hp + (size_t)N * 4, chunks.size() * 16, hipMemcpyHostToDevice, st));
     if (!items.empty())
         HIPCHK(ctx, hipMemcpyAsync(ws.items.p, hp + (size_t)N * 4 + chunks.size() * 16, items.size() * 16,
                                    hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(ws.pbase.p, hp2, (size_t)V * 4, hipMemcpyHostToDevice, st));
+    if (!segtab.empty())
+        HIPCHK(ctx, hipMemcpyAsync(ws.segtab.p, hp2 + (size_t)V * 4, segtab.size() * 16, hipMemcpyHostToDevice, st));
     HIPCHK(ctx, hipEventRecord(ws.staged, st));
 
     // pairs: emit in depth order, stable sort by (view, tile), tile ranges
     int pcur = 0;
     if (D > 0) {
         STAGE(ctx, "emit", launch_emit(ws, V, Kp, g, st));
-        const int sbits = bits_for((uint64_t)V * g.tiles);
-        STAGE(ctx, "sort_pairs", sort_pairs_u32(ws, ws.pkey, ws.pval, ws.hist_b, ws.scan_b, pcur, (uint32_t)D, sbits, 0, st));
+        const int sbits = std::max(bits_for((uint64_t)g.tiles), 1);
+        STAGE(ctx, "sort_pairs", sort_pairs_u32(ws, ws.pkey, ws.pval, ws.hist_b, ws.scan_b, pcur, (uint32_t)Dpad, sbits,
+                                                0, ws.segtab.as<int4>(), st));
     }
     ws.pairs_buf = pcur;
     STAGE(ctx, "ranges", launch_ranges(ws, g, st));
@@ -736,8 +760,8 @@ extern "C" rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *ds
         src = tmp.data();
         n = tmp.size() * 4;
         break;
-    case RXGS_EXPORT_PAIRS: src = ws.pval[ws.pairs_buf].p; n = (size_t)ws.D * 4; break;
-    case RXGS_EXPORT_RANGES: src = ws.ranges.p; n = (size_t)ws.V * ws.g.tiles * 8; break;
+    case RXGS_EXPORT_PAIRS: n = (size_t)ws.D * 4; break;
+    case RXGS_EXPORT_RANGES: n = (size_t)ws.V * ws.g.tiles * 8; break;
     case RXGS_EXPORT_RADIANCE: src = ws.rad.p; n = (size_t)ws.N * ws.Kp * 8; break;
     case RXGS_EXPORT_TFINAL: src = ws.Tfin.p; n = (size_t)ws.n_tslots * P * 4; break;
     case RXGS_EXPORT_NLAST: src = ws.nlast.p; n = (size_t)ws.n_tslots * P * 4; break;
@@ -747,6 +771,41 @@ extern "C" rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *ds
     if (n == 0) return RXGS_OK;
     DeviceScope ds(ctx->device);
     HIPCHK(ctx, hipDeviceSynchronize());
+    if (what == RXGS_EXPORT_PAIRS || what == RXGS_EXPORT_RANGES) {
+        // pairs without the per-view padding, ranges in those compact indices
+        std::vector<uint32_t> hk((size_t)ws.Dpad), hv((size_t)ws.Dpad);
+        std::vector<uint32_t> out;
+        if (ws.Dpad) {
+            HIPCHK(ctx, hipMemcpy(hk.data(), ws.pkey[ws.pairs_buf].p, hk.size() * 4, hipMemcpyDeviceToHost));
+            HIPCHK(ctx, hipMemcpy(hv.data(), ws.pval[ws.pairs_buf].p, hv.size() * 4, hipMemcpyDeviceToHost));
+        }
+        if (what == RXGS_EXPORT_PAIRS) {
+            out.reserve((size_t)ws.D);
+            for (size_t i = 0; i < hk.size(); i++)
+                if (hk[i] != 0xFFFFFFFFu) out.push_back(hv[i]);
+        } else {
+            std::vector<uint32_t> rg((size_t)ws.V * ws.g.tiles * 2);
+            HIPCHK(ctx, hipMemcpy(rg.data(), ws.ranges.p, rg.size() * 4, hipMemcpyDeviceToHost));
+            uint32_t cbase = 0;
+            for (int v = 0; v < ws.V; v++) {
+                for (int t = 0; t < ws.g.tiles; t++) {
+                    uint32_t *r = &rg[((size_t)v * ws.g.tiles + t) * 2];
+                    if (r[1] > r[0]) {
+                        r[0] = r[0] - ws.h_pbase[v] + cbase;
+                        r[1] = r[1] - ws.h_pbase[v] + cbase;
+                    }
+                }
+                cbase += ws.h_pcount[v];
+            }
+            out.swap(rg);
+        }
+        if (out.size() * 4 != n) return fail(ctx, RXGS_E_STATE, "pair export size mismatch");
+        if (dst_on_device)
+            HIPCHK(ctx, hipMemcpy(dst, out.data(), n, hipMemcpyHostToDevice));
+        else
+            std::memcpy(dst, out.data(), n);
+        return RXGS_OK;
+    }
     if (what == RXGS_EXPORT_NVIS) {
         if (dst_on_device)
             HIPCHK(ctx, hipMemcpy(dst, src, n, hipMemcpyHostToDevice));

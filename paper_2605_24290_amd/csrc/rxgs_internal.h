@@ -68,7 +68,7 @@ struct Mlp {
 struct Workspace {
     // sizes of the last render
     int mode = 0, V = 0, N = 0, Q = 0, R = 1;
-    int64_t K = 0, Kp = 0, D = 0, nvis_total = 0;
+    int64_t K = 0, Kp = 0, D = 0, Dpad = 0, nvis_total = 0;
     uint64_t scene_version = 0, mlp_version = 0;
     bool valid = false;
     bool use_mlp = false;
@@ -91,7 +91,11 @@ struct Workspace {
     DevBuf srec;      // V x Kp x 2 float4 (sorted order)
     DevBuf ntl_s;     // V x Kp u32 (sorted order)
     DevBuf poff;      // V x Kp u32 emission offsets
-    DevBuf pkey[2];   // D u32
+    DevBuf pbase;     // V u32: start of each view's segment of the pair arrays
+    DevBuf segtab;    // per pair-sort block int4: (first block, blocks, view, 0) of its segment
+    std::vector<uint32_t> h_pbase;    // V
+    std::vector<uint32_t> h_pcount;   // V: pairs of each view
+    DevBuf pkey[2];   // Dpad u32: local tile id, 0xFFFFFFFF for padding
     DevBuf pval[2];   // D u32
     int pairs_buf = 0;
     DevBuf ranges;    // V x tiles uint2
@@ -179,7 +183,7 @@ hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t 
                           Workspace &ws, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st);
 hipError_t sort_pairs_u32(Workspace &ws, DevBuf *keys, DevBuf *vals, DevBuf &hist, DevBuf &scan_tmp, int &cur,
-                          uint32_t n, int bits, int64_t seg_len, hipStream_t st);
+                          uint32_t n, int bits, int64_t seg_len, const int4 *segtab, hipStream_t st);
 hipError_t scan_exclusive_u32(DevBuf &scan_tmp, const uint32_t *in, uint32_t *out, uint32_t n, hipStream_t st);
 hipError_t launch_gather(Workspace &ws, int V, int64_t Kp, hipStream_t st);
 hipError_t launch_emit(Workspace &ws, int V, int64_t Kp, const DevGrid &g, hipStream_t st);
