@@ -630,7 +630,7 @@ static void blend_bwd_launch(Workspace &ws, const float *C, const float *dC, con
     dim3 grid((unsigned)ws.g.tiles, (unsigned)ws.n_chunks);
     hipLaunchKernelGGL(k_blend_bwd<R>, grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                        ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
-                       ws.chunks.as<int4>(), ws.Kp, ws.g, ws.mode == RXGS_MODE_TX ? 1 : 0, C, dC, dP,
+                       ws.d_chunks, ws.Kp, ws.g, ws.mode == RXGS_MODE_TX ? 1 : 0, C, dC, dP,
                        ws.Tfin.as<float>(), ws.nlast.as<int>(), ws.dS.as<float>(), ws.g2d.as<float>());
 }
 
@@ -653,7 +653,7 @@ hipError_t launch_rad_bwd(const Scene &sc, Workspace &ws, float *grad, hipStream
     if (n == 0 || !grad || sc.K == 0) return hipSuccess;
     hipLaunchKernelGGL(k_rad_direct_bwd, dim3(nblk(n)), dim3(BLOCK), 0, st, ws.dS.as<float2>(),
                        ws.sval[ws.sorted_buf].as<uint32_t>(), ws.counters.as<unsigned long long>(),
-                       ws.rxview.as<int>(), ws.N, ws.Kp, sc.K, grad);
+                       ws.d_rxview, ws.N, ws.Kp, sc.K, grad);
     return hipGetLastError();
 }
 
@@ -672,7 +672,7 @@ hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *g
     if (ws.n_items > 0)
         hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)(nwaves / 4)), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                            ws.Gp.as<float>(), m.w2a.as<float>(), m.w2b.as<float>(), m.tab.as<float4>(), W3,
-                           ws.sval[ws.sorted_buf].as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, sc.K,
+                           ws.sval[ws.sorted_buf].as<uint32_t>(), ws.d_items, ws.n_items, ws.Kp, sc.K,
                            ws.counters.as<unsigned long long>(), ws.dS.as<float2>(), ws.dL.as<float>(),
                            ws.dG.as<float>(), ws.mpart.as<float>());
     if (gmlp) {
@@ -684,7 +684,7 @@ hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *g
             if (e != hipSuccess) return e;
         }
         hipLaunchKernelGGL(k_mlp_w1a, dim3(nblk(HID * (ENC + 1))), dim3(BLOCK), 0, st, ws.dG.as<float>(),
-                           ws.rxpos.as<float>(), ws.N, gmlp);
+                           ws.rxpos_p, ws.N, gmlp);
         const int nchunks = (int)((sc.K + W1B_CHUNK - 1) / W1B_CHUNK);
         if (nchunks > 0) {
             hipLaunchKernelGGL(k_mlp_w1b_part, dim3((unsigned)nchunks), dim3(BLOCK), 0, st, ws.dL.as<float>(),
@@ -709,7 +709,7 @@ hipError_t launch_project_bwd(const Scene &sc, Workspace &ws, const rxgs_grads &
     const int64_t n = (int64_t)ws.V * ws.Kp;
     if (sc.K == 0) return hipSuccess;
     hipLaunchKernelGGL(k_project_bwd, dim3(nblk(n)), dim3(BLOCK), 0, st, sc.soa.as<float>(), sc.K, ws.Kp,
-                       ws.centres.as<float>(), ws.V, ws.g, ws.sval[ws.sorted_buf].as<uint32_t>(),
+                       ws.centres_p, ws.V, ws.g, ws.sval[ws.sorted_buf].as<uint32_t>(),
                        ws.counters.as<unsigned long long>(), ws.g2d.as<float>(), gr.means, gr.log_scales, gr.quats,
                        gr.logits);
     return hipGetLastError();

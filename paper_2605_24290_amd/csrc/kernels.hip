@@ -254,8 +254,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t *__restric
     if (threadIdx.x == 0) bsum[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
 }
 
-// single workgroup: exclusive scan of nb block sums in place
-__global__ __launch_bounds__(BLOCK) void k_scan_top(uint32_t *__restrict__ bsum, uint32_t nb)
+// single workgroup: exclusive scan of nb values (in may equal out)
+__global__ __launch_bounds__(BLOCK) void k_scan_top(const uint32_t *in, uint32_t *out, uint32_t nb)
 {
     __shared__ uint32_t s_w[4];
     uint32_t carry = 0;
@@ -264,13 +264,13 @@ __global__ __launch_bounds__(BLOCK) void k_scan_top(uint32_t *__restrict__ bsum,
         uint32_t loc[SORT_ITEMS];
         uint32_t s = 0;
         for (int i = 0; i < SORT_ITEMS; i++) {
-            loc[i] = (base + i < nb) ? bsum[base + i] : 0u;
+            loc[i] = (base + i < nb) ? in[base + i] : 0u;
             s += loc[i];
         }
         uint32_t tot;
         uint32_t pre = block_exclusive_scan(s, tot, s_w) + carry;
         for (int i = 0; i < SORT_ITEMS; i++) {
-            if (base + i < nb) bsum[base + i] = pre;
+            if (base + i < nb) out[base + i] = pre;
             pre += loc[i];
         }
         carry += tot;
@@ -299,21 +299,23 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t *__restrict_
 }
 
 // ----------------------------------------------------------------------------
-// Stable LSD radix sort, 8-bit digits, 4096 keys per block.  A pass is a
-// per-block digit histogram, an exclusive scan over (segment, digit, block),
-// and a stable scatter.  Segments are runs of whole blocks sorted
-// independently: either uniform (seg_blocks blocks each) or given per block by
-// a table (first block, block count) for segments of different lengths.
+// Stable LSD radix sort, 8-bit digits, 256 x ITEMS keys per block (1024 for
+// small sorts, 4096 for large ones).  A pass is a per-block digit histogram, an
+// exclusive scan over (segment, digit, block), and a stable scatter.  Segments
+// are runs of whole blocks sorted independently: uniform (seg_blocks blocks
+// each) or given per 4096-key unit by a table (first unit, unit count, view).
 struct SegMap {
-    uint32_t seg_blocks;          // uniform segment length in blocks (0: use tab or none)
-    const int4 *tab;              // per block: (first block of its segment, blocks in it, view, 0)
+    uint32_t seg_blocks;          // uniform segment length in blocks (0: table or none)
+    const int4 *tab;              // per 4096-key unit: (first unit of its segment, units in it, view, 0)
+    uint32_t scale;               // blocks per 4096-key unit (4096 / block size)
 };
 
 __device__ __forceinline__ size_t hist_index(uint32_t d, uint32_t blk, uint32_t nblocks, const SegMap &sm)
 {
     if (sm.tab) {
-        const int4 e = sm.tab[blk];
-        return (size_t)e.x * 256 + (size_t)d * (uint32_t)e.y + (blk - (uint32_t)e.x);
+        const int4 e = sm.tab[blk / sm.scale];
+        const uint32_t first = (uint32_t)e.x * sm.scale, nb = (uint32_t)e.y * sm.scale;
+        return (size_t)first * 256 + (size_t)d * nb + (blk - first);
     }
     if (sm.seg_blocks) {
         const uint32_t seg = blk / sm.seg_blocks, b = blk % sm.seg_blocks;
@@ -323,6 +325,7 @@ __device__ __forceinline__ size_t hist_index(uint32_t d, uint32_t blk, uint32_t 
 }
 
 // per-wave LDS histograms (less same-address contention), summed per digit
+template <int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint32_t *__restrict__ keys, uint32_t n, int shift,
                                                       uint32_t *__restrict__ hist, uint32_t nblocks, SegMap sm)
 {
@@ -333,9 +336,9 @@ __global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint32_t *__restrict
     h[2][t] = 0;
     h[3][t] = 0;
     __syncthreads();
-    const size_t base = (size_t)blockIdx.x * SORT_TILE;
+    const size_t base = (size_t)blockIdx.x * (BLOCK * ITEMS);
 #pragma unroll 4
-    for (int i = 0; i < SORT_ITEMS; i++) {
+    for (int i = 0; i < ITEMS; i++) {
         const size_t idx = base + (size_t)i * BLOCK + t;
         if (idx < n) atomicAdd(&h[w][(keys[idx] >> shift) & 255u], 1u);
     }
@@ -343,26 +346,28 @@ __global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint32_t *__restrict
     hist[hist_index(t, blockIdx.x, nblocks, sm)] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
 }
 
-// Stable scatter.  Keys are ranked in 16 rounds of 256 (wave match by 8
-// ballots, prefix over waves, running count per digit) into an LDS copy of the
-// block sorted by digit; the block is then written out digit run by digit run,
-// so consecutive threads store to consecutive addresses.
+// Stable scatter.  Keys are ranked in rounds of 256 (wave match by 8 ballots,
+// prefix over waves, running count per digit) into an LDS copy of the block
+// sorted by digit; the block is then written out digit run by digit run, so
+// consecutive threads store to consecutive addresses.
+template <int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_radix_scatter(const uint32_t *__restrict__ kin,
                                                          const uint32_t *__restrict__ vin,
                                                          uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                          uint32_t n, int shift, const uint32_t *__restrict__ offs,
                                                          uint32_t nblocks, SegMap sm)
 {
-    __shared__ uint32_t s_key[SORT_TILE];
-    __shared__ uint32_t s_val[SORT_TILE];
+    constexpr int TILEN = BLOCK * ITEMS;
+    __shared__ uint32_t s_key[TILEN];
+    __shared__ uint32_t s_val[TILEN];
     __shared__ uint32_t s_loc[256];     // block-local start of each digit
     __shared__ uint32_t s_glob[256];    // global start of each digit for this block
     __shared__ uint32_t run[256];
     __shared__ uint32_t wc[4][256];
     __shared__ uint32_t s_w[4];
     const int t = threadIdx.x, w = t >> 6;
-    const size_t base = (size_t)blockIdx.x * SORT_TILE;
-    const uint32_t cnt = (uint32_t)min((size_t)SORT_TILE, (size_t)n - base);
+    const size_t base = (size_t)blockIdx.x * TILEN;
+    const uint32_t cnt = (uint32_t)min((size_t)TILEN, (size_t)n - base);
     // block histogram and its exclusive scan
     wc[0][t] = 0;
     __syncthreads();
@@ -379,7 +384,7 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(const uint32_t *__restr
     wc[2][t] = 0;
     wc[3][t] = 0;
     __syncthreads();
-    for (int r = 0; r < SORT_ITEMS; r++) {
+    for (int r = 0; r < ITEMS; r++) {
         if ((uint32_t)r * BLOCK >= cnt) break;   // uniform across the block
         const uint32_t li = (uint32_t)r * BLOCK + t;
         const bool valid = li < cnt;
@@ -399,7 +404,7 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(const uint32_t *__restr
         if (valid) {
             uint32_t pos = run[d] + (uint32_t)rank;
             for (int ww = 0; ww < w; ww++) pos += wc[ww][d];
-            if (pos < SORT_TILE) {
+            if (pos < TILEN) {
                 s_key[pos] = key;
                 s_val[pos] = val;
             }
@@ -412,7 +417,7 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(const uint32_t *__restr
         wc[3][t] = 0;
         __syncthreads();
     }
-    // write out: LDS slot i holds digit d = key's digit; destination = global start + (i - local start)
+    // write out: LDS slot i holds digit d; destination = global start + (i - local start)
     for (uint32_t i = t; i < cnt; i += BLOCK) {
         const uint32_t key = s_key[i];
         const uint32_t d = (key >> shift) & 255u;
@@ -447,10 +452,14 @@ __global__ __launch_bounds__(BLOCK) void k_gather(const float4 *__restrict__ rec
 
 // One pair (local tile id, sorted position) per covered tile, in depth order
 // within the view, into the view's segment of the pair arrays (segments start
-// at multiples of 4096 so the pair sort can treat each view on its own).  A
+// at multiples of 4096 so the pair sort can treat each view on its own; the
+// block holding the view's last record also writes the segment's padding).  A
 // workgroup takes 256 consecutive sorted positions (always inside one view),
-// flattens their pairs with a block scan and writes them with consecutive
-// threads on consecutive slots; each thread finds its record by binary search.
+// flattens their pairs with a block scan, and for each window of 2048 output
+// slots marks in LDS which record owns each slot, so consecutive threads write
+// consecutive slots.
+constexpr int EMIT_WIN = 2048;
+
 __global__ __launch_bounds__(BLOCK) void k_emit(const float4 *__restrict__ ext, const uint32_t *__restrict__ order,
                                                 const unsigned long long *__restrict__ counters,
                                                 const uint32_t *__restrict__ poff, const uint32_t *__restrict__ ntl_s,
@@ -458,6 +467,7 @@ __global__ __launch_bounds__(BLOCK) void k_emit(const float4 *__restrict__ ext, 
                                                 uint32_t Dpad, uint32_t *__restrict__ pkey,
                                                 uint32_t *__restrict__ pval)
 {
+    __shared__ unsigned char s_own[EMIT_WIN];
     __shared__ uint32_t s_pre[BLOCK];
     __shared__ int4 s_tp[BLOCK];     // ty0, a0, columns in range a, b0
     __shared__ int s_ncol[BLOCK];
@@ -490,26 +500,56 @@ __global__ __launch_bounds__(BLOCK) void k_emit(const float4 *__restrict__ ext, 
     s_pre[t] = pre;
     s_tp[t] = tp;
     s_ncol[t] = ncol;
-    __syncthreads();
     const uint32_t out0 = pbase[v] + (poff[p0] - poff[(size_t)v * Kp]);
-    for (uint32_t i = t; i < tot; i += BLOCK) {
-        int lo = 0, hi = BLOCK - 1;   // last record with s_pre <= i
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_pre[mid] <= i) lo = mid;
-            else hi = mid - 1;
-        }
-        const int4 q = s_tp[lo];
-        const int nc = s_ncol[lo];
-        const int j = (int)(i - s_pre[lo]);
-        const int ty = q.x + j / nc, c = j % nc;
-        const int tx = c < q.z ? q.y + c : q.w + (c - q.z);
-        const uint32_t o = out0 + i;
-        if (o < Dpad) {
-            pkey[o] = (uint32_t)(ty * g.tiles_x + tx);
-            pval[o] = (uint32_t)(p0 + lo);
+    for (uint32_t c0 = 0; c0 < tot; c0 += EMIT_WIN) {
+        __syncthreads();
+        const uint32_t a = max(pre, c0), b = min(pre + nt, c0 + (uint32_t)EMIT_WIN);
+        for (uint32_t x = a; x < b; x++) s_own[x - c0] = (unsigned char)t;
+        __syncthreads();
+        const uint32_t cend = min(tot, c0 + (uint32_t)EMIT_WIN);
+        for (uint32_t i = c0 + t; i < cend; i += BLOCK) {
+            const int r = s_own[i - c0];
+            const int4 q = s_tp[r];
+            const int nc = s_ncol[r];
+            const int j = (int)(i - s_pre[r]);
+            const int ty = q.x + j / nc, c = j % nc;
+            const int tx = c < q.z ? q.y + c : q.w + (c - q.z);
+            const uint32_t o = out0 + i;
+            if (o < Dpad) {
+                pkey[o] = (uint32_t)(ty * g.tiles_x + tx);
+                pval[o] = (uint32_t)(p0 + r);
+            }
         }
     }
+    if (s0 + BLOCK >= nv) {
+        // this block holds the view's last record: pad the segment to a whole unit
+        const uint32_t dend = out0 + tot;
+        const uint32_t pend = (uint32_t)(((uint64_t)dend + SORT_TILE - 1) / SORT_TILE * SORT_TILE);
+        for (uint32_t o = dend + t; o < pend && o < Dpad; o += BLOCK) pkey[o] = 0xFFFFFFFFu;
+    }
+}
+
+// [start, end) of each (view, tile) list, read from the pair sort's scanned
+// histogram (one 8-bit pass with the tile id as the digit): the start of digit
+// d in the first block of the view's segment, and the start of digit d + 1.
+__global__ __launch_bounds__(BLOCK) void k_ranges_hist(const uint32_t *__restrict__ hist,
+                                                       const uint32_t *__restrict__ pbase,
+                                                       const uint32_t *__restrict__ pcount, int V, int tiles,
+                                                       int blk, uint2 *__restrict__ ranges)
+{
+    const int idx = blockIdx.x * BLOCK + threadIdx.x;
+    if (idx >= V * tiles) return;
+    const int v = idx / tiles, tile = idx % tiles;
+    const uint32_t cnt = pcount[v];
+    uint2 r = make_uint2(0u, 0u);
+    if (cnt) {
+        const uint32_t first = pbase[v] / (uint32_t)blk;              // first sort block of the segment
+        const uint32_t nb = (cnt + SORT_TILE - 1) / SORT_TILE * (SORT_TILE / (uint32_t)blk);
+        const uint32_t s = hist[(size_t)first * 256 + (size_t)tile * nb];
+        const uint32_t e = hist[(size_t)first * 256 + (size_t)(tile + 1) * nb];
+        if (e > s) r = make_uint2(s, e);
+    }
+    ranges[idx] = r;
 }
 
 // [start, end) of each (view, tile) list in the padded pair array
@@ -883,31 +923,46 @@ hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t 
     return hipGetLastError();
 }
 
-// The buffers are sized by the caller before any work that may still be in
-// flight uses them (grow() frees the old buffer).
+// Scratch buffers are sized by the caller before any work that may still be in
+// flight uses them (grow() frees the old buffer).  Small arrays are scanned by
+// one workgroup in a single launch.
 hipError_t scan_exclusive_u32(DevBuf &scan_tmp, const uint32_t *in, uint32_t *out, uint32_t n, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
+    if (n <= SMALL_SCAN) {
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, st, in, out, n);
+        return hipGetLastError();
+    }
     const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
     if (scan_tmp.cap < (size_t)nb * 4) return hipErrorOutOfMemory;
     uint32_t *bs = scan_tmp.as<uint32_t>();
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(BLOCK), 0, st, in, n, bs);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, st, bs, nb);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, st, bs, bs, nb);
     hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(BLOCK), 0, st, in, n, bs, out);
     return hipGetLastError();
 }
 
-// Sort n (key, value) pairs by the low `bits` bits of the key, stably.
-// seg_len > 0: independent segments of seg_len (a multiple of SORT_TILE).
-hipError_t sort_pairs_u32(Workspace &ws, DevBuf *keys, DevBuf *vals, DevBuf &histb, DevBuf &scan_tmp, int &cur,
-                          uint32_t n, int bits, int64_t seg_len, const int4 *segtab, hipStream_t st)
+int sort_items_for(uint32_t n) { return n <= SMALL_SORT ? 4 : 16; }
+
+size_t sort_hist_bytes(uint32_t n)
 {
-    (void)ws;
-    if (n == 0 || bits <= 0) return hipSuccess;
-    const uint32_t nblocks = (n + SORT_TILE - 1) / SORT_TILE;
+    const int it = sort_items_for(n);
+    return (size_t)((n + BLOCK * it - 1) / (BLOCK * it)) * 256 * 4;
+}
+
+// Sort n (key, value) pairs by the low `bits` bits of the key, stably.
+// seg_len > 0: independent segments of seg_len keys (a multiple of 4096);
+// segtab: independent segments given per 4096-key unit.
+template <int ITEMS>
+static hipError_t sort_passes(DevBuf *keys, DevBuf *vals, DevBuf &histb, DevBuf &scan_tmp, int &cur, uint32_t n,
+                              int bits, int64_t seg_len, const int4 *segtab, hipStream_t st)
+{
+    constexpr uint32_t TILEN = BLOCK * ITEMS;
+    const uint32_t nblocks = (n + TILEN - 1) / TILEN;
     SegMap sm;
-    sm.seg_blocks = seg_len > 0 ? (uint32_t)(seg_len / SORT_TILE) : 0u;
+    sm.seg_blocks = seg_len > 0 ? (uint32_t)(seg_len / TILEN) : 0u;
     sm.tab = segtab;
+    sm.scale = SORT_TILE / TILEN;
     const size_t nh = (size_t)nblocks * 256;
     if (histb.cap < nh * 4) return hipErrorOutOfMemory;
     uint32_t *hist = histb.as<uint32_t>();
@@ -916,14 +971,23 @@ hipError_t sort_pairs_u32(Workspace &ws, DevBuf *keys, DevBuf *vals, DevBuf &his
         const uint32_t *vin = vals[cur].as<uint32_t>();
         uint32_t *kout = keys[cur ^ 1].as<uint32_t>();
         uint32_t *vout = vals[cur ^ 1].as<uint32_t>();
-        hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(BLOCK), 0, st, kin, n, shift, hist, nblocks, sm);
+        hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(nblocks), dim3(BLOCK), 0, st, kin, n, shift, hist, nblocks, sm);
         hipError_t e = scan_exclusive_u32(scan_tmp, hist, hist, (uint32_t)nh, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(BLOCK), 0, st, kin, vin, kout, vout, n, shift, hist,
-                           nblocks, sm);
+        hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(nblocks), dim3(BLOCK), 0, st, kin, vin, kout, vout, n, shift,
+                           hist, nblocks, sm);
         cur ^= 1;
     }
     return hipGetLastError();
+}
+
+hipError_t sort_pairs_u32(Workspace &ws, DevBuf *keys, DevBuf *vals, DevBuf &histb, DevBuf &scan_tmp, int &cur,
+                          uint32_t n, int bits, int64_t seg_len, const int4 *segtab, hipStream_t st)
+{
+    (void)ws;
+    if (n == 0 || bits <= 0) return hipSuccess;
+    if (sort_items_for(n) == 4) return sort_passes<4>(keys, vals, histb, scan_tmp, cur, n, bits, seg_len, segtab, st);
+    return sort_passes<16>(keys, vals, histb, scan_tmp, cur, n, bits, seg_len, segtab, st);
 }
 
 hipError_t launch_gather(Workspace &ws, int V, int64_t Kp, hipStream_t st)
@@ -938,11 +1002,9 @@ hipError_t launch_gather(Workspace &ws, int V, int64_t Kp, hipStream_t st)
 hipError_t launch_emit(Workspace &ws, int V, int64_t Kp, const DevGrid &g, hipStream_t st)
 {
     const int64_t total = (int64_t)V * Kp;
-    hipError_t e = launch_fill_u32(ws.pkey[0].as<uint32_t>(), 0xFFFFFFFFu, (size_t)ws.Dpad, st);
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_emit, dim3((unsigned)(total / BLOCK)), dim3(BLOCK), 0, st, ws.ext.as<float4>(),
                        ws.sval[ws.sorted_buf].as<uint32_t>(), ws.counters.as<unsigned long long>(),
-                       ws.poff.as<uint32_t>(), ws.ntl_s.as<uint32_t>(), ws.pbase.as<uint32_t>(), Kp, g,
+                       ws.poff.as<uint32_t>(), ws.ntl_s.as<uint32_t>(), ws.d_pbase, Kp, g,
                        (uint32_t)ws.Dpad, ws.pkey[0].as<uint32_t>(), ws.pval[0].as<uint32_t>());
     return hipGetLastError();
 }
@@ -950,10 +1012,16 @@ hipError_t launch_emit(Workspace &ws, int V, int64_t Kp, const DevGrid &g, hipSt
 hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st)
 {
     const size_t nr = (size_t)ws.V * g.tiles;
+    if (g.tiles <= 255) {
+        // one 8-bit pass: ranges straight from the scanned histogram
+        hipLaunchKernelGGL(k_ranges_hist, dim3(nblk(nr)), dim3(BLOCK), 0, st, ws.hist_b.as<uint32_t>(), ws.d_pbase,
+                           ws.d_pcount, ws.V, g.tiles, ws.pair_blk, ws.ranges.as<uint2>());
+        return hipGetLastError();
+    }
     hipError_t e = launch_fill_u32(ws.ranges.as<uint32_t>(), 0u, nr * 2, st);
     if (e != hipSuccess || ws.Dpad == 0) return e;
     hipLaunchKernelGGL(k_ranges, dim3(nblk((size_t)ws.Dpad)), dim3(BLOCK), 0, st,
-                       ws.pkey[ws.pairs_buf].as<uint32_t>(), (uint32_t)ws.Dpad, ws.segtab.as<int4>(), g.tiles,
+                       ws.pkey[ws.pairs_buf].as<uint32_t>(), (uint32_t)ws.Dpad, ws.d_segtab, g.tiles,
                        ws.ranges.as<uint2>());
     return hipGetLastError();
 }
@@ -964,7 +1032,7 @@ hipError_t launch_rad_direct(const Scene &sc, Workspace &ws, hipStream_t st)
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_rad_direct, dim3(nblk(n)), dim3(BLOCK), 0, st, sc.rad.as<float2>(),
                        ws.sval[ws.sorted_buf].as<uint32_t>(), ws.counters.as<unsigned long long>(),
-                       ws.rxview.as<int>(), ws.N, ws.Kp, ws.K, ws.rad.as<float2>());
+                       ws.d_rxview, ws.N, ws.Kp, ws.K, ws.rad.as<float2>());
     return hipGetLastError();
 }
 
@@ -972,7 +1040,7 @@ hipError_t launch_mlp_global(const Mlp &m, Workspace &ws, hipStream_t st)
 {
     if (ws.N > 0)
         hipLaunchKernelGGL(k_mlp_global, dim3(nblk((size_t)ws.N * HID)), dim3(BLOCK), 0, st, m.raw.as<float>(),
-                           ws.rxpos.as<float>(), ws.N, ws.Gp.as<float>());
+                           ws.rxpos_p, ws.N, ws.Gp.as<float>());
     return hipGetLastError();
 }
 
@@ -993,7 +1061,7 @@ hipError_t launch_mlp_pairs(const Mlp &m, Workspace &ws, hipStream_t st)
         const unsigned blocks = (unsigned)std::min((ws.n_items + 3) / 4, 256 * 8);
         hipLaunchKernelGGL(k_mlp_pairs, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(), ws.Gp.as<float>(),
                            m.w2a.as<float>(), m.tab.as<float4>(), b3, ws.sval[ws.sorted_buf].as<uint32_t>(),
-                           ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K, ws.counters.as<unsigned long long>(),
+                           ws.d_items, ws.n_items, ws.Kp, ws.K, ws.counters.as<unsigned long long>(),
                            ws.rad.as<float2>());
     }
     return hipGetLastError();
@@ -1005,7 +1073,7 @@ static void blend_launch(Workspace &ws, float *C, hipStream_t st)
     dim3 grid((unsigned)ws.g.tiles, (unsigned)ws.n_chunks);
     hipLaunchKernelGGL(k_blend_fwd<R>, grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                        ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
-                       ws.chunks.as<int4>(), ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
+                       ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
                        ws.part.as<float>());
 }
 

@@ -106,12 +106,12 @@ bool ensure_pinned(Workspace &ws, size_t bytes)
 
 void free_workspace(Workspace &ws)
 {
-    DevBuf *bufs[] = {&ws.centres, &ws.rxpos,   &ws.rxview, &ws.rec,   &ws.ext,     &ws.rawkey, &ws.opac,
+    DevBuf *bufs[] = {&ws.centres, &ws.rxpos,   &ws.desc,   &ws.rec,   &ws.ext,     &ws.rawkey, &ws.opac,
                       &ws.ntl,     &ws.skey[0], &ws.skey[1], &ws.sval[0], &ws.sval[1], &ws.srec, &ws.ntl_s,
                       &ws.poff,    &ws.pkey[0], &ws.pkey[1], &ws.pval[0], &ws.pval[1], &ws.ranges, &ws.rad,
-                      &ws.Lp,      &ws.Gp,      &ws.Tfin,   &ws.nlast,  &ws.part,    &ws.chunks, &ws.items,
+                      &ws.Lp,      &ws.Gp,      &ws.Tfin,   &ws.nlast,  &ws.part,
                       &ws.counters, &ws.hist,   &ws.scan_tmp, &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
-                      &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.hist_b,  &ws.scan_b, &ws.pbase,  &ws.segtab};
+                      &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.hist_b,  &ws.scan_b};
     for (DevBuf *b : bufs) release(*b);
     if (ws.staged) (void)hipEventDestroy(ws.staged);
     if (ws.counted) (void)hipEventDestroy(ws.counted);
@@ -504,9 +504,11 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     ws.use_mlp = sc.has_features;
     ws.h_rxview = rxview;
 
-    GROW(ctx, ws.centres, (size_t)V * 12);
-    GROW(ctx, ws.rxpos, (size_t)N * 12);
-    GROW(ctx, ws.rxview, (size_t)N * 4);
+    if (saved) {
+        // the backward needs the view centres and receiver positions later
+        GROW(ctx, ws.centres, (size_t)V * 12);
+        GROW(ctx, ws.rxpos, (size_t)N * 12);
+    }
     GROW(ctx, ws.rec, VK * 32);
     GROW(ctx, ws.ext, VK * 16);
     GROW(ctx, ws.rawkey, VK * 4);
@@ -520,19 +522,25 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     GROW(ctx, ws.ntl_s, VK * 4);
     GROW(ctx, ws.poff, VK * 4);
     GROW(ctx, ws.counters, (size_t)2 * V * 8);
-    GROW(ctx, ws.hist, (VK / SORT_TILE) * 256 * 4);
-    // block sums of two scans: the sort histograms (VK / 16 entries) and the
-    // emission offsets (VK entries), 4096 entries per block
-    GROW(ctx, ws.scan_tmp, (std::max(VK / SORT_TILE, (VK / SORT_TILE) * 256 / SORT_TILE) + 2) * 4);
+    GROW(ctx, ws.hist, sort_hist_bytes((uint32_t)VK));
+    // block sums of two scans: the sort histograms and the emission offsets
+    GROW(ctx, ws.scan_tmp, (std::max(VK / SORT_TILE, sort_hist_bytes((uint32_t)VK) / 4 / SORT_TILE) + 2) * 4);
 
-    HIPCHK(ctx, hipMemcpyAsync(ws.centres.p, mode == RXGS_MODE_TX ? tx : rx, (size_t)V * 12,
-                               hipMemcpyDeviceToDevice, st));
-    HIPCHK(ctx, hipMemcpyAsync(ws.rxpos.p, rx, (size_t)N * 12, hipMemcpyDeviceToDevice, st));
+    if (saved) {
+        HIPCHK(ctx, hipMemcpyAsync(ws.centres.p, mode == RXGS_MODE_TX ? tx : rx, (size_t)V * 12,
+                                   hipMemcpyDeviceToDevice, st));
+        HIPCHK(ctx, hipMemcpyAsync(ws.rxpos.p, rx, (size_t)N * 12, hipMemcpyDeviceToDevice, st));
+        ws.centres_p = ws.centres.as<float>();
+        ws.rxpos_p = ws.rxpos.as<float>();
+    } else {
+        ws.centres_p = mode == RXGS_MODE_TX ? tx : rx;
+        ws.rxpos_p = rx;
+    }
     HIPCHK(ctx, launch_fill_u32(ws.counters.as<uint32_t>(), 0u, (size_t)V * 4, st));
 
     // stage 1: projection, then the per-view depth sort; the host waits only
     // for the counters (visible Gaussians per view, pair count) while the sort runs
-    STAGE(ctx, "project", launch_project(sc, ws.centres.as<float>(), V, Kp, g, ws, st));
+    STAGE(ctx, "project", launch_project(sc, ws.centres_p, V, Kp, g, ws, st));
     if (!ensure_pinned(ws, (size_t)2 * V * 8 + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
     unsigned long long *h_cnt = static_cast<unsigned long long *>(ws.h_pinned);
     HIPCHK(ctx, hipMemcpyAsync(h_cnt, ws.counters.p, (size_t)2 * V * 8, hipMemcpyDeviceToHost, st));
@@ -600,44 +608,46 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     GROW(ctx, ws.pkey[1], std::max<uint64_t>(Dpad, 1) * 4);
     GROW(ctx, ws.pval[0], std::max<uint64_t>(Dpad, 1) * 4);
     GROW(ctx, ws.pval[1], std::max<uint64_t>(Dpad, 1) * 4);
-    GROW(ctx, ws.hist_b, (Dpad / SORT_TILE) * 256 * 4);
-    GROW(ctx, ws.scan_b, ((Dpad / SORT_TILE) * 256 / SORT_TILE + 2) * 4);
-    GROW(ctx, ws.pbase, (size_t)V * 4);
-    GROW(ctx, ws.segtab, std::max<size_t>(segtab.size(), 1) * 16);
+    GROW(ctx, ws.hist_b, sort_hist_bytes((uint32_t)Dpad));
+    GROW(ctx, ws.scan_b, (sort_hist_bytes((uint32_t)Dpad) / 4 / SORT_TILE + 2) * 4);
+    ws.pair_blk = BLOCK * sort_items_for((uint32_t)Dpad);
     GROW(ctx, ws.ranges, (size_t)V * g.tiles * 8);
     GROW(ctx, ws.rad, (size_t)N * Kp * 8);
     GROW(ctx, ws.Tfin, (size_t)ws.n_tslots * P * 4);
     GROW(ctx, ws.nlast, (size_t)ws.n_tslots * P * 4);
     GROW(ctx, ws.part, (size_t)N * g.tiles * 12);
-    GROW(ctx, ws.chunks, std::max<size_t>(chunks.size(), 1) * 16);
-    GROW(ctx, ws.items, std::max<size_t>(items.size(), 1) * 16);
     if (ws.use_mlp) {
         GROW(ctx, ws.Lp, (size_t)std::max<int64_t>(K, 1) * HID * 4);
         GROW(ctx, ws.Gp, (size_t)N * HID * 4);
     }
 
-    // host-to-device copies of the small descriptors
-    const size_t stage_bytes =
-        (size_t)N * 4 + chunks.size() * 16 + items.size() * 16 + (size_t)V * 4 + segtab.size() * 16;
+    // the small descriptors, packed (16-byte aligned parts) into one host-to-device copy
+    auto al16 = [](size_t b) { return (b + 15) / 16 * 16; };
+    const size_t o_chunks = al16((size_t)N * 4);
+    const size_t o_items = o_chunks + chunks.size() * 16;
+    const size_t o_pbase = o_items + items.size() * 16;
+    const size_t o_pcount = o_pbase + al16((size_t)V * 4);
+    const size_t o_segtab = o_pcount + al16((size_t)V * 4);
+    const size_t stage_bytes = o_segtab + segtab.size() * 16;
     const size_t cnt_bytes = (size_t)2 * V * 8;
     const size_t off0 = (cnt_bytes + 63) / 64 * 64;
     if (!ensure_pinned(ws, off0 + stage_bytes + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
+    GROW(ctx, ws.desc, stage_bytes);
     char *hp = static_cast<char *>(ws.h_pinned) + off0;
     std::memcpy(hp, rxview.data(), (size_t)N * 4);
-    std::memcpy(hp + (size_t)N * 4, chunks.data(), chunks.size() * 16);
-    std::memcpy(hp + (size_t)N * 4 + chunks.size() * 16, items.data(), items.size() * 16);
-    char *hp2 = hp + (size_t)N * 4 + chunks.size() * 16 + items.size() * 16;
-    std::memcpy(hp2, ws.h_pbase.data(), (size_t)V * 4);
-    std::memcpy(hp2 + (size_t)V * 4, segtab.data(), segtab.size() * 16);
-    HIPCHK(ctx, hipMemcpyAsync(ws.rxview.p, hp, (size_t)N * 4, hipMemcpyHostToDevice, st));
-    if (!chunks.empty())
-        HIPCHK(ctx, hipMemcpyAsync(ws.chunks.p, hp + (size_t)N * 4, chunks.size() * 16, hipMemcpyHostToDevice, st));
-    if (!items.empty())
-        HIPCHK(ctx, hipMemcpyAsync(ws.items.p, hp + (size_t)N * 4 + chunks.size() * 16, items.size() * 16,
-                                   hipMemcpyHostToDevice, st));
-    HIPCHK(ctx, hipMemcpyAsync(ws.pbase.p, hp2, (size_t)V * 4, hipMemcpyHostToDevice, st));
-    if (!segtab.empty())
-        HIPCHK(ctx, hipMemcpyAsync(ws.segtab.p, hp2 + (size_t)V * 4, segtab.size() * 16, hipMemcpyHostToDevice, st));
+    std::memcpy(hp + o_chunks, chunks.data(), chunks.size() * 16);
+    std::memcpy(hp + o_items, items.data(), items.size() * 16);
+    std::memcpy(hp + o_pbase, ws.h_pbase.data(), (size_t)V * 4);
+    std::memcpy(hp + o_pcount, ws.h_pcount.data(), (size_t)V * 4);
+    std::memcpy(hp + o_segtab, segtab.data(), segtab.size() * 16);
+    char *dd = ws.desc.as<char>();
+    ws.d_rxview = reinterpret_cast<int *>(dd);
+    ws.d_chunks = reinterpret_cast<int4 *>(dd + o_chunks);
+    ws.d_items = reinterpret_cast<int4 *>(dd + o_items);
+    ws.d_pbase = reinterpret_cast<uint32_t *>(dd + o_pbase);
+    ws.d_pcount = reinterpret_cast<uint32_t *>(dd + o_pcount);
+    ws.d_segtab = reinterpret_cast<int4 *>(dd + o_segtab);
+    HIPCHK(ctx, hipMemcpyAsync(dd, hp, stage_bytes, hipMemcpyHostToDevice, st));
     HIPCHK(ctx, hipEventRecord(ws.staged, st));
 
     // pairs: emit in depth order, stable sort by (view, tile), tile ranges
@@ -646,7 +656,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         STAGE(ctx, "emit", launch_emit(ws, V, Kp, g, st));
         const int sbits = std::max(bits_for((uint64_t)g.tiles), 1);
         STAGE(ctx, "sort_pairs", sort_pairs_u32(ws, ws.pkey, ws.pval, ws.hist_b, ws.scan_b, pcur, (uint32_t)Dpad, sbits,
-                                                0, ws.segtab.as<int4>(), st));
+                                                0, ws.d_segtab, st));
     }
     ws.pairs_buf = pcur;
     STAGE(ctx, "ranges", launch_ranges(ws, g, st));

@@ -23,6 +23,8 @@ constexpr int HID = 64;
 constexpr int MLP_IN = ENC + FEAT;
 constexpr int MLP_RG = 16;               // receivers per MLP work item
 constexpr int MLP_PAIRS = 32;            // sorted positions per MLP work item
+constexpr uint32_t SMALL_SCAN = 16384;   // scans up to this length run in one workgroup
+constexpr uint32_t SMALL_SORT = 1u << 20;  // sorts up to this length use 1024-key blocks
 
 // Method constants (Alg. 1 compositing and the readings of its unstated values).
 constexpr float ALPHA_MIN = 1.0f / 255.0f;   // skip threshold on the blend weight
@@ -79,7 +81,6 @@ struct Workspace {
 
     DevBuf centres;   // V x 3
     DevBuf rxpos;     // N x 3
-    DevBuf rxview;    // N int
     DevBuf rec;       // V x Kp x 2 float4 (blend record, unsorted)
     DevBuf ext;       // V x Kp float4 (u, v, rup, rvp)
     DevBuf rawkey;    // V x Kp u32
@@ -91,8 +92,16 @@ struct Workspace {
     DevBuf srec;      // V x Kp x 2 float4 (sorted order)
     DevBuf ntl_s;     // V x Kp u32 (sorted order)
     DevBuf poff;      // V x Kp u32 emission offsets
-    DevBuf pbase;     // V u32: start of each view's segment of the pair arrays
-    DevBuf segtab;    // per pair-sort block int4: (first block, blocks, view, 0) of its segment
+    DevBuf desc;      // small descriptors copied from the host in one transfer:
+    int *d_rxview = nullptr;       //   N: view of each receiver
+    int4 *d_chunks = nullptr;      //   blend chunks (view, first receiver, receivers, T slot)
+    int4 *d_items = nullptr;       //   MLP work items (view, first position, first receiver, receivers)
+    uint32_t *d_pbase = nullptr;   //   V: start of each view's segment of the pair arrays
+    uint32_t *d_pcount = nullptr;  //   V: pairs of each view
+    int4 *d_segtab = nullptr;      //   per 4096 pair slots: (first unit, units, view, 0) of its segment
+    const float *centres_p = nullptr;  // view centres (the caller's or the saved copy)
+    const float *rxpos_p = nullptr;    // receiver positions (the caller's or the saved copy)
+    int pair_blk = 4096;           // keys per block of the pair sort
     std::vector<uint32_t> h_pbase;    // V
     std::vector<uint32_t> h_pcount;   // V: pairs of each view
     DevBuf pkey[2];   // Dpad u32: local tile id, 0xFFFFFFFF for padding
@@ -105,8 +114,6 @@ struct Workspace {
     DevBuf Tfin;      // S x H x W
     DevBuf nlast;     // S x H x W
     DevBuf part;      // N x tiles x 3
-    DevBuf chunks;    // int4
-    DevBuf items;     // int4
     DevBuf counters;  // u64 per view: [2 v] visible Gaussians, [2 v + 1] pairs
     DevBuf hist;      // radix histograms (depth sort)
     DevBuf scan_tmp;  // scan block sums (depth sort, emission offsets)
@@ -200,6 +207,8 @@ hipError_t launch_rad_bwd(const Scene &sc, Workspace &ws, float *grad, hipStream
 hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *gfeat, float *gmlp, hipStream_t st);
 hipError_t launch_project_bwd(const Scene &sc, Workspace &ws, const rxgs_grads &gr, hipStream_t st);
 size_t mlp_part_bytes(const Workspace &ws);
+size_t sort_hist_bytes(uint32_t n);
+int sort_items_for(uint32_t n);
 size_t w1b_part_bytes(int64_t K);
 
 bool grow(DevBuf &b, size_t bytes);
