@@ -232,10 +232,11 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
 
     for (int item = gw; item < nitems; item += nw) {
         const int4 it = items[item];
-        const int view = it.x, s0 = it.y, j0 = it.z, nj = it.w;
-        const int64_t nv = (int64_t)counters[2 * (size_t)view];
+        const int view = it.x, s0 = it.y, j0 = it.z, nj = it.w & 255;
         const int64_t s = s0 + pl;
-        const bool valid = s < nv;
+        const int nvalid = it.w >> 8;
+        const bool valid = pl < nvalid;
+        const int64_t nv = (int64_t)s0 + nvalid;
         const size_t obase = (size_t)view * Kp;
         const uint32_t k = (uint32_t)min((int64_t)order[obase + (valid ? s : s0)], K - 1);
         float l[32];

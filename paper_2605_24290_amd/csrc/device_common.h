@@ -6,6 +6,7 @@
 namespace rxgs {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ int count_below(uint64_t m)
 {
@@ -140,6 +141,24 @@ __device__ __forceinline__ void stage_batch(BlendStage &st, const float4 *__rest
     }
     if (t < 4) st.len[t] = st.wcnt[0][t] + st.wcnt[1][t] + st.wcnt[2][t] + st.wcnt[3][t];
     __syncthreads();
+}
+
+// exclusive scan over the 256 threads of a workgroup; total = sum of all
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t &total, uint32_t *s_w)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t v = x;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(v, off);
+        if (lane >= off) v += y;
+    }
+    if (lane == 63) s_w[w] = v;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int i = 0; i < w; i++) pre += s_w[i];
+    total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    __syncthreads();
+    return pre + v - x;
 }
 
 }  // namespace rxgs

@@ -5,16 +5,16 @@
 //   k_project      stage 1: per (view, Gaussian) projection onto the angular
 //                  grid, FP32 depth key, conservative tile count.   [HBM]
 //   radix sort     stage 1: per-view stable sort of the depth keys (one
-//                  segment per view), 4 passes of 8 bits.          [HBM]
+//                  segment per view), 4 passes of 8 bits (sort.hip). [HBM]
 //   k_gather       records into depth order, tile counts in depth order.
-//   scan + k_emit  one (segment, position) pair per covered tile, emitted in
-//                  depth order.                                      [HBM]
-//   radix sort     stable sort of the pairs by segment = view x tiles + tile,
-//                  so each tile's list stays in depth order.        [HBM]
-//   k_ranges       [start, end) of each tile's list.
+//   scan + k_emit  one (local tile, sorted position) pair per covered tile,
+//                  emitted in depth order into the view's segment.  [HBM]
+//   radix sort     stable 8-bit sort of each view's pairs by tile, so each
+//                  tile's list stays in depth order.                [HBM]
+//   k_ranges_hist  [start, end) of each tile's list.
 //   k_mlp_*        stage 2: receiver term and Gaussian term of the MLP's first
-//                  layer, then the per-(receiver, Gaussian) layers on FP32
-//                  MFMA.                                            [MFMA]
+//                  layer, then the per-(receiver, Gaussian) layers on split
+//                  FP16 MFMA.                                       [MFMA]
 //   k_blend_fwd    stage 3: per (tile, receiver chunk) front-to-back
 //                  compositing from LDS-staged batches.             [VALU]
 //   k_reduce_out   per-receiver power and coherent sum, fixed order.
@@ -223,23 +223,6 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, size_t n)
 // ----------------------------------------------------------------------------
 // exclusive scan of u32 (three kernels: block sums, scan of block sums,
 // block-local scan plus offset); blocks of 4096, 16 consecutive items per thread
-__device__ uint32_t block_exclusive_scan(uint32_t x, uint32_t &total, uint32_t *s_w)
-{
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t v = x;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(v, off);
-        if (lane >= off) v += y;
-    }
-    if (lane == 63) s_w[w] = v;
-    __syncthreads();
-    uint32_t pre = 0;
-    for (int i = 0; i < w; i++) pre += s_w[i];
-    total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
-    __syncthreads();
-    return pre + v - x;
-}
-
 __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t *__restrict__ in, uint32_t n,
                                                        uint32_t *__restrict__ bsum)
 {
@@ -298,138 +281,6 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t *__restrict_
     }
 }
 
-// ----------------------------------------------------------------------------
-// Stable LSD radix sort, 8-bit digits, 256 x ITEMS keys per block (1024 for
-// small sorts, 4096 for large ones).  A pass is a per-block digit histogram, an
-// exclusive scan over (segment, digit, block), and a stable scatter.  Segments
-// are runs of whole blocks sorted independently: uniform (seg_blocks blocks
-// each) or given per 4096-key unit by a table (first unit, unit count, view).
-struct SegMap {
-    uint32_t seg_blocks;          // uniform segment length in blocks (0: table or none)
-    const int4 *tab;              // per 4096-key unit: (first unit of its segment, units in it, view, 0)
-    uint32_t scale;               // blocks per 4096-key unit (4096 / block size)
-};
-
-__device__ __forceinline__ size_t hist_index(uint32_t d, uint32_t blk, uint32_t nblocks, const SegMap &sm)
-{
-    if (sm.tab) {
-        const int4 e = sm.tab[blk / sm.scale];
-        const uint32_t first = (uint32_t)e.x * sm.scale, nb = (uint32_t)e.y * sm.scale;
-        return (size_t)first * 256 + (size_t)d * nb + (blk - first);
-    }
-    if (sm.seg_blocks) {
-        const uint32_t seg = blk / sm.seg_blocks, b = blk % sm.seg_blocks;
-        return ((size_t)seg * 256 + d) * sm.seg_blocks + b;
-    }
-    return (size_t)d * nblocks + blk;
-}
-
-// per-wave LDS histograms (less same-address contention), summed per digit
-template <int ITEMS>
-__global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint32_t *__restrict__ keys, uint32_t n, int shift,
-                                                      uint32_t *__restrict__ hist, uint32_t nblocks, SegMap sm)
-{
-    __shared__ uint32_t h[4][256];
-    const int t = threadIdx.x, w = t >> 6;
-    h[0][t] = 0;
-    h[1][t] = 0;
-    h[2][t] = 0;
-    h[3][t] = 0;
-    __syncthreads();
-    const size_t base = (size_t)blockIdx.x * (BLOCK * ITEMS);
-#pragma unroll 4
-    for (int i = 0; i < ITEMS; i++) {
-        const size_t idx = base + (size_t)i * BLOCK + t;
-        if (idx < n) atomicAdd(&h[w][(keys[idx] >> shift) & 255u], 1u);
-    }
-    __syncthreads();
-    hist[hist_index(t, blockIdx.x, nblocks, sm)] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
-}
-
-// Stable scatter.  Keys are ranked in rounds of 256 (wave match by 8 ballots,
-// prefix over waves, running count per digit) into an LDS copy of the block
-// sorted by digit; the block is then written out digit run by digit run, so
-// consecutive threads store to consecutive addresses.
-template <int ITEMS>
-__global__ __launch_bounds__(BLOCK) void k_radix_scatter(const uint32_t *__restrict__ kin,
-                                                         const uint32_t *__restrict__ vin,
-                                                         uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
-                                                         uint32_t n, int shift, const uint32_t *__restrict__ offs,
-                                                         uint32_t nblocks, SegMap sm)
-{
-    constexpr int TILEN = BLOCK * ITEMS;
-    __shared__ uint32_t s_key[TILEN];
-    __shared__ uint32_t s_val[TILEN];
-    __shared__ uint32_t s_loc[256];     // block-local start of each digit
-    __shared__ uint32_t s_glob[256];    // global start of each digit for this block
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wc[4][256];
-    __shared__ uint32_t s_w[4];
-    const int t = threadIdx.x, w = t >> 6;
-    const size_t base = (size_t)blockIdx.x * TILEN;
-    const uint32_t cnt = (uint32_t)min((size_t)TILEN, (size_t)n - base);
-    // block histogram and its exclusive scan
-    wc[0][t] = 0;
-    __syncthreads();
-    for (uint32_t i = t; i < cnt; i += BLOCK) atomicAdd(&wc[0][(kin[base + i] >> shift) & 255u], 1u);
-    __syncthreads();
-    uint32_t tot;
-    const uint32_t myc = wc[0][t];
-    const uint32_t loc = block_exclusive_scan(myc, tot, s_w);
-    s_loc[t] = loc;
-    s_glob[t] = offs[hist_index(t, blockIdx.x, nblocks, sm)];
-    run[t] = loc;
-    wc[0][t] = 0;
-    wc[1][t] = 0;
-    wc[2][t] = 0;
-    wc[3][t] = 0;
-    __syncthreads();
-    for (int r = 0; r < ITEMS; r++) {
-        if ((uint32_t)r * BLOCK >= cnt) break;   // uniform across the block
-        const uint32_t li = (uint32_t)r * BLOCK + t;
-        const bool valid = li < cnt;
-        const uint32_t key = valid ? kin[base + li] : 0u;
-        const uint32_t val = valid ? vin[base + li] : 0u;
-        const uint32_t d = (key >> shift) & 255u;
-        uint64_t m = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; b++) {
-            const uint32_t bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
-        }
-        const int rank = count_below(m);
-        if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(m);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = run[d] + (uint32_t)rank;
-            for (int ww = 0; ww < w; ww++) pos += wc[ww][d];
-            if (pos < TILEN) {
-                s_key[pos] = key;
-                s_val[pos] = val;
-            }
-        }
-        __syncthreads();
-        run[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
-        wc[0][t] = 0;
-        wc[1][t] = 0;
-        wc[2][t] = 0;
-        wc[3][t] = 0;
-        __syncthreads();
-    }
-    // write out: LDS slot i holds digit d; destination = global start + (i - local start)
-    for (uint32_t i = t; i < cnt; i += BLOCK) {
-        const uint32_t key = s_key[i];
-        const uint32_t d = (key >> shift) & 255u;
-        const uint32_t pos = s_glob[d] + (i - s_loc[d]);
-        if (pos < n) {
-            kout[pos] = key;
-            vout[pos] = s_val[i];
-        }
-    }
-}
-
-// ----------------------------------------------------------------------------
 // records into depth order; tile counts in depth order
 __global__ __launch_bounds__(BLOCK) void k_gather(const float4 *__restrict__ rec, const uint32_t *__restrict__ ntl,
                                                   const uint32_t *__restrict__ order,
@@ -532,24 +383,25 @@ __global__ __launch_bounds__(BLOCK) void k_emit(const float4 *__restrict__ ext, 
 // [start, end) of each (view, tile) list, read from the pair sort's scanned
 // histogram (one 8-bit pass with the tile id as the digit): the start of digit
 // d in the first block of the view's segment, and the start of digit d + 1.
+// one workgroup per view: the pair sort's digit totals of the view are its
+// per-tile list lengths; their exclusive scan from the view's segment start
+// gives the lists' positions.  A view without pairs has empty lists (its
+// totals are not read: the sort, and the clearing of its scratch, is skipped
+// when a render has no pairs at all).
 __global__ __launch_bounds__(BLOCK) void k_ranges_hist(const uint32_t *__restrict__ hist,
                                                        const uint32_t *__restrict__ pbase,
-                                                       const uint32_t *__restrict__ pcount, int V, int tiles,
-                                                       int blk, uint2 *__restrict__ ranges)
+                                                       const uint32_t *__restrict__ pcount, int tiles,
+                                                       uint2 *__restrict__ ranges)
 {
-    const int idx = blockIdx.x * BLOCK + threadIdx.x;
-    if (idx >= V * tiles) return;
-    const int v = idx / tiles, tile = idx % tiles;
-    const uint32_t cnt = pcount[v];
-    uint2 r = make_uint2(0u, 0u);
-    if (cnt) {
-        const uint32_t first = pbase[v] / (uint32_t)blk;              // first sort block of the segment
-        const uint32_t nb = (cnt + SORT_TILE - 1) / SORT_TILE * (SORT_TILE / (uint32_t)blk);
-        const uint32_t s = hist[(size_t)first * 256 + (size_t)tile * nb];
-        const uint32_t e = hist[(size_t)first * 256 + (size_t)(tile + 1) * nb];
-        if (e > s) r = make_uint2(s, e);
+    __shared__ uint32_t s_w[4];
+    const int v = blockIdx.x, t = threadIdx.x;
+    const uint32_t c = pcount[v] ? hist[(size_t)v * 256 + t] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(c, tot, s_w);
+    if (t < tiles) {
+        const uint32_t s0 = pbase[v] + ex;
+        ranges[(size_t)v * tiles + t] = c ? make_uint2(s0, s0 + c) : make_uint2(0u, 0u);
     }
-    ranges[idx] = r;
 }
 
 // [start, end) of each (view, tile) list in the padded pair array
@@ -584,30 +436,57 @@ __global__ __launch_bounds__(BLOCK) void k_rad_direct(const float2 *__restrict__
 }
 
 // receiver ("global") term of layer 1: W1[:, :36] gamma(r_j), stored in hid_pos order
+// largest |x| over the wave, folded into *dst as FP32 bits (non-negative
+// floats order like their bit patterns)
+__device__ __forceinline__ unsigned wave_absmax_bits(float x)
+{
+    unsigned b = __float_as_uint(fabsf(x));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) b = max(b, (unsigned)__shfl_xor((int)b, o));
+    return b;
+}
+
+// workgroup max |x| into one of 64 slots (blockIdx % 64), so that no single
+// address takes an atomic from every workgroup
+__device__ __forceinline__ void block_absmax_to(float x, unsigned *slots)
+{
+    __shared__ unsigned s_m[BLOCK / 64];
+    const unsigned b = wave_absmax_bits(x);
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned m = s_m[0];
+        for (int w = 1; w < BLOCK / 64; w++) m = max(m, s_m[w]);
+        atomicMax(slots + (blockIdx.x & 63), m);
+    }
+}
+
 __global__ __launch_bounds__(BLOCK) void k_mlp_global(const float *__restrict__ W1, const float *__restrict__ rx,
-                                                      int N, float *__restrict__ Gp)
+                                                      int N, float *__restrict__ Gp, unsigned *__restrict__ amax)
 {
     const int idx = blockIdx.x * BLOCK + threadIdx.x;
-    if (idx >= N * HID) return;
-    const int j = idx / HID, d = idx % HID;
     float acc = 0.f;
-    for (int a = 0; a < 3; a++) {
-        const float r = rx[3 * j + a];
-        for (int f = 0; f < 6; f++) {
-            float sn, cs;
-            sincosf(ldexpf(r, f), &sn, &cs);
-            acc = fmaf(W1[d * MLP_IN + 12 * a + 2 * f], sn, acc);
-            acc = fmaf(W1[d * MLP_IN + 12 * a + 2 * f + 1], cs, acc);
+    if (idx < N * HID) {
+        const int j = idx / HID, d = idx % HID;
+        for (int a = 0; a < 3; a++) {
+            const float r = rx[3 * j + a];
+            for (int f = 0; f < 6; f++) {
+                float sn, cs;
+                sincosf(ldexpf(r, f), &sn, &cs);
+                acc = fmaf(W1[d * MLP_IN + 12 * a + 2 * f], sn, acc);
+                acc = fmaf(W1[d * MLP_IN + 12 * a + 2 * f + 1], cs, acc);
+            }
         }
+        Gp[(size_t)j * HID + hid_pos(d)] = acc;
     }
-    Gp[(size_t)j * HID + hid_pos(d)] = acc;
+    block_absmax_to(acc, amax);
 }
 
 // Gaussian ("local") term of layer 1: W1[:, 36:] f_k + b1, stored in hid_pos order
 // 64 Gaussians per workgroup, W1[:, 36:] and the features staged in LDS
 __global__ __launch_bounds__(BLOCK) void k_mlp_local(const float *__restrict__ W1, const float *__restrict__ b1,
                                                      const float *__restrict__ feat, int64_t K,
-                                                     float *__restrict__ Lp)
+                                                     float *__restrict__ Lp, unsigned *__restrict__ amax)
 {
     __shared__ float s_w[FEAT][HID + 1];
     __shared__ float s_f[64][FEAT + 1];
@@ -623,13 +502,16 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_local(const float *__restrict__ W
     __syncthreads();
     const int d = threadIdx.x & 63;
     const float bias = b1[d];
+    float m = 0.f;
     for (int kk = threadIdx.x >> 6; kk < 64; kk += BLOCK / 64) {
         if (k0 + kk >= K) break;
         float acc = bias;
 #pragma unroll
         for (int c = 0; c < FEAT; c++) acc = fmaf(s_w[c][d], s_f[kk][c], acc);
         Lp[(size_t)(k0 + kk) * HID + hid_pos(d)] = acc;
+        m = fmaxf(m, fabsf(acc));
     }
+    block_absmax_to(m, amax);
 }
 
 // Per-(receiver, Gaussian) layers 2 and 3 on FP32 MFMA (v_mfma_f32_32x32x2f32).
@@ -640,7 +522,7 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_local(const float *__restrict__ W
 // hid_of order), so the accumulator leaves each lane with 32 of the 64 hidden
 // outputs of its own pair.  Layer 3 (64 -> 2) is then a per-lane dot product
 // plus one exchange between the two lane halves.
-__global__ __launch_bounds__(BLOCK) void k_mlp_pairs(const float *__restrict__ Lp, const float *__restrict__ Gp,
+__global__ __launch_bounds__(BLOCK) void k_mlp_pairs_f32(const float *__restrict__ Lp, const float *__restrict__ Gp,
                                                      const float *__restrict__ w2a,
                                                      const float4 *__restrict__ tab, const float *__restrict__ b3,
                                                      const uint32_t *__restrict__ order,
@@ -658,7 +540,7 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_pairs(const float *__restrict__ L
     // persistent waves: the workgroup stages W2 once and walks many work items
     for (int item = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); item < nitems; item += gridDim.x * (BLOCK / 64)) {
     const int4 it = items[item];
-    const int view = it.x, s0 = it.y, j0 = it.z, nj = it.w;
+    const int view = it.x, s0 = it.y, j0 = it.z, nj = it.w & 255;
     const int64_t nv = (int64_t)counters[2 * (size_t)view];
     const int64_t s = s0 + pl;
     const bool valid = s < nv;
@@ -715,6 +597,199 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_pairs(const float *__restrict__ L
         o1 += __shfl_xor(o1, 32);
         if (h == 0 && valid) rad[(size_t)j * Kp + s] = make_float2(o0 + b30, o1 + b31);
     }
+    }
+}
+
+// The same layers with layer 2 on FP16 MFMA (v_mfma_f32_32x32x16_f16) in split
+// precision: every FP32 operand x is carried as an FP16 pair hi = fp16(x),
+// lo = fp16(x - hi), and W2 x1 is summed as Wlo xhi + Whi xlo + Whi xhi in an
+// FP32 accumulator, which leaves a relative error near 2^-21 per product (the
+// dropped Wlo xlo term and the rounding of the lo halves) at about a sixth of
+// the matrix-core time of the FP32 instruction.  W2 arrives pre-split and
+// pre-scaled by 2^wexp and stays in registers for the life of the wave.  The
+// layer-1 activations are split unscaled while the largest possible one,
+// max|local| + max|global|, is below 2^15; beyond that a uniform branch scales
+// them by a power of two first, so no operand leaves the FP16 range.
+// one 64-float row stored in hid_pos order: lane half h takes its 32 values
+__device__ __forceinline__ void load_half_row(const float *__restrict__ base, size_t row, int h, float (&v)[32])
+{
+    const float4 *src = reinterpret_cast<const float4 *>(base + row * HID + h * 32);
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        const float4 x = src[q];
+        v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+    }
+}
+
+// Work item descriptor: (view, first sorted position s0, first receiver j0,
+// receivers | valid positions << 8).
+__device__ __forceinline__ int4 read_desc(const int4 &batch, int lane_idx)
+{
+    return make_int4(__builtin_amdgcn_readlane(batch.x, lane_idx), __builtin_amdgcn_readlane(batch.y, lane_idx),
+                     __builtin_amdgcn_readlane(batch.z, lane_idx), __builtin_amdgcn_readlane(batch.w, lane_idx));
+}
+
+// Each wave walks its items n = 0, 1, ... (global index i0 + n S, S = waves in
+// the grid) as a software pipeline: descriptors arrive 64 at a time, one per
+// lane, and are read out as wave-uniform values; the sorted-order entries of
+// item n + 2 are loaded while item n is computed; the local rows of item n + 1
+// and every next receiver's global row are loaded right after the current
+// unit's activations are split, so the loads overlap the unit's MFMA work.
+template <bool SCALED>
+__device__ __forceinline__ void mlp_pairs_walk(const float *__restrict__ Lp, const float *__restrict__ Gp,
+                                               const half8 *s_w2h, const float4 *s_b2, const float4 *s_w3,
+                                               float b30, float b31, float sx,
+                                               const uint32_t *__restrict__ order, const int4 *__restrict__ items,
+                                               int nitems, int64_t Kp, int64_t K, float2 *__restrict__ rad)
+{
+    const int lane = threadIdx.x & 63, h = lane >> 5, pl = lane & 31;
+    const float isx = 1.f / sx;
+    const int S = gridDim.x * (BLOCK / 64);
+    const int i0 = blockIdx.x * (BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (i0 >= nitems) return;
+    const int nmine = (nitems - i0 + S - 1) / S;
+    // descriptors of items base .. base + 63 of this wave, one per lane
+    int base = 0;
+    const int4 zero4 = make_int4(0, 0, 0, 0);
+    int4 batch = lane < nmine ? items[i0 + lane * S] : zero4;
+    int4 dc = read_desc(batch, 0);
+    int4 dn = nmine > 1 ? read_desc(batch, 1) : dc;
+    // sorted positions s0 + pl exist for every item (s0 is a multiple of 32
+    // below the view's visible count and the sorted order has Kp >= that
+    // rounded up to 4096 entries); entries are clamped, stores check validity
+    uint32_t kA = order[(size_t)dn.x * Kp + dn.y + pl];
+    float l[32], g[32];
+    load_half_row(Lp, min((int64_t)order[(size_t)dc.x * Kp + dc.y + pl], K - 1), h, l);
+    load_half_row(Gp, (size_t)dc.z, h, g);
+    for (int n = 0; n < nmine; n++) {
+        int4 dnn = dn;
+        uint32_t kB = kA;
+        if (n + 2 < nmine) {
+            if (n + 2 - base >= 64) {
+                base = n + 2;
+                batch = base + lane < nmine ? items[i0 + (base + lane) * S] : zero4;
+            }
+            dnn = read_desc(batch, n + 2 - base);
+            kB = order[(size_t)dnn.x * Kp + dnn.y + pl];
+        }
+        const int nj = dc.w & 255;
+        const bool valid = pl < (dc.w >> 8);
+        const int64_t s = dc.y + pl;
+        const bool more = n + 1 < nmine;
+        for (int jj = 0; jj < nj; jj++) {
+            int z0 = 0;
+            asm volatile("" : "+v"(z0));
+            const float4 *b2h = s_b2 + h * 8 + z0;
+            const float4 *w3h = s_w3 + h * 16 + z0;
+            half8 bh[4], bl[4];
+#pragma unroll
+            for (int t = 0; t < 32; t++) {
+                float v = fmaxf(l[t] + g[t], 0.f);
+                if (SCALED) v *= sx;
+                const _Float16 hi = (_Float16)v;
+                bh[t >> 3][t & 7] = hi;
+                bl[t >> 3][t & 7] = (_Float16)(v - (float)hi);
+            }
+            const bool last = jj + 1 == nj;
+            if (last && more) load_half_row(Lp, min((int64_t)kA, K - 1), h, l);
+            load_half_row(Gp, (size_t)(last ? (more ? dn.z : dc.z) : dc.z + jj + 1), h, g);
+            floatx16 acc0, acc1;
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const float4 u = b2h[r], w = b2h[4 + r];
+                acc0[4 * r] = u.x; acc0[4 * r + 1] = u.y; acc0[4 * r + 2] = u.z; acc0[4 * r + 3] = u.w;
+                acc1[4 * r] = w.x; acc1[4 * r + 1] = w.y; acc1[4 * r + 2] = w.z; acc1[4 * r + 3] = w.w;
+            }
+            if (SCALED) {
+                acc0 *= sx;
+                acc1 *= sx;
+            }
+            // small cross terms first, then the leading product
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const half8 h0 = s_w2h[(0 * 4 + q) * 64 + lane + z0];
+                const half8 h1 = s_w2h[(1 * 4 + q) * 64 + lane + z0];
+                const half8 l0 = s_w2h[(2 * 4 + q) * 64 + lane + z0];
+                const half8 l1 = s_w2h[(3 * 4 + q) * 64 + lane + z0];
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(l0, bh[q], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(l1, bh[q], acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(h0, bl[q], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(h1, bl[q], acc1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const half8 h0 = s_w2h[(0 * 4 + q) * 64 + lane + z0];
+                const half8 h1 = s_w2h[(1 * 4 + q) * 64 + lane + z0];
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(h0, bh[q], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(h1, bh[q], acc1, 0, 0, 0);
+            }
+            float o0 = 0.f, o1 = 0.f;
+#pragma unroll
+            for (int r = 0; r < 8; r++) {
+                const float4 ta = w3h[r];       // W3 columns of acc0 registers 2r, 2r + 1
+                const float4 tb = w3h[8 + r];   // and of acc1
+                const float a0 = fmaxf(acc0[2 * r], 0.f), a1 = fmaxf(acc0[2 * r + 1], 0.f);
+                const float c0 = fmaxf(acc1[2 * r], 0.f), c1 = fmaxf(acc1[2 * r + 1], 0.f);
+                o0 = fmaf(ta.x, a0, o0);
+                o1 = fmaf(ta.y, a0, o1);
+                o0 = fmaf(ta.z, a1, o0);
+                o1 = fmaf(ta.w, a1, o1);
+                o0 = fmaf(tb.x, c0, o0);
+                o1 = fmaf(tb.y, c0, o1);
+                o0 = fmaf(tb.z, c1, o0);
+                o1 = fmaf(tb.w, c1, o1);
+            }
+            o0 += __shfl_xor(o0, 32);
+            o1 += __shfl_xor(o1, 32);
+            if (SCALED) {
+                o0 *= isx;
+                o1 *= isx;
+            }
+            if (h == 0 && valid) rad[(size_t)(dc.z + jj) * Kp + s] = make_float2(o0 + b30, o1 + b31);
+        }
+        dc = dn;
+        dn = dnn;
+        kA = kB;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_mlp_pairs(const float *__restrict__ Lp, const float *__restrict__ Gp,
+                                                     const half8 *__restrict__ w2h,
+                                                     const float4 *__restrict__ tab, const float *__restrict__ b3,
+                                                     const uint32_t *__restrict__ order,
+                                                     const int4 *__restrict__ items, int nitems, int64_t Kp,
+                                                     int64_t K, const unsigned long long *__restrict__ counters,
+                                                     const unsigned *__restrict__ amax, float2 *__restrict__ rad)
+{
+    // per lane half h: layer-2 bias of accumulator registers (acc0 r, acc1 r)
+    // as 8 float4, and layer-3 weights (W3[0][d], W3[1][d]) of register pairs
+    // as 16 float4
+    __shared__ float4 s_b2[2 * 8];
+    __shared__ float4 s_w3[2 * 16];
+    // split W2, [hi mb0, hi mb1, lo mb0, lo mb1][q][lane] as in w2h
+    __shared__ half8 s_w2h[16 * 64];
+    if (threadIdx.x < 64) {
+        const int hh = threadIdx.x >> 5, i = threadIdx.x & 31;   // (h, mb, r) = (hh, i / 16, i % 16)
+        const float4 e = tab[hh * 32 + i];
+        reinterpret_cast<float *>(s_b2)[hh * 32 + i] = e.z;
+        reinterpret_cast<float2 *>(s_w3)[hh * 32 + i] = make_float2(e.x, e.y);
+    }
+    for (int i = threadIdx.x; i < 16 * 64; i += BLOCK) s_w2h[i] = w2h[i];
+    __syncthreads();
+    const float b30 = b3[0], b31 = b3[1];
+    const int lane = threadIdx.x & 63;
+    // largest layer-1 term magnitudes, spread over 64 slots each
+    unsigned mb = max(amax[lane], amax[64 + lane]);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) mb = max(mb, (unsigned)__shfl_xor((int)mb, o));
+    const float bound = 2.f * __uint_as_float(mb);
+    if (bound < 32768.f) {
+        mlp_pairs_walk<false>(Lp, Gp, s_w2h, s_b2, s_w3, b30, b31, 1.f, order, items, nitems, Kp, K, rad);
+    } else {
+        int e = 0;
+        frexpf(bound, &e);   // bound < 2^e
+        const float sx = (e > 15 && e < 128) ? ldexpf(1.f, 15 - e) : 1.f;
+        mlp_pairs_walk<true>(Lp, Gp, s_w2h, s_b2, s_w3, b30, b31, sx, order, items, nitems, Kp, K, rad);
     }
 }
 
@@ -942,54 +1017,6 @@ hipError_t scan_exclusive_u32(DevBuf &scan_tmp, const uint32_t *in, uint32_t *ou
     return hipGetLastError();
 }
 
-int sort_items_for(uint32_t n) { return n <= SMALL_SORT ? 4 : 16; }
-
-size_t sort_hist_bytes(uint32_t n)
-{
-    const int it = sort_items_for(n);
-    return (size_t)((n + BLOCK * it - 1) / (BLOCK * it)) * 256 * 4;
-}
-
-// Sort n (key, value) pairs by the low `bits` bits of the key, stably.
-// seg_len > 0: independent segments of seg_len keys (a multiple of 4096);
-// segtab: independent segments given per 4096-key unit.
-template <int ITEMS>
-static hipError_t sort_passes(DevBuf *keys, DevBuf *vals, DevBuf &histb, DevBuf &scan_tmp, int &cur, uint32_t n,
-                              int bits, int64_t seg_len, const int4 *segtab, hipStream_t st)
-{
-    constexpr uint32_t TILEN = BLOCK * ITEMS;
-    const uint32_t nblocks = (n + TILEN - 1) / TILEN;
-    SegMap sm;
-    sm.seg_blocks = seg_len > 0 ? (uint32_t)(seg_len / TILEN) : 0u;
-    sm.tab = segtab;
-    sm.scale = SORT_TILE / TILEN;
-    const size_t nh = (size_t)nblocks * 256;
-    if (histb.cap < nh * 4) return hipErrorOutOfMemory;
-    uint32_t *hist = histb.as<uint32_t>();
-    for (int shift = 0; shift < bits; shift += 8) {
-        const uint32_t *kin = keys[cur].as<uint32_t>();
-        const uint32_t *vin = vals[cur].as<uint32_t>();
-        uint32_t *kout = keys[cur ^ 1].as<uint32_t>();
-        uint32_t *vout = vals[cur ^ 1].as<uint32_t>();
-        hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(nblocks), dim3(BLOCK), 0, st, kin, n, shift, hist, nblocks, sm);
-        hipError_t e = scan_exclusive_u32(scan_tmp, hist, hist, (uint32_t)nh, st);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(nblocks), dim3(BLOCK), 0, st, kin, vin, kout, vout, n, shift,
-                           hist, nblocks, sm);
-        cur ^= 1;
-    }
-    return hipGetLastError();
-}
-
-hipError_t sort_pairs_u32(Workspace &ws, DevBuf *keys, DevBuf *vals, DevBuf &histb, DevBuf &scan_tmp, int &cur,
-                          uint32_t n, int bits, int64_t seg_len, const int4 *segtab, hipStream_t st)
-{
-    (void)ws;
-    if (n == 0 || bits <= 0) return hipSuccess;
-    if (sort_items_for(n) == 4) return sort_passes<4>(keys, vals, histb, scan_tmp, cur, n, bits, seg_len, segtab, st);
-    return sort_passes<16>(keys, vals, histb, scan_tmp, cur, n, bits, seg_len, segtab, st);
-}
-
 hipError_t launch_gather(Workspace &ws, int V, int64_t Kp, hipStream_t st)
 {
     const int64_t total = (int64_t)V * Kp;
@@ -1014,8 +1041,8 @@ hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st)
     const size_t nr = (size_t)ws.V * g.tiles;
     if (g.tiles <= 255) {
         // one 8-bit pass: ranges straight from the scanned histogram
-        hipLaunchKernelGGL(k_ranges_hist, dim3(nblk(nr)), dim3(BLOCK), 0, st, ws.hist_b.as<uint32_t>(), ws.d_pbase,
-                           ws.d_pcount, ws.V, g.tiles, ws.pair_blk, ws.ranges.as<uint2>());
+        hipLaunchKernelGGL(k_ranges_hist, dim3((unsigned)ws.V), dim3(BLOCK), 0, st, ws.hist_b.as<uint32_t>(),
+                           ws.d_pbase, ws.d_pcount, g.tiles, ws.ranges.as<uint2>());
         return hipGetLastError();
     }
     hipError_t e = launch_fill_u32(ws.ranges.as<uint32_t>(), 0u, nr * 2, st);
@@ -1036,11 +1063,18 @@ hipError_t launch_rad_direct(const Scene &sc, Workspace &ws, hipStream_t st)
     return hipGetLastError();
 }
 
+// the activation-bound slots after the per-view counters: 64 for the
+// receivers' layer-1 terms, then 64 for the Gaussians'
+static unsigned *amax_words(Workspace &ws)
+{
+    return ws.counters.as<uint32_t>() + (size_t)4 * ws.V;
+}
+
 hipError_t launch_mlp_global(const Mlp &m, Workspace &ws, hipStream_t st)
 {
     if (ws.N > 0)
         hipLaunchKernelGGL(k_mlp_global, dim3(nblk((size_t)ws.N * HID)), dim3(BLOCK), 0, st, m.raw.as<float>(),
-                           ws.rxpos_p, ws.N, ws.Gp.as<float>());
+                           ws.rxpos_p, ws.N, ws.Gp.as<float>(), amax_words(ws));
     return hipGetLastError();
 }
 
@@ -1049,7 +1083,7 @@ hipError_t launch_mlp_local(const Scene &sc, const Mlp &m, Workspace &ws, hipStr
     const float *raw = m.raw.as<float>();
     if (sc.K > 0)
         hipLaunchKernelGGL(k_mlp_local, dim3((unsigned)((sc.K + 63) / 64)), dim3(BLOCK), 0, st, raw,
-                           raw + HID * MLP_IN, sc.feat.as<float>(), sc.K, ws.Lp.as<float>());
+                           raw + HID * MLP_IN, sc.feat.as<float>(), sc.K, ws.Lp.as<float>(), amax_words(ws) + 64);
     return hipGetLastError();
 }
 
@@ -1059,10 +1093,16 @@ hipError_t launch_mlp_pairs(const Mlp &m, Workspace &ws, hipStream_t st)
     const float *b3 = raw + HID * MLP_IN + HID + HID * HID + HID + 2 * HID;
     if (ws.n_items > 0) {
         const unsigned blocks = (unsigned)std::min((ws.n_items + 3) / 4, 256 * 8);
-        hipLaunchKernelGGL(k_mlp_pairs, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(), ws.Gp.as<float>(),
-                           m.w2a.as<float>(), m.tab.as<float4>(), b3, ws.sval[ws.sorted_buf].as<uint32_t>(),
-                           ws.d_items, ws.n_items, ws.Kp, ws.K, ws.counters.as<unsigned long long>(),
-                           ws.rad.as<float2>());
+        if (m.fp32)
+            hipLaunchKernelGGL(k_mlp_pairs_f32, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
+                               ws.Gp.as<float>(), m.w2a.as<float>(), m.tab.as<float4>(), b3,
+                               ws.sval[ws.sorted_buf].as<uint32_t>(), ws.d_items, ws.n_items, ws.Kp, ws.K,
+                               ws.counters.as<unsigned long long>(), ws.rad.as<float2>());
+        else
+            hipLaunchKernelGGL(k_mlp_pairs, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(), ws.Gp.as<float>(),
+                               m.w2h.as<half8>(), m.tabh.as<float4>(), b3, ws.sval[ws.sorted_buf].as<uint32_t>(),
+                               ws.d_items, ws.n_items, ws.Kp, ws.K, ws.counters.as<unsigned long long>(),
+                               amax_words(ws), ws.rad.as<float2>());
     }
     return hipGetLastError();
 }

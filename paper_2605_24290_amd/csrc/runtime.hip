@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 using namespace rxgs;
@@ -111,7 +112,7 @@ void free_workspace(Workspace &ws)
                       &ws.poff,    &ws.pkey[0], &ws.pkey[1], &ws.pval[0], &ws.pval[1], &ws.ranges, &ws.rad,
                       &ws.Lp,      &ws.Gp,      &ws.Tfin,   &ws.nlast,  &ws.part,
                       &ws.counters, &ws.hist,   &ws.scan_tmp, &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
-                      &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.hist_b,  &ws.scan_b};
+                      &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.hist_b};
     for (DevBuf *b : bufs) release(*b);
     if (ws.staged) (void)hipEventDestroy(ws.staged);
     if (ws.counted) (void)hipEventDestroy(ws.counted);
@@ -305,6 +306,8 @@ extern "C" void rxgs_destroy(rxgs_ctx *ctx)
     release(ctx->mlp.w2a);
     release(ctx->mlp.w2b);
     release(ctx->mlp.tab);
+    release(ctx->mlp.w2h);
+    release(ctx->mlp.tabh);
     release(ctx->stage);
     delete ctx;
 }
@@ -434,8 +437,43 @@ extern "C" rxgs_status rxgs_mlp_upload(rxgs_ctx *ctx, const float *params, int s
                 e[1] = W3[HID + d];
                 e[2] = b2[d];
             }
+    // split-FP16 copy of W2 for the forward pair kernel: W2 is scaled by an
+    // exact power of two so that its largest entry lands just under 2^15
+    // (FP16 range, and the low halves stay out of the subnormal range); the
+    // scale is undone exactly in the layer-2 bias and the layer-3 weights.
+    float wmax = 0.f;
+    for (int i = 0; i < HID * HID; i++) wmax = std::max(wmax, std::fabs(W2[i]));
+    int e = 0;
+    if (wmax > 0.f) std::frexp(wmax, &e);   // wmax < 2^e
+    const int wexp = std::min(std::max(15 - e, -60), 60);
+    std::vector<_Float16> w2h(2 * 2 * 4 * 64 * 8);
+    for (int mb = 0; mb < 2; mb++)
+        for (int q = 0; q < 4; q++)
+            for (int l = 0; l < 64; l++)
+                for (int i = 0; i < 8; i++) {
+                    const float w = std::ldexp(W2[(32 * mb + (l & 31)) * HID + hid_of(l >> 5, 8 * q + i)], wexp);
+                    const _Float16 hi = (_Float16)w;
+                    const _Float16 lo = (_Float16)(w - (float)hi);
+                    w2h[(((0 * 2 + mb) * 4 + q) * 64 + l) * 8 + i] = hi;
+                    w2h[(((1 * 2 + mb) * 4 + q) * 64 + l) * 8 + i] = lo;
+                }
+    std::vector<float> tabh(tab);
+    for (size_t i = 0; i < tabh.size(); i += 4) {
+        tabh[i] = std::ldexp(tab[i], -wexp);
+        tabh[i + 1] = std::ldexp(tab[i + 1], -wexp);
+        tabh[i + 2] = std::ldexp(tab[i + 2], wexp);
+    }
+    if (!all_finite_host(tabh.data(), tabh.size()))
+        return fail(ctx, RXGS_E_INVALID, "MLP parameters out of range for the split-FP16 layer 2");
     Mlp &m = ctx->mlp;
     m.valid = false;
+    const char *env = std::getenv("RXGS_MLP_FP32");
+    m.fp32 = env && env[0] == '1';
+    m.wexp = wexp;
+    GROW(ctx, m.w2h, sizeof(_Float16) * w2h.size());
+    GROW(ctx, m.tabh, sizeof(float) * tabh.size());
+    HIPCHK(ctx, hipMemcpy(m.w2h.p, w2h.data(), sizeof(_Float16) * w2h.size(), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(m.tabh.p, tabh.data(), sizeof(float) * tabh.size(), hipMemcpyHostToDevice));
     GROW(ctx, m.raw, sizeof(float) * RXGS_MLP_NPARAM);
     GROW(ctx, m.w2a, sizeof(float) * w2a.size());
     GROW(ctx, m.w2b, sizeof(float) * w2b.size());
@@ -521,10 +559,12 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     GROW(ctx, ws.srec, VK * 32);
     GROW(ctx, ws.ntl_s, VK * 4);
     GROW(ctx, ws.poff, VK * 4);
-    GROW(ctx, ws.counters, (size_t)2 * V * 8);
-    GROW(ctx, ws.hist, sort_hist_bytes((uint32_t)VK));
+    // per view (visible count, pair count), then slots for the largest
+    // |layer-1 term| of the receivers and of the Gaussians (FP32 bits)
+    GROW(ctx, ws.counters, (size_t)2 * V * 8 + 4 * AMAX_SLOTS);
+    GROW(ctx, ws.hist, sort_ws_bytes((uint32_t)VK, 32, V));
     // block sums of two scans: the sort histograms and the emission offsets
-    GROW(ctx, ws.scan_tmp, (std::max(VK / SORT_TILE, sort_hist_bytes((uint32_t)VK) / 4 / SORT_TILE) + 2) * 4);
+    GROW(ctx, ws.scan_tmp, (VK / SORT_TILE + 2) * 4);
 
     if (saved) {
         HIPCHK(ctx, hipMemcpyAsync(ws.centres.p, mode == RXGS_MODE_TX ? tx : rx, (size_t)V * 12,
@@ -536,7 +576,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         ws.centres_p = mode == RXGS_MODE_TX ? tx : rx;
         ws.rxpos_p = rx;
     }
-    HIPCHK(ctx, launch_fill_u32(ws.counters.as<uint32_t>(), 0u, (size_t)V * 4, st));
+    HIPCHK(ctx, launch_fill_u32(ws.counters.as<uint32_t>(), 0u, (size_t)V * 4 + AMAX_SLOTS, st));
 
     // stage 1: projection, then the per-view depth sort; the host waits only
     // for the counters (visible Gaussians per view, pair count) while the sort runs
@@ -546,7 +586,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     HIPCHK(ctx, hipMemcpyAsync(h_cnt, ws.counters.p, (size_t)2 * V * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(ctx, hipEventRecord(ws.counted, st));
     int cur = 0;
-    STAGE(ctx, "sort_depth", sort_pairs_u32(ws, ws.skey, ws.sval, ws.hist, ws.scan_tmp, cur, (uint32_t)VK, 32, Kp, nullptr, st));
+    STAGE(ctx, "sort_depth", sort_pairs_u32(ws.skey, ws.sval, ws.hist, cur, (uint32_t)VK, 32, V, Kp, nullptr, st));
     ws.sorted_buf = cur;
     STAGE(ctx, "gather", launch_gather(ws, V, Kp, st));
     STAGE(ctx, "scan", scan_exclusive_u32(ws.scan_tmp, ws.ntl_s.as<uint32_t>(), ws.poff.as<uint32_t>(), (uint32_t)VK, st));
@@ -594,10 +634,16 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
             const int tslot = (mode == RXGS_MODE_TX) ? (a == 0 ? v : -1) : js[a];
             chunks.push_back(make_int4(v, js[a], n, tslot));
         }
+        // MLP item (view, first sorted position, first receiver, receivers |
+        // valid positions << 8); the receivers of a view are consecutive
         if (ws.use_mlp)
-            for (int s0 = 0; s0 < ws.h_nvis[v]; s0 += MLP_PAIRS)
-                for (size_t a = 0; a < js.size(); a += MLP_RG)
-                    items.push_back(make_int4(v, s0, js[a], (int)std::min<size_t>(MLP_RG, js.size() - a)));
+            for (int s0 = 0; s0 < ws.h_nvis[v]; s0 += MLP_PAIRS) {
+                const int nvalid = std::min(MLP_PAIRS, ws.h_nvis[v] - s0);
+                for (size_t a = 0; a < js.size(); a += MLP_RG) {
+                    const int nj = (int)std::min<size_t>(MLP_RG, js.size() - a);
+                    items.push_back(make_int4(v, s0, js[a], nj | (nvalid << 8)));
+                }
+            }
     }
     ws.n_chunks = (int)chunks.size();
     ws.n_items = (int)items.size();
@@ -608,9 +654,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     GROW(ctx, ws.pkey[1], std::max<uint64_t>(Dpad, 1) * 4);
     GROW(ctx, ws.pval[0], std::max<uint64_t>(Dpad, 1) * 4);
     GROW(ctx, ws.pval[1], std::max<uint64_t>(Dpad, 1) * 4);
-    GROW(ctx, ws.hist_b, sort_hist_bytes((uint32_t)Dpad));
-    GROW(ctx, ws.scan_b, (sort_hist_bytes((uint32_t)Dpad) / 4 / SORT_TILE + 2) * 4);
-    ws.pair_blk = BLOCK * sort_items_for((uint32_t)Dpad);
+    GROW(ctx, ws.hist_b, sort_ws_bytes((uint32_t)Dpad, std::max(bits_for((uint64_t)g.tiles), 1), V));
     GROW(ctx, ws.ranges, (size_t)V * g.tiles * 8);
     GROW(ctx, ws.rad, (size_t)N * Kp * 8);
     GROW(ctx, ws.Tfin, (size_t)ws.n_tslots * P * 4);
@@ -655,8 +699,8 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     if (D > 0) {
         STAGE(ctx, "emit", launch_emit(ws, V, Kp, g, st));
         const int sbits = std::max(bits_for((uint64_t)g.tiles), 1);
-        STAGE(ctx, "sort_pairs", sort_pairs_u32(ws, ws.pkey, ws.pval, ws.hist_b, ws.scan_b, pcur, (uint32_t)Dpad, sbits,
-                                                0, ws.d_segtab, st));
+        STAGE(ctx, "sort_pairs", sort_pairs_u32(ws.pkey, ws.pval, ws.hist_b, pcur, (uint32_t)Dpad, sbits, V, 0,
+                                                ws.d_segtab, st));
     }
     ws.pairs_buf = pcur;
     STAGE(ctx, "ranges", launch_ranges(ws, g, st));

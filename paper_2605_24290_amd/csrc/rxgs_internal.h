@@ -23,6 +23,7 @@ constexpr int HID = 64;
 constexpr int MLP_IN = ENC + FEAT;
 constexpr int MLP_RG = 16;               // receivers per MLP work item
 constexpr int MLP_PAIRS = 32;            // sorted positions per MLP work item
+constexpr int AMAX_SLOTS = 128;          // activation-bound words after the view counters
 constexpr uint32_t SMALL_SCAN = 16384;   // scans up to this length run in one workgroup
 constexpr uint32_t SMALL_SORT = 1u << 20;  // sorts up to this length use 1024-key blocks
 
@@ -65,6 +66,13 @@ struct Mlp {
     DevBuf w2a;    // [2][32][64]  W2[32 mb + l % 32][hid_of(l / 32, t)]
     DevBuf w2b;    // [2][32][64]  W2[hid_of(l / 32, t)][32 ib + l % 32]
     DevBuf tab;    // [2 h][2 mb][16 r] float4 (W3[0][d], W3[1][d], b2[d], 0)
+    // split-FP16 forward: W2 * 2^wexp as FP16 (hi, lo) pairs in the MFMA
+    // 32x32x16 A-operand layout, [2 part][2 mb][4 q][64 lane] x 8 halves,
+    // element i = W2[32 mb + lane % 32][hid_of(lane / 32, 8 q + i)]
+    DevBuf w2h;
+    DevBuf tabh;   // as tab, with (W3 * 2^-wexp, b2 * 2^wexp)
+    int wexp = 0;
+    bool fp32 = false;   // RXGS_MLP_FP32=1: layer 2 on FP32 MFMA instead
 };
 
 struct Workspace {
@@ -101,7 +109,6 @@ struct Workspace {
     int4 *d_segtab = nullptr;      //   per 4096 pair slots: (first unit, units, view, 0) of its segment
     const float *centres_p = nullptr;  // view centres (the caller's or the saved copy)
     const float *rxpos_p = nullptr;    // receiver positions (the caller's or the saved copy)
-    int pair_blk = 4096;           // keys per block of the pair sort
     std::vector<uint32_t> h_pbase;    // V
     std::vector<uint32_t> h_pcount;   // V: pairs of each view
     DevBuf pkey[2];   // Dpad u32: local tile id, 0xFFFFFFFF for padding
@@ -115,10 +122,9 @@ struct Workspace {
     DevBuf nlast;     // S x H x W
     DevBuf part;      // N x tiles x 3
     DevBuf counters;  // u64 per view: [2 v] visible Gaussians, [2 v + 1] pairs
-    DevBuf hist;      // radix histograms (depth sort)
-    DevBuf scan_tmp;  // scan block sums (depth sort, emission offsets)
-    DevBuf hist_b;    // radix histograms (pair sort)
-    DevBuf scan_b;    // scan block sums (pair sort)
+    DevBuf hist;      // radix sort scratch (depth sort)
+    DevBuf scan_tmp;  // scan block sums (emission offsets)
+    DevBuf hist_b;    // radix sort scratch (pair sort); per-view tile counts at its start
     DevBuf nvis_d;    // V int
     // backward scratch
     DevBuf dS;        // N x Kp float2
@@ -189,8 +195,13 @@ namespace rxgs {
 hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t Kp, const DevGrid &g,
                           Workspace &ws, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st);
-hipError_t sort_pairs_u32(Workspace &ws, DevBuf *keys, DevBuf *vals, DevBuf &hist, DevBuf &scan_tmp, int &cur,
-                          uint32_t n, int bits, int64_t seg_len, const int4 *segtab, hipStream_t st);
+// sort.hip: stable segmented radix sort of (key, value) pairs by the low
+// `bits` key bits; segments of seg_len keys (a multiple of 4096), or given per
+// 4096-key unit by segtab; wsb holds sort_ws_bytes(n, bits, nseg) bytes and
+// keeps the per-segment digit totals at its start
+hipError_t sort_pairs_u32(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
+                          int64_t seg_len, const int4 *segtab, hipStream_t st);
+size_t sort_ws_bytes(uint32_t n, int bits, int nseg);
 hipError_t scan_exclusive_u32(DevBuf &scan_tmp, const uint32_t *in, uint32_t *out, uint32_t n, hipStream_t st);
 hipError_t launch_gather(Workspace &ws, int V, int64_t Kp, hipStream_t st);
 hipError_t launch_emit(Workspace &ws, int V, int64_t Kp, const DevGrid &g, hipStream_t st);
@@ -207,7 +218,6 @@ hipError_t launch_rad_bwd(const Scene &sc, Workspace &ws, float *grad, hipStream
 hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *gfeat, float *gmlp, hipStream_t st);
 hipError_t launch_project_bwd(const Scene &sc, Workspace &ws, const rxgs_grads &gr, hipStream_t st);
 size_t mlp_part_bytes(const Workspace &ws);
-size_t sort_hist_bytes(uint32_t n);
 int sort_items_for(uint32_t n);
 size_t w1b_part_bytes(int64_t K);
 

@@ -1,0 +1,255 @@
+// Stable segmented LSD radix sort of (u32 key, u32 value) pairs, one kernel
+// per 8-bit digit ("onesweep" organisation).
+//
+// The keys are split into independent segments (one per view: the per-view
+// depth sort, and the per-view padded pair lists).  One histogram kernel reads
+// every key once and counts all digits of all passes per segment.  Each pass
+// is then a single kernel: a workgroup takes the next 4096-key tile in order
+// from an atomic ticket, ranks its keys stably, publishes its per-digit counts
+// and obtains the counts of the earlier tiles of its segment by decoupled
+// look-back, and writes its keys digit run by digit run.  Ranking is wave
+// synchronous: each wave owns a contiguous quarter of the tile, takes its keys
+// 64 at a time in index order, matches equal digits with 8 ballots and keeps
+// running per-digit counts in LDS, so the only workgroup barriers are the ones
+// around the look-back and the LDS staging of the tile.
+//
+// Look-back progress: a workgroup only waits for tiles with a smaller ticket,
+// whose workgroups took their tickets earlier and are therefore resident; they
+// publish their aggregates before waiting themselves, so every wait ends.  A
+// wait is still bounded; on expiry the kernel records an error word instead
+// of hanging.
+#include "device_common.h"
+
+namespace rxgs {
+
+namespace {
+
+constexpr uint32_t LB_AGG = 1u << 30;    // status word: aggregate of this tile only
+constexpr uint32_t LB_PRE = 1u << 31;    // status word: inclusive prefix up to this tile
+constexpr uint32_t LB_MASK = LB_AGG - 1;
+constexpr int LB_SPIN_MAX = 1 << 20;
+
+struct SortSeg {
+    uint32_t seg_blocks;   // uniform segments of this many tiles (0: table or one segment)
+    const int4 *tab;       // per 4096-key unit: (first unit of its segment, units, segment id, 0)
+    uint32_t scale;        // tiles per 4096-key unit
+};
+
+__device__ __forceinline__ void tile_segment(uint32_t tile, const SortSeg &sm, uint32_t &seg, uint32_t &first)
+{
+    if (sm.tab) {
+        const int4 e = sm.tab[tile / sm.scale];
+        first = (uint32_t)e.x * sm.scale;
+        seg = (uint32_t)e.z;
+    } else if (sm.seg_blocks) {
+        seg = tile / sm.seg_blocks;
+        first = seg * sm.seg_blocks;
+    } else {
+        seg = 0;
+        first = 0;
+    }
+}
+
+// digit counts of every pass, per segment: hist[seg][pass][256]
+template <int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_sort_hist(const uint32_t *__restrict__ keys, uint32_t n, int passes,
+                                                     SortSeg sm, uint32_t *__restrict__ hist)
+{
+    constexpr int TILEN = BLOCK * ITEMS;
+    __shared__ uint32_t h[4][4][256];   // [pass][wave][digit]
+    const int t = threadIdx.x, w = t >> 6;
+#pragma unroll
+    for (int p = 0; p < 4; p++)
+#pragma unroll
+        for (int ww = 0; ww < 4; ww++) h[p][ww][t] = 0;
+    __syncthreads();
+    const size_t base = (size_t)blockIdx.x * TILEN;
+    uint32_t k[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+        const size_t idx = base + (size_t)i * BLOCK + t;
+        k[i] = idx < n ? keys[idx] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; i++) {
+        if (base + (size_t)i * BLOCK + t < n)
+            for (int p = 0; p < passes; p++) atomicAdd(&h[p][w][(k[i] >> (8 * p)) & 255u], 1u);
+    }
+    __syncthreads();
+    uint32_t seg, first;
+    tile_segment(blockIdx.x, sm, seg, first);
+    for (int p = 0; p < passes; p++) {
+        const uint32_t c = h[p][0][t] + h[p][1][t] + h[p][2][t] + h[p][3][t];
+        if (c) atomicAdd(&hist[((size_t)seg * passes + p) * 256 + t], c);
+    }
+}
+
+template <int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict__ kin,
+                                                     const uint32_t *__restrict__ vin,
+                                                     uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                     uint32_t n, int pass, int passes, SortSeg sm,
+                                                     const uint32_t *__restrict__ hist, uint32_t *status,
+                                                     uint32_t *ticket, uint32_t *err)
+{
+    constexpr int TILEN = BLOCK * ITEMS;
+    constexpr int WCH = 64 * ITEMS;   // keys per wave
+    __shared__ uint32_t s_key[TILEN];
+    __shared__ uint32_t s_val[TILEN];
+    __shared__ uint32_t s_wc[4][256];   // per-wave running digit counts, then per-wave digit starts
+    __shared__ uint32_t s_loc[256];     // tile-local start of each digit
+    __shared__ uint32_t s_glob[256];    // output start of each digit for this tile
+    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_tile;
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int shift = 8 * pass;
+    if (t == 0) s_tile = atomicAdd(ticket, 1u);
+#pragma unroll
+    for (int ww = 0; ww < 4; ww++) s_wc[ww][t] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const size_t base = (size_t)tile * TILEN + (size_t)w * WCH;
+
+    uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; r++) {
+        const size_t idx = base + (size_t)r * 64 + lane;
+        const bool valid = idx < n;
+        key[r] = valid ? kin[idx] : 0u;
+        val[r] = valid ? vin[idx] : 0u;
+    }
+    // stable rank inside the wave's chunk: the keys of one round are matched by
+    // digit; a digit's running count is read by all its lanes, then advanced by
+    // its lowest lane (LDS operations of one wave execute in program order)
+#pragma unroll
+    for (int r = 0; r < ITEMS; r++) {
+        const bool valid = base + (size_t)r * 64 + lane < n;
+        const uint32_t d = (key[r] >> shift) & 255u;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            const uint32_t bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        const uint32_t below = (uint32_t)count_below(m);
+        const uint32_t before = s_wc[w][d];
+        rank[r] = before + below;
+        if (valid && below == 0) s_wc[w][d] = before + (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    const uint32_t c0 = s_wc[0][t], c1 = s_wc[1][t], c2 = s_wc[2][t], c3 = s_wc[3][t];
+    const uint32_t cnt = c0 + c1 + c2 + c3;
+
+    // decoupled look-back over the earlier tiles of this segment, digit t
+    uint32_t seg, first;
+    tile_segment(tile, sm, seg, first);
+    uint32_t *mine = status + (size_t)tile * 256 + t;
+    uint32_t excl = 0;
+    if (tile == first) {
+        __hip_atomic_store(mine, LB_PRE | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        __hip_atomic_store(mine, LB_AGG | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t j = tile - 1;
+        while (true) {
+            const uint32_t *src = status + (size_t)j * 256 + t;
+            uint32_t sv = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int spin = 0; sv == 0 && spin < LB_SPIN_MAX; spin++) {
+                __builtin_amdgcn_s_sleep(1);
+                sv = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (sv == 0) {
+                atomicOr(err, 1u);
+                break;
+            }
+            excl += sv & LB_MASK;
+            if ((sv & LB_PRE) || j == first) break;
+            j--;
+        }
+        __hip_atomic_store(mine, LB_PRE | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+
+    // digit starts: in the segment (from the digit totals) and in the tile
+    uint32_t tot;
+    const uint32_t dbase = block_exclusive_scan(hist[((size_t)seg * passes + pass) * 256 + t], tot, s_w);
+    const uint32_t loc = block_exclusive_scan(cnt, tot, s_w);
+    s_glob[t] = first * (uint32_t)TILEN + dbase + excl;
+    s_loc[t] = loc;
+    s_wc[0][t] = loc;
+    s_wc[1][t] = loc + c0;
+    s_wc[2][t] = loc + c0 + c1;
+    s_wc[3][t] = loc + c0 + c1 + c2;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; r++) {
+        if (base + (size_t)r * 64 + lane < n) {
+            const uint32_t pos = s_wc[w][(key[r] >> shift) & 255u] + rank[r];
+            s_key[pos] = key[r];
+            s_val[pos] = val[r];
+        }
+    }
+    __syncthreads();
+    // write out digit run by digit run: consecutive slots go to consecutive addresses
+    const uint32_t tile_n = (uint32_t)min((size_t)TILEN, (size_t)n - (size_t)tile * TILEN);
+    for (uint32_t i = t; i < tile_n; i += BLOCK) {
+        const uint32_t k = s_key[i];
+        const uint32_t d = (k >> shift) & 255u;
+        const uint32_t o = s_glob[d] + (i - s_loc[d]);
+        if (o < n) {
+            kout[o] = k;
+            vout[o] = s_val[i];
+        }
+    }
+}
+
+template <int ITEMS>
+hipError_t sort_run(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
+                    int64_t seg_len, const int4 *segtab, hipStream_t st)
+{
+    constexpr uint32_t TILEN = BLOCK * ITEMS;
+    const uint32_t ntiles = (n + TILEN - 1) / TILEN;
+    const int passes = (bits + 7) / 8;
+    SortSeg sm;
+    sm.seg_blocks = seg_len > 0 ? (uint32_t)(seg_len / TILEN) : 0u;
+    sm.tab = segtab;
+    sm.scale = SORT_TILE / TILEN;
+    const size_t words = sort_ws_bytes(n, bits, nseg) / 4;
+    if (wsb.cap < words * 4) return hipErrorOutOfMemory;
+    uint32_t *hist = wsb.as<uint32_t>();
+    uint32_t *status = hist + (size_t)nseg * passes * 256;
+    uint32_t *tickets = status + (size_t)passes * ntiles * 256;
+    hipError_t e = launch_fill_u32(hist, 0u, words, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sort_hist<ITEMS>, dim3(ntiles), dim3(BLOCK), 0, st, keys[cur].as<uint32_t>(), n, passes, sm,
+                       hist);
+    for (int p = 0; p < passes; p++) {
+        hipLaunchKernelGGL(k_sort_pass<ITEMS>, dim3(ntiles), dim3(BLOCK), 0, st, keys[cur].as<uint32_t>(),
+                           vals[cur].as<uint32_t>(), keys[cur ^ 1].as<uint32_t>(), vals[cur ^ 1].as<uint32_t>(), n, p,
+                           passes, sm, hist, status + (size_t)p * ntiles * 256, tickets + p, tickets + 32);
+        cur ^= 1;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int sort_items_for(uint32_t n) { return n <= SMALL_SORT ? 4 : 16; }
+
+size_t sort_ws_bytes(uint32_t n, int bits, int nseg)
+{
+    const uint32_t tilen = BLOCK * (uint32_t)sort_items_for(n);
+    const size_t ntiles = (n + tilen - 1) / tilen;
+    const size_t passes = (size_t)(std::max(bits, 1) + 7) / 8;
+    return ((size_t)std::max(nseg, 1) * passes * 256 + passes * ntiles * 256 + 64) * 4;
+}
+
+hipError_t sort_pairs_u32(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
+                          int64_t seg_len, const int4 *segtab, hipStream_t st)
+{
+    if (n == 0 || bits <= 0) return hipSuccess;
+    if (bits > 32 || nseg <= 0) return hipErrorInvalidValue;
+    if (sort_items_for(n) == 4) return sort_run<4>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, st);
+    return sort_run<16>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, st);
+}
+
+}  // namespace rxgs
