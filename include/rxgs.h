@@ -111,6 +111,13 @@ rxgs_status rxgs_scene_upload(rxgs_ctx *ctx, int64_t K, const float *means, cons
  * 6 bands of App. E Table 4); hidden layers ReLU; output (Re, Im).
  * Layer 1 is evaluated as W1[:, :36] gamma(r_j) once per receiver plus
  * W1[:, 36:] f_k + b1 once per Gaussian (the global and local branches).
+ * Layer 2, per (receiver, Gaussian), runs on FP16 matrix cores in split
+ * precision (each FP32 operand as an FP16 (hi, lo) pair, three products
+ * accumulated in FP32; relative error near 2^-21 per product) after an exact
+ * power-of-two rescaling of W2 and, when the layer-1 activations exceed
+ * 2^15, of the activations.  If that rescaling cannot be exact for the given
+ * weights, or the environment variable RXGS_MLP_FP32=1 is set at upload,
+ * layer 2 runs on FP32 matrix cores instead.
  */
 rxgs_status rxgs_mlp_upload(rxgs_ctx *ctx, const float *params, int src_on_device, void *stream);
 

@@ -673,7 +673,7 @@ hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *g
     if (ws.n_items > 0)
         hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)(nwaves / 4)), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                            ws.Gp.as<float>(), m.w2a.as<float>(), m.w2b.as<float>(), m.tab.as<float4>(), W3,
-                           ws.sval[ws.sorted_buf].as<uint32_t>(), ws.d_items, ws.n_items, ws.Kp, sc.K,
+                           ws.sval[ws.sorted_buf].as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, sc.K,
                            ws.counters.as<unsigned long long>(), ws.dS.as<float2>(), ws.dL.as<float>(),
                            ws.dG.as<float>(), ws.mpart.as<float>());
     if (gmlp) {

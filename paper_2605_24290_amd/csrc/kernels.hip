@@ -461,9 +461,41 @@ __device__ __forceinline__ void block_absmax_to(float x, unsigned *slots)
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_mlp_global(const float *__restrict__ W1, const float *__restrict__ rx,
-                                                      int N, float *__restrict__ Gp, unsigned *__restrict__ amax)
+// MLP work item i from the per-view item offsets: view by binary search, then
+// (position block, receiver block) in position-major order within the view;
+// item = (view, s0, first receiver, receivers | valid positions << 8)
+__device__ __forceinline__ int4 make_item(int i, const uint32_t *__restrict__ item_off,
+                                          const int4 *__restrict__ vinfo, int V)
 {
+    int lo = 0, hi = V - 1;   // last view with item_off[v] <= i
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (item_off[mid] <= (uint32_t)i) lo = mid;
+        else hi = mid - 1;
+    }
+    const int4 vi = vinfo[lo];   // (first receiver, receivers, visible, 0)
+    const int q = i - (int)item_off[lo];
+    const int nrg = (vi.y + MLP_RG - 1) / MLP_RG;
+    const int sb = q / nrg, a = q - sb * nrg;
+    const int s0 = sb * MLP_PAIRS;
+    const int nvalid = min(MLP_PAIRS, vi.z - s0);
+    const int nj = min(MLP_RG, vi.y - a * MLP_RG);
+    return make_int4(lo, s0, vi.x + a * MLP_RG, nj | (nvalid << 8));
+}
+
+// Receiver ("global") term of layer 1, W1[:, :36] gamma(r_j), in hid_pos
+// order; the workgroups past the receivers' expand the MLP work items.
+__global__ __launch_bounds__(BLOCK) void k_mlp_global(const float *__restrict__ W1, const float *__restrict__ rx,
+                                                      int N, float *__restrict__ Gp, unsigned *__restrict__ amax,
+                                                      int nbg, const uint32_t *__restrict__ item_off,
+                                                      const int4 *__restrict__ vinfo, int V, int nitems,
+                                                      int4 *__restrict__ items)
+{
+    if ((int)blockIdx.x >= nbg) {
+        const int i = ((int)blockIdx.x - nbg) * BLOCK + threadIdx.x;
+        if (i < nitems) items[i] = make_item(i, item_off, vinfo, V);
+        return;
+    }
     const int idx = blockIdx.x * BLOCK + threadIdx.x;
     float acc = 0.f;
     if (idx < N * HID) {
@@ -1072,9 +1104,12 @@ static unsigned *amax_words(Workspace &ws)
 
 hipError_t launch_mlp_global(const Mlp &m, Workspace &ws, hipStream_t st)
 {
-    if (ws.N > 0)
-        hipLaunchKernelGGL(k_mlp_global, dim3(nblk((size_t)ws.N * HID)), dim3(BLOCK), 0, st, m.raw.as<float>(),
-                           ws.rxpos_p, ws.N, ws.Gp.as<float>(), amax_words(ws));
+    const unsigned nbg = (unsigned)nblk((size_t)ws.N * HID);
+    const unsigned nbi = (unsigned)nblk((size_t)ws.n_items);
+    if (nbg + nbi > 0)
+        hipLaunchKernelGGL(k_mlp_global, dim3(nbg + nbi), dim3(BLOCK), 0, st, m.raw.as<float>(), ws.rxpos_p, ws.N,
+                           ws.Gp.as<float>(), amax_words(ws), (int)nbg, ws.d_item_off, ws.d_vinfo, ws.V, ws.n_items,
+                           ws.items.as<int4>());
     return hipGetLastError();
 }
 
@@ -1096,12 +1131,12 @@ hipError_t launch_mlp_pairs(const Mlp &m, Workspace &ws, hipStream_t st)
         if (m.fp32)
             hipLaunchKernelGGL(k_mlp_pairs_f32, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                                ws.Gp.as<float>(), m.w2a.as<float>(), m.tab.as<float4>(), b3,
-                               ws.sval[ws.sorted_buf].as<uint32_t>(), ws.d_items, ws.n_items, ws.Kp, ws.K,
+                               ws.sval[ws.sorted_buf].as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K,
                                ws.counters.as<unsigned long long>(), ws.rad.as<float2>());
         else
             hipLaunchKernelGGL(k_mlp_pairs, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(), ws.Gp.as<float>(),
                                m.w2h.as<half8>(), m.tabh.as<float4>(), b3, ws.sval[ws.sorted_buf].as<uint32_t>(),
-                               ws.d_items, ws.n_items, ws.Kp, ws.K, ws.counters.as<unsigned long long>(),
+                               ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K, ws.counters.as<unsigned long long>(),
                                amax_words(ws), ws.rad.as<float2>());
     }
     return hipGetLastError();

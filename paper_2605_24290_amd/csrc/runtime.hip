@@ -3,6 +3,7 @@
 #include "device_common.h"
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -110,7 +111,7 @@ void free_workspace(Workspace &ws)
     DevBuf *bufs[] = {&ws.centres, &ws.rxpos,   &ws.desc,   &ws.rec,   &ws.ext,     &ws.rawkey, &ws.opac,
                       &ws.ntl,     &ws.skey[0], &ws.skey[1], &ws.sval[0], &ws.sval[1], &ws.srec, &ws.ntl_s,
                       &ws.poff,    &ws.pkey[0], &ws.pkey[1], &ws.pval[0], &ws.pval[1], &ws.ranges, &ws.rad,
-                      &ws.Lp,      &ws.Gp,      &ws.Tfin,   &ws.nlast,  &ws.part,
+                      &ws.Lp,      &ws.Gp,      &ws.items,  &ws.Tfin,   &ws.nlast,  &ws.part,
                       &ws.counters, &ws.hist,   &ws.scan_tmp, &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
                       &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.hist_b};
     for (DevBuf *b : bufs) release(*b);
@@ -445,7 +446,7 @@ extern "C" rxgs_status rxgs_mlp_upload(rxgs_ctx *ctx, const float *params, int s
     for (int i = 0; i < HID * HID; i++) wmax = std::max(wmax, std::fabs(W2[i]));
     int e = 0;
     if (wmax > 0.f) std::frexp(wmax, &e);   // wmax < 2^e
-    const int wexp = std::min(std::max(15 - e, -60), 60);
+    const int wexp = std::min(std::max(15 - e, -120), 120);
     std::vector<_Float16> w2h(2 * 2 * 4 * 64 * 8);
     for (int mb = 0; mb < 2; mb++)
         for (int q = 0; q < 4; q++)
@@ -457,18 +458,21 @@ extern "C" rxgs_status rxgs_mlp_upload(rxgs_ctx *ctx, const float *params, int s
                     w2h[(((0 * 2 + mb) * 4 + q) * 64 + l) * 8 + i] = hi;
                     w2h[(((1 * 2 + mb) * 4 + q) * 64 + l) * 8 + i] = lo;
                 }
+    // the rescaled layer-2 bias and layer-3 weights must stay finite and
+    // normal (an exact rescaling); otherwise layer 2 runs on FP32 MFMA
     std::vector<float> tabh(tab);
+    bool exact = true;
     for (size_t i = 0; i < tabh.size(); i += 4) {
-        tabh[i] = std::ldexp(tab[i], -wexp);
-        tabh[i + 1] = std::ldexp(tab[i + 1], -wexp);
-        tabh[i + 2] = std::ldexp(tab[i + 2], wexp);
+        for (int c = 0; c < 3; c++) {
+            const float x = std::ldexp(tab[i + c], c < 2 ? -wexp : wexp);
+            if (!std::isfinite(x) || (tab[i + c] != 0.f && std::fabs(x) < FLT_MIN)) exact = false;
+            tabh[i + c] = x;
+        }
     }
-    if (!all_finite_host(tabh.data(), tabh.size()))
-        return fail(ctx, RXGS_E_INVALID, "MLP parameters out of range for the split-FP16 layer 2");
     Mlp &m = ctx->mlp;
     m.valid = false;
     const char *env = std::getenv("RXGS_MLP_FP32");
-    m.fp32 = env && env[0] == '1';
+    m.fp32 = !exact || (env && env[0] == '1');
     m.wexp = wexp;
     GROW(ctx, m.w2h, sizeof(_Float16) * w2h.size());
     GROW(ctx, m.tabh, sizeof(float) * tabh.size());
@@ -590,6 +594,30 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     ws.sorted_buf = cur;
     STAGE(ctx, "gather", launch_gather(ws, V, Kp, st));
     STAGE(ctx, "scan", scan_exclusive_u32(ws.scan_tmp, ws.ntl_s.as<uint32_t>(), ws.poff.as<uint32_t>(), (uint32_t)VK, st));
+
+    // receiver chunks of the blend (independent of the counters: built while
+    // the GPU projects and sorts); the receivers of a view are consecutive
+    std::vector<int> vfirst(V, 0), vnrx(V, 0);
+    for (int j = N - 1; j >= 0; j--) {
+        vfirst[rxview[j]] = j;
+        vnrx[rxview[j]]++;
+    }
+    int maxr = 1;
+    for (int v = 0; v < V; v++) maxr = std::max(maxr, vnrx[v]);
+    int R = 1;
+    if (mode == RXGS_MODE_TX)
+        while (R < 16 && R < maxr) R *= 2;
+    ws.R = R;
+    std::vector<int4> chunks;
+    for (int v = 0; v < V; v++)
+        for (int a = 0; a < vnrx[v]; a += R) {
+            const int j = vfirst[v] + a;
+            const int tslot = (mode == RXGS_MODE_TX) ? (a == 0 ? v : -1) : j;
+            chunks.push_back(make_int4(v, j, std::min(R, vnrx[v] - a), tslot));
+        }
+    ws.n_chunks = (int)chunks.size();
+    ws.n_tslots = (mode == RXGS_MODE_TX) ? V : N;
+
     HIPCHK(ctx, hipEventSynchronize(ws.counted));
 
     // pairs per view; each view's pairs get a segment padded to whole sort blocks
@@ -617,37 +645,20 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         ws.nvis_total += ws.h_nvis[v];
     }
 
-    // receiver chunks of the blend and work items of the MLP
-    std::vector<std::vector<int>> vrx(V);
-    for (int j = 0; j < N; j++) vrx[rxview[j]].push_back(j);
-    int maxr = 1;
-    for (int v = 0; v < V; v++) maxr = std::max<int>(maxr, (int)vrx[v].size());
-    int R = 1;
-    if (mode == RXGS_MODE_TX)
-        while (R < 16 && R < maxr) R *= 2;
-    ws.R = R;
-    std::vector<int4> chunks, items;
+    // MLP work items, per view: (32 sorted positions) x (16 receivers),
+    // position-major; only their per-view offsets are built here, the items
+    // themselves on the device
+    std::vector<uint32_t> item_off(V + 1, 0);
+    std::vector<int4> vinfo(V);   // (first receiver, receivers, visible, 0)
     for (int v = 0; v < V; v++) {
-        const auto &js = vrx[v];
-        for (size_t a = 0; a < js.size(); a += R) {
-            const int n = (int)std::min<size_t>(R, js.size() - a);
-            const int tslot = (mode == RXGS_MODE_TX) ? (a == 0 ? v : -1) : js[a];
-            chunks.push_back(make_int4(v, js[a], n, tslot));
-        }
-        // MLP item (view, first sorted position, first receiver, receivers |
-        // valid positions << 8); the receivers of a view are consecutive
-        if (ws.use_mlp)
-            for (int s0 = 0; s0 < ws.h_nvis[v]; s0 += MLP_PAIRS) {
-                const int nvalid = std::min(MLP_PAIRS, ws.h_nvis[v] - s0);
-                for (size_t a = 0; a < js.size(); a += MLP_RG) {
-                    const int nj = (int)std::min<size_t>(MLP_RG, js.size() - a);
-                    items.push_back(make_int4(v, s0, js[a], nj | (nvalid << 8)));
-                }
-            }
+        const int64_t ni = ws.use_mlp ? (int64_t)((ws.h_nvis[v] + MLP_PAIRS - 1) / MLP_PAIRS) *
+                                            ((vnrx[v] + MLP_RG - 1) / MLP_RG)
+                                      : 0;
+        if ((int64_t)item_off[v] + ni >= (1ll << 31)) return fail(ctx, RXGS_E_INVALID, "too many MLP work items");
+        item_off[v + 1] = item_off[v] + (uint32_t)ni;
+        vinfo[v] = make_int4(vfirst[v], vnrx[v], ws.h_nvis[v], 0);
     }
-    ws.n_chunks = (int)chunks.size();
-    ws.n_items = (int)items.size();
-    ws.n_tslots = (mode == RXGS_MODE_TX) ? V : N;
+    ws.n_items = (int)item_off[V];
 
     const size_t P = (size_t)g.H * g.W;
     GROW(ctx, ws.pkey[0], std::max<uint64_t>(Dpad, 1) * 4);
@@ -663,13 +674,15 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     if (ws.use_mlp) {
         GROW(ctx, ws.Lp, (size_t)std::max<int64_t>(K, 1) * HID * 4);
         GROW(ctx, ws.Gp, (size_t)N * HID * 4);
+        GROW(ctx, ws.items, (size_t)std::max(ws.n_items, 1) * 16);
     }
 
     // the small descriptors, packed (16-byte aligned parts) into one host-to-device copy
     auto al16 = [](size_t b) { return (b + 15) / 16 * 16; };
     const size_t o_chunks = al16((size_t)N * 4);
-    const size_t o_items = o_chunks + chunks.size() * 16;
-    const size_t o_pbase = o_items + items.size() * 16;
+    const size_t o_vinfo = o_chunks + chunks.size() * 16;
+    const size_t o_ioff = o_vinfo + (size_t)V * 16;
+    const size_t o_pbase = o_ioff + al16((size_t)(V + 1) * 4);
     const size_t o_pcount = o_pbase + al16((size_t)V * 4);
     const size_t o_segtab = o_pcount + al16((size_t)V * 4);
     const size_t stage_bytes = o_segtab + segtab.size() * 16;
@@ -680,14 +693,16 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     char *hp = static_cast<char *>(ws.h_pinned) + off0;
     std::memcpy(hp, rxview.data(), (size_t)N * 4);
     std::memcpy(hp + o_chunks, chunks.data(), chunks.size() * 16);
-    std::memcpy(hp + o_items, items.data(), items.size() * 16);
+    std::memcpy(hp + o_vinfo, vinfo.data(), (size_t)V * 16);
+    std::memcpy(hp + o_ioff, item_off.data(), (size_t)(V + 1) * 4);
     std::memcpy(hp + o_pbase, ws.h_pbase.data(), (size_t)V * 4);
     std::memcpy(hp + o_pcount, ws.h_pcount.data(), (size_t)V * 4);
     std::memcpy(hp + o_segtab, segtab.data(), segtab.size() * 16);
     char *dd = ws.desc.as<char>();
     ws.d_rxview = reinterpret_cast<int *>(dd);
     ws.d_chunks = reinterpret_cast<int4 *>(dd + o_chunks);
-    ws.d_items = reinterpret_cast<int4 *>(dd + o_items);
+    ws.d_vinfo = reinterpret_cast<int4 *>(dd + o_vinfo);
+    ws.d_item_off = reinterpret_cast<uint32_t *>(dd + o_ioff);
     ws.d_pbase = reinterpret_cast<uint32_t *>(dd + o_pbase);
     ws.d_pcount = reinterpret_cast<uint32_t *>(dd + o_pcount);
     ws.d_segtab = reinterpret_cast<int4 *>(dd + o_segtab);

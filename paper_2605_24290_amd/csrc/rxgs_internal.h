@@ -72,7 +72,8 @@ struct Mlp {
     DevBuf w2h;
     DevBuf tabh;   // as tab, with (W3 * 2^-wexp, b2 * 2^wexp)
     int wexp = 0;
-    bool fp32 = false;   // RXGS_MLP_FP32=1: layer 2 on FP32 MFMA instead
+    bool fp32 = false;   // layer 2 on FP32 MFMA instead: RXGS_MLP_FP32=1, or the
+                         // rescaled tables would not be exact
 };
 
 struct Workspace {
@@ -103,7 +104,8 @@ struct Workspace {
     DevBuf desc;      // small descriptors copied from the host in one transfer:
     int *d_rxview = nullptr;       //   N: view of each receiver
     int4 *d_chunks = nullptr;      //   blend chunks (view, first receiver, receivers, T slot)
-    int4 *d_items = nullptr;       //   MLP work items (view, first position, first receiver, receivers)
+    int4 *d_vinfo = nullptr;       //   V: (first receiver, receivers, visible Gaussians, 0)
+    uint32_t *d_item_off = nullptr;  // V + 1: first MLP work item of each view
     uint32_t *d_pbase = nullptr;   //   V: start of each view's segment of the pair arrays
     uint32_t *d_pcount = nullptr;  //   V: pairs of each view
     int4 *d_segtab = nullptr;      //   per 4096 pair slots: (first unit, units, view, 0) of its segment
@@ -118,6 +120,7 @@ struct Workspace {
     DevBuf rad;       // N x Kp float2
     DevBuf Lp;        // K x 64
     DevBuf Gp;        // N x 64
+    DevBuf items;     // MLP work items (view, s0, first receiver, receivers | valid positions << 8)
     DevBuf Tfin;      // S x H x W
     DevBuf nlast;     // S x H x W
     DevBuf part;      // N x tiles x 3

@@ -126,6 +126,43 @@ def test_mlp_forward_parity_small(mode):
     r.close()
 
 
+@pytest.mark.parametrize("case", ["large_activations", "tiny_w2", "tx_ragged_receivers"])
+def test_mlp_radiance_ranges_and_items(case):
+    """Split-FP16 layer 2 against the FP64 oracle MLP outside the usual ranges:
+    layer-1 activations beyond the FP16 range (scaled path), a W2 near the FP32
+    subnormal range (per-upload W2 scale), and 37 receivers of one view (three
+    receiver blocks per work item, the last one ragged)."""
+    from paper_2605_24290_amd import rxgs
+    N = 37 if case == "tx_ragged_receivers" else 6
+    wl = _wl("c1", K=2500, N=N)
+    if case == "large_activations":
+        wl.mlp[0] = wl.mlp[0] * np.float32(2.0 ** 16)
+    elif case == "tiny_w2":
+        wl.mlp[2] = wl.mlp[2] * np.float32(2.0 ** -100)
+        wl.mlp[3] = wl.mlp[3] + np.float32(2.0 ** -101)
+    mode = "tx" if case == "tx_ragged_receivers" else "rx"
+    r = renderer_for(wl)
+    saved = rxgs.Saved(r)
+    _render(r, wl, mode, saved=saved)
+    info = saved.info()
+    rad = saved.export(rxgs.EXPORT_RADIANCE, np.float32, (info["N"], info["K_pad"], 2))
+    order = saved.export(rxgs.EXPORT_ORDER, np.int32, (info["V"], info["K_pad"]))
+    nvis = saved.export(rxgs.EXPORT_NVIS, np.int32, (info["V"],))
+    ref = O.radiance(wl.scene, wl.rx, mlp=wl.mlp)
+    worst = 0.0
+    for j in range(info["N"]):
+        v = 0 if mode == "tx" else j
+        ks = order[v, :nvis[v]]
+        got = rad[j, :nvis[v]].astype(np.float64)
+        exp = ref[j, ks]
+        scale = max(np.abs(exp).max(), 1e-300)
+        worst = max(worst, float(np.abs(got - exp).max() / scale))
+    print(f"[mlp] {case}: worst radiance error {worst:.3e} of the largest value")
+    assert worst <= 1e-5
+    saved.close()
+    r.close()
+
+
 def test_several_transmitters_uneven_receivers():
     """Three transmitters with 3, 0 and 5 receivers in one launch (TX mode)."""
     wl = _wl("c1", K=2000, N=8, Q=3, grid=GRID_SMALL)
