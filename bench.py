@@ -26,11 +26,21 @@ import time
 
 METRIC = "receiver-views/s (90x360 grid) multi-rx fused vs per-rx loop; serve p50/p99"
 
-# MI355X published peaks
+# MI355X published peaks and the derived vector-ALU rate
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
-PEAK_FP32_VALU_TFLOPS = 157.3
+PEAK_FP16_MFMA_TFLOPS = 2500.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane operations per second
+# (one FP32 op per lane per cycle; an FMA counts as one operation here)
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 MLP_FLOP_PER_PAIR = 2 * 64 * 64 + 2 * 64 * 2     # layers 2 and 3 per (receiver, visible Gaussian)
+MLP_MFMA_FLOP_PER_PAIR = 3 * 2 * 64 * 64         # split FP16: three FP16 products for layer 2
+BLEND_OPS_PER_PAIR = 16      # lane-ops per composited (pixel, Gaussian) pair: offsets, quadratic form,
+                             # exp (4), clamp and test, transmittance update, one complex accumulate
+BLEND_OPS_PER_EXTRA_RX = 2   # TX mode: each further receiver sharing the weight adds one complex FMA
+SORT_BYTES_PER_KEY_PASS = 16  # read and write one (u32 key, u32 value) per pass
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "k_blend_fwd_c1_rx_traffic.txt")
 
 
 def parse():
@@ -49,6 +59,8 @@ def parse():
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-queries", type=int, default=400)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain copy of this many MiB (counter calibration for profiled runs)")
     return ap.parse_args()
 
 
@@ -116,8 +128,11 @@ def gpu_part(args):
         info = saved.info()
         nvis = saved.export(rxgs.EXPORT_NVIS, "int32", (info["V"],))
         pairs_mlp = int(nvis.sum()) if mode == "rx" else int(nvis[0]) * N
+        rpc = 1 if mode == "rx" else min(16, 1 << max(0, (N - 1).bit_length()))
         entry["sizes"] = {"views": info["V"], "visible_total": int(nvis.sum()), "tile_pairs": info["D"],
-                          "mlp_pairs": pairs_mlp}
+                          "mlp_pairs": pairs_mlp, "sort_keys": info["V"] * info["K_pad"],
+                          "composited": info["n_composited"], "composited_px": info["n_composited_px"],
+                          "chunks_per_view": 1 if mode == "rx" else -(-N // rpc)}
         saved.close()
         if not args.no_loop:
             ms_loop = timed(loop(mode), args.loop_steps, 1)
@@ -195,20 +210,81 @@ def serving_part(args):
             "rates_x_saturation": rates, "server_stats": st}
 
 
-def roofline_for(entry):
-    """Roofline entry for the stage with the largest time share."""
+def source_digest() -> str:
+    """SHA-256 of the HIP sources, to tell whether stored counter readings
+    still describe the kernels that were just timed."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2605_24290_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, scaled by the copy-kernel calibration it records; None
+    if there is none for this kernel and workload or the sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel") != kernel or kv.get("workload") != workload or kv.get("source_sha256") != source_digest():
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def roofline_for(entry, mode, workload):
+    """Roofline entry of the stage with the largest time share; the time is the
+    stage's average from HIP events the library records on the launch stream."""
     st = entry["stages_ms_per_step"]
     top = max(st, key=st.get)
     t_s = st[top] / 1000.0
     sz = entry["sizes"]
+    if top == "blend_fwd":
+        if mode == "rx":
+            ops = BLEND_OPS_PER_PAIR * sz["composited"]
+        else:   # weights once per view pixel, one complex FMA per further receiver
+            per_view = sz["composited_px"] / max(sz["chunks_per_view"], 1)
+            ops = BLEND_OPS_PER_PAIR * per_view + BLEND_OPS_PER_EXTRA_RX * (sz["composited"] - per_view)
+        ach = ops / t_s / 1e12
+        return {"kernel": "k_blend_fwd", "bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS,
+                "unit": "Tops/s", "frac": ach / PEAK_VALU_TOPS,
+                "traffic": stored_traffic("k_blend_fwd", workload),
+                "work": f"{BLEND_OPS_PER_PAIR} lane-ops x {sz['composited']} composited (pixel, Gaussian) pairs"}
     if top == "mlp_pairs":
-        flop = MLP_FLOP_PER_PAIR * sz["mlp_pairs"]
+        flop = MLP_MFMA_FLOP_PER_PAIR * sz["mlp_pairs"]
         ach = flop / t_s / 1e12
-        return {"kernel": "k_mlp_pairs", "bound": "mfma", "achieved": ach, "peak": PEAK_FP32_MFMA_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA_TFLOPS, "traffic": None,
-                "work": f"{MLP_FLOP_PER_PAIR} FLOP x {sz['mlp_pairs']} (receiver, visible Gaussian) pairs"}
+        return {"kernel": "k_mlp_pairs", "bound": "mfma", "achieved": ach, "peak": PEAK_FP16_MFMA_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP16_MFMA_TFLOPS, "traffic": None,
+                "work": f"{MLP_MFMA_FLOP_PER_PAIR} FP16 MFMA FLOP x {sz['mlp_pairs']} (receiver, visible Gaussian) "
+                        f"pairs ({MLP_FLOP_PER_PAIR} FP32-equivalent)"}
+    if top == "sort_depth":
+        byts = (4 + 4 * SORT_BYTES_PER_KEY_PASS) * sz["sort_keys"]
+        ach = byts / t_s / 1e9
+        return {"kernel": "radix sort (histogram + 4 passes)", "bound": "hbm", "achieved": ach,
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": None,
+                "work": f"68 B x {sz['sort_keys']} keys"}
     return {"kernel": top, "bound": "unknown", "achieved": None, "peak": None, "unit": None, "frac": None,
             "traffic": None}
+
+
+def copy_calibration(mib: int):
+    """A plain elementwise copy of known size (read mib MiB, write mib MiB),
+    for scaling the FETCH_SIZE / WRITE_SIZE counters of a profiled run."""
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(f"copy calibration: {n * 4} bytes read and written per launch", flush=True)
 
 
 def cpu_baseline(args, wl, mode):
@@ -239,8 +315,11 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the receiver-sharded "
               "multi-GPU layout is a design note, not a measured path", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
     wl, res = gpu_part(args)
     head = res[args.mode]
+    workload = f"{args.config} {args.mode.upper()}"
     out = {
         "metric": METRIC,
         "value": head["rx_views_per_s"],
@@ -260,7 +339,7 @@ def main():
                    "mode": args.mode},
         "fused": head,
         "other_modes": {k: v for k, v in res.items() if k != args.mode},
-        "roofline": roofline_for(head),
+        "roofline": roofline_for(head, args.mode, workload),
     }
     if not args.no_train:
         out["train_step"] = train_step_part(args)

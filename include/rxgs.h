@@ -191,6 +191,10 @@ typedef struct {
     int64_t n_visible;  /* sum over views of Gaussians with a non-empty tile set */
     int64_t tiles;      /* tiles per view */
     int64_t tiles_x;    /* tile columns */
+    int64_t n_composited_px;  /* (pixel, Gaussian) weights composited, counted once per
+                                 receiver chunk that shares them (TX mode: up to 16
+                                 receivers of a view share one weight evaluation) */
+    int64_t n_composited;     /* the same counted once per receiver */
 } rxgs_saved_info_t;
 
 rxgs_status rxgs_saved_info(const rxgs_saved *s, rxgs_saved_info_t *out);

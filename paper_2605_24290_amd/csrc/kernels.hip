@@ -841,7 +841,8 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
                                                      const float2 *__restrict__ rad,
                                                      const int4 *__restrict__ chunks, int64_t Kp, DevGrid g,
                                                      float *__restrict__ C, float *__restrict__ Tfin,
-                                                     int *__restrict__ nlast, float *__restrict__ part)
+                                                     int *__restrict__ nlast, float *__restrict__ part,
+                                                     unsigned long long *__restrict__ stats)
 {
     __shared__ BlendStage st;
     __shared__ float2 s_rad[R][BLOCK];
@@ -864,6 +865,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
 #pragma unroll
     for (int r = 0; r < R; r++) acc[r] = make_float2(0.f, 0.f);
     int last = 0;
+    uint32_t ncomp = 0;   // composited entries of this pixel
     bool done = !inside;
 
     for (uint32_t base = rg.x; base < rg.y; base += BLOCK) {
@@ -901,6 +903,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
                 }
                 T = T * (1.f - w);
                 last = (int)(base - rg.x) + e + 1;
+                ncomp++;
                 if (T < T_EPS) {
                     done = true;
                     break;
@@ -937,12 +940,25 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
             s_red[wv][r][2] = si;
         }
     }
+    const uint32_t nc = wave_sum_u32(ncomp);
+    if (lane == 0) st.wcnt[0][wv] = nc;
     __syncthreads();
     if (t < R * 3) {
         const int r = t / 3, c = t % 3;
         if (r < nrx) {
             const float v = ((s_red[0][r][c] + s_red[1][r][c]) + s_red[2][r][c]) + s_red[3][r][c];
             part[((size_t)(j0 + r) * g.tiles + tile) * 3 + c] = v;
+        }
+    }
+    // composited (pixel, entry) pairs: per chunk pixel and per receiver pixel,
+    // spread over STAT_SLOTS counters
+    if (t == 0) {
+        const unsigned long long n = (unsigned long long)st.wcnt[0][0] + st.wcnt[0][1] + st.wcnt[0][2] +
+                                     st.wcnt[0][3];
+        if (n) {
+            const unsigned slot = (blockIdx.x + blockIdx.y * gridDim.x) % STAT_SLOTS;
+            atomicAdd(stats + slot, n);
+            atomicAdd(stats + STAT_SLOTS + slot, n * (unsigned long long)nrx);
         }
     }
 }
@@ -1095,6 +1111,13 @@ hipError_t launch_rad_direct(const Scene &sc, Workspace &ws, hipStream_t st)
     return hipGetLastError();
 }
 
+// render statistics after the activation-bound slots: STAT_SLOTS u64 of
+// composited pairs per chunk pixel, then STAT_SLOTS per receiver pixel
+unsigned long long *stat_words(Workspace &ws)
+{
+    return ws.counters.as<unsigned long long>() + (size_t)2 * ws.V + AMAX_SLOTS / 2;
+}
+
 // the activation-bound slots after the per-view counters: 64 for the
 // receivers' layer-1 terms, then 64 for the Gaussians'
 static unsigned *amax_words(Workspace &ws)
@@ -1149,7 +1172,7 @@ static void blend_launch(Workspace &ws, float *C, hipStream_t st)
     hipLaunchKernelGGL(k_blend_fwd<R>, grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                        ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                        ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
-                       ws.part.as<float>());
+                       ws.part.as<float>(), stat_words(ws));
 }
 
 hipError_t launch_blend_fwd(Workspace &ws, float *C, hipStream_t st)

@@ -565,7 +565,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     GROW(ctx, ws.poff, VK * 4);
     // per view (visible count, pair count), then slots for the largest
     // |layer-1 term| of the receivers and of the Gaussians (FP32 bits)
-    GROW(ctx, ws.counters, (size_t)2 * V * 8 + 4 * AMAX_SLOTS);
+    GROW(ctx, ws.counters, (size_t)2 * V * 8 + 4 * AMAX_SLOTS + 2 * STAT_SLOTS * 8);
     GROW(ctx, ws.hist, sort_ws_bytes((uint32_t)VK, 32, V));
     // block sums of two scans: the sort histograms and the emission offsets
     GROW(ctx, ws.scan_tmp, (VK / SORT_TILE + 2) * 4);
@@ -580,7 +580,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         ws.centres_p = mode == RXGS_MODE_TX ? tx : rx;
         ws.rxpos_p = rx;
     }
-    HIPCHK(ctx, launch_fill_u32(ws.counters.as<uint32_t>(), 0u, (size_t)V * 4 + AMAX_SLOTS, st));
+    HIPCHK(ctx, launch_fill_u32(ws.counters.as<uint32_t>(), 0u, (size_t)V * 4 + AMAX_SLOTS + 4 * STAT_SLOTS, st));
 
     // stage 1: projection, then the per-view depth sort; the host waits only
     // for the counters (visible Gaussians per view, pair count) while the sort runs
@@ -805,6 +805,18 @@ extern "C" rxgs_status rxgs_saved_info(const rxgs_saved *s, rxgs_saved_info_t *o
     out->n_visible = ws.nvis_total;
     out->tiles = ws.g.tiles;
     out->tiles_x = ws.g.tiles_x;
+    // composited-pair statistics of the forward: wait for it, then sum the slots
+    DeviceScope dsc(s->ctx->device);
+    if (hipDeviceSynchronize() != hipSuccess) return RXGS_E_DEVICE;
+    std::vector<unsigned long long> h(2 * STAT_SLOTS);
+    Workspace &w = const_cast<Workspace &>(ws);
+    if (hipMemcpy(h.data(), stat_words(w), h.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) return RXGS_E_DEVICE;
+    out->n_composited_px = 0;
+    out->n_composited = 0;
+    for (int i = 0; i < STAT_SLOTS; i++) {
+        out->n_composited_px += (int64_t)h[i];
+        out->n_composited += (int64_t)h[STAT_SLOTS + i];
+    }
     return RXGS_OK;
 }
 

@@ -24,6 +24,7 @@ constexpr int MLP_IN = ENC + FEAT;
 constexpr int MLP_RG = 16;               // receivers per MLP work item
 constexpr int MLP_PAIRS = 32;            // sorted positions per MLP work item
 constexpr int AMAX_SLOTS = 128;          // activation-bound words after the view counters
+constexpr int STAT_SLOTS = 64;           // u64 slots per render statistic (spread atomics)
 constexpr uint32_t SMALL_SCAN = 16384;   // scans up to this length run in one workgroup
 constexpr uint32_t SMALL_SORT = 1u << 20;  // sorts up to this length use 1024-key blocks
 
@@ -221,6 +222,7 @@ hipError_t launch_rad_bwd(const Scene &sc, Workspace &ws, float *grad, hipStream
 hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *gfeat, float *gmlp, hipStream_t st);
 hipError_t launch_project_bwd(const Scene &sc, Workspace &ws, const rxgs_grads &gr, hipStream_t st);
 size_t mlp_part_bytes(const Workspace &ws);
+unsigned long long *stat_words(Workspace &ws);
 int sort_items_for(uint32_t n);
 size_t w1b_part_bytes(int64_t K);
 
