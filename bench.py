@@ -132,6 +132,7 @@ def gpu_part(args):
         entry["sizes"] = {"views": info["V"], "visible_total": int(nvis.sum()), "tile_pairs": info["D"],
                           "mlp_pairs": pairs_mlp, "sort_keys": info["V"] * info["K_pad"],
                           "composited": info["n_composited"], "composited_px": info["n_composited_px"],
+                          "evaluated_px": info["n_evaluated_px"], "walked_px": info["n_walked_px"],
                           "chunks_per_view": 1 if mode == "rx" else -(-N // rpc)}
         saved.close()
         if not args.no_loop:

@@ -195,6 +195,10 @@ typedef struct {
                                  receiver chunk that shares them (TX mode: up to 16
                                  receivers of a view share one weight evaluation) */
     int64_t n_composited;     /* the same counted once per receiver */
+    int64_t n_evaluated_px;   /* (pixel, list entry) weights evaluated while the pixel was
+                                 still compositing, once per receiver chunk */
+    int64_t n_walked_px;      /* (pixel, list entry) slots walked by the waves (64 per
+                                 entry and wave, terminated lanes included) */
 } rxgs_saved_info_t;
 
 rxgs_status rxgs_saved_info(const rxgs_saved *s, rxgs_saved_info_t *out);
@@ -205,6 +209,7 @@ rxgs_status rxgs_saved_info(const rxgs_saved *s, rxgs_saved_info_t *out);
  *   RXGS_EXPORT_KEYS      V x K_pad u32: FP32 depth-key bits (0xFFFFFFFF if culled)
  *   RXGS_EXPORT_OPACITY   V x K_pad f32: opacity used for culling
  *   RXGS_EXPORT_ORDER     V x K_pad i32: Gaussian index at each sorted position
+ *                         s < NVIS[v] (later positions are undefined)
  *   RXGS_EXPORT_NVIS      V i32: visible Gaussians per view
  *   RXGS_EXPORT_PAIRS     D i32: sorted position (v * K_pad + s) of each pair
  *   RXGS_EXPORT_RANGES    V x tiles x 2 i32: [start, end) of each tile's pairs

@@ -74,6 +74,7 @@ struct BlendStage {
     int wide[BLOCK];             // azimuth offsets inside the tile may need wrapping
     unsigned short list[4][BLOCK];  // per wave: entries (in list order) that can reach its sub-tile
     int len[4];
+    int wrap[4];                 // per wave: its list holds an entry that needs azimuth wrapping
     int wcnt[4][4];
 };
 
@@ -127,10 +128,16 @@ __device__ __forceinline__ void stage_batch(BlendStage &st, const float4 *__rest
     uint64_t bal[4];
 #pragma unroll
     for (int b = 0; b < 4; b++) bal[b] = __ballot((m >> b) & 1);
+    const uint64_t wide_bal = __ballot(has && st.wide[t]);
     if (lane == 0)
 #pragma unroll
         for (int b = 0; b < 4; b++) st.wcnt[w][b] = (int)__popcll(bal[b]);
+    if (t < 4) st.wrap[t] = 0;
     __syncthreads();
+    // a wide entry reaches every sub-tile (its mask is 0xF)
+    if (lane == 0 && wide_bal)
+#pragma unroll
+        for (int b = 0; b < 4; b++) st.wrap[b] = 1;
 #pragma unroll
     for (int b = 0; b < 4; b++) {
         if ((m >> b) & 1) {

@@ -85,15 +85,162 @@ __device__ __forceinline__ int tile_cols(float u, float rup, int W, int tiles_x,
 }
 
 // ----------------------------------------------------------------------------
-// Stage 1: projection.  One thread per Gaussian (coalesced SoA loads), looping
-// over a chunk of views.  Geometry in FP64 (exact differences of the FP32
-// inputs), stored as FP32.  The depth key is the FP32 squared distance
-// computed with rounded, unfused operations.
+// Stage 1: projection of one Gaussian onto the angular grid of one view
+// (Sec. 4.1 and App. B: azimuth/elevation of the mean, Jacobian-projected
+// covariance plus the 0.3 px^2 dilation).  Geometry is evaluated in FP64 from
+// the FP32 inputs with fused multiply-adds off, so the key kernel and the
+// emission kernel, which both evaluate it, agree bit for bit on every tile
+// count (the per-view pair counts of the first size the pair segments of the
+// second).
+
+// view-independent part: Sigma = R diag(s^2) R^T, opacity, the largest
+// Mahalanobis distance q with o exp(-q/2) >= 1/255, and log2 of the opacity
+struct GaussGeo {
+    float px, py, pz, o32;
+    double S00, S01, S02, S11, S12, S22, qmax, lo2;
+};
+
+__device__ __forceinline__ void gauss_geo(const float *__restrict__ soa, int64_t K, int64_t k, GaussGeo &G)
+{
+#pragma clang fp contract(off)
+    G.px = soa[k];
+    G.py = soa[K + k];
+    G.pz = soa[2 * K + k];
+    const double s0 = exp(2.0 * (double)soa[3 * K + k]);
+    const double s1 = exp(2.0 * (double)soa[4 * K + k]);
+    const double s2 = exp(2.0 * (double)soa[5 * K + k]);
+    double qw = soa[6 * K + k], qx = soa[7 * K + k], qy = soa[8 * K + k], qz = soa[9 * K + k];
+    const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+    const double R00 = 1.0 - 2.0 * (qy * qy + qz * qz), R01 = 2.0 * (qx * qy - qw * qz),
+                 R02 = 2.0 * (qx * qz + qw * qy);
+    const double R10 = 2.0 * (qx * qy + qw * qz), R11 = 1.0 - 2.0 * (qx * qx + qz * qz),
+                 R12 = 2.0 * (qy * qz - qw * qx);
+    const double R20 = 2.0 * (qx * qz - qw * qy), R21 = 2.0 * (qy * qz + qw * qx),
+                 R22 = 1.0 - 2.0 * (qx * qx + qy * qy);
+    G.S00 = R00 * R00 * s0 + R01 * R01 * s1 + R02 * R02 * s2;
+    G.S01 = R00 * R10 * s0 + R01 * R11 * s1 + R02 * R12 * s2;
+    G.S02 = R00 * R20 * s0 + R01 * R21 * s1 + R02 * R22 * s2;
+    G.S11 = R10 * R10 * s0 + R11 * R11 * s1 + R12 * R12 * s2;
+    G.S12 = R10 * R20 * s0 + R11 * R21 * s1 + R12 * R22 * s2;
+    G.S22 = R20 * R20 * s0 + R21 * R21 * s1 + R22 * R22 * s2;
+    G.o32 = (float)(1.0 / (1.0 + exp(-(double)soa[10 * K + k])));
+    G.qmax = 0.0;
+    G.lo2 = 0.0;
+    if (G.o32 >= ALPHA_MIN) {
+        G.qmax = 2.0 * log((double)G.o32 / (double)ALPHA_MIN);
+        G.lo2 = log2((double)G.o32);
+    }
+}
+
+// the view-independent part of every Gaussian, computed once per render and
+// read back by the key and emission kernels (80 bytes per Gaussian)
+struct alignas(16) GaussGeoPacked {
+    double S00, S01, S02, S11, S12, S22, qmax, lo2;
+    float px, py, pz, o32;
+};
+
+__global__ __launch_bounds__(BLOCK) void k_gauss_prep(const float *__restrict__ soa, int64_t K,
+                                                      GaussGeoPacked *__restrict__ out)
+{
+    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= K) return;
+    GaussGeo G;
+    gauss_geo(soa, K, k, G);
+    GaussGeoPacked o;
+    o.S00 = G.S00; o.S01 = G.S01; o.S02 = G.S02; o.S11 = G.S11; o.S12 = G.S12; o.S22 = G.S22;
+    o.qmax = G.qmax; o.lo2 = G.lo2;
+    o.px = G.px; o.py = G.py; o.pz = G.pz; o.o32 = G.o32;
+    out[k] = o;
+}
+
+__device__ __forceinline__ void gauss_geo_load(const GaussGeoPacked *__restrict__ gg, int64_t k, GaussGeo &G)
+{
+    const double2 *d = reinterpret_cast<const double2 *>(gg + k);
+    const double2 a = d[0], b = d[1], c = d[2], e = d[3];
+    const float4 f = *reinterpret_cast<const float4 *>(d + 4);
+    G.S00 = a.x; G.S01 = a.y; G.S02 = b.x; G.S11 = b.y; G.S12 = c.x; G.S22 = c.y;
+    G.qmax = e.x; G.lo2 = e.y;
+    G.px = f.x; G.py = f.y; G.pz = f.z; G.o32 = f.w;
+}
+
+// view part: FP32 depth key, grid position, projected covariance (A, B; B, C)
+// in px^2, padded binning half-extents and the number of covered tiles
+struct ViewGeo {
+    uint32_t kb;   // FP32 bits of the squared distance to the view centre
+    uint32_t nt;   // covered tiles; 0: culled (near, faint, or off the grid)
+    double u, vv, A, B, Cc;
+    float4 e;      // binning box (u, v, rup, rvp) in FP32
+};
+
+__device__ __forceinline__ void view_geo(const GaussGeo &G, float cx, float cy, float cz, const DevGrid &g,
+                                         ViewGeo &P)
+{
+#pragma clang fp contract(off)
+    const float dxf = __fsub_rn(G.px, cx), dyf = __fsub_rn(G.py, cy), dzf = __fsub_rn(G.pz, cz);
+    const float kf = depth_key(dxf, dyf, dzf);
+    P.kb = __float_as_uint(kf);
+    P.nt = 0;
+    P.e = make_float4(0.f, 0.f, 0.f, 0.f);
+    P.u = P.vv = P.A = P.B = P.Cc = 0.0;
+    if (kf < NEAR2) return;
+    const double dx = (double)G.px - (double)cx, dy = (double)G.py - (double)cy, dz = (double)G.pz - (double)cz;
+    double h = sqrt(dx * dx + dy * dy);
+    if (!(h >= H_MIN)) h = H_MIN;
+    double az = atan2(dy, dx);
+    if (az < 0.0) az += 2.0 * M_PI;
+    const double el = atan2(dz, h);
+    P.u = az * g.idaz - 0.5;
+    P.vv = (el - g.el0) * g.idel - 0.5;
+    const double hh = h * h, rh2 = hh + dz * dz;
+    const double ihh = g.idaz / hh;          // 1 / (h^2 daz)
+    const double irh = g.idel / (rh2 * h);   // 1 / (rho^2 h del)
+    const double mu0 = -dy * ihh, mu1 = dx * ihh;
+    const double mv0 = -dx * dz * irh, mv1 = -dy * dz * irh, mv2 = hh * irh;
+    const double Smv0 = G.S00 * mv0 + G.S01 * mv1 + G.S02 * mv2;
+    const double Smv1 = G.S01 * mv0 + G.S11 * mv1 + G.S12 * mv2;
+    const double Smv2 = G.S02 * mv0 + G.S12 * mv1 + G.S22 * mv2;
+    P.A = G.S00 * mu0 * mu0 + 2.0 * G.S01 * mu0 * mu1 + G.S11 * mu1 * mu1 + DILATE;
+    P.B = mu0 * Smv0 + mu1 * Smv1;
+    P.Cc = mv0 * Smv0 + mv1 * Smv1 + mv2 * Smv2 + DILATE;
+    const float u32 = (float)P.u, v32 = (float)P.vv;
+    P.e = make_float4(u32, v32, 0.f, 0.f);
+    if (G.o32 >= ALPHA_MIN) {
+        const float rup = (float)(sqrt(G.qmax * P.A) * (1.0 + PAD_REL) + PAD_ABS);
+        const float rvp = (float)(sqrt(G.qmax * P.Cc) * (1.0 + PAD_REL) + PAD_ABS);
+        P.e.z = rup;
+        P.e.w = rvp;
+        int ty0, ty1, a0, a1, b0, b1;
+        const int nr = tile_rows(v32, rvp, g.H, ty0, ty1);
+        const int nc = nr ? tile_cols(u32, rup, g.W, g.tiles_x, a0, a1, b0, b1) : 0;
+        P.nt = (uint32_t)(nr * nc);
+    }
+}
+
+// blend record of a visible (view, Gaussian): integer and fractional parts of
+// the pixel position (pixel offsets stay exact to ~1e-7 px in FP32), the
+// inverse projected covariance times -log2(e) (1/2, 1, 1/2), log2 opacity
+__device__ __forceinline__ void blend_record(const GaussGeo &G, const ViewGeo &P, float4 &r0, float4 &r1)
+{
+#pragma clang fp contract(off)
+    const double idet = 1.0 / (P.A * P.Cc - P.B * P.B);
+    const double ca = P.Cc * idet, cb = -P.B * idet, cc = P.A * idet;
+    const double uf = floor(P.u), vf = floor(P.vv);
+    constexpr double L2E = 1.4426950408889634;
+    r0 = make_float4((float)uf, (float)(P.u - uf), (float)vf, (float)(P.vv - vf));
+    r1 = make_float4((float)(-0.5 * L2E * ca), (float)(-L2E * cb), (float)(-0.5 * L2E * cc), (float)G.lo2);
+}
+
+// Depth keys of every (view, Gaussian): one thread per Gaussian (coalesced SoA
+// loads), looping over a chunk of views.  Culled entries get the key
+// 0xFFFFFFFF, which the sort drops.  Per view, the visible count
+// and the pair count are reduced per workgroup before one atomic each.  With
+// a saved state the binning boxes, raw keys and opacities are kept for export.
 __global__ __launch_bounds__(BLOCK) void k_project(
-    const float *__restrict__ soa, int64_t K, int64_t Kp, const float *__restrict__ centres, int V,
-    int vchunk, DevGrid g, float4 *__restrict__ rec, float4 *__restrict__ ext, uint32_t *__restrict__ rawkey,
-    float *__restrict__ opac, uint32_t *__restrict__ ntl, uint32_t *__restrict__ skey,
-    uint32_t *__restrict__ sval, unsigned long long *__restrict__ counters)
+    const GaussGeoPacked *__restrict__ gg, int64_t K, int64_t Kp, const float *__restrict__ centres, int V,
+    int vchunk, DevGrid g, uint32_t *__restrict__ skey, uint32_t *__restrict__ sval,
+    unsigned long long *__restrict__ counters, float4 *__restrict__ ext, uint32_t *__restrict__ rawkey,
+    float *__restrict__ opac)
 {
     const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int v0 = blockIdx.y * vchunk;
@@ -101,101 +248,25 @@ __global__ __launch_bounds__(BLOCK) void k_project(
     const bool real = k < K;
     __shared__ uint32_t s_cnt[4][2];
     const int lane = threadIdx.x & 63;
-    float px = 0.f, py = 0.f, pz = 0.f, o32 = 0.f;
-    double qmax = 0.0, lo2 = 0.0;
-    double S00 = 0, S01 = 0, S02 = 0, S11 = 0, S12 = 0, S22 = 0;
-    if (real) {
-        px = soa[k];
-        py = soa[K + k];
-        pz = soa[2 * K + k];
-        const double s0 = exp(2.0 * (double)soa[3 * K + k]);
-        const double s1 = exp(2.0 * (double)soa[4 * K + k]);
-        const double s2 = exp(2.0 * (double)soa[5 * K + k]);
-        double qw = soa[6 * K + k], qx = soa[7 * K + k], qy = soa[8 * K + k], qz = soa[9 * K + k];
-        const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-        qw /= qn; qx /= qn; qy /= qn; qz /= qn;
-        const double R00 = 1.0 - 2.0 * (qy * qy + qz * qz), R01 = 2.0 * (qx * qy - qw * qz),
-                     R02 = 2.0 * (qx * qz + qw * qy);
-        const double R10 = 2.0 * (qx * qy + qw * qz), R11 = 1.0 - 2.0 * (qx * qx + qz * qz),
-                     R12 = 2.0 * (qy * qz - qw * qx);
-        const double R20 = 2.0 * (qx * qz - qw * qy), R21 = 2.0 * (qy * qz + qw * qx),
-                     R22 = 1.0 - 2.0 * (qx * qx + qy * qy);
-        S00 = R00 * R00 * s0 + R01 * R01 * s1 + R02 * R02 * s2;
-        S01 = R00 * R10 * s0 + R01 * R11 * s1 + R02 * R12 * s2;
-        S02 = R00 * R20 * s0 + R01 * R21 * s1 + R02 * R22 * s2;
-        S11 = R10 * R10 * s0 + R11 * R11 * s1 + R12 * R12 * s2;
-        S12 = R10 * R20 * s0 + R11 * R21 * s1 + R12 * R22 * s2;
-        S22 = R20 * R20 * s0 + R21 * R21 * s1 + R22 * R22 * s2;
-        o32 = (float)(1.0 / (1.0 + exp(-(double)soa[10 * K + k])));
-        if (o32 >= ALPHA_MIN) {
-            qmax = 2.0 * log((double)o32 / (double)ALPHA_MIN);
-            lo2 = log2((double)o32);
-        }
-    }
+    GaussGeo G;
+    if (real) gauss_geo_load(gg, k, G);
     for (int v = v0; v < v1; v++) {
         const size_t i = (size_t)v * Kp + k;
-        uint32_t key = 0xFFFFFFFFu, kb = 0xFFFFFFFFu, nt = 0;
-        float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
-        bool vis = false;
-        if (real) {
-            const float cx = centres[3 * v], cy = centres[3 * v + 1], cz = centres[3 * v + 2];
-            const float dxf = __fsub_rn(px, cx), dyf = __fsub_rn(py, cy), dzf = __fsub_rn(pz, cz);
-            const float kf = depth_key(dxf, dyf, dzf);
-            kb = __float_as_uint(kf);
-            if (!(kf < NEAR2)) {
-                const double dx = (double)px - (double)cx, dy = (double)py - (double)cy,
-                             dz = (double)pz - (double)cz;
-                double h = sqrt(dx * dx + dy * dy);
-                if (!(h >= H_MIN)) h = H_MIN;
-                double az = atan2(dy, dx);
-                if (az < 0.0) az += 2.0 * M_PI;
-                const double el = atan2(dz, h);
-                const double u = az * g.idaz - 0.5;
-                const double vv = (el - g.el0) * g.idel - 0.5;
-                const double hh = h * h, rh2 = hh + dz * dz;
-                const double ihh = g.idaz / hh;               // 1 / (h^2 daz)
-                const double irh = g.idel / (rh2 * h);        // 1 / (rho^2 h del)
-                const double mu0 = -dy * ihh, mu1 = dx * ihh;
-                const double mv0 = -dx * dz * irh, mv1 = -dy * dz * irh, mv2 = hh * irh;
-                const double Smv0 = S00 * mv0 + S01 * mv1 + S02 * mv2;
-                const double Smv1 = S01 * mv0 + S11 * mv1 + S12 * mv2;
-                const double Smv2 = S02 * mv0 + S12 * mv1 + S22 * mv2;
-                const double A = S00 * mu0 * mu0 + 2.0 * S01 * mu0 * mu1 + S11 * mu1 * mu1 + DILATE;
-                const double B = mu0 * Smv0 + mu1 * Smv1;
-                const double Cc = mv0 * Smv0 + mv1 * Smv1 + mv2 * Smv2 + DILATE;
-                const float u32 = (float)u, v32 = (float)vv;
-                e = make_float4(u32, v32, 0.f, 0.f);
-                if (o32 >= ALPHA_MIN) {
-                    const float rup = (float)(sqrt(qmax * A) * (1.0 + PAD_REL) + PAD_ABS);
-                    const float rvp = (float)(sqrt(qmax * Cc) * (1.0 + PAD_REL) + PAD_ABS);
-                    e.z = rup;
-                    e.w = rvp;
-                    int ty0, ty1, a0, a1, b0, b1;
-                    const int nr = tile_rows(v32, rvp, g.H, ty0, ty1);
-                    const int nc = nr ? tile_cols(u32, rup, g.W, g.tiles_x, a0, a1, b0, b1) : 0;
-                    nt = (uint32_t)(nr * nc);
-                }
-                vis = nt > 0;
-                if (vis) {
-                    const double idet = 1.0 / (A * Cc - B * B);
-                    const double ca = Cc * idet, cb = -B * idet, cc = A * idet;
-                    const double uf = floor(u), vf = floor(vv);
-                    constexpr double L2E = 1.4426950408889634;
-                    rec[2 * i] = make_float4((float)uf, (float)(u - uf), (float)vf, (float)(vv - vf));
-                    rec[2 * i + 1] = make_float4((float)(-0.5 * L2E * ca), (float)(-L2E * cb),
-                                                 (float)(-0.5 * L2E * cc), (float)lo2);
-                    key = kb;
-                }
-            }
-        }
-        ext[i] = e;
-        rawkey[i] = kb;
-        opac[i] = o32;
-        ntl[i] = nt;
-        skey[i] = key;
+        ViewGeo P;
+        P.kb = 0xFFFFFFFFu;
+        P.nt = 0;
+        P.e = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (real) view_geo(G, centres[3 * v], centres[3 * v + 1], centres[3 * v + 2], g, P);
+        const bool vis = P.nt > 0;
+        skey[i] = vis ? P.kb : 0xFFFFFFFFu;
         sval[i] = (uint32_t)k;
+        if (ext) {
+            ext[i] = P.e;
+            rawkey[i] = P.kb;
+            opac[i] = real ? G.o32 : 0.f;
+        }
         const uint64_t bal = __ballot(vis);
-        const uint32_t tsum = wave_sum_u32(nt);
+        const uint32_t tsum = wave_sum_u32(P.nt);
         if (lane == 0) {
             s_cnt[threadIdx.x >> 6][0] = (uint32_t)__popcll(bal);
             s_cnt[threadIdx.x >> 6][1] = tsum;
@@ -220,138 +291,130 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, size_t n)
     for (; i < n; i += stride) p[i] = value;
 }
 
-// ----------------------------------------------------------------------------
-// exclusive scan of u32 (three kernels: block sums, scan of block sums,
-// block-local scan plus offset); blocks of 4096, 16 consecutive items per thread
-__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t *__restrict__ in, uint32_t n,
-                                                       uint32_t *__restrict__ bsum)
-{
-    __shared__ uint32_t s_w[4];
-    const size_t base = (size_t)blockIdx.x * SORT_TILE + (size_t)threadIdx.x * SORT_ITEMS;
-    uint32_t s = 0;
-    for (int i = 0; i < SORT_ITEMS; i++)
-        if (base + i < n) s += in[base + i];
-    s = wave_sum_u32(s);
-    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) bsum[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
-}
-
-// single workgroup: exclusive scan of nb values (in may equal out)
-__global__ __launch_bounds__(BLOCK) void k_scan_top(const uint32_t *in, uint32_t *out, uint32_t nb)
-{
-    __shared__ uint32_t s_w[4];
-    uint32_t carry = 0;
-    for (uint32_t c = 0; c < nb; c += SORT_TILE) {
-        const uint32_t base = c + threadIdx.x * SORT_ITEMS;
-        uint32_t loc[SORT_ITEMS];
-        uint32_t s = 0;
-        for (int i = 0; i < SORT_ITEMS; i++) {
-            loc[i] = (base + i < nb) ? in[base + i] : 0u;
-            s += loc[i];
-        }
-        uint32_t tot;
-        uint32_t pre = block_exclusive_scan(s, tot, s_w) + carry;
-        for (int i = 0; i < SORT_ITEMS; i++) {
-            if (base + i < nb) out[base + i] = pre;
-            pre += loc[i];
-        }
-        carry += tot;
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t *__restrict__ in, uint32_t n,
-                                                     const uint32_t *__restrict__ bsum,
-                                                     uint32_t *__restrict__ out)
-{
-    __shared__ uint32_t s_w[4];
-    const size_t base = (size_t)blockIdx.x * SORT_TILE + (size_t)threadIdx.x * SORT_ITEMS;
-    uint32_t loc[SORT_ITEMS];
-    uint32_t s = 0;
-    for (int i = 0; i < SORT_ITEMS; i++) {
-        loc[i] = (base + i < n) ? in[base + i] : 0u;
-        s += loc[i];
-    }
-    uint32_t tot;
-    uint32_t pre = block_exclusive_scan(s, tot, s_w) + bsum[blockIdx.x];
-    for (int i = 0; i < SORT_ITEMS; i++) {
-        if (base + i < n) out[base + i] = pre;
-        pre += loc[i];
-    }
-}
-
-// records into depth order; tile counts in depth order
-__global__ __launch_bounds__(BLOCK) void k_gather(const float4 *__restrict__ rec, const uint32_t *__restrict__ ntl,
-                                                  const uint32_t *__restrict__ order,
-                                                  const unsigned long long *__restrict__ counters, int64_t Kp,
-                                                  int64_t total, float4 *__restrict__ srec,
-                                                  uint32_t *__restrict__ ntl_s)
-{
-    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (p >= total) return;
-    const int64_t v = p / Kp, s = p - v * Kp;
-    if (s < (int64_t)counters[2 * (size_t)v]) {
-        const size_t i = (size_t)v * Kp + min((int64_t)order[p], Kp - 1);
-        srec[2 * p] = rec[2 * i];
-        srec[2 * p + 1] = rec[2 * i + 1];
-        ntl_s[p] = ntl[i];
-    } else {
-        ntl_s[p] = 0;
-    }
-}
-
 // One pair (local tile id, sorted position) per covered tile, in depth order
 // within the view, into the view's segment of the pair arrays (segments start
-// at multiples of 4096 so the pair sort can treat each view on its own; the
-// block holding the view's last record also writes the segment's padding).  A
-// workgroup takes 256 consecutive sorted positions (always inside one view),
-// flattens their pairs with a block scan, and for each window of 2048 output
-// slots marks in LDS which record owns each slot, so consecutive threads write
-// consecutive slots.
+// at multiples of 4096 so the pair sort can treat each view on its own), and
+// the blend record of every visible entry in depth order.  A workgroup takes
+// the next 256 sorted positions of a view from an atomic ticket, projects
+// their Gaussians again (the same FP64 evaluation as the key kernel), scans
+// their tile counts, obtains the pairs of the view's earlier chunks by
+// decoupled look-back, and, for each window of 2048 output slots, marks in LDS
+// which entry owns each slot so that consecutive threads write consecutive
+// slots.  The chunk holding the view's last entry pads the segment.
 constexpr int EMIT_WIN = 2048;
+constexpr uint32_t EM_AGG = 1u << 30, EM_PRE = 1u << 31, EM_MASK = EM_AGG - 1;
+constexpr int EM_SPIN_MAX = 1 << 20;
+constexpr int EM_TICKET_STRIDE = 32;   // one ticket counter per view, 128 bytes apart
 
-__global__ __launch_bounds__(BLOCK) void k_emit(const float4 *__restrict__ ext, const uint32_t *__restrict__ order,
+__global__ __launch_bounds__(BLOCK) void k_emit(const GaussGeoPacked *__restrict__ gg, int64_t K, int64_t Kp,
+                                                const float *__restrict__ centres, DevGrid g,
+                                                const uint32_t *__restrict__ order,
                                                 const unsigned long long *__restrict__ counters,
-                                                const uint32_t *__restrict__ poff, const uint32_t *__restrict__ ntl_s,
-                                                const uint32_t *__restrict__ pbase, int64_t Kp, DevGrid g,
-                                                uint32_t Dpad, uint32_t *__restrict__ pkey,
-                                                uint32_t *__restrict__ pval)
+                                                const uint32_t *__restrict__ pbase,
+                                                const uint32_t *__restrict__ pcount,
+                                                const uint32_t *__restrict__ chunk_off, int V,
+                                                float4 *__restrict__ srec, uint32_t *__restrict__ pkey,
+                                                uint32_t *__restrict__ pval, uint32_t *status, uint32_t *tickets,
+                                                uint32_t *err)
 {
     __shared__ unsigned char s_own[EMIT_WIN];
     __shared__ uint32_t s_pre[BLOCK];
     __shared__ int4 s_tp[BLOCK];     // ty0, a0, columns in range a, b0
     __shared__ int s_ncol[BLOCK];
     __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_v, s_chunk, s_base;
     const int t = threadIdx.x;
-    const int64_t p0 = (int64_t)blockIdx.x * BLOCK;
-    const int64_t v = p0 / Kp, s0 = p0 - v * Kp;
+    if (t == 0) {
+        // the view owning this workgroup (chunk_off: first chunk of each view;
+        // the grid has exactly one workgroup per chunk of visible entries),
+        // then the chunk from the view's own ticket
+        int lo = 0, hi = V - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (chunk_off[mid] <= blockIdx.x) lo = mid;
+            else hi = mid - 1;
+        }
+        s_v = (uint32_t)lo;
+        s_chunk = atomicAdd(tickets + (size_t)lo * EM_TICKET_STRIDE, 1u);
+    }
+    __syncthreads();
+    const int v = (int)s_v;
+    const int chunk = (int)s_chunk;
+    const uint32_t c = chunk_off[v] + (uint32_t)chunk;   // look-back status slot
+    const int64_t s0 = (int64_t)chunk * BLOCK;
     const int64_t nv = (int64_t)counters[2 * (size_t)v];
-    if (s0 >= nv) return;   // uniform across the block
-    const int64_t p = p0 + t;
+    const int64_t s = s0 + t;
+    const size_t p = (size_t)v * Kp + (size_t)s;
     uint32_t nt = 0;
     int4 tp = make_int4(0, 0, 0, 0);
     int ncol = 1;
-    if (s0 + t < nv) {
-        nt = ntl_s[p];
-        if (nt) {
-            const float4 e = ext[(size_t)v * Kp + min((int64_t)order[p], Kp - 1)];
+    if (s < nv) {
+        const int64_t k = min((int64_t)order[p], K - 1);
+        GaussGeo G;
+        gauss_geo_load(gg, k, G);
+        ViewGeo P;
+        view_geo(G, centres[3 * v], centres[3 * v + 1], centres[3 * v + 2], g, P);
+        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+        if (P.nt) {
+            blend_record(G, P, r0, r1);
             int ty0, ty1, a0, a1, b0, b1;
-            tile_rows(e.y, e.w, g.H, ty0, ty1);
-            ncol = tile_cols(e.x, e.z, g.W, g.tiles_x, a0, a1, b0, b1);
+            tile_rows(P.e.y, P.e.w, g.H, ty0, ty1);
+            ncol = tile_cols(P.e.x, P.e.z, g.W, g.tiles_x, a0, a1, b0, b1);
             tp = make_int4(ty0, a0, a1 - a0 + 1, b0);
-            if (ncol < 1) {
-                ncol = 1;
-                nt = 0;
-            }
+            nt = P.nt;
+        } else {
+            atomicOr(err, 2u);   // cannot happen: sorted entries below nv were counted visible
         }
+        srec[2 * p] = r0;
+        srec[2 * p + 1] = r1;
     }
     uint32_t tot;
     const uint32_t pre = block_exclusive_scan(nt, tot, s_w);
     s_pre[t] = pre;
     s_tp[t] = tp;
     s_ncol[t] = ncol;
-    const uint32_t out0 = pbase[v] + (poff[p0] - poff[(size_t)v * Kp]);
+    if (t < 64) {
+        // pairs of the view's earlier chunks: decoupled look-back by the first
+        // wave, 64 predecessors per step (lane l reads chunk j - l; positions
+        // before the view's first chunk count as an empty prefix).  Waits only
+        // on chunks with smaller tickets, whose workgroups are resident.
+        uint32_t excl = 0;
+        uint32_t *mine = status + c;
+        if (chunk == 0) {
+            if (t == 0) __hip_atomic_store(mine, EM_PRE | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            if (t == 0) __hip_atomic_store(mine, EM_AGG | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int first = (int)chunk_off[v];
+            int j = (int)c - 1;
+            int spins = 0;
+            while (true) {
+                const int idx = j - t;
+                const uint32_t sv = idx >= first
+                                        ? __hip_atomic_load(status + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                        : EM_PRE;
+                const uint64_t pre_mask = __ballot((sv & EM_PRE) != 0);
+                const int lp = pre_mask ? __builtin_ctzll(pre_mask) : 63;
+                const uint64_t upto = lp == 63 ? ~0ull : ((2ull << lp) - 1);
+                if (__ballot(sv == 0) & upto) {
+                    if (++spins > EM_SPIN_MAX) {
+                        if (t == 0) atomicOr(err, 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += wave_sum_u32(t <= lp ? (sv & EM_MASK) : 0u);
+                if (pre_mask) break;
+                j -= 64;
+            }
+            if (t == 0)
+                __hip_atomic_store(mine, EM_PRE | (excl + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (t == 0) s_base = excl;
+    }
+    __syncthreads();
+    const uint32_t out0 = pbase[v] + s_base;
+    const uint32_t seg_end = pbase[v] + pcount[v];
     for (uint32_t c0 = 0; c0 < tot; c0 += EMIT_WIN) {
         __syncthreads();
         const uint32_t a = max(pre, c0), b = min(pre + nt, c0 + (uint32_t)EMIT_WIN);
@@ -363,20 +426,21 @@ __global__ __launch_bounds__(BLOCK) void k_emit(const float4 *__restrict__ ext, 
             const int4 q = s_tp[r];
             const int nc = s_ncol[r];
             const int j = (int)(i - s_pre[r]);
-            const int ty = q.x + j / nc, c = j % nc;
-            const int tx = c < q.z ? q.y + c : q.w + (c - q.z);
+            const int ty = q.x + j / nc, cc = j % nc;
+            const int tx = cc < q.z ? q.y + cc : q.w + (cc - q.z);
             const uint32_t o = out0 + i;
-            if (o < Dpad) {
+            if (o < seg_end) {
                 pkey[o] = (uint32_t)(ty * g.tiles_x + tx);
-                pval[o] = (uint32_t)(p0 + r);
+                pval[o] = (uint32_t)(p - t + r);
+            } else {
+                atomicOr(err, 4u);
             }
         }
     }
     if (s0 + BLOCK >= nv) {
-        // this block holds the view's last record: pad the segment to a whole unit
-        const uint32_t dend = out0 + tot;
-        const uint32_t pend = (uint32_t)(((uint64_t)dend + SORT_TILE - 1) / SORT_TILE * SORT_TILE);
-        for (uint32_t o = dend + t; o < pend && o < Dpad; o += BLOCK) pkey[o] = 0xFFFFFFFFu;
+        // this chunk holds the view's last entry: pad the segment to a whole unit
+        const uint32_t pend = pbase[v] + (uint32_t)(((uint64_t)pcount[v] + SORT_TILE - 1) / SORT_TILE * SORT_TILE);
+        for (uint32_t o = seg_end + t; o < pend; o += BLOCK) pkey[o] = 0xFFFFFFFFu;
     }
 }
 
@@ -404,17 +468,20 @@ __global__ __launch_bounds__(BLOCK) void k_ranges_hist(const uint32_t *__restric
     }
 }
 
-// [start, end) of each (view, tile) list in the padded pair array
+// [start, end) of each (view, tile) list in the sorted pair array; a view's
+// pairs are the first pcount entries of its segment (the rest is not written)
 __global__ __launch_bounds__(BLOCK) void k_ranges(const uint32_t *__restrict__ skey, uint32_t Dpad,
-                                                  const int4 *__restrict__ segtab, int tiles,
+                                                  const int4 *__restrict__ segtab,
+                                                  const uint32_t *__restrict__ pcount, int tiles,
                                                   uint2 *__restrict__ ranges)
 {
     const uint32_t i = blockIdx.x * BLOCK + threadIdx.x;
     if (i >= Dpad) return;
-    const uint32_t key = skey[i];
-    if (key >= (uint32_t)tiles) return;   // padding
     const int4 e = segtab[i / SORT_TILE];
-    const uint32_t first = (uint32_t)e.x * SORT_TILE, end = first + (uint32_t)e.y * SORT_TILE;
+    const uint32_t first = (uint32_t)e.x * SORT_TILE, end = first + pcount[e.z];
+    if (i >= end) return;
+    const uint32_t key = skey[i];
+    if (key >= (uint32_t)tiles) return;
     const size_t seg = (size_t)e.z * tiles + key;
     if (i == first || skey[i - 1] != key) ranges[seg].x = i;
     if (i + 1 == end || skey[i + 1] != key) ranges[seg].y = i + 1;
@@ -514,34 +581,63 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_global(const float *__restrict__ 
     block_absmax_to(acc, amax);
 }
 
-// Gaussian ("local") term of layer 1: W1[:, 36:] f_k + b1, stored in hid_pos order
-// 64 Gaussians per workgroup, W1[:, 36:] and the features staged in LDS
+// Gaussian ("local") term of layer 1: L_k = W1[:, 36:] f_k + b1, in hid_pos
+// order, on FP32 MFMA (v_mfma_f32_32x32x2f32).  One wave per 32 Gaussians:
+// D (64 hidden x 32 Gaussians) = W1f (64 x 32 features) F^T, with feature
+// c = q + 16 h at step q in lane half h, so each lane loads 16 contiguous
+// features of its Gaussian; the accumulator register r of block mb in lane
+// half h is hidden unit 32 mb + 8 (r / 4) + 4 h + r % 4, stored at position
+// 32 h + 16 mb + r of the row, so each lane writes 32 contiguous floats.
+// Waves are persistent; W1f and b1 stay in registers.
 __global__ __launch_bounds__(BLOCK) void k_mlp_local(const float *__restrict__ W1, const float *__restrict__ b1,
                                                      const float *__restrict__ feat, int64_t K,
                                                      float *__restrict__ Lp, unsigned *__restrict__ amax)
 {
-    __shared__ float s_w[FEAT][HID + 1];
-    __shared__ float s_f[64][FEAT + 1];
-    const int64_t k0 = (int64_t)blockIdx.x * 64;
-    for (int i = threadIdx.x; i < HID * FEAT; i += BLOCK) {
-        const int d = i / FEAT, c = i % FEAT;
-        s_w[c][d] = W1[d * MLP_IN + ENC + c];
-    }
-    for (int i = threadIdx.x; i < 64 * FEAT; i += BLOCK) {
-        const int kk = i / FEAT, c = i % FEAT;
-        s_f[kk][c] = (k0 + kk < K) ? feat[(size_t)(k0 + kk) * FEAT + c] : 0.f;
-    }
-    __syncthreads();
-    const int d = threadIdx.x & 63;
-    const float bias = b1[d];
-    float m = 0.f;
-    for (int kk = threadIdx.x >> 6; kk < 64; kk += BLOCK / 64) {
-        if (k0 + kk >= K) break;
-        float acc = bias;
+    const int lane = threadIdx.x & 63, h = lane >> 5, g = lane & 31;
+    float wa[2][16], bias[2][16];
 #pragma unroll
-        for (int c = 0; c < FEAT; c++) acc = fmaf(s_w[c][d], s_f[kk][c], acc);
-        Lp[(size_t)(k0 + kk) * HID + hid_pos(d)] = acc;
-        m = fmaxf(m, fabsf(acc));
+    for (int mb = 0; mb < 2; mb++)
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            wa[mb][q] = W1[(32 * mb + g) * MLP_IN + ENC + q + 16 * h];
+            bias[mb][q] = b1[32 * mb + 8 * (q >> 2) + 4 * h + (q & 3)];
+        }
+    const int64_t ngroups = (K + 31) / 32;
+    float m = 0.f;
+    for (int64_t grp = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); grp < ngroups;
+         grp += (int64_t)gridDim.x * (BLOCK / 64)) {
+        const int64_t k = grp * 32 + g;
+        const bool valid = k < K;
+        float f[16];
+        {
+            const float4 *src = reinterpret_cast<const float4 *>(feat + (size_t)min(k, K - 1) * FEAT + 16 * h);
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const float4 x = src[q];
+                f[4 * q] = x.x; f[4 * q + 1] = x.y; f[4 * q + 2] = x.z; f[4 * q + 3] = x.w;
+            }
+        }
+        floatx16 acc0, acc1;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            acc0[r] = bias[0][r];
+            acc1[r] = bias[1][r];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(wa[0][q], f[q], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(wa[1][q], f[q], acc1, 0, 0, 0);
+        }
+        if (valid) {
+            float4 *dst = reinterpret_cast<float4 *>(Lp + (size_t)k * HID + 32 * h);
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                dst[q] = make_float4(acc0[4 * q], acc0[4 * q + 1], acc0[4 * q + 2], acc0[4 * q + 3]);
+                dst[4 + q] = make_float4(acc1[4 * q], acc1[4 * q + 1], acc1[4 * q + 2], acc1[4 * q + 3]);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; r++) m = fmaxf(m, fmaxf(fabsf(acc0[r]), fabsf(acc1[r])));
+        }
     }
     block_absmax_to(m, amax);
 }
@@ -834,7 +930,54 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_pairs(const float *__restrict__ L
 // entries that can reach it, so a wave walks only those.  Every lane keeps its
 // own transmittance; a wave stops once all its lanes have terminated and the
 // workgroup stops staging once all its waves have.
-template <int R>
+
+// One wave's walk over its staged list, free of branches per entry: an entry
+// below the alpha threshold, or met after the lane terminated, gets weight 0,
+// which leaves T and the sums bit-identical to skipping it.  WRAP: some entry of
+// the list spans more than half the azimuth circle, so pixel offsets are
+// wrapped into [-W/2, W/2) (selects).  SAVE: track the stop index and the
+// composited count (saved states and statistics only).
+template <int R, bool SAVE, bool WRAP>
+__device__ __forceinline__ void blend_walk(const BlendStage &st, const float2 (*s_rad)[BLOCK], int wv, int n,
+                                           int lbase, float colf, float rowf, float Wf, float halfW, float &T,
+                                           float2 (&acc)[R], int &last, uint32_t &ncomp, uint32_t &neval,
+                                           uint32_t &nslot, bool &done)
+{
+    for (int i = 0; i < n; i++) {
+        if (SAVE) {
+            neval += done ? 0u : 1u;
+            nslot++;
+        }
+        const int e = st.list[wv][i];
+        const float4 r0 = st.r0[e];
+        const float4 r1 = st.r1[e];
+        float du = (colf - r0.x) - r0.y;
+        if (WRAP) {
+            du = du >= halfW ? du - Wf : du;
+            du = du < -halfW ? du + Wf : du;
+        }
+        const float dv = (rowf - r0.z) - r0.w;
+        float w = fminf(W_MAX, __builtin_amdgcn_exp2f(blend_exponent(du, dv, r1)));
+        const bool inc = !done && w >= ALPHA_MIN;
+        w = inc ? w : 0.f;
+        const float tw = T * w;
+#pragma unroll
+        for (int r = 0; r < R; r++) {
+            const float2 sv = s_rad[r][e];
+            acc[r].x = fmaf(tw, sv.x, acc[r].x);
+            acc[r].y = fmaf(tw, sv.y, acc[r].y);
+        }
+        T = T * (1.f - w);
+        if (SAVE) {
+            last = inc ? lbase + e : last;
+            ncomp += inc ? 1u : 0u;
+        }
+        done = done || T < T_EPS;
+        if ((i & 3) == 3 && __all(done)) break;
+    }
+}
+
+template <int R, bool SAVE>
 __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ srec,
                                                      const uint32_t *__restrict__ pval,
                                                      const uint2 *__restrict__ ranges,
@@ -852,7 +995,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
     const int4 ch = chunks[blockIdx.y];
     const int view = ch.x, j0 = ch.y, nrx = ch.z, tslot = ch.w;
     const int ty = tile / g.tiles_x, tx = tile - ty * g.tiles_x;
-    const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+    const int t = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
     const int row = ty * TILE + 8 * (wv >> 1) + (lane >> 3), col = tx * TILE + 8 * (wv & 1) + (lane & 7);
     const bool inside = row < g.H && col < g.W;
     const float rowf = (float)row, colf = (float)col;
@@ -865,7 +1008,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
 #pragma unroll
     for (int r = 0; r < R; r++) acc[r] = make_float2(0.f, 0.f);
     int last = 0;
-    uint32_t ncomp = 0;   // composited entries of this pixel
+    uint32_t ncomp = 0, neval = 0, nslot = 0;   // composited / evaluated while active / walked (SAVE)
     bool done = !inside;
 
     for (uint32_t base = rg.x; base < rg.y; base += BLOCK) {
@@ -880,35 +1023,15 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
                 s_rad[r][t] = (r < nrx) ? rad[(size_t)(j0 + r) * Kp + s] : make_float2(0.f, 0.f);
         }
         stage_batch(st, srec, p, (uint32_t)t < cnt, tx, ty, g);
-        if (!done) {
-            const int n = st.len[wv];
-            for (int i = 0; i < n; i++) {
-                const int e = st.list[wv][i];
-                const float4 r0 = st.r0[e];
-                const float4 r1 = st.r1[e];
-                float du = (colf - r0.x) - r0.y;
-                if (st.wide[e]) {
-                    if (du >= halfW) du -= Wf;
-                    else if (du < -halfW) du += Wf;
-                }
-                const float dv = (rowf - r0.z) - r0.w;
-                const float w = fminf(W_MAX, __builtin_amdgcn_exp2f(blend_exponent(du, dv, r1)));
-                if (w < ALPHA_MIN) continue;
-                const float tw = T * w;
-#pragma unroll
-                for (int r = 0; r < R; r++) {
-                    const float2 sv = s_rad[r][e];
-                    acc[r].x = fmaf(tw, sv.x, acc[r].x);
-                    acc[r].y = fmaf(tw, sv.y, acc[r].y);
-                }
-                T = T * (1.f - w);
-                last = (int)(base - rg.x) + e + 1;
-                ncomp++;
-                if (T < T_EPS) {
-                    done = true;
-                    break;
-                }
-            }
+        if (__any(!done)) {
+            const int n = __builtin_amdgcn_readfirstlane(st.len[wv]);
+            const int lbase = (int)(base - rg.x) + 1;
+            if (__builtin_amdgcn_readfirstlane(st.wrap[wv]))
+                blend_walk<R, SAVE, true>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T, acc, last, ncomp,
+                                          neval, nslot, done);
+            else
+                blend_walk<R, SAVE, false>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T, acc, last, ncomp,
+                                           neval, nslot, done);
         }
         if (__syncthreads_and(done ? 1 : 0)) break;
     }
@@ -923,7 +1046,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
                 C[((size_t)(j0 + r) * 2 + 1) * P + pix] = acc[r].y;
             }
         }
-        if (tslot >= 0) {
+        if (SAVE && tslot >= 0) {
             Tfin[(size_t)tslot * P + pix] = T;
             nlast[(size_t)tslot * P + pix] = last;
         }
@@ -940,8 +1063,14 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
             s_red[wv][r][2] = si;
         }
     }
-    const uint32_t nc = wave_sum_u32(ncomp);
-    if (lane == 0) st.wcnt[0][wv] = nc;
+    if (SAVE) {
+        const uint32_t nc = wave_sum_u32(ncomp), ne = wave_sum_u32(neval), ns = wave_sum_u32(nslot);
+        if (lane == 0) {
+            st.wcnt[0][wv] = (int)nc;
+            st.wcnt[1][wv] = (int)ne;
+            st.wcnt[2][wv] = (int)ns;
+        }
+    }
     __syncthreads();
     if (t < R * 3) {
         const int r = t / 3, c = t % 3;
@@ -952,13 +1081,19 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
     }
     // composited (pixel, entry) pairs: per chunk pixel and per receiver pixel,
     // spread over STAT_SLOTS counters
-    if (t == 0) {
-        const unsigned long long n = (unsigned long long)st.wcnt[0][0] + st.wcnt[0][1] + st.wcnt[0][2] +
-                                     st.wcnt[0][3];
-        if (n) {
-            const unsigned slot = (blockIdx.x + blockIdx.y * gridDim.x) % STAT_SLOTS;
-            atomicAdd(stats + slot, n);
-            atomicAdd(stats + STAT_SLOTS + slot, n * (unsigned long long)nrx);
+    if (SAVE && t == 0) {
+        const unsigned slot = (blockIdx.x + blockIdx.y * gridDim.x) % STAT_SLOTS;
+        unsigned long long n[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+            n[c] = (unsigned long long)st.wcnt[c][0] + st.wcnt[c][1] + st.wcnt[c][2] + st.wcnt[c][3];
+        if (n[0]) {
+            atomicAdd(stats + slot, n[0]);
+            atomicAdd(stats + STAT_SLOTS + slot, n[0] * (unsigned long long)nrx);
+        }
+        if (n[2]) {
+            atomicAdd(stats + 2 * STAT_SLOTS + slot, n[1]);
+            atomicAdd(stats + 3 * STAT_SLOTS + slot, n[2]);
         }
     }
 }
@@ -1035,52 +1170,42 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st
 }
 
 hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t Kp, const DevGrid &g,
-                          Workspace &ws, hipStream_t st)
+                          Workspace &ws, bool keep_boxes, hipStream_t st)
 {
+    if (sc.K > 0)
+        hipLaunchKernelGGL(k_gauss_prep, dim3((unsigned)((sc.K + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st,
+                           sc.soa.as<float>(), sc.K, ws.ggeo.as<GaussGeoPacked>());
     const int vchunk = V <= 4 ? 1 : 4;
     dim3 grid((unsigned)(Kp / BLOCK), (unsigned)((V + vchunk - 1) / vchunk));
-    hipLaunchKernelGGL(k_project, grid, dim3(BLOCK), 0, st, sc.soa.as<float>(), sc.K, Kp, centres, V, vchunk, g,
-                       ws.rec.as<float4>(), ws.ext.as<float4>(), ws.rawkey.as<uint32_t>(), ws.opac.as<float>(),
-                       ws.ntl.as<uint32_t>(), ws.skey[0].as<uint32_t>(), ws.sval[0].as<uint32_t>(),
-                       ws.counters.as<unsigned long long>());
+    hipLaunchKernelGGL(k_project, grid, dim3(BLOCK), 0, st, ws.ggeo.as<GaussGeoPacked>(), sc.K, Kp, centres, V,
+                       vchunk, g,
+                       ws.skey[0].as<uint32_t>(), ws.sval[0].as<uint32_t>(), ws.counters.as<unsigned long long>(),
+                       keep_boxes ? ws.ext.as<float4>() : nullptr, keep_boxes ? ws.rawkey.as<uint32_t>() : nullptr,
+                       keep_boxes ? ws.opac.as<float>() : nullptr);
     return hipGetLastError();
 }
 
-// Scratch buffers are sized by the caller before any work that may still be in
-// flight uses them (grow() frees the old buffer).  Small arrays are scanned by
-// one workgroup in a single launch.
-hipError_t scan_exclusive_u32(DevBuf &scan_tmp, const uint32_t *in, uint32_t *out, uint32_t n, hipStream_t st)
+// the emission kernel's error word, per-view tickets and per-chunk look-back
+// status, after the render statistics in the counters buffer
+uint32_t *emit_words(Workspace &ws)
 {
-    if (n == 0) return hipSuccess;
-    if (n <= SMALL_SCAN) {
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, st, in, out, n);
-        return hipGetLastError();
-    }
-    const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
-    if (scan_tmp.cap < (size_t)nb * 4) return hipErrorOutOfMemory;
-    uint32_t *bs = scan_tmp.as<uint32_t>();
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(BLOCK), 0, st, in, n, bs);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, st, bs, bs, nb);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(BLOCK), 0, st, in, n, bs, out);
-    return hipGetLastError();
+    return ws.counters.as<uint32_t>() + (size_t)4 * ws.V + AMAX_SLOTS + 2 * STAT_WORDS;
 }
 
-hipError_t launch_gather(Workspace &ws, int V, int64_t Kp, hipStream_t st)
+size_t emit_word_count(int V, int64_t VK)
 {
-    const int64_t total = (int64_t)V * Kp;
-    hipLaunchKernelGGL(k_gather, dim3(nblk(total)), dim3(BLOCK), 0, st, ws.rec.as<float4>(), ws.ntl.as<uint32_t>(),
-                       ws.sval[ws.sorted_buf].as<uint32_t>(), ws.counters.as<unsigned long long>(), Kp, total,
-                       ws.srec.as<float4>(), ws.ntl_s.as<uint32_t>());
-    return hipGetLastError();
+    return EM_TICKET_STRIDE + (size_t)V * EM_TICKET_STRIDE + (size_t)(VK / BLOCK);
 }
 
-hipError_t launch_emit(Workspace &ws, int V, int64_t Kp, const DevGrid &g, hipStream_t st)
+hipError_t launch_emit(const Scene &sc, Workspace &ws, const DevGrid &g, hipStream_t st)
 {
-    const int64_t total = (int64_t)V * Kp;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)(total / BLOCK)), dim3(BLOCK), 0, st, ws.ext.as<float4>(),
-                       ws.sval[ws.sorted_buf].as<uint32_t>(), ws.counters.as<unsigned long long>(),
-                       ws.poff.as<uint32_t>(), ws.ntl_s.as<uint32_t>(), ws.d_pbase, Kp, g,
-                       (uint32_t)ws.Dpad, ws.pkey[0].as<uint32_t>(), ws.pval[0].as<uint32_t>());
+    if (ws.n_emit_chunks == 0) return hipSuccess;
+    uint32_t *ew = emit_words(ws);
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)ws.n_emit_chunks), dim3(BLOCK), 0, st, ws.ggeo.as<GaussGeoPacked>(),
+                       sc.K, ws.Kp, ws.centres_p, g, ws.sval[ws.sorted_buf].as<uint32_t>(),
+                       ws.counters.as<unsigned long long>(), ws.d_pbase, ws.d_pcount, ws.d_chunk_off, ws.V,
+                       ws.srec.as<float4>(), ws.pkey[0].as<uint32_t>(), ws.pval[0].as<uint32_t>(),
+                       ew + EM_TICKET_STRIDE + (size_t)ws.V * EM_TICKET_STRIDE, ew + EM_TICKET_STRIDE, ew);
     return hipGetLastError();
 }
 
@@ -1096,7 +1221,7 @@ hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st)
     hipError_t e = launch_fill_u32(ws.ranges.as<uint32_t>(), 0u, nr * 2, st);
     if (e != hipSuccess || ws.Dpad == 0) return e;
     hipLaunchKernelGGL(k_ranges, dim3(nblk((size_t)ws.Dpad)), dim3(BLOCK), 0, st,
-                       ws.pkey[ws.pairs_buf].as<uint32_t>(), (uint32_t)ws.Dpad, ws.d_segtab, g.tiles,
+                       ws.pkey[ws.pairs_buf].as<uint32_t>(), (uint32_t)ws.Dpad, ws.d_segtab, ws.d_pcount, g.tiles,
                        ws.ranges.as<uint2>());
     return hipGetLastError();
 }
@@ -1111,8 +1236,9 @@ hipError_t launch_rad_direct(const Scene &sc, Workspace &ws, hipStream_t st)
     return hipGetLastError();
 }
 
-// render statistics after the activation-bound slots: STAT_SLOTS u64 of
-// composited pairs per chunk pixel, then STAT_SLOTS per receiver pixel
+// render statistics after the activation-bound slots, STAT_SLOTS u64 each:
+// composited pairs per chunk pixel, per receiver pixel, entries evaluated by
+// lanes still compositing, and wave-entry slots walked (64 per entry a wave walks)
 unsigned long long *stat_words(Workspace &ws)
 {
     return ws.counters.as<unsigned long long>() + (size_t)2 * ws.V + AMAX_SLOTS / 2;
@@ -1139,9 +1265,12 @@ hipError_t launch_mlp_global(const Mlp &m, Workspace &ws, hipStream_t st)
 hipError_t launch_mlp_local(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st)
 {
     const float *raw = m.raw.as<float>();
-    if (sc.K > 0)
-        hipLaunchKernelGGL(k_mlp_local, dim3((unsigned)((sc.K + 63) / 64)), dim3(BLOCK), 0, st, raw,
-                           raw + HID * MLP_IN, sc.feat.as<float>(), sc.K, ws.Lp.as<float>(), amax_words(ws) + 64);
+    if (sc.K > 0) {
+        const int64_t waves = (sc.K + 31) / 32;
+        const unsigned blocks = (unsigned)std::min<int64_t>((waves + 3) / 4, 2048);
+        hipLaunchKernelGGL(k_mlp_local, dim3(blocks), dim3(BLOCK), 0, st, raw, raw + HID * MLP_IN,
+                           sc.feat.as<float>(), sc.K, ws.Lp.as<float>(), amax_words(ws) + 64);
+    }
     return hipGetLastError();
 }
 
@@ -1166,24 +1295,29 @@ hipError_t launch_mlp_pairs(const Mlp &m, Workspace &ws, hipStream_t st)
 }
 
 template <int R>
-static void blend_launch(Workspace &ws, float *C, hipStream_t st)
+static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st)
 {
     dim3 grid((unsigned)ws.g.tiles, (unsigned)ws.n_chunks);
-    hipLaunchKernelGGL(k_blend_fwd<R>, grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
-                       ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
-                       ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
-                       ws.part.as<float>(), stat_words(ws));
+    if (save)
+        hipLaunchKernelGGL((k_blend_fwd<R, true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
+                           ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
+                           ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
+                           ws.part.as<float>(), stat_words(ws));
+    else
+        hipLaunchKernelGGL((k_blend_fwd<R, false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
+                           ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
+                           ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr);
 }
 
-hipError_t launch_blend_fwd(Workspace &ws, float *C, hipStream_t st)
+hipError_t launch_blend_fwd(Workspace &ws, float *C, bool save, hipStream_t st)
 {
     if (ws.n_chunks == 0) return hipSuccess;
     switch (ws.R) {
-    case 1: blend_launch<1>(ws, C, st); break;
-    case 2: blend_launch<2>(ws, C, st); break;
-    case 4: blend_launch<4>(ws, C, st); break;
-    case 8: blend_launch<8>(ws, C, st); break;
-    default: blend_launch<16>(ws, C, st); break;
+    case 1: blend_launch<1>(ws, C, save, st); break;
+    case 2: blend_launch<2>(ws, C, save, st); break;
+    case 4: blend_launch<4>(ws, C, save, st); break;
+    case 8: blend_launch<8>(ws, C, save, st); break;
+    default: blend_launch<16>(ws, C, save, st); break;
     }
     return hipGetLastError();
 }

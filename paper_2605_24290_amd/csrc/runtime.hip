@@ -108,11 +108,11 @@ bool ensure_pinned(Workspace &ws, size_t bytes)
 
 void free_workspace(Workspace &ws)
 {
-    DevBuf *bufs[] = {&ws.centres, &ws.rxpos,   &ws.desc,   &ws.rec,   &ws.ext,     &ws.rawkey, &ws.opac,
-                      &ws.ntl,     &ws.skey[0], &ws.skey[1], &ws.sval[0], &ws.sval[1], &ws.srec, &ws.ntl_s,
-                      &ws.poff,    &ws.pkey[0], &ws.pkey[1], &ws.pval[0], &ws.pval[1], &ws.ranges, &ws.rad,
+    DevBuf *bufs[] = {&ws.centres, &ws.rxpos,   &ws.desc,   &ws.ext,     &ws.rawkey, &ws.opac,
+                      &ws.skey[0], &ws.skey[1], &ws.sval[0], &ws.sval[1], &ws.srec,    &ws.ggeo,
+                      &ws.pkey[0], &ws.pkey[1], &ws.pval[0], &ws.pval[1], &ws.ranges, &ws.rad,
                       &ws.Lp,      &ws.Gp,      &ws.items,  &ws.Tfin,   &ws.nlast,  &ws.part,
-                      &ws.counters, &ws.hist,   &ws.scan_tmp, &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
+                      &ws.counters, &ws.hist,   &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
                       &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.hist_b};
     for (DevBuf *b : bufs) release(*b);
     if (ws.staged) (void)hipEventDestroy(ws.staged);
@@ -551,24 +551,25 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         GROW(ctx, ws.centres, (size_t)V * 12);
         GROW(ctx, ws.rxpos, (size_t)N * 12);
     }
-    GROW(ctx, ws.rec, VK * 32);
-    GROW(ctx, ws.ext, VK * 16);
-    GROW(ctx, ws.rawkey, VK * 4);
-    GROW(ctx, ws.opac, VK * 4);
-    GROW(ctx, ws.ntl, VK * 4);
+    if (saved) {
+        // binning boxes, raw keys and opacities, kept for export
+        GROW(ctx, ws.ext, VK * 16);
+        GROW(ctx, ws.rawkey, VK * 4);
+        GROW(ctx, ws.opac, VK * 4);
+    }
     for (int b = 0; b < 2; b++) {
         GROW(ctx, ws.skey[b], VK * 4);
         GROW(ctx, ws.sval[b], VK * 4);
     }
     GROW(ctx, ws.srec, VK * 32);
-    GROW(ctx, ws.ntl_s, VK * 4);
-    GROW(ctx, ws.poff, VK * 4);
-    // per view (visible count, pair count), then slots for the largest
-    // |layer-1 term| of the receivers and of the Gaussians (FP32 bits)
-    GROW(ctx, ws.counters, (size_t)2 * V * 8 + 4 * AMAX_SLOTS + 2 * STAT_SLOTS * 8);
+    GROW(ctx, ws.ggeo, (size_t)std::max<int64_t>(K, 1) * 80);
+    // per view (visible count, pair count); slots for the largest |layer-1
+    // term| of the receivers and of the Gaussians (FP32 bits); render
+    // statistics; the emission's ticket, error word and look-back status
+    const size_t emit_words_n = emit_word_count(V, (int64_t)VK);
+    const size_t cnt_words = (size_t)4 * V + AMAX_SLOTS + 2 * STAT_WORDS + emit_words_n;
+    GROW(ctx, ws.counters, cnt_words * 4);
     GROW(ctx, ws.hist, sort_ws_bytes((uint32_t)VK, 32, V));
-    // block sums of two scans: the sort histograms and the emission offsets
-    GROW(ctx, ws.scan_tmp, (VK / SORT_TILE + 2) * 4);
 
     if (saved) {
         HIPCHK(ctx, hipMemcpyAsync(ws.centres.p, mode == RXGS_MODE_TX ? tx : rx, (size_t)V * 12,
@@ -580,11 +581,11 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         ws.centres_p = mode == RXGS_MODE_TX ? tx : rx;
         ws.rxpos_p = rx;
     }
-    HIPCHK(ctx, launch_fill_u32(ws.counters.as<uint32_t>(), 0u, (size_t)V * 4 + AMAX_SLOTS + 4 * STAT_SLOTS, st));
+    HIPCHK(ctx, launch_fill_u32(ws.counters.as<uint32_t>(), 0u, cnt_words, st));
 
     // stage 1: projection, then the per-view depth sort; the host waits only
     // for the counters (visible Gaussians per view, pair count) while the sort runs
-    STAGE(ctx, "project", launch_project(sc, ws.centres_p, V, Kp, g, ws, st));
+    STAGE(ctx, "project", launch_project(sc, ws.centres_p, V, Kp, g, ws, saved != nullptr, st));
     if (!ensure_pinned(ws, (size_t)2 * V * 8 + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
     unsigned long long *h_cnt = static_cast<unsigned long long *>(ws.h_pinned);
     HIPCHK(ctx, hipMemcpyAsync(h_cnt, ws.counters.p, (size_t)2 * V * 8, hipMemcpyDeviceToHost, st));
@@ -592,8 +593,6 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     int cur = 0;
     STAGE(ctx, "sort_depth", sort_pairs_u32(ws.skey, ws.sval, ws.hist, cur, (uint32_t)VK, 32, V, Kp, nullptr, st));
     ws.sorted_buf = cur;
-    STAGE(ctx, "gather", launch_gather(ws, V, Kp, st));
-    STAGE(ctx, "scan", scan_exclusive_u32(ws.scan_tmp, ws.ntl_s.as<uint32_t>(), ws.poff.as<uint32_t>(), (uint32_t)VK, st));
 
     // receiver chunks of the blend (independent of the counters: built while
     // the GPU projects and sorts); the receivers of a view are consecutive
@@ -659,6 +658,10 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         vinfo[v] = make_int4(vfirst[v], vnrx[v], ws.h_nvis[v], 0);
     }
     ws.n_items = (int)item_off[V];
+    // emission chunks: 256 visible entries of one view each
+    std::vector<uint32_t> chunk_off(V + 1, 0);
+    for (int v = 0; v < V; v++) chunk_off[v + 1] = chunk_off[v] + (uint32_t)((ws.h_nvis[v] + BLOCK - 1) / BLOCK);
+    ws.n_emit_chunks = (int)chunk_off[V];
 
     const size_t P = (size_t)g.H * g.W;
     GROW(ctx, ws.pkey[0], std::max<uint64_t>(Dpad, 1) * 4);
@@ -682,7 +685,8 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     const size_t o_chunks = al16((size_t)N * 4);
     const size_t o_vinfo = o_chunks + chunks.size() * 16;
     const size_t o_ioff = o_vinfo + (size_t)V * 16;
-    const size_t o_pbase = o_ioff + al16((size_t)(V + 1) * 4);
+    const size_t o_coff = o_ioff + al16((size_t)(V + 1) * 4);
+    const size_t o_pbase = o_coff + al16((size_t)(V + 1) * 4);
     const size_t o_pcount = o_pbase + al16((size_t)V * 4);
     const size_t o_segtab = o_pcount + al16((size_t)V * 4);
     const size_t stage_bytes = o_segtab + segtab.size() * 16;
@@ -695,6 +699,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     std::memcpy(hp + o_chunks, chunks.data(), chunks.size() * 16);
     std::memcpy(hp + o_vinfo, vinfo.data(), (size_t)V * 16);
     std::memcpy(hp + o_ioff, item_off.data(), (size_t)(V + 1) * 4);
+    std::memcpy(hp + o_coff, chunk_off.data(), (size_t)(V + 1) * 4);
     std::memcpy(hp + o_pbase, ws.h_pbase.data(), (size_t)V * 4);
     std::memcpy(hp + o_pcount, ws.h_pcount.data(), (size_t)V * 4);
     std::memcpy(hp + o_segtab, segtab.data(), segtab.size() * 16);
@@ -703,6 +708,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     ws.d_chunks = reinterpret_cast<int4 *>(dd + o_chunks);
     ws.d_vinfo = reinterpret_cast<int4 *>(dd + o_vinfo);
     ws.d_item_off = reinterpret_cast<uint32_t *>(dd + o_ioff);
+    ws.d_chunk_off = reinterpret_cast<uint32_t *>(dd + o_coff);
     ws.d_pbase = reinterpret_cast<uint32_t *>(dd + o_pbase);
     ws.d_pcount = reinterpret_cast<uint32_t *>(dd + o_pcount);
     ws.d_segtab = reinterpret_cast<int4 *>(dd + o_segtab);
@@ -712,7 +718,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     // pairs: emit in depth order, stable sort by (view, tile), tile ranges
     int pcur = 0;
     if (D > 0) {
-        STAGE(ctx, "emit", launch_emit(ws, V, Kp, g, st));
+        STAGE(ctx, "emit", launch_emit(sc, ws, g, st));
         const int sbits = std::max(bits_for((uint64_t)g.tiles), 1);
         STAGE(ctx, "sort_pairs", sort_pairs_u32(ws.pkey, ws.pval, ws.hist_b, pcur, (uint32_t)Dpad, sbits, V, 0,
                                                 ws.d_segtab, st));
@@ -730,7 +736,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     }
 
     // stage 3: compositing, then the per-receiver reductions
-    STAGE(ctx, "blend_fwd", launch_blend_fwd(ws, C, st));
+    STAGE(ctx, "blend_fwd", launch_blend_fwd(ws, C, saved != nullptr, st));
     STAGE(ctx, "reduce", launch_reduce_outputs(ws, power, csum, st));
     ws.scene_version = sc.version;
     ws.mlp_version = ctx->mlp.version;
@@ -808,14 +814,15 @@ extern "C" rxgs_status rxgs_saved_info(const rxgs_saved *s, rxgs_saved_info_t *o
     // composited-pair statistics of the forward: wait for it, then sum the slots
     DeviceScope dsc(s->ctx->device);
     if (hipDeviceSynchronize() != hipSuccess) return RXGS_E_DEVICE;
-    std::vector<unsigned long long> h(2 * STAT_SLOTS);
+    std::vector<unsigned long long> h(4 * STAT_SLOTS);
     Workspace &w = const_cast<Workspace &>(ws);
     if (hipMemcpy(h.data(), stat_words(w), h.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) return RXGS_E_DEVICE;
-    out->n_composited_px = 0;
-    out->n_composited = 0;
+    out->n_composited_px = out->n_composited = out->n_evaluated_px = out->n_walked_px = 0;
     for (int i = 0; i < STAT_SLOTS; i++) {
         out->n_composited_px += (int64_t)h[i];
         out->n_composited += (int64_t)h[STAT_SLOTS + i];
+        out->n_evaluated_px += (int64_t)h[2 * STAT_SLOTS + i];
+        out->n_walked_px += (int64_t)h[3 * STAT_SLOTS + i];
     }
     return RXGS_OK;
 }
@@ -854,16 +861,15 @@ extern "C" rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *ds
     HIPCHK(ctx, hipDeviceSynchronize());
     if (what == RXGS_EXPORT_PAIRS || what == RXGS_EXPORT_RANGES) {
         // pairs without the per-view padding, ranges in those compact indices
-        std::vector<uint32_t> hk((size_t)ws.Dpad), hv((size_t)ws.Dpad);
+        std::vector<uint32_t> hv((size_t)ws.Dpad);
         std::vector<uint32_t> out;
-        if (ws.Dpad) {
-            HIPCHK(ctx, hipMemcpy(hk.data(), ws.pkey[ws.pairs_buf].p, hk.size() * 4, hipMemcpyDeviceToHost));
-            HIPCHK(ctx, hipMemcpy(hv.data(), ws.pval[ws.pairs_buf].p, hv.size() * 4, hipMemcpyDeviceToHost));
-        }
+        if (ws.Dpad) HIPCHK(ctx, hipMemcpy(hv.data(), ws.pval[ws.pairs_buf].p, hv.size() * 4, hipMemcpyDeviceToHost));
         if (what == RXGS_EXPORT_PAIRS) {
+            // each view's pairs are the first pcount entries of its segment
+            // (the sort does not write the padding slots)
             out.reserve((size_t)ws.D);
-            for (size_t i = 0; i < hk.size(); i++)
-                if (hk[i] != 0xFFFFFFFFu) out.push_back(hv[i]);
+            for (int v = 0; v < ws.V; v++)
+                for (uint32_t i = 0; i < ws.h_pcount[v]; i++) out.push_back(hv[(size_t)ws.h_pbase[v] + i]);
         } else {
             std::vector<uint32_t> rg((size_t)ws.V * ws.g.tiles * 2);
             HIPCHK(ctx, hipMemcpy(rg.data(), ws.ranges.p, rg.size() * 4, hipMemcpyDeviceToHost));

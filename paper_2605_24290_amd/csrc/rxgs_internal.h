@@ -25,7 +25,7 @@ constexpr int MLP_RG = 16;               // receivers per MLP work item
 constexpr int MLP_PAIRS = 32;            // sorted positions per MLP work item
 constexpr int AMAX_SLOTS = 128;          // activation-bound words after the view counters
 constexpr int STAT_SLOTS = 64;           // u64 slots per render statistic (spread atomics)
-constexpr uint32_t SMALL_SCAN = 16384;   // scans up to this length run in one workgroup
+constexpr int STAT_WORDS = 4 * STAT_SLOTS;   // four statistics, u64 each
 constexpr uint32_t SMALL_SORT = 1u << 20;  // sorts up to this length use 1024-key blocks
 
 // Method constants (Alg. 1 compositing and the readings of its unstated values).
@@ -91,22 +91,21 @@ struct Workspace {
 
     DevBuf centres;   // V x 3
     DevBuf rxpos;     // N x 3
-    DevBuf rec;       // V x Kp x 2 float4 (blend record, unsorted)
-    DevBuf ext;       // V x Kp float4 (u, v, rup, rvp)
-    DevBuf rawkey;    // V x Kp u32
-    DevBuf opac;      // V x Kp f32
-    DevBuf ntl;       // V x Kp u32 tiles per record
+    DevBuf ext;       // V x Kp float4 (u, v, rup, rvp), saved states only
+    DevBuf rawkey;    // V x Kp u32, saved states only
+    DevBuf opac;      // V x Kp f32, saved states only
     DevBuf skey[2];   // V x Kp u32 sort keys (ping-pong)
     DevBuf sval[2];   // V x Kp u32 sort values
     int sorted_buf = 0;
-    DevBuf srec;      // V x Kp x 2 float4 (sorted order)
-    DevBuf ntl_s;     // V x Kp u32 (sorted order)
-    DevBuf poff;      // V x Kp u32 emission offsets
+    DevBuf ggeo;      // K x 80 B view-independent projection terms of every Gaussian
+    DevBuf srec;      // V x Kp x 2 float4 blend records in depth order
     DevBuf desc;      // small descriptors copied from the host in one transfer:
     int *d_rxview = nullptr;       //   N: view of each receiver
     int4 *d_chunks = nullptr;      //   blend chunks (view, first receiver, receivers, T slot)
     int4 *d_vinfo = nullptr;       //   V: (first receiver, receivers, visible Gaussians, 0)
     uint32_t *d_item_off = nullptr;  // V + 1: first MLP work item of each view
+    uint32_t *d_chunk_off = nullptr;  // V + 1: first emission chunk (256 visible entries) of each view
+    int n_emit_chunks = 0;
     uint32_t *d_pbase = nullptr;   //   V: start of each view's segment of the pair arrays
     uint32_t *d_pcount = nullptr;  //   V: pairs of each view
     int4 *d_segtab = nullptr;      //   per 4096 pair slots: (first unit, units, view, 0) of its segment
@@ -125,9 +124,9 @@ struct Workspace {
     DevBuf Tfin;      // S x H x W
     DevBuf nlast;     // S x H x W
     DevBuf part;      // N x tiles x 3
-    DevBuf counters;  // u64 per view: [2 v] visible Gaussians, [2 v + 1] pairs
+    DevBuf counters;  // u64 per view: [2 v] visible Gaussians, [2 v + 1] pairs; then the
+                      // activation bounds, render statistics and the emission's look-back words
     DevBuf hist;      // radix sort scratch (depth sort)
-    DevBuf scan_tmp;  // scan block sums (emission offsets)
     DevBuf hist_b;    // radix sort scratch (pair sort); per-view tile counts at its start
     DevBuf nvis_d;    // V int
     // backward scratch
@@ -197,7 +196,7 @@ namespace rxgs {
 
 // ---- launch wrappers (kernels.hip) ----
 hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t Kp, const DevGrid &g,
-                          Workspace &ws, hipStream_t st);
+                          Workspace &ws, bool keep_boxes, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st);
 // sort.hip: stable segmented radix sort of (key, value) pairs by the low
 // `bits` key bits; segments of seg_len keys (a multiple of 4096), or given per
@@ -206,15 +205,15 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st
 hipError_t sort_pairs_u32(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
                           int64_t seg_len, const int4 *segtab, hipStream_t st);
 size_t sort_ws_bytes(uint32_t n, int bits, int nseg);
-hipError_t scan_exclusive_u32(DevBuf &scan_tmp, const uint32_t *in, uint32_t *out, uint32_t n, hipStream_t st);
-hipError_t launch_gather(Workspace &ws, int V, int64_t Kp, hipStream_t st);
-hipError_t launch_emit(Workspace &ws, int V, int64_t Kp, const DevGrid &g, hipStream_t st);
+hipError_t launch_emit(const Scene &sc, Workspace &ws, const DevGrid &g, hipStream_t st);
+uint32_t *emit_words(Workspace &ws);
+size_t emit_word_count(int V, int64_t VK);
 hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st);
 hipError_t launch_rad_direct(const Scene &sc, Workspace &ws, hipStream_t st);
 hipError_t launch_mlp_global(const Mlp &m, Workspace &ws, hipStream_t st);
 hipError_t launch_mlp_local(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st);
 hipError_t launch_mlp_pairs(const Mlp &m, Workspace &ws, hipStream_t st);
-hipError_t launch_blend_fwd(Workspace &ws, float *C, hipStream_t st);
+hipError_t launch_blend_fwd(Workspace &ws, float *C, bool save, hipStream_t st);
 hipError_t launch_reduce_outputs(Workspace &ws, float *power, float *csum, hipStream_t st);
 // backward (backward.hip)
 hipError_t launch_blend_bwd(Workspace &ws, const float *C, const float *dC, const float *dP, hipStream_t st);

@@ -4,14 +4,22 @@
 // The keys are split into independent segments (one per view: the per-view
 // depth sort, and the per-view padded pair lists).  One histogram kernel reads
 // every key once and counts all digits of all passes per segment.  Each pass
-// is then a single kernel: a workgroup takes the next 4096-key tile in order
-// from an atomic ticket, ranks its keys stably, publishes its per-digit counts
-// and obtains the counts of the earlier tiles of its segment by decoupled
-// look-back, and writes its keys digit run by digit run.  Ranking is wave
+// is then a single kernel: a workgroup takes the next 4096-key tile of its
+// segment in order from the segment's atomic ticket (one counter per segment,
+// so tickets of different segments do not serialise on one address), ranks
+// its keys stably, publishes its per-digit counts and obtains the counts of
+// the earlier tiles of its segment by decoupled look-back, and writes its
+// keys digit run by digit run.  Ranking is wave
 // synchronous: each wave owns a contiguous quarter of the tile, takes its keys
 // 64 at a time in index order, matches equal digits with 8 ballots and keeps
 // running per-digit counts in LDS, so the only workgroup barriers are the ones
 // around the look-back and the LDS staging of the tile.
+//
+// Keys equal to 0xFFFFFFFF (culled depth keys, padding of the pair lists) are
+// dropped: the histogram does not count them and the first pass does not
+// write them, so every segment's output is its surviving keys, in order, at
+// the segment's start, and the later passes only touch that prefix (the
+// segment's surviving count is the sum of its digit totals).
 //
 // Look-back progress: a workgroup only waits for tiles with a smaller ticket,
 // whose workgroups took their tickets earlier and are therefore resident; they
@@ -28,6 +36,8 @@ constexpr uint32_t LB_AGG = 1u << 30;    // status word: aggregate of this tile 
 constexpr uint32_t LB_PRE = 1u << 31;    // status word: inclusive prefix up to this tile
 constexpr uint32_t LB_MASK = LB_AGG - 1;
 constexpr int LB_SPIN_MAX = 1 << 20;
+constexpr uint32_t SORT_DROP = 0xFFFFFFFFu;   // dropped key
+constexpr int TICKET_STRIDE = 32;             // one ticket counter per 128-byte line
 
 struct SortSeg {
     uint32_t seg_blocks;   // uniform segments of this many tiles (0: table or one segment)
@@ -72,7 +82,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_hist(const uint32_t *__restrict_
     }
 #pragma unroll
     for (int i = 0; i < ITEMS; i++) {
-        if (base + (size_t)i * BLOCK + t < n)
+        if (base + (size_t)i * BLOCK + t < n && k[i] != SORT_DROP)
             for (int p = 0; p < passes; p++) atomicAdd(&h[p][w][(k[i] >> (8 * p)) & 255u], 1u);
     }
     __syncthreads();
@@ -103,27 +113,43 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict_
     __shared__ uint32_t s_tile;
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int shift = 8 * pass;
-    if (t == 0) s_tile = atomicAdd(ticket, 1u);
+    // the workgroup's segment follows from its index (segments are runs of
+    // whole tiles); its tile inside the segment comes from the segment's own
+    // ticket, so waits only go to tiles that took smaller tickets
+    uint32_t seg, first;
+    tile_segment(blockIdx.x, sm, seg, first);
+    if (t == 0) s_tile = first + atomicAdd(ticket + (size_t)seg * TICKET_STRIDE, 1u);
 #pragma unroll
     for (int ww = 0; ww < 4; ww++) s_wc[ww][t] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
-    const size_t base = (size_t)tile * TILEN + (size_t)w * WCH;
+    // digit starts in the segment (from its digit totals) and its surviving count
+    uint32_t seg_n;
+    const uint32_t dbase = block_exclusive_scan(hist[((size_t)seg * passes + pass) * 256 + t], seg_n, s_w);
+    // input positions of this tile that hold keys: all (first pass), or the
+    // part of the segment's surviving prefix inside the tile (later passes)
+    const size_t tile0 = (size_t)tile * TILEN, seg0 = (size_t)first * TILEN;
+    size_t lim = min((size_t)n, tile0 + TILEN);
+    if (pass > 0) {
+        lim = min(lim, seg0 + seg_n);
+        if (tile0 >= lim) return;   // uniform; later tiles of the segment are empty too
+    }
+    const size_t base = tile0 + (size_t)w * WCH;
 
     uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
 #pragma unroll
     for (int r = 0; r < ITEMS; r++) {
         const size_t idx = base + (size_t)r * 64 + lane;
-        const bool valid = idx < n;
-        key[r] = valid ? kin[idx] : 0u;
-        val[r] = valid ? vin[idx] : 0u;
+        const bool in = idx < lim;
+        key[r] = in ? kin[idx] : SORT_DROP;
+        val[r] = in ? vin[idx] : 0u;
     }
     // stable rank inside the wave's chunk: the keys of one round are matched by
     // digit; a digit's running count is read by all its lanes, then advanced by
     // its lowest lane (LDS operations of one wave execute in program order)
 #pragma unroll
     for (int r = 0; r < ITEMS; r++) {
-        const bool valid = base + (size_t)r * 64 + lane < n;
+        const bool valid = key[r] != SORT_DROP;
         const uint32_t d = (key[r] >> shift) & 255u;
         uint64_t m = __ballot(valid);
 #pragma unroll
@@ -142,37 +168,51 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict_
     const uint32_t cnt = c0 + c1 + c2 + c3;
 
     // decoupled look-back over the earlier tiles of this segment, digit t
-    uint32_t seg, first;
-    tile_segment(tile, sm, seg, first);
     uint32_t *mine = status + (size_t)tile * 256 + t;
     uint32_t excl = 0;
     if (tile == first) {
         __hip_atomic_store(mine, LB_PRE | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
         __hip_atomic_store(mine, LB_AGG | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t j = tile - 1;
+        // eight predecessors in flight per step; tiles before the segment's
+        // first count as an empty prefix
+        int64_t j = (int64_t)tile - 1;
+        int spins = 0;
         while (true) {
-            const uint32_t *src = status + (size_t)j * 256 + t;
-            uint32_t sv = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            for (int spin = 0; sv == 0 && spin < LB_SPIN_MAX; spin++) {
+            uint32_t w8[8];
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int64_t idx = j - q;
+                w8[q] = idx >= (int64_t)first ? __hip_atomic_load(status + (size_t)idx * 256 + t, __ATOMIC_RELAXED,
+                                                                  __HIP_MEMORY_SCOPE_AGENT)
+                                              : LB_PRE;
+            }
+            int q = 0;
+            bool done = false;
+            for (; q < 8; q++) {
+                if (w8[q] == 0) break;
+                excl += w8[q] & LB_MASK;
+                if (w8[q] & LB_PRE) {
+                    done = true;
+                    break;
+                }
+            }
+            if (done) break;
+            j -= q;
+            if (q < 8) {   // predecessor j has not published yet
+                if (++spins > LB_SPIN_MAX) {
+                    atomicOr(err, 1u);
+                    break;
+                }
                 __builtin_amdgcn_s_sleep(1);
-                sv = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            if (sv == 0) {
-                atomicOr(err, 1u);
-                break;
-            }
-            excl += sv & LB_MASK;
-            if ((sv & LB_PRE) || j == first) break;
-            j--;
         }
         __hip_atomic_store(mine, LB_PRE | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 
-    // digit starts: in the segment (from the digit totals) and in the tile
-    uint32_t tot;
-    const uint32_t dbase = block_exclusive_scan(hist[((size_t)seg * passes + pass) * 256 + t], tot, s_w);
-    const uint32_t loc = block_exclusive_scan(cnt, tot, s_w);
+    // digit starts in the tile
+    uint32_t tile_kept;
+    const uint32_t loc = block_exclusive_scan(cnt, tile_kept, s_w);
     s_glob[t] = first * (uint32_t)TILEN + dbase + excl;
     s_loc[t] = loc;
     s_wc[0][t] = loc;
@@ -182,7 +222,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict_
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < ITEMS; r++) {
-        if (base + (size_t)r * 64 + lane < n) {
+        if (key[r] != SORT_DROP) {
             const uint32_t pos = s_wc[w][(key[r] >> shift) & 255u] + rank[r];
             s_key[pos] = key[r];
             s_val[pos] = val[r];
@@ -190,8 +230,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict_
     }
     __syncthreads();
     // write out digit run by digit run: consecutive slots go to consecutive addresses
-    const uint32_t tile_n = (uint32_t)min((size_t)TILEN, (size_t)n - (size_t)tile * TILEN);
-    for (uint32_t i = t; i < tile_n; i += BLOCK) {
+    for (uint32_t i = t; i < tile_kept; i += BLOCK) {
         const uint32_t k = s_key[i];
         const uint32_t d = (k >> shift) & 255u;
         const uint32_t o = s_glob[d] + (i - s_loc[d]);
@@ -217,7 +256,8 @@ hipError_t sort_run(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t 
     if (wsb.cap < words * 4) return hipErrorOutOfMemory;
     uint32_t *hist = wsb.as<uint32_t>();
     uint32_t *status = hist + (size_t)nseg * passes * 256;
-    uint32_t *tickets = status + (size_t)passes * ntiles * 256;
+    uint32_t *tickets = status + (size_t)passes * ntiles * 256;   // [pass][segment], TICKET_STRIDE apart
+    uint32_t *err = tickets + (size_t)passes * nseg * TICKET_STRIDE;
     hipError_t e = launch_fill_u32(hist, 0u, words, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sort_hist<ITEMS>, dim3(ntiles), dim3(BLOCK), 0, st, keys[cur].as<uint32_t>(), n, passes, sm,
@@ -225,7 +265,8 @@ hipError_t sort_run(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t 
     for (int p = 0; p < passes; p++) {
         hipLaunchKernelGGL(k_sort_pass<ITEMS>, dim3(ntiles), dim3(BLOCK), 0, st, keys[cur].as<uint32_t>(),
                            vals[cur].as<uint32_t>(), keys[cur ^ 1].as<uint32_t>(), vals[cur ^ 1].as<uint32_t>(), n, p,
-                           passes, sm, hist, status + (size_t)p * ntiles * 256, tickets + p, tickets + 32);
+                           passes, sm, hist, status + (size_t)p * ntiles * 256,
+                           tickets + (size_t)p * nseg * TICKET_STRIDE, err);
         cur ^= 1;
     }
     return hipGetLastError();
@@ -240,7 +281,8 @@ size_t sort_ws_bytes(uint32_t n, int bits, int nseg)
     const uint32_t tilen = BLOCK * (uint32_t)sort_items_for(n);
     const size_t ntiles = (n + tilen - 1) / tilen;
     const size_t passes = (size_t)(std::max(bits, 1) + 7) / 8;
-    return ((size_t)std::max(nseg, 1) * passes * 256 + passes * ntiles * 256 + 64) * 4;
+    return ((size_t)std::max(nseg, 1) * passes * 256 + passes * ntiles * 256 +
+            passes * (size_t)std::max(nseg, 1) * TICKET_STRIDE + 64) * 4;
 }
 
 hipError_t sort_pairs_u32(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,

@@ -48,7 +48,8 @@ class CGrads(ctypes.Structure):
 class CSavedInfo(ctypes.Structure):
     _fields_ = [("K", c_int64), ("K_pad", c_int64), ("V", c_int64), ("N", c_int64),
                 ("D", c_int64), ("n_visible", c_int64), ("tiles", c_int64), ("tiles_x", c_int64),
-                ("n_composited_px", c_int64), ("n_composited", c_int64)]
+                ("n_composited_px", c_int64), ("n_composited", c_int64), ("n_evaluated_px", c_int64),
+                ("n_walked_px", c_int64)]
 
 
 class CServerOpts(ctypes.Structure):

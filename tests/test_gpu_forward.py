@@ -185,6 +185,23 @@ def test_full_sphere_small_grid_rx_mode():
     r.close()
 
 
+@pytest.mark.parametrize("mode", ["tx", "rx"])
+def test_large_grid_two_pass_pair_sort(mode):
+    """200 x 400 full-sphere grid: 13 x 25 = 325 tiles per view, so the pair
+    sort takes two 8-bit passes and tile ranges come from the sorted keys."""
+    from paper_2605_24290_amd import rxgs
+    grid = S.Grid(200, 400, -math.pi / 2.0, math.pi / 200.0)
+    wl = _wl("c0", K=700, N=3, grid=grid)
+    r = renderer_for(wl)
+    saved = rxgs.Saved(r)
+    C, P, _ = _render(r, wl, mode, saved=saved)
+    info = _check_binning(r, saved, wl, mode)
+    assert info["tiles"] > 255
+    compare_spectra(C, oracle_render(wl, mode))
+    saved.close()
+    r.close()
+
+
 def test_no_gaussians_and_zero_opacity():
     import torch
     from paper_2605_24290_amd import rxgs
