@@ -749,6 +749,62 @@ __device__ __forceinline__ void load_half_row(const float *__restrict__ base, si
     }
 }
 
+// the 16 features of one lane's Gaussian that its lane half feeds to the
+// layer-1 MFMA: f[8 h .. 8 h + 7] and f[16 + 8 h .. 16 + 8 h + 7]
+__device__ __forceinline__ void load_feat16(const float *__restrict__ feat, size_t k, int h, float (&f)[16])
+{
+    const float4 *a = reinterpret_cast<const float4 *>(feat + k * FEAT + 8 * h);
+    const float4 *b = reinterpret_cast<const float4 *>(feat + k * FEAT + 16 + 8 * h);
+    const float4 x0 = a[0], x1 = a[1], y0 = b[0], y1 = b[1];
+    f[0] = x0.x; f[1] = x0.y; f[2] = x0.z; f[3] = x0.w; f[4] = x1.x; f[5] = x1.y; f[6] = x1.z; f[7] = x1.w;
+    f[8] = y0.x; f[9] = y0.y; f[10] = y0.z; f[11] = y0.w; f[12] = y1.x; f[13] = y1.y; f[14] = y1.z; f[15] = y1.w;
+}
+
+// Layer-1 term of the 32 Gaussians of a work item, L = W1[:, 36:] f + b1, on
+// FP16 MFMA in split precision (as layer 2): A = W1's feature block * 2^w1exp
+// from LDS, B = the features; the accumulator rows of lane half h are hidden
+// units hid_of(h, t), so L lands in the order the activations are built in.
+__device__ __forceinline__ void local_term(const float (&f)[16], const half8 *s_w1h, const float4 *s_b1, int lane,
+                                           int h, int z0, float unscale, float (&l)[32])
+{
+    half8 fh[2], fl[2];
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const float v = f[8 * q + i];
+            const _Float16 hi = (_Float16)v;
+            fh[q][i] = hi;
+            fl[q][i] = (_Float16)(v - (float)hi);
+        }
+    const float4 *b1h = s_b1 + h * 8 + z0;
+    floatx16 L0, L1;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const float4 u = b1h[r], w = b1h[4 + r];
+        L0[4 * r] = u.x; L0[4 * r + 1] = u.y; L0[4 * r + 2] = u.z; L0[4 * r + 3] = u.w;
+        L1[4 * r] = w.x; L1[4 * r + 1] = w.y; L1[4 * r + 2] = w.z; L1[4 * r + 3] = w.w;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        const half8 h0 = s_w1h[((0 * 2 + 0) * 2 + q) * 64 + lane + z0];
+        const half8 h1 = s_w1h[((0 * 2 + 1) * 2 + q) * 64 + lane + z0];
+        const half8 l0 = s_w1h[((1 * 2 + 0) * 2 + q) * 64 + lane + z0];
+        const half8 l1 = s_w1h[((1 * 2 + 1) * 2 + q) * 64 + lane + z0];
+        L0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(l0, fh[q], L0, 0, 0, 0);
+        L1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(l1, fh[q], L1, 0, 0, 0);
+        L0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(h0, fl[q], L0, 0, 0, 0);
+        L1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(h1, fl[q], L1, 0, 0, 0);
+        L0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(h0, fh[q], L0, 0, 0, 0);
+        L1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(h1, fh[q], L1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 16; t++) {
+        l[t] = L0[t] * unscale;
+        l[16 + t] = L1[t] * unscale;
+    }
+}
+
 // Work item descriptor: (view, first sorted position s0, first receiver j0,
 // receivers | valid positions << 8).
 __device__ __forceinline__ int4 read_desc(const int4 &batch, int lane_idx)
@@ -763,10 +819,11 @@ __device__ __forceinline__ int4 read_desc(const int4 &batch, int lane_idx)
 // item n + 2 are loaded while item n is computed; the local rows of item n + 1
 // and every next receiver's global row are loaded right after the current
 // unit's activations are split, so the loads overlap the unit's MFMA work.
-template <bool SCALED>
-__device__ __forceinline__ void mlp_pairs_walk(const float *__restrict__ Lp, const float *__restrict__ Gp,
-                                               const half8 *s_w2h, const float4 *s_b2, const float4 *s_w3,
-                                               float b30, float b31, float sx,
+template <bool SCALED, bool FUSED>
+__device__ __forceinline__ void mlp_pairs_walk(const float *__restrict__ Lp, const float *__restrict__ feat,
+                                               const float *__restrict__ Gp, const half8 *s_w2h,
+                                               const float4 *s_b2, const float4 *s_w3, const half8 *s_w1h,
+                                               const float4 *s_b1, float l1unscale, float b30, float b31, float sx,
                                                const uint32_t *__restrict__ order, const int4 *__restrict__ items,
                                                int nitems, int64_t Kp, int64_t K, float2 *__restrict__ rad)
 {
@@ -786,10 +843,17 @@ __device__ __forceinline__ void mlp_pairs_walk(const float *__restrict__ Lp, con
     // below the view's visible count and the sorted order has Kp >= that
     // rounded up to 4096 entries); entries are clamped, stores check validity
     uint32_t kA = order[(size_t)dn.x * Kp + dn.y + pl];
-    float l[32], g[32];
-    load_half_row(Lp, min((int64_t)order[(size_t)dc.x * Kp + dc.y + pl], K - 1), h, l);
+    float l[32], g[32], fv[16];
+    const int64_t k0 = min((int64_t)order[(size_t)dc.x * Kp + dc.y + pl], K - 1);
+    if (FUSED) load_feat16(feat, (size_t)k0, h, fv);
+    else load_half_row(Lp, (size_t)k0, h, l);
     load_half_row(Gp, (size_t)dc.z, h, g);
     for (int n = 0; n < nmine; n++) {
+        if (FUSED) {
+            int z1 = 0;
+            asm volatile("" : "+v"(z1));
+            local_term(fv, s_w1h, s_b1, lane, h, z1, l1unscale, l);
+        }
         int4 dnn = dn;
         uint32_t kB = kA;
         if (n + 2 < nmine) {
@@ -819,7 +883,10 @@ __device__ __forceinline__ void mlp_pairs_walk(const float *__restrict__ Lp, con
                 bl[t >> 3][t & 7] = (_Float16)(v - (float)hi);
             }
             const bool last = jj + 1 == nj;
-            if (last && more) load_half_row(Lp, min((int64_t)kA, K - 1), h, l);
+            if (last && more) {
+                if (FUSED) load_feat16(feat, (size_t)min((int64_t)kA, K - 1), h, fv);
+                else load_half_row(Lp, (size_t)min((int64_t)kA, K - 1), h, l);
+            }
             load_half_row(Gp, (size_t)(last ? (more ? dn.z : dc.z) : dc.z + jj + 1), h, g);
             floatx16 acc0, acc1;
 #pragma unroll
@@ -881,14 +948,27 @@ __device__ __forceinline__ void mlp_pairs_walk(const float *__restrict__ Lp, con
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_mlp_pairs(const float *__restrict__ Lp, const float *__restrict__ Gp,
-                                                     const half8 *__restrict__ w2h,
+// FUSED: the Gaussians' layer-1 term is computed here from their features
+// (half the bytes of a stored term per pair) and bounded by lbound from the
+// host; otherwise it is read from Lp and bounded by its tracked maximum.
+template <bool FUSED>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_mlp_pairs(
+    const float *__restrict__ Lp, const float *__restrict__ feat,
+                                                     const float *__restrict__ Gp, const half8 *__restrict__ w2h,
                                                      const float4 *__restrict__ tab, const float *__restrict__ b3,
+                                                     const half8 *__restrict__ w1h, const float *__restrict__ b1tab,
+                                                     float l1unscale, float lbound,
                                                      const uint32_t *__restrict__ order,
                                                      const int4 *__restrict__ items, int nitems, int64_t Kp,
-                                                     int64_t K, const unsigned long long *__restrict__ counters,
-                                                     const unsigned *__restrict__ amax, float2 *__restrict__ rad)
+                                                     int64_t K, const unsigned *__restrict__ amax,
+                                                     float2 *__restrict__ rad)
 {
+    __shared__ half8 s_w1h[FUSED ? 8 * 64 : 1];
+    __shared__ float4 s_b1[FUSED ? 2 * 8 : 1];
+    if (FUSED) {
+        for (int i = threadIdx.x; i < 8 * 64; i += BLOCK) s_w1h[i] = w1h[i];
+        if (threadIdx.x < 64) reinterpret_cast<float *>(s_b1)[threadIdx.x] = b1tab[threadIdx.x];
+    }
     // per lane half h: layer-2 bias of accumulator registers (acc0 r, acc1 r)
     // as 8 float4, and layer-3 weights (W3[0][d], W3[1][d]) of register pairs
     // as 16 float4
@@ -906,18 +986,24 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_pairs(const float *__restrict__ L
     __syncthreads();
     const float b30 = b3[0], b31 = b3[1];
     const int lane = threadIdx.x & 63;
-    // largest layer-1 term magnitudes, spread over 64 slots each
-    unsigned mb = max(amax[lane], amax[64 + lane]);
+    // largest layer-1 term magnitudes (receivers, and Gaussians unless
+    // bounded by the host), spread over 64 slots each
+    unsigned mg = amax[lane], ml = FUSED ? 0u : amax[64 + lane];
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) mb = max(mb, (unsigned)__shfl_xor((int)mb, o));
-    const float bound = 2.f * __uint_as_float(mb);
+    for (int o = 32; o >= 1; o >>= 1) {
+        mg = max(mg, (unsigned)__shfl_xor((int)mg, o));
+        ml = max(ml, (unsigned)__shfl_xor((int)ml, o));
+    }
+    const float bound = __uint_as_float(mg) + (FUSED ? lbound : __uint_as_float(ml));
     if (bound < 32768.f) {
-        mlp_pairs_walk<false>(Lp, Gp, s_w2h, s_b2, s_w3, b30, b31, 1.f, order, items, nitems, Kp, K, rad);
+        mlp_pairs_walk<false, FUSED>(Lp, feat, Gp, s_w2h, s_b2, s_w3, s_w1h, s_b1, l1unscale, b30, b31, 1.f, order,
+                                     items, nitems, Kp, K, rad);
     } else {
         int e = 0;
         frexpf(bound, &e);   // bound < 2^e
         const float sx = (e > 15 && e < 128) ? ldexpf(1.f, 15 - e) : 1.f;
-        mlp_pairs_walk<true>(Lp, Gp, s_w2h, s_b2, s_w3, b30, b31, sx, order, items, nitems, Kp, K, rad);
+        mlp_pairs_walk<true, FUSED>(Lp, feat, Gp, s_w2h, s_b2, s_w3, s_w1h, s_b1, l1unscale, b30, b31, sx, order,
+                                    items, nitems, Kp, K, rad);
     }
 }
 
@@ -1274,22 +1360,40 @@ hipError_t launch_mlp_local(const Scene &sc, const Mlp &m, Workspace &ws, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_pairs(const Mlp &m, Workspace &ws, hipStream_t st)
+bool mlp_fused_ok(const Scene &sc, const Mlp &m)
+{
+    return !m.fp32 && m.w1_ok && sc.fmax < 32768.f;
+}
+
+hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st)
 {
     const float *raw = m.raw.as<float>();
     const float *b3 = raw + HID * MLP_IN + HID + HID * HID + HID + 2 * HID;
     if (ws.n_items > 0) {
         const unsigned blocks = (unsigned)std::min((ws.n_items + 3) / 4, 256 * 8);
-        if (m.fp32)
+        if (m.fp32) {
             hipLaunchKernelGGL(k_mlp_pairs_f32, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                                ws.Gp.as<float>(), m.w2a.as<float>(), m.tab.as<float4>(), b3,
                                ws.sval[ws.sorted_buf].as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K,
                                ws.counters.as<unsigned long long>(), ws.rad.as<float2>());
-        else
-            hipLaunchKernelGGL(k_mlp_pairs, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(), ws.Gp.as<float>(),
-                               m.w2h.as<half8>(), m.tabh.as<float4>(), b3, ws.sval[ws.sorted_buf].as<uint32_t>(),
-                               ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K, ws.counters.as<unsigned long long>(),
+        } else if (mlp_fused_ok(sc, m)) {
+            // bound of the Gaussians' layer-1 term: per hidden unit
+            // sum_c |W1[d, 36 + c]| max|f| + |b1[d]|, rounded up
+            double lb = 0.0;
+            for (int d = 0; d < HID; d++) lb = std::max(lb, m.w1abs[d] * (double)sc.fmax + m.b1abs[d]);
+            const float lbound = (float)(lb * (1.0 + 1e-6)) + 1e-30f;
+            hipLaunchKernelGGL(k_mlp_pairs<true>, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
+                               sc.feat.as<float>(), ws.Gp.as<float>(), m.w2h.as<half8>(), m.tabh.as<float4>(), b3,
+                               m.w1h.as<half8>(), m.b1tab.as<float>(), std::ldexp(1.f, -m.w1exp), lbound,
+                               ws.sval[ws.sorted_buf].as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K,
                                amax_words(ws), ws.rad.as<float2>());
+        } else {
+            hipLaunchKernelGGL(k_mlp_pairs<false>, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
+                               sc.feat.as<float>(), ws.Gp.as<float>(), m.w2h.as<half8>(), m.tabh.as<float4>(), b3,
+                               m.w1h.as<half8>(), m.b1tab.as<float>(), 1.f, 0.f,
+                               ws.sval[ws.sorted_buf].as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K,
+                               amax_words(ws), ws.rad.as<float2>());
+        }
     }
     return hipGetLastError();
 }

@@ -60,6 +60,18 @@ __global__ void k_count_nonfinite(const float *__restrict__ p, size_t n, unsigne
     if (c) atomicAdd(cnt, c);
 }
 
+// largest |p[i]| as FP32 bits (non-negative floats order like their bits)
+__global__ void k_absmax_bits(const float *__restrict__ p, size_t n, unsigned *__restrict__ out)
+{
+    size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * BLOCK;
+    unsigned m = 0;
+    for (; i < n; i += stride) m = max(m, __float_as_uint(fabsf(p[i])));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o));
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+}
+
 // AoS inputs -> SoA planes (x, y, z, ls0, ls1, ls2, qw, qx, qy, qz, logit)
 __global__ void k_to_soa(const float *__restrict__ means, const float *__restrict__ ls,
                          const float *__restrict__ q, const float *__restrict__ lg, int64_t K,
@@ -309,6 +321,8 @@ extern "C" void rxgs_destroy(rxgs_ctx *ctx)
     release(ctx->mlp.tab);
     release(ctx->mlp.w2h);
     release(ctx->mlp.tabh);
+    release(ctx->mlp.w1h);
+    release(ctx->mlp.b1tab);
     release(ctx->stage);
     delete ctx;
 }
@@ -379,19 +393,25 @@ extern "C" rxgs_status rxgs_scene_upload(rxgs_ctx *ctx, int64_t K, const float *
     DevBuf &dst = feat ? sc.feat : sc.rad;
     GROW(ctx, dst, std::max<size_t>(nrad, 1) * 4);
     if (K > 0) HIPCHK(ctx, hipMemcpyAsync(dst.p, radsrc, nrad * 4, kind, st));
+    float fmax = 0.f;   // largest |feature|, for the split-FP16 layer-1 path
     if (src_on_device && K > 0) {
         unsigned *cnt = reinterpret_cast<unsigned *>(stg + 11 * K);
-        HIPCHK(ctx, hipMemsetAsync(cnt, 0, 4, st));
+        HIPCHK(ctx, hipMemsetAsync(cnt, 0, 8, st));
         const unsigned blocks = (unsigned)std::min<int64_t>((11 * K + BLOCK - 1) / BLOCK, 2048);
         hipLaunchKernelGGL(k_count_nonfinite, dim3(blocks), dim3(BLOCK), 0, st, sc.soa.as<float>(), (size_t)11 * K,
                            cnt);
         hipLaunchKernelGGL(k_count_nonfinite, dim3(blocks), dim3(BLOCK), 0, st, dst.as<float>(), nrad, cnt);
+        if (feat) hipLaunchKernelGGL(k_absmax_bits, dim3(blocks), dim3(BLOCK), 0, st, dst.as<float>(), nrad, cnt + 1);
         HIPCHK(ctx, hipGetLastError());
-        unsigned h = 0;
-        HIPCHK(ctx, hipMemcpyAsync(&h, cnt, 4, hipMemcpyDeviceToHost, st));
+        unsigned h[2] = {0, 0};
+        HIPCHK(ctx, hipMemcpyAsync(h, cnt, 8, hipMemcpyDeviceToHost, st));
         HIPCHK(ctx, hipStreamSynchronize(st));
-        if (h) return fail(ctx, RXGS_E_INVALID, "non-finite value in the scene");
+        if (h[0]) return fail(ctx, RXGS_E_INVALID, "non-finite value in the scene");
+        std::memcpy(&fmax, &h[1], 4);
+    } else if (feat) {
+        for (size_t i = 0; i < nrad; i++) fmax = std::max(fmax, std::fabs(radsrc[i]));
     }
+    sc.fmax = fmax;
     sc.K = K;
     sc.has_features = feat;
     sc.version = ++ctx->version_counter;
@@ -458,6 +478,47 @@ extern "C" rxgs_status rxgs_mlp_upload(rxgs_ctx *ctx, const float *params, int s
                     w2h[(((0 * 2 + mb) * 4 + q) * 64 + l) * 8 + i] = hi;
                     w2h[(((1 * 2 + mb) * 4 + q) * 64 + l) * 8 + i] = lo;
                 }
+    // split-FP16 copy of the feature block of W1 for computing the Gaussians'
+    // layer-1 term inside the pair kernel: W1[:, 36:] * 2^w1exp (largest entry
+    // just under 2^15) as FP16 (hi, lo) pairs in the MFMA 32x32x16 A-operand
+    // layout, [2 part][2 mb][2 q][64 lane] x 8 halves, element i =
+    // W1[32 mb + lane % 32][36 + 16 q + 8 (lane / 32) + i]; b1 in the
+    // accumulator order of each lane half; per-row sums of |W1[:, 36:]|
+    const float *W1 = h.data();
+    const float *b1 = W1 + HID * MLP_IN;
+    float w1max = 0.f;
+    for (int d = 0; d < HID; d++)
+        for (int c = 0; c < FEAT; c++) w1max = std::max(w1max, std::fabs(W1[d * MLP_IN + ENC + c]));
+    int e1 = 0;
+    if (w1max > 0.f) std::frexp(w1max, &e1);
+    const int w1exp = std::min(std::max(15 - e1, -120), 120);
+    std::vector<_Float16> w1h(2 * 2 * 2 * 64 * 8);
+    for (int mb = 0; mb < 2; mb++)
+        for (int q = 0; q < 2; q++)
+            for (int l = 0; l < 64; l++)
+                for (int i = 0; i < 8; i++) {
+                    const float w = std::ldexp(W1[(32 * mb + (l & 31)) * MLP_IN + ENC + 16 * q + 8 * (l >> 5) + i],
+                                               w1exp);
+                    const _Float16 hi = (_Float16)w;
+                    const _Float16 lo = (_Float16)(w - (float)hi);
+                    w1h[(((0 * 2 + mb) * 2 + q) * 64 + l) * 8 + i] = hi;
+                    w1h[(((1 * 2 + mb) * 2 + q) * 64 + l) * 8 + i] = lo;
+                }
+    std::vector<float> b1tab(2 * 32);
+    bool b1_exact = true;
+    for (int hh = 0; hh < 2; hh++)
+        for (int t = 0; t < 32; t++) {
+            const float x = std::ldexp(b1[hid_of(hh, t)], w1exp);
+            if (!std::isfinite(x) || (b1[hid_of(hh, t)] != 0.f && std::fabs(x) < FLT_MIN)) b1_exact = false;
+            b1tab[hh * 32 + t] = x;
+        }
+    std::vector<double> w1abs(HID);
+    for (int d = 0; d < HID; d++) {
+        double r = 0.0;
+        for (int c = 0; c < FEAT; c++) r += std::fabs((double)W1[d * MLP_IN + ENC + c]);
+        w1abs[d] = r;
+    }
+
     // the rescaled layer-2 bias and layer-3 weights must stay finite and
     // normal (an exact rescaling); otherwise layer 2 runs on FP32 MFMA
     std::vector<float> tabh(tab);
@@ -474,6 +535,16 @@ extern "C" rxgs_status rxgs_mlp_upload(rxgs_ctx *ctx, const float *params, int s
     const char *env = std::getenv("RXGS_MLP_FP32");
     m.fp32 = !exact || (env && env[0] == '1');
     m.wexp = wexp;
+    m.w1exp = w1exp;
+    m.w1_ok = b1_exact && w1max < 32768.f;
+    for (int d = 0; d < HID; d++) {
+        m.w1abs[d] = w1abs[d];
+        m.b1abs[d] = std::fabs((double)b1[d]);
+    }
+    GROW(ctx, m.w1h, sizeof(_Float16) * w1h.size());
+    GROW(ctx, m.b1tab, sizeof(float) * b1tab.size());
+    HIPCHK(ctx, hipMemcpy(m.w1h.p, w1h.data(), sizeof(_Float16) * w1h.size(), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(m.b1tab.p, b1tab.data(), sizeof(float) * b1tab.size(), hipMemcpyHostToDevice));
     GROW(ctx, m.w2h, sizeof(_Float16) * w2h.size());
     GROW(ctx, m.tabh, sizeof(float) * tabh.size());
     HIPCHK(ctx, hipMemcpy(m.w2h.p, w2h.data(), sizeof(_Float16) * w2h.size(), hipMemcpyHostToDevice));
@@ -729,8 +800,10 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     // stage 2: radiance per (receiver, sorted position)
     if (ws.use_mlp) {
         STAGE(ctx, "mlp_global", launch_mlp_global(ctx->mlp, ws, st));
-        STAGE(ctx, "mlp_local", launch_mlp_local(sc, ctx->mlp, ws, st));
-        STAGE(ctx, "mlp_pairs", launch_mlp_pairs(ctx->mlp, ws, st));
+        // the stored Gaussian term: for the backward, or when the pair kernel
+        // cannot compute it itself
+        if (saved || !mlp_fused_ok(sc, ctx->mlp)) STAGE(ctx, "mlp_local", launch_mlp_local(sc, ctx->mlp, ws, st));
+        STAGE(ctx, "mlp_pairs", launch_mlp_pairs(sc, ctx->mlp, ws, st));
     } else {
         STAGE(ctx, "rad_direct", launch_rad_direct(sc, ws, st));
     }

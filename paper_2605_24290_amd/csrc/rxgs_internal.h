@@ -58,6 +58,7 @@ struct Scene {
     DevBuf soa;    // 11 x K: x, y, z, ls0, ls1, ls2, qw, qx, qy, qz, logit
     DevBuf rad;    // K x 2
     DevBuf feat;   // K x 32
+    float fmax = 0.f;   // largest |feature|
 };
 
 struct Mlp {
@@ -73,6 +74,16 @@ struct Mlp {
     DevBuf w2h;
     DevBuf tabh;   // as tab, with (W3 * 2^-wexp, b2 * 2^wexp)
     int wexp = 0;
+    // the Gaussians' layer-1 term inside the pair kernel: W1[:, 36:] * 2^w1exp
+    // split to FP16 (hi, lo) in the A-operand layout, [2 part][2 mb][2 q][64]
+    // x 8 halves; b1 * 2^w1exp per lane half in accumulator order; per-row
+    // sums of |W1[:, 36:]| and |b1| for the activation bound
+    DevBuf w1h;
+    DevBuf b1tab;
+    int w1exp = 0;
+    bool w1_ok = false;
+    double w1abs[64] = {};
+    double b1abs[64] = {};
     bool fp32 = false;   // layer 2 on FP32 MFMA instead: RXGS_MLP_FP32=1, or the
                          // rescaled tables would not be exact
 };
@@ -212,7 +223,8 @@ hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st);
 hipError_t launch_rad_direct(const Scene &sc, Workspace &ws, hipStream_t st);
 hipError_t launch_mlp_global(const Mlp &m, Workspace &ws, hipStream_t st);
 hipError_t launch_mlp_local(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st);
-hipError_t launch_mlp_pairs(const Mlp &m, Workspace &ws, hipStream_t st);
+hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st);
+bool mlp_fused_ok(const Scene &sc, const Mlp &m);
 hipError_t launch_blend_fwd(Workspace &ws, float *C, bool save, hipStream_t st);
 hipError_t launch_reduce_outputs(Workspace &ws, float *power, float *csum, hipStream_t st);
 // backward (backward.hip)

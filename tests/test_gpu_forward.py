@@ -126,17 +126,20 @@ def test_mlp_forward_parity_small(mode):
     r.close()
 
 
-@pytest.mark.parametrize("case", ["large_activations", "tiny_w2", "tx_ragged_receivers"])
+@pytest.mark.parametrize("case", ["large_activations", "large_features", "tiny_w2", "tx_ragged_receivers"])
 def test_mlp_radiance_ranges_and_items(case):
-    """Split-FP16 layer 2 against the FP64 oracle MLP outside the usual ranges:
-    layer-1 activations beyond the FP16 range (scaled path), a W2 near the FP32
-    subnormal range (per-upload W2 scale), and 37 receivers of one view (three
+    """Split-FP16 MLP against the FP64 oracle MLP outside the usual ranges:
+    layer-1 activations beyond the FP16 range (scaled path), features beyond it
+    (stored layer-1 term instead of the in-kernel one), a W2 near the FP32
+    subnormal range (FP32 fallback), and 37 receivers of one view (three
     receiver blocks per work item, the last one ragged)."""
     from paper_2605_24290_amd import rxgs
     N = 37 if case == "tx_ragged_receivers" else 6
     wl = _wl("c1", K=2500, N=N)
     if case == "large_activations":
         wl.mlp[0] = wl.mlp[0] * np.float32(2.0 ** 16)
+    elif case == "large_features":   # beyond the FP16 range: the stored layer-1 term is used
+        wl.scene.features = wl.scene.features * np.float32(2.0 ** 16)
     elif case == "tiny_w2":
         wl.mlp[2] = wl.mlp[2] * np.float32(2.0 ** -100)
         wl.mlp[3] = wl.mlp[3] + np.float32(2.0 ** -101)
