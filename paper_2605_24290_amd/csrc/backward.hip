@@ -653,7 +653,7 @@ hipError_t launch_rad_bwd(const Scene &sc, Workspace &ws, float *grad, hipStream
     const int64_t n = (int64_t)ws.N * ws.Kp;
     if (n == 0 || !grad || sc.K == 0) return hipSuccess;
     hipLaunchKernelGGL(k_rad_direct_bwd, dim3(nblk(n)), dim3(BLOCK), 0, st, ws.dS.as<float2>(),
-                       ws.sval[ws.sorted_buf].as<uint32_t>(), ws.counters.as<unsigned long long>(),
+                       ws.vorder.as<uint32_t>(), ws.counters.as<unsigned long long>(),
                        ws.d_rxview, ws.N, ws.Kp, sc.K, grad);
     return hipGetLastError();
 }
@@ -673,7 +673,7 @@ hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *g
     if (ws.n_items > 0)
         hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)(nwaves / 4)), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                            ws.Gp.as<float>(), m.w2a.as<float>(), m.w2b.as<float>(), m.tab.as<float4>(), W3,
-                           ws.sval[ws.sorted_buf].as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, sc.K,
+                           ws.vorder.as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, sc.K,
                            ws.counters.as<unsigned long long>(), ws.dS.as<float2>(), ws.dL.as<float>(),
                            ws.dG.as<float>(), ws.mpart.as<float>());
     if (gmlp) {
@@ -710,7 +710,7 @@ hipError_t launch_project_bwd(const Scene &sc, Workspace &ws, const rxgs_grads &
     const int64_t n = (int64_t)ws.V * ws.Kp;
     if (sc.K == 0) return hipSuccess;
     hipLaunchKernelGGL(k_project_bwd, dim3(nblk(n)), dim3(BLOCK), 0, st, sc.soa.as<float>(), sc.K, ws.Kp,
-                       ws.centres_p, ws.V, ws.g, ws.sval[ws.sorted_buf].as<uint32_t>(),
+                       ws.centres_p, ws.V, ws.g, ws.vorder.as<uint32_t>(),
                        ws.counters.as<unsigned long long>(), ws.g2d.as<float>(), gr.means, gr.log_scales, gr.quats,
                        gr.logits);
     return hipGetLastError();

@@ -2,12 +2,16 @@
 //
 // Pipeline of one render (Alg. 1 of RxGS, arXiv 2605.24290, with the view
 // index added to the sort key):
-//   k_project      stage 1: per (view, Gaussian) projection onto the angular
-//                  grid, FP32 depth key, conservative tile count.   [HBM]
+//   k_gauss_prep   stage 1: view-independent projection terms of every
+//                  Gaussian (covariance, opacity, cut-off).
+//   k_project      stage 1: per (view, Gaussian) FP32 depth key with the
+//                  near, opacity and conservative elevation culls.  [HBM]
 //   radix sort     stage 1: per-view stable sort of the depth keys (one
 //                  segment per view), 4 passes of 8 bits (sort.hip). [HBM]
-//   k_gather       records into depth order, tile counts in depth order.
-//   scan + k_emit  one (local tile, sorted position) pair per covered tile,
+//   k_emit1        stage 1: exact FP64 projection of the kept entries in
+//                  depth order; visible ones compacted into blend
+//                  records, boxes and pair offsets.                 [ALU]
+//   k_emit2        one (local tile, sorted position) pair per covered tile,
 //                  emitted in depth order into the view's segment.  [HBM]
 //   radix sort     stable 8-bit sort of each view's pairs by tile, so each
 //                  tile's list stays in depth order.                [HBM]
@@ -72,7 +76,10 @@ __device__ __forceinline__ int tile_cols(float u, float rup, int W, int tiles_x,
     }
     int c0 = (int)ceilf(__fsub_rn(u, rup)), c1 = (int)floorf(__fadd_rn(u, rup));
     if (c0 > c1) return 0;
-    int m = ((c0 % W) + W) % W;
+    // c0 mod W; c0 lies in (-W, W) for every box on the grid, other values
+    // take the general form
+    int m = c0 < 0 ? c0 + W : c0;
+    if ((unsigned)m >= (unsigned)W) m = ((c0 % W) + W) % W;
     int e = m + (c1 - c0);
     a0 = m / TILE;
     if (e < W) {
@@ -140,8 +147,11 @@ struct alignas(16) GaussGeoPacked {
     float px, py, pz, o32;
 };
 
+// Also the cull bound of each Gaussian, qcull >= q_max trace(Sigma) (rounded
+// up): the vertical variance of any projection is at most
+// lambda_max(Sigma) / (rho^2 del^2) + 0.3 px^2 <= trace(Sigma) / (rho^2 del^2) + 0.3.
 __global__ __launch_bounds__(BLOCK) void k_gauss_prep(const float *__restrict__ soa, int64_t K,
-                                                      GaussGeoPacked *__restrict__ out)
+                                                      GaussGeoPacked *__restrict__ out, float *__restrict__ qcull)
 {
     const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (k >= K) return;
@@ -152,6 +162,7 @@ __global__ __launch_bounds__(BLOCK) void k_gauss_prep(const float *__restrict__ 
     o.qmax = G.qmax; o.lo2 = G.lo2;
     o.px = G.px; o.py = G.py; o.pz = G.pz; o.o32 = G.o32;
     out[k] = o;
+    qcull[k] = (float)(G.qmax * (G.S00 + G.S11 + G.S22) * (1.0 + 1e-6));
 }
 
 __device__ __forceinline__ void gauss_geo_load(const GaussGeoPacked *__restrict__ gg, int64_t k, GaussGeo &G)
@@ -231,54 +242,71 @@ __device__ __forceinline__ void blend_record(const GaussGeo &G, const ViewGeo &P
     r1 = make_float4((float)(-0.5 * L2E * ca), (float)(-L2E * cb), (float)(-0.5 * L2E * cc), (float)G.lo2);
 }
 
-// Depth keys of every (view, Gaussian): one thread per Gaussian (coalesced SoA
-// loads), looping over a chunk of views.  Culled entries get the key
-// 0xFFFFFFFF, which the sort drops.  Per view, the visible count
-// and the pair count are reduced per workgroup before one atomic each.  With
-// a saved state the binning boxes, raw keys and opacities are kept for export.
+// Conservative elevation test in FP32: false only if the Gaussian's padded
+// binning box lies entirely below row 0 or above row H - 1 of the grid, which
+// the exact FP64 projection would also find.  The half-extent bound uses
+// qcull and the 0.3 px^2 dilation with q_max <= 2 ln 255 < 11.1, a relative
+// margin for the FP32 evaluation, and 0.01 px for the elevation error of
+// atan2f (< 1e-4 px on 1-degree rows).
+__device__ __forceinline__ bool maybe_on_grid(float dxf, float dyf, float dzf, float key, float qcull,
+                                              const DevGrid &g)
+{
+    const float h = sqrtf(dxf * dxf + dyf * dyf);
+    const float el = atan2f(dzf, h);
+    const float vv = (el - (float)g.el0) * (float)g.idel - 0.5f;
+    const float idel = (float)g.idel;
+    const float R = sqrtf(qcull * idel * idel / key + 3.33f) * 1.0002f + 0.02f;
+    return !(vv + R < -0.01f || vv - R > (float)(g.H - 1) + 0.01f);
+}
+
+// Depth keys of every (view, Gaussian): one thread per Gaussian (coalesced
+// loads), looping over a chunk of views.  A key is dropped (0xFFFFFFFF) when
+// the Gaussian is too near (FP32 key below 0.2^2 m^2), too faint (opacity
+// below 1/255) or surely off the grid's rows; the emission kernel applies the
+// exact test to the rest.  SAVE: the exact binning boxes, raw keys and
+// opacities are also kept for export.
+template <bool SAVE>
 __global__ __launch_bounds__(BLOCK) void k_project(
-    const GaussGeoPacked *__restrict__ gg, int64_t K, int64_t Kp, const float *__restrict__ centres, int V,
-    int vchunk, DevGrid g, uint32_t *__restrict__ skey, uint32_t *__restrict__ sval,
-    unsigned long long *__restrict__ counters, float4 *__restrict__ ext, uint32_t *__restrict__ rawkey,
-    float *__restrict__ opac)
+    const GaussGeoPacked *__restrict__ gg, const float *__restrict__ qcull, int64_t K, int64_t Kp,
+    const float *__restrict__ centres, int V, int vchunk, DevGrid g, uint32_t *__restrict__ skey,
+    uint32_t *__restrict__ sval, float4 *__restrict__ ext, uint32_t *__restrict__ rawkey, float *__restrict__ opac)
 {
     const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int v0 = blockIdx.y * vchunk;
     const int v1 = min(V, v0 + vchunk);
     const bool real = k < K;
-    __shared__ uint32_t s_cnt[4][2];
-    const int lane = threadIdx.x & 63;
     GaussGeo G;
-    if (real) gauss_geo_load(gg, k, G);
+    float4 po = make_float4(0.f, 0.f, 0.f, 0.f);
+    float qc = 0.f;
+    if (real) {
+        if (SAVE) {
+            gauss_geo_load(gg, k, G);
+            po = make_float4(G.px, G.py, G.pz, G.o32);
+        } else {
+            po = *reinterpret_cast<const float4 *>(reinterpret_cast<const double2 *>(gg + k) + 4);
+        }
+        qc = qcull[k];
+    }
     for (int v = v0; v < v1; v++) {
         const size_t i = (size_t)v * Kp + k;
-        ViewGeo P;
-        P.kb = 0xFFFFFFFFu;
-        P.nt = 0;
-        P.e = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (real) view_geo(G, centres[3 * v], centres[3 * v + 1], centres[3 * v + 2], g, P);
-        const bool vis = P.nt > 0;
-        skey[i] = vis ? P.kb : 0xFFFFFFFFu;
+        uint32_t key = 0xFFFFFFFFu, kb = 0xFFFFFFFFu;
+        if (real) {
+            const float cx = centres[3 * v], cy = centres[3 * v + 1], cz = centres[3 * v + 2];
+            const float dxf = __fsub_rn(po.x, cx), dyf = __fsub_rn(po.y, cy), dzf = __fsub_rn(po.z, cz);
+            const float kf = depth_key(dxf, dyf, dzf);
+            kb = __float_as_uint(kf);
+            if (!(kf < NEAR2) && po.w >= ALPHA_MIN && maybe_on_grid(dxf, dyf, dzf, kf, qc, g)) key = kb;
+        }
+        skey[i] = key;
         sval[i] = (uint32_t)k;
-        if (ext) {
+        if (SAVE) {
+            ViewGeo P;
+            P.e = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (real) view_geo(G, centres[3 * v], centres[3 * v + 1], centres[3 * v + 2], g, P);
             ext[i] = P.e;
-            rawkey[i] = P.kb;
-            opac[i] = real ? G.o32 : 0.f;
+            rawkey[i] = kb;
+            opac[i] = real ? po.w : 0.f;
         }
-        const uint64_t bal = __ballot(vis);
-        const uint32_t tsum = wave_sum_u32(P.nt);
-        if (lane == 0) {
-            s_cnt[threadIdx.x >> 6][0] = (uint32_t)__popcll(bal);
-            s_cnt[threadIdx.x >> 6][1] = tsum;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const uint32_t nv = s_cnt[0][0] + s_cnt[1][0] + s_cnt[2][0] + s_cnt[3][0];
-            const uint32_t nd = s_cnt[0][1] + s_cnt[1][1] + s_cnt[2][1] + s_cnt[3][1];
-            if (nv) atomicAdd(&counters[2 * (size_t)v], (unsigned long long)nv);
-            if (nd) atomicAdd(&counters[2 * (size_t)v + 1], (unsigned long long)nd);
-        }
-        __syncthreads();
     }
 }
 
@@ -291,107 +319,119 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, size_t n)
     for (; i < n; i += stride) p[i] = value;
 }
 
-// One pair (local tile id, sorted position) per covered tile, in depth order
-// within the view, into the view's segment of the pair arrays (segments start
-// at multiples of 4096 so the pair sort can treat each view on its own), and
-// the blend record of every visible entry in depth order.  A workgroup takes
-// the next 256 sorted positions of a view from an atomic ticket, projects
-// their Gaussians again (the same FP64 evaluation as the key kernel), scans
-// their tile counts, obtains the pairs of the view's earlier chunks by
-// decoupled look-back, and, for each window of 2048 output slots, marks in LDS
-// which entry owns each slot so that consecutive threads write consecutive
-// slots.  The chunk holding the view's last entry pads the segment.
-constexpr int EMIT_WIN = 2048;
-constexpr uint32_t EM_AGG = 1u << 30, EM_PRE = 1u << 31, EM_MASK = EM_AGG - 1;
+// Emission, part 1 (after the depth sort): the exact projection of every kept
+// entry in depth order.  A workgroup takes the next chunk of 256 x PER sorted
+// entries of its view from the view's ticket (PER consecutive entries per
+// thread: 4 when there are many chunks, which amortises each chunk's
+// look-back; 1 for small launches, which keeps the chain of chunks short), evaluates them (FP64, the same code as the key kernel's exports)
+// and compacts the visible ones (at least one tile covered): their depth rank
+// among the view's visible Gaussians and their first pair slot come from one
+// workgroup scan of the per-thread (visible, pairs) counts plus a
+// wave-parallel decoupled look-back over the view's earlier chunks (one 64-bit
+// status word per chunk: flags, visible count, pair count).  Each visible
+// entry writes its blend record, binning box, Gaussian index and first pair
+// slot at its rank; the view's last chunk writes the view's visible and pair
+// counts.  Errors (a look-back that does not end, more than 2^32 - 1 pairs in
+// a view) set bits of the error word, which the host checks.
+constexpr uint64_t EM_AGG = 1ull << 62, EM_PRE = 1ull << 63;
 constexpr int EM_SPIN_MAX = 1 << 20;
 constexpr int EM_TICKET_STRIDE = 32;   // one ticket counter per view, 128 bytes apart
 
-__global__ __launch_bounds__(BLOCK) void k_emit(const GaussGeoPacked *__restrict__ gg, int64_t K, int64_t Kp,
-                                                const float *__restrict__ centres, DevGrid g,
-                                                const uint32_t *__restrict__ order,
-                                                const unsigned long long *__restrict__ counters,
-                                                const uint32_t *__restrict__ pbase,
-                                                const uint32_t *__restrict__ pcount,
-                                                const uint32_t *__restrict__ chunk_off, int V,
-                                                float4 *__restrict__ srec, uint32_t *__restrict__ pkey,
-                                                uint32_t *__restrict__ pval, uint32_t *status, uint32_t *tickets,
-                                                uint32_t *err)
+__device__ __forceinline__ uint64_t em_pack(uint64_t flag, uint32_t vis, uint32_t pairs)
 {
-    __shared__ unsigned char s_own[EMIT_WIN];
-    __shared__ uint32_t s_pre[BLOCK];
-    __shared__ int4 s_tp[BLOCK];     // ty0, a0, columns in range a, b0
-    __shared__ int s_ncol[BLOCK];
-    __shared__ uint32_t s_w[4];
-    __shared__ uint32_t s_v, s_chunk, s_base;
-    const int t = threadIdx.x;
-    if (t == 0) {
-        // the view owning this workgroup (chunk_off: first chunk of each view;
-        // the grid has exactly one workgroup per chunk of visible entries),
-        // then the chunk from the view's own ticket
-        int lo = 0, hi = V - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (chunk_off[mid] <= blockIdx.x) lo = mid;
-            else hi = mid - 1;
+    return flag | ((uint64_t)(vis & 0x3FFFFFFFu) << 32) | pairs;
+}
+
+// exclusive workgroup scan of two counts at once
+__device__ __forceinline__ uint2 block_exclusive_scan2(uint32_t x, uint32_t y, uint2 &total, uint2 *s_w)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t a = x, b = y;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t ya = __shfl_up(a, off), yb = __shfl_up(b, off);
+        if (lane >= off) {
+            a += ya;
+            b += yb;
         }
-        s_v = (uint32_t)lo;
-        s_chunk = atomicAdd(tickets + (size_t)lo * EM_TICKET_STRIDE, 1u);
     }
+    if (lane == 63) s_w[w] = make_uint2(a, b);
     __syncthreads();
-    const int v = (int)s_v;
-    const int chunk = (int)s_chunk;
-    const uint32_t c = chunk_off[v] + (uint32_t)chunk;   // look-back status slot
-    const int64_t s0 = (int64_t)chunk * BLOCK;
-    const int64_t nv = (int64_t)counters[2 * (size_t)v];
-    const int64_t s = s0 + t;
-    const size_t p = (size_t)v * Kp + (size_t)s;
-    uint32_t nt = 0;
-    int4 tp = make_int4(0, 0, 0, 0);
-    int ncol = 1;
-    if (s < nv) {
-        const int64_t k = min((int64_t)order[p], K - 1);
-        GaussGeo G;
-        gauss_geo_load(gg, k, G);
-        ViewGeo P;
-        view_geo(G, centres[3 * v], centres[3 * v + 1], centres[3 * v + 2], g, P);
-        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
-        if (P.nt) {
-            blend_record(G, P, r0, r1);
-            int ty0, ty1, a0, a1, b0, b1;
-            tile_rows(P.e.y, P.e.w, g.H, ty0, ty1);
-            ncol = tile_cols(P.e.x, P.e.z, g.W, g.tiles_x, a0, a1, b0, b1);
-            tp = make_int4(ty0, a0, a1 - a0 + 1, b0);
-            nt = P.nt;
-        } else {
-            atomicOr(err, 2u);   // cannot happen: sorted entries below nv were counted visible
-        }
-        srec[2 * p] = r0;
-        srec[2 * p + 1] = r1;
+    uint2 pre = make_uint2(0u, 0u);
+    for (int i = 0; i < w; i++) {
+        pre.x += s_w[i].x;
+        pre.y += s_w[i].y;
     }
-    uint32_t tot;
-    const uint32_t pre = block_exclusive_scan(nt, tot, s_w);
-    s_pre[t] = pre;
-    s_tp[t] = tp;
-    s_ncol[t] = ncol;
+    total = make_uint2(s_w[0].x + s_w[1].x + s_w[2].x + s_w[3].x, s_w[0].y + s_w[1].y + s_w[2].y + s_w[3].y);
+    __syncthreads();
+    return make_uint2(pre.x + a - x, pre.y + b - y);
+}
+
+template <int EM1_PER>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_emit1(
+    const GaussGeoPacked *__restrict__ gg, int64_t K, int64_t Kp, const float *__restrict__ centres, DevGrid g,
+    const uint32_t *__restrict__ order, const uint32_t *__restrict__ hist, int passes, int cpv,
+    float4 *__restrict__ srec, float4 *__restrict__ sbox, uint32_t *__restrict__ vorder, uint32_t *__restrict__ poff,
+    unsigned long long *__restrict__ counters, unsigned long long *status, uint32_t *tickets, uint32_t *err)
+{
+    __shared__ uint32_t s_w[4];
+    __shared__ uint2 s_w2[4];
+    __shared__ uint32_t s_chunk, s_vbase, s_pbase;
+    constexpr int EM1_CHUNK = BLOCK * EM1_PER;
+    const int t = threadIdx.x;
+    const int v = (int)(blockIdx.x / (unsigned)cpv);
+    if (t == 0) s_chunk = atomicAdd(tickets + (size_t)v * EM_TICKET_STRIDE, 1u);
+    // entries the depth sort kept for this view: the sum of its digit totals
+    uint32_t seg_n;
+    (void)block_exclusive_scan(hist[((size_t)v * passes) * 256 + t], seg_n, s_w);
+    const uint32_t chunk = s_chunk;
+    const int64_t s0 = (int64_t)chunk * EM1_CHUNK;
+    // uniform; chunks with higher tickets of this view are past the end too
+    if (s0 >= (int64_t)seg_n) return;
+    const int64_t sb = s0 + (int64_t)t * EM1_PER;
+    const float cx = centres[3 * v], cy = centres[3 * v + 1], cz = centres[3 * v + 2];
+    uint32_t kk[EM1_PER], nt[EM1_PER];
+    float4 r0[EM1_PER], r1[EM1_PER], box[EM1_PER];
+#pragma unroll
+    for (int j = 0; j < EM1_PER; j++) kk[j] = sb + j < (int64_t)seg_n ? order[(size_t)v * Kp + sb + j] : 0xFFFFFFFFu;
+    uint32_t nvis = 0, npairs = 0;
+#pragma unroll
+    for (int j = 0; j < EM1_PER; j++) {
+        nt[j] = 0;
+        r0[j] = r1[j] = box[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (kk[j] != 0xFFFFFFFFu) {
+            kk[j] = (uint32_t)min((int64_t)kk[j], K - 1);
+            GaussGeo G;
+            gauss_geo_load(gg, kk[j], G);
+            ViewGeo P;
+            view_geo(G, cx, cy, cz, g, P);
+            if (P.nt) {
+                nt[j] = P.nt;
+                box[j] = P.e;
+                blend_record(G, P, r0[j], r1[j]);
+                nvis++;
+            }
+        }
+        npairs += nt[j];
+    }
+    uint2 tot;
+    const uint2 pre = block_exclusive_scan2(nvis, npairs, tot, s_w2);
     if (t < 64) {
-        // pairs of the view's earlier chunks: decoupled look-back by the first
-        // wave, 64 predecessors per step (lane l reads chunk j - l; positions
-        // before the view's first chunk count as an empty prefix).  Waits only
-        // on chunks with smaller tickets, whose workgroups are resident.
-        uint32_t excl = 0;
-        uint32_t *mine = status + c;
+        uint32_t evis = 0;
+        uint64_t epairs = 0;
+        unsigned long long *mine = status + (size_t)v * cpv + chunk;
         if (chunk == 0) {
-            if (t == 0) __hip_atomic_store(mine, EM_PRE | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (t == 0) __hip_atomic_store(mine, em_pack(EM_PRE, tot.x, tot.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            if (t == 0) __hip_atomic_store(mine, EM_AGG | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int first = (int)chunk_off[v];
-            int j = (int)c - 1;
+            if (t == 0) __hip_atomic_store(mine, em_pack(EM_AGG, tot.x, tot.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // 64 predecessors per step (lane l reads chunk j - l; before the
+            // view's first chunk counts as an empty prefix)
+            int j = (int)chunk - 1;
             int spins = 0;
             while (true) {
                 const int idx = j - t;
-                const uint32_t sv = idx >= first
-                                        ? __hip_atomic_load(status + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                        : EM_PRE;
+                const uint64_t sv = idx >= 0 ? __hip_atomic_load(status + (size_t)v * cpv + idx, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT)
+                                             : EM_PRE;
                 const uint64_t pre_mask = __ballot((sv & EM_PRE) != 0);
                 const int lp = pre_mask ? __builtin_ctzll(pre_mask) : 63;
                 const uint64_t upto = lp == 63 ? ~0ull : ((2ull << lp) - 1);
@@ -403,51 +443,157 @@ __global__ __launch_bounds__(BLOCK) void k_emit(const GaussGeoPacked *__restrict
                     __builtin_amdgcn_s_sleep(1);
                     continue;
                 }
-                excl += wave_sum_u32(t <= lp ? (sv & EM_MASK) : 0u);
+                evis += wave_sum_u32(t <= lp ? (uint32_t)((sv >> 32) & 0x3FFFFFFFu) : 0u);
+                const uint32_t pv = t <= lp ? (uint32_t)sv : 0u;
+                const uint32_t lo = wave_sum_u32(pv & 0xFFFFu), hi = wave_sum_u32(pv >> 16);
+                epairs += (uint64_t)lo + ((uint64_t)hi << 16);
                 if (pre_mask) break;
                 j -= 64;
             }
+            if (epairs + tot.y > 0xFFFFFFFFull) {
+                if (t == 0) atomicOr(err, 2u);
+                epairs = 0;
+            }
             if (t == 0)
-                __hip_atomic_store(mine, EM_PRE | (excl + tot), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(mine, em_pack(EM_PRE, evis + tot.x, (uint32_t)epairs + tot.y), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (t == 0) s_base = excl;
+        if (t == 0) {
+            s_vbase = evis;
+            s_pbase = (uint32_t)epairs;
+        }
     }
     __syncthreads();
-    const uint32_t out0 = pbase[v] + s_base;
-    const uint32_t seg_end = pbase[v] + pcount[v];
-    for (uint32_t c0 = 0; c0 < tot; c0 += EMIT_WIN) {
-        __syncthreads();
-        const uint32_t a = max(pre, c0), b = min(pre + nt, c0 + (uint32_t)EMIT_WIN);
-        for (uint32_t x = a; x < b; x++) s_own[x - c0] = (unsigned char)t;
-        __syncthreads();
-        const uint32_t cend = min(tot, c0 + (uint32_t)EMIT_WIN);
-        for (uint32_t i = c0 + t; i < cend; i += BLOCK) {
-            const int r = s_own[i - c0];
-            const int4 q = s_tp[r];
-            const int nc = s_ncol[r];
-            const int j = (int)(i - s_pre[r]);
-            const int ty = q.x + j / nc, cc = j % nc;
-            const int tx = cc < q.z ? q.y + cc : q.w + (cc - q.z);
-            const uint32_t o = out0 + i;
-            if (o < seg_end) {
-                pkey[o] = (uint32_t)(ty * g.tiles_x + tx);
-                pval[o] = (uint32_t)(p - t + r);
-            } else {
-                atomicOr(err, 4u);
+    size_t q = (size_t)v * Kp + s_vbase + pre.x;
+    uint32_t po = s_pbase + pre.y;
+#pragma unroll
+    for (int j = 0; j < EM1_PER; j++) {
+        if (nt[j]) {
+            srec[2 * q] = r0[j];
+            srec[2 * q + 1] = r1[j];
+            sbox[q] = box[j];
+            vorder[q] = kk[j];
+            poff[q] = po;
+            q++;
+            po += nt[j];
+        }
+    }
+    if (t == 0 && s0 + EM1_CHUNK >= (int64_t)seg_n) {
+        counters[2 * (size_t)v] = s_vbase + tot.x;
+        counters[2 * (size_t)v + 1] = (uint64_t)s_pbase + tot.y;
+    }
+}
+
+// Emission, part 2 (after the counts are known): one (local tile id, sorted
+// position) pair per covered tile of every visible entry, in depth order,
+// into the view's segment of the pair arrays (segments start at multiples of
+// 4096 so the pair sort can treat each view on its own).  One workgroup per
+// EM2_CHUNK visible entries of a view, taken 256 at a time; the first pair
+// slots come from part 1, and for each window of 2048 output slots an LDS
+// table records which entry owns each slot, so consecutive threads write
+// consecutive slots.  The chunk holding the view's last entry writes the
+// segment's padding keys.
+constexpr int EMIT_WIN = 2048;
+
+__global__ __launch_bounds__(BLOCK) void k_emit2(const float4 *__restrict__ sbox, const uint32_t *__restrict__ poff,
+                                                 int64_t Kp, DevGrid g,
+                                                 const unsigned long long *__restrict__ counters,
+                                                 const uint32_t *__restrict__ pbase,
+                                                 const uint32_t *__restrict__ pcount,
+                                                 const uint32_t *__restrict__ chunk_off, int V,
+                                                 uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval)
+{
+    __shared__ unsigned char s_own[EMIT_WIN];
+    __shared__ uint32_t s_pre[BLOCK];
+    __shared__ int4 s_tp[BLOCK];     // ty0, a0, columns in range a, b0
+    __shared__ float2 s_ncol[BLOCK]; // columns, 1 / columns
+    __shared__ uint32_t s_w[4];
+    const int t = threadIdx.x;
+    // the view owning this chunk: the last view whose first chunk is at or
+    // before it, i.e. the number of views after the first with that property
+    // (chunk_off is non-decreasing), counted in one parallel pass
+    uint32_t cnt = 0;
+    for (int i = 1 + t; i < V; i += BLOCK) cnt += chunk_off[i] <= blockIdx.x ? 1u : 0u;
+    uint32_t vcount;
+    (void)block_exclusive_scan(cnt, vcount, s_w);
+    const int v = (int)vcount;
+    const int64_t c0s = (int64_t)(blockIdx.x - chunk_off[v]) * EM2_CHUNK;
+    const int64_t nv = (int64_t)counters[2 * (size_t)v];
+    const uint32_t pb = pbase[v], seg_end = pb + pcount[v];
+    const size_t row = (size_t)v * Kp;
+    float4 e[EM2_PER];
+#pragma unroll
+    for (int j = 0; j < EM2_PER; j++) {
+        const int64_t s = c0s + j * BLOCK + t;
+        e[j] = s < nv ? sbox[row + s] : make_float4(0.f, 0.f, -1.f, -1.f);
+    }
+#pragma unroll
+    for (int j = 0; j < EM2_PER; j++) {
+        const int64_t s0 = c0s + j * BLOCK;
+        if (s0 >= nv) break;   // uniform
+        const int64_t s = s0 + t;
+        uint32_t nt = 0;
+        int4 tp = make_int4(0, 0, 0, 0);
+        int ncol = 1;
+        if (s < nv) {
+            int ty0, ty1, a0, a1, b0, b1;
+            const int nr = tile_rows(e[j].y, e[j].w, g.H, ty0, ty1);
+            const int nc = nr ? tile_cols(e[j].x, e[j].z, g.W, g.tiles_x, a0, a1, b0, b1) : 0;
+            if (nr && nc) {
+                nt = (uint32_t)(nr * nc);
+                ncol = nc;
+                tp = make_int4(ty0, a0, a1 - a0 + 1, b0);
+            }
+        }
+        // (the scan's barriers also order this sub-chunk's table writes after
+        // the previous sub-chunk's reads)
+        uint32_t tot;
+        const uint32_t pre = block_exclusive_scan(nt, tot, s_w);
+        s_pre[t] = pre;
+        s_tp[t] = tp;
+        s_ncol[t] = make_float2((float)ncol, 1.0f / (float)ncol);
+        const uint32_t out0 = pb + poff[row + s0];
+        const size_t p0 = row + (size_t)s0;
+        for (uint32_t c0 = 0; c0 < tot; c0 += EMIT_WIN) {
+            __syncthreads();
+            const uint32_t a = max(pre, c0), b = min(pre + nt, c0 + (uint32_t)EMIT_WIN);
+            for (uint32_t x = a; x < b; x++) s_own[x - c0] = (unsigned char)t;
+            __syncthreads();
+            const uint32_t cend = min(tot, c0 + (uint32_t)EMIT_WIN);
+            for (uint32_t i = c0 + t; i < cend; i += BLOCK) {
+                const int r = s_own[i - c0];
+                const int4 q = s_tp[r];
+                const float2 nc = s_ncol[r];
+                const int jj = (int)(i - s_pre[r]);
+                // jj / columns through the reciprocal (exact after the
+                // correction: jj < 2^24, the quotient is off by at most one)
+                int row_i = (int)((float)jj * nc.y);
+                int cc = jj - row_i * (int)nc.x;
+                if (cc < 0) {
+                    row_i--;
+                    cc += (int)nc.x;
+                } else if (cc >= (int)nc.x) {
+                    row_i++;
+                    cc -= (int)nc.x;
+                }
+                const int ty = q.x + row_i;
+                const int tx = cc < q.z ? q.y + cc : q.w + (cc - q.z);
+                const uint32_t o = out0 + i;
+                if (o < seg_end) {
+                    pkey[o] = (uint32_t)(ty * g.tiles_x + tx);
+                    pval[o] = (uint32_t)(p0 + r);
+                }
             }
         }
     }
-    if (s0 + BLOCK >= nv) {
+    if (c0s + EM2_CHUNK >= nv) {
         // this chunk holds the view's last entry: pad the segment to a whole unit
-        const uint32_t pend = pbase[v] + (uint32_t)(((uint64_t)pcount[v] + SORT_TILE - 1) / SORT_TILE * SORT_TILE);
+        const uint32_t pend = pb + (uint32_t)(((uint64_t)pcount[v] + SORT_TILE - 1) / SORT_TILE * SORT_TILE);
         for (uint32_t o = seg_end + t; o < pend; o += BLOCK) pkey[o] = 0xFFFFFFFFu;
     }
 }
 
-// [start, end) of each (view, tile) list, read from the pair sort's scanned
-// histogram (one 8-bit pass with the tile id as the digit): the start of digit
-// d in the first block of the view's segment, and the start of digit d + 1.
-// one workgroup per view: the pair sort's digit totals of the view are its
+// One workgroup per view: the pair sort's digit totals of the view are its
 // per-tile list lengths; their exclusive scan from the view's segment start
 // gives the lists' positions.  A view without pairs has empty lists (its
 // totals are not read: the sort, and the clearing of its scratch, is skipped
@@ -1260,38 +1406,56 @@ hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t 
 {
     if (sc.K > 0)
         hipLaunchKernelGGL(k_gauss_prep, dim3((unsigned)((sc.K + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st,
-                           sc.soa.as<float>(), sc.K, ws.ggeo.as<GaussGeoPacked>());
+                           sc.soa.as<float>(), sc.K, ws.ggeo.as<GaussGeoPacked>(), ws.qcull.as<float>());
     const int vchunk = V <= 4 ? 1 : 4;
     dim3 grid((unsigned)(Kp / BLOCK), (unsigned)((V + vchunk - 1) / vchunk));
-    hipLaunchKernelGGL(k_project, grid, dim3(BLOCK), 0, st, ws.ggeo.as<GaussGeoPacked>(), sc.K, Kp, centres, V,
-                       vchunk, g,
-                       ws.skey[0].as<uint32_t>(), ws.sval[0].as<uint32_t>(), ws.counters.as<unsigned long long>(),
-                       keep_boxes ? ws.ext.as<float4>() : nullptr, keep_boxes ? ws.rawkey.as<uint32_t>() : nullptr,
-                       keep_boxes ? ws.opac.as<float>() : nullptr);
+    if (keep_boxes)
+        hipLaunchKernelGGL(k_project<true>, grid, dim3(BLOCK), 0, st, ws.ggeo.as<GaussGeoPacked>(),
+                           ws.qcull.as<float>(), sc.K, Kp, centres, V, vchunk, g, ws.skey[0].as<uint32_t>(),
+                           ws.sval[0].as<uint32_t>(), ws.ext.as<float4>(), ws.rawkey.as<uint32_t>(),
+                           ws.opac.as<float>());
+    else
+        hipLaunchKernelGGL(k_project<false>, grid, dim3(BLOCK), 0, st, ws.ggeo.as<GaussGeoPacked>(),
+                           ws.qcull.as<float>(), sc.K, Kp, centres, V, vchunk, g, ws.skey[0].as<uint32_t>(),
+                           ws.sval[0].as<uint32_t>(), nullptr, nullptr, nullptr);
     return hipGetLastError();
 }
 
-// the emission kernel's error word, per-view tickets and per-chunk look-back
-// status, after the render statistics in the counters buffer
+// the emission's error word, per-view tickets and per-chunk 64-bit look-back
+// status, after the render statistics in the counters buffer (the offset is
+// even, so the status words are 8-byte aligned)
 uint32_t *emit_words(Workspace &ws)
 {
     return ws.counters.as<uint32_t>() + (size_t)4 * ws.V + AMAX_SLOTS + 2 * STAT_WORDS;
 }
 
-size_t emit_word_count(int V, int64_t VK)
+size_t emit_word_count(int V, int64_t Kp)
 {
-    return EM_TICKET_STRIDE + (size_t)V * EM_TICKET_STRIDE + (size_t)(VK / BLOCK);
+    return EM_TICKET_STRIDE + (size_t)V * EM_TICKET_STRIDE + 2 * (size_t)V * (size_t)((Kp + BLOCK - 1) / BLOCK);
 }
 
-hipError_t launch_emit(const Scene &sc, Workspace &ws, const DevGrid &g, hipStream_t st)
+hipError_t launch_emit1(const Scene &sc, Workspace &ws, const DevGrid &g, hipStream_t st)
+{
+    uint32_t *ew = emit_words(ws);
+    const bool wide = (size_t)ws.V * (size_t)(ws.Kp / (4 * BLOCK)) >= 1024;
+    const int per = wide ? 4 : 1;
+    const int cpv = (int)((ws.Kp + per * BLOCK - 1) / (per * BLOCK));
+    auto kern = wide ? k_emit1<4> : k_emit1<1>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(ws.V * cpv)), dim3(BLOCK), 0, st, ws.ggeo.as<GaussGeoPacked>(), sc.K,
+                       ws.Kp, ws.centres_p, g, ws.sval[ws.sorted_buf].as<uint32_t>(), ws.hist.as<uint32_t>(), 4, cpv,
+                       ws.srec.as<float4>(), ws.sbox.as<float4>(), ws.vorder.as<uint32_t>(), ws.poff.as<uint32_t>(),
+                       ws.counters.as<unsigned long long>(),
+                       reinterpret_cast<unsigned long long *>(ew + EM_TICKET_STRIDE + (size_t)ws.V * EM_TICKET_STRIDE),
+                       ew + EM_TICKET_STRIDE, ew);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit2(Workspace &ws, const DevGrid &g, hipStream_t st)
 {
     if (ws.n_emit_chunks == 0) return hipSuccess;
-    uint32_t *ew = emit_words(ws);
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)ws.n_emit_chunks), dim3(BLOCK), 0, st, ws.ggeo.as<GaussGeoPacked>(),
-                       sc.K, ws.Kp, ws.centres_p, g, ws.sval[ws.sorted_buf].as<uint32_t>(),
-                       ws.counters.as<unsigned long long>(), ws.d_pbase, ws.d_pcount, ws.d_chunk_off, ws.V,
-                       ws.srec.as<float4>(), ws.pkey[0].as<uint32_t>(), ws.pval[0].as<uint32_t>(),
-                       ew + EM_TICKET_STRIDE + (size_t)ws.V * EM_TICKET_STRIDE, ew + EM_TICKET_STRIDE, ew);
+    hipLaunchKernelGGL(k_emit2, dim3((unsigned)ws.n_emit_chunks), dim3(BLOCK), 0, st, ws.sbox.as<float4>(),
+                       ws.poff.as<uint32_t>(), ws.Kp, g, ws.counters.as<unsigned long long>(), ws.d_pbase,
+                       ws.d_pcount, ws.d_chunk_off, ws.V, ws.pkey[0].as<uint32_t>(), ws.pval[0].as<uint32_t>());
     return hipGetLastError();
 }
 
@@ -1317,7 +1481,7 @@ hipError_t launch_rad_direct(const Scene &sc, Workspace &ws, hipStream_t st)
     const int64_t n = (int64_t)ws.N * ws.Kp;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_rad_direct, dim3(nblk(n)), dim3(BLOCK), 0, st, sc.rad.as<float2>(),
-                       ws.sval[ws.sorted_buf].as<uint32_t>(), ws.counters.as<unsigned long long>(),
+                       ws.vorder.as<uint32_t>(), ws.counters.as<unsigned long long>(),
                        ws.d_rxview, ws.N, ws.Kp, ws.K, ws.rad.as<float2>());
     return hipGetLastError();
 }
@@ -1374,7 +1538,7 @@ hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStr
         if (m.fp32) {
             hipLaunchKernelGGL(k_mlp_pairs_f32, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                                ws.Gp.as<float>(), m.w2a.as<float>(), m.tab.as<float4>(), b3,
-                               ws.sval[ws.sorted_buf].as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K,
+                               ws.vorder.as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K,
                                ws.counters.as<unsigned long long>(), ws.rad.as<float2>());
         } else if (mlp_fused_ok(sc, m)) {
             // bound of the Gaussians' layer-1 term: per hidden unit
@@ -1385,13 +1549,13 @@ hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStr
             hipLaunchKernelGGL(k_mlp_pairs<true>, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                                sc.feat.as<float>(), ws.Gp.as<float>(), m.w2h.as<half8>(), m.tabh.as<float4>(), b3,
                                m.w1h.as<half8>(), m.b1tab.as<float>(), std::ldexp(1.f, -m.w1exp), lbound,
-                               ws.sval[ws.sorted_buf].as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K,
+                               ws.vorder.as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K,
                                amax_words(ws), ws.rad.as<float2>());
         } else {
             hipLaunchKernelGGL(k_mlp_pairs<false>, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                                sc.feat.as<float>(), ws.Gp.as<float>(), m.w2h.as<half8>(), m.tabh.as<float4>(), b3,
                                m.w1h.as<half8>(), m.b1tab.as<float>(), 1.f, 0.f,
-                               ws.sval[ws.sorted_buf].as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K,
+                               ws.vorder.as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K,
                                amax_words(ws), ws.rad.as<float2>());
         }
     }

@@ -122,6 +122,7 @@ void free_workspace(Workspace &ws)
 {
     DevBuf *bufs[] = {&ws.centres, &ws.rxpos,   &ws.desc,   &ws.ext,     &ws.rawkey, &ws.opac,
                       &ws.skey[0], &ws.skey[1], &ws.sval[0], &ws.sval[1], &ws.srec,    &ws.ggeo,
+                      &ws.qcull,   &ws.sbox,    &ws.vorder, &ws.poff,
                       &ws.pkey[0], &ws.pkey[1], &ws.pval[0], &ws.pval[1], &ws.ranges, &ws.rad,
                       &ws.Lp,      &ws.Gp,      &ws.items,  &ws.Tfin,   &ws.nlast,  &ws.part,
                       &ws.counters, &ws.hist,   &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
@@ -633,11 +634,15 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         GROW(ctx, ws.sval[b], VK * 4);
     }
     GROW(ctx, ws.srec, VK * 32);
+    GROW(ctx, ws.sbox, VK * 16);
+    GROW(ctx, ws.vorder, VK * 4);
+    GROW(ctx, ws.poff, VK * 4);
     GROW(ctx, ws.ggeo, (size_t)std::max<int64_t>(K, 1) * 80);
+    GROW(ctx, ws.qcull, (size_t)std::max<int64_t>(K, 1) * 4);
     // per view (visible count, pair count); slots for the largest |layer-1
     // term| of the receivers and of the Gaussians (FP32 bits); render
     // statistics; the emission's ticket, error word and look-back status
-    const size_t emit_words_n = emit_word_count(V, (int64_t)VK);
+    const size_t emit_words_n = emit_word_count(V, Kp);
     const size_t cnt_words = (size_t)4 * V + AMAX_SLOTS + 2 * STAT_WORDS + emit_words_n;
     GROW(ctx, ws.counters, cnt_words * 4);
     GROW(ctx, ws.hist, sort_ws_bytes((uint32_t)VK, 32, V));
@@ -654,16 +659,21 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     }
     HIPCHK(ctx, launch_fill_u32(ws.counters.as<uint32_t>(), 0u, cnt_words, st));
 
-    // stage 1: projection, then the per-view depth sort; the host waits only
-    // for the counters (visible Gaussians per view, pair count) while the sort runs
+    // stage 1: depth keys (with the cheap culls), the per-view depth sort,
+    // then the exact projection in depth order, which compacts the visible
+    // entries and counts them and their pairs; the host waits only for those
+    // counts
     STAGE(ctx, "project", launch_project(sc, ws.centres_p, V, Kp, g, ws, saved != nullptr, st));
-    if (!ensure_pinned(ws, (size_t)2 * V * 8 + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
-    unsigned long long *h_cnt = static_cast<unsigned long long *>(ws.h_pinned);
-    HIPCHK(ctx, hipMemcpyAsync(h_cnt, ws.counters.p, (size_t)2 * V * 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(ctx, hipEventRecord(ws.counted, st));
     int cur = 0;
     STAGE(ctx, "sort_depth", sort_pairs_u32(ws.skey, ws.sval, ws.hist, cur, (uint32_t)VK, 32, V, Kp, nullptr, st));
     ws.sorted_buf = cur;
+    STAGE(ctx, "emit_records", launch_emit1(sc, ws, g, st));
+    if (!ensure_pinned(ws, (size_t)2 * V * 8 + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
+    unsigned long long *h_cnt = static_cast<unsigned long long *>(ws.h_pinned);
+    uint32_t *h_err = reinterpret_cast<uint32_t *>(h_cnt + 2 * (size_t)V);
+    HIPCHK(ctx, hipMemcpyAsync(h_cnt, ws.counters.p, (size_t)2 * V * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipMemcpyAsync(h_err, emit_words(ws), 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipEventRecord(ws.counted, st));
 
     // receiver chunks of the blend (independent of the counters: built while
     // the GPU projects and sorts); the receivers of a view are consecutive
@@ -689,6 +699,8 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     ws.n_tslots = (mode == RXGS_MODE_TX) ? V : N;
 
     HIPCHK(ctx, hipEventSynchronize(ws.counted));
+    if (*h_err & 2u) return fail(ctx, RXGS_E_INVALID, "more than 2^32 - 1 pairs in one view; use a coarser grid");
+    if (*h_err) return fail(ctx, RXGS_E_DEVICE, "emission look-back did not complete");
 
     // pairs per view; each view's pairs get a segment padded to whole sort blocks
     uint64_t D = 0, Dpad = 0;
@@ -729,9 +741,10 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         vinfo[v] = make_int4(vfirst[v], vnrx[v], ws.h_nvis[v], 0);
     }
     ws.n_items = (int)item_off[V];
-    // emission chunks: 256 visible entries of one view each
+    // pair-emission chunks: EM2_CHUNK visible entries of one view each
     std::vector<uint32_t> chunk_off(V + 1, 0);
-    for (int v = 0; v < V; v++) chunk_off[v + 1] = chunk_off[v] + (uint32_t)((ws.h_nvis[v] + BLOCK - 1) / BLOCK);
+    for (int v = 0; v < V; v++)
+        chunk_off[v + 1] = chunk_off[v] + (uint32_t)((ws.h_nvis[v] + EM2_CHUNK - 1) / EM2_CHUNK);
     ws.n_emit_chunks = (int)chunk_off[V];
 
     const size_t P = (size_t)g.H * g.W;
@@ -761,7 +774,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     const size_t o_pcount = o_pbase + al16((size_t)V * 4);
     const size_t o_segtab = o_pcount + al16((size_t)V * 4);
     const size_t stage_bytes = o_segtab + segtab.size() * 16;
-    const size_t cnt_bytes = (size_t)2 * V * 8;
+    const size_t cnt_bytes = (size_t)2 * V * 8 + 4;   // counters and the emission error word
     const size_t off0 = (cnt_bytes + 63) / 64 * 64;
     if (!ensure_pinned(ws, off0 + stage_bytes + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
     GROW(ctx, ws.desc, stage_bytes);
@@ -789,7 +802,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     // pairs: emit in depth order, stable sort by (view, tile), tile ranges
     int pcur = 0;
     if (D > 0) {
-        STAGE(ctx, "emit", launch_emit(sc, ws, g, st));
+        STAGE(ctx, "emit_pairs", launch_emit2(ws, g, st));
         const int sbits = std::max(bits_for((uint64_t)g.tiles), 1);
         STAGE(ctx, "sort_pairs", sort_pairs_u32(ws.pkey, ws.pval, ws.hist_b, pcur, (uint32_t)Dpad, sbits, V, 0,
                                                 ws.d_segtab, st));
@@ -915,7 +928,7 @@ extern "C" rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *ds
     case RXGS_EXPORT_BIN: src = ws.ext.p; n = VK * 16; break;
     case RXGS_EXPORT_KEYS: src = ws.rawkey.p; n = VK * 4; break;
     case RXGS_EXPORT_OPACITY: src = ws.opac.p; n = VK * 4; break;
-    case RXGS_EXPORT_ORDER: src = ws.sval[ws.sorted_buf].p; n = VK * 4; break;
+    case RXGS_EXPORT_ORDER: src = ws.vorder.p; n = VK * 4; break;
     case RXGS_EXPORT_NVIS:
         tmp = ws.h_nvis;
         src = tmp.data();

@@ -27,6 +27,8 @@ constexpr int AMAX_SLOTS = 128;          // activation-bound words after the vie
 constexpr int STAT_SLOTS = 64;           // u64 slots per render statistic (spread atomics)
 constexpr int STAT_WORDS = 4 * STAT_SLOTS;   // four statistics, u64 each
 constexpr uint32_t SMALL_SORT = 1u << 20;  // sorts up to this length use 1024-key blocks
+constexpr int EM2_PER = 1;               // pair emission: 256-entry sub-chunks per workgroup
+constexpr int EM2_CHUNK = BLOCK * EM2_PER;
 
 // Method constants (Alg. 1 compositing and the readings of its unstated values).
 constexpr float ALPHA_MIN = 1.0f / 255.0f;   // skip threshold on the blend weight
@@ -109,13 +111,17 @@ struct Workspace {
     DevBuf sval[2];   // V x Kp u32 sort values
     int sorted_buf = 0;
     DevBuf ggeo;      // K x 80 B view-independent projection terms of every Gaussian
-    DevBuf srec;      // V x Kp x 2 float4 blend records in depth order
+    DevBuf qcull;     // K f32 elevation-cull bound of every Gaussian
+    DevBuf srec;      // V x Kp x 2 float4 blend records of the visible entries in depth order
+    DevBuf sbox;      // V x Kp float4 binning boxes (u, v, rup, rvp), same order
+    DevBuf vorder;    // V x Kp u32 Gaussian of each visible entry, same order
+    DevBuf poff;      // V x Kp u32 first pair slot of each visible entry within its view
     DevBuf desc;      // small descriptors copied from the host in one transfer:
     int *d_rxview = nullptr;       //   N: view of each receiver
     int4 *d_chunks = nullptr;      //   blend chunks (view, first receiver, receivers, T slot)
     int4 *d_vinfo = nullptr;       //   V: (first receiver, receivers, visible Gaussians, 0)
     uint32_t *d_item_off = nullptr;  // V + 1: first MLP work item of each view
-    uint32_t *d_chunk_off = nullptr;  // V + 1: first emission chunk (256 visible entries) of each view
+    uint32_t *d_chunk_off = nullptr;  // V + 1: first pair-emission chunk (EM2_CHUNK visible entries) of each view
     int n_emit_chunks = 0;
     uint32_t *d_pbase = nullptr;   //   V: start of each view's segment of the pair arrays
     uint32_t *d_pcount = nullptr;  //   V: pairs of each view
@@ -216,9 +222,10 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st
 hipError_t sort_pairs_u32(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
                           int64_t seg_len, const int4 *segtab, hipStream_t st);
 size_t sort_ws_bytes(uint32_t n, int bits, int nseg);
-hipError_t launch_emit(const Scene &sc, Workspace &ws, const DevGrid &g, hipStream_t st);
+hipError_t launch_emit1(const Scene &sc, Workspace &ws, const DevGrid &g, hipStream_t st);
+hipError_t launch_emit2(Workspace &ws, const DevGrid &g, hipStream_t st);
 uint32_t *emit_words(Workspace &ws);
-size_t emit_word_count(int V, int64_t VK);
+size_t emit_word_count(int V, int64_t Kp);
 hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st);
 hipError_t launch_rad_direct(const Scene &sc, Workspace &ws, hipStream_t st);
 hipError_t launch_mlp_global(const Mlp &m, Workspace &ws, hipStream_t st);

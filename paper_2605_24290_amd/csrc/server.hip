@@ -103,13 +103,14 @@ extern "C" int64_t rxgs_workspace_estimate(int32_t mode, int32_t Q, int32_t N, i
     const int64_t P = (int64_t)H * W;
     const int64_t tiles = (int64_t)((H + TILE - 1) / TILE) * ((W + TILE - 1) / TILE);
     const int64_t D_est = 6 * V * std::max<int64_t>(K, 1);
-    int64_t b = VK * 52;                // keys and values (ping-pong), sorted records, sort and emission scratch
+    int64_t b = VK * 76;                // keys and values (ping-pong), sorted records, boxes, order, pair
+                                        // offsets, sort and emission scratch
     b += D_est * 16;                    // pair keys and values, ping-pong
     b += (int64_t)N * Kp * 8;           // radiance
     b += (int64_t)N * P * 8;            // spectra
     b += (mode == RXGS_MODE_TX ? V : N) * P * 8;   // final transmittance, stop index
     b += (int64_t)N * tiles * 12 + V * tiles * 8;  // partial sums, ranges
-    b += std::max<int64_t>(K, 1) * (256 + 80) + (int64_t)N * 256;  // MLP layer-1 terms, projection terms
+    b += std::max<int64_t>(K, 1) * (256 + 84) + (int64_t)N * 256;  // MLP layer-1 terms, projection terms
     return b;
 }
 
