@@ -254,7 +254,7 @@ def roofline_for(entry, mode, workload):
             per_view = sz["composited_px"] / max(sz["chunks_per_view"], 1)
             ops = BLEND_OPS_PER_PAIR * per_view + BLEND_OPS_PER_EXTRA_RX * (sz["composited"] - per_view)
         ach = ops / t_s / 1e12
-        return {"kernel": "k_blend_fwd", "bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS,
+        return {"kernel": "k_blend_fwd1", "bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS,
                 "unit": "Tops/s", "frac": ach / PEAK_VALU_TOPS,
                 "traffic": stored_traffic("k_blend_fwd", workload),
                 "work": f"{BLEND_OPS_PER_PAIR} lane-ops x {sz['composited']} composited (pixel, Gaussian) pairs"}

@@ -1156,21 +1156,313 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) v
 // ----------------------------------------------------------------------------
 // Stage 3: front-to-back compositing.  One workgroup per (tile, chunk of R
 // receivers of one view); one pixel per thread, each wave an 8 x 8 sub-tile.
-// Batches of 256 list entries (record + R radiance values) are staged in LDS;
-// while staging, each entry's conservative support box is tested against the
-// four sub-tiles and a ballot/prefix pass builds, per wave, the ordered list of
-// entries that can reach it, so a wave walks only those.  Every lane keeps its
-// own transmittance; a wave stops once all its lanes have terminated and the
+// Batches of 256 list entries are staged in LDS; while staging, each entry's
+// conservative support box is tested against the four sub-tiles and a
+// ballot/prefix pass builds, per wave, the ordered list of entries that can
+// reach it, so a wave walks only those.  Every lane keeps its own
+// transmittance; a wave stops once all its lanes have terminated and the
 // workgroup stops staging once all its waves have.
+//
+// Two kernels.  With one receiver per workgroup (RX mode, and TX chunks of one
+// receiver) the staged form is per (wave, entry), so the walk needs no
+// indirection: with
+// (X, Y) a pixel's offset from its sub-tile's centre (lane constants, halves
+// of odd integers) and (du0, dv0) the entry's centre-to-sub-tile-centre offset,
+// the blend exponent (the log2 weight, Sec. 4.3 Eq. for alpha) is the quadratic
+//   E = E0 + gx X + gy Y + a X^2 + b XY + c Y^2,
+//   E0 = du0 (a du0 + b dv0) + c dv0^2 + log2 o,  gx = 2 a du0 + b dv0,
+//   gy = b du0 + 2 c dv0,
+// evaluated in five FMAs.  A batch holding an entry that spans more than half
+// the azimuth circle keeps (du0, dv0, log2 o) instead and wraps each pixel's
+// azimuth offset into [-W/2, W/2).  Record (32 B): (E0 | du0, gx | dv0,
+// gy | log2 o, a), (b, c, radiance).  With several receivers per workgroup
+// (TX chunks) the walk is bound by broadcasting their radiance from LDS, and
+// the shared per-entry form below serves better (k_blend_fwd_multi).
 
-// One wave's walk over its staged list, free of branches per entry: an entry
+// entries per staged batch (five workgroups per CU)
+constexpr int NB1 = BLOCK / 2;
+
+template <int NB> struct BlendFwdStage {
+    float4 q[4][NB][2];              // per wave, in list order
+    unsigned short list[4][NB];      // per wave: batch index of each entry
+    int len[4];
+    int wcnt[4][4];
+    int wide[4];
+};
+
+// Conservative sub-tile mask of one record (the hardware reciprocal and square
+// root, with a relative margin far above their error): bit w set when the box
+// around the ellipse {E >= log2(1/255)} meets wave w's 8 x 8 sub-tile.
+__device__ __forceinline__ int subtile_mask_fast(const float4 &r0, const float4 &r1, int wide, int tx, int ty)
+{
+    if (wide) return 0xF;
+    float lo = r1.w - (-7.99435343685886f);   // log2 o - log2(1/255)
+    if (!(lo >= -1e-3f)) return 0;
+    lo = fmaxf(lo, 0.f) + 1e-3f;
+    const float muu = -r1.x, muv = -0.5f * r1.y, mvv = -r1.z;
+    const float det = muu * mvv - muv * muv;
+    if (!(det > 0.f)) return 0xF;
+    const float q = lo * __builtin_amdgcn_rcpf(det);
+    const float ru = __builtin_amdgcn_sqrtf(q * mvv) * 1.001f + 0.05f;
+    const float rv = __builtin_amdgcn_sqrtf(q * muu) * 1.001f + 0.05f;
+    const float u = r0.x + r0.y, v = r0.z + r0.w;
+    const float c0 = (float)(tx * TILE), r0f = (float)(ty * TILE);
+    int m = 0;
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+        const float cl = c0 + 8.f * (float)(w & 1), rl = r0f + 8.f * (float)(w >> 1);
+        const bool hit = (u + ru >= cl) && (u - ru <= cl + 7.f) && (v + rv >= rl) && (v - rv <= rl + 7.f);
+        m |= hit ? (1 << w) : 0;
+    }
+    return m;
+}
+
+// Stage one batch (this thread's entry, if `has`, with its radiance rv) into
+// per-wave records.  All threads of the workgroup call it; on return st.len,
+// st.wide and the records of every wave are final (lists padded with
+// zero-weight records to a multiple of 4).
+template <int NB>
+__device__ __forceinline__ void stage_fwd(BlendFwdStage<NB> &st, const float4 *__restrict__ srec, uint32_t p, bool has,
+                                          float2 rv, int tx, int ty, const DevGrid &g, float invW)
+{
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    int m = 0, wide = 0;
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+    const float Wf = (float)g.W, halfW = 0.5f * (float)g.W;
+    if (has) {
+        r0 = srec[2 * (size_t)p];
+        r1 = srec[2 * (size_t)p + 1];
+        const float tcol = (float)(tx * TILE) + 7.5f;
+        // representative of the azimuth closest to this tile's centre (the
+        // box of a non-wide entry in this tile's list keeps its centre well
+        // inside half a circle of it, so the rounding of the quotient cannot
+        // change the choice)
+        const float sh = rintf((tcol - r0.x) * invW);
+        r0.x = fmaf(sh, Wf, r0.x);
+        wide = fabsf(tcol - (r0.x + r0.y)) >= halfW - 9.0f;
+        m = subtile_mask_fast(r0, r1, wide, tx, ty);
+    }
+    uint64_t bal[4];
+#pragma unroll
+    for (int b = 0; b < 4; b++) bal[b] = __ballot((m >> b) & 1);
+    const uint64_t wide_bal = __ballot(wide);
+    if (lane == 0) {
+#pragma unroll
+        for (int b = 0; b < 4; b++) st.wcnt[w][b] = (int)__popcll(bal[b]);
+        st.wide[w] = wide_bal ? 1 : 0;
+    }
+    __syncthreads();
+    const bool anywide = (st.wide[0] | st.wide[1] | st.wide[2] | st.wide[3]) != 0;
+    if (m) {
+        const float a = r1.x, bb = r1.y, c = r1.z;
+        const float4 q1 = make_float4(bb, c, rv.x, rv.y);
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            if ((m >> b) & 1) {
+                int pos = count_below(bal[b]);
+                for (int ww = 0; ww < w; ww++) pos += st.wcnt[ww][b];
+                const float colc = (float)(tx * TILE + 8 * (b & 1)) + 3.5f;
+                const float rowc = (float)(ty * TILE + 8 * (b >> 1)) + 3.5f;
+                const float du0 = (colc - r0.x) - r0.y;
+                const float dv0 = (rowc - r0.z) - r0.w;
+                float4 q0;
+                if (anywide) {
+                    q0 = make_float4(du0, dv0, r1.w, a);
+                } else {
+                    const float e0 = fmaf(du0, fmaf(a, du0, bb * dv0), fmaf(c * dv0, dv0, r1.w));
+                    q0 = make_float4(e0, fmaf(2.f * a, du0, bb * dv0), fmaf(bb, du0, 2.f * c * dv0), a);
+                }
+                st.q[b][pos][0] = q0;
+                st.q[b][pos][1] = q1;
+                st.list[b][pos] = (unsigned short)t;
+            }
+        }
+    }
+    if (t < 4) {
+        const int n = st.wcnt[0][t] + st.wcnt[1][t] + st.wcnt[2][t] + st.wcnt[3][t];
+        st.len[t] = n;
+        // zero-weight padding: E = -inf in either form (only the constant
+        // term is infinite, so no product of infinity and zero arises)
+        const float4 pad = anywide ? make_float4(0.f, 0.f, -INFINITY, 0.f) : make_float4(-INFINITY, 0.f, 0.f, 0.f);
+        for (int k = n; k < ((n + 3) & ~3); k++) {
+            st.q[t][k][0] = pad;
+            st.q[t][k][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            st.list[t][k] = 0;
+        }
+    }
+    __syncthreads();
+}
+
+// One wave's walk over its staged list (length n, padded to a multiple of
+// 4, four entries in flight), free of branches per entry: an entry below the
+// alpha threshold, or met after the lane terminated, gets weight 0, which
+// leaves T and the sums unchanged.  WRAP: the list is in the wrapped form.
+// SAVE: track the stop index and the composited count (saved states and
+// statistics only).
+template <bool SAVE, bool WRAP, int NB>
+__device__ __forceinline__ void blend_walk1(const BlendFwdStage<NB> &st, int wv, int n, int lbase, float X, float Y,
+                                            float XX, float XY, float YY, float Wf, float halfW, float &T,
+                                            float2 &acc, int &last, uint32_t &ncomp, uint32_t &neval,
+                                            uint32_t &nslot, bool &done)
+{
+    for (int i0 = 0; i0 < n; i0 += 4) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int i = i0 + k;
+            if (SAVE) {
+                const bool real = i < n;
+                neval += (real && !done) ? 1u : 0u;
+                nslot += real ? 1u : 0u;
+            }
+            const float4 q0 = st.q[wv][i][0];
+            const float4 q1 = st.q[wv][i][1];
+            float ex;
+            if (WRAP) {
+                float du = q0.x + X;
+                du = du >= halfW ? du - Wf : du;
+                du = du < -halfW ? du + Wf : du;
+                const float dv = q0.y + Y;
+                ex = fmaf(du, fmaf(q0.w, du, q1.x * dv), fmaf(q1.y * dv, dv, q0.z));
+            } else {
+                ex = fmaf(q1.y, YY, fmaf(q1.x, XY, fmaf(q0.w, XX, fmaf(q0.z, Y, fmaf(q0.y, X, q0.x)))));
+            }
+            float w = fminf(W_MAX, __builtin_amdgcn_exp2f(ex));
+            const bool inc = !done && w >= ALPHA_MIN;
+            w = inc ? w : 0.f;
+            const float tw = T * w;
+            acc.x = fmaf(tw, q1.z, acc.x);
+            acc.y = fmaf(tw, q1.w, acc.y);
+            T = T - tw;
+            if (SAVE) {
+                last = inc ? lbase + (int)st.list[wv][i] : last;
+                ncomp += inc ? 1u : 0u;
+            }
+            done = done || T < T_EPS;
+        }
+        if (__all(done)) break;
+    }
+}
+
+template <bool SAVE>
+__global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__ srec,
+                                                      const uint32_t *__restrict__ pval,
+                                                      const uint2 *__restrict__ ranges,
+                                                      const float2 *__restrict__ rad,
+                                                      const int4 *__restrict__ chunks, int64_t Kp, DevGrid g,
+                                                      float *__restrict__ C, float *__restrict__ Tfin,
+                                                      int *__restrict__ nlast, float *__restrict__ part,
+                                                      unsigned long long *__restrict__ stats)
+{
+    constexpr int NB = NB1;
+    __shared__ BlendFwdStage<NB> st;
+    __shared__ float s_red[4][3];
+
+    const int tile = blockIdx.x;
+    const int4 ch = chunks[blockIdx.y];
+    const int view = ch.x, j0 = ch.y, nrx = ch.z, tslot = ch.w;
+    const int ty = tile / g.tiles_x, tx = tile - ty * g.tiles_x;
+    const int t = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
+    const int row = ty * TILE + 8 * (wv >> 1) + (lane >> 3), col = tx * TILE + 8 * (wv & 1) + (lane & 7);
+    const bool inside = row < g.H && col < g.W;
+    const float X = (float)(lane & 7) - 3.5f, Y = (float)(lane >> 3) - 3.5f;
+    const float XX = X * X, XY = X * Y, YY = Y * Y;
+    const float Wf = (float)g.W, halfW = 0.5f * (float)g.W, invW = 1.0f / (float)g.W;
+    const uint2 rg = ranges[(size_t)view * g.tiles + tile];
+    const int64_t view_end = ((int64_t)view + 1) * Kp;
+
+    float T = 1.f;
+    float2 acc = make_float2(0.f, 0.f);
+    int last = 0;
+    uint32_t ncomp = 0, neval = 0, nslot = 0;   // composited / evaluated while active / walked (SAVE)
+    bool done = !inside;
+
+    for (uint32_t base = rg.x; base < rg.y; base += NB) {
+        const uint32_t cnt = min((uint32_t)NB, rg.y - base);
+        __syncthreads();
+        uint32_t p = 0;
+        float2 rv = make_float2(0.f, 0.f);
+        if ((uint32_t)t < cnt) {
+            p = min(pval[base + t], (uint32_t)(view_end - 1));
+            const int64_t s = max((int64_t)p - (int64_t)view * Kp, (int64_t)0);
+            rv = rad[(size_t)j0 * Kp + s];
+        }
+        stage_fwd<NB>(st, srec, p, (uint32_t)t < cnt, rv, tx, ty, g, invW);
+        if (__any(!done)) {
+            const int n = __builtin_amdgcn_readfirstlane(st.len[wv]);
+            const int lbase = (int)(base - rg.x) + 1;
+            if (st.wide[0] | st.wide[1] | st.wide[2] | st.wide[3])
+                blend_walk1<SAVE, true>(st, wv, n, lbase, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
+                                        nslot, done);
+            else
+                blend_walk1<SAVE, false>(st, wv, n, lbase, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
+                                         nslot, done);
+        }
+        if (__syncthreads_and(done ? 1 : 0)) break;
+    }
+
+    const size_t P = (size_t)g.H * g.W;
+    const size_t pix = (size_t)row * g.W + col;
+    if (inside && nrx > 0) {
+        C[((size_t)j0 * 2) * P + pix] = acc.x;
+        C[((size_t)j0 * 2 + 1) * P + pix] = acc.y;
+        if (SAVE && tslot >= 0) {
+            Tfin[(size_t)tslot * P + pix] = T;
+            nlast[(size_t)tslot * P + pix] = last;
+        }
+    }
+    // per-tile partial sums: power, Re, Im (fixed-order reduction)
+    {
+        const float pw = wave_sum_f32(acc.x * acc.x + acc.y * acc.y);
+        const float sr = wave_sum_f32(acc.x);
+        const float si = wave_sum_f32(acc.y);
+        if (lane == 0) {
+            s_red[wv][0] = pw;
+            s_red[wv][1] = sr;
+            s_red[wv][2] = si;
+        }
+    }
+    if (SAVE) {
+        const uint32_t nc = wave_sum_u32(ncomp), ne = wave_sum_u32(neval), ns = wave_sum_u32(nslot);
+        if (lane == 0) {
+            st.wcnt[0][wv] = (int)nc;
+            st.wcnt[1][wv] = (int)ne;
+            st.wcnt[2][wv] = (int)ns;
+        }
+    }
+    __syncthreads();
+    if (t < 3 && nrx > 0) {
+        const float v = ((s_red[0][t] + s_red[1][t]) + s_red[2][t]) + s_red[3][t];
+        part[((size_t)j0 * g.tiles + tile) * 3 + t] = v;
+    }
+    // composited (pixel, entry) pairs: per chunk pixel and per receiver pixel,
+    // spread over STAT_SLOTS counters
+    if (SAVE && t == 0) {
+        const unsigned slot = (blockIdx.x + blockIdx.y * gridDim.x) % STAT_SLOTS;
+        unsigned long long n[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+            n[c] = (unsigned long long)st.wcnt[c][0] + st.wcnt[c][1] + st.wcnt[c][2] + st.wcnt[c][3];
+        if (n[0]) {
+            atomicAdd(stats + slot, n[0]);
+            atomicAdd(stats + STAT_SLOTS + slot, n[0] * (unsigned long long)nrx);
+        }
+        if (n[2]) {
+            atomicAdd(stats + 2 * STAT_SLOTS + slot, n[1]);
+            atomicAdd(stats + 3 * STAT_SLOTS + slot, n[2]);
+        }
+    }
+}
+
+// Several receivers per workgroup: entries staged once per batch (record,
+// batch index lists per wave), radiance of the R receivers in LDS.  One wave's
+// walk over its staged list, free of branches per entry: an entry
 // below the alpha threshold, or met after the lane terminated, gets weight 0,
 // which leaves T and the sums bit-identical to skipping it.  WRAP: some entry of
 // the list spans more than half the azimuth circle, so pixel offsets are
 // wrapped into [-W/2, W/2) (selects).  SAVE: track the stop index and the
 // composited count (saved states and statistics only).
 template <int R, bool SAVE, bool WRAP>
-__device__ __forceinline__ void blend_walk(const BlendStage &st, const float2 (*s_rad)[BLOCK], int wv, int n,
+__device__ __forceinline__ void blend_walk_multi(const BlendStage &st, const float2 (*s_rad)[BLOCK], int wv, int n,
                                            int lbase, float colf, float rowf, float Wf, float halfW, float &T,
                                            float2 (&acc)[R], int &last, uint32_t &ncomp, uint32_t &neval,
                                            uint32_t &nslot, bool &done)
@@ -1210,7 +1502,7 @@ __device__ __forceinline__ void blend_walk(const BlendStage &st, const float2 (*
 }
 
 template <int R, bool SAVE>
-__global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ srec,
+__global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restrict__ srec,
                                                      const uint32_t *__restrict__ pval,
                                                      const uint2 *__restrict__ ranges,
                                                      const float2 *__restrict__ rad,
@@ -1259,10 +1551,10 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd(const float4 *__restrict__ 
             const int n = __builtin_amdgcn_readfirstlane(st.len[wv]);
             const int lbase = (int)(base - rg.x) + 1;
             if (__builtin_amdgcn_readfirstlane(st.wrap[wv]))
-                blend_walk<R, SAVE, true>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T, acc, last, ncomp,
+                blend_walk_multi<R, SAVE, true>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T, acc, last, ncomp,
                                           neval, nslot, done);
             else
-                blend_walk<R, SAVE, false>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T, acc, last, ncomp,
+                blend_walk_multi<R, SAVE, false>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T, acc, last, ncomp,
                                            neval, nslot, done);
         }
         if (__syncthreads_and(done ? 1 : 0)) break;
@@ -1566,15 +1858,27 @@ template <int R>
 static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st)
 {
     dim3 grid((unsigned)ws.g.tiles, (unsigned)ws.n_chunks);
-    if (save)
-        hipLaunchKernelGGL((k_blend_fwd<R, true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
-                           ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
-                           ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
-                           ws.part.as<float>(), stat_words(ws));
-    else
-        hipLaunchKernelGGL((k_blend_fwd<R, false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
-                           ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
-                           ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr);
+    if constexpr (R == 1) {
+        if (save)
+            hipLaunchKernelGGL((k_blend_fwd1<true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
+                               ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
+                               ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
+                               ws.part.as<float>(), stat_words(ws));
+        else
+            hipLaunchKernelGGL((k_blend_fwd1<false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
+                               ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
+                               ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr);
+    } else {
+        if (save)
+            hipLaunchKernelGGL((k_blend_fwd_multi<R, true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
+                               ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
+                               ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
+                               ws.part.as<float>(), stat_words(ws));
+        else
+            hipLaunchKernelGGL((k_blend_fwd_multi<R, false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
+                               ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
+                               ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr);
+    }
 }
 
 hipError_t launch_blend_fwd(Workspace &ws, float *C, bool save, hipStream_t st)
