@@ -40,7 +40,7 @@ BLEND_OPS_PER_PAIR = 16      # lane-ops per composited (pixel, Gaussian) pair: o
 BLEND_OPS_PER_EXTRA_RX = 2   # TX mode: each further receiver sharing the weight adds one complex FMA
 SORT_BYTES_PER_KEY_PASS = 16  # read and write one (u32 key, u32 value) per pass
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                            "k_blend_fwd_c1_rx_traffic.txt")
+                            "k_blend_fwd1_c1_rx_traffic.txt")
 
 
 def parse():
@@ -256,7 +256,7 @@ def roofline_for(entry, mode, workload):
         ach = ops / t_s / 1e12
         return {"kernel": "k_blend_fwd1", "bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS,
                 "unit": "Tops/s", "frac": ach / PEAK_VALU_TOPS,
-                "traffic": stored_traffic("k_blend_fwd", workload),
+                "traffic": stored_traffic("k_blend_fwd1", workload),
                 "work": f"{BLEND_OPS_PER_PAIR} lane-ops x {sz['composited']} composited (pixel, Gaussian) pairs"}
     if top == "mlp_pairs":
         flop = MLP_MFMA_FLOP_PER_PAIR * sz["mlp_pairs"]
