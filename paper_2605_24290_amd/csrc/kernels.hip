@@ -597,20 +597,30 @@ __global__ __launch_bounds__(BLOCK) void k_emit2(const float4 *__restrict__ sbox
 // per-tile list lengths; their exclusive scan from the view's segment start
 // gives the lists' positions.  A view without pairs has empty lists (its
 // totals are not read: the sort, and the clearing of its scratch, is skipped
-// when a render has no pairs at all).
+// when a render has no pairs at all).  Also the view's tiles ordered by list
+// length, longest first (ties by tile index): the blend starts the longest
+// lists of every view first, which shortens the tail of its grid.
 __global__ __launch_bounds__(BLOCK) void k_ranges_hist(const uint32_t *__restrict__ hist,
                                                        const uint32_t *__restrict__ pbase,
                                                        const uint32_t *__restrict__ pcount, int tiles,
-                                                       uint2 *__restrict__ ranges)
+                                                       uint2 *__restrict__ ranges, uint32_t *__restrict__ torder)
 {
     __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_c[BLOCK];
     const int v = blockIdx.x, t = threadIdx.x;
     const uint32_t c = pcount[v] ? hist[(size_t)v * 256 + t] : 0u;
+    s_c[t] = c;
     uint32_t tot;
     const uint32_t ex = block_exclusive_scan(c, tot, s_w);
     if (t < tiles) {
         const uint32_t s0 = pbase[v] + ex;
         ranges[(size_t)v * tiles + t] = c ? make_uint2(s0, s0 + c) : make_uint2(0u, 0u);
+        int rank = 0;
+        for (int u = 0; u < tiles; u++) {
+            const uint32_t cu = s_c[u];
+            rank += (cu > c || (cu == c && u < t)) ? 1 : 0;
+        }
+        torder[(size_t)v * tiles + rank] = (uint32_t)t;
     }
 }
 
@@ -1184,6 +1194,9 @@ constexpr int NB1 = BLOCK / 2;
 
 template <int NB> struct BlendFwdStage {
     float4 q[4][NB][2];              // per wave, in list order
+    float4 r0[NB];                   // the batch's records (azimuth shifted near the tile)
+    float4 r1[NB];
+    float2 rad[NB];                  // and radiance
     unsigned short list[4][NB];      // per wave: batch index of each entry
     int len[4];
     int wcnt[4][4];
@@ -1217,8 +1230,11 @@ __device__ __forceinline__ int subtile_mask_fast(const float4 &r0, const float4 
     return m;
 }
 
-// Stage one batch (this thread's entry, if `has`, with its radiance rv) into
-// per-wave records.  All threads of the workgroup call it; on return st.len,
+// Stage one batch (this thread's entry, if `has`, with its radiance rv).  All
+// threads of the workgroup call it.  First every entry is tested against the
+// four sub-tiles and the per-wave lists are built (ballots and prefix counts);
+// then each wave turns its own list into records, one entry per lane, so no
+// lane computes records for sub-tiles other waves need.  On return st.len,
 // st.wide and the records of every wave are final (lists padded with
 // zero-weight records to a multiple of 4).
 template <int NB>
@@ -1227,11 +1243,10 @@ __device__ __forceinline__ void stage_fwd(BlendFwdStage<NB> &st, const float4 *_
 {
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     int m = 0, wide = 0;
-    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
     const float Wf = (float)g.W, halfW = 0.5f * (float)g.W;
     if (has) {
-        r0 = srec[2 * (size_t)p];
-        r1 = srec[2 * (size_t)p + 1];
+        float4 r0 = srec[2 * (size_t)p];
+        const float4 r1 = srec[2 * (size_t)p + 1];
         const float tcol = (float)(tx * TILE) + 7.5f;
         // representative of the azimuth closest to this tile's centre (the
         // box of a non-wide entry in this tile's list keeps its centre well
@@ -1241,6 +1256,9 @@ __device__ __forceinline__ void stage_fwd(BlendFwdStage<NB> &st, const float4 *_
         r0.x = fmaf(sh, Wf, r0.x);
         wide = fabsf(tcol - (r0.x + r0.y)) >= halfW - 9.0f;
         m = subtile_mask_fast(r0, r1, wide, tx, ty);
+        st.r0[t] = r0;
+        st.r1[t] = r1;
+        st.rad[t] = rv;
     }
     uint64_t bal[4];
 #pragma unroll
@@ -1252,43 +1270,47 @@ __device__ __forceinline__ void stage_fwd(BlendFwdStage<NB> &st, const float4 *_
         st.wide[w] = wide_bal ? 1 : 0;
     }
     __syncthreads();
-    const bool anywide = (st.wide[0] | st.wide[1] | st.wide[2] | st.wide[3]) != 0;
-    if (m) {
-        const float a = r1.x, bb = r1.y, c = r1.z;
-        const float4 q1 = make_float4(bb, c, rv.x, rv.y);
 #pragma unroll
-        for (int b = 0; b < 4; b++) {
-            if ((m >> b) & 1) {
-                int pos = count_below(bal[b]);
-                for (int ww = 0; ww < w; ww++) pos += st.wcnt[ww][b];
-                const float colc = (float)(tx * TILE + 8 * (b & 1)) + 3.5f;
-                const float rowc = (float)(ty * TILE + 8 * (b >> 1)) + 3.5f;
-                const float du0 = (colc - r0.x) - r0.y;
-                const float dv0 = (rowc - r0.z) - r0.w;
-                float4 q0;
-                if (anywide) {
-                    q0 = make_float4(du0, dv0, r1.w, a);
-                } else {
-                    const float e0 = fmaf(du0, fmaf(a, du0, bb * dv0), fmaf(c * dv0, dv0, r1.w));
-                    q0 = make_float4(e0, fmaf(2.f * a, du0, bb * dv0), fmaf(bb, du0, 2.f * c * dv0), a);
-                }
-                st.q[b][pos][0] = q0;
-                st.q[b][pos][1] = q1;
-                st.list[b][pos] = (unsigned short)t;
-            }
+    for (int b = 0; b < 4; b++) {
+        if ((m >> b) & 1) {
+            int pos = count_below(bal[b]);
+            for (int ww = 0; ww < w; ww++) pos += st.wcnt[ww][b];
+            st.list[b][pos] = (unsigned short)t;
         }
     }
-    if (t < 4) {
-        const int n = st.wcnt[0][t] + st.wcnt[1][t] + st.wcnt[2][t] + st.wcnt[3][t];
-        st.len[t] = n;
-        // zero-weight padding: E = -inf in either form (only the constant
-        // term is infinite, so no product of infinity and zero arises)
-        const float4 pad = anywide ? make_float4(0.f, 0.f, -INFINITY, 0.f) : make_float4(-INFINITY, 0.f, 0.f, 0.f);
-        for (int k = n; k < ((n + 3) & ~3); k++) {
-            st.q[t][k][0] = pad;
-            st.q[t][k][1] = make_float4(0.f, 0.f, 0.f, 0.f);
-            st.list[t][k] = 0;
+    const bool anywide = (st.wide[0] | st.wide[1] | st.wide[2] | st.wide[3]) != 0;
+    const int n = st.wcnt[0][w] + st.wcnt[1][w] + st.wcnt[2][w] + st.wcnt[3][w];
+    if (lane == 0) st.len[w] = n;
+    __syncthreads();
+    // this wave's records (its sub-tile's centre: colc, rowc)
+    const float colc = (float)(tx * TILE + 8 * (w & 1)) + 3.5f;
+    const float rowc = (float)(ty * TILE + 8 * (w >> 1)) + 3.5f;
+    const int np = (n + 3) & ~3;
+    for (int i = lane; i < np; i += 64) {
+        float4 q0, q1;
+        if (i < n) {
+            const int e = st.list[w][i];
+            const float4 r0 = st.r0[e], r1 = st.r1[e];
+            const float2 re = st.rad[e];
+            const float a = r1.x, bb = r1.y, c = r1.z;
+            const float du0 = (colc - r0.x) - r0.y;
+            const float dv0 = (rowc - r0.z) - r0.w;
+            if (anywide) {
+                q0 = make_float4(du0, dv0, r1.w, a);
+            } else {
+                const float e0 = fmaf(du0, fmaf(a, du0, bb * dv0), fmaf(c * dv0, dv0, r1.w));
+                q0 = make_float4(e0, fmaf(2.f * a, du0, bb * dv0), fmaf(bb, du0, 2.f * c * dv0), a);
+            }
+            q1 = make_float4(bb, c, re.x, re.y);
+        } else {
+            // zero-weight padding: E = -inf in either form (only the constant
+            // term is infinite, so no product of infinity and zero arises)
+            q0 = anywide ? make_float4(0.f, 0.f, -INFINITY, 0.f) : make_float4(-INFINITY, 0.f, 0.f, 0.f);
+            q1 = make_float4(0.f, 0.f, 0.f, 0.f);
+            st.list[w][i] = 0;
         }
+        st.q[w][i][0] = q0;
+        st.q[w][i][1] = q1;
     }
     __syncthreads();
 }
@@ -1351,14 +1373,16 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
                                                       const int4 *__restrict__ chunks, int64_t Kp, DevGrid g,
                                                       float *__restrict__ C, float *__restrict__ Tfin,
                                                       int *__restrict__ nlast, float *__restrict__ part,
-                                                      unsigned long long *__restrict__ stats)
+                                                      unsigned long long *__restrict__ stats,
+                                                     const uint32_t *__restrict__ torder)
 {
     constexpr int NB = NB1;
     __shared__ BlendFwdStage<NB> st;
     __shared__ float s_red[4][3];
 
-    const int tile = blockIdx.x;
-    const int4 ch = chunks[blockIdx.y];
+    // grid: (chunk, rank of the tile in its view's longest-first order)
+    const int4 ch = chunks[blockIdx.x];
+    const int tile = torder ? (int)torder[(size_t)ch.x * g.tiles + blockIdx.y] : (int)blockIdx.y;
     const int view = ch.x, j0 = ch.y, nrx = ch.z, tslot = ch.w;
     const int ty = tile / g.tiles_x, tx = tile - ty * g.tiles_x;
     const int t = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
@@ -1509,14 +1533,16 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restr
                                                      const int4 *__restrict__ chunks, int64_t Kp, DevGrid g,
                                                      float *__restrict__ C, float *__restrict__ Tfin,
                                                      int *__restrict__ nlast, float *__restrict__ part,
-                                                     unsigned long long *__restrict__ stats)
+                                                     unsigned long long *__restrict__ stats,
+                                                     const uint32_t *__restrict__ torder)
 {
     __shared__ BlendStage st;
     __shared__ float2 s_rad[R][BLOCK];
     __shared__ float s_red[4][R][3];
 
-    const int tile = blockIdx.x;
-    const int4 ch = chunks[blockIdx.y];
+    // grid: (chunk, rank of the tile in its view's longest-first order)
+    const int4 ch = chunks[blockIdx.x];
+    const int tile = torder ? (int)torder[(size_t)ch.x * g.tiles + blockIdx.y] : (int)blockIdx.y;
     const int view = ch.x, j0 = ch.y, nrx = ch.z, tslot = ch.w;
     const int ty = tile / g.tiles_x, tx = tile - ty * g.tiles_x;
     const int t = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
@@ -1757,9 +1783,11 @@ hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st)
     if (g.tiles <= 255) {
         // one 8-bit pass: ranges straight from the scanned histogram
         hipLaunchKernelGGL(k_ranges_hist, dim3((unsigned)ws.V), dim3(BLOCK), 0, st, ws.hist_b.as<uint32_t>(),
-                           ws.d_pbase, ws.d_pcount, g.tiles, ws.ranges.as<uint2>());
+                           ws.d_pbase, ws.d_pcount, g.tiles, ws.ranges.as<uint2>(), ws.torder.as<uint32_t>());
+        ws.tiles_ordered = true;
         return hipGetLastError();
     }
+    ws.tiles_ordered = false;
     hipError_t e = launch_fill_u32(ws.ranges.as<uint32_t>(), 0u, nr * 2, st);
     if (e != hipSuccess || ws.Dpad == 0) return e;
     hipLaunchKernelGGL(k_ranges, dim3(nblk((size_t)ws.Dpad)), dim3(BLOCK), 0, st,
@@ -1857,33 +1885,35 @@ hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStr
 template <int R>
 static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st)
 {
-    dim3 grid((unsigned)ws.g.tiles, (unsigned)ws.n_chunks);
+    dim3 grid((unsigned)ws.n_chunks, (unsigned)ws.g.tiles);
+    const uint32_t *tord = ws.tiles_ordered ? ws.torder.as<uint32_t>() : nullptr;
     if constexpr (R == 1) {
         if (save)
             hipLaunchKernelGGL((k_blend_fwd1<true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
-                               ws.part.as<float>(), stat_words(ws));
+                               ws.part.as<float>(), stat_words(ws), tord);
         else
             hipLaunchKernelGGL((k_blend_fwd1<false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
-                               ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr);
+                               ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord);
     } else {
         if (save)
             hipLaunchKernelGGL((k_blend_fwd_multi<R, true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
-                               ws.part.as<float>(), stat_words(ws));
+                               ws.part.as<float>(), stat_words(ws), tord);
         else
             hipLaunchKernelGGL((k_blend_fwd_multi<R, false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
-                               ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr);
+                               ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord);
     }
 }
 
 hipError_t launch_blend_fwd(Workspace &ws, float *C, bool save, hipStream_t st)
 {
     if (ws.n_chunks == 0) return hipSuccess;
+    if (ws.g.tiles > 65535) return hipErrorInvalidConfiguration;   // grid y limit
     switch (ws.R) {
     case 1: blend_launch<1>(ws, C, save, st); break;
     case 2: blend_launch<2>(ws, C, save, st); break;

@@ -122,7 +122,7 @@ void free_workspace(Workspace &ws)
 {
     DevBuf *bufs[] = {&ws.centres, &ws.rxpos,   &ws.desc,   &ws.ext,     &ws.rawkey, &ws.opac,
                       &ws.skey[0], &ws.skey[1], &ws.sval[0], &ws.sval[1], &ws.srec,    &ws.ggeo,
-                      &ws.qcull,   &ws.sbox,    &ws.vorder, &ws.poff,
+                      &ws.qcull,   &ws.sbox,    &ws.vorder, &ws.poff, &ws.torder,
                       &ws.pkey[0], &ws.pkey[1], &ws.pval[0], &ws.pval[1], &ws.ranges, &ws.rad,
                       &ws.Lp,      &ws.Gp,      &ws.items,  &ws.Tfin,   &ws.nlast,  &ws.part,
                       &ws.counters, &ws.hist,   &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
@@ -754,6 +754,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     GROW(ctx, ws.pval[1], std::max<uint64_t>(Dpad, 1) * 4);
     GROW(ctx, ws.hist_b, sort_ws_bytes((uint32_t)Dpad, std::max(bits_for((uint64_t)g.tiles), 1), V));
     GROW(ctx, ws.ranges, (size_t)V * g.tiles * 8);
+    GROW(ctx, ws.torder, (size_t)V * g.tiles * 4);
     GROW(ctx, ws.rad, (size_t)N * Kp * 8);
     GROW(ctx, ws.Tfin, (size_t)ws.n_tslots * P * 4);
     GROW(ctx, ws.nlast, (size_t)ws.n_tslots * P * 4);

@@ -134,6 +134,8 @@ struct Workspace {
     DevBuf pval[2];   // D u32
     int pairs_buf = 0;
     DevBuf ranges;    // V x tiles uint2
+    DevBuf torder;    // V x tiles u32: tiles by list length, longest first
+    bool tiles_ordered = false;
     DevBuf rad;       // N x Kp float2
     DevBuf Lp;        // K x 64
     DevBuf Gp;        // N x 64
