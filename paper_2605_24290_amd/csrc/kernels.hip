@@ -1821,14 +1821,25 @@ static unsigned *amax_words(Workspace &ws)
     return ws.counters.as<uint32_t>() + (size_t)4 * ws.V;
 }
 
-hipError_t launch_mlp_global(const Mlp &m, Workspace &ws, hipStream_t st)
+// the receivers' layer-1 term (needs no per-render descriptors)
+hipError_t launch_mlp_global_term(const Mlp &m, Workspace &ws, hipStream_t st)
 {
     const unsigned nbg = (unsigned)nblk((size_t)ws.N * HID);
+    if (nbg > 0 && ws.Gp.cap < (size_t)ws.N * HID * 4) return hipErrorInvalidValue;   // not allocated
+    if (nbg > 0)
+        hipLaunchKernelGGL(k_mlp_global, dim3(nbg), dim3(BLOCK), 0, st, m.raw.as<float>(), ws.rxpos_p, ws.N,
+                           ws.Gp.as<float>(), amax_words(ws), (int)nbg, nullptr, nullptr, ws.V, 0, nullptr);
+    return hipGetLastError();
+}
+
+// the MLP work items, expanded from the per-view offsets
+hipError_t launch_mlp_items(Workspace &ws, hipStream_t st)
+{
     const unsigned nbi = (unsigned)nblk((size_t)ws.n_items);
-    if (nbg + nbi > 0)
-        hipLaunchKernelGGL(k_mlp_global, dim3(nbg + nbi), dim3(BLOCK), 0, st, m.raw.as<float>(), ws.rxpos_p, ws.N,
-                           ws.Gp.as<float>(), amax_words(ws), (int)nbg, ws.d_item_off, ws.d_vinfo, ws.V, ws.n_items,
-                           ws.items.as<int4>());
+    if (nbi > 0 && ws.items.cap < (size_t)ws.n_items * 16) return hipErrorInvalidValue;   // not allocated
+    if (nbi > 0)
+        hipLaunchKernelGGL(k_mlp_global, dim3(nbi), dim3(BLOCK), 0, st, nullptr, nullptr, 0, nullptr, nullptr, 0,
+                           ws.d_item_off, ws.d_vinfo, ws.V, ws.n_items, ws.items.as<int4>());
     return hipGetLastError();
 }
 

@@ -668,12 +668,19 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     STAGE(ctx, "sort_depth", sort_pairs_u32(ws.skey, ws.sval, ws.hist, cur, (uint32_t)VK, 32, V, Kp, nullptr, st));
     ws.sorted_buf = cur;
     STAGE(ctx, "emit_records", launch_emit1(sc, ws, g, st));
-    if (!ensure_pinned(ws, (size_t)2 * V * 8 + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
+    // one copy: the per-view counts up to and including the emission's error word
+    const size_t head_bytes = (size_t)(emit_words(ws) - ws.counters.as<uint32_t>() + 1) * 4;
+    if (!ensure_pinned(ws, head_bytes + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
     unsigned long long *h_cnt = static_cast<unsigned long long *>(ws.h_pinned);
-    uint32_t *h_err = reinterpret_cast<uint32_t *>(h_cnt + 2 * (size_t)V);
-    HIPCHK(ctx, hipMemcpyAsync(h_cnt, ws.counters.p, (size_t)2 * V * 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(ctx, hipMemcpyAsync(h_err, emit_words(ws), 4, hipMemcpyDeviceToHost, st));
+    const uint32_t *h_err = static_cast<const uint32_t *>(ws.h_pinned) + (head_bytes / 4 - 1);
+    HIPCHK(ctx, hipMemcpyAsync(h_cnt, ws.counters.p, head_bytes, hipMemcpyDeviceToHost, st));
     HIPCHK(ctx, hipEventRecord(ws.counted, st));
+    // the receivers' layer-1 term depends on nothing above: it runs while the
+    // host waits for the counts
+    if (ws.use_mlp) {
+        GROW(ctx, ws.Gp, (size_t)N * HID * 4);
+        STAGE(ctx, "mlp_global", launch_mlp_global_term(ctx->mlp, ws, st));
+    }
 
     // receiver chunks of the blend (independent of the counters: built while
     // the GPU projects and sorts); the receivers of a view are consecutive
@@ -761,7 +768,6 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     GROW(ctx, ws.part, (size_t)N * g.tiles * 12);
     if (ws.use_mlp) {
         GROW(ctx, ws.Lp, (size_t)std::max<int64_t>(K, 1) * HID * 4);
-        GROW(ctx, ws.Gp, (size_t)N * HID * 4);
         GROW(ctx, ws.items, (size_t)std::max(ws.n_items, 1) * 16);
     }
 
@@ -775,7 +781,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     const size_t o_pcount = o_pbase + al16((size_t)V * 4);
     const size_t o_segtab = o_pcount + al16((size_t)V * 4);
     const size_t stage_bytes = o_segtab + segtab.size() * 16;
-    const size_t cnt_bytes = (size_t)2 * V * 8 + 4;   // counters and the emission error word
+    const size_t cnt_bytes = head_bytes;   // the counts and the emission error word
     const size_t off0 = (cnt_bytes + 63) / 64 * 64;
     if (!ensure_pinned(ws, off0 + stage_bytes + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
     GROW(ctx, ws.desc, stage_bytes);
@@ -813,7 +819,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
 
     // stage 2: radiance per (receiver, sorted position)
     if (ws.use_mlp) {
-        STAGE(ctx, "mlp_global", launch_mlp_global(ctx->mlp, ws, st));
+        STAGE(ctx, "mlp_items", launch_mlp_items(ws, st));
         // the stored Gaussian term: for the backward, or when the pair kernel
         // cannot compute it itself
         if (saved || !mlp_fused_ok(sc, ctx->mlp)) STAGE(ctx, "mlp_local", launch_mlp_local(sc, ctx->mlp, ws, st));

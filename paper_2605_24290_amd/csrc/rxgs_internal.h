@@ -230,7 +230,8 @@ uint32_t *emit_words(Workspace &ws);
 size_t emit_word_count(int V, int64_t Kp);
 hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st);
 hipError_t launch_rad_direct(const Scene &sc, Workspace &ws, hipStream_t st);
-hipError_t launch_mlp_global(const Mlp &m, Workspace &ws, hipStream_t st);
+hipError_t launch_mlp_global_term(const Mlp &m, Workspace &ws, hipStream_t st);
+hipError_t launch_mlp_items(Workspace &ws, hipStream_t st);
 hipError_t launch_mlp_local(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st);
 hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st);
 bool mlp_fused_ok(const Scene &sc, const Mlp &m);
