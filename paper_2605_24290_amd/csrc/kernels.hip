@@ -204,8 +204,11 @@ __device__ __forceinline__ void view_geo(const GaussGeo &G, float cx, float cy, 
     P.u = az * g.idaz - 0.5;
     P.vv = (el - g.el0) * g.idel - 0.5;
     const double hh = h * h, rh2 = hh + dz * dz;
-    const double ihh = g.idaz / hh;          // 1 / (h^2 daz)
-    const double irh = g.idel / (rh2 * h);   // 1 / (rho^2 h del)
+    // 1 / (h^2 daz) and 1 / (rho^2 h del) from one reciprocal
+    const double rhh = rh2 * h;
+    const double qd = 1.0 / (hh * rhh);
+    const double ihh = g.idaz * (rhh * qd);
+    const double irh = g.idel * (hh * qd);
     const double mu0 = -dy * ihh, mu1 = dx * ihh;
     const double mv0 = -dx * dz * irh, mv1 = -dy * dz * irh, mv2 = hh * irh;
     const double Smv0 = G.S00 * mv0 + G.S01 * mv1 + G.S02 * mv2;
@@ -342,7 +345,8 @@ __device__ __forceinline__ uint64_t em_pack(uint64_t flag, uint32_t vis, uint32_
     return flag | ((uint64_t)(vis & 0x3FFFFFFFu) << 32) | pairs;
 }
 
-// exclusive workgroup scan of two counts at once
+// exclusive scan of two counts at once over a workgroup of NW waves
+template <int NW>
 __device__ __forceinline__ uint2 block_exclusive_scan2(uint32_t x, uint32_t y, uint2 &total, uint2 *s_w)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -356,33 +360,41 @@ __device__ __forceinline__ uint2 block_exclusive_scan2(uint32_t x, uint32_t y, u
     }
     if (lane == 63) s_w[w] = make_uint2(a, b);
     __syncthreads();
-    uint2 pre = make_uint2(0u, 0u);
-    for (int i = 0; i < w; i++) {
-        pre.x += s_w[i].x;
-        pre.y += s_w[i].y;
+    uint2 pre = make_uint2(0u, 0u), tot = make_uint2(0u, 0u);
+#pragma unroll
+    for (int i = 0; i < NW; i++) {
+        const uint2 c = s_w[i];
+        if (i < w) {
+            pre.x += c.x;
+            pre.y += c.y;
+        }
+        tot.x += c.x;
+        tot.y += c.y;
     }
-    total = make_uint2(s_w[0].x + s_w[1].x + s_w[2].x + s_w[3].x, s_w[0].y + s_w[1].y + s_w[2].y + s_w[3].y);
+    total = tot;
     __syncthreads();
     return make_uint2(pre.x + a - x, pre.y + b - y);
 }
 
-template <int EM1_PER>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_emit1(
+// NT threads per workgroup, EM1_PER entries per thread
+template <int EM1_PER, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_emit1(
     const GaussGeoPacked *__restrict__ gg, int64_t K, int64_t Kp, const float *__restrict__ centres, DevGrid g,
     const uint32_t *__restrict__ order, const uint32_t *__restrict__ hist, int passes, int cpv,
     float4 *__restrict__ srec, float4 *__restrict__ sbox, uint32_t *__restrict__ vorder, uint32_t *__restrict__ poff,
     unsigned long long *__restrict__ counters, unsigned long long *status, uint32_t *tickets, uint32_t *err)
 {
-    __shared__ uint32_t s_w[4];
-    __shared__ uint2 s_w2[4];
+    constexpr int NW = NT / 64;
+    __shared__ uint2 s_w2[NW];
     __shared__ uint32_t s_chunk, s_vbase, s_pbase;
-    constexpr int EM1_CHUNK = BLOCK * EM1_PER;
+    constexpr int EM1_CHUNK = NT * EM1_PER;
     const int t = threadIdx.x;
     const int v = (int)(blockIdx.x / (unsigned)cpv);
     if (t == 0) s_chunk = atomicAdd(tickets + (size_t)v * EM_TICKET_STRIDE, 1u);
     // entries the depth sort kept for this view: the sum of its digit totals
-    uint32_t seg_n;
-    (void)block_exclusive_scan(hist[((size_t)v * passes) * 256 + t], seg_n, s_w);
+    uint2 seg2;
+    (void)block_exclusive_scan2<NW>(t < 256 ? hist[((size_t)v * passes) * 256 + t] : 0u, 0u, seg2, s_w2);
+    const uint32_t seg_n = seg2.x;
     const uint32_t chunk = s_chunk;
     const int64_t s0 = (int64_t)chunk * EM1_CHUNK;
     // uniform; chunks with higher tickets of this view are past the end too
@@ -414,7 +426,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4, 8))) v
         npairs += nt[j];
     }
     uint2 tot;
-    const uint2 pre = block_exclusive_scan2(nvis, npairs, tot, s_w2);
+    const uint2 pre = block_exclusive_scan2<NW>(nvis, npairs, tot, s_w2);
     if (t < 64) {
         uint32_t evis = 0;
         uint64_t epairs = 0;
@@ -1755,13 +1767,17 @@ size_t emit_word_count(int V, int64_t Kp)
 hipError_t launch_emit1(const Scene &sc, Workspace &ws, const DevGrid &g, hipStream_t st)
 {
     uint32_t *ew = emit_words(ws);
+    // chunks of 1024 entries (512 threads, 2 per thread) when there are many,
+    // which amortises each chunk's look-back; 256 (1 per thread) for small
+    // launches, which keeps the chain of chunks short
     const bool wide = (size_t)ws.V * (size_t)(ws.Kp / (4 * BLOCK)) >= 1024;
-    const int per = wide ? 4 : 1;
-    const int cpv = (int)((ws.Kp + per * BLOCK - 1) / (per * BLOCK));
-    auto kern = wide ? k_emit1<4> : k_emit1<1>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)(ws.V * cpv)), dim3(BLOCK), 0, st, ws.ggeo.as<GaussGeoPacked>(), sc.K,
-                       ws.Kp, ws.centres_p, g, ws.sval[ws.sorted_buf].as<uint32_t>(), ws.hist.as<uint32_t>(), 4, cpv,
-                       ws.srec.as<float4>(), ws.sbox.as<float4>(), ws.vorder.as<uint32_t>(), ws.poff.as<uint32_t>(),
+    const int chunk = wide ? 4 * BLOCK : BLOCK;
+    const int cpv = (int)((ws.Kp + chunk - 1) / chunk);
+    auto kern = wide ? k_emit1<2, 2 * BLOCK> : k_emit1<1, BLOCK>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)(ws.V * cpv)), dim3(wide ? 2 * BLOCK : BLOCK), 0, st,
+                       ws.ggeo.as<GaussGeoPacked>(), sc.K, ws.Kp, ws.centres_p, g,
+                       ws.sval[ws.sorted_buf].as<uint32_t>(), ws.hist.as<uint32_t>(), 4, cpv, ws.srec.as<float4>(),
+                       ws.sbox.as<float4>(), ws.vorder.as<uint32_t>(), ws.poff.as<uint32_t>(),
                        ws.counters.as<unsigned long long>(),
                        reinterpret_cast<unsigned long long *>(ew + EM_TICKET_STRIDE + (size_t)ws.V * EM_TICKET_STRIDE),
                        ew + EM_TICKET_STRIDE, ew);
