@@ -906,6 +906,28 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_pairs_f32(const float *__restrict
 // layer-1 activations are split unscaled while the largest possible one,
 // max|local| + max|global|, is below 2^15; beyond that a uniform branch scales
 // them by a power of two first, so no operand leaves the FP16 range.
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+// Split two FP32 values into FP16 (hi, lo) pairs, v = hi + lo: hi is v with
+// its 13 low mantissa bits cleared, exactly an FP16 value while |v| is in the
+// FP16 normal range (below it the dropped part is under 2^-24 in absolute
+// value), lo = v - hi is exact in FP32 and below one FP16 ulp of v, so its
+// rounding toward zero costs at most 2^-21 |v|.  Two packing conversions
+// for the pair.
+__device__ __forceinline__ void split2(float a, float b, half2v &hi, half2v &lo)
+{
+    const float ha = __uint_as_float(__float_as_uint(a) & 0xFFFFE000u);
+    const float hb = __uint_as_float(__float_as_uint(b) & 0xFFFFE000u);
+    hi = (half2v)__builtin_amdgcn_cvt_pkrtz(ha, hb);
+    lo = (half2v)__builtin_amdgcn_cvt_pkrtz(a - ha, b - hb);
+}
+
+__device__ __forceinline__ half8 cat4(const half2v &a, const half2v &b, const half2v &c, const half2v &d)
+{
+    return __builtin_shufflevector(__builtin_shufflevector(a, b, 0, 1, 2, 3), __builtin_shufflevector(c, d, 0, 1, 2, 3),
+                                   0, 1, 2, 3, 4, 5, 6, 7);
+}
+
 // one 64-float row stored in hid_pos order: lane half h takes its 32 values
 __device__ __forceinline__ void load_half_row(const float *__restrict__ base, size_t row, int h, float (&v)[32])
 {
@@ -937,14 +959,13 @@ __device__ __forceinline__ void local_term(const float (&f)[16], const half8 *s_
 {
     half8 fh[2], fl[2];
 #pragma unroll
-    for (int q = 0; q < 2; q++)
+    for (int q = 0; q < 2; q++) {
+        half2v hh[4], ll[4];
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            const float v = f[8 * q + i];
-            const _Float16 hi = (_Float16)v;
-            fh[q][i] = hi;
-            fl[q][i] = (_Float16)(v - (float)hi);
-        }
+        for (int i = 0; i < 4; i++) split2(f[8 * q + 2 * i], f[8 * q + 2 * i + 1], hh[i], ll[i]);
+        fh[q] = cat4(hh[0], hh[1], hh[2], hh[3]);
+        fl[q] = cat4(ll[0], ll[1], ll[2], ll[3]);
+    }
     const float4 *b1h = s_b1 + h * 8 + z0;
     floatx16 L0, L1;
 #pragma unroll
@@ -1043,12 +1064,20 @@ __device__ __forceinline__ void mlp_pairs_walk(const float *__restrict__ Lp, con
             const float4 *w3h = s_w3 + h * 16 + z0;
             half8 bh[4], bl[4];
 #pragma unroll
-            for (int t = 0; t < 32; t++) {
-                float v = fmaxf(l[t] + g[t], 0.f);
-                if (SCALED) v *= sx;
-                const _Float16 hi = (_Float16)v;
-                bh[t >> 3][t & 7] = hi;
-                bl[t >> 3][t & 7] = (_Float16)(v - (float)hi);
+            for (int q = 0; q < 4; q++) {
+                half2v hh[4], ll[4];
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const int t = 8 * q + 2 * i;
+                    float v0 = fmaxf(l[t] + g[t], 0.f), v1 = fmaxf(l[t + 1] + g[t + 1], 0.f);
+                    if (SCALED) {
+                        v0 *= sx;
+                        v1 *= sx;
+                    }
+                    split2(v0, v1, hh[i], ll[i]);
+                }
+                bh[q] = cat4(hh[0], hh[1], hh[2], hh[3]);
+                bl[q] = cat4(ll[0], ll[1], ll[2], ll[3]);
             }
             const bool last = jj + 1 == nj;
             if (last && more) {
