@@ -275,6 +275,54 @@ def roofline_for(entry, mode, workload):
             "traffic": None}
 
 
+# Algorithmic work per stage of one render (bytes that must cross HBM, lane-ops,
+# matrix FLOP), for the per-stage roofline fractions and the overall one,
+# sum of t_roof over the stages / measured time per render.
+EMIT_RECORD_BYTES = 84 + 56   # per visible entry: order index + projection terms read; record,
+                              # box, index and pair slot written
+EMIT_PAIR_BYTES_ENTRY = 20    # per visible entry: box and first pair slot read
+PAIR_BYTES = 8                # per pair: tile and sorted position written
+PAIR_SORT_BYTES = 4 + SORT_BYTES_PER_KEY_PASS   # per pair: histogram read + one 8-bit pass
+
+
+def stage_rooflines(entry, mode, K):
+    """Per stage: bound, algorithmic work, t_roof = work / peak, the measured
+    time (HIP events, per render) and t_roof / t; the overall fraction
+    divides the sum of t_roof by the measured time per render."""
+    st = entry["stages_ms_per_step"]
+    sz = entry["sizes"]
+    nvis, D, VK = sz["visible_total"], sz["tile_pairs"], sz["sort_keys"]
+    if mode == "rx":
+        blend_ops = BLEND_OPS_PER_PAIR * sz["composited"]
+    else:
+        per_view = sz["composited_px"] / max(sz["chunks_per_view"], 1)
+        blend_ops = BLEND_OPS_PER_PAIR * per_view + BLEND_OPS_PER_EXTRA_RX * (sz["composited"] - per_view)
+    model = {
+        "project": ("hbm", 44 * K + 8 * VK, "44 B per Gaussian read, 8 B per (view, Gaussian) key written"),
+        "sort_depth": ("hbm", (4 + 4 * SORT_BYTES_PER_KEY_PASS) * VK, "68 B per (view, Gaussian) key"),
+        "emit_records": ("hbm", EMIT_RECORD_BYTES * nvis, f"{EMIT_RECORD_BYTES} B per visible entry"),
+        "emit_pairs": ("hbm", EMIT_PAIR_BYTES_ENTRY * nvis + PAIR_BYTES * D,
+                       f"{EMIT_PAIR_BYTES_ENTRY} B per visible entry + {PAIR_BYTES} B per pair"),
+        "sort_pairs": ("hbm", PAIR_SORT_BYTES * D, f"{PAIR_SORT_BYTES} B per pair"),
+        "mlp_pairs": ("mfma", MLP_MFMA_FLOP_PER_PAIR * sz["mlp_pairs"],
+                      f"{MLP_MFMA_FLOP_PER_PAIR} FP16 MFMA FLOP per (receiver, visible Gaussian)"),
+        "blend_fwd": ("alu", blend_ops, f"{BLEND_OPS_PER_PAIR} lane-ops per composited pair"),
+    }
+    peak = {"hbm": PEAK_HBM_GBS * 1e9, "mfma": PEAK_FP16_MFMA_TFLOPS * 1e12, "alu": PEAK_VALU_TOPS * 1e12}
+    rows, t_roof_sum = {}, 0.0
+    for name, t_ms in st.items():
+        if name not in model:
+            rows[name] = {"bound": "negligible", "t_us": t_ms * 1e3}
+            continue
+        bound, work, desc = model[name]
+        t_roof = work / peak[bound]
+        t_roof_sum += t_roof
+        rows[name] = {"bound": bound, "work": work, "work_model": desc, "t_roof_us": t_roof * 1e6,
+                      "t_us": t_ms * 1e3, "frac": t_roof / (t_ms * 1e-3) if t_ms > 0 else None}
+    return {"stages": rows, "overall_frac": t_roof_sum / (entry["ms_per_step"] * 1e-3),
+            "note": "stage times from the profiled pass; overall = sum of t_roof / unprofiled time per render"}
+
+
 def copy_calibration(mib: int):
     """A plain elementwise copy of known size (read mib MiB, write mib MiB),
     for scaling the FETCH_SIZE / WRITE_SIZE counters of a profiled run."""
@@ -346,6 +394,7 @@ def main():
         "fused": head,
         "other_modes": {k: v for k, v in res.items() if k != args.mode},
         "roofline": roofline_for(head, args.mode, workload),
+        "stage_roofline": stage_rooflines(head, args.mode, wl.scene.K),
     }
     if not args.no_train:
         out["train_step"] = train_step_part(args)
