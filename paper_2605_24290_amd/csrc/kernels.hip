@@ -15,7 +15,7 @@
 //                  emitted in depth order into the view's segment.  [HBM]
 //   radix sort     stable 8-bit sort of each view's pairs by tile, so each
 //                  tile's list stays in depth order.                [HBM]
-//   k_ranges_hist  [start, end) of each tile's list.
+//   k_ranges_items [start, end) of each tile's list (and the MLP work items).
 //   k_mlp_*        stage 2: receiver term and Gaussian term of the MLP's first
 //                  layer, then the per-(receiver, Gaussian) layers on split
 //                  FP16 MFMA.                                       [MFMA]
@@ -272,8 +272,17 @@ template <bool SAVE>
 __global__ __launch_bounds__(BLOCK) void k_project(
     const GaussGeoPacked *__restrict__ gg, const float *__restrict__ qcull, int64_t K, int64_t Kp,
     const float *__restrict__ centres, int V, int vchunk, DevGrid g, uint32_t *__restrict__ skey,
-    uint32_t *__restrict__ sval, float4 *__restrict__ ext, uint32_t *__restrict__ rawkey, float *__restrict__ opac)
+    uint32_t *__restrict__ sval, float4 *__restrict__ ext, uint32_t *__restrict__ rawkey, float *__restrict__ opac,
+    uint32_t *__restrict__ z0, size_t n0, uint32_t *__restrict__ z1, size_t n1)
 {
+    {
+        // clears the render's counters and the depth sort's scratch (both
+        // first used by later kernels of the stream)
+        const size_t stride = (size_t)gridDim.x * gridDim.y * BLOCK;
+        const size_t i0 = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * BLOCK + threadIdx.x;
+        for (size_t i = i0; i < n0; i += stride) z0[i] = 0u;
+        for (size_t i = i0; i < n1; i += stride) z1[i] = 0u;
+    }
     const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int v0 = blockIdx.y * vchunk;
     const int v1 = min(V, v0 + vchunk);
@@ -513,8 +522,11 @@ __global__ __launch_bounds__(BLOCK) void k_emit2(const float4 *__restrict__ sbox
                                                  const uint32_t *__restrict__ pbase,
                                                  const uint32_t *__restrict__ pcount,
                                                  const uint32_t *__restrict__ chunk_off, int V,
-                                                 uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval)
+                                                 uint32_t *__restrict__ pkey, uint32_t *__restrict__ pval,
+                                                 uint32_t *__restrict__ zs, size_t nzs)
 {
+    // clears the pair sort's scratch (first used by the next kernel)
+    for (size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x; i < nzs; i += (size_t)gridDim.x * BLOCK) zs[i] = 0u;
     __shared__ unsigned char s_own[EMIT_WIN];
     __shared__ uint32_t s_pre[BLOCK];
     __shared__ int4 s_tp[BLOCK];     // ty0, a0, columns in range a, b0
@@ -612,14 +624,14 @@ __global__ __launch_bounds__(BLOCK) void k_emit2(const float4 *__restrict__ sbox
 // when a render has no pairs at all).  Also the view's tiles ordered by list
 // length, longest first (ties by tile index): the blend starts the longest
 // lists of every view first, which shortens the tail of its grid.
-__global__ __launch_bounds__(BLOCK) void k_ranges_hist(const uint32_t *__restrict__ hist,
-                                                       const uint32_t *__restrict__ pbase,
-                                                       const uint32_t *__restrict__ pcount, int tiles,
-                                                       uint2 *__restrict__ ranges, uint32_t *__restrict__ torder)
+__device__ __forceinline__ void ranges_of_view(int v, const uint32_t *__restrict__ hist,
+                                               const uint32_t *__restrict__ pbase,
+                                               const uint32_t *__restrict__ pcount, int tiles,
+                                               uint2 *__restrict__ ranges, uint32_t *__restrict__ torder)
 {
     __shared__ uint32_t s_w[4];
     __shared__ uint32_t s_c[BLOCK];
-    const int v = blockIdx.x, t = threadIdx.x;
+    const int t = threadIdx.x;
     const uint32_t c = pcount[v] ? hist[(size_t)v * 256 + t] : 0u;
     s_c[t] = c;
     uint32_t tot;
@@ -747,6 +759,24 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_global(const float *__restrict__ 
         Gp[(size_t)j * HID + hid_pos(d)] = acc;
     }
     block_absmax_to(acc, amax);
+}
+
+// The tile ranges (one workgroup per view) and the MLP work
+// items (the workgroups after them) in one launch.
+__global__ __launch_bounds__(BLOCK) void k_ranges_items(const uint32_t *__restrict__ hist,
+                                                        const uint32_t *__restrict__ pbase,
+                                                        const uint32_t *__restrict__ pcount, int tiles,
+                                                        uint2 *__restrict__ ranges, uint32_t *__restrict__ torder,
+                                                        const uint32_t *__restrict__ item_off,
+                                                        const int4 *__restrict__ vinfo, int V, int nitems,
+                                                        int4 *__restrict__ items)
+{
+    if ((int)blockIdx.x < V) {
+        ranges_of_view(blockIdx.x, hist, pbase, pcount, tiles, ranges, torder);
+        return;
+    }
+    const int i = ((int)blockIdx.x - V) * BLOCK + threadIdx.x;
+    if (i < nitems) items[i] = make_item(i, item_off, vinfo, V);
 }
 
 // Gaussian ("local") term of layer 1: L_k = W1[:, 36:] f_k + b1, in hid_pos
@@ -1761,7 +1791,7 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st
 }
 
 hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t Kp, const DevGrid &g,
-                          Workspace &ws, bool keep_boxes, hipStream_t st)
+                          Workspace &ws, bool keep_boxes, size_t counter_words, size_t sort_words, hipStream_t st)
 {
     if (sc.K > 0)
         hipLaunchKernelGGL(k_gauss_prep, dim3((unsigned)((sc.K + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st,
@@ -1772,11 +1802,13 @@ hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t 
         hipLaunchKernelGGL(k_project<true>, grid, dim3(BLOCK), 0, st, ws.ggeo.as<GaussGeoPacked>(),
                            ws.qcull.as<float>(), sc.K, Kp, centres, V, vchunk, g, ws.skey[0].as<uint32_t>(),
                            ws.sval[0].as<uint32_t>(), ws.ext.as<float4>(), ws.rawkey.as<uint32_t>(),
-                           ws.opac.as<float>());
+                           ws.opac.as<float>(), ws.counters.as<uint32_t>(), counter_words, ws.hist.as<uint32_t>(),
+                           sort_words);
     else
         hipLaunchKernelGGL(k_project<false>, grid, dim3(BLOCK), 0, st, ws.ggeo.as<GaussGeoPacked>(),
                            ws.qcull.as<float>(), sc.K, Kp, centres, V, vchunk, g, ws.skey[0].as<uint32_t>(),
-                           ws.sval[0].as<uint32_t>(), nullptr, nullptr, nullptr);
+                           ws.sval[0].as<uint32_t>(), nullptr, nullptr, nullptr, ws.counters.as<uint32_t>(),
+                           counter_words, ws.hist.as<uint32_t>(), sort_words);
     return hipGetLastError();
 }
 
@@ -1813,23 +1845,30 @@ hipError_t launch_emit1(const Scene &sc, Workspace &ws, const DevGrid &g, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_emit2(Workspace &ws, const DevGrid &g, hipStream_t st)
+hipError_t launch_emit2(Workspace &ws, const DevGrid &g, size_t sort_words, hipStream_t st)
 {
     if (ws.n_emit_chunks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit2, dim3((unsigned)ws.n_emit_chunks), dim3(BLOCK), 0, st, ws.sbox.as<float4>(),
                        ws.poff.as<uint32_t>(), ws.Kp, g, ws.counters.as<unsigned long long>(), ws.d_pbase,
-                       ws.d_pcount, ws.d_chunk_off, ws.V, ws.pkey[0].as<uint32_t>(), ws.pval[0].as<uint32_t>());
+                       ws.d_pcount, ws.d_chunk_off, ws.V, ws.pkey[0].as<uint32_t>(), ws.pval[0].as<uint32_t>(),
+                       ws.hist_b.as<uint32_t>(), sort_words);
     return hipGetLastError();
 }
 
 hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st)
 {
     const size_t nr = (size_t)ws.V * g.tiles;
+    ws.items_built = false;
     if (g.tiles <= 255) {
-        // one 8-bit pass: ranges straight from the scanned histogram
-        hipLaunchKernelGGL(k_ranges_hist, dim3((unsigned)ws.V), dim3(BLOCK), 0, st, ws.hist_b.as<uint32_t>(),
-                           ws.d_pbase, ws.d_pcount, g.tiles, ws.ranges.as<uint2>(), ws.torder.as<uint32_t>());
+        // one 8-bit pass: ranges straight from the scanned histogram; the MLP
+        // work items in the same launch
+        const unsigned nbi = ws.use_mlp ? (unsigned)nblk((size_t)ws.n_items) : 0u;
+        if (nbi > 0 && ws.items.cap < (size_t)ws.n_items * 16) return hipErrorInvalidValue;   // not allocated
+        hipLaunchKernelGGL(k_ranges_items, dim3((unsigned)ws.V + nbi), dim3(BLOCK), 0, st, ws.hist_b.as<uint32_t>(),
+                           ws.d_pbase, ws.d_pcount, g.tiles, ws.ranges.as<uint2>(), ws.torder.as<uint32_t>(),
+                           ws.d_item_off, ws.d_vinfo, ws.V, ws.n_items, ws.items.as<int4>());
         ws.tiles_ordered = true;
+        ws.items_built = nbi > 0;
         return hipGetLastError();
     }
     ws.tiles_ordered = false;
@@ -1979,6 +2018,7 @@ hipError_t launch_blend_fwd(Workspace &ws, float *C, bool save, hipStream_t st)
     }
     return hipGetLastError();
 }
+
 
 hipError_t launch_reduce_outputs(Workspace &ws, float *power, float *csum, hipStream_t st)
 {

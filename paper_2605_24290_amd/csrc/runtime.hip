@@ -657,15 +657,18 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         ws.centres_p = mode == RXGS_MODE_TX ? tx : rx;
         ws.rxpos_p = rx;
     }
-    HIPCHK(ctx, launch_fill_u32(ws.counters.as<uint32_t>(), 0u, cnt_words, st));
 
     // stage 1: depth keys (with the cheap culls), the per-view depth sort,
     // then the exact projection in depth order, which compacts the visible
     // entries and counts them and their pairs; the host waits only for those
     // counts
-    STAGE(ctx, "project", launch_project(sc, ws.centres_p, V, Kp, g, ws, saved != nullptr, st));
+    // (the key kernel also clears the counters and the depth sort's scratch)
+    const size_t depth_sort_words = sort_ws_bytes((uint32_t)VK, 32, V) / 4;
+    STAGE(ctx, "project",
+          launch_project(sc, ws.centres_p, V, Kp, g, ws, saved != nullptr, cnt_words, depth_sort_words, st));
     int cur = 0;
-    STAGE(ctx, "sort_depth", sort_pairs_u32(ws.skey, ws.sval, ws.hist, cur, (uint32_t)VK, 32, V, Kp, nullptr, st));
+    STAGE(ctx, "sort_depth",
+          sort_pairs_u32(ws.skey, ws.sval, ws.hist, cur, (uint32_t)VK, 32, V, Kp, nullptr, st, true));
     ws.sorted_buf = cur;
     STAGE(ctx, "emit_records", launch_emit1(sc, ws, g, st));
     // one copy: the per-view counts up to and including the emission's error word
@@ -809,17 +812,18 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     // pairs: emit in depth order, stable sort by (view, tile), tile ranges
     int pcur = 0;
     if (D > 0) {
-        STAGE(ctx, "emit_pairs", launch_emit2(ws, g, st));
+        // (the emission kernel also clears the pair sort's scratch)
         const int sbits = std::max(bits_for((uint64_t)g.tiles), 1);
+        STAGE(ctx, "emit_pairs", launch_emit2(ws, g, sort_ws_bytes((uint32_t)Dpad, sbits, V) / 4, st));
         STAGE(ctx, "sort_pairs", sort_pairs_u32(ws.pkey, ws.pval, ws.hist_b, pcur, (uint32_t)Dpad, sbits, V, 0,
-                                                ws.d_segtab, st));
+                                                ws.d_segtab, st, true));
     }
     ws.pairs_buf = pcur;
     STAGE(ctx, "ranges", launch_ranges(ws, g, st));
 
     // stage 2: radiance per (receiver, sorted position)
     if (ws.use_mlp) {
-        STAGE(ctx, "mlp_items", launch_mlp_items(ws, st));
+        if (!ws.items_built) STAGE(ctx, "mlp_items", launch_mlp_items(ws, st));
         // the stored Gaussian term: for the backward, or when the pair kernel
         // cannot compute it itself
         if (saved || !mlp_fused_ok(sc, ctx->mlp)) STAGE(ctx, "mlp_local", launch_mlp_local(sc, ctx->mlp, ws, st));

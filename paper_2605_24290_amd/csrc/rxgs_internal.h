@@ -136,6 +136,7 @@ struct Workspace {
     DevBuf ranges;    // V x tiles uint2
     DevBuf torder;    // V x tiles u32: tiles by list length, longest first
     bool tiles_ordered = false;
+    bool items_built = false;   // the MLP work items were expanded with the ranges
     DevBuf rad;       // N x Kp float2
     DevBuf Lp;        // K x 64
     DevBuf Gp;        // N x 64
@@ -215,17 +216,18 @@ namespace rxgs {
 
 // ---- launch wrappers (kernels.hip) ----
 hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t Kp, const DevGrid &g,
-                          Workspace &ws, bool keep_boxes, hipStream_t st);
+                          Workspace &ws, bool keep_boxes, size_t counter_words, size_t sort_words, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st);
 // sort.hip: stable segmented radix sort of (key, value) pairs by the low
 // `bits` key bits; segments of seg_len keys (a multiple of 4096), or given per
 // 4096-key unit by segtab; wsb holds sort_ws_bytes(n, bits, nseg) bytes and
-// keeps the per-segment digit totals at its start
+// keeps the per-segment digit totals at its start; zeroed: the caller has
+// cleared those bytes already on this stream
 hipError_t sort_pairs_u32(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
-                          int64_t seg_len, const int4 *segtab, hipStream_t st);
+                          int64_t seg_len, const int4 *segtab, hipStream_t st, bool zeroed = false);
 size_t sort_ws_bytes(uint32_t n, int bits, int nseg);
 hipError_t launch_emit1(const Scene &sc, Workspace &ws, const DevGrid &g, hipStream_t st);
-hipError_t launch_emit2(Workspace &ws, const DevGrid &g, hipStream_t st);
+hipError_t launch_emit2(Workspace &ws, const DevGrid &g, size_t sort_words, hipStream_t st);
 uint32_t *emit_words(Workspace &ws);
 size_t emit_word_count(int V, int64_t Kp);
 hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st);

@@ -243,7 +243,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict_
 
 template <int ITEMS>
 hipError_t sort_run(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
-                    int64_t seg_len, const int4 *segtab, hipStream_t st)
+                    int64_t seg_len, const int4 *segtab, bool zeroed, hipStream_t st)
 {
     constexpr uint32_t TILEN = BLOCK * ITEMS;
     const uint32_t ntiles = (n + TILEN - 1) / TILEN;
@@ -258,8 +258,10 @@ hipError_t sort_run(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t 
     uint32_t *status = hist + (size_t)nseg * passes * 256;
     uint32_t *tickets = status + (size_t)passes * ntiles * 256;   // [pass][segment], TICKET_STRIDE apart
     uint32_t *err = tickets + (size_t)passes * nseg * TICKET_STRIDE;
-    hipError_t e = launch_fill_u32(hist, 0u, words, st);
-    if (e != hipSuccess) return e;
+    if (!zeroed) {
+        hipError_t e = launch_fill_u32(hist, 0u, words, st);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_sort_hist<ITEMS>, dim3(ntiles), dim3(BLOCK), 0, st, keys[cur].as<uint32_t>(), n, passes, sm,
                        hist);
     for (int p = 0; p < passes; p++) {
@@ -286,12 +288,12 @@ size_t sort_ws_bytes(uint32_t n, int bits, int nseg)
 }
 
 hipError_t sort_pairs_u32(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
-                          int64_t seg_len, const int4 *segtab, hipStream_t st)
+                          int64_t seg_len, const int4 *segtab, hipStream_t st, bool zeroed)
 {
     if (n == 0 || bits <= 0) return hipSuccess;
     if (bits > 32 || nseg <= 0) return hipErrorInvalidValue;
-    if (sort_items_for(n) == 4) return sort_run<4>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, st);
-    return sort_run<16>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, st);
+    if (sort_items_for(n) == 4) return sort_run<4>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, zeroed, st);
+    return sort_run<16>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, zeroed, st);
 }
 
 }  // namespace rxgs
