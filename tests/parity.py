@@ -53,7 +53,12 @@ def compare_spectra(C_gpu, ora, tol=TOL, flag=FLAG_MARGIN, max_flagged=MAX_FLAGG
                                f"{err[~flagged[j]].max():.3e} at {np.unravel_index(np.argmax(np.where(flagged[j], 0, err)), err.shape)}")
         worst = max(worst, float(err[~flagged[j]].max()) if (~flagged[j]).any() else 0.0)
     frac = float(flagged.mean())
-    print(f"[parity] worst rel err {worst:.3e}, flagged pixels {frac:.2e}")
+    wf = 0.0
+    for j in range(N):
+        if flagged[j].any():
+            scale = max(np.abs(C_ora[j]).max(), 1e-30)
+            wf = max(wf, float((np.abs(C_gpu[j].astype(np.float64) - C_ora[j]).max(axis=0) / scale)[flagged[j]].max()))
+    print(f"[parity] worst rel err {worst:.3e}, flagged pixels {frac:.2e} (worst there {wf:.2e})")
     assert frac <= max_flagged, f"flagged fraction {frac:.2e}"
     return worst, frac
 
