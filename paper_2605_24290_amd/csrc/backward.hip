@@ -22,6 +22,7 @@ namespace rxgs {
 
 constexpr int MLPB_PART = 4096 + 64 + 128 + 2 + 62;   // dW2, db2, dW3, db3, pad
 constexpr int W1B_CHUNK = 128;                        // Gaussians per dW1b partial
+constexpr int RED_GROUPS = 64;                        // row groups of the two-stage column sums
 constexpr float LN2F = 0.69314718055994531f;
 
 // ----------------------------------------------------------------------------
@@ -238,6 +239,19 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
         const bool valid = pl < nvalid;
         const int64_t nv = (int64_t)s0 + nvalid;
         const size_t obase = (size_t)view * Kp;
+        // A pair whose dL/ds is zero for every receiver adds exactly zero to
+        // every gradient below.  In optically thick scenes only the nearest
+        // few hundred Gaussians of a view are composited, so most items have
+        // no nonzero dL/ds at all and are skipped here (uniform per wave).
+        {
+            bool any = false;
+            if (valid)
+                for (int jj = 0; jj < nj; jj++) {
+                    const float2 d = dS[(size_t)(j0 + jj) * Kp + s];
+                    any = any || d.x != 0.f || d.y != 0.f;
+                }
+            if (__ballot(any) == 0) continue;
+        }
         const uint32_t k = (uint32_t)min((int64_t)order[obase + (valid ? s : s0)], K - 1);
         float l[32];
         {
@@ -264,6 +278,7 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
         for (int jj = 0; jj < nj; jj++) {
             const int j = j0 + jj;
             const float2 dsv = valid ? dS[(size_t)j * Kp + s] : make_float2(0.f, 0.f);
+            if (__ballot(dsv.x != 0.f || dsv.y != 0.f) == 0) continue;   // adds exactly zero
             float x1[32];
             {
                 const float4 *gs = reinterpret_cast<const float4 *>(Gp + (size_t)j * HID + h * 32);
@@ -387,14 +402,30 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
     }
 }
 
-// fixed-order sum of the per-wave partials into the flat MLP gradient
-__global__ __launch_bounds__(BLOCK) void k_mlp_bwd_reduce(const float *__restrict__ part, int nwaves,
-                                                          float *__restrict__ gmlp)
+// First stage of a fixed-order column sum of a (nrows x ld) partial-sum
+// matrix: group blockIdx.y sums its contiguous run of rows in order, in FP64.
+// The groups run in parallel; the second stage adds the RED_GROUPS group sums
+// in order, so the result does not depend on scheduling.
+__global__ __launch_bounds__(BLOCK) void k_colsum_groups(const float *__restrict__ part, int nrows, int ld, int ncols,
+                                                         double *__restrict__ out)
+{
+    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    if (c >= ncols) return;
+    const int per = (nrows + RED_GROUPS - 1) / RED_GROUPS;
+    const int r0 = blockIdx.y * per, r1 = min(nrows, r0 + per);
+    double acc = 0.0;
+#pragma unroll 8
+    for (int r = r0; r < r1; r++) acc += part[(size_t)r * ld + c];
+    out[(size_t)blockIdx.y * ncols + c] = acc;
+}
+
+// second stage: the flat MLP gradient of layers 2 and 3 from the group sums
+__global__ __launch_bounds__(BLOCK) void k_mlp_bwd_reduce(const double *__restrict__ red, float *__restrict__ gmlp)
 {
     const int e = blockIdx.x * BLOCK + threadIdx.x;
     if (e >= 4096 + 194) return;
     double acc = 0.0;
-    for (int w = 0; w < nwaves; w++) acc += part[(size_t)w * MLPB_PART + e];
+    for (int gi = 0; gi < RED_GROUPS; gi++) acc += red[(size_t)gi * (4096 + 194) + e];
     const int W2OFF = HID * MLP_IN + HID, B2OFF = W2OFF + HID * HID, W3OFF = B2OFF + HID, B3OFF = W3OFF + 2 * HID;
     int dst;
     if (e < 4096) dst = W2OFF + e;
@@ -453,13 +484,12 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_w1b_part(const float *__restrict_
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_mlp_w1b_reduce(const float *__restrict__ part, int nchunks,
-                                                          float *__restrict__ gmlp)
+__global__ __launch_bounds__(BLOCK) void k_mlp_w1b_reduce(const double *__restrict__ red, float *__restrict__ gmlp)
 {
     const int o = blockIdx.x * BLOCK + threadIdx.x;
     if (o >= HID * FEAT) return;
     double acc = 0.0;
-    for (int c = 0; c < nchunks; c++) acc += part[(size_t)c * HID * FEAT + o];
+    for (int gi = 0; gi < RED_GROUPS; gi++) acc += red[(size_t)gi * HID * FEAT + o];
     const int d = o / FEAT, c = o % FEAT;
     gmlp[d * MLP_IN + ENC + c] = (float)acc;
 }
@@ -678,8 +708,10 @@ hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *g
                            ws.dG.as<float>(), ws.mpart.as<float>());
     if (gmlp) {
         if (ws.n_items > 0) {
-            hipLaunchKernelGGL(k_mlp_bwd_reduce, dim3(nblk(4096 + 194)), dim3(BLOCK), 0, st, ws.mpart.as<float>(),
-                               nwaves, gmlp);
+            hipLaunchKernelGGL(k_colsum_groups, dim3(nblk(4096 + 194), RED_GROUPS), dim3(BLOCK), 0, st,
+                               ws.mpart.as<float>(), nwaves, MLPB_PART, 4096 + 194, ws.mred.as<double>());
+            hipLaunchKernelGGL(k_mlp_bwd_reduce, dim3(nblk(4096 + 194)), dim3(BLOCK), 0, st, ws.mred.as<double>(),
+                               gmlp);
         } else {
             hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(gmlp), 0u, RXGS_MLP_NPARAM, st);
             if (e != hipSuccess) return e;
@@ -690,8 +722,10 @@ hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *g
         if (nchunks > 0) {
             hipLaunchKernelGGL(k_mlp_w1b_part, dim3((unsigned)nchunks), dim3(BLOCK), 0, st, ws.dL.as<float>(),
                                sc.feat.as<float>(), sc.K, ws.w1part.as<float>());
-            hipLaunchKernelGGL(k_mlp_w1b_reduce, dim3(nblk(HID * FEAT)), dim3(BLOCK), 0, st, ws.w1part.as<float>(),
-                               nchunks, gmlp);
+            hipLaunchKernelGGL(k_colsum_groups, dim3(nblk(HID * FEAT), RED_GROUPS), dim3(BLOCK), 0, st,
+                               ws.w1part.as<float>(), nchunks, HID * FEAT, HID * FEAT, ws.mred.as<double>());
+            hipLaunchKernelGGL(k_mlp_w1b_reduce, dim3(nblk(HID * FEAT)), dim3(BLOCK), 0, st, ws.mred.as<double>(),
+                               gmlp);
         } else {
             hipError_t e = hipSuccess;
             for (int d = 0; d < HID && e == hipSuccess; d++)
@@ -717,6 +751,7 @@ hipError_t launch_project_bwd(const Scene &sc, Workspace &ws, const rxgs_grads &
 }
 
 size_t mlp_part_bytes(const Workspace &ws) { return (size_t)mlp_bwd_waves(ws) * MLPB_PART * 4; }
+size_t mlp_red_bytes() { return (size_t)RED_GROUPS * MLPB_PART * 8; }
 size_t w1b_part_bytes(int64_t K) { return (size_t)std::max<int64_t>((K + W1B_CHUNK - 1) / W1B_CHUNK, 1) * HID * FEAT * 4; }
 
 }  // namespace rxgs

@@ -126,7 +126,7 @@ void free_workspace(Workspace &ws)
                       &ws.pkey[0], &ws.pkey[1], &ws.pval[0], &ws.pval[1], &ws.ranges, &ws.rad,
                       &ws.Lp,      &ws.Gp,      &ws.items,  &ws.Tfin,   &ws.nlast,  &ws.part,
                       &ws.counters, &ws.hist,   &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
-                      &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.hist_b};
+                      &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.mred,   &ws.hist_b};
     for (DevBuf *b : bufs) release(*b);
     if (ws.staged) (void)hipEventDestroy(ws.staged);
     if (ws.counted) (void)hipEventDestroy(ws.counted);
@@ -882,6 +882,7 @@ extern "C" rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *sav
         GROW(ctx, ws.dG, (size_t)ws.N * HID * 4);
         GROW(ctx, ws.mpart, mlp_part_bytes(ws));
         GROW(ctx, ws.w1part, w1b_part_bytes(K));
+        GROW(ctx, ws.mred, mlp_red_bytes());
         HIPCHK(ctx, launch_fill_u32(ws.dL.as<uint32_t>(), 0u, (size_t)K * HID, st));
         HIPCHK(ctx, launch_fill_u32(ws.dG.as<uint32_t>(), 0u, (size_t)ws.N * HID, st));
     }

@@ -156,6 +156,7 @@ struct Workspace {
     DevBuf dG;        // N x 64
     DevBuf mpart;     // per-wave partial sums of the MLP backward
     DevBuf w1part;    // per-chunk partial sums of dW1 (Gaussian part)
+    DevBuf mred;      // FP64 group sums of the two-stage column reductions
     // host staging (pinned) and the events guarding it
     void *h_pinned = nullptr;
     size_t h_pinned_cap = 0;
@@ -248,6 +249,7 @@ size_t mlp_part_bytes(const Workspace &ws);
 unsigned long long *stat_words(Workspace &ws);
 int sort_items_for(uint32_t n);
 size_t w1b_part_bytes(int64_t K);
+size_t mlp_red_bytes();
 
 bool grow(DevBuf &b, size_t bytes);
 void release(DevBuf &b);
