@@ -28,22 +28,31 @@ constexpr float LN2F = 0.69314718055994531f;
 // ----------------------------------------------------------------------------
 // Same (tile, receiver chunk) grid, pixel mapping, LDS staging and per-wave
 // entry lists as the forward; batches are staged from the end of the consumed
-// part of the tile list towards its start and walked in reverse.
+// part of the tile list towards its start and walked in reverse.  Each
+// forward chunk is split into `split` blocks of at most R receivers.  The
+// per-entry wave sums of a batch are accumulated in LDS over the block's four
+// waves and flushed to global memory once per batch, one entry per thread:
+// global atomics inside the walk stall it (they count against the wave's
+// outstanding-memory budget) and contend across the waves of a tile.
 template <int R>
 __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
     const float4 *__restrict__ srec, const uint32_t *__restrict__ pval, const uint2 *__restrict__ ranges,
-    const float2 *__restrict__ rad, const int4 *__restrict__ chunks, int64_t Kp, DevGrid g, int tx_mode,
-    const float *__restrict__ C, const float *__restrict__ dC, const float *__restrict__ dP,
+    const float2 *__restrict__ rad, const int4 *__restrict__ chunks, int split, int64_t Kp, DevGrid g,
+    int tx_mode, const float *__restrict__ C, const float *__restrict__ dC, const float *__restrict__ dP,
     const float *__restrict__ Tfin, const int *__restrict__ nlast, float *__restrict__ dS,
     float *__restrict__ g2d)
 {
     __shared__ BlendStage st;
     __shared__ float2 s_rad[R][BLOCK];
+    __shared__ float s_acc[6][BLOCK];
+    __shared__ float2 s_dacc[R][BLOCK];
     __shared__ int s_max[4];
 
     const int tile = blockIdx.x;
-    const int4 ch = chunks[blockIdx.y];
-    const int view = ch.x, j0 = ch.y, nrx = ch.z;
+    const int4 ch = chunks[blockIdx.y / split];
+    const int sub = blockIdx.y - (blockIdx.y / split) * split;
+    const int view = ch.x, j0 = ch.y + sub * R, nrx = min(ch.z - sub * R, R);
+    if (nrx <= 0) return;   // uniform over the block, before any barrier
     const int tread = tx_mode ? view : j0;
     const int ty = tile / g.tiles_x, tx = tile - ty * g.tiles_x;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -85,6 +94,10 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
         const int cnt = end - start;
         __syncthreads();
         uint32_t p = 0;
+#pragma unroll
+        for (int c = 0; c < 6; c++) s_acc[c][t] = 0.f;
+#pragma unroll
+        for (int r = 0; r < R; r++) s_dacc[r][t] = make_float2(0.f, 0.f);
         if (t < cnt) {
             p = (uint32_t)min((int64_t)pval[rg.x + start + t], view_end - 1);
             const int64_t s = max((int64_t)p - (int64_t)view * Kp, (int64_t)0);
@@ -141,24 +154,41 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
                 }
             }
             if (__ballot(act) == 0) continue;   // uniform across the wave
-            const uint32_t pe = st.p[e];
             float vals[6] = {gu, gv, gca, gcb, gcc, glo};
 #pragma unroll
             for (int c = 0; c < 6; c++) {
                 const float v = wave_sum_last(vals[c]);
-                if (lane == 63 && v != 0.f) atomicAdd(&g2d[(size_t)pe * 8 + c], v);
+                if (lane == 63 && v != 0.f) atomicAdd(&s_acc[c][e], v);
             }
-            const int64_t s = (int64_t)pe - (int64_t)view * Kp;
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 if (r < nrx) {
                     const float vx = wave_sum_last(dsr[r].x);
                     const float vy = wave_sum_last(dsr[r].y);
                     if (lane == 63) {
-                        float *d = dS + ((size_t)(j0 + r) * Kp + s) * 2;
-                        if (vx != 0.f) atomicAdd(d, vx);
-                        if (vy != 0.f) atomicAdd(d + 1, vy);
+                        if (vx != 0.f) atomicAdd(&s_dacc[r][e].x, vx);
+                        if (vy != 0.f) atomicAdd(&s_dacc[r][e].y, vy);
                     }
+                }
+            }
+        }
+        __syncthreads();
+        // flush the batch: thread t owns entry t
+        if (t < cnt) {
+            const uint32_t pe = st.p[t];
+#pragma unroll
+            for (int c = 0; c < 6; c++) {
+                const float v = s_acc[c][t];
+                if (v != 0.f) atomicAdd(&g2d[(size_t)pe * 8 + c], v);
+            }
+            const int64_t s = (int64_t)pe - (int64_t)view * Kp;
+#pragma unroll
+            for (int r = 0; r < R; r++) {
+                if (r < nrx) {
+                    const float2 d = s_dacc[r][t];
+                    float *dd = dS + ((size_t)(j0 + r) * Kp + s) * 2;
+                    if (d.x != 0.f) atomicAdd(dd, d.x);
+                    if (d.y != 0.f) atomicAdd(dd + 1, d.y);
                 }
             }
         }
@@ -656,26 +686,29 @@ __global__ __launch_bounds__(BLOCK) void k_project_bwd(
 static inline unsigned nblk(size_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
 template <int R>
-static void blend_bwd_launch(Workspace &ws, const float *C, const float *dC, const float *dP, hipStream_t st)
+static hipError_t blend_bwd_launch(Workspace &ws, const float *C, const float *dC, const float *dP, hipStream_t st)
 {
-    dim3 grid((unsigned)ws.g.tiles, (unsigned)ws.n_chunks);
+    // forward chunks hold at most ws.R receivers; split them into R-receiver blocks
+    const int split = (ws.R + R - 1) / R;
+    const int64_t ny = (int64_t)ws.n_chunks * split;
+    if (ny > 65535 || ws.g.tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
+    dim3 grid((unsigned)ws.g.tiles, (unsigned)ny);
     hipLaunchKernelGGL(k_blend_bwd<R>, grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                        ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
-                       ws.d_chunks, ws.Kp, ws.g, ws.mode == RXGS_MODE_TX ? 1 : 0, C, dC, dP,
+                       ws.d_chunks, split, ws.Kp, ws.g, ws.mode == RXGS_MODE_TX ? 1 : 0, C, dC, dP,
                        ws.Tfin.as<float>(), ws.nlast.as<int>(), ws.dS.as<float>(), ws.g2d.as<float>());
+    return hipGetLastError();
 }
 
 hipError_t launch_blend_bwd(Workspace &ws, const float *C, const float *dC, const float *dP, hipStream_t st)
 {
     if (ws.n_chunks == 0) return hipSuccess;
     switch (ws.R) {
-    case 1: blend_bwd_launch<1>(ws, C, dC, dP, st); break;
-    case 2: blend_bwd_launch<2>(ws, C, dC, dP, st); break;
-    case 4: blend_bwd_launch<4>(ws, C, dC, dP, st); break;
-    case 8: blend_bwd_launch<8>(ws, C, dC, dP, st); break;
-    default: blend_bwd_launch<16>(ws, C, dC, dP, st); break;
+    case 1: return blend_bwd_launch<1>(ws, C, dC, dP, st);
+    case 2: return blend_bwd_launch<2>(ws, C, dC, dP, st);
+    case 4: return blend_bwd_launch<4>(ws, C, dC, dP, st);
+    default: return blend_bwd_launch<8>(ws, C, dC, dP, st);   // 8 and 16
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_rad_bwd(const Scene &sc, Workspace &ws, float *grad, hipStream_t st)
