@@ -40,7 +40,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
     const float2 *__restrict__ rad, const int4 *__restrict__ chunks, int split, int64_t Kp, DevGrid g,
     int tx_mode, const float *__restrict__ C, const float *__restrict__ dC, const float *__restrict__ dP,
     const float *__restrict__ Tfin, const int *__restrict__ nlast, float *__restrict__ dS,
-    float *__restrict__ g2d)
+    float *__restrict__ g2d, uint8_t *__restrict__ live)
 {
     __shared__ BlendStage st;
     __shared__ float2 s_rad[R][BLOCK];
@@ -182,6 +182,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
                 if (v != 0.f) atomicAdd(&g2d[(size_t)pe * 8 + c], v);
             }
             const int64_t s = (int64_t)pe - (int64_t)view * Kp;
+            bool any = false;
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 if (r < nrx) {
@@ -189,8 +190,11 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
                     float *dd = dS + ((size_t)(j0 + r) * Kp + s) * 2;
                     if (d.x != 0.f) atomicAdd(dd, d.x);
                     if (d.y != 0.f) atomicAdd(dd + 1, d.y);
+                    any = any || d.x != 0.f || d.y != 0.f;
                 }
             }
+            // the MLP backward only visits position blocks marked here
+            if (any) live[pe / MLP_PAIRS] = 1;
         }
     }
 }
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
     const float *__restrict__ Lp, const float *__restrict__ Gp, const float *__restrict__ w2a,
     const float *__restrict__ w2b, const float4 *__restrict__ tab, const float *__restrict__ W3,
     const uint32_t *__restrict__ order, const int4 *__restrict__ items, int nitems, int64_t Kp, int64_t K,
-    const unsigned long long *__restrict__ counters, const float2 *__restrict__ dS, float *__restrict__ dL,
+    const uint8_t *__restrict__ live, const float2 *__restrict__ dS, float *__restrict__ dL,
     float *__restrict__ dG, float *__restrict__ part)
 {
     __shared__ float s_w2a[2 * 32 * 64];
@@ -261,7 +265,25 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
         for (int ob = 0; ob < 2; ob++) w3o[c][ob] = W3[c * HID + pl + 32 * ob];
     const int pos_i0 = hid_pos(pl), pos_i1 = hid_pos(pl + 32);
 
-    for (int item = gw; item < nitems; item += nw) {
+    // A pair whose dL/ds is zero for every receiver adds exactly zero to every
+    // gradient below.  In optically thick scenes only the nearest few hundred
+    // Gaussians of a view are composited, so most items have no nonzero dL/ds;
+    // the blend backward marks the position blocks that do, and each round
+    // reads the marks of this wave's next 64 items at once.
+    for (int base = gw; base < nitems; base += 64 * nw) {
+    uint64_t todo;
+    {
+        const int mine = base + lane * nw;
+        bool lv = false;
+        if (mine < nitems) {
+            const int4 it = items[mine];
+            lv = live[((size_t)it.x * Kp + it.y) / MLP_PAIRS] != 0;
+        }
+        todo = __ballot(lv);
+    }
+    while (todo) {
+        const int item = base + __builtin_ctzll(todo) * nw;
+        todo &= todo - 1;
         const int4 it = items[item];
         const int view = it.x, s0 = it.y, j0 = it.z, nj = it.w & 255;
         const int64_t s = s0 + pl;
@@ -269,19 +291,6 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
         const bool valid = pl < nvalid;
         const int64_t nv = (int64_t)s0 + nvalid;
         const size_t obase = (size_t)view * Kp;
-        // A pair whose dL/ds is zero for every receiver adds exactly zero to
-        // every gradient below.  In optically thick scenes only the nearest
-        // few hundred Gaussians of a view are composited, so most items have
-        // no nonzero dL/ds at all and are skipped here (uniform per wave).
-        {
-            bool any = false;
-            if (valid)
-                for (int jj = 0; jj < nj; jj++) {
-                    const float2 d = dS[(size_t)(j0 + jj) * Kp + s];
-                    any = any || d.x != 0.f || d.y != 0.f;
-                }
-            if (__ballot(any) == 0) continue;
-        }
         const uint32_t k = (uint32_t)min((int64_t)order[obase + (valid ? s : s0)], K - 1);
         float l[32];
         {
@@ -403,6 +412,7 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
             for (int q = 0; q < 32; q++)
                 if (dl[q] != 0.f) atomicAdd(&dL[(size_t)k * HID + h * 32 + q], dl[q]);
     }
+    }
     // per-wave partial sums (natural layouts), reduced in a fixed order later
     float *pw = part + (size_t)gw * MLPB_PART;
 #pragma unroll
@@ -500,6 +510,19 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_w1b_part(const float *__restrict_
         const int kk = i / HID, d = i % HID;
         s_dl[kk][d] = kk < n ? dL[(size_t)(k0 + kk) * HID + hid_pos(d)] : 0.f;
     }
+    __syncthreads();
+    // rows with a zero dL add exactly zero: list the others in increasing
+    // order (threads 0..127 own one row each; waves 0 and 1 hold them)
+    __shared__ unsigned char s_list[W1B_CHUNK];
+    __shared__ int s_cnt[2];
+    bool nz = false;
+    if (threadIdx.x < W1B_CHUNK)
+        for (int d = 0; d < HID; d++) nz = nz || s_dl[threadIdx.x][d] != 0.f;
+    const uint64_t bal = __ballot(nz);
+    if ((threadIdx.x & 63) == 0 && threadIdx.x < W1B_CHUNK) s_cnt[threadIdx.x >> 6] = (int)__popcll(bal);
+    __syncthreads();
+    if (nz) s_list[(threadIdx.x >= 64 ? s_cnt[0] : 0) + count_below(bal)] = (unsigned char)threadIdx.x;
+    const int nl = s_cnt[0] + s_cnt[1];
     for (int i = threadIdx.x; i < W1B_CHUNK * FEAT; i += BLOCK) {
         const int kk = i / FEAT, c = i % FEAT;
         s_f[kk][c] = kk < n ? feat[(size_t)(k0 + kk) * FEAT + c] : 0.f;
@@ -509,7 +532,10 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_w1b_part(const float *__restrict_
     for (int o = threadIdx.x; o < HID * FEAT; o += BLOCK) {
         const int d = o / FEAT, c = o % FEAT;
         float acc = 0.f;
-        for (int kk = 0; kk < n; kk++) acc = fmaf(s_dl[kk][d], s_f[kk][c], acc);
+        for (int q = 0; q < nl; q++) {
+            const int kk = s_list[q];
+            acc = fmaf(s_dl[kk][d], s_f[kk][c], acc);
+        }
         part[(size_t)blockIdx.x * HID * FEAT + o] = acc;
     }
 }
@@ -524,17 +550,38 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_w1b_reduce(const double *__restri
     gmlp[d * MLP_IN + ENC + c] = (float)acc;
 }
 
-// feature gradients: df_k = W1[:, 36:]^T dL_k
+// feature gradients: df_k = W1[:, 36:]^T dL_k, DF_CHUNK Gaussians per block;
+// W1's feature columns and 8 dL rows at a time are staged in LDS
+constexpr int DF_CHUNK = 64;
 __global__ __launch_bounds__(BLOCK) void k_mlp_dfeat(const float *__restrict__ dL, const float *__restrict__ W1,
                                                      int64_t K, float *__restrict__ gfeat)
 {
-    const int64_t idx = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (idx >= K * FEAT) return;
-    const int64_t k = idx / FEAT;
-    const int c = (int)(idx % FEAT);
-    float acc = 0.f;
-    for (int d = 0; d < HID; d++) acc = fmaf(W1[d * MLP_IN + ENC + c], dL[(size_t)k * HID + hid_pos(d)], acc);
-    gfeat[idx] = acc;
+    __shared__ float s_w[HID][FEAT];
+    __shared__ float s_dl[8][HID];
+    __shared__ int s_nz[8];
+    for (int i = threadIdx.x; i < HID * FEAT; i += BLOCK) s_w[i / FEAT][i % FEAT] = W1[(i / FEAT) * MLP_IN + ENC + i % FEAT];
+    const int64_t k0 = (int64_t)blockIdx.x * DF_CHUNK;
+    const int kk = threadIdx.x >> 5, c = threadIdx.x & 31;
+    for (int r = 0; r < DF_CHUNK / 8; r++) {
+        const int64_t kb = k0 + 8 * r;
+        __syncthreads();
+        if (threadIdx.x < 8) s_nz[threadIdx.x] = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < 8 * HID; i += BLOCK) {
+            const int q = i / HID, d = i % HID;
+            const float x = kb + q < K ? dL[(size_t)(kb + q) * HID + hid_pos(d)] : 0.f;
+            s_dl[q][d] = x;
+            if (x != 0.f) s_nz[q] = 1;
+        }
+        __syncthreads();
+        const int64_t k = kb + kk;
+        if (k < K) {
+            float acc = 0.f;
+            if (s_nz[kk])   // a zero row gives exactly zero
+                for (int d = 0; d < HID; d++) acc = fmaf(s_w[d][c], s_dl[kk][d], acc);
+            gfeat[(size_t)k * FEAT + c] = acc;
+        }
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -696,7 +743,8 @@ static hipError_t blend_bwd_launch(Workspace &ws, const float *C, const float *d
     hipLaunchKernelGGL(k_blend_bwd<R>, grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                        ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                        ws.d_chunks, split, ws.Kp, ws.g, ws.mode == RXGS_MODE_TX ? 1 : 0, C, dC, dP,
-                       ws.Tfin.as<float>(), ws.nlast.as<int>(), ws.dS.as<float>(), ws.g2d.as<float>());
+                       ws.Tfin.as<float>(), ws.nlast.as<int>(), ws.dS.as<float>(), ws.g2d.as<float>(),
+                       ws.live.as<uint8_t>());
     return hipGetLastError();
 }
 
@@ -724,7 +772,7 @@ hipError_t launch_rad_bwd(const Scene &sc, Workspace &ws, float *grad, hipStream
 int mlp_bwd_waves(const Workspace &ws)
 {
     const int want = (ws.n_items + 3) / 4;
-    return 4 * std::max(1, std::min(want, 1024));
+    return 4 * std::max(1, std::min(want, 256));   // one wave per SIMD fits (372 registers a lane)
 }
 
 hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *gfeat, float *gmlp, hipStream_t st)
@@ -737,7 +785,7 @@ hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *g
         hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)(nwaves / 4)), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                            ws.Gp.as<float>(), m.w2a.as<float>(), m.w2b.as<float>(), m.tab.as<float4>(), W3,
                            ws.vorder.as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, sc.K,
-                           ws.counters.as<unsigned long long>(), ws.dS.as<float2>(), ws.dL.as<float>(),
+                           ws.live.as<uint8_t>(), ws.dS.as<float2>(), ws.dL.as<float>(),
                            ws.dG.as<float>(), ws.mpart.as<float>());
     if (gmlp) {
         if (ws.n_items > 0) {
@@ -767,8 +815,8 @@ hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *g
         }
     }
     if (gfeat && sc.K > 0)
-        hipLaunchKernelGGL(k_mlp_dfeat, dim3(nblk((size_t)sc.K * FEAT)), dim3(BLOCK), 0, st, ws.dL.as<float>(), W1,
-                           sc.K, gfeat);
+        hipLaunchKernelGGL(k_mlp_dfeat, dim3((unsigned)((sc.K + DF_CHUNK - 1) / DF_CHUNK)), dim3(BLOCK), 0, st,
+                           ws.dL.as<float>(), W1, sc.K, gfeat);
     return hipGetLastError();
 }
 

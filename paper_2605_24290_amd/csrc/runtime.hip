@@ -126,7 +126,7 @@ void free_workspace(Workspace &ws)
                       &ws.pkey[0], &ws.pkey[1], &ws.pval[0], &ws.pval[1], &ws.ranges, &ws.rad,
                       &ws.Lp,      &ws.Gp,      &ws.items,  &ws.Tfin,   &ws.nlast,  &ws.part,
                       &ws.counters, &ws.hist,   &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
-                      &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.mred,   &ws.hist_b};
+                      &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.mred,   &ws.live,   &ws.hist_b};
     for (DevBuf *b : bufs) release(*b);
     if (ws.staged) (void)hipEventDestroy(ws.staged);
     if (ws.counted) (void)hipEventDestroy(ws.counted);
@@ -877,6 +877,8 @@ extern "C" rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *sav
     GROW(ctx, ws.g2d, VK * 32);
     HIPCHK(ctx, launch_fill_u32(ws.dS.as<uint32_t>(), 0u, (size_t)ws.N * ws.Kp * 2, st));
     HIPCHK(ctx, launch_fill_u32(ws.g2d.as<uint32_t>(), 0u, VK * 8, st));
+    GROW(ctx, ws.live, VK / MLP_PAIRS + 4);
+    HIPCHK(ctx, launch_fill_u32(ws.live.as<uint32_t>(), 0u, (VK / MLP_PAIRS + 3) / 4, st));
     if (ws.use_mlp) {
         GROW(ctx, ws.dL, (size_t)K * HID * 4);
         GROW(ctx, ws.dG, (size_t)ws.N * HID * 4);

@@ -157,6 +157,7 @@ struct Workspace {
     DevBuf mpart;     // per-wave partial sums of the MLP backward
     DevBuf w1part;    // per-chunk partial sums of dW1 (Gaussian part)
     DevBuf mred;      // FP64 group sums of the two-stage column reductions
+    DevBuf live;      // per (view, 32 sorted positions): some dL/ds is nonzero
     // host staging (pinned) and the events guarding it
     void *h_pinned = nullptr;
     size_t h_pinned_cap = 0;
