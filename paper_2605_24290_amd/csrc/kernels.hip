@@ -720,7 +720,7 @@ __device__ __forceinline__ int4 make_item(int i, const uint32_t *__restrict__ it
         if (item_off[mid] <= (uint32_t)i) lo = mid;
         else hi = mid - 1;
     }
-    const int4 vi = vinfo[lo];   // (first receiver, receivers, visible, 0)
+    const int4 vi = vinfo[lo];   // (first receiver, receivers, visible, takes the weights pass)
     const int q = i - (int)item_off[lo];
     const int nrg = (vi.y + MLP_RG - 1) / MLP_RG;
     const int sb = q / nrg, a = q - sb * nrg;
@@ -854,8 +854,9 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_pairs_f32(const float *__restrict
                                                      const uint32_t *__restrict__ order,
                                                      const int4 *__restrict__ items, int nitems, int64_t Kp,
                                                      int64_t K, const unsigned long long *__restrict__ counters,
-                                                     float2 *__restrict__ rad)
+                                                     float2 *__restrict__ rad, const int *__restrict__ nlive)
 {
+    if (nlive) nitems = min(nitems, *nlive);
     __shared__ float s_w2a[2 * 32 * 64];
     __shared__ float4 s_tab[2 * 2 * 16];
     for (int i = threadIdx.x; i < 2 * 32 * 64; i += BLOCK) s_w2a[i] = w2a[i];
@@ -1188,8 +1189,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) v
                                                      const uint32_t *__restrict__ order,
                                                      const int4 *__restrict__ items, int nitems, int64_t Kp,
                                                      int64_t K, const unsigned *__restrict__ amax,
-                                                     float2 *__restrict__ rad)
+                                                     float2 *__restrict__ rad, const int *__restrict__ nlive)
 {
+    if (nlive) nitems = min(nitems, *nlive);
     __shared__ half8 s_w1h[FUSED ? 8 * 64 : 1];
     __shared__ float4 s_b1[FUSED ? 2 * 8 : 1];
     if (FUSED) {
@@ -1555,12 +1557,13 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
 // which leaves T and the sums bit-identical to skipping it.  WRAP: some entry of
 // the list spans more than half the azimuth circle, so pixel offsets are
 // wrapped into [-W/2, W/2) (selects).  SAVE: track the stop index and the
-// composited count (saved states and statistics only).
-template <int R, bool SAVE, bool WRAP>
+// composited count (saved states and statistics only).  MARK: flag in s_mark
+// every entry that some lane composites (the weights-only pass).
+template <int R, bool SAVE, bool WRAP, bool MARK = false>
 __device__ __forceinline__ void blend_walk_multi(const BlendStage &st, const float2 (*s_rad)[BLOCK], int wv, int n,
                                            int lbase, float colf, float rowf, float Wf, float halfW, float &T,
                                            float2 (&acc)[R], int &last, uint32_t &ncomp, uint32_t &neval,
-                                           uint32_t &nslot, bool &done)
+                                           uint32_t &nslot, bool &done, unsigned char *s_mark = nullptr)
 {
     for (int i = 0; i < n; i++) {
         if (SAVE) {
@@ -1591,12 +1594,19 @@ __device__ __forceinline__ void blend_walk_multi(const BlendStage &st, const flo
             last = inc ? lbase + e : last;
             ncomp += inc ? 1u : 0u;
         }
+        if (MARK && inc) s_mark[e] = 1;
         done = done || T < T_EPS;
         if ((i & 3) == 3 && __all(done)) break;
     }
 }
 
-template <int R, bool SAVE>
+// MARK (weights-only pass over chunks with no receivers): set live[b] for
+// every block b of MLP_PAIRS sorted positions holding an entry that some pixel
+// composites; the walk is the colour pass's own, so the decisions are the
+// same.  Otherwise, when live is given, positions of unmarked blocks read a
+// zero radiance: no pixel composites them, so their weight is zero and the
+// sums are unchanged.
+template <int R, bool SAVE, bool MARK = false>
 __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restrict__ srec,
                                                      const uint32_t *__restrict__ pval,
                                                      const uint2 *__restrict__ ranges,
@@ -1605,11 +1615,14 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restr
                                                      float *__restrict__ C, float *__restrict__ Tfin,
                                                      int *__restrict__ nlast, float *__restrict__ part,
                                                      unsigned long long *__restrict__ stats,
-                                                     const uint32_t *__restrict__ torder)
+                                                     const uint32_t *__restrict__ torder,
+                                                     uint8_t *__restrict__ live)
 {
     __shared__ BlendStage st;
     __shared__ float2 s_rad[R][BLOCK];
     __shared__ float s_red[4][R][3];
+    __shared__ unsigned char s_mark[MARK ? BLOCK : 1];
+    if (MARK) s_mark[threadIdx.x] = 0;
 
     // grid: (chunk, rank of the tile in its view's longest-first order)
     const int4 ch = chunks[blockIdx.x];
@@ -1639,23 +1652,30 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restr
         if ((uint32_t)t < cnt) {
             p = min(pval[base + t], (uint32_t)(view_end - 1));
             const int64_t s = max((int64_t)p - (int64_t)view * Kp, (int64_t)0);
+            const bool used = MARK || live == nullptr || live[p / MLP_PAIRS] != 0;
 #pragma unroll
             for (int r = 0; r < R; r++)
-                s_rad[r][t] = (r < nrx) ? rad[(size_t)(j0 + r) * Kp + s] : make_float2(0.f, 0.f);
+                s_rad[r][t] = (r < nrx && used) ? rad[(size_t)(j0 + r) * Kp + s] : make_float2(0.f, 0.f);
         }
         stage_batch(st, srec, p, (uint32_t)t < cnt, tx, ty, g);
         if (__any(!done)) {
             const int n = __builtin_amdgcn_readfirstlane(st.len[wv]);
             const int lbase = (int)(base - rg.x) + 1;
             if (__builtin_amdgcn_readfirstlane(st.wrap[wv]))
-                blend_walk_multi<R, SAVE, true>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T, acc, last, ncomp,
-                                          neval, nslot, done);
+                blend_walk_multi<R, SAVE, true, MARK>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T, acc, last,
+                                                      ncomp, neval, nslot, done, s_mark);
             else
-                blend_walk_multi<R, SAVE, false>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T, acc, last, ncomp,
-                                           neval, nslot, done);
+                blend_walk_multi<R, SAVE, false, MARK>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T, acc, last,
+                                                       ncomp, neval, nslot, done, s_mark);
         }
-        if (__syncthreads_and(done ? 1 : 0)) break;
+        const int alldone = __syncthreads_and(done ? 1 : 0);
+        if (MARK) {
+            if ((uint32_t)t < cnt && s_mark[t]) live[st.p[t] / MLP_PAIRS] = 1;
+            s_mark[t] = 0;
+        }
+        if (alldone) break;
     }
+    if (MARK) return;
 
     const size_t P = (size_t)g.H * g.W;
     const size_t pix = (size_t)row * g.W + col;
@@ -1948,13 +1968,15 @@ hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStr
 {
     const float *raw = m.raw.as<float>();
     const float *b3 = raw + HID * MLP_IN + HID + HID * HID + HID + 2 * HID;
+    const int4 *items = ws.lazy ? ws.items_live.as<int4>() : ws.items.as<int4>();
+    const int *nlive = ws.lazy ? live_count(ws) : nullptr;
     if (ws.n_items > 0) {
         const unsigned blocks = (unsigned)std::min((ws.n_items + 3) / 4, 256 * 8);
         if (m.fp32) {
             hipLaunchKernelGGL(k_mlp_pairs_f32, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                                ws.Gp.as<float>(), m.w2a.as<float>(), m.tab.as<float4>(), b3,
-                               ws.vorder.as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K,
-                               ws.counters.as<unsigned long long>(), ws.rad.as<float2>());
+                               ws.vorder.as<uint32_t>(), items, ws.n_items, ws.Kp, ws.K,
+                               ws.counters.as<unsigned long long>(), ws.rad.as<float2>(), nlive);
         } else if (mlp_fused_ok(sc, m)) {
             // bound of the Gaussians' layer-1 term: per hidden unit
             // sum_c |W1[d, 36 + c]| max|f| + |b1[d]|, rounded up
@@ -1964,14 +1986,14 @@ hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStr
             hipLaunchKernelGGL(k_mlp_pairs<true>, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                                sc.feat.as<float>(), ws.Gp.as<float>(), m.w2h.as<half8>(), m.tabh.as<float4>(), b3,
                                m.w1h.as<half8>(), m.b1tab.as<float>(), std::ldexp(1.f, -m.w1exp), lbound,
-                               ws.vorder.as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K,
-                               amax_words(ws), ws.rad.as<float2>());
+                               ws.vorder.as<uint32_t>(), items, ws.n_items, ws.Kp, ws.K,
+                               amax_words(ws), ws.rad.as<float2>(), nlive);
         } else {
             hipLaunchKernelGGL(k_mlp_pairs<false>, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                                sc.feat.as<float>(), ws.Gp.as<float>(), m.w2h.as<half8>(), m.tabh.as<float4>(), b3,
                                m.w1h.as<half8>(), m.b1tab.as<float>(), 1.f, 0.f,
-                               ws.vorder.as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, ws.K,
-                               amax_words(ws), ws.rad.as<float2>());
+                               ws.vorder.as<uint32_t>(), items, ws.n_items, ws.Kp, ws.K,
+                               amax_words(ws), ws.rad.as<float2>(), nlive);
         }
     }
     return hipGetLastError();
@@ -1997,11 +2019,12 @@ static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st)
             hipLaunchKernelGGL((k_blend_fwd_multi<R, true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
-                               ws.part.as<float>(), stat_words(ws), tord);
+                               ws.part.as<float>(), stat_words(ws), tord, ws.lazy ? ws.live.as<uint8_t>() : nullptr);
         else
             hipLaunchKernelGGL((k_blend_fwd_multi<R, false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
-                               ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord);
+                               ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord,
+                               ws.lazy ? ws.live.as<uint8_t>() : nullptr);
     }
 }
 
@@ -2019,6 +2042,66 @@ hipError_t launch_blend_fwd(Workspace &ws, float *C, bool save, hipStream_t st)
     return hipGetLastError();
 }
 
+
+// Initial marks of the lazy path: blocks of views that take the weights pass
+// start unmarked, those of the other views (few receivers: the pass would
+// cost more than the MLP it saves) start marked; plus the live-item counter.
+__global__ __launch_bounds__(BLOCK) void k_live_init(uint8_t *__restrict__ live, int64_t nblocks, int64_t bpv,
+                                                     const int4 *__restrict__ vinfo, int *__restrict__ count)
+{
+    const int64_t b = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (b == 0) *count = 0;
+    if (b >= nblocks) return;
+    live[b] = vinfo[b / bpv].w ? 0 : 1;
+}
+
+// Compact the MLP work items whose position block is marked live (any order:
+// items are independent) and count them.
+__global__ __launch_bounds__(BLOCK) void k_live_items(const int4 *__restrict__ items, int nitems,
+                                                      const uint8_t *__restrict__ live, int64_t Kp,
+                                                      int4 *__restrict__ out, int *__restrict__ count)
+{
+    const int i = blockIdx.x * BLOCK + threadIdx.x;
+    bool lv = false;
+    int4 it = make_int4(0, 0, 0, 0);
+    if (i < nitems) {
+        it = items[i];
+        lv = live[((size_t)it.x * Kp + it.y) / MLP_PAIRS] != 0;
+    }
+    const uint64_t b = __ballot(lv);
+    int base = 0;
+    if ((threadIdx.x & 63) == 0 && b) base = atomicAdd(count, (int)__popcll(b));
+    base = __shfl(base, 0);
+    if (lv) out[base + count_below(b)] = it;
+}
+
+// Weights-only pass of the lazy TX path: marks the live position blocks of
+// every view (one chunk per view with receivers, no outputs), then compacts
+// the MLP work items of those blocks.
+hipError_t launch_blend_weights(Workspace &ws, hipStream_t st)
+{
+    const int64_t nblocks = (int64_t)ws.V * ws.Kp / MLP_PAIRS;
+    hipLaunchKernelGGL(k_live_init, dim3(nblk(nblocks)), dim3(BLOCK), 0, st, ws.live.as<uint8_t>(), nblocks,
+                       ws.Kp / MLP_PAIRS, ws.d_vinfo, live_count(ws));
+    if (ws.g.tiles > 65535) return hipErrorInvalidConfiguration;
+    const uint32_t *tord = ws.tiles_ordered ? ws.torder.as<uint32_t>() : nullptr;
+    if (ws.n_wchunks > 0)
+        hipLaunchKernelGGL((k_blend_fwd_multi<1, false, true>), dim3((unsigned)ws.n_wchunks, (unsigned)ws.g.tiles),
+                       dim3(BLOCK), 0, st, ws.srec.as<float4>(), ws.pval[ws.pairs_buf].as<uint32_t>(),
+                       ws.ranges.as<uint2>(), ws.rad.as<float2>(), ws.d_wchunks, ws.Kp, ws.g, nullptr, nullptr,
+                       nullptr, nullptr, nullptr, tord, ws.live.as<uint8_t>());
+    if (ws.n_items > 0)
+        hipLaunchKernelGGL(k_live_items, dim3(nblk(ws.n_items)), dim3(BLOCK), 0, st, ws.items.as<int4>(), ws.n_items,
+                           ws.live.as<uint8_t>(), ws.Kp, ws.items_live.as<int4>(), live_count(ws));
+    return hipGetLastError();
+}
+
+int *live_count(Workspace &ws)
+{
+    return reinterpret_cast<int *>(ws.live.as<char>() + live_count_offset(ws));
+}
+
+size_t live_count_offset(const Workspace &ws) { return ((size_t)ws.V * ws.Kp / MLP_PAIRS + 63) / 64 * 64; }
 
 hipError_t launch_reduce_outputs(Workspace &ws, float *power, float *csum, hipStream_t st)
 {

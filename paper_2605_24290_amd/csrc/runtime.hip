@@ -126,7 +126,7 @@ void free_workspace(Workspace &ws)
                       &ws.pkey[0], &ws.pkey[1], &ws.pval[0], &ws.pval[1], &ws.ranges, &ws.rad,
                       &ws.Lp,      &ws.Gp,      &ws.items,  &ws.Tfin,   &ws.nlast,  &ws.part,
                       &ws.counters, &ws.hist,   &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
-                      &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.mred,   &ws.live,   &ws.hist_b};
+                      &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.mred,   &ws.live,   &ws.items_live, &ws.hist_b};
     for (DevBuf *b : bufs) release(*b);
     if (ws.staged) (void)hipEventDestroy(ws.staged);
     if (ws.counted) (void)hipEventDestroy(ws.counted);
@@ -707,6 +707,21 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         }
     ws.n_chunks = (int)chunks.size();
     ws.n_tslots = (mode == RXGS_MODE_TX) ? V : N;
+    // Lazy radiance (TX mode, several receivers per view, nothing saved): the
+    // weights do not depend on the receiver, so one weights-only pass per view
+    // marks the position blocks some pixel composites and the pair MLP runs
+    // on those blocks only.  Saved states keep every visible position's
+    // radiance (it is exported).
+    std::vector<int4> wchunks;
+    if (mode == RXGS_MODE_TX && !saved && ws.use_mlp)
+        for (int v = 0; v < V; v++)
+            if (vnrx[v] >= LAZY_MIN_RX) wchunks.push_back(make_int4(v, 0, 0, -1));
+    ws.n_wchunks = (int)wchunks.size();
+    ws.lazy = ws.n_wchunks > 0 && R >= 2;   // the colour pass is the multi-receiver one
+    if (!ws.lazy) {
+        wchunks.clear();
+        ws.n_wchunks = 0;
+    }
 
     HIPCHK(ctx, hipEventSynchronize(ws.counted));
     if (*h_err & 2u) return fail(ctx, RXGS_E_INVALID, "more than 2^32 - 1 pairs in one view; use a coarser grid");
@@ -741,14 +756,14 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     // position-major; only their per-view offsets are built here, the items
     // themselves on the device
     std::vector<uint32_t> item_off(V + 1, 0);
-    std::vector<int4> vinfo(V);   // (first receiver, receivers, visible, 0)
+    std::vector<int4> vinfo(V);   // (first receiver, receivers, visible, takes the weights pass)
     for (int v = 0; v < V; v++) {
         const int64_t ni = ws.use_mlp ? (int64_t)((ws.h_nvis[v] + MLP_PAIRS - 1) / MLP_PAIRS) *
                                             ((vnrx[v] + MLP_RG - 1) / MLP_RG)
                                       : 0;
         if ((int64_t)item_off[v] + ni >= (1ll << 31)) return fail(ctx, RXGS_E_INVALID, "too many MLP work items");
         item_off[v + 1] = item_off[v] + (uint32_t)ni;
-        vinfo[v] = make_int4(vfirst[v], vnrx[v], ws.h_nvis[v], 0);
+        vinfo[v] = make_int4(vfirst[v], vnrx[v], ws.h_nvis[v], ws.lazy && vnrx[v] >= LAZY_MIN_RX ? 1 : 0);
     }
     ws.n_items = (int)item_off[V];
     // pair-emission chunks: EM2_CHUNK visible entries of one view each
@@ -773,6 +788,10 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         GROW(ctx, ws.Lp, (size_t)std::max<int64_t>(K, 1) * HID * 4);
         GROW(ctx, ws.items, (size_t)std::max(ws.n_items, 1) * 16);
     }
+    if (ws.lazy) {
+        GROW(ctx, ws.items_live, (size_t)std::max(ws.n_items, 1) * 16);
+        GROW(ctx, ws.live, live_count_offset(ws) + 64);
+    }
 
     // the small descriptors, packed (16-byte aligned parts) into one host-to-device copy
     auto al16 = [](size_t b) { return (b + 15) / 16 * 16; };
@@ -783,7 +802,8 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     const size_t o_pbase = o_coff + al16((size_t)(V + 1) * 4);
     const size_t o_pcount = o_pbase + al16((size_t)V * 4);
     const size_t o_segtab = o_pcount + al16((size_t)V * 4);
-    const size_t stage_bytes = o_segtab + segtab.size() * 16;
+    const size_t o_wchunks = o_segtab + segtab.size() * 16;
+    const size_t stage_bytes = o_wchunks + wchunks.size() * 16;
     const size_t cnt_bytes = head_bytes;   // the counts and the emission error word
     const size_t off0 = (cnt_bytes + 63) / 64 * 64;
     if (!ensure_pinned(ws, off0 + stage_bytes + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
@@ -797,6 +817,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     std::memcpy(hp + o_pbase, ws.h_pbase.data(), (size_t)V * 4);
     std::memcpy(hp + o_pcount, ws.h_pcount.data(), (size_t)V * 4);
     std::memcpy(hp + o_segtab, segtab.data(), segtab.size() * 16);
+    if (!wchunks.empty()) std::memcpy(hp + o_wchunks, wchunks.data(), wchunks.size() * 16);
     char *dd = ws.desc.as<char>();
     ws.d_rxview = reinterpret_cast<int *>(dd);
     ws.d_chunks = reinterpret_cast<int4 *>(dd + o_chunks);
@@ -806,6 +827,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     ws.d_pbase = reinterpret_cast<uint32_t *>(dd + o_pbase);
     ws.d_pcount = reinterpret_cast<uint32_t *>(dd + o_pcount);
     ws.d_segtab = reinterpret_cast<int4 *>(dd + o_segtab);
+    ws.d_wchunks = reinterpret_cast<int4 *>(dd + o_wchunks);
     HIPCHK(ctx, hipMemcpyAsync(dd, hp, stage_bytes, hipMemcpyHostToDevice, st));
     HIPCHK(ctx, hipEventRecord(ws.staged, st));
 
@@ -824,6 +846,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     // stage 2: radiance per (receiver, sorted position)
     if (ws.use_mlp) {
         if (!ws.items_built) STAGE(ctx, "mlp_items", launch_mlp_items(ws, st));
+        if (ws.lazy) STAGE(ctx, "blend_weights", launch_blend_weights(ws, st));
         // the stored Gaussian term: for the backward, or when the pair kernel
         // cannot compute it itself
         if (saved || !mlp_fused_ok(sc, ctx->mlp)) STAGE(ctx, "mlp_local", launch_mlp_local(sc, ctx->mlp, ws, st));

@@ -23,6 +23,7 @@ constexpr int HID = 64;
 constexpr int MLP_IN = ENC + FEAT;
 constexpr int MLP_RG = 16;               // receivers per MLP work item
 constexpr int MLP_PAIRS = 32;            // sorted positions per MLP work item
+constexpr int LAZY_MIN_RX = 4;           // receivers of a TX view for its weights-only pass
 constexpr int AMAX_SLOTS = 128;          // activation-bound words after the view counters
 constexpr int STAT_SLOTS = 64;           // u64 slots per render statistic (spread atomics)
 constexpr int STAT_WORDS = 4 * STAT_SLOTS;   // four statistics, u64 each
@@ -157,7 +158,11 @@ struct Workspace {
     DevBuf mpart;     // per-wave partial sums of the MLP backward
     DevBuf w1part;    // per-chunk partial sums of dW1 (Gaussian part)
     DevBuf mred;      // FP64 group sums of the two-stage column reductions
-    DevBuf live;      // per (view, 32 sorted positions): some dL/ds is nonzero
+    DevBuf live;      // per (view, 32 sorted positions): composited (lazy forward) or some dL/ds nonzero (backward)
+    DevBuf items_live;   // MLP work items of the live blocks (lazy forward)
+    bool lazy = false;   // this render evaluates the pair MLP on live blocks only
+    int n_wchunks = 0;   // weights-pass chunks: one per view with receivers
+    int4 *d_wchunks = nullptr;
     // host staging (pinned) and the events guarding it
     void *h_pinned = nullptr;
     size_t h_pinned_cap = 0;
@@ -251,6 +256,9 @@ unsigned long long *stat_words(Workspace &ws);
 int sort_items_for(uint32_t n);
 size_t w1b_part_bytes(int64_t K);
 size_t mlp_red_bytes();
+hipError_t launch_blend_weights(Workspace &ws, hipStream_t st);
+int *live_count(Workspace &ws);
+size_t live_count_offset(const Workspace &ws);
 
 bool grow(DevBuf &b, size_t bytes);
 void release(DevBuf &b);

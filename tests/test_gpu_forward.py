@@ -166,6 +166,41 @@ def test_mlp_radiance_ranges_and_items(case):
     r.close()
 
 
+@pytest.mark.parametrize("case", ["one_tx", "several_tx", "tiny_w2", "large_activations"])
+def test_lazy_tx_radiance_bit_identical(case):
+    """TX mode without saved state evaluates the pair MLP only on the blocks of
+    32 sorted positions that some pixel composites (marked by a weights-only
+    pass over the view); spectra and power must equal, bit for bit, those of
+    the saved render, which evaluates every visible position, and match the
+    oracle."""
+    from paper_2605_24290_amd import rxgs
+    rx_off = None
+    if case == "several_tx":   # 6 receivers (weights pass), none, 2 and 1 (all blocks live)
+        wl = _wl("c1", K=3000, N=9, Q=4)
+        rx_off = [0, 6, 6, 8, 9]
+    else:
+        wl = _wl("c1", K=3000, N=12)
+    if case == "tiny_w2":
+        wl.mlp[2] = wl.mlp[2] * np.float32(2.0 ** -100)
+        wl.mlp[3] = wl.mlp[3] + np.float32(2.0 ** -101)
+    elif case == "large_activations":
+        wl.mlp[0] = wl.mlp[0] * np.float32(2.0 ** 16)
+    r = renderer_for(wl)
+    C0, P0, S0 = _render(r, wl, "tx", rx_off=rx_off)
+    saved = rxgs.Saved(r)
+    C1, P1, S1 = _render(r, wl, "tx", saved=saved, rx_off=rx_off)
+    assert np.array_equal(C0, C1) and np.array_equal(P0, P1) and np.array_equal(S0, S1)
+    if case == "several_tx":
+        cen = wl.tx.astype(np.float64)
+        rv = np.array([0] * 6 + [2] * 2 + [3], dtype=np.int32)
+        ora = O.render(wl.scene, wl.grid, cen, wl.rx, rv, mlp=wl.mlp)
+    else:
+        ora = oracle_render(wl, "tx")
+    compare_spectra(C0, ora)
+    saved.close()
+    r.close()
+
+
 def test_several_transmitters_uneven_receivers():
     """Three transmitters with 3, 0 and 5 receivers in one launch (TX mode)."""
     wl = _wl("c1", K=2000, N=8, Q=3, grid=GRID_SMALL)
