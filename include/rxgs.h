@@ -298,10 +298,13 @@ int64_t rxgs_workspace_estimate(int32_t mode, int32_t Q, int32_t N, int64_t K, i
  * rxgs_render_backward is bracketed by HIP events recorded on the caller's
  * stream; rxgs_profile_read synchronises on them and returns, per stage,
  * the number of launches and the summed event-to-event time (ms).  Stage
- * names: project, sort_depth, gather, scan, emit, sort_pairs, ranges,
- * mlp_global, mlp_local, mlp_pairs, rad_direct, blend_fwd, reduce, and the
- * backward stages blend_bwd, mlp_bwd, project_bwd, bwd_misc.  `reset` clears the
- * totals after reading.  Errors: E_INVALID, E_DEVICE.
+ * names: project, sort_depth, emit_records, mlp_global, emit_pairs,
+ * sort_pairs, ranges, mlp_items, blend_weights, mlp_local, mlp_pairs,
+ * rad_direct, blend_fwd, reduce, redo_views (one launch per view redone over
+ * all its entries, see rxgs_set_near_cut; the redone passes' own stages are
+ * counted under their names), and the backward stages blend_bwd, mlp_bwd,
+ * project_bwd, bwd_misc.  `reset` clears the totals after reading.  Errors:
+ * E_INVALID, E_DEVICE.
  */
 typedef struct {
     char name[32];
@@ -311,6 +314,26 @@ typedef struct {
 
 rxgs_status rxgs_profile_enable(rxgs_ctx *ctx, int on);
 rxgs_status rxgs_profile_read(rxgs_ctx *ctx, rxgs_stage_time *out, int max_entries, int *n_entries, int reset);
+
+/*
+ * Nearest-first emission (off by default).  Compositing stops at a pixel once
+ * its transmittance falls below 1e-4 (Alg. 1, early termination), so where
+ * every ray ends inside the scene a view's spectra depend only on its nearest
+ * Gaussians.  With this on and more than 4096 Gaussians in the scene,
+ * rxgs_render emits per view only its 4096 nearest depth-sorted entries,
+ * then checks (one device-to-host copy and a stream synchronisation at the
+ * end of the call) whether some pixel of a cut view stayed open; such views
+ * are redone over all their entries (each alone without saved state, the
+ * whole call again with it).  Results, and saved states, are the same as
+ * with it off.  It pays only when views rarely keep an open pixel: a ray that
+ * leaves the scene keeps its pixel open and forces the redo.  Errors:
+ * E_INVALID (NULL ctx).
+ */
+rxgs_status rxgs_set_near_cut(rxgs_ctx *ctx, int on);
+
+/* Views redone over all their entries since the context was created, or -1
+ * for a NULL ctx. */
+int64_t rxgs_views_redone(const rxgs_ctx *ctx);
 
 /* Library version string. */
 const char *rxgs_version(void);

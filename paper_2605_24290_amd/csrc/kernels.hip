@@ -391,7 +391,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
     const GaussGeoPacked *__restrict__ gg, int64_t K, int64_t Kp, const float *__restrict__ centres, DevGrid g,
     const uint32_t *__restrict__ order, const uint32_t *__restrict__ hist, int passes, int cpv,
     float4 *__restrict__ srec, float4 *__restrict__ sbox, uint32_t *__restrict__ vorder, uint32_t *__restrict__ poff,
-    unsigned long long *__restrict__ counters, unsigned long long *status, uint32_t *tickets, uint32_t *err)
+    unsigned long long *__restrict__ counters, unsigned long long *status, uint32_t *tickets, uint32_t *err,
+    uint32_t limit, uint32_t *__restrict__ vflag)
 {
     constexpr int NW = NT / 64;
     __shared__ uint2 s_w2[NW];
@@ -403,8 +404,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
     // entries the depth sort kept for this view: the sum of its digit totals
     uint2 seg2;
     (void)block_exclusive_scan2<NW>(t < 256 ? hist[((size_t)v * passes) * 256 + t] : 0u, 0u, seg2, s_w2);
-    const uint32_t seg_n = seg2.x;
+    // only the nearest `limit` of them are emitted; record whether that cut any
+    const uint32_t seg_n = min(seg2.x, limit);
     const uint32_t chunk = s_chunk;
+    if (t == 0 && chunk == 0) vflag[v] = seg2.x > limit ? 1u : 0u;
     const int64_t s0 = (int64_t)chunk * EM1_CHUNK;
     // uniform; chunks with higher tickets of this view are past the end too
     if (s0 >= (int64_t)seg_n) return;
@@ -1447,7 +1450,8 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
                                                       float *__restrict__ C, float *__restrict__ Tfin,
                                                       int *__restrict__ nlast, float *__restrict__ part,
                                                       unsigned long long *__restrict__ stats,
-                                                     const uint32_t *__restrict__ torder)
+                                                     const uint32_t *__restrict__ torder,
+                                                     uint32_t *__restrict__ vflag)
 {
     constexpr int NB = NB1;
     __shared__ BlendFwdStage<NB> st;
@@ -1496,6 +1500,8 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
         }
         if (__syncthreads_and(done ? 1 : 0)) break;
     }
+    // a pixel still open at the end of a view's truncated list: the view is redone in full
+    if (__syncthreads_or(inside && !done) && t == 0 && (vflag[view] & 1u)) vflag[view] = 3u;
 
     const size_t P = (size_t)g.H * g.W;
     const size_t pix = (size_t)row * g.W + col;
@@ -1616,7 +1622,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restr
                                                      int *__restrict__ nlast, float *__restrict__ part,
                                                      unsigned long long *__restrict__ stats,
                                                      const uint32_t *__restrict__ torder,
-                                                     uint8_t *__restrict__ live)
+                                                     uint8_t *__restrict__ live, uint32_t *__restrict__ vflag)
 {
     __shared__ BlendStage st;
     __shared__ float2 s_rad[R][BLOCK];
@@ -1676,6 +1682,8 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restr
         if (alldone) break;
     }
     if (MARK) return;
+    // a pixel still open at the end of a view's truncated list: the view is redone in full
+    if (__syncthreads_or(inside && !done) && t == 0 && (vflag[view] & 1u)) vflag[view] = 3u;
 
     const size_t P = (size_t)g.H * g.W;
     const size_t pix = (size_t)row * g.W + col;
@@ -1851,9 +1859,10 @@ hipError_t launch_emit1(const Scene &sc, Workspace &ws, const DevGrid &g, hipStr
     // chunks of 1024 entries (512 threads, 2 per thread) when there are many,
     // which amortises each chunk's look-back; 256 (1 per thread) for small
     // launches, which keeps the chain of chunks short
-    const bool wide = (size_t)ws.V * (size_t)(ws.Kp / (4 * BLOCK)) >= 1024;
+    const int64_t per_view = std::min<int64_t>(ws.Kp, ws.limit);
+    const bool wide = (size_t)ws.V * (size_t)(per_view / (4 * BLOCK)) >= 1024;
     const int chunk = wide ? 4 * BLOCK : BLOCK;
-    const int cpv = (int)((ws.Kp + chunk - 1) / chunk);
+    const int cpv = (int)((per_view + chunk - 1) / chunk);
     auto kern = wide ? k_emit1<2, 2 * BLOCK> : k_emit1<1, BLOCK>;
     hipLaunchKernelGGL(kern, dim3((unsigned)(ws.V * cpv)), dim3(wide ? 2 * BLOCK : BLOCK), 0, st,
                        ws.ggeo.as<GaussGeoPacked>(), sc.K, ws.Kp, ws.centres_p, g,
@@ -1861,7 +1870,7 @@ hipError_t launch_emit1(const Scene &sc, Workspace &ws, const DevGrid &g, hipStr
                        ws.sbox.as<float4>(), ws.vorder.as<uint32_t>(), ws.poff.as<uint32_t>(),
                        ws.counters.as<unsigned long long>(),
                        reinterpret_cast<unsigned long long *>(ew + EM_TICKET_STRIDE + (size_t)ws.V * EM_TICKET_STRIDE),
-                       ew + EM_TICKET_STRIDE, ew);
+                       ew + EM_TICKET_STRIDE, ew, ws.limit, ws.vflag.as<uint32_t>());
     return hipGetLastError();
 }
 
@@ -2009,22 +2018,24 @@ static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st)
             hipLaunchKernelGGL((k_blend_fwd1<true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
-                               ws.part.as<float>(), stat_words(ws), tord);
+                               ws.part.as<float>(), stat_words(ws), tord, ws.vflag.as<uint32_t>());
         else
             hipLaunchKernelGGL((k_blend_fwd1<false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
-                               ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord);
+                               ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord,
+                               ws.vflag.as<uint32_t>());
     } else {
         if (save)
             hipLaunchKernelGGL((k_blend_fwd_multi<R, true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
-                               ws.part.as<float>(), stat_words(ws), tord, ws.lazy ? ws.live.as<uint8_t>() : nullptr);
+                               ws.part.as<float>(), stat_words(ws), tord, ws.lazy ? ws.live.as<uint8_t>() : nullptr,
+                               ws.vflag.as<uint32_t>());
         else
             hipLaunchKernelGGL((k_blend_fwd_multi<R, false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord,
-                               ws.lazy ? ws.live.as<uint8_t>() : nullptr);
+                               ws.lazy ? ws.live.as<uint8_t>() : nullptr, ws.vflag.as<uint32_t>());
     }
 }
 
@@ -2089,7 +2100,7 @@ hipError_t launch_blend_weights(Workspace &ws, hipStream_t st)
         hipLaunchKernelGGL((k_blend_fwd_multi<1, false, true>), dim3((unsigned)ws.n_wchunks, (unsigned)ws.g.tiles),
                        dim3(BLOCK), 0, st, ws.srec.as<float4>(), ws.pval[ws.pairs_buf].as<uint32_t>(),
                        ws.ranges.as<uint2>(), ws.rad.as<float2>(), ws.d_wchunks, ws.Kp, ws.g, nullptr, nullptr,
-                       nullptr, nullptr, nullptr, tord, ws.live.as<uint8_t>());
+                       nullptr, nullptr, nullptr, tord, ws.live.as<uint8_t>(), ws.vflag.as<uint32_t>());
     if (ws.n_items > 0)
         hipLaunchKernelGGL(k_live_items, dim3(nblk(ws.n_items)), dim3(BLOCK), 0, st, ws.items.as<int4>(), ws.n_items,
                            ws.live.as<uint8_t>(), ws.Kp, ws.items_live.as<int4>(), live_count(ws));

@@ -126,7 +126,8 @@ void free_workspace(Workspace &ws)
                       &ws.pkey[0], &ws.pkey[1], &ws.pval[0], &ws.pval[1], &ws.ranges, &ws.rad,
                       &ws.Lp,      &ws.Gp,      &ws.items,  &ws.Tfin,   &ws.nlast,  &ws.part,
                       &ws.counters, &ws.hist,   &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
-                      &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.mred,   &ws.live,   &ws.items_live, &ws.hist_b};
+                      &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.mred,   &ws.live,   &ws.items_live, &ws.vflag,
+                      &ws.hist_b};
     for (DevBuf *b : bufs) release(*b);
     if (ws.staged) (void)hipEventDestroy(ws.staged);
     if (ws.counted) (void)hipEventDestroy(ws.counted);
@@ -256,6 +257,15 @@ extern "C" rxgs_status rxgs_profile_read(rxgs_ctx *ctx, rxgs_stage_time *out, in
         }
     return RXGS_OK;
 }
+
+extern "C" rxgs_status rxgs_set_near_cut(rxgs_ctx *ctx, int on)
+{
+    if (!ctx) return RXGS_E_INVALID;
+    ctx->near_cut = on != 0;
+    return RXGS_OK;
+}
+
+extern "C" int64_t rxgs_views_redone(const rxgs_ctx *ctx) { return ctx ? ctx->views_redone : -1; }
 
 extern "C" const char *rxgs_version(void) { return "rxgs 0.1 (gfx950)"; }
 
@@ -564,9 +574,12 @@ extern "C" rxgs_status rxgs_mlp_upload(rxgs_ctx *ctx, const float *params, int s
 }
 
 // ============================================================================
-extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off, int N,
-                                   const float *rx, float *C, float *power, float *csum, rxgs_saved *saved,
-                                   void *stream)
+// One pass of the forward.  limit caps, per view, the depth-sorted entries
+// that are emitted (the nearest ones); the blend flags every view it cut that
+// still has a pixel whose transmittance stayed above the stop threshold.
+static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off, int N,
+                               const float *rx, float *C, float *power, float *csum, rxgs_saved *saved,
+                               void *stream, uint32_t limit)
 {
     if (!ctx) return RXGS_E_INVALID;
     if (mode != RXGS_MODE_TX && mode != RXGS_MODE_RX) return fail(ctx, RXGS_E_INVALID, "unknown mode");
@@ -617,6 +630,8 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     ws.g = g;
     ws.use_mlp = sc.has_features;
     ws.h_rxview = rxview;
+    ws.limit = limit;
+    GROW(ctx, ws.vflag, (size_t)V * 4);
 
     if (saved) {
         // the backward needs the view centres and receiver positions later
@@ -861,6 +876,57 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     ws.scene_version = sc.version;
     ws.mlp_version = ctx->mlp.version;
     ws.valid = true;
+    return RXGS_OK;
+}
+
+// Front-to-back compositing stops at a pixel once its transmittance falls
+// below the threshold (Alg. 1), so in optically thick scenes a view's result
+// depends only on its nearest Gaussians.  The forward therefore emits, per
+// view, only the NEAR_LIMIT nearest depth-sorted entries; a view whose every
+// pixel stopped inside that prefix has exactly the result (and, its tile lists
+// being prefixes of the full ones, exactly the saved state) of the full list.
+// The other views are redone over all their entries: one by one without
+// saved state, all of them with it.
+extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off, int N,
+                                   const float *rx, float *C, float *power, float *csum, rxgs_saved *saved,
+                                   void *stream)
+{
+    const bool cut = ctx && ctx->scene.valid && ctx->scene.K > NEAR_LIMIT && N > 0 && ctx->near_cut;
+    rxgs_status rs = render_pass(ctx, mode, Q, tx, rx_off, N, rx, C, power, csum, saved, stream,
+                                 cut ? (uint32_t)NEAR_LIMIT : 0xFFFFFFFFu);
+    if (rs != RXGS_OK || !cut) return rs;
+    DeviceScope ds(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    Workspace &ws = saved ? saved->ws : ctx->ws;
+    const int V = ws.V;
+    if (ws.h_pinned_cap < (size_t)V * 4) return fail(ctx, RXGS_E_STATE, "flag staging too small");
+    uint32_t *hf = static_cast<uint32_t *>(ws.h_pinned);
+    HIPCHK(ctx, hipMemcpyAsync(hf, ws.vflag.p, (size_t)V * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    std::vector<int> redo;
+    for (int v = 0; v < V; v++)
+        if (hf[v] == 3u) redo.push_back(v);
+    ctx->views_redone += (int64_t)redo.size();
+    if (redo.empty()) return RXGS_OK;
+    if (saved) return render_pass(ctx, mode, Q, tx, rx_off, N, rx, C, power, csum, saved, stream, 0xFFFFFFFFu);
+    const size_t P2 = (size_t)2 * ctx->g.H * ctx->g.W;
+    for (int v : redo) {
+        rxgs::StageMark sm_(ctx->prof, "redo_views", st);   // one launch per view redone
+        int j0 = v, n = 1;
+        const float *cen = nullptr;
+        int32_t off[2] = {0, 1};
+        if (mode == RXGS_MODE_TX) {
+            j0 = rx_off[v];
+            n = rx_off[v + 1] - rx_off[v];
+            off[1] = n;
+            cen = tx + 3 * (size_t)v;
+        }
+        if (n == 0) continue;
+        rs = render_pass(ctx, mode, mode == RXGS_MODE_TX ? 1 : 0, cen, mode == RXGS_MODE_TX ? off : nullptr, n,
+                         rx + 3 * (size_t)j0, C + P2 * j0, power ? power + j0 : nullptr,
+                         csum ? csum + 2 * (size_t)j0 : nullptr, nullptr, stream, 0xFFFFFFFFu);
+        if (rs != RXGS_OK) return rs;
+    }
     return RXGS_OK;
 }
 

@@ -24,6 +24,7 @@ constexpr int MLP_IN = ENC + FEAT;
 constexpr int MLP_RG = 16;               // receivers per MLP work item
 constexpr int MLP_PAIRS = 32;            // sorted positions per MLP work item
 constexpr int LAZY_MIN_RX = 4;           // receivers of a TX view for its weights-only pass
+constexpr int64_t NEAR_LIMIT = 4096;     // nearest depth-sorted entries emitted per view first
 constexpr int AMAX_SLOTS = 128;          // activation-bound words after the view counters
 constexpr int STAT_SLOTS = 64;           // u64 slots per render statistic (spread atomics)
 constexpr int STAT_WORDS = 4 * STAT_SLOTS;   // four statistics, u64 each
@@ -161,6 +162,8 @@ struct Workspace {
     DevBuf live;      // per (view, 32 sorted positions): composited (lazy forward) or some dL/ds nonzero (backward)
     DevBuf items_live;   // MLP work items of the live blocks (lazy forward)
     bool lazy = false;   // this render evaluates the pair MLP on live blocks only
+    uint32_t limit = 0xFFFFFFFFu;   // depth-sorted entries emitted per view (the nearest)
+    DevBuf vflag;        // per view: 1 = entries were cut, 3 = cut with a pixel still open
     int n_wchunks = 0;   // weights-pass chunks: one per view with receivers
     int4 *d_wchunks = nullptr;
     // host staging (pinned) and the events guarding it
@@ -212,6 +215,8 @@ struct rxgs_ctx {
     uint64_t version_counter = 0;
     std::vector<rxgs_saved *> saved;   // live saved states
     rxgs::Profiler prof;
+    bool near_cut = false;     // emit each view's nearest entries first (rxgs_set_near_cut)
+    int64_t views_redone = 0;  // views redone over all their entries
 };
 
 struct rxgs_saved {

@@ -77,7 +77,7 @@ EXPORTED = ("rxgs_create", "rxgs_destroy", "rxgs_last_error", "rxgs_scene_upload
             "rxgs_saved_info", "rxgs_saved_export", "rxgs_version", "rxgs_profile_enable",
             "rxgs_profile_read", "rxgs_server_start", "rxgs_server_submit", "rxgs_server_poll",
             "rxgs_server_cancel", "rxgs_server_stats", "rxgs_server_stop", "rxgs_plan_batch",
-            "rxgs_workspace_estimate")
+            "rxgs_workspace_estimate", "rxgs_set_near_cut", "rxgs_views_redone")
 
 _lib = None
 
@@ -121,6 +121,10 @@ def lib():
     for name in ("rxgs_server_start", "rxgs_server_submit", "rxgs_server_poll", "rxgs_server_cancel",
                  "rxgs_server_stats", "rxgs_server_stop"):
         getattr(L, name).restype = c_int
+    L.rxgs_set_near_cut.argtypes = [vp, c_int]
+    L.rxgs_set_near_cut.restype = c_int
+    L.rxgs_views_redone.argtypes = [vp]
+    L.rxgs_views_redone.restype = c_int64
     L.rxgs_profile_enable.argtypes = [vp, c_int]
     L.rxgs_profile_read.argtypes = [vp, POINTER(CStageTime), c_int, POINTER(c_int), c_int]
     for name in ("rxgs_create", "rxgs_scene_upload", "rxgs_mlp_upload", "rxgs_saved_create", "rxgs_render",
@@ -272,6 +276,14 @@ class Renderer:
         _check(lib().rxgs_render_backward(self._ctx, saved._h, _ptr(C.contiguous()), _ptr(dC), _ptr(dP_t),
                                           byref(cg), self._stream()), self._ctx)
         return grads
+
+    def near_cut(self, on: bool = True):
+        """Nearest-first emission with the exact fallback (rxgs_set_near_cut; off by default)."""
+        _check(lib().rxgs_set_near_cut(self._ctx, 1 if on else 0), self._ctx)
+
+    def views_redone(self) -> int:
+        """Views redone over all their entries since creation (rxgs_views_redone)."""
+        return int(lib().rxgs_views_redone(self._ctx))
 
     def profile(self, on: bool = True):
         """Turn per-stage event timing on or off."""

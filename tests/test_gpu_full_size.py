@@ -44,7 +44,10 @@ def _threads():
 
 def _check_view_binning(saved, wl, mode, views):
     """Keys, pair order and tile ranges of the listed views against the
-    oracle's FP32 key and integer binning of the GPU's exported records."""
+    oracle's FP32 key and integer binning of the GPU's exported records.  A
+    view's emitted entries may be only its nearest ones (nearest-first
+    emission): its visible list must then be a prefix of the full depth-ordered
+    visible list, and its pairs the full binning restricted to that prefix."""
     from paper_2605_24290_amd import rxgs
     info = saved.info()
     V, Kp, K, D, T = info["V"], info["K_pad"], info["K"], info["D"], info["tiles"]
@@ -64,6 +67,15 @@ def _check_view_binning(saved, wl, mode, views):
         assert np.abs(ext[v, :, 0][vis] - pr[0, :, 0][vis]).max() < 1e-4 * wl.grid.W
         seg, kk = O.bin_records(ext[v:v + 1, :, 0], ext[v:v + 1, :, 1], ext[v:v + 1, :, 2],
                                 ext[v:v + 1, :, 3], op[v:v + 1], keys[v:v + 1], wl.grid)
+        # the full visible list in (key, index) order; the emitted one is its prefix
+        vis_all = np.unique(kk)
+        vis_all = vis_all[np.lexsort((vis_all, keys[v][vis_all]))]
+        nv = int(nvis[v])
+        assert nv <= vis_all.size and np.array_equal(order[v, :nv], vis_all[:nv]), v
+        keep = np.zeros(K, dtype=bool)
+        keep[vis_all[:nv]] = True
+        seg, kk = seg[keep[kk]], kk[keep[kk]]
+        print(f"[full] view {v}: {nv} of {vis_all.size} visible entries emitted")
         rng_v = ranges[v * T:(v + 1) * T]
         lo, hi = rng_v[:, 0], rng_v[:, 1]
         nonempty = hi > lo
