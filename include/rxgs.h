@@ -153,6 +153,23 @@ rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *tx, const i
                         int N, const float *rx, float *C, float *power, float *csum,
                         rxgs_saved *saved, void *stream);
 
+/*
+ * Coverage-map render: the receivers of rxgs_render (same arguments, no saved
+ * state) streamed through consecutive chunks, each one rxgs_render call, the
+ * largest whose workspace estimate (rxgs_workspace_estimate) fits
+ * budget_bytes; budget_bytes <= 0 takes half the device memory free at the
+ * call.  A chunk may split one transmitter's receivers (its view is then
+ * projected and sorted once per chunk).  Every receiver's outputs are those
+ * of rxgs_render up to the summation order of its blend workgroup (a chunk
+ * of one receiver per view uses the one-receiver kernel).  The library's
+ * internal workspace keeps the largest chunk's buffers until rxgs_destroy.
+ * Writes the number of chunks to *n_chunks when it is not NULL.  Errors:
+ * those of rxgs_render, and E_OOM when one receiver does not fit the budget.
+ */
+rxgs_status rxgs_render_chunked(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off,
+                                int N, const float *rx, float *C, float *power, float *csum,
+                                int64_t budget_bytes, int32_t *n_chunks, void *stream);
+
 /* Gradient outputs of rxgs_render_backward (device pointers, caller-owned,
  * overwritten).  Any may be NULL to skip it; radiance is used for direct
  * radiance scenes, features and mlp for MLP scenes. */

@@ -931,6 +931,72 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
 }
 
 // ============================================================================
+extern "C" rxgs_status rxgs_render_chunked(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off,
+                                           int N, const float *rx, float *C, float *power, float *csum,
+                                           int64_t budget_bytes, int32_t *n_chunks, void *stream)
+{
+    if (!ctx) return RXGS_E_INVALID;
+    if (mode != RXGS_MODE_TX && mode != RXGS_MODE_RX) return fail(ctx, RXGS_E_INVALID, "unknown mode");
+    if (N < 0) return fail(ctx, RXGS_E_INVALID, "N < 0");
+    if (n_chunks) *n_chunks = 0;
+    if (N == 0) return RXGS_OK;
+    if (!rx || !C) return fail(ctx, RXGS_E_INVALID, "rx or C is NULL");
+    if (!ctx->scene.valid) return fail(ctx, RXGS_E_STATE, "no scene uploaded");
+    std::vector<int> owner(N, 0);   // transmitter of each receiver (TX mode)
+    if (mode == RXGS_MODE_TX) {
+        if (Q < 1 || !tx || !rx_off) return fail(ctx, RXGS_E_INVALID, "TX mode needs Q >= 1, tx and rx_off");
+        if (rx_off[0] != 0 || rx_off[Q] != N) return fail(ctx, RXGS_E_INVALID, "rx_off must run from 0 to N");
+        for (int q = 0; q < Q; q++) {
+            if (rx_off[q + 1] < rx_off[q]) return fail(ctx, RXGS_E_INVALID, "rx_off must be non-decreasing");
+            for (int j = rx_off[q]; j < rx_off[q + 1]; j++) owner[j] = q;
+        }
+    }
+    if (budget_bytes <= 0) {
+        DeviceScope ds(ctx->device);
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return hip_fail(ctx, hipGetLastError(), "hipMemGetInfo");
+        budget_bytes = (int64_t)(free_b / 2);
+    }
+    const int64_t K = ctx->scene.K;
+    const int H = ctx->g.H, W = ctx->g.W;
+    const size_t P2 = (size_t)2 * H * W;
+    int32_t chunks = 0;
+    for (int a = 0; a < N;) {
+        // transmitters the chunk [a, b) spans
+        auto views_of = [&](int b) { return mode == RXGS_MODE_TX ? owner[b - 1] - owner[a] + 1 : 0; };
+        auto fits = [&](int b) {
+            return rxgs_workspace_estimate(mode, views_of(b), b - a, K, H, W) <= budget_bytes;
+        };
+        if (!fits(a + 1)) return fail(ctx, RXGS_E_OOM, "one receiver's workspace exceeds the budget");
+        int lo = a + 1, hi = N;   // largest b in [lo, hi] that fits (the estimate grows with b)
+        while (lo < hi) {
+            const int mid = lo + (hi - lo + 1) / 2;
+            if (fits(mid)) lo = mid;
+            else hi = mid - 1;
+        }
+        const int b = lo;
+        rxgs_status rs;
+        if (mode == RXGS_MODE_TX) {
+            const int q0 = owner[a], q1 = owner[b - 1];
+            std::vector<int32_t> off(q1 - q0 + 2);
+            off[0] = 0;
+            for (int q = q0; q <= q1; q++) off[q - q0 + 1] = std::min(rx_off[q + 1], b) - a;
+            rs = rxgs_render(ctx, mode, q1 - q0 + 1, tx + 3 * (size_t)q0, off.data(), b - a, rx + 3 * (size_t)a,
+                             C + P2 * a, power ? power + a : nullptr, csum ? csum + 2 * (size_t)a : nullptr,
+                             nullptr, stream);
+        } else {
+            rs = rxgs_render(ctx, mode, 0, nullptr, nullptr, b - a, rx + 3 * (size_t)a, C + P2 * a,
+                             power ? power + a : nullptr, csum ? csum + 2 * (size_t)a : nullptr, nullptr, stream);
+        }
+        if (rs != RXGS_OK) return rs;
+        chunks++;
+        a = b;
+    }
+    if (n_chunks) *n_chunks = chunks;
+    return RXGS_OK;
+}
+
+// ============================================================================
 extern "C" rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *saved, const float *C, const float *dC,
                                             const float *dP, const rxgs_grads *grads, void *stream)
 {

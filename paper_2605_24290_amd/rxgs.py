@@ -77,7 +77,7 @@ EXPORTED = ("rxgs_create", "rxgs_destroy", "rxgs_last_error", "rxgs_scene_upload
             "rxgs_saved_info", "rxgs_saved_export", "rxgs_version", "rxgs_profile_enable",
             "rxgs_profile_read", "rxgs_server_start", "rxgs_server_submit", "rxgs_server_poll",
             "rxgs_server_cancel", "rxgs_server_stats", "rxgs_server_stop", "rxgs_plan_batch",
-            "rxgs_workspace_estimate", "rxgs_set_near_cut", "rxgs_views_redone")
+            "rxgs_workspace_estimate", "rxgs_set_near_cut", "rxgs_views_redone", "rxgs_render_chunked")
 
 _lib = None
 
@@ -121,6 +121,9 @@ def lib():
     for name in ("rxgs_server_start", "rxgs_server_submit", "rxgs_server_poll", "rxgs_server_cancel",
                  "rxgs_server_stats", "rxgs_server_stop"):
         getattr(L, name).restype = c_int
+    L.rxgs_render_chunked.argtypes = [vp, c_int, c_int, vp, POINTER(c_int32), c_int, vp, vp, vp, vp, c_int64,
+                                      POINTER(c_int32), vp]
+    L.rxgs_render_chunked.restype = c_int
     L.rxgs_set_near_cut.argtypes = [vp, c_int]
     L.rxgs_set_near_cut.restype = c_int
     L.rxgs_views_redone.argtypes = [vp]
@@ -256,6 +259,35 @@ class Renderer:
         _check(lib().rxgs_render(self._ctx, m, Q, _ptr(tx_t), off_arr, N, _ptr(rx_t), _ptr(C), _ptr(P), _ptr(S),
                                  None if saved is None else saved._h, self._stream()), self._ctx)
         return C, P, S
+
+    def render_chunked(self, rx, tx=None, rx_off=None, mode: str = "tx", budget_bytes: int = 0, out=None):
+        """Coverage map: the receivers streamed through chunks whose workspace fits
+        budget_bytes (0: half the free device memory).  Returns (C, power, chunks)."""
+        torch = _torch()
+        rx_t = _dev_f32(rx, self.device).reshape(-1, 3)
+        N = int(rx_t.shape[0])
+        if mode not in ("tx", "rx"):
+            raise ValueError("mode must be 'tx' or 'rx'")
+        m = MODE_TX if mode == "tx" else MODE_RX
+        tx_t, Q, off_arr = None, 0, None
+        if m == MODE_TX:
+            tx_t = _dev_f32(tx, self.device).reshape(-1, 3)
+            Q = int(tx_t.shape[0])
+            if rx_off is None:
+                if Q != 1:
+                    raise ValueError("rx_off is needed with several transmitters")
+                rx_off = [0, N]
+            off_arr = (c_int32 * (Q + 1))(*[int(x) for x in rx_off])
+        H, W = self.grid.H, self.grid.W
+        if out is None:
+            C = torch.empty((N, 2, H, W), device=self.device, dtype=torch.float32)
+            P = torch.empty((N,), device=self.device, dtype=torch.float32)
+        else:
+            C, P = out
+        nch = c_int32(0)
+        _check(lib().rxgs_render_chunked(self._ctx, m, Q, _ptr(tx_t), off_arr, N, _ptr(rx_t), _ptr(C), _ptr(P), None,
+                                         int(budget_bytes), byref(nch), self._stream()), self._ctx)
+        return C, P, int(nch.value)
 
     def backward(self, saved: Saved, C, dC, dP=None, grads: dict | None = None) -> dict:
         """Gradients w.r.t. the scene (and MLP) given dL/dC and dL/dpower."""
