@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the oracle sample")
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-scale", action="store_true", help="skip the 1M-Gaussian scale workload")
     ap.add_argument("--serve-queries", type=int, default=400)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain copy of this many MiB (counter calibration for profiled runs)")
@@ -183,6 +184,62 @@ def train_step_part(args):
                         "backward to all parameters (no optimizer update)", **out}
 
 
+def scale_part(args):
+    """The 1M-Gaussian scale workload: the training step over 512 RX views, and
+    a 4,096-receiver coverage map of one transmitter streamed in receiver
+    chunks sized to half the free HBM."""
+    import torch
+    from paper_2605_24290_amd import rxgs
+    from paper_2605_24290_amd import scenes as S
+
+    dev = torch.device("cuda", 0)
+    out = {}
+    wl = S.make_workload("c4")
+    sc = wl.scene
+    r = rxgs.Renderer(wl.grid)
+    r.upload_scene(sc.means, sc.log_scales, sc.quats, sc.logits, features=sc.features)
+    r.upload_mlp(S.flat_mlp(wl.mlp))
+    rx = torch.as_tensor(wl.rx, device=dev)
+    Y = torch.as_tensor(wl.targets, device=dev)
+    saved = rxgs.Saved(r)
+    grads = None
+
+    def step():
+        nonlocal grads
+        C, P, _ = r.render(rx, mode="rx", saved=saved)
+        grads = r.backward(saved, C, 2.0 * (C - Y), None, grads)
+    ms = timed(step, 2, 1)
+    info = saved.info()
+    out["train_step_rx"] = {"ms_per_step": ms, "rx_views_per_s": wl.rx.shape[0] * 1000.0 / ms,
+                            "tile_pairs": int(info["D"]), "visible": int(info["n_visible"])}
+    saved.close()
+    r.close()
+    del Y, rx, grads
+    torch.cuda.empty_cache()
+
+    wl = S.make_workload("c4", N=4096, targets=False)
+    sc = wl.scene
+    r = rxgs.Renderer(wl.grid)
+    r.upload_scene(sc.means, sc.log_scales, sc.quats, sc.logits, features=sc.features)
+    r.upload_mlp(S.flat_mlp(wl.mlp))
+    rx = torch.as_tensor(wl.rx, device=dev)
+    tx = torch.as_tensor(wl.tx, device=dev)
+    N = wl.rx.shape[0]
+    C = torch.empty((N, 2, wl.grid.H, wl.grid.W), device=dev)
+    P = torch.empty((N,), device=dev)
+    nch = [0]
+
+    def cover():
+        nch[0] = r.render_chunked(rx, tx=tx, mode="tx", out=(C, P))[2]
+    ms = timed(cover, 3, 1)
+    out["coverage_tx"] = {"ms_per_map": ms, "rx_views_per_s": N * 1000.0 / ms, "chunks": nch[0]}
+    r.close()
+    del C, P
+    torch.cuda.empty_cache()
+    return {"workload": f"c4: {sc.K} Gaussians in a 40x40x4 m box, 90x360, MLP; training step over 512 RX views "
+                        f"(L2 loss, all gradients); coverage map of {N} receivers of one transmitter", **out}
+
+
 def serving_part(args):
     """Continuous batching on the 200k-Gaussian scene: saturation throughput of
     a burst, then open-loop Poisson arrivals at 0.3 / 0.6 / 0.9 of it."""
@@ -211,16 +268,19 @@ def serving_part(args):
             "rates_x_saturation": rates, "server_stats": st}
 
 
+# the sources the forward kernels are compiled from (host-only files excluded)
+KERNEL_SOURCES = ("device_common.h", "kernels.hip", "rxgs_internal.h")
+
+
 def source_digest() -> str:
-    """SHA-256 of the HIP sources, to tell whether stored counter readings
-    still describe the kernels that were just timed."""
-    import glob
+    """SHA-256 of the forward kernels' sources, to tell whether stored counter
+    readings still describe the kernels that were just timed."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2605_24290_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
-        with open(f, "rb") as fh:
-            h.update(os.path.basename(f).encode())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
             h.update(fh.read())
     return h.hexdigest()
 
@@ -398,6 +458,8 @@ def main():
     }
     if not args.no_train:
         out["train_step"] = train_step_part(args)
+    if not args.no_scale:
+        out["scale"] = scale_part(args)
     if not args.no_serve:
         out["serving"] = serving_part(args)
     if not args.no_cpu_baseline:
