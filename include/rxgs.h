@@ -352,6 +352,18 @@ rxgs_status rxgs_set_near_cut(rxgs_ctx *ctx, int on);
  * for a NULL ctx. */
 int64_t rxgs_views_redone(const rxgs_ctx *ctx);
 
+/*
+ * Per-view flags of the last rxgs_render without saved state (device-to-host
+ * copy, synchronous): bit 0 the view's entries were cut (nearest-first
+ * emission), bit 1 a pixel stayed open after the cut, bit 2 the blend
+ * composited a sorted position past the radiance prefix (TX mode: the pair
+ * MLP first runs on each view's 4096 nearest sorted positions; such a view
+ * gets the rest of its radiance and is blended again on the device).  Copies
+ * up to max_views words to out and writes the view count to *n_views when
+ * not NULL.  Errors: E_INVALID, E_DEVICE.
+ */
+rxgs_status rxgs_view_flags(rxgs_ctx *ctx, uint32_t *out, int32_t max_views, int32_t *n_views);
+
 /* Library version string. */
 const char *rxgs_version(void);
 

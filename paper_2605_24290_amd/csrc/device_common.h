@@ -76,6 +76,7 @@ struct BlendStage {
     int len[4];
     int wrap[4];                 // per wave: its list holds an entry that needs azimuth wrapping
     int wcnt[4][4];
+    int ncnt[4][4];              // per source wave and sub-tile: entries below a position prefix
 };
 
 // Conservative sub-tile mask of one record: bit w set when the box around the
@@ -106,7 +107,7 @@ __device__ __forceinline__ int subtile_mask(const float4 &r0, const float4 &r1, 
 // Stage the batch entry of this thread (if `has`) and build the per-wave lists.
 // All threads of the block must call it.
 __device__ __forceinline__ void stage_batch(BlendStage &st, const float4 *__restrict__ srec, uint32_t p, bool has,
-                                            int tx, int ty, const DevGrid &g)
+                                            int tx, int ty, const DevGrid &g, bool nearp = true)
 {
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     int m = 0;
@@ -125,13 +126,19 @@ __device__ __forceinline__ void stage_batch(BlendStage &st, const float4 *__rest
         st.wide[t] = wide;
         m = subtile_mask(r0, r1, wide, tx, ty);
     }
-    uint64_t bal[4];
+    uint64_t bal[4], nbal[4];
 #pragma unroll
-    for (int b = 0; b < 4; b++) bal[b] = __ballot((m >> b) & 1);
+    for (int b = 0; b < 4; b++) {
+        bal[b] = __ballot((m >> b) & 1);
+        nbal[b] = __ballot(((m >> b) & 1) && nearp);
+    }
     const uint64_t wide_bal = __ballot(has && st.wide[t]);
     if (lane == 0)
 #pragma unroll
-        for (int b = 0; b < 4; b++) st.wcnt[w][b] = (int)__popcll(bal[b]);
+        for (int b = 0; b < 4; b++) {
+            st.wcnt[w][b] = (int)__popcll(bal[b]);
+            st.ncnt[w][b] = (int)__popcll(nbal[b]);
+        }
     if (t < 4) st.wrap[t] = 0;
     __syncthreads();
     // a wide entry reaches every sub-tile (its mask is 0xF)

@@ -1276,6 +1276,7 @@ template <int NB> struct BlendFwdStage {
     unsigned short list[4][NB];      // per wave: batch index of each entry
     int len[4];
     int wcnt[4][4];
+    int ncnt[4][4];                  // per source wave and sub-tile: entries below the position prefix
     int wide[4];
 };
 
@@ -1315,7 +1316,7 @@ __device__ __forceinline__ int subtile_mask_fast(const float4 &r0, const float4 
 // zero-weight records to a multiple of 4).
 template <int NB>
 __device__ __forceinline__ void stage_fwd(BlendFwdStage<NB> &st, const float4 *__restrict__ srec, uint32_t p, bool has,
-                                          float2 rv, int tx, int ty, const DevGrid &g, float invW)
+                                          float2 rv, int tx, int ty, const DevGrid &g, float invW, bool nearp)
 {
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     int m = 0, wide = 0;
@@ -1336,13 +1337,19 @@ __device__ __forceinline__ void stage_fwd(BlendFwdStage<NB> &st, const float4 *_
         st.r1[t] = r1;
         st.rad[t] = rv;
     }
-    uint64_t bal[4];
+    uint64_t bal[4], nbal[4];
 #pragma unroll
-    for (int b = 0; b < 4; b++) bal[b] = __ballot((m >> b) & 1);
+    for (int b = 0; b < 4; b++) {
+        bal[b] = __ballot((m >> b) & 1);
+        nbal[b] = __ballot(((m >> b) & 1) && nearp);
+    }
     const uint64_t wide_bal = __ballot(wide);
     if (lane == 0) {
 #pragma unroll
-        for (int b = 0; b < 4; b++) st.wcnt[w][b] = (int)__popcll(bal[b]);
+        for (int b = 0; b < 4; b++) {
+            st.wcnt[w][b] = (int)__popcll(bal[b]);
+            st.ncnt[w][b] = (int)__popcll(nbal[b]);
+        }
         st.wide[w] = wide_bal ? 1 : 0;
     }
     __syncthreads();
@@ -1396,14 +1403,16 @@ __device__ __forceinline__ void stage_fwd(BlendFwdStage<NB> &st, const float4 *_
 // alpha threshold, or met after the lane terminated, gets weight 0, which
 // leaves T and the sums unchanged.  WRAP: the list is in the wrapped form.
 // SAVE: track the stop index and the composited count (saved states and
-// statistics only).
-template <bool SAVE, bool WRAP, int NB>
+// statistics only).  DETECT: set *far_hit when the lane composites an entry
+// at list index i_far or later.
+template <bool SAVE, bool WRAP, bool DETECT = false, int NB>
 __device__ __forceinline__ void blend_walk1(const BlendFwdStage<NB> &st, int wv, int n, int lbase, float X, float Y,
                                             float XX, float XY, float YY, float Wf, float halfW, float &T,
                                             float2 &acc, int &last, uint32_t &ncomp, uint32_t &neval,
-                                            uint32_t &nslot, bool &done)
+                                            uint32_t &nslot, bool &done, int i_begin = 0, int i_far = 0,
+                                            bool *far_hit = nullptr)
 {
-    for (int i0 = 0; i0 < n; i0 += 4) {
+    for (int i0 = i_begin; i0 < n; i0 += 4) {
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             const int i = i0 + k;
@@ -1435,6 +1444,7 @@ __device__ __forceinline__ void blend_walk1(const BlendFwdStage<NB> &st, int wv,
                 last = inc ? lbase + (int)st.list[wv][i] : last;
                 ncomp += inc ? 1u : 0u;
             }
+            if (DETECT) *far_hit = *far_hit || (inc && i >= i_far);
             done = done || T < T_EPS;
         }
         if (__all(done)) break;
@@ -1451,7 +1461,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
                                                       int *__restrict__ nlast, float *__restrict__ part,
                                                       unsigned long long *__restrict__ stats,
                                                      const uint32_t *__restrict__ torder,
-                                                     uint32_t *__restrict__ vflag)
+                                                     uint32_t *__restrict__ vflag, uint32_t mpos, int redo)
 {
     constexpr int NB = NB1;
     __shared__ BlendFwdStage<NB> st;
@@ -1459,6 +1469,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
 
     // grid: (chunk, rank of the tile in its view's longest-first order)
     const int4 ch = chunks[blockIdx.x];
+    if (redo && !(vflag[ch.x] & 4u)) return;   // uniform over the block, before any barrier
     const int tile = torder ? (int)torder[(size_t)ch.x * g.tiles + blockIdx.y] : (int)blockIdx.y;
     const int view = ch.x, j0 = ch.y, nrx = ch.z, tslot = ch.w;
     const int ty = tile / g.tiles_x, tx = tile - ty * g.tiles_x;
@@ -1475,33 +1486,50 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
     float2 acc = make_float2(0.f, 0.f);
     int last = 0;
     uint32_t ncomp = 0, neval = 0, nslot = 0;   // composited / evaluated while active / walked (SAVE)
-    bool done = !inside;
+    bool done = !inside, far_hit = false;
 
     for (uint32_t base = rg.x; base < rg.y; base += NB) {
         const uint32_t cnt = min((uint32_t)NB, rg.y - base);
         __syncthreads();
         uint32_t p = 0;
         float2 rv = make_float2(0.f, 0.f);
+        bool nearp = true;
         if ((uint32_t)t < cnt) {
             p = min(pval[base + t], (uint32_t)(view_end - 1));
             const int64_t s = max((int64_t)p - (int64_t)view * Kp, (int64_t)0);
-            rv = rad[(size_t)j0 * Kp + s];
+            nearp = s < (int64_t)mpos;
+            if (nearp) rv = rad[(size_t)j0 * Kp + s];
         }
-        stage_fwd<NB>(st, srec, p, (uint32_t)t < cnt, rv, tx, ty, g, invW);
+        stage_fwd<NB>(st, srec, p, (uint32_t)t < cnt, rv, tx, ty, g, invW, nearp);
         if (__any(!done)) {
             const int n = __builtin_amdgcn_readfirstlane(st.len[wv]);
             const int lbase = (int)(base - rg.x) + 1;
-            if (st.wide[0] | st.wide[1] | st.wide[2] | st.wide[3])
-                blend_walk1<SAVE, true>(st, wv, n, lbase, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
-                                        nslot, done);
+            // list entries below the position prefix come first (the tile list is in depth order)
+            const int i_far = __builtin_amdgcn_readfirstlane(st.ncnt[0][wv] + st.ncnt[1][wv] + st.ncnt[2][wv] +
+                                                             st.ncnt[3][wv]);
+            const int i4 = i_far & ~3;
+            const bool wide = st.wide[0] | st.wide[1] | st.wide[2] | st.wide[3];
+            if (wide)
+                blend_walk1<SAVE, true>(st, wv, min(n, i4), lbase, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp,
+                                        neval, nslot, done);
             else
-                blend_walk1<SAVE, false>(st, wv, n, lbase, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
-                                         nslot, done);
+                blend_walk1<SAVE, false>(st, wv, min(n, i4), lbase, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp,
+                                         neval, nslot, done);
+            if (i4 < n && __any(!done)) {
+                if (wide)
+                    blend_walk1<SAVE, true, true>(st, wv, n, lbase, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp,
+                                                  neval, nslot, done, i4, i_far, &far_hit);
+                else
+                    blend_walk1<SAVE, false, true>(st, wv, n, lbase, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp,
+                                                   neval, nslot, done, i4, i_far, &far_hit);
+            }
         }
         if (__syncthreads_and(done ? 1 : 0)) break;
     }
     // a pixel still open at the end of a view's truncated list: the view is redone in full
-    if (__syncthreads_or(inside && !done) && t == 0 && (vflag[view] & 1u)) vflag[view] = 3u;
+    if (__syncthreads_or(inside && !done) && t == 0 && (vflag[view] & 1u)) atomicOr(vflag + view, 2u);
+    // a composited entry past the position prefix (zero radiance here): the view is redone
+    if (__syncthreads_or(far_hit) && t == 0) atomicOr(vflag + view, 4u);
 
     const size_t P = (size_t)g.H * g.W;
     const size_t pix = (size_t)row * g.W + col;
@@ -1565,13 +1593,14 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
 // wrapped into [-W/2, W/2) (selects).  SAVE: track the stop index and the
 // composited count (saved states and statistics only).  MARK: flag in s_mark
 // every entry that some lane composites (the weights-only pass).
-template <int R, bool SAVE, bool WRAP, bool MARK = false>
+template <int R, bool SAVE, bool WRAP, bool MARK = false, bool DETECT = false>
 __device__ __forceinline__ void blend_walk_multi(const BlendStage &st, const float2 (*s_rad)[BLOCK], int wv, int n,
                                            int lbase, float colf, float rowf, float Wf, float halfW, float &T,
                                            float2 (&acc)[R], int &last, uint32_t &ncomp, uint32_t &neval,
-                                           uint32_t &nslot, bool &done, unsigned char *s_mark = nullptr)
+                                           uint32_t &nslot, bool &done, unsigned char *s_mark = nullptr,
+                                           int i_begin = 0, bool *far_hit = nullptr)
 {
-    for (int i = 0; i < n; i++) {
+    for (int i = i_begin; i < n; i++) {
         if (SAVE) {
             neval += done ? 0u : 1u;
             nslot++;
@@ -1601,6 +1630,7 @@ __device__ __forceinline__ void blend_walk_multi(const BlendStage &st, const flo
             ncomp += inc ? 1u : 0u;
         }
         if (MARK && inc) s_mark[e] = 1;
+        if (DETECT) *far_hit = *far_hit || inc;
         done = done || T < T_EPS;
         if ((i & 3) == 3 && __all(done)) break;
     }
@@ -1622,12 +1652,14 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restr
                                                      int *__restrict__ nlast, float *__restrict__ part,
                                                      unsigned long long *__restrict__ stats,
                                                      const uint32_t *__restrict__ torder,
-                                                     uint8_t *__restrict__ live, uint32_t *__restrict__ vflag)
+                                                     uint8_t *__restrict__ live, uint32_t *__restrict__ vflag,
+                                                     uint32_t mpos, int redo)
 {
     __shared__ BlendStage st;
     __shared__ float2 s_rad[R][BLOCK];
     __shared__ float s_red[4][R][3];
     __shared__ unsigned char s_mark[MARK ? BLOCK : 1];
+    if (redo && !(vflag[chunks[blockIdx.x].x] & 4u)) return;   // uniform, before any barrier
     if (MARK) s_mark[threadIdx.x] = 0;
 
     // grid: (chunk, rank of the tile in its view's longest-first order)
@@ -1649,30 +1681,46 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restr
     for (int r = 0; r < R; r++) acc[r] = make_float2(0.f, 0.f);
     int last = 0;
     uint32_t ncomp = 0, neval = 0, nslot = 0;   // composited / evaluated while active / walked (SAVE)
-    bool done = !inside;
+    bool done = !inside, far_hit = false;
 
     for (uint32_t base = rg.x; base < rg.y; base += BLOCK) {
         const uint32_t cnt = min((uint32_t)BLOCK, rg.y - base);
         __syncthreads();
         uint32_t p = 0;
+        bool nearp = true;
         if ((uint32_t)t < cnt) {
             p = min(pval[base + t], (uint32_t)(view_end - 1));
             const int64_t s = max((int64_t)p - (int64_t)view * Kp, (int64_t)0);
-            const bool used = MARK || live == nullptr || live[p / MLP_PAIRS] != 0;
+            nearp = s < (int64_t)mpos;
+            const bool used = MARK || ((live == nullptr || live[p / MLP_PAIRS] != 0) && nearp);
 #pragma unroll
             for (int r = 0; r < R; r++)
                 s_rad[r][t] = (r < nrx && used) ? rad[(size_t)(j0 + r) * Kp + s] : make_float2(0.f, 0.f);
         }
-        stage_batch(st, srec, p, (uint32_t)t < cnt, tx, ty, g);
+        stage_batch(st, srec, p, (uint32_t)t < cnt, tx, ty, g, nearp);
         if (__any(!done)) {
             const int n = __builtin_amdgcn_readfirstlane(st.len[wv]);
             const int lbase = (int)(base - rg.x) + 1;
-            if (__builtin_amdgcn_readfirstlane(st.wrap[wv]))
-                blend_walk_multi<R, SAVE, true, MARK>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T, acc, last,
-                                                      ncomp, neval, nslot, done, s_mark);
+            // list entries below the position prefix come first (the tile list is in depth order)
+            const int i_far = __builtin_amdgcn_readfirstlane(st.ncnt[0][wv] + st.ncnt[1][wv] + st.ncnt[2][wv] +
+                                                             st.ncnt[3][wv]);
+            const bool wrap = __builtin_amdgcn_readfirstlane(st.wrap[wv]) != 0;
+            if (wrap)
+                blend_walk_multi<R, SAVE, true, MARK>(st, s_rad, wv, i_far, lbase, colf, rowf, Wf, halfW, T, acc,
+                                                      last, ncomp, neval, nslot, done, s_mark);
             else
-                blend_walk_multi<R, SAVE, false, MARK>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T, acc, last,
-                                                       ncomp, neval, nslot, done, s_mark);
+                blend_walk_multi<R, SAVE, false, MARK>(st, s_rad, wv, i_far, lbase, colf, rowf, Wf, halfW, T, acc,
+                                                       last, ncomp, neval, nslot, done, s_mark);
+            if (i_far < n && __any(!done)) {
+                if (wrap)
+                    blend_walk_multi<R, SAVE, true, MARK, true>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T, acc,
+                                                                last, ncomp, neval, nslot, done, s_mark, i_far,
+                                                                &far_hit);
+                else
+                    blend_walk_multi<R, SAVE, false, MARK, true>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T,
+                                                                 acc, last, ncomp, neval, nslot, done, s_mark, i_far,
+                                                                 &far_hit);
+            }
         }
         const int alldone = __syncthreads_and(done ? 1 : 0);
         if (MARK) {
@@ -1683,7 +1731,9 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restr
     }
     if (MARK) return;
     // a pixel still open at the end of a view's truncated list: the view is redone in full
-    if (__syncthreads_or(inside && !done) && t == 0 && (vflag[view] & 1u)) vflag[view] = 3u;
+    if (__syncthreads_or(inside && !done) && t == 0 && (vflag[view] & 1u)) atomicOr(vflag + view, 2u);
+    // a composited entry past the position prefix (zero radiance here): the view is redone
+    if (__syncthreads_or(far_hit) && t == 0) atomicOr(vflag + view, 4u);
 
     const size_t P = (size_t)g.H * g.W;
     const size_t pix = (size_t)row * g.W + col;
@@ -1973,18 +2023,20 @@ bool mlp_fused_ok(const Scene &sc, const Mlp &m)
     return !m.fp32 && m.w1_ok && sc.fmax < 32768.f;
 }
 
-hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st)
+hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st, bool far)
 {
     const float *raw = m.raw.as<float>();
     const float *b3 = raw + HID * MLP_IN + HID + HID * HID + HID + 2 * HID;
-    const int4 *items = ws.lazy ? ws.items_live.as<int4>() : ws.items.as<int4>();
-    const int *nlive = ws.lazy ? live_count(ws) : nullptr;
-    if (ws.n_items > 0) {
-        const unsigned blocks = (unsigned)std::min((ws.n_items + 3) / 4, 256 * 8);
+    // the items: the prefix's (or all), the live ones (lazy TX), or those past the prefix of flagged views
+    const int4 *items = far ? ws.items_far.as<int4>() : ws.lazy ? ws.items_live.as<int4>() : ws.items.as<int4>();
+    const int *nlive = far ? far_count(ws) : ws.lazy ? live_count(ws) : nullptr;
+    const int nmax = far ? ws.n_items_far : ws.n_items;
+    if (nmax > 0) {
+        const unsigned blocks = (unsigned)std::min((nmax + 3) / 4, 256 * 8);
         if (m.fp32) {
             hipLaunchKernelGGL(k_mlp_pairs_f32, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                                ws.Gp.as<float>(), m.w2a.as<float>(), m.tab.as<float4>(), b3,
-                               ws.vorder.as<uint32_t>(), items, ws.n_items, ws.Kp, ws.K,
+                               ws.vorder.as<uint32_t>(), items, nmax, ws.Kp, ws.K,
                                ws.counters.as<unsigned long long>(), ws.rad.as<float2>(), nlive);
         } else if (mlp_fused_ok(sc, m)) {
             // bound of the Gaussians' layer-1 term: per hidden unit
@@ -1995,13 +2047,13 @@ hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStr
             hipLaunchKernelGGL(k_mlp_pairs<true>, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                                sc.feat.as<float>(), ws.Gp.as<float>(), m.w2h.as<half8>(), m.tabh.as<float4>(), b3,
                                m.w1h.as<half8>(), m.b1tab.as<float>(), std::ldexp(1.f, -m.w1exp), lbound,
-                               ws.vorder.as<uint32_t>(), items, ws.n_items, ws.Kp, ws.K,
+                               ws.vorder.as<uint32_t>(), items, nmax, ws.Kp, ws.K,
                                amax_words(ws), ws.rad.as<float2>(), nlive);
         } else {
             hipLaunchKernelGGL(k_mlp_pairs<false>, dim3(blocks), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                                sc.feat.as<float>(), ws.Gp.as<float>(), m.w2h.as<half8>(), m.tabh.as<float4>(), b3,
                                m.w1h.as<half8>(), m.b1tab.as<float>(), 1.f, 0.f,
-                               ws.vorder.as<uint32_t>(), items, ws.n_items, ws.Kp, ws.K,
+                               ws.vorder.as<uint32_t>(), items, nmax, ws.Kp, ws.K,
                                amax_words(ws), ws.rad.as<float2>(), nlive);
         }
     }
@@ -2009,8 +2061,11 @@ hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStr
 }
 
 template <int R>
-static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st)
+static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st, bool redo)
 {
+    // the redo pass renders the flagged views again with every position's radiance
+    const uint32_t mpos = redo ? 0xFFFFFFFFu : ws.mpos;
+    const int rd = redo ? 1 : 0;
     dim3 grid((unsigned)ws.n_chunks, (unsigned)ws.g.tiles);
     const uint32_t *tord = ws.tiles_ordered ? ws.torder.as<uint32_t>() : nullptr;
     if constexpr (R == 1) {
@@ -2018,38 +2073,73 @@ static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st)
             hipLaunchKernelGGL((k_blend_fwd1<true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
-                               ws.part.as<float>(), stat_words(ws), tord, ws.vflag.as<uint32_t>());
+                               ws.part.as<float>(), stat_words(ws), tord, ws.vflag.as<uint32_t>(), mpos, rd);
         else
             hipLaunchKernelGGL((k_blend_fwd1<false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord,
-                               ws.vflag.as<uint32_t>());
+                               ws.vflag.as<uint32_t>(), mpos, rd);
     } else {
         if (save)
             hipLaunchKernelGGL((k_blend_fwd_multi<R, true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
                                ws.part.as<float>(), stat_words(ws), tord, ws.lazy ? ws.live.as<uint8_t>() : nullptr,
-                               ws.vflag.as<uint32_t>());
+                               ws.vflag.as<uint32_t>(), mpos, rd);
         else
             hipLaunchKernelGGL((k_blend_fwd_multi<R, false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord,
-                               ws.lazy ? ws.live.as<uint8_t>() : nullptr, ws.vflag.as<uint32_t>());
+                               ws.lazy ? ws.live.as<uint8_t>() : nullptr, ws.vflag.as<uint32_t>(), mpos, rd);
     }
 }
 
-hipError_t launch_blend_fwd(Workspace &ws, float *C, bool save, hipStream_t st)
+hipError_t launch_blend_fwd(Workspace &ws, float *C, bool save, hipStream_t st, bool redo)
 {
     if (ws.n_chunks == 0) return hipSuccess;
     if (ws.g.tiles > 65535) return hipErrorInvalidConfiguration;   // grid y limit
     switch (ws.R) {
-    case 1: blend_launch<1>(ws, C, save, st); break;
-    case 2: blend_launch<2>(ws, C, save, st); break;
-    case 4: blend_launch<4>(ws, C, save, st); break;
-    case 8: blend_launch<8>(ws, C, save, st); break;
-    default: blend_launch<16>(ws, C, save, st); break;
+    case 1: blend_launch<1>(ws, C, save, st, redo); break;
+    case 2: blend_launch<2>(ws, C, save, st, redo); break;
+    case 4: blend_launch<4>(ws, C, save, st, redo); break;
+    case 8: blend_launch<8>(ws, C, save, st, redo); break;
+    default: blend_launch<16>(ws, C, save, st, redo); break;
     }
+    return hipGetLastError();
+}
+
+// MLP work items of the positions past the prefix, for the views whose blend
+// composited such a position (flag 4); one workgroup per view, any order
+__global__ __launch_bounds__(BLOCK) void k_far_items(const int4 *__restrict__ vinfo, const uint32_t *__restrict__ vflag,
+                                                     uint32_t mpos, int4 *__restrict__ out, int *__restrict__ count)
+{
+    const int v = blockIdx.x;
+    if (!(vflag[v] & 4u)) return;
+    const int4 vi = vinfo[v];   // (first receiver, receivers, visible, -)
+    const int nb = (vi.z + MLP_PAIRS - 1) / MLP_PAIRS, nb0 = min(nb, (int)(mpos / MLP_PAIRS));
+    const int nrg = (vi.y + MLP_RG - 1) / MLP_RG;
+    const int n = (nb - nb0) * nrg;
+    __shared__ int s_base;
+    if (threadIdx.x == 0) s_base = n > 0 ? atomicAdd(count, n) : 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += BLOCK) {
+        const int sb = nb0 + i / nrg, a = i - (i / nrg) * nrg;
+        const int s0 = sb * MLP_PAIRS;
+        out[s_base + i] = make_int4(v, s0, vi.x + a * MLP_RG,
+                                    min(MLP_RG, vi.y - a * MLP_RG) | (min(MLP_PAIRS, vi.z - s0) << 8));
+    }
+}
+
+int *far_count(Workspace &ws)
+{
+    return reinterpret_cast<int *>(emit_words(ws) + emit_word_count(ws.V, ws.Kp));
+}
+
+hipError_t launch_far_items(Workspace &ws, hipStream_t st)
+{
+    if (ws.V == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_far_items, dim3((unsigned)ws.V), dim3(BLOCK), 0, st, ws.d_vinfo, ws.vflag.as<uint32_t>(),
+                       ws.mpos, ws.items_far.as<int4>(), far_count(ws));
     return hipGetLastError();
 }
 
@@ -2100,7 +2190,7 @@ hipError_t launch_blend_weights(Workspace &ws, hipStream_t st)
         hipLaunchKernelGGL((k_blend_fwd_multi<1, false, true>), dim3((unsigned)ws.n_wchunks, (unsigned)ws.g.tiles),
                        dim3(BLOCK), 0, st, ws.srec.as<float4>(), ws.pval[ws.pairs_buf].as<uint32_t>(),
                        ws.ranges.as<uint2>(), ws.rad.as<float2>(), ws.d_wchunks, ws.Kp, ws.g, nullptr, nullptr,
-                       nullptr, nullptr, nullptr, tord, ws.live.as<uint8_t>(), ws.vflag.as<uint32_t>());
+                       nullptr, nullptr, nullptr, tord, ws.live.as<uint8_t>(), ws.vflag.as<uint32_t>(), 0xFFFFFFFFu, 0);
     if (ws.n_items > 0)
         hipLaunchKernelGGL(k_live_items, dim3(nblk(ws.n_items)), dim3(BLOCK), 0, st, ws.items.as<int4>(), ws.n_items,
                            ws.live.as<uint8_t>(), ws.Kp, ws.items_live.as<int4>(), live_count(ws));

@@ -267,6 +267,19 @@ extern "C" rxgs_status rxgs_set_near_cut(rxgs_ctx *ctx, int on)
 
 extern "C" int64_t rxgs_views_redone(const rxgs_ctx *ctx) { return ctx ? ctx->views_redone : -1; }
 
+extern "C" rxgs_status rxgs_view_flags(rxgs_ctx *ctx, uint32_t *out, int32_t max_views, int32_t *n_views)
+{
+    if (!ctx || (max_views > 0 && !out)) return RXGS_E_INVALID;
+    const Workspace &ws = ctx->ws;
+    const int n = ws.vflag.p ? std::min<int>(ws.V, std::max(max_views, 0)) : 0;
+    if (n_views) *n_views = ws.vflag.p ? ws.V : 0;
+    if (n == 0) return RXGS_OK;
+    DeviceScope ds(ctx->device);
+    if (hipMemcpy(out, ws.vflag.p, (size_t)n * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return hip_fail(ctx, hipGetLastError(), "view flags");
+    return RXGS_OK;
+}
+
 extern "C" const char *rxgs_version(void) { return "rxgs 0.1 (gfx950)"; }
 
 extern "C" const char *rxgs_last_error(const rxgs_ctx *ctx)
@@ -658,7 +671,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     // term| of the receivers and of the Gaussians (FP32 bits); render
     // statistics; the emission's ticket, error word and look-back status
     const size_t emit_words_n = emit_word_count(V, Kp);
-    const size_t cnt_words = (size_t)4 * V + AMAX_SLOTS + 2 * STAT_WORDS + emit_words_n;
+    const size_t cnt_words = (size_t)4 * V + AMAX_SLOTS + 2 * STAT_WORDS + emit_words_n + 16;   // + far-item count
     GROW(ctx, ws.counters, cnt_words * 4);
     GROW(ctx, ws.hist, sort_ws_bytes((uint32_t)VK, 32, V));
 
@@ -766,21 +779,43 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         ws.h_nvis[v] = (int)h_cnt[2 * v];
         ws.nvis_total += ws.h_nvis[v];
     }
+    // Prefix radiance (TX-mode MLP renders without saved state): compositing stops
+    // at T < 1e-4, so in thick scenes a view composites only its nearest few
+    // hundred Gaussians.  The pair MLP first runs on the PREFIX_POS nearest
+    // sorted positions of each view; the blend gives the others zero radiance
+    // and flags any view that composites one of them; those views get the
+    // rest of their radiance and are blended again (all on the device).
+    // TX views only: there the weights, and so the composited set, are shared
+    // by all the view's receivers; in RX mode the far radiance of the views
+    // that need it and their second blend cost more than the prefix saves.
+    ws.mpos = 0xFFFFFFFFu;
+    if (!saved && ws.use_mlp && mode == RXGS_MODE_TX)
+        for (int v = 0; v < V; v++)
+            if ((uint32_t)ws.h_nvis[v] > PREFIX_POS) ws.mpos = PREFIX_POS;
+    if (ws.mpos != 0xFFFFFFFFu && ws.lazy) {   // the prefix replaces the weights-only pass
+        ws.lazy = false;
+        wchunks.clear();
+        ws.n_wchunks = 0;
+    }
 
     // MLP work items, per view: (32 sorted positions) x (16 receivers),
     // position-major; only their per-view offsets are built here, the items
     // themselves on the device
     std::vector<uint32_t> item_off(V + 1, 0);
     std::vector<int4> vinfo(V);   // (first receiver, receivers, visible, takes the weights pass)
+    int64_t nfar = 0;
     for (int v = 0; v < V; v++) {
-        const int64_t ni = ws.use_mlp ? (int64_t)((ws.h_nvis[v] + MLP_PAIRS - 1) / MLP_PAIRS) *
-                                            ((vnrx[v] + MLP_RG - 1) / MLP_RG)
-                                      : 0;
+        const int64_t nb = (ws.h_nvis[v] + MLP_PAIRS - 1) / MLP_PAIRS, nrg = (vnrx[v] + MLP_RG - 1) / MLP_RG;
+        const int64_t nb0 = std::min<int64_t>(nb, ws.mpos / MLP_PAIRS);
+        const int64_t ni = ws.use_mlp ? nb0 * nrg : 0;
+        nfar += ws.use_mlp ? (nb - nb0) * nrg : 0;
         if ((int64_t)item_off[v] + ni >= (1ll << 31)) return fail(ctx, RXGS_E_INVALID, "too many MLP work items");
         item_off[v + 1] = item_off[v] + (uint32_t)ni;
         vinfo[v] = make_int4(vfirst[v], vnrx[v], ws.h_nvis[v], ws.lazy && vnrx[v] >= LAZY_MIN_RX ? 1 : 0);
     }
     ws.n_items = (int)item_off[V];
+    if (nfar >= (1ll << 31)) return fail(ctx, RXGS_E_INVALID, "too many MLP work items");
+    ws.n_items_far = (int)nfar;
     // pair-emission chunks: EM2_CHUNK visible entries of one view each
     std::vector<uint32_t> chunk_off(V + 1, 0);
     for (int v = 0; v < V; v++)
@@ -807,6 +842,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         GROW(ctx, ws.items_live, (size_t)std::max(ws.n_items, 1) * 16);
         GROW(ctx, ws.live, live_count_offset(ws) + 64);
     }
+    if (ws.mpos != 0xFFFFFFFFu) GROW(ctx, ws.items_far, (size_t)std::max(ws.n_items_far, 1) * 16);
 
     // the small descriptors, packed (16-byte aligned parts) into one host-to-device copy
     auto al16 = [](size_t b) { return (b + 15) / 16 * 16; };
@@ -872,6 +908,13 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
 
     // stage 3: compositing, then the per-receiver reductions
     STAGE(ctx, "blend_fwd", launch_blend_fwd(ws, C, saved != nullptr, st));
+    if (ws.mpos != 0xFFFFFFFFu) {
+        // views that composited a position past the prefix: the rest of their
+        // radiance, then their blend again (other views' workgroups return at once)
+        STAGE(ctx, "far_items", launch_far_items(ws, st));
+        STAGE(ctx, "mlp_far", launch_mlp_pairs(sc, ctx->mlp, ws, st, true));
+        STAGE(ctx, "blend_redo", launch_blend_fwd(ws, C, false, st, true));
+    }
     STAGE(ctx, "reduce", launch_reduce_outputs(ws, power, csum, st));
     ws.scene_version = sc.version;
     ws.mlp_version = ctx->mlp.version;
@@ -905,7 +948,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
     HIPCHK(ctx, hipStreamSynchronize(st));
     std::vector<int> redo;
     for (int v = 0; v < V; v++)
-        if (hf[v] == 3u) redo.push_back(v);
+        if ((hf[v] & 3u) == 3u) redo.push_back(v);
     ctx->views_redone += (int64_t)redo.size();
     if (redo.empty()) return RXGS_OK;
     if (saved) return render_pass(ctx, mode, Q, tx, rx_off, N, rx, C, power, csum, saved, stream, 0xFFFFFFFFu);

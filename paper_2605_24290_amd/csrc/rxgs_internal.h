@@ -25,6 +25,7 @@ constexpr int MLP_RG = 16;               // receivers per MLP work item
 constexpr int MLP_PAIRS = 32;            // sorted positions per MLP work item
 constexpr int LAZY_MIN_RX = 4;           // receivers of a TX view for its weights-only pass
 constexpr int64_t NEAR_LIMIT = 4096;     // nearest depth-sorted entries emitted per view first
+constexpr uint32_t PREFIX_POS = 4096;    // sorted positions whose radiance the first blend pass gets
 constexpr int AMAX_SLOTS = 128;          // activation-bound words after the view counters
 constexpr int STAT_SLOTS = 64;           // u64 slots per render statistic (spread atomics)
 constexpr int STAT_WORDS = 4 * STAT_SLOTS;   // four statistics, u64 each
@@ -163,7 +164,10 @@ struct Workspace {
     DevBuf items_live;   // MLP work items of the live blocks (lazy forward)
     bool lazy = false;   // this render evaluates the pair MLP on live blocks only
     uint32_t limit = 0xFFFFFFFFu;   // depth-sorted entries emitted per view (the nearest)
-    DevBuf vflag;        // per view: 1 = entries were cut, 3 = cut with a pixel still open
+    uint32_t mpos = 0xFFFFFFFFu;    // pair MLP first on sorted positions below this (prefix radiance)
+    DevBuf items_far;    // MLP work items past the prefix of the views that need them
+    int n_items_far = 0; // their largest possible number
+    DevBuf vflag;        // per view bits: 1 entries cut, 2 a pixel open after a cut, 4 composited past the prefix
     int n_wchunks = 0;   // weights-pass chunks: one per view with receivers
     int4 *d_wchunks = nullptr;
     // host staging (pinned) and the events guarding it
@@ -247,9 +251,11 @@ hipError_t launch_rad_direct(const Scene &sc, Workspace &ws, hipStream_t st);
 hipError_t launch_mlp_global_term(const Mlp &m, Workspace &ws, hipStream_t st);
 hipError_t launch_mlp_items(Workspace &ws, hipStream_t st);
 hipError_t launch_mlp_local(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st);
-hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st);
+hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st, bool far = false);
 bool mlp_fused_ok(const Scene &sc, const Mlp &m);
-hipError_t launch_blend_fwd(Workspace &ws, float *C, bool save, hipStream_t st);
+hipError_t launch_blend_fwd(Workspace &ws, float *C, bool save, hipStream_t st, bool redo = false);
+hipError_t launch_far_items(Workspace &ws, hipStream_t st);
+int *far_count(Workspace &ws);
 hipError_t launch_reduce_outputs(Workspace &ws, float *power, float *csum, hipStream_t st);
 // backward (backward.hip)
 hipError_t launch_blend_bwd(Workspace &ws, const float *C, const float *dC, const float *dP, hipStream_t st);

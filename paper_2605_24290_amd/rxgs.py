@@ -77,7 +77,8 @@ EXPORTED = ("rxgs_create", "rxgs_destroy", "rxgs_last_error", "rxgs_scene_upload
             "rxgs_saved_info", "rxgs_saved_export", "rxgs_version", "rxgs_profile_enable",
             "rxgs_profile_read", "rxgs_server_start", "rxgs_server_submit", "rxgs_server_poll",
             "rxgs_server_cancel", "rxgs_server_stats", "rxgs_server_stop", "rxgs_plan_batch",
-            "rxgs_workspace_estimate", "rxgs_set_near_cut", "rxgs_views_redone", "rxgs_render_chunked")
+            "rxgs_workspace_estimate", "rxgs_set_near_cut", "rxgs_views_redone", "rxgs_render_chunked",
+            "rxgs_view_flags")
 
 _lib = None
 
@@ -124,6 +125,8 @@ def lib():
     L.rxgs_render_chunked.argtypes = [vp, c_int, c_int, vp, POINTER(c_int32), c_int, vp, vp, vp, vp, c_int64,
                                       POINTER(c_int32), vp]
     L.rxgs_render_chunked.restype = c_int
+    L.rxgs_view_flags.argtypes = [vp, vp, c_int32, POINTER(c_int32)]
+    L.rxgs_view_flags.restype = c_int
     L.rxgs_set_near_cut.argtypes = [vp, c_int]
     L.rxgs_set_near_cut.restype = c_int
     L.rxgs_views_redone.argtypes = [vp]
@@ -312,6 +315,14 @@ class Renderer:
     def near_cut(self, on: bool = True):
         """Nearest-first emission with the exact fallback (rxgs_set_near_cut; off by default)."""
         _check(lib().rxgs_set_near_cut(self._ctx, 1 if on else 0), self._ctx)
+
+    def view_flags(self) -> np.ndarray:
+        """Per-view flags of the last render without saved state (rxgs_view_flags)."""
+        n = c_int32(0)
+        _check(lib().rxgs_view_flags(self._ctx, None, 0, byref(n)), self._ctx)
+        out = np.zeros(max(n.value, 1), dtype=np.uint32)
+        _check(lib().rxgs_view_flags(self._ctx, out.ctypes.data, n.value, None), self._ctx)
+        return out[:n.value]
 
     def views_redone(self) -> int:
         """Views redone over all their entries since creation (rxgs_views_redone)."""
