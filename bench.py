@@ -41,6 +41,8 @@ BLEND_OPS_PER_EXTRA_RX = 2   # TX mode: each further receiver sharing the weight
 SORT_BYTES_PER_KEY_PASS = 16  # read and write one (u32 key, u32 value) per pass
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                             "k_blend_fwd1_c1_rx_traffic.txt")
+SQ_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "c1_rx_sq_counters.txt")
+VALU_ISSUE_PEAK = 256 * 2.4e9   # wave64 VALU instructions per second (one per CU per cycle)
 
 
 def parse():
@@ -285,19 +287,28 @@ def source_digest() -> str:
     return h.hexdigest()
 
 
-def stored_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary, scaled by the copy-kernel calibration it records; None
+def stored_figure(path: str, field: str, kernel: str, workload: str):
+    """A per-launch figure of `kernel` from a committed rocprofv3 summary; None
     if there is none for this kernel and workload or the sources changed since."""
     try:
-        with open(TRAFFIC_FILE) as fh:
-            kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
+        with open(path) as fh:
+            kv = dict(line.split(":", 1) for line in fh
+                      if ":" in line and not line.startswith("#") and not line.startswith(" "))
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
     if kv.get("kernel") != kernel or kv.get("workload") != workload or kv.get("source_sha256") != source_digest():
         return None
-    return float(kv["hbm_bytes_per_launch"])
+    try:
+        return float(kv[field])
+    except (KeyError, ValueError):
+        return None
+
+
+def stored_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE summary, scaled by
+    the copy-kernel calibration it records."""
+    return stored_figure(TRAFFIC_FILE, "hbm_bytes_per_launch", kernel, workload)
 
 
 def roofline_for(entry, mode, workload):
@@ -314,9 +325,13 @@ def roofline_for(entry, mode, workload):
             per_view = sz["composited_px"] / max(sz["chunks_per_view"], 1)
             ops = BLEND_OPS_PER_PAIR * per_view + BLEND_OPS_PER_EXTRA_RX * (sz["composited"] - per_view)
         ach = ops / t_s / 1e12
+        # executed wave64 VALU instructions per launch (SQ_INSTS_VALU of the
+        # committed counter run) against the issue peak, over the live launch time
+        insts = stored_figure(SQ_FILE, "valu_wave_insts_per_launch", "k_blend_fwd1", workload)
         return {"kernel": "k_blend_fwd1", "bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS,
                 "unit": "Tops/s", "frac": ach / PEAK_VALU_TOPS,
                 "traffic": stored_traffic("k_blend_fwd1", workload),
+                "valu_issue_frac": None if insts is None else insts / (VALU_ISSUE_PEAK * t_s),
                 "work": f"{BLEND_OPS_PER_PAIR} lane-ops x {sz['composited']} composited (pixel, Gaussian) pairs"}
     if top == "mlp_pairs":
         flop = MLP_MFMA_FLOP_PER_PAIR * sz["mlp_pairs"]
