@@ -23,6 +23,7 @@ namespace rxgs {
 constexpr int MLPB_PART = 4096 + 64 + 128 + 2 + 62;   // dW2, db2, dW3, db3, pad
 constexpr int W1B_CHUNK = 128;                        // Gaussians per dW1b partial
 constexpr int RED_GROUPS = 64;                        // row groups of the two-stage column sums
+constexpr int MLPB_RSUB = 4;                          // receivers per virtual item of the MLP backward (at least)
 constexpr float LN2F = 0.69314718055994531f;
 
 // ----------------------------------------------------------------------------
@@ -232,8 +233,8 @@ __global__ __launch_bounds__(BLOCK) void k_rad_direct_bwd(const float2 *__restri
 __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
     const float *__restrict__ Lp, const float *__restrict__ Gp, const float *__restrict__ w2a,
     const float *__restrict__ w2b, const float4 *__restrict__ tab, const float *__restrict__ W3,
-    const uint32_t *__restrict__ order, const int4 *__restrict__ items, int nitems, int64_t Kp, int64_t K,
-    const uint8_t *__restrict__ live, const float2 *__restrict__ dS, float *__restrict__ dL,
+    const uint32_t *__restrict__ order, const int4 *__restrict__ items, int nitems, int nsub, int64_t Kp,
+    int64_t K, const uint8_t *__restrict__ live, const float2 *__restrict__ dS, float *__restrict__ dL,
     float *__restrict__ dG, float *__restrict__ part)
 {
     __shared__ float s_w2a[2 * 32 * 64];
@@ -270,22 +271,30 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
     // Gaussians of a view are composited, so most items have no nonzero dL/ds;
     // the blend backward marks the position blocks that do, and each round
     // reads the marks of this wave's next 64 items at once.
-    for (int base = gw; base < nitems; base += 64 * nw) {
+    // Each work item is split into nsub virtual items of at most
+    // MLP_RG / nsub receivers, so a live item's receivers spread over waves
+    // instead of running one after another in one wave (nsub = 1 when every
+    // view has few receivers, as in RX mode).
+    const int nvirt = nitems * nsub, rsub = (MLP_RG + nsub - 1) / nsub;
+    for (int base = gw; base < nvirt; base += 64 * nw) {
     uint64_t todo;
     {
         const int mine = base + lane * nw;
         bool lv = false;
-        if (mine < nitems) {
-            const int4 it = items[mine];
-            lv = live[((size_t)it.x * Kp + it.y) / MLP_PAIRS] != 0;
+        if (mine < nvirt) {
+            const int4 it = items[mine / nsub];
+            const int sub = mine % nsub;
+            lv = sub * rsub < (it.w & 255) && live[((size_t)it.x * Kp + it.y) / MLP_PAIRS] != 0;
         }
         todo = __ballot(lv);
     }
     while (todo) {
-        const int item = base + __builtin_ctzll(todo) * nw;
+        const int vitem = base + __builtin_ctzll(todo) * nw;
         todo &= todo - 1;
-        const int4 it = items[item];
-        const int view = it.x, s0 = it.y, j0 = it.z, nj = it.w & 255;
+        const int4 it = items[vitem / nsub];
+        const int sub = vitem % nsub;
+        const int view = it.x, s0 = it.y, j0 = it.z + sub * rsub;
+        const int nj = min(rsub, (it.w & 255) - sub * rsub);
         const int64_t s = s0 + pl;
         const int nvalid = it.w >> 8;
         const bool valid = pl < nvalid;
@@ -781,11 +790,14 @@ hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *g
     const float *W1 = raw;
     const float *W3 = raw + HID * MLP_IN + HID + HID * HID + HID;
     const int nwaves = mlp_bwd_waves(ws);
+    // virtual items per work item: enough that each holds at most MLPB_RSUB receivers
+    const int nsub = (std::min(ws.R_max, MLP_RG) + MLPB_RSUB - 1) / MLPB_RSUB;
+    if (ws.n_items > INT32_MAX / std::max(nsub, 1)) return hipErrorInvalidValue;   // virtual item indices are int
     if (ws.n_items > 0)
         hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)(nwaves / 4)), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                            ws.Gp.as<float>(), m.w2a.as<float>(), m.w2b.as<float>(), m.tab.as<float4>(), W3,
-                           ws.vorder.as<uint32_t>(), ws.items.as<int4>(), ws.n_items, ws.Kp, sc.K,
-                           ws.live.as<uint8_t>(), ws.dS.as<float2>(), ws.dL.as<float>(),
+                           ws.vorder.as<uint32_t>(), ws.items.as<int4>(), ws.n_items, std::max(nsub, 1), ws.Kp,
+                           sc.K, ws.live.as<uint8_t>(), ws.dS.as<float2>(), ws.dL.as<float>(),
                            ws.dG.as<float>(), ws.mpart.as<float>());
     if (gmlp) {
         if (ws.n_items > 0) {

@@ -722,6 +722,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     }
     int maxr = 1;
     for (int v = 0; v < V; v++) maxr = std::max(maxr, vnrx[v]);
+    ws.R_max = maxr;
     int R = 1;
     if (mode == RXGS_MODE_TX)
         while (R < 16 && R < maxr) R *= 2;

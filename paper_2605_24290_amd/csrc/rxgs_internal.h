@@ -165,6 +165,7 @@ struct Workspace {
     bool lazy = false;   // this render evaluates the pair MLP on live blocks only
     uint32_t limit = 0xFFFFFFFFu;   // depth-sorted entries emitted per view (the nearest)
     uint32_t mpos = 0xFFFFFFFFu;    // pair MLP first on sorted positions below this (prefix radiance)
+    int R_max = 1;       // most receivers of one view
     DevBuf items_far;    // MLP work items past the prefix of the views that need them
     int n_items_far = 0; // their largest possible number
     DevBuf vflag;        // per view bits: 1 entries cut, 2 a pixel open after a cut, 4 composited past the prefix
