@@ -159,18 +159,21 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
                 }
             }
             if (__ballot(act) == 0) continue;   // uniform across the wave
+            // sums over each 16-lane row, added into the batch's LDS
+            // accumulators by the rows' last lanes
             float vals[6] = {gu, gv, gca, gcb, gcc, glo};
+            const bool row_last = (lane & 15) == 15;
 #pragma unroll
             for (int c = 0; c < 6; c++) {
-                const float v = wave_sum_last(vals[c]);
-                if (lane == 63 && v != 0.f) atomicAdd(&s_acc[c][e], v);
+                const float v = row_sum(vals[c]);
+                if (row_last && v != 0.f) atomicAdd(&s_acc[c][e], v);
             }
 #pragma unroll
             for (int r = 0; r < R; r++) {
                 if (r < nrx) {
-                    const float vx = wave_sum_last(dsr[r].x);
-                    const float vy = wave_sum_last(dsr[r].y);
-                    if (lane == 63) {
+                    const float vx = row_sum(dsr[r].x);
+                    const float vy = row_sum(dsr[r].y);
+                    if (row_last) {
                         if (vx != 0.f) atomicAdd(&s_dacc[r][e].x, vx);
                         if (vy != 0.f) atomicAdd(&s_dacc[r][e].y, vy);
                     }

@@ -46,6 +46,16 @@ __device__ __forceinline__ float dpp_shift(float x)
                                                                  0xf, false));
 }
 
+// Sum over each 16-lane row; lanes 15, 31, 47 and 63 hold the four sums.
+__device__ __forceinline__ float row_sum(float x)
+{
+    x += dpp_shift<0x111, 0xf>(x);   // row_shr:1
+    x += dpp_shift<0x112, 0xf>(x);   // row_shr:2
+    x += dpp_shift<0x114, 0xf>(x);   // row_shr:4
+    x += dpp_shift<0x118, 0xf>(x);   // row_shr:8
+    return x;
+}
+
 // Sum over each 32-lane half of the wave; lanes 31 and 63 hold the two sums.
 __device__ __forceinline__ float half_wave_sum(float x)
 {
