@@ -587,6 +587,10 @@ extern "C" rxgs_status rxgs_mlp_upload(rxgs_ctx *ctx, const float *params, int s
 }
 
 // ============================================================================
+// TX renders whose views have at most this many receivers take the prefix
+// radiance path; with more, the weights-only pass (see render_pass).
+constexpr int PREFIX_MAX_RX = 128;
+
 // One pass of the forward.  limit caps, per view, the depth-sorted entries
 // that are emitted (the nearest ones); the blend flags every view it cut that
 // still has a pixel whose transmittance stayed above the stop threshold.
@@ -789,8 +793,12 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     // TX views only: there the weights, and so the composited set, are shared
     // by all the view's receivers; in RX mode the far radiance of the views
     // that need it and their second blend cost more than the prefix saves.
+    // With many receivers on a view the prefix costs PREFIX_POS MLP pairs per
+    // receiver (and a flagged view its whole list per receiver), while the
+    // weights-only pass costs one blend of the view whatever the receiver
+    // count: such renders keep the weights pass.
     ws.mpos = 0xFFFFFFFFu;
-    if (!saved && ws.use_mlp && mode == RXGS_MODE_TX)
+    if (!saved && ws.use_mlp && mode == RXGS_MODE_TX && maxr < PREFIX_MAX_RX)
         for (int v = 0; v < V; v++)
             if ((uint32_t)ws.h_nvis[v] > PREFIX_POS) ws.mpos = PREFIX_POS;
     if (ws.mpos != 0xFFFFFFFFu && ws.lazy) {   // the prefix replaces the weights-only pass
