@@ -1268,11 +1268,24 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) v
 // entries per staged batch (five workgroups per CU)
 constexpr int NB1 = BLOCK / 2;
 
+// Far entries of the radiance prefix path: a lane that composites an entry
+// past the prefix (its radiance not yet evaluated) records (T w, sorted
+// position) so its contribution can be added, in list order, once the
+// radiance exists; up to FAR_REC per pixel, more sends the view to a full
+// second blend.
+constexpr int FAR_REC = FAR_RECORDS;
+struct FarState {
+    uint2 *rec;      // per (view, pixel): FAR_REC records (bits of T w, sorted position)
+    uint8_t *cnt;    // per (view, pixel): records made (saturating at 255)
+    uint8_t *tile;   // per (view, tile): some pixel made records
+};
+
 template <int NB> struct BlendFwdStage {
     float4 q[4][NB][2];              // per wave, in list order
     float4 r0[NB];                   // the batch's records (azimuth shifted near the tile)
     float4 r1[NB];
     float2 rad[NB];                  // and radiance
+    uint32_t p[NB];                  // and sorted positions
     unsigned short list[4][NB];      // per wave: batch index of each entry
     int len[4];
     int wcnt[4][4];
@@ -1336,6 +1349,7 @@ __device__ __forceinline__ void stage_fwd(BlendFwdStage<NB> &st, const float4 *_
         st.r0[t] = r0;
         st.r1[t] = r1;
         st.rad[t] = rv;
+        st.p[t] = p;
     }
     uint64_t bal[4], nbal[4];
 #pragma unroll
@@ -1403,14 +1417,14 @@ __device__ __forceinline__ void stage_fwd(BlendFwdStage<NB> &st, const float4 *_
 // alpha threshold, or met after the lane terminated, gets weight 0, which
 // leaves T and the sums unchanged.  WRAP: the list is in the wrapped form.
 // SAVE: track the stop index and the composited count (saved states and
-// statistics only).  DETECT: set *far_hit when the lane composites an entry
-// at list index i_far or later.
+// statistics only).  DETECT: record every entry at list index i_far or later
+// that the lane composites (FarState).
 template <bool SAVE, bool WRAP, bool DETECT = false, int NB>
 __device__ __forceinline__ void blend_walk1(const BlendFwdStage<NB> &st, int wv, int n, int lbase, float X, float Y,
                                             float XX, float XY, float YY, float Wf, float halfW, float &T,
                                             float2 &acc, int &last, uint32_t &ncomp, uint32_t &neval,
                                             uint32_t &nslot, bool &done, int i_begin = 0, int i_far = 0,
-                                            bool *far_hit = nullptr)
+                                            uint2 *myrec = nullptr, int *fcount = nullptr)
 {
     for (int i0 = i_begin; i0 < n; i0 += 4) {
 #pragma unroll
@@ -1444,7 +1458,10 @@ __device__ __forceinline__ void blend_walk1(const BlendFwdStage<NB> &st, int wv,
                 last = inc ? lbase + (int)st.list[wv][i] : last;
                 ncomp += inc ? 1u : 0u;
             }
-            if (DETECT) *far_hit = *far_hit || (inc && i >= i_far);
+            if (DETECT && inc && i >= i_far) {
+                if (*fcount < FAR_REC && myrec) myrec[*fcount] = make_uint2(__float_as_uint(tw), st.p[st.list[wv][i]]);
+                ++*fcount;
+            }
             done = done || T < T_EPS;
         }
         if (__all(done)) break;
@@ -1461,7 +1478,8 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
                                                       int *__restrict__ nlast, float *__restrict__ part,
                                                       unsigned long long *__restrict__ stats,
                                                      const uint32_t *__restrict__ torder,
-                                                     uint32_t *__restrict__ vflag, uint32_t mpos, int redo)
+                                                     uint32_t *__restrict__ vflag, uint32_t mpos, int redo,
+                                                     FarState fs)
 {
     constexpr int NB = NB1;
     __shared__ BlendFwdStage<NB> st;
@@ -1469,8 +1487,17 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
 
     // grid: (chunk, rank of the tile in its view's longest-first order)
     const int4 ch = chunks[blockIdx.x];
-    if (redo && !(vflag[ch.x] & 4u)) return;   // uniform over the block, before any barrier
     const int tile = torder ? (int)torder[(size_t)ch.x * g.tiles + blockIdx.y] : (int)blockIdx.y;
+    // second launch of the prefix path: blend views that overflowed their
+    // records again, add the recorded far entries in tiles that have some,
+    // nothing elsewhere (uniform over the block, before any barrier)
+    bool deferred = false;
+    if (redo) {
+        if (!(vflag[ch.x] & 4u)) {
+            if (!fs.tile[(size_t)ch.x * g.tiles + tile]) return;
+            deferred = true;
+        }
+    }
     const int view = ch.x, j0 = ch.y, nrx = ch.z, tslot = ch.w;
     const int ty = tile / g.tiles_x, tx = tile - ty * g.tiles_x;
     const int t = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
@@ -1486,9 +1513,31 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
     float2 acc = make_float2(0.f, 0.f);
     int last = 0;
     uint32_t ncomp = 0, neval = 0, nslot = 0;   // composited / evaluated while active / walked (SAVE)
-    bool done = !inside, far_hit = false;
+    bool done = !inside;
+    const size_t P = (size_t)g.H * g.W;
+    const size_t pix = (size_t)row * g.W + col;
+    int fcount = 0;
+    uint2 *myrec = (inside && mpos != 0xFFFFFFFFu) ? fs.rec + ((size_t)view * P + pix) * FAR_REC : nullptr;
 
-    for (uint32_t base = rg.x; base < rg.y; base += NB) {
+    if (deferred) {
+        // the first pass's sum, then its recorded entries in list order with
+        // their radiance: the same operations, in the same order, as one pass
+        if (inside && nrx > 0) {
+            acc.x = C[((size_t)j0 * 2) * P + pix];
+            acc.y = C[((size_t)j0 * 2 + 1) * P + pix];
+            const size_t q = (size_t)view * P + pix;
+            const int n = min((int)fs.cnt[q], FAR_REC);
+            for (int k = 0; k < n; k++) {
+                const uint2 rc = fs.rec[q * FAR_REC + k];
+                const float tw = __uint_as_float(rc.x);
+                const int64_t s = (int64_t)rc.y - (int64_t)view * Kp;
+                const float2 sv = rad[(size_t)j0 * Kp + s];
+                acc.x = fmaf(tw, sv.x, acc.x);
+                acc.y = fmaf(tw, sv.y, acc.y);
+            }
+        }
+    }
+    for (uint32_t base = rg.x; !deferred && base < rg.y; base += NB) {
         const uint32_t cnt = min((uint32_t)NB, rg.y - base);
         __syncthreads();
         uint32_t p = 0;
@@ -1518,21 +1567,29 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
             if (i4 < n && __any(!done)) {
                 if (wide)
                     blend_walk1<SAVE, true, true>(st, wv, n, lbase, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp,
-                                                  neval, nslot, done, i4, i_far, &far_hit);
+                                                  neval, nslot, done, i4, i_far, myrec, &fcount);
                 else
                     blend_walk1<SAVE, false, true>(st, wv, n, lbase, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp,
-                                                   neval, nslot, done, i4, i_far, &far_hit);
+                                                   neval, nslot, done, i4, i_far, myrec, &fcount);
             }
         }
         if (__syncthreads_and(done ? 1 : 0)) break;
     }
-    // a pixel still open at the end of a view's truncated list: the view is redone in full
-    if (__syncthreads_or(inside && !done) && t == 0 && (vflag[view] & 1u)) atomicOr(vflag + view, 2u);
-    // a composited entry past the position prefix (zero radiance here): the view is redone
-    if (__syncthreads_or(far_hit) && t == 0) atomicOr(vflag + view, 4u);
+    if (!redo) {
+        // a pixel still open at the end of a view's truncated list: the view is redone in full
+        if (__syncthreads_or(inside && !done) && t == 0 && (vflag[view] & 1u)) atomicOr(vflag + view, 2u);
+        if (mpos != 0xFFFFFFFFu) {
+            // entries past the prefix composited here: records kept (8), or too many (4)
+            if (inside) fs.cnt[(size_t)view * P + pix] = (uint8_t)min(fcount, 255);
+            const int any_rec = __syncthreads_or(fcount > 0 && fcount <= FAR_REC);
+            const int any_ovf = __syncthreads_or(fcount > FAR_REC);
+            if (t == 0) {
+                fs.tile[(size_t)view * g.tiles + tile] = any_rec ? 1 : 0;
+                if (any_ovf || any_rec) atomicOr(vflag + view, any_ovf ? 12u : 8u);
+            }
+        }
+    }
 
-    const size_t P = (size_t)g.H * g.W;
-    const size_t pix = (size_t)row * g.W + col;
     if (inside && nrx > 0) {
         C[((size_t)j0 * 2) * P + pix] = acc.x;
         C[((size_t)j0 * 2 + 1) * P + pix] = acc.y;
@@ -1598,7 +1655,7 @@ __device__ __forceinline__ void blend_walk_multi(const BlendStage &st, const flo
                                            int lbase, float colf, float rowf, float Wf, float halfW, float &T,
                                            float2 (&acc)[R], int &last, uint32_t &ncomp, uint32_t &neval,
                                            uint32_t &nslot, bool &done, unsigned char *s_mark = nullptr,
-                                           int i_begin = 0, bool *far_hit = nullptr)
+                                           int i_begin = 0, uint2 *myrec = nullptr, int *fcount = nullptr)
 {
     for (int i = i_begin; i < n; i++) {
         if (SAVE) {
@@ -1630,7 +1687,10 @@ __device__ __forceinline__ void blend_walk_multi(const BlendStage &st, const flo
             ncomp += inc ? 1u : 0u;
         }
         if (MARK && inc) s_mark[e] = 1;
-        if (DETECT) *far_hit = *far_hit || inc;
+        if (DETECT && inc) {
+            if (*fcount < FAR_REC && myrec) myrec[*fcount] = make_uint2(__float_as_uint(tw), st.p[e]);
+            ++*fcount;
+        }
         done = done || T < T_EPS;
         if ((i & 3) == 3 && __all(done)) break;
     }
@@ -1653,18 +1713,25 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restr
                                                      unsigned long long *__restrict__ stats,
                                                      const uint32_t *__restrict__ torder,
                                                      uint8_t *__restrict__ live, uint32_t *__restrict__ vflag,
-                                                     uint32_t mpos, int redo)
+                                                     uint32_t mpos, int redo, FarState fs)
 {
     __shared__ BlendStage st;
     __shared__ float2 s_rad[R][BLOCK];
     __shared__ float s_red[4][R][3];
     __shared__ unsigned char s_mark[MARK ? BLOCK : 1];
-    if (redo && !(vflag[chunks[blockIdx.x].x] & 4u)) return;   // uniform, before any barrier
     if (MARK) s_mark[threadIdx.x] = 0;
 
     // grid: (chunk, rank of the tile in its view's longest-first order)
     const int4 ch = chunks[blockIdx.x];
     const int tile = torder ? (int)torder[(size_t)ch.x * g.tiles + blockIdx.y] : (int)blockIdx.y;
+    // second launch of the prefix path (see k_blend_fwd1)
+    bool deferred = false;
+    if (redo) {
+        if (!(vflag[ch.x] & 4u)) {
+            if (!fs.tile[(size_t)ch.x * g.tiles + tile]) return;
+            deferred = true;
+        }
+    }
     const int view = ch.x, j0 = ch.y, nrx = ch.z, tslot = ch.w;
     const int ty = tile / g.tiles_x, tx = tile - ty * g.tiles_x;
     const int t = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
@@ -1681,9 +1748,37 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restr
     for (int r = 0; r < R; r++) acc[r] = make_float2(0.f, 0.f);
     int last = 0;
     uint32_t ncomp = 0, neval = 0, nslot = 0;   // composited / evaluated while active / walked (SAVE)
-    bool done = !inside, far_hit = false;
+    bool done = !inside;
+    const size_t P = (size_t)g.H * g.W;
+    const size_t pix = (size_t)row * g.W + col;
+    int fcount = 0;
+    uint2 *myrec = (!MARK && inside && mpos != 0xFFFFFFFFu) ? fs.rec + ((size_t)view * P + pix) * FAR_REC : nullptr;
 
-    for (uint32_t base = rg.x; base < rg.y; base += BLOCK) {
+    if (deferred && inside) {
+        // the first pass's sums, then the view's recorded entries in list order
+        // with each receiver's radiance (see k_blend_fwd1)
+#pragma unroll
+        for (int r = 0; r < R; r++)
+            if (r < nrx) {
+                acc[r].x = C[((size_t)(j0 + r) * 2) * P + pix];
+                acc[r].y = C[((size_t)(j0 + r) * 2 + 1) * P + pix];
+            }
+        const size_t q = (size_t)view * P + pix;
+        const int n = min((int)fs.cnt[q], FAR_REC);
+        for (int k = 0; k < n; k++) {
+            const uint2 rc = fs.rec[q * FAR_REC + k];
+            const float tw = __uint_as_float(rc.x);
+            const int64_t s = (int64_t)rc.y - (int64_t)view * Kp;
+#pragma unroll
+            for (int r = 0; r < R; r++)
+                if (r < nrx) {
+                    const float2 sv = rad[(size_t)(j0 + r) * Kp + s];
+                    acc[r].x = fmaf(tw, sv.x, acc[r].x);
+                    acc[r].y = fmaf(tw, sv.y, acc[r].y);
+                }
+        }
+    }
+    for (uint32_t base = rg.x; !deferred && base < rg.y; base += BLOCK) {
         const uint32_t cnt = min((uint32_t)BLOCK, rg.y - base);
         __syncthreads();
         uint32_t p = 0;
@@ -1715,11 +1810,11 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restr
                 if (wrap)
                     blend_walk_multi<R, SAVE, true, MARK, true>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T, acc,
                                                                 last, ncomp, neval, nslot, done, s_mark, i_far,
-                                                                &far_hit);
+                                                                myrec, &fcount);
                 else
                     blend_walk_multi<R, SAVE, false, MARK, true>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T,
                                                                  acc, last, ncomp, neval, nslot, done, s_mark, i_far,
-                                                                 &far_hit);
+                                                                 myrec, &fcount);
             }
         }
         const int alldone = __syncthreads_and(done ? 1 : 0);
@@ -1730,13 +1825,22 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restr
         if (alldone) break;
     }
     if (MARK) return;
-    // a pixel still open at the end of a view's truncated list: the view is redone in full
-    if (__syncthreads_or(inside && !done) && t == 0 && (vflag[view] & 1u)) atomicOr(vflag + view, 2u);
-    // a composited entry past the position prefix (zero radiance here): the view is redone
-    if (__syncthreads_or(far_hit) && t == 0) atomicOr(vflag + view, 4u);
+    if (!redo) {
+        // a pixel still open at the end of a view's truncated list: the view is redone in full
+        if (__syncthreads_or(inside && !done) && t == 0 && (vflag[view] & 1u)) atomicOr(vflag + view, 2u);
+        if (mpos != 0xFFFFFFFFu) {
+            // entries past the prefix composited here: records kept (8), or too many (4);
+            // every chunk of a view walks the same weights and writes the same records
+            if (inside) fs.cnt[(size_t)view * P + pix] = (uint8_t)min(fcount, 255);
+            const int any_rec = __syncthreads_or(fcount > 0 && fcount <= FAR_REC);
+            const int any_ovf = __syncthreads_or(fcount > FAR_REC);
+            if (t == 0) {
+                fs.tile[(size_t)view * g.tiles + tile] = any_rec ? 1 : 0;
+                if (any_ovf || any_rec) atomicOr(vflag + view, any_ovf ? 12u : 8u);
+            }
+        }
+    }
 
-    const size_t P = (size_t)g.H * g.W;
-    const size_t pix = (size_t)row * g.W + col;
     if (inside) {
 #pragma unroll
         for (int r = 0; r < R; r++) {
@@ -2063,9 +2167,11 @@ hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStr
 template <int R>
 static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st, bool redo)
 {
-    // the redo pass renders the flagged views again with every position's radiance
+    // the second pass blends overflowed views again with every position's
+    // radiance and adds the recorded far entries elsewhere
     const uint32_t mpos = redo ? 0xFFFFFFFFu : ws.mpos;
     const int rd = redo ? 1 : 0;
+    const FarState fs{ws.frec.as<uint2>(), ws.fcnt.as<uint8_t>(), ws.ftile.as<uint8_t>()};
     dim3 grid((unsigned)ws.n_chunks, (unsigned)ws.g.tiles);
     const uint32_t *tord = ws.tiles_ordered ? ws.torder.as<uint32_t>() : nullptr;
     if constexpr (R == 1) {
@@ -2073,24 +2179,24 @@ static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st, boo
             hipLaunchKernelGGL((k_blend_fwd1<true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
-                               ws.part.as<float>(), stat_words(ws), tord, ws.vflag.as<uint32_t>(), mpos, rd);
+                               ws.part.as<float>(), stat_words(ws), tord, ws.vflag.as<uint32_t>(), mpos, rd, fs);
         else
             hipLaunchKernelGGL((k_blend_fwd1<false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord,
-                               ws.vflag.as<uint32_t>(), mpos, rd);
+                               ws.vflag.as<uint32_t>(), mpos, rd, fs);
     } else {
         if (save)
             hipLaunchKernelGGL((k_blend_fwd_multi<R, true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
                                ws.part.as<float>(), stat_words(ws), tord, ws.lazy ? ws.live.as<uint8_t>() : nullptr,
-                               ws.vflag.as<uint32_t>(), mpos, rd);
+                               ws.vflag.as<uint32_t>(), mpos, rd, fs);
         else
             hipLaunchKernelGGL((k_blend_fwd_multi<R, false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord,
-                               ws.lazy ? ws.live.as<uint8_t>() : nullptr, ws.vflag.as<uint32_t>(), mpos, rd);
+                               ws.lazy ? ws.live.as<uint8_t>() : nullptr, ws.vflag.as<uint32_t>(), mpos, rd, fs);
     }
 }
 
@@ -2109,12 +2215,12 @@ hipError_t launch_blend_fwd(Workspace &ws, float *C, bool save, hipStream_t st, 
 }
 
 // MLP work items of the positions past the prefix, for the views whose blend
-// composited such a position (flag 4); one workgroup per view, any order
+// composited such a position (flags 4 and 8); one workgroup per view, any order
 __global__ __launch_bounds__(BLOCK) void k_far_items(const int4 *__restrict__ vinfo, const uint32_t *__restrict__ vflag,
                                                      uint32_t mpos, int4 *__restrict__ out, int *__restrict__ count)
 {
     const int v = blockIdx.x;
-    if (!(vflag[v] & 4u)) return;
+    if (!(vflag[v] & 12u)) return;
     const int4 vi = vinfo[v];   // (first receiver, receivers, visible, -)
     const int nb = (vi.z + MLP_PAIRS - 1) / MLP_PAIRS, nb0 = min(nb, (int)(mpos / MLP_PAIRS));
     const int nrg = (vi.y + MLP_RG - 1) / MLP_RG;
@@ -2190,7 +2296,8 @@ hipError_t launch_blend_weights(Workspace &ws, hipStream_t st)
         hipLaunchKernelGGL((k_blend_fwd_multi<1, false, true>), dim3((unsigned)ws.n_wchunks, (unsigned)ws.g.tiles),
                        dim3(BLOCK), 0, st, ws.srec.as<float4>(), ws.pval[ws.pairs_buf].as<uint32_t>(),
                        ws.ranges.as<uint2>(), ws.rad.as<float2>(), ws.d_wchunks, ws.Kp, ws.g, nullptr, nullptr,
-                       nullptr, nullptr, nullptr, tord, ws.live.as<uint8_t>(), ws.vflag.as<uint32_t>(), 0xFFFFFFFFu, 0);
+                       nullptr, nullptr, nullptr, tord, ws.live.as<uint8_t>(), ws.vflag.as<uint32_t>(), 0xFFFFFFFFu, 0,
+                       FarState{nullptr, nullptr, nullptr});
     if (ws.n_items > 0)
         hipLaunchKernelGGL(k_live_items, dim3(nblk(ws.n_items)), dim3(BLOCK), 0, st, ws.items.as<int4>(), ws.n_items,
                            ws.live.as<uint8_t>(), ws.Kp, ws.items_live.as<int4>(), live_count(ws));

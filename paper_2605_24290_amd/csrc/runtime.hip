@@ -127,7 +127,7 @@ void free_workspace(Workspace &ws)
                       &ws.Lp,      &ws.Gp,      &ws.items,  &ws.Tfin,   &ws.nlast,  &ws.part,
                       &ws.counters, &ws.hist,   &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
                       &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.mred,   &ws.live,   &ws.items_live, &ws.vflag,
-                      &ws.hist_b};
+                      &ws.items_far, &ws.frec, &ws.fcnt,  &ws.ftile,  &ws.hist_b};
     for (DevBuf *b : bufs) release(*b);
     if (ws.staged) (void)hipEventDestroy(ws.staged);
     if (ws.counted) (void)hipEventDestroy(ws.counted);
@@ -790,17 +790,19 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     // sorted positions of each view; the blend gives the others zero radiance
     // and flags any view that composites one of them; those views get the
     // rest of their radiance and are blended again (all on the device).
-    // TX views only: there the weights, and so the composited set, are shared
-    // by all the view's receivers; in RX mode the far radiance of the views
-    // that need it and their second blend cost more than the prefix saves.
-    // With many receivers on a view the prefix costs PREFIX_POS MLP pairs per
-    // receiver (and a flagged view its whole list per receiver), while the
-    // weights-only pass costs one blend of the view whatever the receiver
-    // count: such renders keep the weights pass.
+    // A lane that composites an entry past the prefix records it (T w and
+    // position, up to FAR_RECORDS per pixel); once the rest of the view's
+    // radiance exists, a second launch adds the recorded terms in list order
+    // (after the prefix's, as in one pass: the tile lists are in depth order),
+    // and blends again only views whose pixels recorded more.  With many
+    // receivers on a TX view the prefix costs PREFIX_POS MLP pairs per
+    // receiver, while the weights-only pass costs one blend of the view
+    // whatever the receiver count: such renders keep the weights pass.
     ws.mpos = 0xFFFFFFFFu;
-    if (!saved && ws.use_mlp && mode == RXGS_MODE_TX && maxr < PREFIX_MAX_RX)
+    const uint32_t prefix = mode == RXGS_MODE_TX ? PREFIX_POS : PREFIX_POS_RX;
+    if (!saved && ws.use_mlp && (mode == RXGS_MODE_RX || maxr < PREFIX_MAX_RX))
         for (int v = 0; v < V; v++)
-            if ((uint32_t)ws.h_nvis[v] > PREFIX_POS) ws.mpos = PREFIX_POS;
+            if ((uint32_t)ws.h_nvis[v] > prefix) ws.mpos = prefix;
     if (ws.mpos != 0xFFFFFFFFu && ws.lazy) {   // the prefix replaces the weights-only pass
         ws.lazy = false;
         wchunks.clear();
@@ -851,7 +853,12 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         GROW(ctx, ws.items_live, (size_t)std::max(ws.n_items, 1) * 16);
         GROW(ctx, ws.live, live_count_offset(ws) + 64);
     }
-    if (ws.mpos != 0xFFFFFFFFu) GROW(ctx, ws.items_far, (size_t)std::max(ws.n_items_far, 1) * 16);
+    if (ws.mpos != 0xFFFFFFFFu) {
+        GROW(ctx, ws.items_far, (size_t)std::max(ws.n_items_far, 1) * 16);
+        GROW(ctx, ws.frec, (size_t)V * P * FAR_RECORDS * 8);
+        GROW(ctx, ws.fcnt, (size_t)V * P);
+        GROW(ctx, ws.ftile, (size_t)V * g.tiles);
+    }
 
     // the small descriptors, packed (16-byte aligned parts) into one host-to-device copy
     auto al16 = [](size_t b) { return (b + 15) / 16 * 16; };
@@ -919,10 +926,11 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     STAGE(ctx, "blend_fwd", launch_blend_fwd(ws, C, saved != nullptr, st));
     if (ws.mpos != 0xFFFFFFFFu) {
         // views that composited a position past the prefix: the rest of their
-        // radiance, then their blend again (other views' workgroups return at once)
+        // radiance, then their recorded terms added, or their blend again
+        // (the workgroups of other tiles return at once)
         STAGE(ctx, "far_items", launch_far_items(ws, st));
         STAGE(ctx, "mlp_far", launch_mlp_pairs(sc, ctx->mlp, ws, st, true));
-        STAGE(ctx, "blend_redo", launch_blend_fwd(ws, C, false, st, true));
+        STAGE(ctx, "blend_far", launch_blend_fwd(ws, C, false, st, true));
     }
     STAGE(ctx, "reduce", launch_reduce_outputs(ws, power, csum, st));
     ws.scene_version = sc.version;

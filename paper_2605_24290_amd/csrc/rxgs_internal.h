@@ -25,7 +25,9 @@ constexpr int MLP_RG = 16;               // receivers per MLP work item
 constexpr int MLP_PAIRS = 32;            // sorted positions per MLP work item
 constexpr int LAZY_MIN_RX = 4;           // receivers of a TX view for its weights-only pass
 constexpr int64_t NEAR_LIMIT = 4096;     // nearest depth-sorted entries emitted per view first
-constexpr uint32_t PREFIX_POS = 4096;    // sorted positions whose radiance the first blend pass gets
+constexpr uint32_t PREFIX_POS = 4096;    // sorted positions whose radiance the first blend pass gets (TX)
+constexpr uint32_t PREFIX_POS_RX = 8192; // the same for RX views (a view is one receiver)
+constexpr int FAR_RECORDS = 16;          // recorded far entries per pixel (FarState)
 constexpr int AMAX_SLOTS = 128;          // activation-bound words after the view counters
 constexpr int STAT_SLOTS = 64;           // u64 slots per render statistic (spread atomics)
 constexpr int STAT_WORDS = 4 * STAT_SLOTS;   // four statistics, u64 each
@@ -167,6 +169,7 @@ struct Workspace {
     uint32_t mpos = 0xFFFFFFFFu;    // pair MLP first on sorted positions below this (prefix radiance)
     int R_max = 1;       // most receivers of one view
     DevBuf items_far;    // MLP work items past the prefix of the views that need them
+    DevBuf frec, fcnt, ftile;   // composited entries past the prefix: records, counts, tile marks
     int n_items_far = 0; // their largest possible number
     DevBuf vflag;        // per view bits: 1 entries cut, 2 a pixel open after a cut, 4 composited past the prefix
     int n_wchunks = 0;   // weights-pass chunks: one per view with receivers
