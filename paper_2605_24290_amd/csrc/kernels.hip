@@ -1468,7 +1468,9 @@ __device__ __forceinline__ void blend_walk1(const BlendFwdStage<NB> &st, int wv,
     }
 }
 
-template <bool SAVE>
+// SECOND: the prefix path's second launch (its own instantiation, so that
+// profiles tell the two launches apart).
+template <bool SAVE, bool SECOND = false>
 __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__ srec,
                                                       const uint32_t *__restrict__ pval,
                                                       const uint2 *__restrict__ ranges,
@@ -1478,10 +1480,10 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
                                                       int *__restrict__ nlast, float *__restrict__ part,
                                                       unsigned long long *__restrict__ stats,
                                                      const uint32_t *__restrict__ torder,
-                                                     uint32_t *__restrict__ vflag, uint32_t mpos, int redo,
-                                                     FarState fs)
+                                                     uint32_t *__restrict__ vflag, uint32_t mpos, FarState fs)
 {
     constexpr int NB = NB1;
+    constexpr bool redo = SECOND;
     __shared__ BlendFwdStage<NB> st;
     __shared__ float s_red[4][3];
 
@@ -1702,7 +1704,7 @@ __device__ __forceinline__ void blend_walk_multi(const BlendStage &st, const flo
 // same.  Otherwise, when live is given, positions of unmarked blocks read a
 // zero radiance: no pixel composites them, so their weight is zero and the
 // sums are unchanged.
-template <int R, bool SAVE, bool MARK = false>
+template <int R, bool SAVE, bool MARK = false, bool SECOND = false>
 __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restrict__ srec,
                                                      const uint32_t *__restrict__ pval,
                                                      const uint2 *__restrict__ ranges,
@@ -1713,8 +1715,9 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restr
                                                      unsigned long long *__restrict__ stats,
                                                      const uint32_t *__restrict__ torder,
                                                      uint8_t *__restrict__ live, uint32_t *__restrict__ vflag,
-                                                     uint32_t mpos, int redo, FarState fs)
+                                                     uint32_t mpos, FarState fs)
 {
+    constexpr bool redo = SECOND;
     __shared__ BlendStage st;
     __shared__ float2 s_rad[R][BLOCK];
     __shared__ float s_red[4][R][3];
@@ -2170,7 +2173,6 @@ static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st, boo
     // the second pass blends overflowed views again with every position's
     // radiance and adds the recorded far entries elsewhere
     const uint32_t mpos = redo ? 0xFFFFFFFFu : ws.mpos;
-    const int rd = redo ? 1 : 0;
     const FarState fs{ws.frec.as<uint2>(), ws.fcnt.as<uint8_t>(), ws.ftile.as<uint8_t>()};
     dim3 grid((unsigned)ws.n_chunks, (unsigned)ws.g.tiles);
     const uint32_t *tord = ws.tiles_ordered ? ws.torder.as<uint32_t>() : nullptr;
@@ -2179,24 +2181,35 @@ static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st, boo
             hipLaunchKernelGGL((k_blend_fwd1<true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
-                               ws.part.as<float>(), stat_words(ws), tord, ws.vflag.as<uint32_t>(), mpos, rd, fs);
+                               ws.part.as<float>(), stat_words(ws), tord, ws.vflag.as<uint32_t>(), mpos, fs);
+        else if (redo)
+            hipLaunchKernelGGL((k_blend_fwd1<false, true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
+                               ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
+                               ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord,
+                               ws.vflag.as<uint32_t>(), mpos, fs);
         else
             hipLaunchKernelGGL((k_blend_fwd1<false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord,
-                               ws.vflag.as<uint32_t>(), mpos, rd, fs);
+                               ws.vflag.as<uint32_t>(), mpos, fs);
     } else {
         if (save)
             hipLaunchKernelGGL((k_blend_fwd_multi<R, true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
                                ws.part.as<float>(), stat_words(ws), tord, ws.lazy ? ws.live.as<uint8_t>() : nullptr,
-                               ws.vflag.as<uint32_t>(), mpos, rd, fs);
+                               ws.vflag.as<uint32_t>(), mpos, fs);
+        else if (redo)
+            hipLaunchKernelGGL((k_blend_fwd_multi<R, false, false, true>), grid, dim3(BLOCK), 0, st,
+                               ws.srec.as<float4>(), ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(),
+                               ws.rad.as<float2>(), ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr,
+                               ws.part.as<float>(), nullptr, tord, ws.lazy ? ws.live.as<uint8_t>() : nullptr,
+                               ws.vflag.as<uint32_t>(), mpos, fs);
         else
             hipLaunchKernelGGL((k_blend_fwd_multi<R, false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                                ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord,
-                               ws.lazy ? ws.live.as<uint8_t>() : nullptr, ws.vflag.as<uint32_t>(), mpos, rd, fs);
+                               ws.lazy ? ws.live.as<uint8_t>() : nullptr, ws.vflag.as<uint32_t>(), mpos, fs);
     }
 }
 
@@ -2296,7 +2309,7 @@ hipError_t launch_blend_weights(Workspace &ws, hipStream_t st)
         hipLaunchKernelGGL((k_blend_fwd_multi<1, false, true>), dim3((unsigned)ws.n_wchunks, (unsigned)ws.g.tiles),
                        dim3(BLOCK), 0, st, ws.srec.as<float4>(), ws.pval[ws.pairs_buf].as<uint32_t>(),
                        ws.ranges.as<uint2>(), ws.rad.as<float2>(), ws.d_wchunks, ws.Kp, ws.g, nullptr, nullptr,
-                       nullptr, nullptr, nullptr, tord, ws.live.as<uint8_t>(), ws.vflag.as<uint32_t>(), 0xFFFFFFFFu, 0,
+                       nullptr, nullptr, nullptr, tord, ws.live.as<uint8_t>(), ws.vflag.as<uint32_t>(), 0xFFFFFFFFu,
                        FarState{nullptr, nullptr, nullptr});
     if (ws.n_items > 0)
         hipLaunchKernelGGL(k_live_items, dim3(nblk(ws.n_items)), dim3(BLOCK), 0, st, ws.items.as<int4>(), ws.n_items,
