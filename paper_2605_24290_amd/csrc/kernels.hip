@@ -1278,6 +1278,7 @@ struct FarState {
     uint2 *rec;      // per (view, pixel): FAR_REC records (bits of T w, sorted position)
     uint8_t *cnt;    // per (view, pixel): records made (saturating at 255)
     uint8_t *tile;   // per (view, tile): some pixel made records
+    uint8_t *mark;   // per block of MLP_PAIRS sorted positions: a record points into it
 };
 
 template <int NB> struct BlendFwdStage {
@@ -1424,7 +1425,7 @@ __device__ __forceinline__ void blend_walk1(const BlendFwdStage<NB> &st, int wv,
                                             float XX, float XY, float YY, float Wf, float halfW, float &T,
                                             float2 &acc, int &last, uint32_t &ncomp, uint32_t &neval,
                                             uint32_t &nslot, bool &done, int i_begin = 0, int i_far = 0,
-                                            uint2 *myrec = nullptr, int *fcount = nullptr)
+                                            uint2 *myrec = nullptr, int *fcount = nullptr, uint8_t *mark = nullptr)
 {
     for (int i0 = i_begin; i0 < n; i0 += 4) {
 #pragma unroll
@@ -1459,7 +1460,11 @@ __device__ __forceinline__ void blend_walk1(const BlendFwdStage<NB> &st, int wv,
                 ncomp += inc ? 1u : 0u;
             }
             if (DETECT && inc && i >= i_far) {
-                if (*fcount < FAR_REC && myrec) myrec[*fcount] = make_uint2(__float_as_uint(tw), st.p[st.list[wv][i]]);
+                if (*fcount < FAR_REC && myrec) {
+                    const uint32_t pe = st.p[st.list[wv][i]];
+                    myrec[*fcount] = make_uint2(__float_as_uint(tw), pe);
+                    mark[pe / MLP_PAIRS] = 1;
+                }
                 ++*fcount;
             }
             done = done || T < T_EPS;
@@ -1569,10 +1574,10 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
             if (i4 < n && __any(!done)) {
                 if (wide)
                     blend_walk1<SAVE, true, true>(st, wv, n, lbase, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp,
-                                                  neval, nslot, done, i4, i_far, myrec, &fcount);
+                                                  neval, nslot, done, i4, i_far, myrec, &fcount, fs.mark);
                 else
                     blend_walk1<SAVE, false, true>(st, wv, n, lbase, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp,
-                                                   neval, nslot, done, i4, i_far, myrec, &fcount);
+                                                   neval, nslot, done, i4, i_far, myrec, &fcount, fs.mark);
             }
         }
         if (__syncthreads_and(done ? 1 : 0)) break;
@@ -1657,7 +1662,8 @@ __device__ __forceinline__ void blend_walk_multi(const BlendStage &st, const flo
                                            int lbase, float colf, float rowf, float Wf, float halfW, float &T,
                                            float2 (&acc)[R], int &last, uint32_t &ncomp, uint32_t &neval,
                                            uint32_t &nslot, bool &done, unsigned char *s_mark = nullptr,
-                                           int i_begin = 0, uint2 *myrec = nullptr, int *fcount = nullptr)
+                                           int i_begin = 0, uint2 *myrec = nullptr, int *fcount = nullptr,
+                                           uint8_t *mark = nullptr)
 {
     for (int i = i_begin; i < n; i++) {
         if (SAVE) {
@@ -1690,7 +1696,10 @@ __device__ __forceinline__ void blend_walk_multi(const BlendStage &st, const flo
         }
         if (MARK && inc) s_mark[e] = 1;
         if (DETECT && inc) {
-            if (*fcount < FAR_REC && myrec) myrec[*fcount] = make_uint2(__float_as_uint(tw), st.p[e]);
+            if (*fcount < FAR_REC && myrec) {
+                myrec[*fcount] = make_uint2(__float_as_uint(tw), st.p[e]);
+                mark[st.p[e] / MLP_PAIRS] = 1;
+            }
             ++*fcount;
         }
         done = done || T < T_EPS;
@@ -1813,11 +1822,11 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restr
                 if (wrap)
                     blend_walk_multi<R, SAVE, true, MARK, true>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T, acc,
                                                                 last, ncomp, neval, nslot, done, s_mark, i_far,
-                                                                myrec, &fcount);
+                                                                myrec, &fcount, fs.mark);
                 else
                     blend_walk_multi<R, SAVE, false, MARK, true>(st, s_rad, wv, n, lbase, colf, rowf, Wf, halfW, T,
                                                                  acc, last, ncomp, neval, nslot, done, s_mark, i_far,
-                                                                 myrec, &fcount);
+                                                                 myrec, &fcount, fs.mark);
             }
         }
         const int alldone = __syncthreads_and(done ? 1 : 0);
@@ -2173,7 +2182,7 @@ static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st, boo
     // the second pass blends overflowed views again with every position's
     // radiance and adds the recorded far entries elsewhere
     const uint32_t mpos = redo ? 0xFFFFFFFFu : ws.mpos;
-    const FarState fs{ws.frec.as<uint2>(), ws.fcnt.as<uint8_t>(), ws.ftile.as<uint8_t>()};
+    const FarState fs{ws.frec.as<uint2>(), ws.fcnt.as<uint8_t>(), ws.ftile.as<uint8_t>(), ws.live.as<uint8_t>()};
     dim3 grid((unsigned)ws.n_chunks, (unsigned)ws.g.tiles);
     const uint32_t *tord = ws.tiles_ordered ? ws.torder.as<uint32_t>() : nullptr;
     if constexpr (R == 1) {
@@ -2230,13 +2239,28 @@ hipError_t launch_blend_fwd(Workspace &ws, float *C, bool save, hipStream_t st, 
 // MLP work items of the positions past the prefix, for the views whose blend
 // composited such a position (flags 4 and 8); one workgroup per view, any order
 __global__ __launch_bounds__(BLOCK) void k_far_items(const int4 *__restrict__ vinfo, const uint32_t *__restrict__ vflag,
-                                                     uint32_t mpos, int4 *__restrict__ out, int *__restrict__ count)
+                                                     uint32_t mpos, const uint8_t *__restrict__ mark, int64_t Kp,
+                                                     int4 *__restrict__ out, int *__restrict__ count)
 {
     const int v = blockIdx.x;
-    if (!(vflag[v] & 12u)) return;
+    const uint32_t f = vflag[v];
+    if (!(f & 12u)) return;
     const int4 vi = vinfo[v];   // (first receiver, receivers, visible, -)
     const int nb = (vi.z + MLP_PAIRS - 1) / MLP_PAIRS, nb0 = min(nb, (int)(mpos / MLP_PAIRS));
     const int nrg = (vi.y + MLP_RG - 1) / MLP_RG;
+    if (!(f & 4u)) {
+        // records only: the blocks they point into
+        for (int sb = nb0 + threadIdx.x; sb < nb; sb += BLOCK) {
+            if (!mark[((size_t)v * Kp) / MLP_PAIRS + sb]) continue;
+            const int base = atomicAdd(count, nrg);
+            const int s0 = sb * MLP_PAIRS;
+            for (int a = 0; a < nrg; a++)
+                out[base + a] = make_int4(v, s0, vi.x + a * MLP_RG,
+                                          min(MLP_RG, vi.y - a * MLP_RG) | (min(MLP_PAIRS, vi.z - s0) << 8));
+        }
+        return;
+    }
+    // blended again: every block past the prefix
     const int n = (nb - nb0) * nrg;
     __shared__ int s_base;
     if (threadIdx.x == 0) s_base = n > 0 ? atomicAdd(count, n) : 0;
@@ -2258,7 +2282,7 @@ hipError_t launch_far_items(Workspace &ws, hipStream_t st)
 {
     if (ws.V == 0) return hipSuccess;
     hipLaunchKernelGGL(k_far_items, dim3((unsigned)ws.V), dim3(BLOCK), 0, st, ws.d_vinfo, ws.vflag.as<uint32_t>(),
-                       ws.mpos, ws.items_far.as<int4>(), far_count(ws));
+                       ws.mpos, ws.live.as<uint8_t>(), ws.Kp, ws.items_far.as<int4>(), far_count(ws));
     return hipGetLastError();
 }
 
@@ -2310,7 +2334,7 @@ hipError_t launch_blend_weights(Workspace &ws, hipStream_t st)
                        dim3(BLOCK), 0, st, ws.srec.as<float4>(), ws.pval[ws.pairs_buf].as<uint32_t>(),
                        ws.ranges.as<uint2>(), ws.rad.as<float2>(), ws.d_wchunks, ws.Kp, ws.g, nullptr, nullptr,
                        nullptr, nullptr, nullptr, tord, ws.live.as<uint8_t>(), ws.vflag.as<uint32_t>(), 0xFFFFFFFFu,
-                       FarState{nullptr, nullptr, nullptr});
+                       FarState{nullptr, nullptr, nullptr, nullptr});
     if (ws.n_items > 0)
         hipLaunchKernelGGL(k_live_items, dim3(nblk(ws.n_items)), dim3(BLOCK), 0, st, ws.items.as<int4>(), ws.n_items,
                            ws.live.as<uint8_t>(), ws.Kp, ws.items_live.as<int4>(), live_count(ws));

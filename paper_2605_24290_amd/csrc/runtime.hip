@@ -858,6 +858,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         GROW(ctx, ws.frec, (size_t)V * P * FAR_RECORDS * 8);
         GROW(ctx, ws.fcnt, (size_t)V * P);
         GROW(ctx, ws.ftile, (size_t)V * g.tiles);
+        GROW(ctx, ws.live, live_count_offset(ws) + 64);   // marks of the blocks records point into
     }
 
     // the small descriptors, packed (16-byte aligned parts) into one host-to-device copy
@@ -923,6 +924,8 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     }
 
     // stage 3: compositing, then the per-receiver reductions
+    if (ws.mpos != 0xFFFFFFFFu)
+        HIPCHK(ctx, launch_fill_u32(ws.live.as<uint32_t>(), 0u, (live_count_offset(ws) + 3) / 4, st));
     STAGE(ctx, "blend_fwd", launch_blend_fwd(ws, C, saved != nullptr, st));
     if (ws.mpos != 0xFFFFFFFFu) {
         // views that composited a position past the prefix: the rest of their
