@@ -231,6 +231,9 @@ rxgs_status rxgs_saved_info(const rxgs_saved *s, rxgs_saved_info_t *out);
  *   RXGS_EXPORT_PAIRS     D i32: sorted position (v * K_pad + s) of each pair
  *   RXGS_EXPORT_RANGES    V x tiles x 2 i32: [start, end) of each tile's pairs
  *   RXGS_EXPORT_RADIANCE  N x K_pad x 2 f32: radiance at each sorted position
+ *                         s < NVIS[view of the receiver] (a render that evaluated
+ *                         only the radiance its blend needed, see
+ *                         rxgs_view_flags, evaluates the rest first, on the device)
  *   RXGS_EXPORT_TFINAL    S x H x W f32: final transmittance (S = V in TX mode, N in RX)
  *   RXGS_EXPORT_NLAST     S x H x W i32: entries of the tile list consumed
  * `bytes` must be at least the size above; E_INVALID otherwise. */
@@ -353,12 +356,15 @@ rxgs_status rxgs_set_near_cut(rxgs_ctx *ctx, int on);
 int64_t rxgs_views_redone(const rxgs_ctx *ctx);
 
 /*
- * Per-view flags of the last rxgs_render without saved state (device-to-host
- * copy, synchronous): bit 0 the view's entries were cut (nearest-first
- * emission), bit 1 a pixel stayed open after the cut, bit 2 the blend
- * composited a sorted position past the radiance prefix (TX mode: the pair
- * MLP first runs on each view's 4096 nearest sorted positions; such a view
- * gets the rest of its radiance and is blended again on the device).  Copies
+ * Per-view flags of the last rxgs_render (device-to-host copy, synchronous):
+ * bit 0 the view's entries were cut (nearest-first emission; never with saved
+ * state, which emits every entry), bit 1 a pixel stayed open after the cut;
+ * with the radiance
+ * prefix (the pair MLP first runs on each view's nearest sorted positions,
+ * 4096 for TX views with fewer than 128 receivers, 8192 for RX views, when a
+ * view has more visible), bit 3 some pixel composited a position past it
+ * (those terms are added once their radiance exists) and bit 2 some pixel
+ * composited more than 16 such positions (the view is blended again).  Copies
  * up to max_views words to out and writes the view count to *n_views when
  * not NULL.  Errors: E_INVALID, E_DEVICE.
  */

@@ -240,7 +240,8 @@ __global__ __launch_bounds__(BLOCK) void k_rad_direct_bwd(const float2 *__restri
 __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
     const float *__restrict__ Lp, const float *__restrict__ Gp, const float *__restrict__ w2a,
     const float *__restrict__ w2b, const float4 *__restrict__ tab, const float *__restrict__ W3,
-    const uint32_t *__restrict__ order, const int4 *__restrict__ items, int nitems, int nsub, int64_t Kp,
+    const uint32_t *__restrict__ order, const int4 *__restrict__ items, int nitems,
+    const int4 *__restrict__ items2, const int *__restrict__ count2, int nsub, int64_t Kp,
     int64_t K, const uint8_t *__restrict__ live, const float2 *__restrict__ dS, float *__restrict__ dL,
     float *__restrict__ dG, float *__restrict__ part)
 {
@@ -282,23 +283,35 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
     // MLP_RG / nsub receivers, so a live item's receivers spread over waves
     // instead of running one after another in one wave (nsub = 1 when every
     // view has few receivers, as in RX mode).
+    // work items: the forward's list, then (a radiance-prefix forward) the
+    // list of its blocks past the prefix that hold composited entries
+    const int n1 = nitems;
+    nitems += items2 ? *count2 : 0;
     const int nvirt = nitems * nsub, rsub = (MLP_RG + nsub - 1) / nsub;
+    // Virtual items are dealt to waves in a scattered order, x -> x * HASH mod
+    // nvirt (a bijection: HASH is a prime above any count), so the few live
+    // items at the start of every view spread over waves instead of piling
+    // onto the same ones when the views' item counts are regular.
+    constexpr uint64_t HASH = 2654435761ull;
     for (int base = gw; base < nvirt; base += 64 * nw) {
     uint64_t todo;
     {
         const int mine = base + lane * nw;
         bool lv = false;
         if (mine < nvirt) {
-            const int4 it = items[mine / nsub];
-            const int sub = mine % nsub;
+            const int vm = (int)(((uint64_t)mine * HASH) % (uint64_t)nvirt);
+            const int ii = vm / nsub;
+            const int4 it = ii < n1 ? items[ii] : items2[ii - n1];
+            const int sub = vm % nsub;
             lv = sub * rsub < (it.w & 255) && live[((size_t)it.x * Kp + it.y) / MLP_PAIRS] != 0;
         }
         todo = __ballot(lv);
     }
     while (todo) {
-        const int vitem = base + __builtin_ctzll(todo) * nw;
+        const int vitem = (int)(((uint64_t)(base + __builtin_ctzll(todo) * nw) * HASH) % (uint64_t)nvirt);
         todo &= todo - 1;
-        const int4 it = items[vitem / nsub];
+        const int iv = vitem / nsub;
+        const int4 it = iv < n1 ? items[iv] : items2[iv - n1];
         const int sub = vitem % nsub;
         const int view = it.x, s0 = it.y, j0 = it.z + sub * rsub;
         const int nj = min(rsub, (it.w & 255) - sub * rsub);
@@ -797,17 +810,22 @@ hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *g
     const float *W1 = raw;
     const float *W3 = raw + HID * MLP_IN + HID + HID * HID + HID;
     const int nwaves = mlp_bwd_waves(ws);
+    const bool far = ws.mpos != 0xFFFFFFFFu;   // the forward evaluated a radiance prefix first
+    if (far && (int64_t)ws.n_items + ws.n_items_far >= (1ll << 31)) return hipErrorInvalidValue;
     // virtual items per work item: enough that each holds at most MLPB_RSUB receivers
     const int nsub = (std::min(ws.R_max, MLP_RG) + MLPB_RSUB - 1) / MLPB_RSUB;
-    if (ws.n_items > INT32_MAX / std::max(nsub, 1)) return hipErrorInvalidValue;   // virtual item indices are int
-    if (ws.n_items > 0)
+    const int64_t nall = (int64_t)ws.n_items + (far ? ws.n_items_far : 0);
+    if (nall > INT32_MAX / std::max(nsub, 1)) return hipErrorInvalidValue;   // virtual item indices are int
+    if (nall > 0)
         hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)(nwaves / 4)), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                            ws.Gp.as<float>(), m.w2a.as<float>(), m.w2b.as<float>(), m.tab.as<float4>(), W3,
-                           ws.vorder.as<uint32_t>(), ws.items.as<int4>(), ws.n_items, std::max(nsub, 1), ws.Kp,
+                           ws.vorder.as<uint32_t>(), ws.items.as<int4>(), ws.n_items,
+                           far ? ws.items_far.as<int4>() : nullptr, far ? far_count(ws) : nullptr,
+                           std::max(nsub, 1), ws.Kp,
                            sc.K, ws.live.as<uint8_t>(), ws.dS.as<float2>(), ws.dL.as<float>(),
                            ws.dG.as<float>(), ws.mpart.as<float>());
     if (gmlp) {
-        if (ws.n_items > 0) {
+        if (nall > 0) {
             hipLaunchKernelGGL(k_colsum_groups, dim3(nblk(4096 + 194), RED_GROUPS), dim3(BLOCK), 0, st,
                                ws.mpart.as<float>(), nwaves, MLPB_PART, 4096 + 194, ws.mred.as<double>());
             hipLaunchKernelGGL(k_mlp_bwd_reduce, dim3(nblk(4096 + 194)), dim3(BLOCK), 0, st, ws.mred.as<double>(),

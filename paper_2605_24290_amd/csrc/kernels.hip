@@ -2273,6 +2273,20 @@ __global__ __launch_bounds__(BLOCK) void k_far_items(const int4 *__restrict__ vi
     }
 }
 
+// every view of a prefix render needs all its radiance (a radiance export):
+// all blocks past the prefix, and the work-item count restarted
+__global__ __launch_bounds__(BLOCK) void k_far_all(uint32_t *__restrict__ vflag, int V, int *__restrict__ count)
+{
+    for (int v = threadIdx.x; v < V; v += BLOCK) vflag[v] |= 4u;
+    if (threadIdx.x == 0) *count = 0;
+}
+
+hipError_t launch_far_all(Workspace &ws, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_far_all, dim3(1), dim3(BLOCK), 0, st, ws.vflag.as<uint32_t>(), ws.V, far_count(ws));
+    return hipGetLastError();
+}
+
 int *far_count(Workspace &ws)
 {
     return reinterpret_cast<int *>(emit_words(ws) + emit_word_count(ws.V, ws.Kp));

@@ -800,9 +800,14 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     // whatever the receiver count: such renders keep the weights pass.
     ws.mpos = 0xFFFFFFFFu;
     const uint32_t prefix = mode == RXGS_MODE_TX ? PREFIX_POS : PREFIX_POS_RX;
-    if (!saved && ws.use_mlp && (mode == RXGS_MODE_RX || maxr < PREFIX_MAX_RX))
+    // Saved states take it too: the transmittances, stop indices and
+    // statistics come from the first pass (weights do not depend on the
+    // radiance), the backward reads the radiance of composited entries only,
+    // and a radiance export evaluates the rest first.
+    if (ws.use_mlp && (mode == RXGS_MODE_RX || maxr < PREFIX_MAX_RX))
         for (int v = 0; v < V; v++)
             if ((uint32_t)ws.h_nvis[v] > prefix) ws.mpos = prefix;
+    ws.rad_complete = ws.mpos == 0xFFFFFFFFu;
     if (ws.mpos != 0xFFFFFFFFu && ws.lazy) {   // the prefix replaces the weights-only pass
         ws.lazy = false;
         wchunks.clear();
@@ -1176,6 +1181,19 @@ extern "C" rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *ds
     if ((size_t)bytes < n) return fail(ctx, RXGS_E_INVALID, "destination too small");
     if (n == 0) return RXGS_OK;
     DeviceScope ds(ctx->device);
+    if (what == RXGS_EXPORT_RADIANCE && !ws.rad_complete) {
+        // the prefix render evaluated only the radiance the blend needed:
+        // evaluate the rest (it completes a cached part of the state; nothing
+        // the state describes changes, hence the cast)
+        if (ws.scene_version != ctx->scene.version || ws.mlp_version != ctx->mlp.version)
+            return fail(ctx, RXGS_E_STATE, "scene or MLP changed since the forward");
+        Workspace &w = const_cast<Workspace &>(ws);
+        HIPCHK(ctx, hipDeviceSynchronize());   // the render, on the caller's stream
+        HIPCHK(ctx, launch_far_all(w, nullptr));
+        HIPCHK(ctx, launch_far_items(w, nullptr));
+        HIPCHK(ctx, launch_mlp_pairs(ctx->scene, ctx->mlp, w, nullptr, true));
+        w.rad_complete = true;
+    }
     HIPCHK(ctx, hipDeviceSynchronize());
     if (what == RXGS_EXPORT_PAIRS || what == RXGS_EXPORT_RANGES) {
         // pairs without the per-view padding, ranges in those compact indices

@@ -171,6 +171,7 @@ struct Workspace {
     DevBuf items_far;    // MLP work items past the prefix of the views that need them
     DevBuf frec, fcnt, ftile;   // composited entries past the prefix: records, counts, tile marks
     int n_items_far = 0; // their largest possible number
+    bool rad_complete = true;   // every visible position's radiance is evaluated
     DevBuf vflag;        // per view bits: 1 entries cut, 2 a pixel open after a cut, 4 composited past the prefix
     int n_wchunks = 0;   // weights-pass chunks: one per view with receivers
     int4 *d_wchunks = nullptr;
@@ -259,6 +260,7 @@ hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStr
 bool mlp_fused_ok(const Scene &sc, const Mlp &m);
 hipError_t launch_blend_fwd(Workspace &ws, float *C, bool save, hipStream_t st, bool redo = false);
 hipError_t launch_far_items(Workspace &ws, hipStream_t st);
+hipError_t launch_far_all(Workspace &ws, hipStream_t st);
 int *far_count(Workspace &ws);
 hipError_t launch_reduce_outputs(Workspace &ws, float *power, float *csum, hipStream_t st);
 // backward (backward.hip)

@@ -99,6 +99,32 @@ def test_backward_mlp_several_transmitters():
     _compare(gg, go, FIELDS_MLP)
 
 
+@pytest.mark.parametrize("mode", ["tx", "rx"])
+def test_backward_radiance_prefix_far_entries(mode):
+    """A sparse scene (30,000 Gaussians in 40 x 40 x 4 m, full-sphere 45 x 90
+    grid) whose views have more visible Gaussians than the radiance prefix
+    and whose open rays composite Gaussians past it: the saved forward
+    evaluates their radiance in its second pass and the MLP backward must
+    cover them too (gradients against the oracle's reverse mode)."""
+    grid = S.Grid(45, 90, -math.pi / 2, math.pi / 45)
+    wl = S.make_workload("c1", K=30000, N=3, box=(40.0, 40.0, 4.0), grid=grid)
+    from .parity import renderer_for
+    import torch
+    r = renderer_for(wl)
+    r.render(wl.rx, tx=wl.tx, mode=mode)   # without saved state, for the view flags
+    torch.cuda.synchronize()
+    flags = r.view_flags()
+    r.close()
+    print(f"[prefix bwd] {mode}: view flags {flags.tolist()}")
+    assert (flags & 12).any()
+    rng = np.random.default_rng(12)
+    dC = rng.normal(size=(3, 2, grid.H, grid.W)).astype(np.float32)
+    gg, _ = _gpu_grads(wl, mode, dC=dC)
+    cen, rv = O.views_for(mode, wl.tx, wl.rx)
+    go = O.backward(wl.scene, wl.grid, cen, wl.rx, rv, dC, None, mlp=wl.mlp)
+    _compare(gg, go, FIELDS_MLP)
+
+
 def test_gpu_gradient_matches_fp64_central_differences():
     """GPU gradient of L = sum(dC * C) against FP64 central differences (step
     1e-6) of the oracle's forward on 64 random parameters; parameters whose
