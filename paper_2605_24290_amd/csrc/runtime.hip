@@ -629,6 +629,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     DeviceScope ds(ctx->device);
     hipStream_t st = (hipStream_t)stream;
     Workspace &ws = saved ? saved->ws : ctx->ws;
+    const bool save = saved && saved->keep;   // keep state for the backward and the exports
     ws.valid = false;
     if (!ws.staged) {
         HIPCHK(ctx, hipEventCreateWithFlags(&ws.staged, hipEventDisableTiming));
@@ -650,12 +651,12 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     ws.limit = limit;
     GROW(ctx, ws.vflag, (size_t)V * 4);
 
-    if (saved) {
+    if (save) {
         // the backward needs the view centres and receiver positions later
         GROW(ctx, ws.centres, (size_t)V * 12);
         GROW(ctx, ws.rxpos, (size_t)N * 12);
     }
-    if (saved) {
+    if (save) {
         // binning boxes, raw keys and opacities, kept for export
         GROW(ctx, ws.ext, VK * 16);
         GROW(ctx, ws.rawkey, VK * 4);
@@ -679,7 +680,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     GROW(ctx, ws.counters, cnt_words * 4);
     GROW(ctx, ws.hist, sort_ws_bytes((uint32_t)VK, 32, V));
 
-    if (saved) {
+    if (save) {
         HIPCHK(ctx, hipMemcpyAsync(ws.centres.p, mode == RXGS_MODE_TX ? tx : rx, (size_t)V * 12,
                                    hipMemcpyDeviceToDevice, st));
         HIPCHK(ctx, hipMemcpyAsync(ws.rxpos.p, rx, (size_t)N * 12, hipMemcpyDeviceToDevice, st));
@@ -697,7 +698,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     // (the key kernel also clears the counters and the depth sort's scratch)
     const size_t depth_sort_words = sort_ws_bytes((uint32_t)VK, 32, V) / 4;
     STAGE(ctx, "project",
-          launch_project(sc, ws.centres_p, V, Kp, g, ws, saved != nullptr, cnt_words, depth_sort_words, st));
+          launch_project(sc, ws.centres_p, V, Kp, g, ws, save, cnt_words, depth_sort_words, st));
     int cur = 0;
     STAGE(ctx, "sort_depth",
           sort_pairs_u32(ws.skey, ws.sval, ws.hist, cur, (uint32_t)VK, 32, V, Kp, nullptr, st, true));
@@ -746,7 +747,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     // on those blocks only.  Saved states keep every visible position's
     // radiance (it is exported).
     std::vector<int4> wchunks;
-    if (mode == RXGS_MODE_TX && !saved && ws.use_mlp)
+    if (mode == RXGS_MODE_TX && !save && ws.use_mlp)
         for (int v = 0; v < V; v++)
             if (vnrx[v] >= LAZY_MIN_RX) wchunks.push_back(make_int4(v, 0, 0, -1));
     ws.n_wchunks = (int)wchunks.size();
@@ -922,7 +923,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         if (ws.lazy) STAGE(ctx, "blend_weights", launch_blend_weights(ws, st));
         // the stored Gaussian term: for the backward, or when the pair kernel
         // cannot compute it itself
-        if (saved || !mlp_fused_ok(sc, ctx->mlp)) STAGE(ctx, "mlp_local", launch_mlp_local(sc, ctx->mlp, ws, st));
+        if (save || !mlp_fused_ok(sc, ctx->mlp)) STAGE(ctx, "mlp_local", launch_mlp_local(sc, ctx->mlp, ws, st));
         STAGE(ctx, "mlp_pairs", launch_mlp_pairs(sc, ctx->mlp, ws, st));
     } else {
         STAGE(ctx, "rad_direct", launch_rad_direct(sc, ws, st));
@@ -931,7 +932,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     // stage 3: compositing, then the per-receiver reductions
     if (ws.mpos != 0xFFFFFFFFu)
         HIPCHK(ctx, launch_fill_u32(ws.live.as<uint32_t>(), 0u, (live_count_offset(ws) + 3) / 4, st));
-    STAGE(ctx, "blend_fwd", launch_blend_fwd(ws, C, saved != nullptr, st));
+    STAGE(ctx, "blend_fwd", launch_blend_fwd(ws, C, save, st));
     if (ws.mpos != 0xFFFFFFFFu) {
         // views that composited a position past the prefix: the rest of their
         // radiance, then their recorded terms added, or their blend again
@@ -943,7 +944,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     STAGE(ctx, "reduce", launch_reduce_outputs(ws, power, csum, st));
     ws.scene_version = sc.version;
     ws.mlp_version = ctx->mlp.version;
-    ws.valid = true;
+    ws.valid = !saved || save;
     return RXGS_OK;
 }
 

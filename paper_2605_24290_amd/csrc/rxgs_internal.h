@@ -231,6 +231,9 @@ struct rxgs_ctx {
 struct rxgs_saved {
     rxgs_ctx *ctx = nullptr;
     rxgs::Workspace ws;
+    // false: the object is only a private workspace (a serving slot): renders
+    // into it keep no state for the backward or the exports
+    bool keep = true;
 };
 
 namespace rxgs {

@@ -343,6 +343,7 @@ extern "C" rxgs_status rxgs_server_start(rxgs_ctx *ctx, const rxgs_server_opts *
             rxgs_server_stop(s);
             return RXGS_E_DEVICE;
         }
+        sl.saved->keep = false;   // the slot's private workspace; nothing is kept for a backward
     }
     s->running = true;
     s->worker = std::thread(worker_main, s);
