@@ -227,6 +227,54 @@ __global__ __launch_bounds__(BLOCK) void k_rad_direct_bwd(const float2 *__restri
     atomicAdd(&grad[2 * k + 1], d.y);
 }
 
+// Live virtual items of the MLP backward, listed in index order (a virtual
+// item is live when its receiver range is not empty and its position block
+// holds a nonzero dL/ds).  The MLP backward then gives the item of rank r to
+// wave r mod (waves): the few hundred live items of an RX training step get
+// a wave each, whatever their positions in the item list.  Two launches over
+// chunks of 1024 virtual items: counts per chunk, then each chunk writes its
+// live items after those of the chunks before it.
+__device__ __forceinline__ bool mlp_virt_live(int x, const int4 *__restrict__ items, int n1,
+                                              const int4 *__restrict__ items2, int nsub, int rsub, int64_t Kp,
+                                              const uint8_t *__restrict__ live)
+{
+    const int ii = x / nsub;
+    const int4 it = ii < n1 ? items[ii] : items2[ii - n1];
+    return (x % nsub) * rsub < (it.w & 255) && live[((size_t)it.x * Kp + it.y) / MLP_PAIRS] != 0;
+}
+
+template <bool WRITE>
+__global__ __launch_bounds__(BLOCK) void k_live_list(const int4 *__restrict__ items, int n1,
+                                                     const int4 *__restrict__ items2, const int *__restrict__ count2,
+                                                     int nsub, int64_t Kp, const uint8_t *__restrict__ live,
+                                                     uint32_t *__restrict__ counts, uint32_t *__restrict__ nlist,
+                                                     uint32_t *__restrict__ list)
+{
+    __shared__ uint32_t s_w[4];
+    const int t = threadIdx.x;
+    const int nvirt = (n1 + (items2 ? *count2 : 0)) * nsub, rsub = (MLP_RG + nsub - 1) / nsub;
+    const int x0 = (int)blockIdx.x * 4 * BLOCK + 4 * t;
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+        if (x0 + j < nvirt && mlp_virt_live(x0 + j, items, n1, items2, nsub, rsub, Kp, live)) m |= 1u << j;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan((uint32_t)__builtin_popcount(m), tot, s_w);
+    if (!WRITE) {
+        if (t == 0) counts[blockIdx.x] = tot;
+        return;
+    }
+    uint32_t pre = 0;
+    for (uint32_t g = t; g < blockIdx.x; g += BLOCK) pre += counts[g];
+    uint32_t before;
+    (void)block_exclusive_scan(pre, before, s_w);
+    uint32_t pos = before + ex;
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+        if (m & (1u << j)) list[pos++] = (uint32_t)(x0 + j);
+    if (blockIdx.x == gridDim.x - 1 && t == 0) *nlist = before + tot;
+}
+
 // ----------------------------------------------------------------------------
 // MLP backward, layers 2 and 3, persistent waves.  Per work item (view, 32
 // sorted positions, receivers) and receiver:
@@ -242,8 +290,8 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
     const float *__restrict__ w2b, const float4 *__restrict__ tab, const float *__restrict__ W3,
     const uint32_t *__restrict__ order, const int4 *__restrict__ items, int nitems,
     const int4 *__restrict__ items2, const int *__restrict__ count2, int nsub, int64_t Kp,
-    int64_t K, const uint8_t *__restrict__ live, const float2 *__restrict__ dS, float *__restrict__ dL,
-    float *__restrict__ dG, float *__restrict__ part)
+    int64_t K, const uint8_t *__restrict__ live, const uint32_t *__restrict__ list, const uint32_t *__restrict__ nlist,
+    const float2 *__restrict__ dS, float *__restrict__ dL, float *__restrict__ dG, float *__restrict__ part)
 {
     __shared__ float s_w2a[2 * 32 * 64];
     __shared__ float s_w2b[2 * 32 * 64];
@@ -292,13 +340,18 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
     // nvirt (a bijection: HASH is a prime above any count), so the few live
     // items at the start of every view spread over waves instead of piling
     // onto the same ones when the views' item counts are regular.
+    // With the list of live virtual items, the item of rank r goes to wave
+    // r mod (waves) instead.
     constexpr uint64_t HASH = 2654435761ull;
-    for (int base = gw; base < nvirt; base += 64 * nw) {
+    const int nsrc = list ? (int)*nlist : nvirt;
+    for (int base = gw; base < nsrc; base += 64 * nw) {
     uint64_t todo;
     {
         const int mine = base + lane * nw;
         bool lv = false;
-        if (mine < nvirt) {
+        if (mine < nsrc && list) {
+            lv = true;
+        } else if (mine < nsrc) {
             const int vm = (int)(((uint64_t)mine * HASH) % (uint64_t)nvirt);
             const int ii = vm / nsub;
             const int4 it = ii < n1 ? items[ii] : items2[ii - n1];
@@ -308,7 +361,8 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
         todo = __ballot(lv);
     }
     while (todo) {
-        const int vitem = (int)(((uint64_t)(base + __builtin_ctzll(todo) * nw) * HASH) % (uint64_t)nvirt);
+        const int src = base + __builtin_ctzll(todo) * nw;
+        const int vitem = list ? (int)list[src] : (int)(((uint64_t)src * HASH) % (uint64_t)nvirt);
         todo &= todo - 1;
         const int iv = vitem / nsub;
         const int4 it = iv < n1 ? items[iv] : items2[iv - n1];
@@ -816,13 +870,34 @@ hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *g
     const int nsub = (std::min(ws.R_max, MLP_RG) + MLPB_RSUB - 1) / MLPB_RSUB;
     const int64_t nall = (int64_t)ws.n_items + (far ? ws.n_items_far : 0);
     if (nall > INT32_MAX / std::max(nsub, 1)) return hipErrorInvalidValue;   // virtual item indices are int
+    // the list of live virtual items (in the reduction scratch, first written
+    // after the MLP backward) when every item holds one receiver (views of
+    // one receiver: their live items are few and sit at the start of each
+    // view's items) and there are at most 256 chunks of 1024; items of several
+    // receivers are split into virtual items, which the scattered order
+    // already spreads well (the list's two launches would cost more)
+    const int64_t nvirt_max = nall * std::max(nsub, 1);
+    const int64_t nchunk = (nvirt_max + 4 * BLOCK - 1) / (4 * BLOCK);
+    constexpr size_t LIST_AT = 512;   // u32 words: chunk counts, the list length, then the list
+    const bool ranked = ws.R_max == 1 && nchunk > 0 && nchunk <= BLOCK &&
+                        ws.mred.cap >= (LIST_AT + (size_t)nvirt_max) * 4;
+    uint32_t *lw = ranked ? ws.mred.as<uint32_t>() : nullptr;
+    const int4 *items2 = far ? ws.items_far.as<int4>() : nullptr;
+    const int *count2 = far ? far_count(ws) : nullptr;
+    if (ranked) {
+        hipLaunchKernelGGL(k_live_list<false>, dim3((unsigned)nchunk), dim3(BLOCK), 0, st, ws.items.as<int4>(),
+                           ws.n_items, items2, count2, std::max(nsub, 1), ws.Kp, ws.live.as<uint8_t>(), lw,
+                           lw + BLOCK, lw + LIST_AT);
+        hipLaunchKernelGGL(k_live_list<true>, dim3((unsigned)nchunk), dim3(BLOCK), 0, st, ws.items.as<int4>(),
+                           ws.n_items, items2, count2, std::max(nsub, 1), ws.Kp, ws.live.as<uint8_t>(), lw,
+                           lw + BLOCK, lw + LIST_AT);
+    }
     if (nall > 0)
         hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)(nwaves / 4)), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                            ws.Gp.as<float>(), m.w2a.as<float>(), m.w2b.as<float>(), m.tab.as<float4>(), W3,
-                           ws.vorder.as<uint32_t>(), ws.items.as<int4>(), ws.n_items,
-                           far ? ws.items_far.as<int4>() : nullptr, far ? far_count(ws) : nullptr,
-                           std::max(nsub, 1), ws.Kp,
-                           sc.K, ws.live.as<uint8_t>(), ws.dS.as<float2>(), ws.dL.as<float>(),
+                           ws.vorder.as<uint32_t>(), ws.items.as<int4>(), ws.n_items, items2, count2,
+                           std::max(nsub, 1), ws.Kp, sc.K, ws.live.as<uint8_t>(), ranked ? lw + LIST_AT : nullptr,
+                           ranked ? lw + BLOCK : nullptr, ws.dS.as<float2>(), ws.dL.as<float>(),
                            ws.dG.as<float>(), ws.mpart.as<float>());
     if (gmlp) {
         if (nall > 0) {
