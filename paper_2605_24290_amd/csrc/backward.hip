@@ -815,6 +815,28 @@ __global__ __launch_bounds__(BLOCK) void k_project_bwd(
 // ============================================================================
 static inline unsigned nblk(size_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
+// zeroes up to ZERO_RANGES buffers in one launch (blockIdx.y picks the range)
+__global__ __launch_bounds__(BLOCK) void k_zero_ranges(ZeroRanges z)
+{
+    const int r = blockIdx.y;
+    if (r >= z.n) return;
+    uint32_t *p = z.p[r];
+    const size_t n = z.len[r];
+    for (size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (size_t)gridDim.x * BLOCK) p[i] = 0u;
+}
+
+hipError_t launch_zero_ranges(const ZeroRanges &z, hipStream_t st)
+{
+    if (z.n <= 0) return hipSuccess;
+    if (z.n > ZERO_RANGES) return hipErrorInvalidValue;
+    size_t most = 0;
+    for (int r = 0; r < z.n; r++) most = std::max(most, z.len[r]);
+    if (most == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<size_t>(nblk(most), 4096);
+    hipLaunchKernelGGL(k_zero_ranges, dim3(blocks, (unsigned)z.n), dim3(BLOCK), 0, st, z);
+    return hipGetLastError();
+}
+
 template <int R>
 static hipError_t blend_bwd_launch(Workspace &ws, const float *C, const float *dC, const float *dP, hipStream_t st)
 {

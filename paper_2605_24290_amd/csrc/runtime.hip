@@ -1089,9 +1089,11 @@ extern "C" rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *sav
         size_t n;
     } outs[] = {{gr.means, (size_t)K * 3}, {gr.log_scales, (size_t)K * 3}, {gr.quats, (size_t)K * 4},
                 {gr.logits, (size_t)K},   {ws.use_mlp ? nullptr : gr.radiance, (size_t)K * 2}};
-    for (auto &o : outs)
-        if (o.p) HIPCHK(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(o.p), 0u, o.n, st));
+    // (one launch zeroes the outputs and, below, the backward's accumulators)
+    ZeroRanges zr;
+    for (auto &o : outs) zr.add(o.p, o.n);
     if (ws.N == 0 || K == 0) {
+        HIPCHK(ctx, launch_zero_ranges(zr, st));
         if (ws.use_mlp && gr.features) HIPCHK(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(gr.features), 0u, (size_t)K * FEAT, st));
         if (ws.use_mlp && gr.mlp) HIPCHK(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(gr.mlp), 0u, RXGS_MLP_NPARAM, st));
         return RXGS_OK;
@@ -1099,19 +1101,20 @@ extern "C" rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *sav
     const size_t VK = (size_t)ws.V * ws.Kp;
     GROW(ctx, ws.dS, (size_t)ws.N * ws.Kp * 8);
     GROW(ctx, ws.g2d, VK * 32);
-    HIPCHK(ctx, launch_fill_u32(ws.dS.as<uint32_t>(), 0u, (size_t)ws.N * ws.Kp * 2, st));
-    HIPCHK(ctx, launch_fill_u32(ws.g2d.as<uint32_t>(), 0u, VK * 8, st));
     GROW(ctx, ws.live, VK / MLP_PAIRS + 4);
-    HIPCHK(ctx, launch_fill_u32(ws.live.as<uint32_t>(), 0u, (VK / MLP_PAIRS + 3) / 4, st));
+    zr.add(ws.dS.p, (size_t)ws.N * ws.Kp * 2);
+    zr.add(ws.g2d.p, VK * 8);
+    zr.add(ws.live.p, (VK / MLP_PAIRS + 3) / 4);
     if (ws.use_mlp) {
         GROW(ctx, ws.dL, (size_t)K * HID * 4);
         GROW(ctx, ws.dG, (size_t)ws.N * HID * 4);
         GROW(ctx, ws.mpart, mlp_part_bytes(ws));
         GROW(ctx, ws.w1part, w1b_part_bytes(K));
         GROW(ctx, ws.mred, mlp_red_bytes());
-        HIPCHK(ctx, launch_fill_u32(ws.dL.as<uint32_t>(), 0u, (size_t)K * HID, st));
-        HIPCHK(ctx, launch_fill_u32(ws.dG.as<uint32_t>(), 0u, (size_t)ws.N * HID, st));
+        zr.add(ws.dL.p, (size_t)K * HID);
+        zr.add(ws.dG.p, (size_t)ws.N * HID);
     }
+    HIPCHK(ctx, launch_zero_ranges(zr, st));
     STAGE(ctx, "blend_bwd", launch_blend_bwd(ws, C, dC, dP, st));
     if (ws.use_mlp)
         STAGE(ctx, "mlp_bwd", launch_mlp_bwd(sc, ctx->mlp, ws, gr.features, gr.mlp, st));

@@ -242,6 +242,21 @@ namespace rxgs {
 hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t Kp, const DevGrid &g,
                           Workspace &ws, bool keep_boxes, size_t counter_words, size_t sort_words, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st);
+// zeroes several buffers (u32 words) in one launch (backward.hip)
+constexpr int ZERO_RANGES = 12;
+struct ZeroRanges {
+    uint32_t *p[ZERO_RANGES];
+    size_t len[ZERO_RANGES];
+    int n = 0;
+    void add(void *ptr, size_t words)
+    {
+        if (ptr && words) {
+            p[n] = static_cast<uint32_t *>(ptr);
+            len[n++] = words;
+        }
+    }
+};
+hipError_t launch_zero_ranges(const ZeroRanges &z, hipStream_t st);
 // sort.hip: stable segmented radix sort of (key, value) pairs by the low
 // `bits` key bits; segments of seg_len keys (a multiple of 4096), or given per
 // 4096-key unit by segtab; wsb holds sort_ws_bytes(n, bits, nseg) bytes and
