@@ -267,8 +267,9 @@ __device__ __forceinline__ bool maybe_on_grid(float dxf, float dyf, float dzf, f
 // the Gaussian is too near (FP32 key below 0.2^2 m^2), too faint (opacity
 // below 1/255) or surely off the grid's rows; the emission kernel applies the
 // exact test to the rest.  SAVE: the exact binning boxes, raw keys and
-// opacities are also kept for export.
-template <bool SAVE>
+// opacities are written for export; KEYS = false: only those (a saved
+// state's export, computed when first asked for).
+template <bool SAVE, bool KEYS = true>
 __global__ __launch_bounds__(BLOCK) void k_project(
     const GaussGeoPacked *__restrict__ gg, const float *__restrict__ qcull, int64_t K, int64_t Kp,
     const float *__restrict__ centres, int V, int vchunk, DevGrid g, uint32_t *__restrict__ skey,
@@ -309,8 +310,10 @@ __global__ __launch_bounds__(BLOCK) void k_project(
             kb = __float_as_uint(kf);
             if (!(kf < NEAR2) && po.w >= ALPHA_MIN && maybe_on_grid(dxf, dyf, dzf, kf, qc, g)) key = kb;
         }
-        skey[i] = key;
-        sval[i] = (uint32_t)k;
+        if (KEYS) {
+            skey[i] = key;
+            sval[i] = (uint32_t)k;
+        }
         if (SAVE) {
             ViewGeo P;
             P.e = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1981,6 +1984,19 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st
     if (n == 0) return hipSuccess;
     unsigned blocks = (unsigned)std::min<size_t>(nblk(n), 4096);
     hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(BLOCK), 0, st, p, value, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_exports(Workspace &ws, hipStream_t st)
+{
+    const int V = ws.V;
+    const int vchunk = V <= 4 ? 1 : 4;
+    if (V == 0 || ws.Kp == 0) return hipSuccess;
+    dim3 grid((unsigned)(ws.Kp / BLOCK), (unsigned)((V + vchunk - 1) / vchunk));
+    hipLaunchKernelGGL((k_project<true, false>), grid, dim3(BLOCK), 0, st, ws.ggeo.as<GaussGeoPacked>(),
+                       ws.qcull.as<float>(), ws.K, ws.Kp, ws.centres.as<float>(), V, vchunk, ws.g, nullptr, nullptr,
+                       ws.ext.as<float4>(), ws.rawkey.as<uint32_t>(), ws.opac.as<float>(), nullptr, (size_t)0,
+                       nullptr, (size_t)0);
     return hipGetLastError();
 }
 

@@ -656,12 +656,9 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         GROW(ctx, ws.centres, (size_t)V * 12);
         GROW(ctx, ws.rxpos, (size_t)N * 12);
     }
-    if (save) {
-        // binning boxes, raw keys and opacities, kept for export
-        GROW(ctx, ws.ext, VK * 16);
-        GROW(ctx, ws.rawkey, VK * 4);
-        GROW(ctx, ws.opac, VK * 4);
-    }
+    // (a saved state's binning boxes, raw keys and opacities are computed
+    // when first exported: the backward does not read them)
+    ws.exports_ready = false;
     for (int b = 0; b < 2; b++) {
         GROW(ctx, ws.skey[b], VK * 4);
         GROW(ctx, ws.sval[b], VK * 4);
@@ -698,7 +695,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     // (the key kernel also clears the counters and the depth sort's scratch)
     const size_t depth_sort_words = sort_ws_bytes((uint32_t)VK, 32, V) / 4;
     STAGE(ctx, "project",
-          launch_project(sc, ws.centres_p, V, Kp, g, ws, save, cnt_words, depth_sort_words, st));
+          launch_project(sc, ws.centres_p, V, Kp, g, ws, false, cnt_words, depth_sort_words, st));
     int cur = 0;
     STAGE(ctx, "sort_depth",
           sort_pairs_u32(ws.skey, ws.sval, ws.hist, cur, (uint32_t)VK, 32, V, Kp, nullptr, st, true));
@@ -1162,6 +1159,20 @@ extern "C" rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *ds
     if (!ws.valid) return fail(ctx, RXGS_E_STATE, "no forward state");
     const size_t VK = (size_t)ws.V * ws.Kp;
     const size_t P = (size_t)ws.g.H * ws.g.W;
+    if ((what == RXGS_EXPORT_BIN || what == RXGS_EXPORT_KEYS || what == RXGS_EXPORT_OPACITY) && !ws.exports_ready) {
+        // computed from the saved view centres and the scene's projection
+        // terms (a cached part of the state, hence the cast)
+        if (ws.scene_version != ctx->scene.version)
+            return fail(ctx, RXGS_E_STATE, "scene changed since the forward");
+        Workspace &w = const_cast<Workspace &>(ws);
+        DeviceScope ds0(ctx->device);
+        GROW(ctx, w.ext, VK * 16);
+        GROW(ctx, w.rawkey, VK * 4);
+        GROW(ctx, w.opac, VK * 4);
+        HIPCHK(ctx, hipDeviceSynchronize());   // the render, on the caller's stream
+        HIPCHK(ctx, launch_project_exports(w, nullptr));
+        w.exports_ready = true;
+    }
     const void *src = nullptr;
     size_t n = 0;
     std::vector<int> tmp;

@@ -172,6 +172,7 @@ struct Workspace {
     DevBuf frec, fcnt, ftile;   // composited entries past the prefix: records, counts, tile marks
     int n_items_far = 0; // their largest possible number
     bool rad_complete = true;   // every visible position's radiance is evaluated
+    bool exports_ready = false; // binning boxes, raw keys and opacities computed (saved states, on export)
     DevBuf vflag;        // per view bits: 1 entries cut, 2 a pixel open after a cut, 4 composited past the prefix
     int n_wchunks = 0;   // weights-pass chunks: one per view with receivers
     int4 *d_wchunks = nullptr;
@@ -242,6 +243,8 @@ namespace rxgs {
 hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t Kp, const DevGrid &g,
                           Workspace &ws, bool keep_boxes, size_t counter_words, size_t sort_words, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st);
+// a saved state's binning boxes, raw keys and opacities, from its own centres
+hipError_t launch_project_exports(Workspace &ws, hipStream_t st);
 // zeroes several buffers (u32 words) in one launch (backward.hip)
 constexpr int ZERO_RANGES = 12;
 struct ZeroRanges {
