@@ -296,3 +296,37 @@ def test_invalid_arguments_raise():
     with pytest.raises(rxgs.RxgsError):
         r.upload_scene(bad, wl.scene.log_scales, wl.scene.quats, wl.scene.logits, radiance=wl.scene.radiance)
     r.close()
+
+
+def test_saved_binning_exports_on_demand():
+    """A saved state's binning boxes, raw keys and opacities are computed on
+    their first export (from the saved view centres): equal on repeated
+    exports and equal to those of a second saved render of the same batch;
+    refused once the scene has changed before that first export."""
+    from paper_2605_24290_amd import rxgs
+    wl = _wl("c0", K=300, N=3)
+    r = renderer_for(wl)
+    s1, s2 = rxgs.Saved(r), rxgs.Saved(r)
+    r.render(wl.rx, tx=wl.tx, mode="rx", saved=s1)
+    r.render(wl.rx, tx=wl.tx, mode="rx", saved=s2)
+    info = s1.info()
+    V, Kp = info["V"], info["K_pad"]
+    k1 = s1.export(rxgs.EXPORT_KEYS, np.uint32, (V, Kp))
+    b1 = s1.export(rxgs.EXPORT_BIN, np.float32, (V, Kp, 4))
+    assert np.array_equal(k1, s1.export(rxgs.EXPORT_KEYS, np.uint32, (V, Kp)))
+    assert np.array_equal(k1, s2.export(rxgs.EXPORT_KEYS, np.uint32, (V, Kp)))
+    assert np.array_equal(b1, s2.export(rxgs.EXPORT_BIN, np.float32, (V, Kp, 4)))
+    assert np.array_equal(s1.export(rxgs.EXPORT_OPACITY, np.float32, (V, Kp)),
+                          s2.export(rxgs.EXPORT_OPACITY, np.float32, (V, Kp)))
+    # keys of real Gaussians are their FP32 squared distances (bit patterns)
+    K = wl.scene.K
+    assert np.isfinite(k1[:, :K].view(np.float32)).all()
+    s3 = rxgs.Saved(r)
+    r.render(wl.rx, tx=wl.tx, mode="rx", saved=s3)
+    sc = wl.scene
+    r.upload_scene(sc.means, sc.log_scales, sc.quats, sc.logits, radiance=sc.radiance)
+    with pytest.raises(rxgs.RxgsError):
+        s3.export(rxgs.EXPORT_BIN, np.float32, (V, Kp, 4))
+    for s in (s1, s2, s3):
+        s.close()
+    r.close()
