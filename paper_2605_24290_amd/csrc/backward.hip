@@ -825,6 +825,32 @@ __global__ __launch_bounds__(BLOCK) void k_zero_ranges(ZeroRanges z)
     for (size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (size_t)gridDim.x * BLOCK) p[i] = 0u;
 }
 
+// zeroes, per segment y (a view, or a receiver and its view), the words of
+// the view's visible positions only: [0, visible(view) x wpr) of the
+// segment's Kp x wpr words (nothing reads the rest)
+__global__ __launch_bounds__(BLOCK) void k_zero_visible(uint32_t *__restrict__ p, int64_t Kp, int wpr,
+                                                        const unsigned long long *__restrict__ counters,
+                                                        const int *__restrict__ segview, int nseg)
+{
+    const int y = blockIdx.y;
+    if (y >= nseg) return;
+    const int v = segview ? segview[y] : y;
+    const size_t n = (size_t)min((int64_t)counters[2 * (size_t)v], Kp) * (size_t)wpr;
+    uint32_t *base = p + (size_t)y * (size_t)Kp * (size_t)wpr;
+    for (size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (size_t)gridDim.x * BLOCK) base[i] = 0u;
+}
+
+hipError_t launch_zero_visible(uint32_t *p, int64_t Kp, int wpr, const unsigned long long *counters,
+                               const int *segview, int nseg, hipStream_t st)
+{
+    if (nseg <= 0 || Kp <= 0) return hipSuccess;
+    if (nseg > 65535) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)std::min<size_t>(nblk((size_t)Kp * (size_t)wpr), 1024);
+    hipLaunchKernelGGL(k_zero_visible, dim3(blocks, (unsigned)nseg), dim3(BLOCK), 0, st, p, Kp, wpr, counters,
+                       segview, nseg);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero_ranges(const ZeroRanges &z, hipStream_t st)
 {
     if (z.n <= 0) return hipSuccess;

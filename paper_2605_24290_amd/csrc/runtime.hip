@@ -1099,8 +1099,17 @@ extern "C" rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *sav
     GROW(ctx, ws.dS, (size_t)ws.N * ws.Kp * 8);
     GROW(ctx, ws.g2d, VK * 32);
     GROW(ctx, ws.live, VK / MLP_PAIRS + 4);
-    zr.add(ws.dS.p, (size_t)ws.N * ws.Kp * 2);
-    zr.add(ws.g2d.p, VK * 8);
+    // dL/ds and the 2-D record gradients are written and read at visible
+    // positions only; when they are large, only those are cleared
+    const bool rows = VK * 32 > ((size_t)256 << 20) && ws.N <= 65535 && ws.V <= 65535;
+    if (rows) {
+        const unsigned long long *cnt = ws.counters.as<unsigned long long>();
+        HIPCHK(ctx, launch_zero_visible(ws.dS.as<uint32_t>(), ws.Kp, 2, cnt, ws.d_rxview, ws.N, st));
+        HIPCHK(ctx, launch_zero_visible(ws.g2d.as<uint32_t>(), ws.Kp, 8, cnt, nullptr, ws.V, st));
+    } else {
+        zr.add(ws.dS.p, (size_t)ws.N * ws.Kp * 2);
+        zr.add(ws.g2d.p, VK * 8);
+    }
     zr.add(ws.live.p, (VK / MLP_PAIRS + 3) / 4);
     if (ws.use_mlp) {
         GROW(ctx, ws.dL, (size_t)K * HID * 4);

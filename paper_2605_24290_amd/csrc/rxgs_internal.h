@@ -260,6 +260,10 @@ struct ZeroRanges {
     }
 };
 hipError_t launch_zero_ranges(const ZeroRanges &z, hipStream_t st);
+// zeroes the visible positions' words of per-view (segview NULL) or
+// per-receiver (segview: receiver -> view) rows of Kp x wpr words (backward.hip)
+hipError_t launch_zero_visible(uint32_t *p, int64_t Kp, int wpr, const unsigned long long *counters,
+                               const int *segview, int nseg, hipStream_t st);
 // sort.hip: stable segmented radix sort of (key, value) pairs by the low
 // `bits` key bits; segments of seg_len keys (a multiple of 4096), or given per
 // 4096-key unit by segtab; wsb holds sort_ws_bytes(n, bits, nseg) bytes and
