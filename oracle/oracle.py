@@ -54,7 +54,7 @@ def lib():
         i32p = ctypes.POINTER(ctypes.c_int32)
         ci, cd = ctypes.c_int, ctypes.c_double
         L.orc_render.argtypes = [ci, dp, dp, dp, dp, dp, dp, dp, ci, dp, ci, dp, ip, ci, ci, cd, cd, ci,
-                                 dp, dp, ip, dp, dp, dp, u64p]
+                                 dp, dp, ip, dp, dp, dp, u64p, ip]
         L.orc_render.restype = ci
         L.orc_project.argtypes = [ci, dp, dp, dp, dp, ci, dp, ci, ci, cd, cd, up, ip, dp]
         L.orc_project.restype = ci
@@ -127,8 +127,9 @@ def _scene_args(scene, mlp):
 
 
 def render(scene, grid, centres, rx, rx_view, mlp=None, nthreads=None, want_hash=False):
-    """Forward render.  Returns a dict with C (N,2,H,W), T_final and ncomp
-    (N,H,W), margin (N,H,W), power (N), csum (N,2) and optionally rowhash (N,H)."""
+    """Forward render.  Returns a dict with C (N,2,H,W), T_final, ncomp and
+    nclamp (clamped composited entries) (N,H,W), margin (N,H,W), power (N),
+    csum (N,2) and optionally rowhash (N,H)."""
     L = lib()
     keep, ptrs = _scene_args(scene, mlp)
     cen, pc = _d(np.asarray(centres).reshape(-1, 3))
@@ -139,6 +140,7 @@ def render(scene, grid, centres, rx, rx_view, mlp=None, nthreads=None, want_hash
     C = np.zeros((N, 2, H, W))
     T = np.zeros((N, H, W))
     nc = np.zeros((N, H, W), dtype=np.int32)
+    ncl = np.zeros((N, H, W), dtype=np.int32)
     mg = np.zeros((N, H, W))
     pw = np.zeros(N)
     cs = np.zeros((N, 2))
@@ -147,11 +149,11 @@ def render(scene, grid, centres, rx, rx_view, mlp=None, nthreads=None, want_hash
     rc = L.orc_render(K, *ptrs, V, pc, N, prx, _ptr(rv, ctypes.c_int), H, W, grid.el0, grid.del_el, nt,
                       _ptr(C, ctypes.c_double), _ptr(T, ctypes.c_double), _ptr(nc, ctypes.c_int),
                       _ptr(mg, ctypes.c_double), _ptr(pw, ctypes.c_double), _ptr(cs, ctypes.c_double),
-                      _ptr(rh, ctypes.c_uint64))
+                      _ptr(rh, ctypes.c_uint64), _ptr(ncl, ctypes.c_int))
     if rc != 0:
         raise RuntimeError(f"orc_render failed ({rc})")
     del keep
-    out = dict(C=C, T_final=T, ncomp=nc, margin=mg, power=pw, csum=cs)
+    out = dict(C=C, T_final=T, ncomp=nc, nclamp=ncl, margin=mg, power=pw, csum=cs)
     if want_hash:
         out["rowhash"] = rh
     return out

@@ -373,13 +373,13 @@ typedef struct { int k; double T, w, G, du, dv; int clamped; } entry_t;
 /* Composite one pixel.  Returns the number of composited entries; fills C,
  * T_final, the decision margin and (optionally) the entry list. */
 static int composite_pixel(const scene_t *s, int j, int row, int col, double *C, double *Tfin,
-                           double *margin, entry_t *ent, uint64_t *hash)
+                           double *margin, entry_t *ent, uint64_t *hash, int *nclamp)
 {
     const view_t *vw = &s->views[s->rx_view[j]];
     const double W = s->g.W, halfW = 0.5 * s->g.W;
     const double *rad = s->rad + (size_t)j * s->K * 2;
     double T = 1.0, cr = 0.0, ci = 0.0, marg = INFINITY;
-    int n = 0;
+    int n = 0, ncl = 0;
     for (int idx = 0; idx < vw->n; idx++) {
         int k = vw->order[idx];
         const double *pv = vw->pv + (size_t)k * NPROJ;
@@ -413,6 +413,7 @@ static int composite_pixel(const scene_t *s, int j, int row, int col, double *C,
             h *= 1099511628211ULL;
             *hash = h;
         }
+        ncl += ow >= ORC_W_MAX;
         cr += T * w * rad[2 * k + 0];
         ci += T * w * rad[2 * k + 1];
         T = T * (1.0 - w);
@@ -423,6 +424,7 @@ static int composite_pixel(const scene_t *s, int j, int row, int col, double *C,
     }
     C[0] = cr; C[1] = ci; *Tfin = T;
     if (margin) *margin = marg;
+    if (nclamp) *nclamp = ncl;
     return n;
 }
 
@@ -431,6 +433,7 @@ typedef struct {
     double *C, *Tfin, *margin;
     int *ncomp;
     uint64_t *rowhash;
+    int *nclamp;
 } render_ctx;
 
 static void render_item(void *vctx, long item, int tid)
@@ -445,7 +448,9 @@ static void render_item(void *vctx, long item, int tid)
         size_t p = (size_t)row * W + col;
         size_t P = (size_t)H * W;
         double C[2], T, m;
-        int n = composite_pixel(s, j, row, col, C, &T, &m, NULL, r->rowhash ? &h : NULL);
+        int ncl = 0;
+        int n = composite_pixel(s, j, row, col, C, &T, &m, NULL, r->rowhash ? &h : NULL, &ncl);
+        if (r->nclamp) r->nclamp[(size_t)j * P + p] = ncl;
         r->C[((size_t)j * 2 + 0) * P + p] = C[0];
         r->C[((size_t)j * 2 + 1) * P + p] = C[1];
         if (r->Tfin) r->Tfin[(size_t)j * P + p] = T;
@@ -463,7 +468,8 @@ static void render_item(void *vctx, long item, int tid)
  * W1 64x68, b1, W2 64x64, b2, W3 2x64, b3);  centres V x 3 view points;
  * rx N x 3 receiver positions (MLP input); rx_view N view index per receiver.
  * Outputs: C N x 2 x H x W; optional T_final / ncomp / margin N x H x W;
- * power N; csum N x 2; rowhash N x H decision fingerprints (optional).
+ * power N; csum N x 2; rowhash N x H decision fingerprints (optional);
+ * nclamp N x H x W composited entries whose weight was clamped (optional).
  * Returns 0 on success.
  */
 int orc_render(int K, const double *means, const double *log_scales, const double *quats,
@@ -471,7 +477,7 @@ int orc_render(int K, const double *means, const double *log_scales, const doubl
                const double *mlp, int V, const double *centres, int N, const double *rx,
                const int *rx_view, int H, int W, double el0, double del, int nthreads,
                double *C, double *T_final, int *ncomp, double *margin, double *power,
-               double *csum, uint64_t *rowhash)
+               double *csum, uint64_t *rowhash, int *nclamp)
 {
     if (K < 0 || V < 1 || N < 0 || H < 1 || W < 1) return -1;
     if (!radiance && (!features || !mlp)) return -1;
@@ -483,7 +489,7 @@ int orc_render(int K, const double *means, const double *log_scales, const doubl
     s.radiance = radiance; s.features = features; s.mlp = mlp; s.centres = centres;
     s.rx = rx; s.rx_view = rx_view; s.g = mkgrid(H, W, el0, del);
     if (scene_setup(&s, nthreads)) return -2;
-    render_ctx r = { &s, C, T_final, margin, ncomp, rowhash };
+    render_ctx r = { &s, C, T_final, margin, ncomp, rowhash, nclamp };
     pool_run(nthreads, (long)N * H, render_item, &r);
     size_t P = (size_t)H * W;
     for (int j = 0; j < N; j++) {
@@ -576,7 +582,7 @@ static void bwd_item(void *vctx, long item, int tid)
     for (int col = 0; col < W; col++) {
         size_t p = (size_t)row * W + col;
         double C[2], T;
-        int n = composite_pixel(s, j, row, col, C, &T, NULL, ent, NULL);
+        int n = composite_pixel(s, j, row, col, C, &T, NULL, ent, NULL, NULL);
         double gp0 = b->dC[((size_t)j * 2) * P + p], gp1 = b->dC[((size_t)j * 2 + 1) * P + p];
         if (b->dP) { gp0 += 2.0 * b->dP[j] * C[0]; gp1 += 2.0 * b->dP[j] * C[1]; }
         double A0 = 0.0, A1 = 0.0;   /* sum over later entries of T_m w_m s_m */

@@ -1,0 +1,137 @@
+"""GPU parity on the two discrete rules of Alg. 1 stage 3 that random scenes
+rarely reach: the stop rule (break once T < 1e-4, after compositing the
+Gaussian that crosses it) and the weight clamp w = min(0.99, o exp(-q/2))
+with no gradient through a clamped weight.
+
+The closed-form stacks of ``stack_scenes`` pin the GPU directly; thick random
+scenes with a tenth of the opacity logits at +6 (o = 0.9975, clamped near
+their centres) check spectra and every gradient against the oracle, with the
+oracle's counts of clamped entries and terminated pixels asserted non-zero.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2605_24290_amd import scenes as S
+
+from . import stack_scenes as SS
+from .parity import compare_spectra, gpu, needs_gpu, renderer_for
+from .test_gpu_backward import FIELDS_DIRECT, FIELDS_MLP, _compare
+
+pytestmark = [gpu, needs_gpu]
+
+GRID = S.Grid(18, 36, -math.pi / 2, math.pi / 18)
+
+
+def _render_saved(sc, centre, mode):
+    import torch
+    from paper_2605_24290_amd import rxgs
+    wl = S.Workload(S.Scene(*[None if a is None else np.asarray(a, np.float32) for a in
+                              (sc.means, sc.log_scales, sc.quats, sc.logits, sc.radiance, sc.features)]),
+                    np.asarray(centre, np.float32)[None], np.asarray(centre, np.float32)[None], GRID)
+    r = renderer_for(wl)
+    saved = rxgs.Saved(r)
+    C, P, _ = r.render(wl.rx, tx=wl.tx, mode=mode, saved=saved)
+    torch.cuda.synchronize()
+    return r, saved, wl, C
+
+
+@pytest.mark.parametrize("mode", ["tx", "rx"])
+@pytest.mark.parametrize("o", [0.8, 0.6])
+def test_stop_rule_stack(mode, o):
+    from paper_2605_24290_amd import rxgs
+    row, col = 11, 5
+    centre = np.array([0.3, -0.2, 0.1])
+    m = 14
+    rad = np.stack([1.0 + np.arange(m), 0.5 - 0.1 * np.arange(m) ** 2], axis=1)
+    logit = math.log(o / (1.0 - o))
+    sc = SS.stack(GRID, row, col, centre, 1.0 + 0.15 * np.arange(m), [logit] * m, 0.03, rad,
+                  dtype=np.float32)
+    r, saved, wl, C = _render_saved(sc, centre, mode)
+    o32 = SS.sigmoid(float(np.float32(logit)))
+    n_star = SS.stop_index(o32)
+    C_exp, T_exp = SS.closed_form(o32, rad.astype(np.float32), n_star)
+    Cg = C.cpu().numpy()[0, :, row, col].astype(np.float64)
+    assert np.abs(Cg - C_exp).max() <= 1e-5 * np.abs(C_exp).max()
+    T = saved.export(rxgs.EXPORT_TFINAL, np.float32, (1, GRID.H, GRID.W))[0, row, col]
+    nl = saved.export(rxgs.EXPORT_NLAST, np.int32, (1, GRID.H, GRID.W))[0, row, col]
+    assert abs(T - T_exp) <= 1e-5 * T_exp and T < 1e-4
+    assert nl == n_star   # every entry of the pixel's tile list is one of the stack
+    ora = O.render(wl.scene, GRID, centre[None], centre[None], [0])
+    compare_spectra(C.cpu().numpy(), ora)
+    saved.close()
+    r.close()
+
+
+def test_clamp_stack_forward_and_gradient():
+    """The clamped Gaussian of a two-Gaussian stack: C = 0.99 s1 + 0.01 w2 s2
+    at the pixel; with dL/dC at that pixel only, its geometry and logit get
+    exactly zero gradient on the GPU, as in the oracle."""
+    import torch
+    row, col = 8, 20
+    centre = np.array([-0.4, 0.25, 0.0])
+    s1, s2 = np.array([0.7, -0.4]), np.array([-1.1, 0.3])
+    o2 = 0.8
+    sc = SS.stack(GRID, row, col, centre, [1.5, 2.0], [6.0, math.log(o2 / (1 - o2))], 0.03, [s1, s2],
+                  dtype=np.float32)
+    for mode in ("tx", "rx"):
+        r, saved, wl, C = _render_saved(sc, centre, mode)
+        o2f = SS.sigmoid(float(np.float32(math.log(o2 / (1 - o2)))))
+        exp = 0.99 * s1.astype(np.float32) + 0.01 * o2f * s2.astype(np.float32)
+        assert np.abs(C.cpu().numpy()[0, :, row, col] - exp).max() <= 1e-5
+        dC = np.zeros((1, 2, GRID.H, GRID.W), np.float32)
+        dC[0, 0, row, col] = 1.0
+        dC[0, 1, row, col] = 0.5
+        g = r.backward(saved, C, torch.as_tensor(dC, device=C.device))
+        torch.cuda.synchronize()
+        gg = {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
+        for f in ("means", "log_scales", "quats", "logits"):
+            assert np.abs(gg[f][0]).max() == 0.0, (mode, f, gg[f][0])
+        go = O.backward(wl.scene, GRID, centre[None], centre[None], [0], dC.astype(np.float64))
+        _compare(gg, go, FIELDS_DIRECT)
+        saved.close()
+        r.close()
+
+
+def _thick(use_mlp, seed):
+    wl = S.make_workload(S.Preset("thick", 3000, 4, (3.0, 3.0, 2.0), -1.5, 0.3, S.GRID_90x180, use_mlp),
+                         seed=seed, grid=S.Grid(45, 90, -math.pi / 2, math.pi / 45))
+    rng = np.random.default_rng(seed)
+    idx = rng.choice(wl.scene.K, wl.scene.K // 10, replace=False)
+    wl.scene.logits[idx] = np.float32(6.0)
+    return wl
+
+
+@pytest.mark.parametrize("mode", ["tx", "rx"])
+@pytest.mark.parametrize("use_mlp", [False, True])
+def test_thick_scene_with_clamped_and_terminated_pixels(mode, use_mlp):
+    """3,000 Gaussians in a 3 x 3 x 2 m box (most rays stop at T < 1e-4), a
+    tenth of them with logit +6: spectra, power and every gradient against
+    the oracle."""
+    import torch
+    from paper_2605_24290_amd import rxgs
+    wl = _thick(use_mlp, 91 + use_mlp)
+    cen, rv = O.views_for(mode, wl.tx, wl.rx)
+    ora = O.render(wl.scene, wl.grid, cen, wl.rx, rv, mlp=wl.mlp)
+    n_clamp = int(ora["nclamp"].sum())
+    n_term = int((ora["T_final"] < 1e-4).sum())
+    print(f"[decisions] clamped composited entries {n_clamp}, terminated pixels {n_term} of {ora['T_final'].size}")
+    assert n_clamp > 0 and n_term > 0
+    r = renderer_for(wl)
+    saved = rxgs.Saved(r)
+    C, P, _ = r.render(wl.rx, tx=wl.tx, mode=mode, saved=saved)
+    torch.cuda.synchronize()
+    compare_spectra(C.cpu().numpy(), ora)
+    assert np.abs(P.cpu().numpy() - ora["power"]).max() <= 1e-4 * np.abs(ora["power"]).max()
+    rng = np.random.default_rng(3)
+    dC = rng.normal(size=C.shape).astype(np.float32)
+    dP = rng.normal(size=P.shape).astype(np.float32)
+    g = r.backward(saved, C, torch.as_tensor(dC, device=C.device), torch.as_tensor(dP, device=C.device))
+    torch.cuda.synchronize()
+    gg = {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
+    go = O.backward(wl.scene, wl.grid, cen, wl.rx, rv, dC, dP, mlp=wl.mlp)
+    _compare(gg, go, FIELDS_MLP if use_mlp else FIELDS_DIRECT)
+    saved.close()
+    r.close()

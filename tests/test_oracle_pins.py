@@ -499,3 +499,112 @@ def test_table4_hyperparameters_fixture():
     assert S.HIDDEN == t4["mlp_hidden"]
     assert (S.GRID_90x360.W, S.GRID_90x360.H) == tuple(t4["ray_directions_phi_theta"])
     assert abs(S.GRID_90x360.del_az - 2 * math.pi / t4["ray_directions_phi_theta"][0]) < 1e-15
+
+
+# ---------------------------------------------------------------- Pin-4: the stop rule (R5)
+@pytest.mark.parametrize("o,expect_n", [(0.8, 6), (0.6, 11)])
+def test_stop_rule_includes_the_crossing_gaussian(oracle_lib, o, expect_n):
+    """m equal-opacity Gaussians stacked on the ray of one pixel centre (q = 0
+    there, so every weight is o): Alg. 1 composites in order, updates T and
+    breaks once T < 1e-4, the Gaussian that crosses the threshold included.
+    Closed form at that pixel: n* = the first n with (1 - o)^n < 1e-4,
+    C = sum_{i < n*} o (1 - o)^i s_i, T_final = (1 - o)^n*.  Breaking before
+    the crossing Gaussian (n* - 1 terms) or never breaking (m terms) fails."""
+    from tests import stack_scenes as SS
+    grid = S.Grid(18, 36, -math.pi / 2, math.pi / 18)
+    row, col = 11, 5
+    centre = np.array([0.3, -0.2, 0.1])
+    m = 14
+    rad = np.stack([1.0 + np.arange(m), 0.5 - 0.1 * np.arange(m) ** 2], axis=1)
+    logit = math.log(o / (1.0 - o))
+    sc = SS.stack(grid, row, col, centre, 1.0 + 0.15 * np.arange(m), [logit] * m, 0.03, rad)
+    n_star = SS.stop_index(SS.sigmoid(logit))
+    assert n_star == expect_n
+    out = O.render(sc, grid, centre[None], np.zeros((1, 3)), [0])
+    C_exp, T_exp = SS.closed_form(SS.sigmoid(logit), rad, n_star)
+    assert out["ncomp"][0, row, col] == n_star
+    assert abs(out["T_final"][0, row, col] - T_exp) <= 1e-12 * T_exp
+    assert out["T_final"][0, row, col] < 1e-4
+    assert np.abs(out["C"][0, :, row, col] - C_exp).max() < 1e-12
+    # the off-by-one readings give values far from the oracle's
+    C_early, _ = SS.closed_form(SS.sigmoid(logit), rad, n_star - 1)
+    C_all, _ = SS.closed_form(SS.sigmoid(logit), rad, m)
+    assert np.abs(C_early - C_exp).max() > 1e-6 and np.abs(C_all - C_exp).max() > 1e-6
+    # Gaussians behind the stop do not matter at that pixel (bit-identical),
+    # but they do at pixels whose transmittance stays above the threshold
+    rad2 = rad.copy()
+    rad2[n_star:] *= -3.0
+    sc2 = SS.stack(grid, row, col, centre, 1.0 + 0.15 * np.arange(m), [logit] * m, 0.03, rad2)
+    out2 = O.render(sc2, grid, centre[None], np.zeros((1, 3)), [0])
+    assert np.array_equal(out2["C"][0, :, row, col], out["C"][0, :, row, col])
+    open_px = (out["T_final"][0] >= 1e-4) & (out["ncomp"][0] > n_star)
+    assert open_px.any()
+    assert not np.array_equal(out2["C"][0][:, open_px], out["C"][0][:, open_px])
+    # T is non-increasing along the list: every pixel's T_final <= 1 and a
+    # pixel that composited nothing keeps T = 1
+    assert ((out["ncomp"][0] == 0) == (out["T_final"][0] == 1.0)).all()
+
+
+# ---------------------------------------------------------------- the clamp (R7)
+def test_clamp_caps_the_weight_and_stops_its_gradient(oracle_lib):
+    """A Gaussian with logit 6 (o = 0.9975) on a pixel's ray: at that pixel
+    w = min(0.99, o) = 0.99, so C = 0.99 s and a second Gaussian behind it
+    adds 0.01 w2 s2.  While clamped, the weight does not depend on the
+    opacity or the footprint: with dL/dC non-zero at that pixel only, the
+    gradients of the clamped Gaussian's geometry and logit are exactly 0, and
+    FP64 central differences (the pixel stays clamped under +-1e-6) give 0
+    too.  At a neighbouring pixel the weight o exp(-q/2) is below 0.99 and
+    its logit gradient is s o (1 - o) exp(-q/2), matched by central
+    differences."""
+    from tests import stack_scenes as SS
+    grid = S.Grid(18, 36, -math.pi / 2, math.pi / 18)
+    row, col = 8, 20
+    centre = np.array([-0.4, 0.25, 0.0])
+    s1, s2 = np.array([0.7, -0.4]), np.array([-1.1, 0.3])
+    o2 = 0.8
+    sc = SS.stack(grid, row, col, centre, [1.5, 2.0], [6.0, math.log(o2 / (1 - o2))], 0.03, [s1, s2])
+    out = O.render(sc, grid, centre[None], np.zeros((1, 3)), [0])
+    assert SS.sigmoid(6.0) > 0.99
+    assert out["nclamp"][0, row, col] == 1
+    assert np.abs(out["C"][0, :, row, col] - (0.99 * s1 + 0.01 * o2 * s2)).max() < 1e-12
+    assert abs(out["T_final"][0, row, col] - 0.01 * (1 - o2)) < 1e-14
+    # the clamped Gaussian alone: neighbouring pixels hold o exp(-q/2) s
+    one = SS.stack(grid, row, col, centre, [1.5], [6.0], 0.03, [s1])
+    o1 = O.render(one, grid, centre[None], np.zeros((1, 3)), [0])
+    assert np.abs(o1["C"][0, :, row, col] - 0.99 * s1).max() < 1e-12
+    _, _, pr = O.project(one, grid, centre[None])
+    a = pr[0, 0, 2]
+    w_nb = SS.sigmoid(6.0) * math.exp(-0.5 * a)      # du = 1, dv = 0
+    assert 1.0 / 255.0 < w_nb < 0.99
+    assert np.abs(o1["C"][0, :, row, col + 1] - w_nb * s1).max() < 1e-12
+    assert o1["nclamp"][0, row, col + 1] == 0
+
+    def grads_and_fd(pix):
+        dC = np.zeros((1, 2, grid.H, grid.W))
+        dC[0, 0][pix] = 1.0
+        dC[0, 1][pix] = 0.5
+        g = O.backward(one, grid, centre[None], np.zeros((1, 3)), [0], dC)
+        fds = {}
+        for f, idx in (("logits", 0), ("means", 1), ("log_scales", 2)):
+            vals = []
+            for sgn in (1, -1):
+                arr = getattr(one, f).copy().ravel()
+                arr[idx] += sgn * 1e-6
+                sc2 = S.Scene(**{**one.__dict__, f: arr.reshape(getattr(one, f).shape)})
+                vals.append(float((dC * O.render(sc2, grid, centre[None], np.zeros((1, 3)), [0])["C"]).sum()))
+            fds[f] = ((vals[0] - vals[1]) / 2e-6, g[f].ravel()[idx])
+        return g, fds
+
+    g, fds = grads_and_fd((row, col))
+    for f in ("means", "log_scales", "quats", "logits"):
+        assert np.abs(g[f]).max() == 0.0, f
+    for f, (fd, gv) in fds.items():
+        assert abs(fd) < 1e-9 and gv == 0.0, (f, fd, gv)
+    assert np.abs(g["radiance"][0] - 0.99 * np.array([1.0, 0.5])).max() < 1e-12
+    g, fds = grads_and_fd((row, col + 1))
+    o = SS.sigmoid(6.0)
+    expect = (s1[0] * 1.0 + s1[1] * 0.5) * o * (1 - o) * math.exp(-0.5 * a)
+    assert abs(g["logits"][0] - expect) < 1e-12
+    for f, (fd, gv) in fds.items():
+        assert abs(fd - gv) <= 1e-6 * abs(gv) + 1e-9, (f, fd, gv)
+    assert abs(fds["means"][1]) > 1e-6
