@@ -20,6 +20,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "rxgs_oracle.c")
+SRCS = [SRC, os.path.join(HERE, "rxcond_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 TILE_W = 16
@@ -33,7 +34,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (FP64, no FMA contraction)."""
     if force or not os.path.exists(LIB):
         cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-ffp-contract=off",
-               "-fno-fast-math", "-o", LIB + ".tmp", SRC, "-lm", "-lpthread"]
+               "-fno-fast-math", "-o", LIB + ".tmp", *SRCS, "-lm", "-lpthread"]
         subprocess.run(cmd, check=True)
         os.replace(LIB + ".tmp", LIB)
     return LIB
@@ -42,7 +43,7 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(f) for f in SRCS):
             build()
         L = ctypes.CDLL(LIB)
         dp = ctypes.POINTER(ctypes.c_double)
@@ -67,6 +68,18 @@ def lib():
         L.orc_backward.restype = ci
         L.orc_bin.argtypes = [ci, ci, fp, fp, fp, fp, fp, up, ci, ci, ci, ci, i64p, i32p, ctypes.c_int64]
         L.orc_bin.restype = ctypes.c_int64
+        L.orc_render_rad.argtypes = [ci, dp, dp, dp, dp, dp, ci, dp, ci, ip, ci, ci, cd, cd, ci,
+                                     dp, dp, ip, dp, dp, dp, u64p, ip]
+        L.orc_render_rad.restype = ci
+        L.orc_basis.argtypes = [ci, ci, cd, cd, cd, dp]
+        L.orc_basis.restype = ci
+        L.orc_occupancy.argtypes = [ci, dp, dp, dp, ci, ci, dp, dp, dp]
+        L.orc_occupancy.restype = ci
+        L.orc_rxcond_param_count.argtypes = [ci, ci, ci, ci]
+        L.orc_rxcond_param_count.restype = ctypes.c_long
+        L.orc_rxcond_radiance.argtypes = [ci, ci, ci, ci, ci, ci, ci, dp, dp, dp, ci, dp, ci, dp, ip, ci, dp, dp,
+                                          dp, ci, dp, dp]
+        L.orc_rxcond_radiance.restype = ci
         _lib = L
     return _lib
 
@@ -248,3 +261,119 @@ def bin_records(u, v, rup, rvp, o, keybits, grid, tile_w=TILE_W, tile_h=TILE_H):
                    _ptr(seg, ctypes.c_int64), _ptr(kk, ctypes.c_int32), n)
     assert n2 == n
     return seg[:n], kk[:n]
+
+
+# ---------------------------------------------------------------------------
+# the paper's conditioned radiance (rxcond_oracle.c)
+
+BASIS_FLE = 0
+BASIS_SH = 1
+
+
+def basis(kind: int, lmax: int, d) -> np.ndarray:
+    """Basis values at direction d (3,): (L, 2) Re / Im, component index deg^2 + deg + ord."""
+    L = (lmax + 1) ** 2
+    out = np.zeros((L, 2))
+    d = np.asarray(d, dtype=np.float64)
+    rc = lib().orc_basis(kind, lmax, float(d[0]), float(d[1]), float(d[2]), _ptr(out, ctypes.c_double))
+    if rc != 0:
+        raise ValueError("bad basis arguments")
+    return out
+
+
+def occupancy(scene, G: int = 128, nthreads=None):
+    """(grid (G, G, G) indexed [z, y, x], lo (3,), hi (3,)) of the scene's Gaussians."""
+    means, pm = _d(scene.means)
+    ls, pl = _d(scene.log_scales)
+    lg, pg = _d(scene.logits)
+    lo = np.zeros(3)
+    hi = np.zeros(3)
+    grid = np.zeros((G, G, G))
+    rc = lib().orc_occupancy(scene.K, pm, pl, pg, G, nthreads or default_threads(), _ptr(lo, ctypes.c_double),
+                             _ptr(hi, ctypes.c_double), _ptr(grid, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError(f"orc_occupancy failed ({rc})")
+    del means, ls, lg
+    return grid, lo, hi
+
+
+def rxcond_param_count(lmax: int, C: int, F: int, H: int) -> int:
+    return int(lib().orc_rxcond_param_count(lmax, C, F, H))
+
+
+def rxcond_radiance(model, scene, centres, rx, rx_view, occ=None, nthreads=None, want_feats=False):
+    """Conditioned radiance of every (receiver, channel, Gaussian): (N, C, K, 2),
+    and the local-branch inputs (N, K, 6) when want_feats.  model has kind,
+    lmax, C, F, H, S, G, coeffs (K, L, C, 2) and params (flat)."""
+    L = lib()
+    means, pm = _d(scene.means)
+    co, pco = _d(model.coeffs)
+    pa, ppa = _d(model.params)
+    assert pa.size == rxcond_param_count(model.lmax, model.C, model.F, model.H)
+    cen, pc = _d(np.asarray(centres).reshape(-1, 3))
+    rxa, prx = _d(np.asarray(rx).reshape(-1, 3))
+    rv = np.ascontiguousarray(np.asarray(rx_view, dtype=np.int32))
+    if occ is None:
+        occ = occupancy(scene, model.G, nthreads)
+    grid, lo, hi = occ
+    G = grid.shape[0]
+    assert grid.shape == (G, G, G)
+    gr, pgr = _d(grid)
+    lo_, plo = _d(lo)
+    hi_, phi = _d(hi)
+    N, K = rxa.shape[0], scene.K
+    out = np.zeros((N, model.C, K, 2))
+    feats = np.zeros((N, K, 6)) if want_feats else None
+    rc = L.orc_rxcond_radiance(model.kind, model.lmax, model.C, model.F, model.H, model.S, K, pm, pco, ppa,
+                               cen.shape[0], pc, N, prx, _ptr(rv, ctypes.c_int), G, plo, phi, pgr,
+                               nthreads or default_threads(), _ptr(out, ctypes.c_double),
+                               _ptr(feats, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError(f"orc_rxcond_radiance failed ({rc})")
+    del means, co, pa, cen, rxa, gr, lo_, hi_
+    return (out, feats) if want_feats else out
+
+
+def render_rad(scene, grid, centres, rad_rx, rx_view, nthreads=None, want_hash=False):
+    """Forward render with per-receiver radiance rad_rx (N, K, 2) given
+    (receiver j uses view rx_view[j]); outputs as render()."""
+    L = lib()
+    means, pm = _d(scene.means)
+    ls, pl = _d(scene.log_scales)
+    qu, pq = _d(scene.quats)
+    lg, pg = _d(scene.logits)
+    rr, prr = _d(rad_rx)
+    cen, pc = _d(np.asarray(centres).reshape(-1, 3))
+    rv = np.ascontiguousarray(np.asarray(rx_view, dtype=np.int32))
+    N, V, K = rr.shape[0], cen.shape[0], scene.K
+    assert rr.shape == (N, K, 2)
+    H, W = grid.H, grid.W
+    C = np.zeros((N, 2, H, W))
+    T = np.zeros((N, H, W))
+    nc = np.zeros((N, H, W), dtype=np.int32)
+    ncl = np.zeros((N, H, W), dtype=np.int32)
+    mg = np.zeros((N, H, W))
+    pw = np.zeros(N)
+    cs = np.zeros((N, 2))
+    rh = np.zeros((N, H), dtype=np.uint64) if want_hash else None
+    rc = L.orc_render_rad(K, pm, pl, pq, pg, prr, V, pc, N, _ptr(rv, ctypes.c_int), H, W, grid.el0, grid.del_el,
+                          nthreads or default_threads(), _ptr(C, ctypes.c_double), _ptr(T, ctypes.c_double),
+                          _ptr(nc, ctypes.c_int), _ptr(mg, ctypes.c_double), _ptr(pw, ctypes.c_double),
+                          _ptr(cs, ctypes.c_double), _ptr(rh, ctypes.c_uint64), _ptr(ncl, ctypes.c_int))
+    if rc != 0:
+        raise RuntimeError(f"orc_render_rad failed ({rc})")
+    del means, ls, qu, lg, rr, cen
+    out = dict(C=C, T_final=T, ncomp=nc, nclamp=ncl, margin=mg, power=pw, csum=cs)
+    if want_hash:
+        out["rowhash"] = rh
+    return out
+
+
+def render_rxcond(scene, model, grid, centres, rx, rx_view, nthreads=None, occ=None):
+    """Render with the conditioned radiance: every (receiver, channel) is one
+    output row (receiver-major), composited over its receiver's view.  C
+    (N * C, 2, H, W) and the other outputs of render()."""
+    rad = rxcond_radiance(model, scene, centres, rx, rx_view, occ=occ, nthreads=nthreads)   # (N, C, K, 2)
+    N, Ch = rad.shape[0], rad.shape[1]
+    rv = np.repeat(np.asarray(rx_view, dtype=np.int32), Ch)
+    return render_rad(scene, grid, centres, rad.reshape(N * Ch, scene.K, 2), rv, nthreads=nthreads)

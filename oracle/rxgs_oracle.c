@@ -320,6 +320,7 @@ typedef struct {
     orc_grid g;
     view_t *views;
     double *rad;        /* N x K x 2 */
+    const double *rad_rx;   /* given per-receiver radiance N x K x 2, or NULL */
 } scene_t;
 
 static void rad_item(void *vctx, long item, int tid)
@@ -357,7 +358,10 @@ static int scene_setup(scene_t *s, int nthreads)
     s->rad = malloc(sizeof(double) * 2 * (size_t)(s->N > 0 ? s->N : 1) * (size_t)(s->K > 0 ? s->K : 1));
     if (!s->views || !s->rad) return -1;
     pool_run(nthreads, s->V, view_item, s);
-    pool_run(nthreads, s->N, rad_item, s);
+    if (s->rad_rx)
+        memcpy(s->rad, s->rad_rx, sizeof(double) * 2 * (size_t)s->N * (size_t)s->K);
+    else
+        pool_run(nthreads, s->N, rad_item, s);
     return 0;
 }
 
@@ -472,21 +476,22 @@ static void render_item(void *vctx, long item, int tid)
  * nclamp N x H x W composited entries whose weight was clamped (optional).
  * Returns 0 on success.
  */
-int orc_render(int K, const double *means, const double *log_scales, const double *quats,
-               const double *logits, const double *radiance, const double *features,
-               const double *mlp, int V, const double *centres, int N, const double *rx,
-               const int *rx_view, int H, int W, double el0, double del, int nthreads,
-               double *C, double *T_final, int *ncomp, double *margin, double *power,
-               double *csum, uint64_t *rowhash, int *nclamp)
+static int render_impl(int K, const double *means, const double *log_scales, const double *quats,
+                       const double *logits, const double *radiance, const double *features,
+                       const double *mlp, const double *rad_rx, int V, const double *centres, int N,
+                       const double *rx, const int *rx_view, int H, int W, double el0, double del,
+                       int nthreads, double *C, double *T_final, int *ncomp, double *margin, double *power,
+                       double *csum, uint64_t *rowhash, int *nclamp)
 {
     if (K < 0 || V < 1 || N < 0 || H < 1 || W < 1) return -1;
-    if (!radiance && (!features || !mlp)) return -1;
+    if (!radiance && !rad_rx && (!features || !mlp)) return -1;
     for (int j = 0; j < N; j++) if (rx_view[j] < 0 || rx_view[j] >= V) return -1;
     scene_t s;
     memset(&s, 0, sizeof s);
     s.K = K; s.V = V; s.N = N;
     s.means = means; s.ls = log_scales; s.quats = quats; s.logits = logits;
     s.radiance = radiance; s.features = features; s.mlp = mlp; s.centres = centres;
+    s.rad_rx = rad_rx;
     s.rx = rx; s.rx_view = rx_view; s.g = mkgrid(H, W, el0, del);
     if (scene_setup(&s, nthreads)) return -2;
     render_ctx r = { &s, C, T_final, margin, ncomp, rowhash, nclamp };
@@ -503,6 +508,35 @@ int orc_render(int K, const double *means, const double *log_scales, const doubl
     }
     scene_free(&s);
     return 0;
+}
+
+int orc_render(int K, const double *means, const double *log_scales, const double *quats,
+               const double *logits, const double *radiance, const double *features,
+               const double *mlp, int V, const double *centres, int N, const double *rx,
+               const int *rx_view, int H, int W, double el0, double del, int nthreads,
+               double *C, double *T_final, int *ncomp, double *margin, double *power,
+               double *csum, uint64_t *rowhash, int *nclamp)
+{
+    return render_impl(K, means, log_scales, quats, logits, radiance, features, mlp, NULL, V, centres, N, rx,
+                       rx_view, H, W, el0, del, nthreads, C, T_final, ncomp, margin, power, csum, rowhash,
+                       nclamp);
+}
+
+/*
+ * The forward render with per-receiver radiance given (rad_rx N x K x 2, row
+ * j for receiver j), e.g. from orc_rxcond_radiance with one row per
+ * (receiver, channel).  Other arguments and outputs as orc_render.
+ */
+int orc_render_rad(int K, const double *means, const double *log_scales, const double *quats,
+                   const double *logits, const double *rad_rx, int V, const double *centres, int N,
+                   const int *rx_view, int H, int W, double el0, double del, int nthreads, double *C,
+                   double *T_final, int *ncomp, double *margin, double *power, double *csum, uint64_t *rowhash,
+                   int *nclamp)
+{
+    if (!rad_rx) return -1;
+    return render_impl(K, means, log_scales, quats, logits, NULL, NULL, NULL, rad_rx, V, centres, N, NULL,
+                       rx_view, H, W, el0, del, nthreads, C, T_final, ncomp, margin, power, csum, rowhash,
+                       nclamp);
 }
 
 /*

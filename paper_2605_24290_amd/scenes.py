@@ -217,3 +217,82 @@ def serving_queries(seed: int, count: int, box, max_rx: int = 256):
         rxq = _uniform_box(rng, n, box).astype(np.float32)
         out.append((float(gaps[i]), txq, rxq))
     return out
+
+
+# ---------------------------------------------------------------------------
+# The paper's receiver-conditioned radiance model (Sec. 4.3.2; App. E.2, E.5)
+
+EMB_DIM = 16          # component embedding width d_c (App. E Table 4)
+BASIS_FLE = 0         # complex Fourier-Legendre basis (App. E.2)
+BASIS_SH = 1          # real spherical harmonics (the RF-3DGS backbone, Sec. 5)
+
+
+def rxcond_shapes(lmax: int, C: int, F: int, H: int) -> list:
+    """Shapes of the conditioning parameters, in the order of the flat vector:
+    Fourier frequency vectors (3F x 3), component embeddings (L x 16), the
+    global MLP (W1, b1, W2, b2, W3, b3; input 6F + 2 + 16, output 4C) and the
+    local MLP (input 6, output 4LC); matrices are (out, in)."""
+    L = (lmax + 1) ** 2
+    gin = 6 * F + 2 + EMB_DIM
+    return [(3 * F, 3), (L, EMB_DIM),
+            (H, gin), (H,), (H, H), (H,), (4 * C, H), (4 * C,),
+            (H, 6), (H,), (H, H), (H,), (4 * L * C, H), (4 * L * C,)]
+
+
+@dataclasses.dataclass
+class RxCondModel:
+    kind: int            # BASIS_FLE or BASIS_SH
+    lmax: int
+    C: int               # complex signal channels
+    F: int               # Fourier bands per axis
+    H: int               # hidden width of both MLPs
+    coeffs: np.ndarray   # (K, L, C, 2) f32 base coefficients (Re, Im)
+    params: np.ndarray   # flat f32, rxcond_shapes order
+    S: int = 16          # occupancy probes per (receiver, Gaussian)
+    G: int = 128         # occupancy grid resolution
+
+    @property
+    def L(self) -> int:
+        return (self.lmax + 1) ** 2
+
+
+def make_rxcond_model(K: int, *, kind: int = BASIS_FLE, lmax: int = 9, C: int = 1, F: int = 6, H: int = 64,
+                      seed: int = BASE_SEED + 7000, coeff_sd: float = 0.3, zero_final: bool = False) -> RxCondModel:
+    """Seeded synthetic stand-in for a trained conditioning model: frequency
+    vectors at 2^f along each axis (their initialisation, App. E.5),
+    embeddings N(0, 1), Xavier-uniform weights with zero biases (final layers
+    too unless zero_final, the paper's initialisation), base coefficients
+    N(0, coeff_sd^2).  Draw order: coefficients, embeddings, weight matrices
+    in rxcond_shapes order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    L = (lmax + 1) ** 2
+    coeffs = rng.normal(0.0, coeff_sd, size=(K, L, C, 2)).astype(np.float32)
+    shapes = rxcond_shapes(lmax, C, F, H)
+    parts = []
+    freq = np.zeros((3 * F, 3), dtype=np.float32)
+    for d in range(3):
+        for f in range(F):
+            freq[d * F + f, d] = 2.0 ** f
+    parts.append(freq)
+    parts.append(rng.normal(0.0, 1.0, size=shapes[1]).astype(np.float32))
+    final = {6, 7, 12, 13}
+    for i, shape in enumerate(shapes[2:], start=2):
+        if len(shape) == 2 and not (zero_final and i in final):
+            fo, fi = shape
+            bound = math.sqrt(6.0 / (fi + fo))
+            parts.append(rng.uniform(-bound, bound, size=shape).astype(np.float32))
+        else:
+            parts.append(np.zeros(shape, dtype=np.float32))
+    params = np.concatenate([p.ravel() for p in parts])
+    return RxCondModel(kind, lmax, C, F, H, coeffs, params)
+
+
+def split_rxcond_params(model: RxCondModel) -> list:
+    """The flat parameter vector cut into its rxcond_shapes arrays (views)."""
+    out, off = [], 0
+    for shape in rxcond_shapes(model.lmax, model.C, model.F, model.H):
+        n = int(np.prod(shape))
+        out.append(model.params[off:off + n].reshape(shape))
+        off += n
+    assert off == model.params.size
+    return out
