@@ -33,6 +33,7 @@
 #ifndef RXGS_H
 #define RXGS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -74,9 +75,26 @@ enum { RXGS_MODE_TX = 0, RXGS_MODE_RX = 1 };
 #define RXGS_FEAT_DIM 32
 #define RXGS_TILE 16
 
-/* Create a context on HIP device `device` for one angular grid.
- * Errors: E_INVALID (grid), E_DEVICE. */
+/* Create a context on HIP device `device` for one angular grid.  Its device
+ * buffers come from hipMalloc.  Errors: E_INVALID (grid), E_DEVICE. */
 rxgs_status rxgs_create(int device, const rxgs_grid *grid, rxgs_ctx **out);
+
+/* Caller-supplied device allocator (e.g. a framework's caching allocator).
+ * alloc returns `bytes` of device memory on `device` (256-byte aligned), or
+ * NULL on failure (the library then reports E_OOM); free returns a block
+ * with the size it was allocated with.  Both may be called from the thread
+ * that calls into the context and from a server's worker thread.  Before
+ * handing a block back the library waits until no queued device work uses
+ * it (a device synchronisation), so a block may be reused on any stream. */
+typedef void *(*rxgs_alloc_fn)(size_t bytes, int device, void *user);
+typedef void (*rxgs_free_fn)(void *ptr, size_t bytes, int device, void *user);
+
+/* rxgs_create whose every device buffer (scene, MLP, workspaces, saved
+ * states, server slots) comes from alloc / free (both non-NULL); `user` is
+ * passed through.  Pinned host staging still comes from hipHostMalloc.
+ * Errors: those of rxgs_create, E_INVALID (NULL callback). */
+rxgs_status rxgs_create_with_allocator(int device, const rxgs_grid *grid, rxgs_alloc_fn alloc,
+                                       rxgs_free_fn free_fn, void *user, rxgs_ctx **out);
 
 /* Destroy a context, its scene, MLP and internal workspaces.  Saved states
  * created from it must be destroyed first.  NULL is ignored. */
@@ -138,6 +156,8 @@ void rxgs_saved_destroy(rxgs_saved *s);
  *   power   device N output, received power sum_p |C_p|^2 (App. A Def. 2
  *           aggregates over rays; here over the grid's pixels), or NULL.
  *   csum    device N x 2 output, coherent sum sum_p C_p, or NULL.
+ *   amp     device N x H x W output amplitude sqrt(Re^2 + Im^2 + 1e-8) of every
+ *           pixel (App. E.2, the stabilised |R|), or NULL.
  *   saved   state for rxgs_render_backward, or NULL (an internal workspace is
  *           used and nothing is kept).
  * Compositing per pixel (Alg. 1 stage 3): Gaussians of the view in ascending
@@ -150,7 +170,7 @@ void rxgs_saved_destroy(rxgs_saved *s);
  * E_DEVICE.  The call synchronises the stream once.
  */
 rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off,
-                        int N, const float *rx, float *C, float *power, float *csum,
+                        int N, const float *rx, float *C, float *power, float *csum, float *amp,
                         rxgs_saved *saved, void *stream);
 
 /*
@@ -167,12 +187,14 @@ rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *tx, const i
  * those of rxgs_render, and E_OOM when one receiver does not fit the budget.
  */
 rxgs_status rxgs_render_chunked(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off,
-                                int N, const float *rx, float *C, float *power, float *csum,
+                                int N, const float *rx, float *C, float *power, float *csum, float *amp,
                                 int64_t budget_bytes, int32_t *n_chunks, void *stream);
 
-/* Gradient outputs of rxgs_render_backward (device pointers, caller-owned,
- * overwritten).  Any may be NULL to skip it; radiance is used for direct
- * radiance scenes, features and mlp for MLP scenes. */
+/* Gradient outputs of rxgs_render_backward (device pointers, caller-owned).
+ * Any may be NULL to skip it; radiance is used for direct radiance scenes,
+ * features and mlp for MLP scenes.  accumulate = 0: the outputs are
+ * overwritten; 1: this backward's gradients are added to their contents (a
+ * loss summed over several renders, e.g. several transmitters). */
 typedef struct {
     float *means;        /* K x 3 */
     float *log_scales;   /* K x 3 */
@@ -181,22 +203,24 @@ typedef struct {
     float *radiance;     /* K x 2 */
     float *features;     /* K x 32 */
     float *mlp;          /* RXGS_MLP_NPARAM */
+    int32_t accumulate;  /* 0 overwrite, 1 add */
 } rxgs_grads;
 
 /*
  * Backward pass of the last rxgs_render into `saved` (App. D: per-receiver
  * dL/ds, Gaussian-level gradients accumulated over receivers and pixels).
- *   C    device N x 2 x H x W, the forward's output (used for dL/dP).
- *   dC   device N x 2 x H x W, dL/dC.
+ *   C    device N x 2 x H x W, the forward's output (used for dL/dP and dL/damp).
+ *   dC   device N x 2 x H x W, dL/dC, or NULL (zero).
  *   dP   device N, dL/dpower, or NULL.
+ *   dA   device N x H x W, dL/damp for the amplitude output, or NULL.
  * Gradients flow through w = o exp(-q/2) when it is not clamped at 0.99, the
  * projected mean and covariance, the quaternion normalisation and the MLP
  * (ReLU derivative 0 at 0).  Float atomics make results vary in the last
  * bits from run to run.  Errors: E_INVALID, E_STATE, E_OOM, E_DEVICE.
  */
 rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *saved, const float *C,
-                                 const float *dC, const float *dP, const rxgs_grads *grads,
-                                 void *stream);
+                                 const float *dC, const float *dP, const float *dA,
+                                 const rxgs_grads *grads, void *stream);
 
 /* Sizes of a saved forward state. */
 typedef struct {
@@ -216,6 +240,10 @@ typedef struct {
                                  still compositing, once per receiver chunk */
     int64_t n_walked_px;      /* (pixel, list entry) slots walked by the waves (64 per
                                  entry and wave, terminated lanes included) */
+    int64_t n_sort_fallbacks; /* radix-sort tiles (depth and pair sorts) whose bounded
+                                 look-back wait expired and that counted the digits of
+                                 their segment's earlier tiles directly instead (exact;
+                                 normally 0) */
 } rxgs_saved_info_t;
 
 rxgs_status rxgs_saved_info(const rxgs_saved *s, rxgs_saved_info_t *out);

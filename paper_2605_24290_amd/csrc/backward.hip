@@ -40,7 +40,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
     const float4 *__restrict__ srec, const uint32_t *__restrict__ pval, const uint2 *__restrict__ ranges,
     const float2 *__restrict__ rad, const int4 *__restrict__ chunks, int split, int64_t Kp, DevGrid g,
     int tx_mode, const float *__restrict__ C, const float *__restrict__ dC, const float *__restrict__ dP,
-    const float *__restrict__ Tfin, const int *__restrict__ nlast, float *__restrict__ dS,
+    const float *__restrict__ dA, const float *__restrict__ Tfin, const int *__restrict__ nlast, float *__restrict__ dS,
     float *__restrict__ g2d, uint8_t *__restrict__ live)
 {
     __shared__ BlendStage st;
@@ -79,9 +79,17 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
         A[r] = make_float2(0.f, 0.f);
         if (inside && r < nrx) {
             const size_t j = (size_t)(j0 + r);
+            // dL/dC of the pixel: the spectrum's own gradient, the power's
+            // (d|C|^2/dC = 2 C) and the amplitude's (d sqrt(|C|^2 + 1e-8)/dC = C / amplitude)
             const float gp = dP ? 2.f * dP[j] : 0.f;
-            G[r].x = dC[(j * 2) * P + pix] + gp * C[(j * 2) * P + pix];
-            G[r].y = dC[(j * 2 + 1) * P + pix] + gp * C[(j * 2 + 1) * P + pix];
+            const float cx = C[(j * 2) * P + pix], cy = C[(j * 2 + 1) * P + pix];
+            G[r].x = (dC ? dC[(j * 2) * P + pix] : 0.f) + gp * cx;
+            G[r].y = (dC ? dC[(j * 2 + 1) * P + pix] : 0.f) + gp * cy;
+            if (dA) {
+                const float ga = dA[j * P + pix] / sqrtf(cx * cx + cy * cy + AMP_EPS);
+                G[r].x += ga * cx;
+                G[r].y += ga * cy;
+            }
         }
     }
     int m = last;
@@ -864,7 +872,8 @@ hipError_t launch_zero_ranges(const ZeroRanges &z, hipStream_t st)
 }
 
 template <int R>
-static hipError_t blend_bwd_launch(Workspace &ws, const float *C, const float *dC, const float *dP, hipStream_t st)
+static hipError_t blend_bwd_launch(Workspace &ws, const float *C, const float *dC, const float *dP, const float *dA,
+                                   hipStream_t st)
 {
     // forward chunks hold at most ws.R receivers; split them into R-receiver blocks
     const int split = (ws.R + R - 1) / R;
@@ -873,20 +882,21 @@ static hipError_t blend_bwd_launch(Workspace &ws, const float *C, const float *d
     dim3 grid((unsigned)ws.g.tiles, (unsigned)ny);
     hipLaunchKernelGGL(k_blend_bwd<R>, grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                        ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
-                       ws.d_chunks, split, ws.Kp, ws.g, ws.mode == RXGS_MODE_TX ? 1 : 0, C, dC, dP,
+                       ws.d_chunks, split, ws.Kp, ws.g, ws.mode == RXGS_MODE_TX ? 1 : 0, C, dC, dP, dA,
                        ws.Tfin.as<float>(), ws.nlast.as<int>(), ws.dS.as<float>(), ws.g2d.as<float>(),
                        ws.live.as<uint8_t>());
     return hipGetLastError();
 }
 
-hipError_t launch_blend_bwd(Workspace &ws, const float *C, const float *dC, const float *dP, hipStream_t st)
+hipError_t launch_blend_bwd(Workspace &ws, const float *C, const float *dC, const float *dP, const float *dA,
+                            hipStream_t st)
 {
     if (ws.n_chunks == 0) return hipSuccess;
     switch (ws.R) {
-    case 1: return blend_bwd_launch<1>(ws, C, dC, dP, st);
-    case 2: return blend_bwd_launch<2>(ws, C, dC, dP, st);
-    case 4: return blend_bwd_launch<4>(ws, C, dC, dP, st);
-    default: return blend_bwd_launch<8>(ws, C, dC, dP, st);   // 8 and 16
+    case 1: return blend_bwd_launch<1>(ws, C, dC, dP, dA, st);
+    case 2: return blend_bwd_launch<2>(ws, C, dC, dP, dA, st);
+    case 4: return blend_bwd_launch<4>(ws, C, dC, dP, dA, st);
+    default: return blend_bwd_launch<8>(ws, C, dC, dP, dA, st);   // 8 and 16
     }
 }
 

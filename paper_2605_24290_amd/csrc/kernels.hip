@@ -1949,16 +1949,33 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_out(const float *__restrict__ 
 // host-side launch wrappers
 static inline unsigned nblk(size_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
-bool grow(DevBuf &b, size_t bytes)
+bool grow(DevBuf &b, size_t bytes, Allocator *al)
 {
     if (bytes == 0) bytes = 256;
-    if (b.cap >= bytes) return true;
-    if (b.p) {
-        (void)hipFree(b.p);
-        b.p = nullptr;
-        b.cap = 0;
+    if (b.cap >= bytes && b.al == al) return true;
+    release(b);
+    if (al && al->base) {   // carved from the fixed region, 256-byte aligned
+        const size_t at = (al->used + 255) / 256 * 256;
+        if (at > al->cap || bytes > al->cap - at) return false;
+        b.p = al->base + at;
+        b.cap = bytes;
+        b.al = al;
+        al->used = at + bytes;
+        return true;
     }
     size_t want = bytes + bytes / 4;
+    if (al && al->alloc) {
+        void *p = al->alloc(want, al->device, al->user);
+        if (!p) {
+            p = al->alloc(bytes, al->device, al->user);
+            want = bytes;
+        }
+        if (!p) return false;
+        b.p = p;
+        b.cap = want;
+        b.al = al;
+        return true;
+    }
     if (hipMalloc(&b.p, want) != hipSuccess) {
         (void)hipGetLastError();
         if (hipMalloc(&b.p, bytes) != hipSuccess) {
@@ -1969,14 +1986,27 @@ bool grow(DevBuf &b, size_t bytes)
         want = bytes;
     }
     b.cap = want;
+    b.al = al;
     return true;
 }
 
 void release(DevBuf &b)
 {
-    if (b.p) (void)hipFree(b.p);
+    if (b.p) {
+        if (b.al && b.al->base) {
+            // a carved buffer: the region is rewound as a whole
+        } else if (b.al && b.al->free) {
+            // the caller's allocator may hand the block out again at once:
+            // nothing queued on any stream may still use it
+            (void)hipDeviceSynchronize();
+            b.al->free(b.p, b.cap, b.al->device, b.al->user);
+        } else {
+            (void)hipFree(b.p);
+        }
+    }
     b.p = nullptr;
     b.cap = 0;
+    b.al = nullptr;
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st)
@@ -2377,6 +2407,38 @@ int *live_count(Workspace &ws)
 }
 
 size_t live_count_offset(const Workspace &ws) { return ((size_t)ws.V * ws.Kp / MLP_PAIRS + 63) / 64 * 64; }
+
+// output amplitude of every pixel, |C| = sqrt(Re^2 + Im^2 + eps) (App. E.2)
+__global__ __launch_bounds__(BLOCK) void k_amplitude(const float *__restrict__ C, float *__restrict__ amp, int N,
+                                                     size_t P)
+{
+    const size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= (size_t)N * P) return;
+    const size_t j = i / P, p = i - j * P;
+    const float re = C[2 * j * P + p], im = C[(2 * j + 1) * P + p];
+    amp[i] = sqrtf(re * re + im * im + AMP_EPS);
+}
+
+hipError_t launch_amplitude(const float *C, float *amp, int N, size_t P, hipStream_t st)
+{
+    const size_t n = (size_t)N * P;
+    if (n == 0 || !amp) return hipSuccess;
+    hipLaunchKernelGGL(k_amplitude, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, C, amp, N, P);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(BLOCK) void k_add_f32(float *__restrict__ out, const float *__restrict__ add, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n) out[i] += add[i];
+}
+
+hipError_t launch_add_f32(float *out, const float *add, size_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_f32, dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, out, add, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_reduce_outputs(Workspace &ws, float *power, float *csum, hipStream_t st)
 {

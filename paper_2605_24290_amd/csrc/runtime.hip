@@ -33,9 +33,20 @@ rxgs_status hip_fail(rxgs_ctx *ctx, hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
     } while (0)
 
+// a buffer of the context (scene, MLP, staging)
 #define GROW(ctx, buf, bytes)                                                     \
     do {                                                                          \
-        if (!grow((buf), (bytes))) return fail(ctx, RXGS_E_OOM, "device allocation failed: " #buf); \
+        if (!grow((buf), (bytes), &(ctx)->alloc))                                 \
+            return fail(ctx, RXGS_E_OOM, "device allocation failed: " #buf);      \
+    } while (0)
+
+// a buffer of workspace w (its own allocator, else the context's)
+#define WGROW(ctx, w, buf, bytes)                                                 \
+    do {                                                                          \
+        if (!grow((buf), (bytes), (w).al ? (w).al : &(ctx)->alloc))               \
+            return fail(ctx, RXGS_E_OOM, (w).al && (w).al->base                   \
+                                             ? "scratch region exhausted: " #buf  \
+                                             : "device allocation failed: " #buf); \
     } while (0)
 
 struct DeviceScope {
@@ -127,16 +138,49 @@ void free_workspace(Workspace &ws)
                       &ws.Lp,      &ws.Gp,      &ws.items,  &ws.Tfin,   &ws.nlast,  &ws.part,
                       &ws.counters, &ws.hist,   &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
                       &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.mred,   &ws.live,   &ws.items_live, &ws.vflag,
-                      &ws.items_far, &ws.frec, &ws.fcnt,  &ws.ftile,  &ws.hist_b};
+                      &ws.items_far, &ws.frec, &ws.fcnt,  &ws.ftile,  &ws.hist_b, &ws.gfeat_tmp, &ws.gmlp_tmp};
     for (DevBuf *b : bufs) release(*b);
     if (ws.staged) (void)hipEventDestroy(ws.staged);
     if (ws.counted) (void)hipEventDestroy(ws.counted);
+    if (ws.done) (void)hipEventDestroy(ws.done);
     ws.staged = nullptr;
     ws.counted = nullptr;
+    ws.done = nullptr;
     if (ws.h_pinned) (void)hipHostFree(ws.h_pinned);
     ws.h_pinned = nullptr;
     ws.h_pinned_cap = 0;
     ws.valid = false;
+}
+
+// waits for the last render or backward into ws (on whatever stream it ran)
+hipError_t wait_workspace(const Workspace &ws)
+{
+    return ws.done ? hipEventSynchronize(ws.done) : hipSuccess;
+}
+
+// the context's private stream (non-blocking: it never waits for, nor stalls,
+// the caller's or a server slot's streams)
+hipError_t aux_stream(rxgs_ctx *ctx, hipStream_t &out)
+{
+    if (!ctx->aux) {
+        hipError_t e = hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            ctx->aux = nullptr;
+            return e;
+        }
+    }
+    out = ctx->aux;
+    return hipSuccess;
+}
+
+// synchronous copy on the context's private stream
+hipError_t aux_copy(rxgs_ctx *ctx, void *dst, const void *src, size_t n, hipMemcpyKind kind)
+{
+    hipStream_t a = nullptr;
+    hipError_t e = aux_stream(ctx, a);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, src, n, kind, a);
+    if (e == hipSuccess) e = hipStreamSynchronize(a);
+    return e;
 }
 
 }  // namespace
@@ -275,8 +319,8 @@ extern "C" rxgs_status rxgs_view_flags(rxgs_ctx *ctx, uint32_t *out, int32_t max
     if (n_views) *n_views = ws.vflag.p ? ws.V : 0;
     if (n == 0) return RXGS_OK;
     DeviceScope ds(ctx->device);
-    if (hipMemcpy(out, ws.vflag.p, (size_t)n * 4, hipMemcpyDeviceToHost) != hipSuccess)
-        return hip_fail(ctx, hipGetLastError(), "view flags");
+    HIPCHK(ctx, wait_workspace(ws));
+    HIPCHK(ctx, aux_copy(ctx, out, ws.vflag.p, (size_t)n * 4, hipMemcpyDeviceToHost));
     return RXGS_OK;
 }
 
@@ -313,6 +357,7 @@ extern "C" rxgs_status rxgs_create(int device, const rxgs_grid *grid, rxgs_ctx *
         return RXGS_E_OOM;
     }
     ctx->device = device;
+    ctx->alloc.device = device;
     ctx->grid = *grid;
     DevGrid &g = ctx->g;
     g.H = grid->H;
@@ -329,11 +374,28 @@ extern "C" rxgs_status rxgs_create(int device, const rxgs_grid *grid, rxgs_ctx *
     return RXGS_OK;
 }
 
+extern "C" rxgs_status rxgs_create_with_allocator(int device, const rxgs_grid *grid, rxgs_alloc_fn alloc,
+                                                  rxgs_free_fn free_fn, void *user, rxgs_ctx **out)
+{
+    if (!alloc || !free_fn) {
+        g_create_err = "allocator callbacks must both be given";
+        if (out) *out = nullptr;
+        return RXGS_E_INVALID;
+    }
+    rxgs_status rs = rxgs_create(device, grid, out);
+    if (rs != RXGS_OK) return rs;
+    (*out)->alloc.alloc = alloc;
+    (*out)->alloc.free = free_fn;
+    (*out)->alloc.user = user;
+    return RXGS_OK;
+}
+
 extern "C" void rxgs_destroy(rxgs_ctx *ctx)
 {
     if (!ctx) return;
     DeviceScope ds(ctx->device);
-    (void)hipDeviceSynchronize();
+    (void)wait_workspace(ctx->ws);
+    if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
     ctx->prof.release_all();
     free_workspace(ctx->ws);
     release(ctx->scene.soa);
@@ -348,6 +410,7 @@ extern "C" void rxgs_destroy(rxgs_ctx *ctx)
     release(ctx->mlp.w1h);
     release(ctx->mlp.b1tab);
     release(ctx->stage);
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     delete ctx;
 }
 
@@ -367,7 +430,8 @@ extern "C" void rxgs_saved_destroy(rxgs_saved *s)
     if (!s) return;
     rxgs_ctx *ctx = s->ctx;
     DeviceScope ds(ctx->device);
-    (void)hipDeviceSynchronize();
+    (void)wait_workspace(s->ws);
+    if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
     free_workspace(s->ws);
     auto &v = ctx->saved;
     v.erase(std::remove(v.begin(), v.end(), s), v.end());
@@ -567,20 +631,23 @@ extern "C" rxgs_status rxgs_mlp_upload(rxgs_ctx *ctx, const float *params, int s
     }
     GROW(ctx, m.w1h, sizeof(_Float16) * w1h.size());
     GROW(ctx, m.b1tab, sizeof(float) * b1tab.size());
-    HIPCHK(ctx, hipMemcpy(m.w1h.p, w1h.data(), sizeof(_Float16) * w1h.size(), hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemcpy(m.b1tab.p, b1tab.data(), sizeof(float) * b1tab.size(), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpyAsync(m.w1h.p, w1h.data(), sizeof(_Float16) * w1h.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(m.b1tab.p, b1tab.data(), sizeof(float) * b1tab.size(), hipMemcpyHostToDevice, st));
     GROW(ctx, m.w2h, sizeof(_Float16) * w2h.size());
     GROW(ctx, m.tabh, sizeof(float) * tabh.size());
-    HIPCHK(ctx, hipMemcpy(m.w2h.p, w2h.data(), sizeof(_Float16) * w2h.size(), hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemcpy(m.tabh.p, tabh.data(), sizeof(float) * tabh.size(), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpyAsync(m.w2h.p, w2h.data(), sizeof(_Float16) * w2h.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(m.tabh.p, tabh.data(), sizeof(float) * tabh.size(), hipMemcpyHostToDevice, st));
     GROW(ctx, m.raw, sizeof(float) * RXGS_MLP_NPARAM);
     GROW(ctx, m.w2a, sizeof(float) * w2a.size());
     GROW(ctx, m.w2b, sizeof(float) * w2b.size());
     GROW(ctx, m.tab, sizeof(float) * tab.size());
-    HIPCHK(ctx, hipMemcpy(m.raw.p, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemcpy(m.w2a.p, w2a.data(), sizeof(float) * w2a.size(), hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemcpy(m.w2b.p, w2b.data(), sizeof(float) * w2b.size(), hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemcpy(m.tab.p, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpyAsync(m.raw.p, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(m.w2a.p, w2a.data(), sizeof(float) * w2a.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(m.w2b.p, w2b.data(), sizeof(float) * w2b.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(m.tab.p, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice, st));
+    // (ordered after earlier work on the caller's stream that may still read
+    // the old tables; the host vectors must outlive the copies)
+    HIPCHK(ctx, hipStreamSynchronize(st));
     m.version = ++ctx->version_counter;
     m.valid = true;
     return RXGS_OK;
@@ -595,7 +662,7 @@ constexpr int PREFIX_MAX_RX = 128;
 // that are emitted (the nearest ones); the blend flags every view it cut that
 // still has a pixel whose transmittance stayed above the stop threshold.
 static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off, int N,
-                               const float *rx, float *C, float *power, float *csum, rxgs_saved *saved,
+                               const float *rx, float *C, float *power, float *csum, float *amp, rxgs_saved *saved,
                                void *stream, uint32_t limit)
 {
     if (!ctx) return RXGS_E_INVALID;
@@ -634,6 +701,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     if (!ws.staged) {
         HIPCHK(ctx, hipEventCreateWithFlags(&ws.staged, hipEventDisableTiming));
         HIPCHK(ctx, hipEventCreateWithFlags(&ws.counted, hipEventDisableTiming));
+        HIPCHK(ctx, hipEventCreateWithFlags(&ws.done, hipEventDisableTiming));
     } else {
         // the previous render's host-to-device copies out of the staging buffer
         HIPCHK(ctx, hipEventSynchronize(ws.staged));
@@ -649,33 +717,33 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     ws.use_mlp = sc.has_features;
     ws.h_rxview = rxview;
     ws.limit = limit;
-    GROW(ctx, ws.vflag, (size_t)V * 4);
+    WGROW(ctx, ws, ws.vflag, (size_t)V * 4);
 
     if (save) {
         // the backward needs the view centres and receiver positions later
-        GROW(ctx, ws.centres, (size_t)V * 12);
-        GROW(ctx, ws.rxpos, (size_t)N * 12);
+        WGROW(ctx, ws, ws.centres, (size_t)V * 12);
+        WGROW(ctx, ws, ws.rxpos, (size_t)N * 12);
     }
     // (a saved state's binning boxes, raw keys and opacities are computed
     // when first exported: the backward does not read them)
     ws.exports_ready = false;
     for (int b = 0; b < 2; b++) {
-        GROW(ctx, ws.skey[b], VK * 4);
-        GROW(ctx, ws.sval[b], VK * 4);
+        WGROW(ctx, ws, ws.skey[b], VK * 4);
+        WGROW(ctx, ws, ws.sval[b], VK * 4);
     }
-    GROW(ctx, ws.srec, VK * 32);
-    GROW(ctx, ws.sbox, VK * 16);
-    GROW(ctx, ws.vorder, VK * 4);
-    GROW(ctx, ws.poff, VK * 4);
-    GROW(ctx, ws.ggeo, (size_t)std::max<int64_t>(K, 1) * 80);
-    GROW(ctx, ws.qcull, (size_t)std::max<int64_t>(K, 1) * 4);
+    WGROW(ctx, ws, ws.srec, VK * 32);
+    WGROW(ctx, ws, ws.sbox, VK * 16);
+    WGROW(ctx, ws, ws.vorder, VK * 4);
+    WGROW(ctx, ws, ws.poff, VK * 4);
+    WGROW(ctx, ws, ws.ggeo, (size_t)std::max<int64_t>(K, 1) * 80);
+    WGROW(ctx, ws, ws.qcull, (size_t)std::max<int64_t>(K, 1) * 4);
     // per view (visible count, pair count); slots for the largest |layer-1
     // term| of the receivers and of the Gaussians (FP32 bits); render
     // statistics; the emission's ticket, error word and look-back status
     const size_t emit_words_n = emit_word_count(V, Kp);
     const size_t cnt_words = (size_t)4 * V + AMAX_SLOTS + 2 * STAT_WORDS + emit_words_n + 16;   // + far-item count
-    GROW(ctx, ws.counters, cnt_words * 4);
-    GROW(ctx, ws.hist, sort_ws_bytes((uint32_t)VK, 32, V));
+    WGROW(ctx, ws, ws.counters, cnt_words * 4);
+    WGROW(ctx, ws, ws.hist, sort_ws_bytes((uint32_t)VK, 32, V));
 
     if (save) {
         HIPCHK(ctx, hipMemcpyAsync(ws.centres.p, mode == RXGS_MODE_TX ? tx : rx, (size_t)V * 12,
@@ -711,7 +779,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     // the receivers' layer-1 term depends on nothing above: it runs while the
     // host waits for the counts
     if (ws.use_mlp) {
-        GROW(ctx, ws.Gp, (size_t)N * HID * 4);
+        WGROW(ctx, ws, ws.Gp, (size_t)N * HID * 4);
         STAGE(ctx, "mlp_global", launch_mlp_global_term(ctx->mlp, ws, st));
     }
 
@@ -837,31 +905,31 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     ws.n_emit_chunks = (int)chunk_off[V];
 
     const size_t P = (size_t)g.H * g.W;
-    GROW(ctx, ws.pkey[0], std::max<uint64_t>(Dpad, 1) * 4);
-    GROW(ctx, ws.pkey[1], std::max<uint64_t>(Dpad, 1) * 4);
-    GROW(ctx, ws.pval[0], std::max<uint64_t>(Dpad, 1) * 4);
-    GROW(ctx, ws.pval[1], std::max<uint64_t>(Dpad, 1) * 4);
-    GROW(ctx, ws.hist_b, sort_ws_bytes((uint32_t)Dpad, std::max(bits_for((uint64_t)g.tiles), 1), V));
-    GROW(ctx, ws.ranges, (size_t)V * g.tiles * 8);
-    GROW(ctx, ws.torder, (size_t)V * g.tiles * 4);
-    GROW(ctx, ws.rad, (size_t)N * Kp * 8);
-    GROW(ctx, ws.Tfin, (size_t)ws.n_tslots * P * 4);
-    GROW(ctx, ws.nlast, (size_t)ws.n_tslots * P * 4);
-    GROW(ctx, ws.part, (size_t)N * g.tiles * 12);
+    WGROW(ctx, ws, ws.pkey[0], std::max<uint64_t>(Dpad, 1) * 4);
+    WGROW(ctx, ws, ws.pkey[1], std::max<uint64_t>(Dpad, 1) * 4);
+    WGROW(ctx, ws, ws.pval[0], std::max<uint64_t>(Dpad, 1) * 4);
+    WGROW(ctx, ws, ws.pval[1], std::max<uint64_t>(Dpad, 1) * 4);
+    WGROW(ctx, ws, ws.hist_b, sort_ws_bytes((uint32_t)Dpad, std::max(bits_for((uint64_t)g.tiles), 1), V));
+    WGROW(ctx, ws, ws.ranges, (size_t)V * g.tiles * 8);
+    WGROW(ctx, ws, ws.torder, (size_t)V * g.tiles * 4);
+    WGROW(ctx, ws, ws.rad, (size_t)N * Kp * 8);
+    WGROW(ctx, ws, ws.Tfin, (size_t)ws.n_tslots * P * 4);
+    WGROW(ctx, ws, ws.nlast, (size_t)ws.n_tslots * P * 4);
+    WGROW(ctx, ws, ws.part, (size_t)N * g.tiles * 12);
     if (ws.use_mlp) {
-        GROW(ctx, ws.Lp, (size_t)std::max<int64_t>(K, 1) * HID * 4);
-        GROW(ctx, ws.items, (size_t)std::max(ws.n_items, 1) * 16);
+        WGROW(ctx, ws, ws.Lp, (size_t)std::max<int64_t>(K, 1) * HID * 4);
+        WGROW(ctx, ws, ws.items, (size_t)std::max(ws.n_items, 1) * 16);
     }
     if (ws.lazy) {
-        GROW(ctx, ws.items_live, (size_t)std::max(ws.n_items, 1) * 16);
-        GROW(ctx, ws.live, live_count_offset(ws) + 64);
+        WGROW(ctx, ws, ws.items_live, (size_t)std::max(ws.n_items, 1) * 16);
+        WGROW(ctx, ws, ws.live, live_count_offset(ws) + 64);
     }
     if (ws.mpos != 0xFFFFFFFFu) {
-        GROW(ctx, ws.items_far, (size_t)std::max(ws.n_items_far, 1) * 16);
-        GROW(ctx, ws.frec, (size_t)V * P * FAR_RECORDS * 8);
-        GROW(ctx, ws.fcnt, (size_t)V * P);
-        GROW(ctx, ws.ftile, (size_t)V * g.tiles);
-        GROW(ctx, ws.live, live_count_offset(ws) + 64);   // marks of the blocks records point into
+        WGROW(ctx, ws, ws.items_far, (size_t)std::max(ws.n_items_far, 1) * 16);
+        WGROW(ctx, ws, ws.frec, (size_t)V * P * FAR_RECORDS * 8);
+        WGROW(ctx, ws, ws.fcnt, (size_t)V * P);
+        WGROW(ctx, ws, ws.ftile, (size_t)V * g.tiles);
+        WGROW(ctx, ws, ws.live, live_count_offset(ws) + 64);   // marks of the blocks records point into
     }
 
     // the small descriptors, packed (16-byte aligned parts) into one host-to-device copy
@@ -878,7 +946,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     const size_t cnt_bytes = head_bytes;   // the counts and the emission error word
     const size_t off0 = (cnt_bytes + 63) / 64 * 64;
     if (!ensure_pinned(ws, off0 + stage_bytes + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
-    GROW(ctx, ws.desc, stage_bytes);
+    WGROW(ctx, ws, ws.desc, stage_bytes);
     char *hp = static_cast<char *>(ws.h_pinned) + off0;
     std::memcpy(hp, rxview.data(), (size_t)N * 4);
     std::memcpy(hp + o_chunks, chunks.data(), chunks.size() * 16);
@@ -910,6 +978,9 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         STAGE(ctx, "emit_pairs", launch_emit2(ws, g, sort_ws_bytes((uint32_t)Dpad, sbits, V) / 4, st));
         STAGE(ctx, "sort_pairs", sort_pairs_u32(ws.pkey, ws.pval, ws.hist_b, pcur, (uint32_t)Dpad, sbits, V, 0,
                                                 ws.d_segtab, st, true));
+        ws.pair_bits = sbits;
+    } else {
+        ws.pair_bits = 0;
     }
     ws.pairs_buf = pcur;
     STAGE(ctx, "ranges", launch_ranges(ws, g, st));
@@ -939,6 +1010,8 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         STAGE(ctx, "blend_far", launch_blend_fwd(ws, C, false, st, true));
     }
     STAGE(ctx, "reduce", launch_reduce_outputs(ws, power, csum, st));
+    if (amp) STAGE(ctx, "amplitude", launch_amplitude(C, amp, N, P, st));
+    HIPCHK(ctx, hipEventRecord(ws.done, st));
     ws.scene_version = sc.version;
     ws.mlp_version = ctx->mlp.version;
     ws.valid = !saved || save;
@@ -954,11 +1027,11 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
 // The other views are redone over all their entries: one by one without
 // saved state, all of them with it.
 extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off, int N,
-                                   const float *rx, float *C, float *power, float *csum, rxgs_saved *saved,
-                                   void *stream)
+                                   const float *rx, float *C, float *power, float *csum, float *amp,
+                                   rxgs_saved *saved, void *stream)
 {
     const bool cut = ctx && ctx->scene.valid && ctx->scene.K > NEAR_LIMIT && N > 0 && ctx->near_cut;
-    rxgs_status rs = render_pass(ctx, mode, Q, tx, rx_off, N, rx, C, power, csum, saved, stream,
+    rxgs_status rs = render_pass(ctx, mode, Q, tx, rx_off, N, rx, C, power, csum, amp, saved, stream,
                                  cut ? (uint32_t)NEAR_LIMIT : 0xFFFFFFFFu);
     if (rs != RXGS_OK || !cut) return rs;
     DeviceScope ds(ctx->device);
@@ -974,7 +1047,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         if ((hf[v] & 3u) == 3u) redo.push_back(v);
     ctx->views_redone += (int64_t)redo.size();
     if (redo.empty()) return RXGS_OK;
-    if (saved) return render_pass(ctx, mode, Q, tx, rx_off, N, rx, C, power, csum, saved, stream, 0xFFFFFFFFu);
+    if (saved) return render_pass(ctx, mode, Q, tx, rx_off, N, rx, C, power, csum, amp, saved, stream, 0xFFFFFFFFu);
     const size_t P2 = (size_t)2 * ctx->g.H * ctx->g.W;
     for (int v : redo) {
         rxgs::StageMark sm_(ctx->prof, "redo_views", st);   // one launch per view redone
@@ -990,7 +1063,8 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         if (n == 0) continue;
         rs = render_pass(ctx, mode, mode == RXGS_MODE_TX ? 1 : 0, cen, mode == RXGS_MODE_TX ? off : nullptr, n,
                          rx + 3 * (size_t)j0, C + P2 * j0, power ? power + j0 : nullptr,
-                         csum ? csum + 2 * (size_t)j0 : nullptr, nullptr, stream, 0xFFFFFFFFu);
+                         csum ? csum + 2 * (size_t)j0 : nullptr, amp ? amp + P2 / 2 * j0 : nullptr, nullptr, stream,
+                         0xFFFFFFFFu);
         if (rs != RXGS_OK) return rs;
     }
     return RXGS_OK;
@@ -998,7 +1072,7 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
 
 // ============================================================================
 extern "C" rxgs_status rxgs_render_chunked(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off,
-                                           int N, const float *rx, float *C, float *power, float *csum,
+                                           int N, const float *rx, float *C, float *power, float *csum, float *amp,
                                            int64_t budget_bytes, int32_t *n_chunks, void *stream)
 {
     if (!ctx) return RXGS_E_INVALID;
@@ -1049,10 +1123,11 @@ extern "C" rxgs_status rxgs_render_chunked(rxgs_ctx *ctx, int mode, int Q, const
             for (int q = q0; q <= q1; q++) off[q - q0 + 1] = std::min(rx_off[q + 1], b) - a;
             rs = rxgs_render(ctx, mode, q1 - q0 + 1, tx + 3 * (size_t)q0, off.data(), b - a, rx + 3 * (size_t)a,
                              C + P2 * a, power ? power + a : nullptr, csum ? csum + 2 * (size_t)a : nullptr,
-                             nullptr, stream);
+                             amp ? amp + P2 / 2 * a : nullptr, nullptr, stream);
         } else {
             rs = rxgs_render(ctx, mode, 0, nullptr, nullptr, b - a, rx + 3 * (size_t)a, C + P2 * a,
-                             power ? power + a : nullptr, csum ? csum + 2 * (size_t)a : nullptr, nullptr, stream);
+                             power ? power + a : nullptr, csum ? csum + 2 * (size_t)a : nullptr,
+                             amp ? amp + P2 / 2 * a : nullptr, nullptr, stream);
         }
         if (rs != RXGS_OK) return rs;
         chunks++;
@@ -1064,7 +1139,7 @@ extern "C" rxgs_status rxgs_render_chunked(rxgs_ctx *ctx, int mode, int Q, const
 
 // ============================================================================
 extern "C" rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *saved, const float *C, const float *dC,
-                                            const float *dP, const rxgs_grads *grads, void *stream)
+                                            const float *dP, const float *dA, const rxgs_grads *grads, void *stream)
 {
     if (!ctx) return RXGS_E_INVALID;
     if (!saved || !grads) return fail(ctx, RXGS_E_INVALID, "saved or grads is NULL");
@@ -1075,12 +1150,15 @@ extern "C" rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *sav
     if (!ws.valid) return fail(ctx, RXGS_E_STATE, "no forward state in saved");
     if (ws.scene_version != sc.version || (ws.use_mlp && ws.mlp_version != ctx->mlp.version))
         return fail(ctx, RXGS_E_STATE, "scene or MLP changed since the forward");
-    if (ws.N > 0 && (!C || !dC)) return fail(ctx, RXGS_E_INVALID, "C or dC is NULL");
+    if (ws.N > 0 && !C) return fail(ctx, RXGS_E_INVALID, "C is NULL");
+    if (grads->accumulate != 0 && grads->accumulate != 1) return fail(ctx, RXGS_E_INVALID, "accumulate must be 0 or 1");
     DeviceScope ds(ctx->device);
     hipStream_t st = (hipStream_t)stream;
     const rxgs_grads &gr = *grads;
+    const bool accum = gr.accumulate == 1;
     const int64_t K = ws.K;
-    // gradients accumulate with atomics: clear them first
+    // gradients accumulate with atomics: clear them first (unless the caller
+    // asked to add into its buffers)
     struct {
         float *p;
         size_t n;
@@ -1088,17 +1166,19 @@ extern "C" rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *sav
                 {gr.logits, (size_t)K},   {ws.use_mlp ? nullptr : gr.radiance, (size_t)K * 2}};
     // (one launch zeroes the outputs and, below, the backward's accumulators)
     ZeroRanges zr;
-    for (auto &o : outs) zr.add(o.p, o.n);
+    if (!accum)
+        for (auto &o : outs) zr.add(o.p, o.n);
     if (ws.N == 0 || K == 0) {
+        if (accum) return RXGS_OK;   // nothing to add
         HIPCHK(ctx, launch_zero_ranges(zr, st));
         if (ws.use_mlp && gr.features) HIPCHK(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(gr.features), 0u, (size_t)K * FEAT, st));
         if (ws.use_mlp && gr.mlp) HIPCHK(ctx, launch_fill_u32(reinterpret_cast<uint32_t *>(gr.mlp), 0u, RXGS_MLP_NPARAM, st));
         return RXGS_OK;
     }
     const size_t VK = (size_t)ws.V * ws.Kp;
-    GROW(ctx, ws.dS, (size_t)ws.N * ws.Kp * 8);
-    GROW(ctx, ws.g2d, VK * 32);
-    GROW(ctx, ws.live, VK / MLP_PAIRS + 4);
+    WGROW(ctx, ws, ws.dS, (size_t)ws.N * ws.Kp * 8);
+    WGROW(ctx, ws, ws.g2d, VK * 32);
+    WGROW(ctx, ws, ws.live, VK / MLP_PAIRS + 4);
     // dL/ds and the 2-D record gradients are written and read at visible
     // positions only; when they are large, only those are cleared
     const bool rows = VK * 32 > ((size_t)256 << 20) && ws.N <= 65535 && ws.V <= 65535;
@@ -1112,21 +1192,39 @@ extern "C" rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *sav
     }
     zr.add(ws.live.p, (VK / MLP_PAIRS + 3) / 4);
     if (ws.use_mlp) {
-        GROW(ctx, ws.dL, (size_t)K * HID * 4);
-        GROW(ctx, ws.dG, (size_t)ws.N * HID * 4);
-        GROW(ctx, ws.mpart, mlp_part_bytes(ws));
-        GROW(ctx, ws.w1part, w1b_part_bytes(K));
-        GROW(ctx, ws.mred, mlp_red_bytes());
+        WGROW(ctx, ws, ws.dL, (size_t)K * HID * 4);
+        WGROW(ctx, ws, ws.dG, (size_t)ws.N * HID * 4);
+        WGROW(ctx, ws, ws.mpart, mlp_part_bytes(ws));
+        WGROW(ctx, ws, ws.w1part, w1b_part_bytes(K));
+        WGROW(ctx, ws, ws.mred, mlp_red_bytes());
         zr.add(ws.dL.p, (size_t)K * HID);
         zr.add(ws.dG.p, (size_t)ws.N * HID);
     }
+    // features and MLP gradients are stored, not added, by their kernels: to
+    // accumulate, they go to scratch first and are added afterwards
+    float *gfeat = gr.features, *gmlp = gr.mlp;
+    if (accum && ws.use_mlp) {
+        if (gfeat) {
+            WGROW(ctx, ws, ws.gfeat_tmp, (size_t)K * FEAT * 4);
+            gfeat = ws.gfeat_tmp.as<float>();
+        }
+        if (gmlp) {
+            WGROW(ctx, ws, ws.gmlp_tmp, (size_t)RXGS_MLP_NPARAM * 4);
+            gmlp = ws.gmlp_tmp.as<float>();
+        }
+    }
     HIPCHK(ctx, launch_zero_ranges(zr, st));
-    STAGE(ctx, "blend_bwd", launch_blend_bwd(ws, C, dC, dP, st));
+    STAGE(ctx, "blend_bwd", launch_blend_bwd(ws, C, dC, dP, dA, st));
     if (ws.use_mlp)
-        STAGE(ctx, "mlp_bwd", launch_mlp_bwd(sc, ctx->mlp, ws, gr.features, gr.mlp, st));
+        STAGE(ctx, "mlp_bwd", launch_mlp_bwd(sc, ctx->mlp, ws, gfeat, gmlp, st));
     else
         STAGE(ctx, "bwd_misc", launch_rad_bwd(sc, ws, gr.radiance, st));
     STAGE(ctx, "project_bwd", launch_project_bwd(sc, ws, gr, st));
+    if (accum && ws.use_mlp) {
+        if (gr.features) HIPCHK(ctx, launch_add_f32(gr.features, gfeat, (size_t)K * FEAT, st));
+        if (gr.mlp) HIPCHK(ctx, launch_add_f32(gr.mlp, gmlp, RXGS_MLP_NPARAM, st));
+    }
+    if (ws.done) HIPCHK(ctx, hipEventRecord(ws.done, st));
     return RXGS_OK;
 }
 
@@ -1144,18 +1242,29 @@ extern "C" rxgs_status rxgs_saved_info(const rxgs_saved *s, rxgs_saved_info_t *o
     out->n_visible = ws.nvis_total;
     out->tiles = ws.g.tiles;
     out->tiles_x = ws.g.tiles_x;
-    // composited-pair statistics of the forward: wait for it, then sum the slots
-    DeviceScope dsc(s->ctx->device);
-    if (hipDeviceSynchronize() != hipSuccess) return RXGS_E_DEVICE;
+    // composited-pair statistics of the forward: wait for it (its own event,
+    // not the device), then sum the slots
+    rxgs_ctx *ctx = s->ctx;
+    DeviceScope dsc(ctx->device);
+    if (wait_workspace(ws) != hipSuccess) return hip_fail(ctx, hipGetLastError(), "saved info: wait");
     std::vector<unsigned long long> h(4 * STAT_SLOTS);
     Workspace &w = const_cast<Workspace &>(ws);
-    if (hipMemcpy(h.data(), stat_words(w), h.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) return RXGS_E_DEVICE;
+    HIPCHK(ctx, aux_copy(ctx, h.data(), stat_words(w), h.size() * 8, hipMemcpyDeviceToHost));
     out->n_composited_px = out->n_composited = out->n_evaluated_px = out->n_walked_px = 0;
     for (int i = 0; i < STAT_SLOTS; i++) {
         out->n_composited_px += (int64_t)h[i];
         out->n_composited += (int64_t)h[STAT_SLOTS + i];
         out->n_evaluated_px += (int64_t)h[2 * STAT_SLOTS + i];
         out->n_walked_px += (int64_t)h[3 * STAT_SLOTS + i];
+    }
+    out->n_sort_fallbacks = 0;
+    const uint32_t *fw[2] = {sort_fallback_word(w.hist, (uint32_t)((size_t)ws.V * ws.Kp), 32, ws.V),
+                             sort_fallback_word(w.hist_b, (uint32_t)ws.Dpad, ws.pair_bits, ws.V)};
+    for (const uint32_t *p : fw) {
+        if (!p) continue;
+        uint32_t c = 0;
+        HIPCHK(ctx, aux_copy(ctx, &c, p, 4, hipMemcpyDeviceToHost));
+        out->n_sort_fallbacks += c;
     }
     return RXGS_OK;
 }
@@ -1175,11 +1284,14 @@ extern "C" rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *ds
             return fail(ctx, RXGS_E_STATE, "scene changed since the forward");
         Workspace &w = const_cast<Workspace &>(ws);
         DeviceScope ds0(ctx->device);
-        GROW(ctx, w.ext, VK * 16);
-        GROW(ctx, w.rawkey, VK * 4);
-        GROW(ctx, w.opac, VK * 4);
-        HIPCHK(ctx, hipDeviceSynchronize());   // the render, on the caller's stream
-        HIPCHK(ctx, launch_project_exports(w, nullptr));
+        WGROW(ctx, w, w.ext, VK * 16);
+        WGROW(ctx, w, w.rawkey, VK * 4);
+        WGROW(ctx, w, w.opac, VK * 4);
+        hipStream_t a = nullptr;
+        HIPCHK(ctx, aux_stream(ctx, a));
+        HIPCHK(ctx, wait_workspace(ws));   // the render, on the caller's stream
+        HIPCHK(ctx, launch_project_exports(w, a));
+        HIPCHK(ctx, hipStreamSynchronize(a));
         w.exports_ready = true;
     }
     const void *src = nullptr;
@@ -1212,18 +1324,21 @@ extern "C" rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *ds
         if (ws.scene_version != ctx->scene.version || ws.mlp_version != ctx->mlp.version)
             return fail(ctx, RXGS_E_STATE, "scene or MLP changed since the forward");
         Workspace &w = const_cast<Workspace &>(ws);
-        HIPCHK(ctx, hipDeviceSynchronize());   // the render, on the caller's stream
-        HIPCHK(ctx, launch_far_all(w, nullptr));
-        HIPCHK(ctx, launch_far_items(w, nullptr));
-        HIPCHK(ctx, launch_mlp_pairs(ctx->scene, ctx->mlp, w, nullptr, true));
+        hipStream_t a = nullptr;
+        HIPCHK(ctx, aux_stream(ctx, a));
+        HIPCHK(ctx, wait_workspace(ws));   // the render, on the caller's stream
+        HIPCHK(ctx, launch_far_all(w, a));
+        HIPCHK(ctx, launch_far_items(w, a));
+        HIPCHK(ctx, launch_mlp_pairs(ctx->scene, ctx->mlp, w, a, true));
+        HIPCHK(ctx, hipStreamSynchronize(a));
         w.rad_complete = true;
     }
-    HIPCHK(ctx, hipDeviceSynchronize());
+    HIPCHK(ctx, wait_workspace(ws));
     if (what == RXGS_EXPORT_PAIRS || what == RXGS_EXPORT_RANGES) {
         // pairs without the per-view padding, ranges in those compact indices
         std::vector<uint32_t> hv((size_t)ws.Dpad);
         std::vector<uint32_t> out;
-        if (ws.Dpad) HIPCHK(ctx, hipMemcpy(hv.data(), ws.pval[ws.pairs_buf].p, hv.size() * 4, hipMemcpyDeviceToHost));
+        if (ws.Dpad) HIPCHK(ctx, aux_copy(ctx, hv.data(), ws.pval[ws.pairs_buf].p, hv.size() * 4, hipMemcpyDeviceToHost));
         if (what == RXGS_EXPORT_PAIRS) {
             // each view's pairs are the first pcount entries of its segment
             // (the sort does not write the padding slots)
@@ -1232,7 +1347,7 @@ extern "C" rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *ds
                 for (uint32_t i = 0; i < ws.h_pcount[v]; i++) out.push_back(hv[(size_t)ws.h_pbase[v] + i]);
         } else {
             std::vector<uint32_t> rg((size_t)ws.V * ws.g.tiles * 2);
-            HIPCHK(ctx, hipMemcpy(rg.data(), ws.ranges.p, rg.size() * 4, hipMemcpyDeviceToHost));
+            HIPCHK(ctx, aux_copy(ctx, rg.data(), ws.ranges.p, rg.size() * 4, hipMemcpyDeviceToHost));
             uint32_t cbase = 0;
             for (int v = 0; v < ws.V; v++) {
                 for (int t = 0; t < ws.g.tiles; t++) {
@@ -1248,18 +1363,18 @@ extern "C" rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *ds
         }
         if (out.size() * 4 != n) return fail(ctx, RXGS_E_STATE, "pair export size mismatch");
         if (dst_on_device)
-            HIPCHK(ctx, hipMemcpy(dst, out.data(), n, hipMemcpyHostToDevice));
+            HIPCHK(ctx, aux_copy(ctx, dst, out.data(), n, hipMemcpyHostToDevice));
         else
             std::memcpy(dst, out.data(), n);
         return RXGS_OK;
     }
     if (what == RXGS_EXPORT_NVIS) {
         if (dst_on_device)
-            HIPCHK(ctx, hipMemcpy(dst, src, n, hipMemcpyHostToDevice));
+            HIPCHK(ctx, aux_copy(ctx, dst, src, n, hipMemcpyHostToDevice));
         else
             std::memcpy(dst, src, n);
         return RXGS_OK;
     }
-    HIPCHK(ctx, hipMemcpy(dst, src, n, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    HIPCHK(ctx, aux_copy(ctx, dst, src, n, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
     return RXGS_OK;
 }

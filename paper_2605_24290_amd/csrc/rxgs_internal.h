@@ -44,16 +44,31 @@ constexpr float NEAR2 = 0.04f;               // cull Gaussians closer than 0.2 m
 constexpr double H_MIN = 1e-6;               // horizontal distance floor (poles)
 constexpr double PAD_REL = 1e-4;             // conservative padding of the
 constexpr double PAD_ABS = 0.01;             //   binning ellipse box, px
+constexpr float AMP_EPS = 1e-8f;             // amplitude stabiliser, sqrt(Re^2 + Im^2 + eps)
 
 struct DevGrid {
     int H, W, tiles_x, tiles_y, tiles;
     double el0, del, daz, idel, idaz;
 };
 
+// Where a context's device buffers come from: the caller's allocator
+// callbacks when given, else hipMalloc / hipFree; or a fixed region whose
+// buffers are carved in order and never freed one by one (the
+// allocation-free entry point: the region is rewound before each call).
+struct Allocator {
+    rxgs_alloc_fn alloc = nullptr;
+    rxgs_free_fn free = nullptr;
+    void *user = nullptr;
+    int device = 0;
+    char *base = nullptr;   // fixed region (nullptr: none)
+    size_t cap = 0, used = 0;
+};
+
 // grow-only device buffer
 struct DevBuf {
     void *p = nullptr;
     size_t cap = 0;
+    Allocator *al = nullptr;   // its source (nullptr: hipMalloc)
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
@@ -96,6 +111,8 @@ struct Mlp {
 };
 
 struct Workspace {
+    Allocator *al = nullptr;   // source of its device buffers (nullptr: the context's)
+    bool fixed_host = false;   // h_pinned is a fixed buffer made at set-up (never regrown)
     // sizes of the last render
     int mode = 0, V = 0, N = 0, Q = 0, R = 1;
     int64_t K = 0, Kp = 0, D = 0, Dpad = 0, nvis_total = 0;
@@ -162,6 +179,8 @@ struct Workspace {
     DevBuf mpart;     // per-wave partial sums of the MLP backward
     DevBuf w1part;    // per-chunk partial sums of dW1 (Gaussian part)
     DevBuf mred;      // FP64 group sums of the two-stage column reductions
+    DevBuf gfeat_tmp; // K x 32 feature gradients before they are added (accumulating backward)
+    DevBuf gmlp_tmp;  // MLP gradients before they are added (accumulating backward)
     DevBuf live;      // per (view, 32 sorted positions): composited (lazy forward) or some dL/ds nonzero (backward)
     DevBuf items_live;   // MLP work items of the live blocks (lazy forward)
     bool lazy = false;   // this render evaluates the pair MLP on live blocks only
@@ -181,6 +200,8 @@ struct Workspace {
     size_t h_pinned_cap = 0;
     hipEvent_t staged = nullptr;   // last host-to-device copy out of h_pinned
     hipEvent_t counted = nullptr;  // counters copied to h_pinned
+    hipEvent_t done = nullptr;     // end of the last render or backward into this workspace
+    int pair_bits = 0;             // key bits of the last pair sort
 };
 
 // Per-stage event timing (rxgs_profile_enable / rxgs_profile_read).
@@ -227,6 +248,8 @@ struct rxgs_ctx {
     rxgs::Profiler prof;
     bool near_cut = false;     // emit each view's nearest entries first (rxgs_set_near_cut)
     int64_t views_redone = 0;  // views redone over all their entries
+    hipStream_t aux = nullptr; // private non-blocking stream of the saved-state queries and exports
+    rxgs::Allocator alloc;     // the context's device allocations
 };
 
 struct rxgs_saved {
@@ -272,6 +295,9 @@ hipError_t launch_zero_visible(uint32_t *p, int64_t Kp, int wpr, const unsigned 
 hipError_t sort_pairs_u32(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
                           int64_t seg_len, const int4 *segtab, hipStream_t st, bool zeroed = false);
 size_t sort_ws_bytes(uint32_t n, int bits, int nseg);
+// the sort's counter of look-back waits that expired and took the direct count
+// (inside wsb; zeroed with the rest of the scratch)
+uint32_t *sort_fallback_word(DevBuf &wsb, uint32_t n, int bits, int nseg);
 hipError_t launch_emit1(const Scene &sc, Workspace &ws, const DevGrid &g, hipStream_t st);
 hipError_t launch_emit2(Workspace &ws, const DevGrid &g, size_t sort_words, hipStream_t st);
 uint32_t *emit_words(Workspace &ws);
@@ -289,7 +315,12 @@ hipError_t launch_far_all(Workspace &ws, hipStream_t st);
 int *far_count(Workspace &ws);
 hipError_t launch_reduce_outputs(Workspace &ws, float *power, float *csum, hipStream_t st);
 // backward (backward.hip)
-hipError_t launch_blend_bwd(Workspace &ws, const float *C, const float *dC, const float *dP, hipStream_t st);
+hipError_t launch_blend_bwd(Workspace &ws, const float *C, const float *dC, const float *dP, const float *dA,
+                            hipStream_t st);
+// amp[j, p] = sqrt(Re^2 + Im^2 + AMP_EPS) of C (N x 2 x P) (kernels.hip)
+hipError_t launch_amplitude(const float *C, float *amp, int N, size_t P, hipStream_t st);
+// out[i] += add[i] for n floats (kernels.hip)
+hipError_t launch_add_f32(float *out, const float *add, size_t n, hipStream_t st);
 hipError_t launch_rad_bwd(const Scene &sc, Workspace &ws, float *grad, hipStream_t st);
 hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *gfeat, float *gmlp, hipStream_t st);
 hipError_t launch_project_bwd(const Scene &sc, Workspace &ws, const rxgs_grads &gr, hipStream_t st);
@@ -302,7 +333,7 @@ hipError_t launch_blend_weights(Workspace &ws, hipStream_t st);
 int *live_count(Workspace &ws);
 size_t live_count_offset(const Workspace &ws);
 
-bool grow(DevBuf &b, size_t bytes);
+bool grow(DevBuf &b, size_t bytes, Allocator *al);
 void release(DevBuf &b);
 
 }  // namespace rxgs

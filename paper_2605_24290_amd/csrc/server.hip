@@ -160,8 +160,9 @@ rxgs_status launch_batch(rxgs_server *s, Slot &sl, std::vector<Ticket *> &batch)
         std::memcpy(sl.h_in + 3 * Q + 3 * sl.offs[q], batch[q]->rx.data(), (size_t)batch[q]->n * 12);
         rx_off[q + 1] = rx_off[q] + batch[q]->n;
     }
-    if (!grow(sl.d_tx, (size_t)Q * 12) || !grow(sl.d_rx, (size_t)N * 12) || !grow(sl.d_P, (size_t)N * 4) ||
-        !grow(sl.d_C, (size_t)N * 2 * P * 4))
+    rxgs::Allocator *al = &s->ctx->alloc;
+    if (!grow(sl.d_tx, (size_t)Q * 12, al) || !grow(sl.d_rx, (size_t)N * 12, al) || !grow(sl.d_P, (size_t)N * 4, al) ||
+        !grow(sl.d_C, (size_t)N * 2 * P * 4, al))
         return RXGS_E_OOM;
     if (hipMemcpyAsync(sl.d_tx.p, sl.h_in, (size_t)Q * 12, hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
         hipMemcpyAsync(sl.d_rx.p, sl.h_in + 3 * Q, (size_t)N * 12, hipMemcpyHostToDevice, sl.stream) != hipSuccess) {
@@ -169,7 +170,7 @@ rxgs_status launch_batch(rxgs_server *s, Slot &sl, std::vector<Ticket *> &batch)
         return RXGS_E_DEVICE;
     }
     rxgs_status rs = rxgs_render(ctx, mode, Q, sl.d_tx.as<float>(), rx_off.data(), N, sl.d_rx.as<float>(),
-                                 sl.d_C.as<float>(), sl.d_P.as<float>(), nullptr, sl.saved, sl.stream);
+                                 sl.d_C.as<float>(), sl.d_P.as<float>(), nullptr, nullptr, sl.saved, sl.stream);
     if (rs != RXGS_OK) return rs;
     if (hipMemcpyAsync(sl.h_P, sl.d_P.p, (size_t)N * 4, hipMemcpyDeviceToHost, sl.stream) != hipSuccess) {
         (void)hipGetLastError();

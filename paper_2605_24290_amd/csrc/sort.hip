@@ -24,9 +24,13 @@
 // Look-back progress: a workgroup only waits for tiles with a smaller ticket,
 // whose workgroups took their tickets earlier and are therefore resident; they
 // publish their aggregates before waiting themselves, so every wait ends.  A
-// wait is still bounded; on expiry the kernel records an error word instead
-// of hanging.
+// wait is still bounded: on expiry the workgroup counts the digit totals of
+// the segment's earlier tiles directly from their input keys (exact, slow),
+// publishes them like a look-back result and adds one to the sort's
+// fallback counter, so the order is right either way.
 #include "device_common.h"
+
+#include <cstdlib>
 
 namespace rxgs {
 
@@ -35,7 +39,6 @@ namespace {
 constexpr uint32_t LB_AGG = 1u << 30;    // status word: aggregate of this tile only
 constexpr uint32_t LB_PRE = 1u << 31;    // status word: inclusive prefix up to this tile
 constexpr uint32_t LB_MASK = LB_AGG - 1;
-constexpr int LB_SPIN_MAX = 1 << 20;
 constexpr uint32_t SORT_DROP = 0xFFFFFFFFu;   // dropped key
 constexpr int TICKET_STRIDE = 32;             // one ticket counter per 128-byte line
 
@@ -100,7 +103,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict_
                                                      uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                      uint32_t n, int pass, int passes, SortSeg sm,
                                                      const uint32_t *__restrict__ hist, uint32_t *status,
-                                                     uint32_t *ticket, uint32_t *err)
+                                                     uint32_t *ticket, uint32_t *err, int spin_max)
 {
     constexpr int TILEN = BLOCK * ITEMS;
     constexpr int WCH = 64 * ITEMS;   // keys per wave
@@ -170,15 +173,16 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict_
     // decoupled look-back over the earlier tiles of this segment, digit t
     uint32_t *mine = status + (size_t)tile * 256 + t;
     uint32_t excl = 0;
+    bool gave_up = false;
     if (tile == first) {
         __hip_atomic_store(mine, LB_PRE | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
         __hip_atomic_store(mine, LB_AGG | cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // eight predecessors in flight per step; tiles before the segment's
-        // first count as an empty prefix
+        // first count as an empty prefix (spin_max < 0: no look-back at all)
         int64_t j = (int64_t)tile - 1;
         int spins = 0;
-        while (true) {
+        while (spin_max >= 0) {
             uint32_t w8[8];
 #pragma unroll
             for (int q = 0; q < 8; q++) {
@@ -200,14 +204,34 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict_
             if (done) break;
             j -= q;
             if (q < 8) {   // predecessor j has not published yet
-                if (++spins > LB_SPIN_MAX) {
-                    atomicOr(err, 1u);
+                if (++spins > spin_max) {
+                    gave_up = true;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
         }
-        __hip_atomic_store(mine, LB_PRE | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        gave_up |= spin_max < 0;
+        if (!gave_up)
+            __hip_atomic_store(mine, LB_PRE | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // an expired wait: the digit totals of the segment's earlier tiles, counted
+    // from their input keys (positions seg0 .. tile0 hold keys in every pass)
+    if (__syncthreads_or(gave_up)) {
+        s_glob[t] = 0;
+        __syncthreads();
+        const size_t e0 = (size_t)first * TILEN, e1 = (size_t)tile * TILEN;
+        for (size_t i = e0 + t; i < e1; i += BLOCK) {
+            const uint32_t k = kin[i];
+            if (k != SORT_DROP) atomicAdd(&s_glob[(k >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (gave_up) {
+            excl = s_glob[t];
+            __hip_atomic_store(mine, LB_PRE | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (t == 0) atomicAdd(err, 1u);
+        __syncthreads();
     }
 
     // digit starts in the tile
@@ -241,6 +265,17 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict_
     }
 }
 
+// Bound of a look-back wait, in polls of a predecessor's status.
+// RXGS_SORT_SPIN_LIMIT overrides it (a negative value skips the look-back and
+// takes the direct count in every tile after a segment's first: the path an
+// expired wait takes, forced from the host so that it can be tested).
+int sort_spin_limit()
+{
+    const char *e = std::getenv("RXGS_SORT_SPIN_LIMIT");
+    if (e && e[0]) return std::atoi(e);
+    return 1 << 20;
+}
+
 template <int ITEMS>
 hipError_t sort_run(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
                     int64_t seg_len, const int4 *segtab, bool zeroed, hipStream_t st)
@@ -264,11 +299,12 @@ hipError_t sort_run(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t 
     }
     hipLaunchKernelGGL(k_sort_hist<ITEMS>, dim3(ntiles), dim3(BLOCK), 0, st, keys[cur].as<uint32_t>(), n, passes, sm,
                        hist);
+    const int spin_max = sort_spin_limit();
     for (int p = 0; p < passes; p++) {
         hipLaunchKernelGGL(k_sort_pass<ITEMS>, dim3(ntiles), dim3(BLOCK), 0, st, keys[cur].as<uint32_t>(),
                            vals[cur].as<uint32_t>(), keys[cur ^ 1].as<uint32_t>(), vals[cur ^ 1].as<uint32_t>(), n, p,
                            passes, sm, hist, status + (size_t)p * ntiles * 256,
-                           tickets + (size_t)p * nseg * TICKET_STRIDE, err);
+                           tickets + (size_t)p * nseg * TICKET_STRIDE, err, spin_max);
         cur ^= 1;
     }
     return hipGetLastError();
@@ -277,6 +313,16 @@ hipError_t sort_run(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t 
 }  // namespace
 
 int sort_items_for(uint32_t n) { return n <= SMALL_SORT ? 4 : 16; }
+
+uint32_t *sort_fallback_word(DevBuf &wsb, uint32_t n, int bits, int nseg)
+{
+    if (n == 0 || bits <= 0 || nseg <= 0 || !wsb.p) return nullptr;
+    const uint32_t tilen = BLOCK * (uint32_t)sort_items_for(n);
+    const size_t ntiles = (n + tilen - 1) / tilen;
+    const size_t passes = (size_t)(bits + 7) / 8;
+    return wsb.as<uint32_t>() + (size_t)nseg * passes * 256 + passes * ntiles * 256 +
+           passes * (size_t)nseg * TICKET_STRIDE;
+}
 
 size_t sort_ws_bytes(uint32_t n, int bits, int nseg)
 {

@@ -42,14 +42,14 @@ class CGrid(ctypes.Structure):
 class CGrads(ctypes.Structure):
     _fields_ = [("means", c_void_p), ("log_scales", c_void_p), ("quats", c_void_p),
                 ("logits", c_void_p), ("radiance", c_void_p), ("features", c_void_p),
-                ("mlp", c_void_p)]
+                ("mlp", c_void_p), ("accumulate", c_int32)]
 
 
 class CSavedInfo(ctypes.Structure):
     _fields_ = [("K", c_int64), ("K_pad", c_int64), ("V", c_int64), ("N", c_int64),
                 ("D", c_int64), ("n_visible", c_int64), ("tiles", c_int64), ("tiles_x", c_int64),
                 ("n_composited_px", c_int64), ("n_composited", c_int64), ("n_evaluated_px", c_int64),
-                ("n_walked_px", c_int64)]
+                ("n_walked_px", c_int64), ("n_sort_fallbacks", c_int64)]
 
 
 class CServerOpts(ctypes.Structure):
@@ -72,7 +72,10 @@ class CStageTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", c_int64), ("total_ms", c_double)]
 
 
-EXPORTED = ("rxgs_create", "rxgs_destroy", "rxgs_last_error", "rxgs_scene_upload", "rxgs_mlp_upload",
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_int, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, ctypes.c_size_t, c_int, c_void_p)
+
+EXPORTED = ("rxgs_create", "rxgs_create_with_allocator", "rxgs_destroy", "rxgs_last_error", "rxgs_scene_upload", "rxgs_mlp_upload",
             "rxgs_saved_create", "rxgs_saved_destroy", "rxgs_render", "rxgs_render_backward",
             "rxgs_saved_info", "rxgs_saved_export", "rxgs_version", "rxgs_profile_enable",
             "rxgs_profile_read", "rxgs_server_start", "rxgs_server_submit", "rxgs_server_poll",
@@ -93,6 +96,8 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     vp = c_void_p
     L.rxgs_create.argtypes = [c_int, POINTER(CGrid), POINTER(vp)]
+    L.rxgs_create_with_allocator.argtypes = [c_int, POINTER(CGrid), ALLOC_FN, FREE_FN, vp, POINTER(vp)]
+    L.rxgs_create_with_allocator.restype = c_int
     L.rxgs_destroy.argtypes = [vp]
     L.rxgs_destroy.restype = None
     L.rxgs_last_error.argtypes = [vp]
@@ -103,9 +108,9 @@ def lib():
     L.rxgs_saved_create.argtypes = [vp, POINTER(vp)]
     L.rxgs_saved_destroy.argtypes = [vp]
     L.rxgs_saved_destroy.restype = None
-    L.rxgs_render.argtypes = [vp, c_int, c_int, vp, POINTER(c_int32), c_int, vp, vp, vp, vp, vp, vp]
+    L.rxgs_render.argtypes = [vp, c_int, c_int, vp, POINTER(c_int32), c_int, vp, vp, vp, vp, vp, vp, vp]
     if hasattr(L, "rxgs_render_backward"):
-        L.rxgs_render_backward.argtypes = [vp, vp, vp, vp, vp, POINTER(CGrads), vp]
+        L.rxgs_render_backward.argtypes = [vp, vp, vp, vp, vp, vp, POINTER(CGrads), vp]
     L.rxgs_saved_info.argtypes = [vp, POINTER(CSavedInfo)]
     L.rxgs_saved_export.argtypes = [vp, c_int, vp, c_int64, c_int]
     L.rxgs_server_start.argtypes = [vp, POINTER(CServerOpts), POINTER(vp)]
@@ -122,7 +127,7 @@ def lib():
     for name in ("rxgs_server_start", "rxgs_server_submit", "rxgs_server_poll", "rxgs_server_cancel",
                  "rxgs_server_stats", "rxgs_server_stop"):
         getattr(L, name).restype = c_int
-    L.rxgs_render_chunked.argtypes = [vp, c_int, c_int, vp, POINTER(c_int32), c_int, vp, vp, vp, vp, c_int64,
+    L.rxgs_render_chunked.argtypes = [vp, c_int, c_int, vp, POINTER(c_int32), c_int, vp, vp, vp, vp, vp, c_int64,
                                       POINTER(c_int32), vp]
     L.rxgs_render_chunked.restype = c_int
     L.rxgs_view_flags.argtypes = [vp, vp, c_int32, POINTER(c_int32)]
@@ -199,16 +204,57 @@ class Saved:
             pass
 
 
-class Renderer:
-    """One librxgs context on a device, for one angular grid."""
+class TorchAllocator:
+    """Device memory for a context from PyTorch's caching allocator (the
+    allocator callbacks of rxgs_create_with_allocator).  Counts what passes
+    through it."""
 
-    def __init__(self, grid, device: int = 0):
+    def __init__(self):
+        self.live = {}          # pointer -> bytes
+        self.n_alloc = 0
+        self.bytes_alloc = 0
+        self.n_free = 0
+        self._cb = (ALLOC_FN(self._alloc), FREE_FN(self._free))
+
+    @property
+    def live_bytes(self) -> int:
+        return sum(self.live.values())
+
+    def _alloc(self, nbytes, device, user):
+        try:
+            p = _torch().cuda.caching_allocator_alloc(int(nbytes), int(device))
+        except Exception:
+            return None
+        self.live[int(p)] = int(nbytes)
+        self.n_alloc += 1
+        self.bytes_alloc += int(nbytes)
+        return int(p)
+
+    def _free(self, ptr, nbytes, device, user):
+        if ptr is None:
+            return
+        self.live.pop(int(ptr), None)
+        self.n_free += 1
+        _torch().cuda.caching_allocator_delete(int(ptr))
+
+
+class Renderer:
+    """One librxgs context on a device, for one angular grid.  allocator: None
+    (hipMalloc) or a TorchAllocator (device buffers from PyTorch's caching
+    allocator)."""
+
+    def __init__(self, grid, device: int = 0, allocator: TorchAllocator | None = None):
         torch = _torch()
         self.device = torch.device("cuda", device)
         self.grid = grid
         self._cgrid = CGrid(int(grid.H), int(grid.W), 0, float(grid.el0), float(grid.del_el))
         ctx = c_void_p()
-        _check(lib().rxgs_create(device, byref(self._cgrid), byref(ctx)), None)
+        self.allocator = allocator
+        if allocator is None:
+            _check(lib().rxgs_create(device, byref(self._cgrid), byref(ctx)), None)
+        else:
+            _check(lib().rxgs_create_with_allocator(device, byref(self._cgrid), allocator._cb[0], allocator._cb[1],
+                                                    None, byref(ctx)), None)
         self._ctx = ctx
         self.K = 0
         self.use_mlp = False
@@ -217,6 +263,7 @@ class Renderer:
         return c_void_p(_torch().cuda.current_stream(self.device).cuda_stream)
 
     def upload_scene(self, means, log_scales, quats, logits, radiance=None, features=None):
+        self._autograd_scene = None   # the autograd wrapper's record of what is resident
         ts = [_dev_f32(x, self.device) for x in (means, log_scales, quats, logits, radiance, features)]
         K = int(ts[0].shape[0])
         self._scene_keep = ts
@@ -225,6 +272,7 @@ class Renderer:
         self.use_mlp = features is not None
 
     def upload_mlp(self, params):
+        self._autograd_mlp = None
         if isinstance(params, (list, tuple)):
             params = np.concatenate([np.asarray(p, dtype=np.float32).ravel() for p in params])
         t = _dev_f32(params, self.device).reshape(-1)
@@ -233,8 +281,9 @@ class Renderer:
         _check(lib().rxgs_mlp_upload(self._ctx, _ptr(t), 1, self._stream()), self._ctx)
 
     def render(self, rx, tx=None, rx_off=None, mode: str = "tx", saved: Saved | None = None,
-               want_csum: bool = False, out=None):
-        """Render receivers rx (N x 3).  Returns (C (N,2,H,W), power (N), csum or None)."""
+               want_csum: bool = False, out=None, want_amp: bool = False):
+        """Render receivers rx (N x 3).  Returns (C (N,2,H,W), power (N), csum or None), or with
+        want_amp=True (C, power, csum or None, amplitude (N,H,W))."""
         torch = _torch()
         rx_t = _dev_f32(rx, self.device).reshape(-1, 3)
         N = int(rx_t.shape[0])
@@ -259,8 +308,11 @@ class Renderer:
         else:
             C, P = out
         S = torch.empty((N, 2), device=self.device, dtype=torch.float32) if want_csum else None
+        A = torch.empty((N, H, W), device=self.device, dtype=torch.float32) if want_amp else None
         _check(lib().rxgs_render(self._ctx, m, Q, _ptr(tx_t), off_arr, N, _ptr(rx_t), _ptr(C), _ptr(P), _ptr(S),
-                                 None if saved is None else saved._h, self._stream()), self._ctx)
+                                 _ptr(A), None if saved is None else saved._h, self._stream()), self._ctx)
+        if want_amp:
+            return C, P, S, A
         return C, P, S
 
     def render_chunked(self, rx, tx=None, rx_off=None, mode: str = "tx", budget_bytes: int = 0, out=None):
@@ -289,11 +341,13 @@ class Renderer:
             C, P = out
         nch = c_int32(0)
         _check(lib().rxgs_render_chunked(self._ctx, m, Q, _ptr(tx_t), off_arr, N, _ptr(rx_t), _ptr(C), _ptr(P), None,
-                                         int(budget_bytes), byref(nch), self._stream()), self._ctx)
+                                         None, int(budget_bytes), byref(nch), self._stream()), self._ctx)
         return C, P, int(nch.value)
 
-    def backward(self, saved: Saved, C, dC, dP=None, grads: dict | None = None) -> dict:
-        """Gradients w.r.t. the scene (and MLP) given dL/dC and dL/dpower."""
+    def backward(self, saved: Saved, C, dC, dP=None, grads: dict | None = None, dA=None,
+                 accumulate: bool = False) -> dict:
+        """Gradients w.r.t. the scene (and MLP) given dL/dC (or None), dL/dpower and dL/damplitude.
+        With accumulate=True the gradients are added into the given `grads` tensors."""
         torch = _torch()
         K = self.K
         dev = self.device
@@ -305,11 +359,15 @@ class Renderer:
                 grads["mlp"] = torch.empty((MLP_NPARAM,), device=dev)
             else:
                 grads["radiance"] = torch.empty((K, 2), device=dev)
-        cg = CGrads(*[None if grads.get(f) is None else grads[f].data_ptr() for f, _ in CGrads._fields_])
-        dC = dC.contiguous()
+        if accumulate and not grads:
+            raise ValueError("accumulate needs the gradient tensors to add into")
+        cg = CGrads(*[None if grads.get(f) is None else grads[f].data_ptr() for f, _ in CGrads._fields_[:-1]],
+                    1 if accumulate else 0)
+        dC_t = None if dC is None else dC.contiguous()
         dP_t = None if dP is None else _dev_f32(dP, dev)
-        _check(lib().rxgs_render_backward(self._ctx, saved._h, _ptr(C.contiguous()), _ptr(dC), _ptr(dP_t),
-                                          byref(cg), self._stream()), self._ctx)
+        dA_t = None if dA is None else _dev_f32(dA, dev)
+        _check(lib().rxgs_render_backward(self._ctx, saved._h, _ptr(C.contiguous()), _ptr(dC_t), _ptr(dP_t),
+                                          _ptr(dA_t), byref(cg), self._stream()), self._ctx)
         return grads
 
     def near_cut(self, on: bool = True):
@@ -438,5 +496,6 @@ def version() -> str:
     return lib().rxgs_version().decode()
 
 
-__all__ = ["Renderer", "Saved", "Server", "RxgsError", "lib", "version", "plan_batch", "workspace_estimate",
+__all__ = ["Renderer", "Saved", "Server", "TorchAllocator", "RxgsError", "lib", "version", "plan_batch",
+           "workspace_estimate",
            "MODE_TX", "MODE_RX", "EXPORTED"]

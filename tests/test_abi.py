@@ -46,7 +46,7 @@ def test_version_and_create_rejects_bad_grid():
 def test_null_context_calls_are_rejected():
     from paper_2605_24290_amd import rxgs
     L = rxgs.lib()
-    assert L.rxgs_render(None, 0, 1, None, None, 1, None, None, None, None, None, None) == 1
+    assert L.rxgs_render(None, 0, 1, None, None, 1, None, None, None, None, None, None, None) == 1
     assert L.rxgs_scene_upload(None, 0, None, None, None, None, None, None, 0, None) == 1
     assert L.rxgs_mlp_upload(None, None, 0, None) == 1
     assert L.rxgs_saved_info(None, None) == 1
