@@ -21,12 +21,16 @@
  *   phi~ = (1 + alpha) phi_k + beta    (complex, per l and c)    (eq. film_apply)
  *   probes q_s = p + t_s (r - p), t_s = 0.05 + 0.9 s / (S - 1)   (App. E.5)
  *   T_k = prod_s (1 - V(q_s)), rho_k = mean_s V(q_s)             (eq. transmittance)
- *   (alpha', beta')_{l,c} = MLP_l([(r - p)/|r - p|; |r - p|; T_k; rho_k])
+ *   (alpha', beta')_c = MLP_l([(r - p)/|r - p|; |r - p|; T_k; rho_k])
  *                                                                (eq. local)
- *   phi = (1 + alpha') phi~ + beta'                              (eq. combined_local)
+ *   phi_{l,c} = (1 + alpha'_c) phi~_{l,c} + beta'_c              (eq. combined_local)
  *   s_c = sum_l phi_{l,c} B_l(d)                                 (App. E.2; Alg. 1 l. eval_fle)
  *
- * with complex products throughout, and B_l the basis:
+ * with complex products throughout.  The local branch gives one complex
+ * scale and shift per (receiver, Gaussian, channel), shared by every
+ * component: App. E.5 calls them per-Gaussian parameters (the global ones
+ * per-component), and Sec. 4.3.2 puts the conditioning's cost at O(L + K).
+ * B_l is the basis:
  *   FLE (complex): B_{deg,ord} = N P_deg^|ord|(cos th) e^{i ord ph}, so that
  *     Re s = sum [a cos(ord ph) - b sin(ord ph)] N P and
  *     Im s = sum [a sin(ord ph) + b cos(ord ph)] N P       (App. E.2)
@@ -213,7 +217,7 @@ int orc_occupancy(int K, const double *means, const double *log_scales, const do
  *               W3 (4C x Hd), b3 (4C); output rows 4c + (alpha re, alpha im,
  *               beta re, beta im)
  *   local MLP:  W1 (Hd x 6), b1 (Hd), W2 (Hd x Hd), b2 (Hd),
- *               W3 (4LC x Hd), b3 (4LC); output rows 4 (l C + c) + (...)
+ *               W3 (4C x Hd), b3 (4C); output rows 4c + (...)
  * Matrices row-major (out x in). */
 typedef struct {
     int L, C, F, H;
@@ -227,7 +231,7 @@ static long rc_count(int lmax, int C, int F, int H)
     const long L = (long)(lmax + 1) * (lmax + 1);
     const long gin = 6L * F + 2 + RC_EMB;
     return 9L * F + L * RC_EMB + (H * gin + H + (long)H * H + H + 4L * C * H + 4L * C) +
-           (H * 6L + H + (long)H * H + H + 4L * L * C * H + 4L * L * C);
+           (H * 6L + H + (long)H * H + H + 4L * C * H + 4L * C);
 }
 
 long orc_rxcond_param_count(int lmax, int C, int F, int H) { return rc_count(lmax, C, F, H); }
@@ -249,7 +253,7 @@ static rc_params rc_view(const double *q, int lmax, int C, int F, int H)
     r.lb1 = q; q += H;
     r.l2 = q; q += H * H;
     r.lb2 = q; q += H;
-    r.l3 = q; q += 4 * r.L * C * H;
+    r.l3 = q; q += 4 * C * H;
     r.lb3 = q;
     return r;
 }
@@ -354,7 +358,7 @@ static void *rad_worker(void *arg)
     rad_ctx *c = arg;
     const int L = c->P.L, C = c->C, H = c->H;
     double *ab = malloc(sizeof(double) * (size_t)L * C * 4);
-    double *loc = malloc(sizeof(double) * (size_t)L * C * 4);
+    double *loc = malloc(sizeof(double) * (size_t)C * 4);
     double *h1 = malloc(sizeof(double) * H), *h2 = malloc(sizeof(double) * H);
     double *B = malloc(sizeof(double) * (size_t)L * 2);
     for (;;) {
@@ -368,7 +372,7 @@ static void *rad_worker(void *arg)
             double f[6];
             local_features(r, p, c->grid, c->G, c->lo, c->hi, c->S, f);
             if (c->feats) memcpy(c->feats + ((size_t)j * c->K + k) * 6, f, sizeof f);
-            mlp3(f, 6, H, 4 * L * C, c->P.l1, c->P.lb1, c->P.l2, c->P.lb2, c->P.l3, c->P.lb3, h1, h2, loc);
+            mlp3(f, 6, H, 4 * C, c->P.l1, c->P.lb1, c->P.l2, c->P.lb2, c->P.l3, c->P.lb3, h1, h2, loc);
             const double dx = p[0] - cen[0], dy = p[1] - cen[1], dz = p[2] - cen[2];
             if (orc_basis(c->kind, c->lmax, dx, dy, dz, B) != 0)
                 for (int i = 0; i < 2 * L; i++) B[i] = 0.0;   /* Gaussian at the view centre */
@@ -376,7 +380,7 @@ static void *rad_worker(void *arg)
                 double sr = 0.0, si = 0.0;
                 for (int l = 0; l < L; l++) {
                     const double *g = ab + ((size_t)l * C + ch) * 4;
-                    const double *q = loc + ((size_t)l * C + ch) * 4;
+                    const double *q = loc + (size_t)ch * 4;
                     const double *ph = c->coeffs + (((size_t)k * L + l) * C + ch) * 2;
                     double tr, ti, ur, ui, vr, vi;
                     cmul(1.0 + g[0], g[1], ph[0], ph[1], &tr, &ti);         /* (1 + alpha) phi */

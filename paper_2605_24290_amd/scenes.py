@@ -231,12 +231,13 @@ def rxcond_shapes(lmax: int, C: int, F: int, H: int) -> list:
     """Shapes of the conditioning parameters, in the order of the flat vector:
     Fourier frequency vectors (3F x 3), component embeddings (L x 16), the
     global MLP (W1, b1, W2, b2, W3, b3; input 6F + 2 + 16, output 4C) and the
-    local MLP (input 6, output 4LC); matrices are (out, in)."""
+    local MLP (input 6, output 4C: one complex scale and shift per channel,
+    shared by the components); matrices are (out, in)."""
     L = (lmax + 1) ** 2
     gin = 6 * F + 2 + EMB_DIM
     return [(3 * F, 3), (L, EMB_DIM),
             (H, gin), (H,), (H, H), (H,), (4 * C, H), (4 * C,),
-            (H, 6), (H,), (H, H), (H,), (4 * L * C, H), (4 * L * C,)]
+            (H, 6), (H,), (H, H), (H,), (4 * C, H), (4 * C,)]
 
 
 @dataclasses.dataclass

@@ -12,7 +12,9 @@ routines:
   radiance is the plain basis expansion of the base coefficients;
 * a global final layer with zero weights and bias (alpha, beta) applies the
   affine map (1 + alpha) phi + beta to every component (eq. film_apply); a
-  local one does the same after it (eq. combined_local);
+  local one applies its per-Gaussian (alpha', beta') after it, the same for
+  every component (eq. combined_local; App. E.5 "per-Gaussian scale and
+  shift"), so beta' adds beta' sum_l B_l to the radiance;
 * special weights that pass the inputs through the global MLP expose the
   receiver encoding (eq. rx_enc), the (degree, order) features and the
   embeddings, and through the local MLP its six inputs (eq. local);
@@ -110,21 +112,21 @@ def test_zero_final_layers_give_the_plain_basis_expansion(oracle_lib, kind):
 
 def test_affine_modulations_closed_form(oracle_lib):
     """Global final layer W3 = 0 with bias (alpha, beta) per channel, then a
-    local final layer W3 = 0 with bias (alpha', beta') per (component,
-    channel): phi -> (1 + alpha') ((1 + alpha) phi + beta) + beta'."""
+    local final layer W3 = 0 with bias (alpha', beta') per channel, shared by
+    the components: phi -> (1 + alpha') ((1 + alpha) phi + beta) + beta'."""
     wl = _small_scene(K=5, seed=4)
     lmax, C = 3, 2
     m = S.make_rxcond_model(wl.scene.K, kind=O.BASIS_FLE, lmax=lmax, C=C, F=4, H=16, zero_final=True)
     P = S.split_rxcond_params(m)
     rng = np.random.default_rng(9)
     gb = rng.normal(size=4 * C).astype(np.float32)
-    lb = rng.normal(size=4 * m.L * C).astype(np.float32)
+    lb = rng.normal(size=4 * C).astype(np.float32)
     P[7][:] = gb
     P[13][:] = lb
     cen = wl.tx.astype(np.float64)
     rad = O.rxcond_radiance(m, wl.scene, cen, wl.rx, [0, 0], occ=O.occupancy(wl.scene, 16))
     g = gb.astype(np.float64).reshape(C, 4)
-    q = lb.astype(np.float64).reshape(m.L, C, 4)
+    q = lb.astype(np.float64).reshape(C, 4)
     for k in range(wl.scene.K):
         B = O.basis(O.BASIS_FLE, lmax, wl.scene.means[k].astype(np.float64) - cen[0])
         Bz = B[:, 0] + 1j * B[:, 1]
@@ -188,7 +190,7 @@ def test_global_branch_inputs_by_pass_through_weights(oracle_lib):
 
 def test_local_branch_inputs_by_pass_through_weights(oracle_lib):
     """Local MLP with identity layers (width 6) and a final layer reading input
-    i into alpha'_re of component 0: the radiance of phi = (1, 0) in component
+    i into alpha'_re of channel 0: the radiance of phi = (1, 0) in component
     0 seen along +z is (1 + relu(f_i)) / sqrt(4 pi), f = [(r - p)/|r - p|;
     |r - p|; T; rho] with the local features reported by the oracle."""
     sc = S.Scene(np.array([[0.0, 0.0, 1.0], [0.4, 0.1, 1.2]]), np.full((2, 3), -1.0),
