@@ -110,8 +110,10 @@ const char *rxgs_last_error(const rxgs_ctx *ctx);
  * (K x 4, (w, x, y, z), normalised inside the renderer) and opacity logits
  * (K; opacity = sigmoid(logit)).  Radiance is either direct, radiance
  * (K x 2, Re/Im, the same for every receiver), or per-Gaussian features
- * (K x 32) fed to the conditioning MLP; exactly one of the two is non-NULL
- * (with K = 0 both may be NULL: an empty direct-radiance scene).
+ * (K x 32) fed to the conditioning MLP; at most one of the two is non-NULL.
+ * With both NULL the scene is geometry only: rxgs_render refuses it
+ * (E_STATE) unless K = 0, and rxgs_render_rxcond takes its radiance from a
+ * conditioning model (rxgs_rxcond_upload).
  * The library copies everything into its own device buffers (the scene stays
  * resident for serving).  src_on_device: 1 if the pointers are device memory,
  * 0 for host memory.  Validates that every value is finite (E_INVALID).
@@ -397,6 +399,99 @@ int64_t rxgs_views_redone(const rxgs_ctx *ctx);
  * not NULL.  Errors: E_INVALID, E_DEVICE.
  */
 rxgs_status rxgs_view_flags(rxgs_ctx *ctx, uint32_t *out, int32_t max_views, int32_t *n_views);
+
+/*
+ * The paper's receiver-conditioned radiance (Sec. 4.3.2 eqs. rx_enc, film,
+ * film_apply, transmittance, local, combined_local; App. E.2 and E.5; Alg. 1
+ * stage 2).  Per Gaussian k a base coefficient phi_k[l][c] (complex) for each
+ * basis component l = (deg, ord), index deg^2 + deg + ord, and channel c.
+ * Per receiver j at r and Gaussian k at p, seen from the view centre c_v
+ * along d = p - c_v:
+ *   gamma(r) = [sin(w_i . r), cos(w_i . r)], i < 3F        (eq. rx_enc)
+ *   (alpha_l, beta_l)[c] = MLP_g([gamma(r); deg/m, ord/m; e_l]),
+ *       m = max(lmax, 1)                                    (eq. film)
+ *   phi~ = (1 + alpha_l) phi_k + beta_l                    (eq. film_apply)
+ *   q_s = p + t_s (r - p), t_s = 0.05 + 0.9 s / (S - 1); V(q) the occupancy of
+ *   the voxel containing q (0 outside the grid); T = prod (1 - V(q_s)),
+ *   rho = mean V(q_s)                                      (eq. transmittance)
+ *   (alpha', beta')[c] = MLP_l([(r - p)/|r - p|; |r - p|; T; rho]), one pair
+ *   per (receiver, Gaussian, channel) shared by all components (App. E.5:
+ *   "per-Gaussian" scale and shift)                        (eq. local)
+ *   s_c = sum_l ((1 + alpha') phi~_{l,c} + beta') B_l(d)   (eq. combined_local; App. E.2)
+ * with complex products and B_l the basis: RXGS_BASIS_FLE the complex
+ * Fourier-Legendre basis N_lm P_l^|m|(cos th) e^{i m ph} (App. E.2; N_lm the
+ * orthonormal factor, P without the Condon-Shortley phase, th the polar angle
+ * of d from +z, ph its azimuth); RXGS_BASIS_SH the real spherical harmonics
+ * of the RF-3DGS backbone (Sec. 5): N P for m = 0, sqrt2 N P cos(m ph) for
+ * m > 0, sqrt2 N P_l^|m| sin(|m| ph) for m < 0.  MLPs have three Linear
+ * layers with ReLU after the first two (App. E.5).  The occupancy grid
+ * (App. E.5) spans the box of the Gaussian means with G^3 voxels, voxel i at
+ * lo + (i + 1/2)(hi - lo)/G per axis (an axis narrower than 1e-6 m gets
+ * hi = lo + 1e-6), and holds V(x) = 1 - prod_k (1 - o_k exp(-|x - p_k|^2 /
+ * (2 sigma_k^2))) over the Gaussians with |x - p_k| <= 2 sigma_k, o_k =
+ * sigmoid(logit_k), sigma_k = the largest of its three scales.
+ */
+enum { RXGS_BASIS_FLE = 0, RXGS_BASIS_SH = 1 };
+#define RXGS_RXCOND_EMB 16     /* component embedding width d_c (App. E Table 4) */
+#define RXGS_RXCOND_HIDDEN 64  /* hidden width of both MLPs (Table 4: 64) */
+
+typedef struct {
+    int32_t basis;     /* RXGS_BASIS_FLE or RXGS_BASIS_SH */
+    int32_t lmax;      /* largest degree, 0..12; L = (lmax + 1)^2 components */
+    int32_t channels;  /* complex signal channels C, 1..32 (App. E.1: f in R^{L x C}) */
+    int32_t bands;     /* Fourier bands F, 1..16: 3F frequency vectors */
+    int32_t hidden;    /* must be RXGS_RXCOND_HIDDEN */
+    int32_t probes;    /* occupancy probes S per (receiver, Gaussian), 2..64 */
+    int32_t grid;      /* occupancy grid resolution G, 1..512 */
+    int32_t reserved;  /* must be 0 */
+} rxgs_rxcond_desc;
+
+/* Number of conditioning parameters for a descriptor (-1 if invalid), in
+ * this order, matrices row-major (out x in):
+ *   w    3F x 3              Fourier frequency vectors w_i (eq. rx_enc)
+ *   e    L x 16              component embeddings e_l
+ *   global MLP  W1 (64 x (6F + 18)), b1 (64), W2 (64 x 64), b2 (64),
+ *               W3 (4C x 64), b3 (4C); output row 4c + (alpha re, alpha im,
+ *               beta re, beta im); input [gamma; deg/m, ord/m; e_l] with
+ *               gamma[2i] = sin(w_i . r), gamma[2i + 1] = cos(w_i . r)
+ *   local MLP   W1 (64 x 6), b1 (64), W2 (64 x 64), b2 (64), W3 (4C x 64),
+ *               b3 (4C); output row 4c + (alpha' re, alpha' im, beta' re, beta' im) */
+int64_t rxgs_rxcond_param_count(const rxgs_rxcond_desc *d);
+
+/*
+ * Upload a conditioning model for the current scene: coeffs K x L x C x 2
+ * (Re, Im) base coefficients, params rxgs_rxcond_param_count floats.  Builds
+ * the occupancy grid from the scene's means, log-scales and logits on the
+ * device (once per upload: App. E.5 builds it once).  The call synchronises
+ * the stream.  A later rxgs_scene_upload invalidates the model (E_STATE on
+ * render until it is uploaded again).  Errors: E_INVALID (descriptor,
+ * non-finite value), E_STATE (no scene), E_OOM, E_DEVICE.
+ */
+rxgs_status rxgs_rxcond_upload(rxgs_ctx *ctx, const rxgs_rxcond_desc *d, const float *coeffs,
+                               const float *params, int src_on_device, void *stream);
+
+/*
+ * rxgs_render with the conditioned radiance above (Alg. 1 stages 2-3: every
+ * (receiver, Gaussian) pair gets its coefficients modulated by both branches
+ * and reduced against the basis of the view centre's direction, then each
+ * channel is composited like a receiver of its own with the receiver's
+ * weights).  Arguments as rxgs_render, with receiver-major channel rows:
+ *   C      device N x C x 2 x H x W     power  device N x C, or NULL
+ *   csum   device N x C x 2, or NULL   amp    device N x C x H x W, or NULL
+ *   saved  state for rxgs_saved_export (its radiance rows are (receiver,
+ *          channel)), or NULL; rxgs_render_backward refuses it (E_STATE).
+ * Errors: those of rxgs_render; E_STATE without a current model.
+ */
+rxgs_status rxgs_render_rxcond(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off, int N,
+                               const float *rx, float *C, float *power, float *csum, float *amp,
+                               rxgs_saved *saved, void *stream);
+
+/* Copies of the model's derived arrays (synchronous):
+ *   RXGS_RXCOND_OCCUPANCY  G^3 f32 occupancy values, x fastest
+ *   RXGS_RXCOND_BOX        6 f64: lo[3], hi[3] of the grid
+ * Errors: E_INVALID (kind, size), E_STATE (no model). */
+enum { RXGS_RXCOND_OCCUPANCY = 0, RXGS_RXCOND_BOX = 1 };
+rxgs_status rxgs_rxcond_export(rxgs_ctx *ctx, int what, void *dst, int64_t bytes, int dst_on_device);
 
 /* Library version string. */
 const char *rxgs_version(void);

@@ -2103,7 +2103,7 @@ hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st)
     if (g.tiles <= 255) {
         // one 8-bit pass: ranges straight from the scanned histogram; the MLP
         // work items in the same launch
-        const unsigned nbi = ws.use_mlp ? (unsigned)nblk((size_t)ws.n_items) : 0u;
+        const unsigned nbi = ws.use_items ? (unsigned)nblk((size_t)ws.n_items) : 0u;
         if (nbi > 0 && ws.items.cap < (size_t)ws.n_items * 16) return hipErrorInvalidValue;   // not allocated
         hipLaunchKernelGGL(k_ranges_items, dim3((unsigned)ws.V + nbi), dim3(BLOCK), 0, st, ws.hist_b.as<uint32_t>(),
                            ws.d_pbase, ws.d_pcount, g.tiles, ws.ranges.as<uint2>(), ws.torder.as<uint32_t>(),

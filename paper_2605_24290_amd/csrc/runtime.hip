@@ -138,7 +138,8 @@ void free_workspace(Workspace &ws)
                       &ws.Lp,      &ws.Gp,      &ws.items,  &ws.Tfin,   &ws.nlast,  &ws.part,
                       &ws.counters, &ws.hist,   &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
                       &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.mred,   &ws.live,   &ws.items_live, &ws.vflag,
-                      &ws.items_far, &ws.frec, &ws.fcnt,  &ws.ftile,  &ws.hist_b, &ws.gfeat_tmp, &ws.gmlp_tmp};
+                      &ws.items_far, &ws.frec, &ws.fcnt,  &ws.ftile,  &ws.hist_b, &ws.gfeat_tmp, &ws.gmlp_tmp,
+                      &ws.rgam,    &ws.rab,     &ws.rloc};
     for (DevBuf *b : bufs) release(*b);
     if (ws.staged) (void)hipEventDestroy(ws.staged);
     if (ws.counted) (void)hipEventDestroy(ws.counted);
@@ -409,6 +410,7 @@ extern "C" void rxgs_destroy(rxgs_ctx *ctx)
     release(ctx->mlp.tabh);
     release(ctx->mlp.w1h);
     release(ctx->mlp.b1tab);
+    release_rxcond(ctx->rxc);
     release(ctx->stage);
     if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     delete ctx;
@@ -444,8 +446,7 @@ extern "C" rxgs_status rxgs_scene_upload(rxgs_ctx *ctx, int64_t K, const float *
 {
     if (!ctx) return RXGS_E_INVALID;
     if (K < 0 || K > (1ll << 27)) return fail(ctx, RXGS_E_INVALID, "K out of range [0, 2^27]");
-    if (K > 0 && (radiance == nullptr) == (features == nullptr))
-        return fail(ctx, RXGS_E_INVALID, "exactly one of radiance and features must be given");
+    if (radiance && features) return fail(ctx, RXGS_E_INVALID, "at most one of radiance and features may be given");
     if (K > 0 && (!means || !log_scales || !quats || !logits))
         return fail(ctx, RXGS_E_INVALID, "NULL scene array");
     DeviceScope ds(ctx->device);
@@ -453,7 +454,8 @@ extern "C" rxgs_status rxgs_scene_upload(rxgs_ctx *ctx, int64_t K, const float *
     Scene &sc = ctx->scene;
     sc.valid = false;
     const bool feat = features != nullptr;
-    const size_t nrad = (size_t)K * (feat ? FEAT : 2);
+    const bool geo = !feat && !radiance;   // geometry only: radiance from a conditioning model
+    const size_t nrad = geo ? 0 : (size_t)K * (feat ? FEAT : 2);
     const float *radsrc = feat ? features : radiance;
     const hipMemcpyKind kind = src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     if (!src_on_device) {
@@ -480,7 +482,7 @@ extern "C" rxgs_status rxgs_scene_upload(rxgs_ctx *ctx, int64_t K, const float *
     }
     DevBuf &dst = feat ? sc.feat : sc.rad;
     GROW(ctx, dst, std::max<size_t>(nrad, 1) * 4);
-    if (K > 0) HIPCHK(ctx, hipMemcpyAsync(dst.p, radsrc, nrad * 4, kind, st));
+    if (K > 0 && nrad > 0) HIPCHK(ctx, hipMemcpyAsync(dst.p, radsrc, nrad * 4, kind, st));
     float fmax = 0.f;   // largest |feature|, for the split-FP16 layer-1 path
     if (src_on_device && K > 0) {
         unsigned *cnt = reinterpret_cast<unsigned *>(stg + 11 * K);
@@ -502,6 +504,8 @@ extern "C" rxgs_status rxgs_scene_upload(rxgs_ctx *ctx, int64_t K, const float *
     sc.fmax = fmax;
     sc.K = K;
     sc.has_features = feat;
+    sc.geometry_only = geo && K > 0;
+    ctx->rxc.valid = false;   // its occupancy grid and coefficients belong to the old scene
     sc.version = ++ctx->version_counter;
     sc.valid = true;
     return RXGS_OK;
@@ -663,7 +667,7 @@ constexpr int PREFIX_MAX_RX = 128;
 // still has a pixel whose transmittance stayed above the stop threshold.
 static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off, int N,
                                const float *rx, float *C, float *power, float *csum, float *amp, rxgs_saved *saved,
-                               void *stream, uint32_t limit)
+                               void *stream, uint32_t limit, int rsrc = RSRC_SCENE)
 {
     if (!ctx) return RXGS_E_INVALID;
     if (mode != RXGS_MODE_TX && mode != RXGS_MODE_RX) return fail(ctx, RXGS_E_INVALID, "unknown mode");
@@ -672,7 +676,15 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     if (saved && saved->ctx != ctx) return fail(ctx, RXGS_E_INVALID, "saved state of another context");
     const Scene &sc = ctx->scene;
     if (!sc.valid) return fail(ctx, RXGS_E_STATE, "no scene uploaded");
-    if (sc.has_features && !ctx->mlp.valid) return fail(ctx, RXGS_E_STATE, "MLP scene without an uploaded MLP");
+    const bool rxc = rsrc == RSRC_RXCOND;
+    if (!rxc && sc.has_features && !ctx->mlp.valid)
+        return fail(ctx, RXGS_E_STATE, "MLP scene without an uploaded MLP");
+    if (!rxc && sc.geometry_only)
+        return fail(ctx, RXGS_E_STATE, "the scene has no radiance of its own: render it with rxgs_render_rxcond");
+    if (rxc && (!ctx->rxc.valid || ctx->rxc.scene_version != sc.version))
+        return fail(ctx, RXGS_E_STATE, "no conditioning model uploaded for the current scene");
+    const int Ch = rxc ? ctx->rxc.C : 1;   // output rows per receiver
+    if ((int64_t)N * Ch > (1ll << 30)) return fail(ctx, RXGS_E_INVALID, "too many receiver channels");
     std::vector<int> rxview(N);
     int V = 0;
     if (mode == RXGS_MODE_TX) {
@@ -688,6 +700,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         V = N;
     }
     if (N == 0) return RXGS_OK;
+    const int NR = N * Ch;   // rows (receiver, channel), receiver-major
     const DevGrid &g = ctx->g;
     const int64_t K = sc.K;
     const int64_t Kp = round_up(std::max<int64_t>(K, 1), SORT_TILE);
@@ -709,13 +722,20 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     const size_t VK = (size_t)V * Kp;
     ws.mode = mode;
     ws.V = V;
-    ws.N = N;
+    ws.N = NR;
+    ws.Nrx = N;
+    ws.Ch = Ch;
+    ws.rsrc = rsrc;
     ws.Q = Q;
     ws.K = K;
     ws.Kp = Kp;
     ws.g = g;
-    ws.use_mlp = sc.has_features;
-    ws.h_rxview = rxview;
+    ws.use_mlp = !rxc && sc.has_features;
+    ws.use_items = ws.use_mlp || rxc;
+    std::vector<int> rowview(NR);   // view of each output row
+    for (int j = 0; j < N; j++)
+        for (int c = 0; c < Ch; c++) rowview[(size_t)j * Ch + c] = rxview[j];
+    ws.h_rxview = rowview;
     ws.limit = limit;
     WGROW(ctx, ws, ws.vflag, (size_t)V * 4);
 
@@ -782,6 +802,13 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         WGROW(ctx, ws, ws.Gp, (size_t)N * HID * 4);
         STAGE(ctx, "mlp_global", launch_mlp_global_term(ctx->mlp, ws, st));
     }
+    if (rxc) {
+        // the conditioning's receiver terms: the encoding into the global
+        // MLP and its modulation of every component (O(L) per receiver)
+        WGROW(ctx, ws, ws.rgam, (size_t)N * RXGS_RXCOND_HIDDEN * 4);
+        WGROW(ctx, ws, ws.rab, (size_t)N * ctx->rxc.L * Ch * 16);
+        STAGE(ctx, "rxcond_global", launch_rxcond_receivers(ctx->rxc, ws, st));
+    }
 
     // receiver chunks of the blend (independent of the counters: built while
     // the GPU projects and sorts); the receivers of a view are consecutive
@@ -790,29 +817,31 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         vfirst[rxview[j]] = j;
         vnrx[rxview[j]]++;
     }
+    // (in rows: a view's receivers, and each receiver's channels, are consecutive)
+    const bool shared_view = mode == RXGS_MODE_TX || Ch > 1;   // several rows share a view's weights
     int maxr = 1;
-    for (int v = 0; v < V; v++) maxr = std::max(maxr, vnrx[v]);
+    for (int v = 0; v < V; v++) maxr = std::max(maxr, vnrx[v] * Ch);
     ws.R_max = maxr;
     int R = 1;
-    if (mode == RXGS_MODE_TX)
+    if (shared_view)
         while (R < 16 && R < maxr) R *= 2;
     ws.R = R;
     std::vector<int4> chunks;
     for (int v = 0; v < V; v++)
-        for (int a = 0; a < vnrx[v]; a += R) {
-            const int j = vfirst[v] + a;
-            const int tslot = (mode == RXGS_MODE_TX) ? (a == 0 ? v : -1) : j;
-            chunks.push_back(make_int4(v, j, std::min(R, vnrx[v] - a), tslot));
+        for (int a = 0; a < vnrx[v] * Ch; a += R) {
+            const int j = vfirst[v] * Ch + a;
+            const int tslot = shared_view ? (a == 0 ? v : -1) : j;
+            chunks.push_back(make_int4(v, j, std::min(R, vnrx[v] * Ch - a), tslot));
         }
     ws.n_chunks = (int)chunks.size();
-    ws.n_tslots = (mode == RXGS_MODE_TX) ? V : N;
+    ws.n_tslots = shared_view ? V : N;
     // Lazy radiance (TX mode, several receivers per view, nothing saved): the
     // weights do not depend on the receiver, so one weights-only pass per view
     // marks the position blocks some pixel composites and the pair MLP runs
     // on those blocks only.  Saved states keep every visible position's
     // radiance (it is exported).
     std::vector<int4> wchunks;
-    if (mode == RXGS_MODE_TX && !save && ws.use_mlp)
+    if (mode == RXGS_MODE_TX && !save && ws.use_items)
         for (int v = 0; v < V; v++)
             if (vnrx[v] >= LAZY_MIN_RX) wchunks.push_back(make_int4(v, 0, 0, -1));
     ws.n_wchunks = (int)wchunks.size();
@@ -870,7 +899,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     // statistics come from the first pass (weights do not depend on the
     // radiance), the backward reads the radiance of composited entries only,
     // and a radiance export evaluates the rest first.
-    if (ws.use_mlp && (mode == RXGS_MODE_RX || maxr < PREFIX_MAX_RX))
+    if (ws.use_items && (mode == RXGS_MODE_RX || maxr < PREFIX_MAX_RX))
         for (int v = 0; v < V; v++)
             if ((uint32_t)ws.h_nvis[v] > prefix) ws.mpos = prefix;
     ws.rad_complete = ws.mpos == 0xFFFFFFFFu;
@@ -889,8 +918,8 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     for (int v = 0; v < V; v++) {
         const int64_t nb = (ws.h_nvis[v] + MLP_PAIRS - 1) / MLP_PAIRS, nrg = (vnrx[v] + MLP_RG - 1) / MLP_RG;
         const int64_t nb0 = std::min<int64_t>(nb, ws.mpos / MLP_PAIRS);
-        const int64_t ni = ws.use_mlp ? nb0 * nrg : 0;
-        nfar += ws.use_mlp ? (nb - nb0) * nrg : 0;
+        const int64_t ni = ws.use_items ? nb0 * nrg : 0;
+        nfar += ws.use_items ? (nb - nb0) * nrg : 0;
         if ((int64_t)item_off[v] + ni >= (1ll << 31)) return fail(ctx, RXGS_E_INVALID, "too many MLP work items");
         item_off[v + 1] = item_off[v] + (uint32_t)ni;
         vinfo[v] = make_int4(vfirst[v], vnrx[v], ws.h_nvis[v], ws.lazy && vnrx[v] >= LAZY_MIN_RX ? 1 : 0);
@@ -912,14 +941,13 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     WGROW(ctx, ws, ws.hist_b, sort_ws_bytes((uint32_t)Dpad, std::max(bits_for((uint64_t)g.tiles), 1), V));
     WGROW(ctx, ws, ws.ranges, (size_t)V * g.tiles * 8);
     WGROW(ctx, ws, ws.torder, (size_t)V * g.tiles * 4);
-    WGROW(ctx, ws, ws.rad, (size_t)N * Kp * 8);
+    WGROW(ctx, ws, ws.rad, (size_t)NR * Kp * 8);
     WGROW(ctx, ws, ws.Tfin, (size_t)ws.n_tslots * P * 4);
     WGROW(ctx, ws, ws.nlast, (size_t)ws.n_tslots * P * 4);
-    WGROW(ctx, ws, ws.part, (size_t)N * g.tiles * 12);
-    if (ws.use_mlp) {
-        WGROW(ctx, ws, ws.Lp, (size_t)std::max<int64_t>(K, 1) * HID * 4);
-        WGROW(ctx, ws, ws.items, (size_t)std::max(ws.n_items, 1) * 16);
-    }
+    WGROW(ctx, ws, ws.part, (size_t)NR * g.tiles * 12);
+    if (ws.use_mlp) WGROW(ctx, ws, ws.Lp, (size_t)std::max<int64_t>(K, 1) * HID * 4);
+    if (ws.use_items) WGROW(ctx, ws, ws.items, (size_t)std::max(ws.n_items, 1) * 16);
+    if (rxc) WGROW(ctx, ws, ws.rloc, (size_t)N * Kp * Ch * 16);
     if (ws.lazy) {
         WGROW(ctx, ws, ws.items_live, (size_t)std::max(ws.n_items, 1) * 16);
         WGROW(ctx, ws, ws.live, live_count_offset(ws) + 64);
@@ -934,7 +962,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
 
     // the small descriptors, packed (16-byte aligned parts) into one host-to-device copy
     auto al16 = [](size_t b) { return (b + 15) / 16 * 16; };
-    const size_t o_chunks = al16((size_t)N * 4);
+    const size_t o_chunks = al16((size_t)NR * 4);
     const size_t o_vinfo = o_chunks + chunks.size() * 16;
     const size_t o_ioff = o_vinfo + (size_t)V * 16;
     const size_t o_coff = o_ioff + al16((size_t)(V + 1) * 4);
@@ -948,7 +976,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     if (!ensure_pinned(ws, off0 + stage_bytes + 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
     WGROW(ctx, ws, ws.desc, stage_bytes);
     char *hp = static_cast<char *>(ws.h_pinned) + off0;
-    std::memcpy(hp, rxview.data(), (size_t)N * 4);
+    std::memcpy(hp, rowview.data(), (size_t)NR * 4);
     std::memcpy(hp + o_chunks, chunks.data(), chunks.size() * 16);
     std::memcpy(hp + o_vinfo, vinfo.data(), (size_t)V * 16);
     std::memcpy(hp + o_ioff, item_off.data(), (size_t)(V + 1) * 4);
@@ -993,6 +1021,10 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         // cannot compute it itself
         if (save || !mlp_fused_ok(sc, ctx->mlp)) STAGE(ctx, "mlp_local", launch_mlp_local(sc, ctx->mlp, ws, st));
         STAGE(ctx, "mlp_pairs", launch_mlp_pairs(sc, ctx->mlp, ws, st));
+    } else if (rxc) {
+        if (!ws.items_built) STAGE(ctx, "mlp_items", launch_mlp_items(ws, st));
+        if (ws.lazy) STAGE(ctx, "blend_weights", launch_blend_weights(ws, st));
+        STAGE(ctx, "rxcond_pairs", launch_rxcond_pairs(sc, ctx->rxc, ws, st, false));
     } else {
         STAGE(ctx, "rad_direct", launch_rad_direct(sc, ws, st));
     }
@@ -1006,14 +1038,16 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         // radiance, then their recorded terms added, or their blend again
         // (the workgroups of other tiles return at once)
         STAGE(ctx, "far_items", launch_far_items(ws, st));
-        STAGE(ctx, "mlp_far", launch_mlp_pairs(sc, ctx->mlp, ws, st, true));
+        STAGE(ctx, "mlp_far", rxc ? launch_rxcond_pairs(sc, ctx->rxc, ws, st, true)
+                                  : launch_mlp_pairs(sc, ctx->mlp, ws, st, true));
         STAGE(ctx, "blend_far", launch_blend_fwd(ws, C, false, st, true));
     }
     STAGE(ctx, "reduce", launch_reduce_outputs(ws, power, csum, st));
-    if (amp) STAGE(ctx, "amplitude", launch_amplitude(C, amp, N, P, st));
+    if (amp) STAGE(ctx, "amplitude", launch_amplitude(C, amp, NR, P, st));
     HIPCHK(ctx, hipEventRecord(ws.done, st));
     ws.scene_version = sc.version;
     ws.mlp_version = ctx->mlp.version;
+    ws.rxc_version = ctx->rxc.version;
     ws.valid = !saved || save;
     return RXGS_OK;
 }
@@ -1068,6 +1102,213 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         if (rs != RXGS_OK) return rs;
     }
     return RXGS_OK;
+}
+
+// ============================================================================
+// The paper's conditioned radiance (Sec. 4.3.2; App. E.2, E.5)
+
+static bool rc_desc_ok(const rxgs_rxcond_desc *d)
+{
+    return d && (d->basis == RXGS_BASIS_FLE || d->basis == RXGS_BASIS_SH) && d->lmax >= 0 && d->lmax <= 12 &&
+           d->channels >= 1 && d->channels <= 32 && d->bands >= 1 && d->bands <= 16 &&
+           d->hidden == RXGS_RXCOND_HIDDEN && d->probes >= 2 && d->probes <= 64 && d->grid >= 1 && d->grid <= 512 &&
+           d->reserved == 0;
+}
+
+extern "C" int64_t rxgs_rxcond_param_count(const rxgs_rxcond_desc *d)
+{
+    if (!rc_desc_ok(d)) return -1;
+    const int L = (d->lmax + 1) * (d->lmax + 1);
+    return (int64_t)rc_offsets(L, d->channels, d->bands).total;
+}
+
+extern "C" rxgs_status rxgs_rxcond_upload(rxgs_ctx *ctx, const rxgs_rxcond_desc *d, const float *coeffs,
+                                          const float *params, int src_on_device, void *stream)
+{
+    if (!ctx) return RXGS_E_INVALID;
+    if (!rc_desc_ok(d))
+        return fail(ctx, RXGS_E_INVALID,
+                    "invalid conditioning descriptor (basis FLE or SH, lmax 0..12, channels 1..32, bands 1..16, "
+                    "hidden 64, probes 2..64, grid 1..512, reserved 0)");
+    const Scene &sc = ctx->scene;
+    if (!sc.valid) return fail(ctx, RXGS_E_STATE, "no scene uploaded");
+    const int64_t K = sc.K;
+    if (!params || (K > 0 && !coeffs)) return fail(ctx, RXGS_E_INVALID, "coefficients or parameters are NULL");
+    DeviceScope ds(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    RxCond &m = ctx->rxc;
+    m.valid = false;
+    m.kind = d->basis;
+    m.lmax = d->lmax;
+    m.L = (d->lmax + 1) * (d->lmax + 1);
+    m.C = d->channels;
+    m.F = d->bands;
+    m.S = d->probes;
+    m.G = d->grid;
+    m.off = rc_offsets(m.L, m.C, m.F);
+    const int L = m.L, C = m.C, F = m.F, G = m.G, H = RXGS_RXCOND_HIDDEN;
+    const size_t np = m.off.total;
+    const size_t ncoef = (size_t)K * L * C * 2;
+    std::vector<float> hp(np);
+    if (src_on_device) {
+        HIPCHK(ctx, hipMemcpyAsync(hp.data(), params, np * 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+    } else {
+        std::memcpy(hp.data(), params, np * 4);
+        if (!all_finite_host(coeffs, ncoef)) return fail(ctx, RXGS_E_INVALID, "non-finite coefficient");
+    }
+    if (!all_finite_host(hp.data(), np)) return fail(ctx, RXGS_E_INVALID, "non-finite conditioning parameter");
+    // walk order: half 0 takes the even |m|, half 1 the odd; m ascending, then
+    // the degree, (l, +m) before (l, -m)
+    std::vector<int> walk;
+    for (int h = 0; h < 2; h++) {
+        for (int mm = h; mm <= m.lmax; mm += 2)
+            for (int l = mm; l <= m.lmax; l++) {
+                walk.push_back(l * l + l + mm);
+                if (mm > 0) walk.push_back(l * l + l - mm);
+            }
+        if (h == 0) m.n0 = (int)walk.size();
+    }
+    // layer-1 term of each component of the global MLP, in walk order:
+    // b1 + W1[:, 6F] deg / m + W1[:, 6F + 1] ord / m + W1[:, 6F + 2 ..] e_l
+    const int gin = 6 * F + 2 + RXGS_RXCOND_EMB;
+    const double dn = m.lmax > 0 ? (double)m.lmax : 1.0;
+    std::vector<float> comp((size_t)L * H);
+    for (int w = 0; w < L; w++) {
+        const int idx = walk[w];
+        int l = 0;
+        while ((l + 1) * (l + 1) <= idx) l++;
+        const int ord = idx - l * l - l;
+        for (int u = 0; u < H; u++) {
+            const float *row = hp.data() + m.off.g1 + (size_t)u * gin;
+            double a = hp[m.off.gb1 + u];
+            a += (double)row[6 * F] * ((double)l / dn);
+            a += (double)row[6 * F + 1] * ((double)ord / dn);
+            for (int e = 0; e < RXGS_RXCOND_EMB; e++)
+                a += (double)row[6 * F + 2 + e] * (double)hp[m.off.e + (size_t)idx * RXGS_RXCOND_EMB + e];
+            comp[(size_t)w * H + u] = (float)a;
+        }
+    }
+    // orthonormal factors and the recurrence constants of the associated
+    // Legendre functions, per (l, m)
+    std::vector<float> ctab(13 * 13 * 4, 0.f);
+    for (int l = 0; l <= 12; l++)
+        for (int mm = 0; mm <= l; mm++) {
+            double r = (2.0 * l + 1.0) / (4.0 * M_PI);
+            for (int i = l - mm + 1; i <= l + mm; i++) r /= (double)i;
+            float *t = &ctab[(l * 13 + mm) * 4];
+            t[0] = (float)std::sqrt(r);
+            if (l > mm) {
+                t[1] = (float)((2.0 * l - 1.0) / (double)(l - mm));
+                t[2] = (float)((double)(l + mm - 1) / (double)(l - mm));
+            }
+        }
+    // the local MLP's W2 in the FP32 MFMA A-operand layout
+    std::vector<float> w2t(2 * 32 * 64);
+    for (int b = 0; b < 2; b++)
+        for (int t = 0; t < 32; t++)
+            for (int lane = 0; lane < 64; lane++)
+                w2t[(b * 32 + t) * 64 + lane] = hp[m.off.l2 + (size_t)(32 * b + lane % 32) * H + 2 * t + lane / 32];
+    std::vector<double> tp(m.S);
+    for (int i = 0; i < m.S; i++) {
+        double t = 0.9 * (double)i;
+        t = t / (double)(m.S - 1);
+        tp[i] = 0.05 + t;
+    }
+    GROW(ctx, m.params, np * 4);
+    GROW(ctx, m.comp, comp.size() * 4);
+    GROW(ctx, m.walk, (size_t)L * 4);
+    GROW(ctx, m.ctab, ctab.size() * 4);
+    GROW(ctx, m.w2t, w2t.size() * 4);
+    GROW(ctx, m.tprobe, tp.size() * 8);
+    GROW(ctx, m.coef, std::max<size_t>(ncoef, 2) * 4);
+    GROW(ctx, m.occ, (size_t)G * G * G * 4);
+    HIPCHK(ctx, hipMemcpyAsync(m.params.p, hp.data(), np * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(m.comp.p, comp.data(), comp.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(m.walk.p, walk.data(), (size_t)L * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(m.ctab.p, ctab.data(), ctab.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(m.w2t.p, w2t.data(), w2t.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(m.tprobe.p, tp.data(), tp.size() * 8, hipMemcpyHostToDevice, st));
+    // coefficients into walk order (through the staging buffer from the host)
+    DevBuf tmp;
+    const size_t n3 = (size_t)G * G * G;
+    if (!grow(tmp, std::max<size_t>(n3 * 8, 64), &ctx->alloc)) return fail(ctx, RXGS_E_OOM, "occupancy accumulator");
+    struct TmpGuard {
+        DevBuf &b;
+        ~TmpGuard() { release(b); }
+    } guard{tmp};
+    unsigned *words = tmp.as<unsigned>();   // first used for the checks and the bounds
+    if (K > 0) {
+        const float *src = coeffs;
+        if (!src_on_device) {
+            GROW(ctx, ctx->stage, ncoef * 4);
+            HIPCHK(ctx, hipMemcpyAsync(ctx->stage.p, coeffs, ncoef * 4, hipMemcpyHostToDevice, st));
+            src = ctx->stage.as<float>();
+        } else {
+            HIPCHK(ctx, hipMemsetAsync(words, 0, 4, st));
+            const unsigned blocks = (unsigned)std::min<size_t>((ncoef + BLOCK - 1) / BLOCK, 2048);
+            hipLaunchKernelGGL(k_count_nonfinite, dim3(blocks), dim3(BLOCK), 0, st, coeffs, ncoef, words);
+            HIPCHK(ctx, hipGetLastError());
+            unsigned bad = 0;
+            HIPCHK(ctx, hipMemcpyAsync(&bad, words, 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(ctx, hipStreamSynchronize(st));
+            if (bad) return fail(ctx, RXGS_E_INVALID, "non-finite coefficient");
+        }
+        HIPCHK(ctx, launch_rc_coef_perm(src, K, m, st));
+    }
+    // occupancy grid over the box of the means
+    unsigned keys[6] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0u, 0u, 0u};
+    if (K > 0) {
+        HIPCHK(ctx, hipMemcpyAsync(words, keys, 24, hipMemcpyHostToDevice, st));
+        HIPCHK(ctx, launch_rc_bounds(sc, words, st));
+        HIPCHK(ctx, hipMemcpyAsync(keys, words, 24, hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+    }
+    for (int a = 0; a < 3; a++) {
+        m.lo[a] = K > 0 ? (double)rc_key_value(keys[a]) : 0.0;
+        m.hi[a] = K > 0 ? (double)rc_key_value(keys[3 + a]) : 0.0;
+        if (!(m.hi[a] - m.lo[a] >= 1e-6)) m.hi[a] = m.lo[a] + 1e-6;
+        m.vs[a] = (m.hi[a] - m.lo[a]) / G;
+        m.inv[a] = (double)G / (m.hi[a] - m.lo[a]);
+    }
+    unsigned long long *acc = tmp.as<unsigned long long>();
+    HIPCHK(ctx, hipMemsetAsync(acc, 0, n3 * 8, st));
+    HIPCHK(ctx, launch_rc_splat(sc, m, acc, st));
+    HIPCHK(ctx, launch_rc_finish(m, acc, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    m.version = ++ctx->version_counter;
+    m.scene_version = sc.version;
+    m.valid = true;
+    return RXGS_OK;
+}
+
+extern "C" rxgs_status rxgs_rxcond_export(rxgs_ctx *ctx, int what, void *dst, int64_t bytes, int dst_on_device)
+{
+    if (!ctx) return RXGS_E_INVALID;
+    if (!dst || bytes < 0) return fail(ctx, RXGS_E_INVALID, "NULL destination");
+    const RxCond &m = ctx->rxc;
+    if (!m.valid) return fail(ctx, RXGS_E_STATE, "no conditioning model");
+    DeviceScope ds(ctx->device);
+    if (what == RXGS_RXCOND_BOX) {
+        if (bytes < 48) return fail(ctx, RXGS_E_INVALID, "destination too small");
+        double box[6] = {m.lo[0], m.lo[1], m.lo[2], m.hi[0], m.hi[1], m.hi[2]};
+        if (dst_on_device) HIPCHK(ctx, aux_copy(ctx, dst, box, 48, hipMemcpyHostToDevice));
+        else std::memcpy(dst, box, 48);
+        return RXGS_OK;
+    }
+    if (what != RXGS_RXCOND_OCCUPANCY) return fail(ctx, RXGS_E_INVALID, "unknown export");
+    const size_t n = (size_t)m.G * m.G * m.G * 4;
+    if ((size_t)bytes < n) return fail(ctx, RXGS_E_INVALID, "destination too small");
+    HIPCHK(ctx, aux_copy(ctx, dst, m.occ.p, n, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    return RXGS_OK;
+}
+
+extern "C" rxgs_status rxgs_render_rxcond(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off,
+                                          int N, const float *rx, float *C, float *power, float *csum, float *amp,
+                                          rxgs_saved *saved, void *stream)
+{
+    return render_pass(ctx, mode, Q, tx, rx_off, N, rx, C, power, csum, amp, saved, stream, 0xFFFFFFFFu,
+                       RSRC_RXCOND);
 }
 
 // ============================================================================
@@ -1146,6 +1387,8 @@ extern "C" rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *sav
     if (saved->ctx != ctx) return fail(ctx, RXGS_E_INVALID, "saved state of another context");
     // the backward uses scratch buffers of the saved state: calls on one saved state must not overlap
     Workspace &ws = const_cast<rxgs_saved *>(saved)->ws;
+    if (ws.valid && ws.rsrc == RSRC_RXCOND)
+        return fail(ctx, RXGS_E_STATE, "no backward through the conditioned radiance: the state is for exports only");
     const Scene &sc = ctx->scene;
     if (!ws.valid) return fail(ctx, RXGS_E_STATE, "no forward state in saved");
     if (ws.scene_version != sc.version || (ws.use_mlp && ws.mlp_version != ctx->mlp.version))
@@ -1321,15 +1564,18 @@ extern "C" rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *ds
         // the prefix render evaluated only the radiance the blend needed:
         // evaluate the rest (it completes a cached part of the state; nothing
         // the state describes changes, hence the cast)
-        if (ws.scene_version != ctx->scene.version || ws.mlp_version != ctx->mlp.version)
-            return fail(ctx, RXGS_E_STATE, "scene or MLP changed since the forward");
+        const bool rxc = ws.rsrc == RSRC_RXCOND;
+        if (ws.scene_version != ctx->scene.version ||
+            (rxc ? ws.rxc_version != ctx->rxc.version || !ctx->rxc.valid : ws.mlp_version != ctx->mlp.version))
+            return fail(ctx, RXGS_E_STATE, "scene or radiance model changed since the forward");
         Workspace &w = const_cast<Workspace &>(ws);
         hipStream_t a = nullptr;
         HIPCHK(ctx, aux_stream(ctx, a));
         HIPCHK(ctx, wait_workspace(ws));   // the render, on the caller's stream
         HIPCHK(ctx, launch_far_all(w, a));
         HIPCHK(ctx, launch_far_items(w, a));
-        HIPCHK(ctx, launch_mlp_pairs(ctx->scene, ctx->mlp, w, a, true));
+        if (rxc) HIPCHK(ctx, launch_rxcond_pairs(ctx->scene, ctx->rxc, w, a, true));
+        else HIPCHK(ctx, launch_mlp_pairs(ctx->scene, ctx->mlp, w, a, true));
         HIPCHK(ctx, hipStreamSynchronize(a));
         w.rad_complete = true;
     }

@@ -75,6 +75,7 @@ struct DevBuf {
 struct Scene {
     int64_t K = 0;
     bool has_features = false;
+    bool geometry_only = false;   // no radiance of its own (conditioning model only)
     bool valid = false;
     uint64_t version = 0;
     DevBuf soa;    // 11 x K: x, y, z, ls0, ls1, ls2, qw, qx, qy, qz, logit
@@ -110,8 +111,46 @@ struct Mlp {
                          // rescaled tables would not be exact
 };
 
+// The receiver-conditioned radiance model (rxgs_rxcond_upload).  Component
+// tables are stored in the basis walk's order (rxcond.hip: lane half h walks
+// the orders |m| of parity h, m ascending, degree ascending, +m before -m).
+// Offsets (floats) of the parts of the flat conditioning parameters.
+struct RcOffsets {
+    size_t w, e, g1, gb1, g2, gb2, g3, gb3, l1, lb1, l2, lb2, l3, lb3, total;
+};
+RcOffsets rc_offsets(int L, int C, int F);
+
+struct RxCond {
+    bool valid = false;
+    uint64_t version = 0;
+    uint64_t scene_version = 0;
+    int kind = 0, lmax = 0, L = 0, C = 1, F = 1, S = 16, G = 128;
+    int n0 = 0;                 // walk positions of lane half 0 (half 1 follows)
+    RcOffsets off{};
+    DevBuf coef;                // K x L x C float2, walk order
+    DevBuf params;              // the flat parameters as uploaded
+    DevBuf comp;                // L x 64: b1 + W1 [deg/m, ord/m; e_l] per component, walk order
+    DevBuf walk;                // L int: component index deg^2 + deg + ord at each walk position
+    DevBuf ctab;                // 13 x 13 float4 (N_lm, (2l-1)/(l-m), (l+m-1)/(l-m), 0)
+    DevBuf tprobe;              // S f64 probe fractions t_s
+    DevBuf occ;                 // G^3 occupancy
+    DevBuf w2t;                 // local W2 in the FP32 MFMA A-operand layout [2 blk][32 t][64 lane]
+    double lo[3] = {}, hi[3] = {}, inv[3] = {}, vs[3] = {};   // grid box, G / (hi - lo), (hi - lo) / G
+};
+
+// radiance of a render: the scene's own (direct or conditioning MLP) or a
+// conditioning model's
+enum { RSRC_SCENE = 0, RSRC_RXCOND = 1 };
+
 struct Workspace {
     Allocator *al = nullptr;   // source of its device buffers (nullptr: the context's)
+    int rsrc = RSRC_SCENE;     // radiance source of the last render
+    int Nrx = 0, Ch = 1;       // receivers and channels (rows N = Nrx x Ch)
+    bool use_items = false;    // radiance evaluated per MLP work item (MLP or conditioning model)
+    uint64_t rxc_version = 0;
+    DevBuf rgam;               // Nrx x 64 receiver term of the conditioning's global layer 1
+    DevBuf rab;                // Nrx x L x C float4 global modulation (1 + alpha, beta), walk order
+    DevBuf rloc;               // Nrx x Kp x C float4 local modulation (1 + alpha', beta') per sorted position
     bool fixed_host = false;   // h_pinned is a fixed buffer made at set-up (never regrown)
     // sizes of the last render
     int mode = 0, V = 0, N = 0, Q = 0, R = 1;
@@ -240,6 +279,7 @@ struct rxgs_ctx {
     rxgs_grid grid{};
     rxgs::Scene scene;
     rxgs::Mlp mlp;
+    rxgs::RxCond rxc;       // conditioning model of the paper's radiance path
     rxgs::Workspace ws;     // used when the caller passes no saved state
     rxgs::DevBuf stage;     // scene upload staging
     std::string err;
@@ -332,6 +372,19 @@ size_t mlp_red_bytes();
 hipError_t launch_blend_weights(Workspace &ws, hipStream_t st);
 int *live_count(Workspace &ws);
 size_t live_count_offset(const Workspace &ws);
+// conditioned radiance (rxcond.hip): the receiver terms (no per-render
+// counts needed), then the per-item local modulation and basis reduction
+hipError_t launch_rxcond_receivers(const RxCond &m, Workspace &ws, hipStream_t st);
+hipError_t launch_rxcond_pairs(const Scene &sc, const RxCond &m, Workspace &ws, hipStream_t st, bool far);
+// upload steps: bounds of the means (6 order keys, preset by the caller to
+// min = ~0, max = 0), the integer splat into acc (G^3 u64, zeroed), the
+// occupancy values, the coefficients into walk order
+hipError_t launch_rc_bounds(const Scene &sc, unsigned *keys, hipStream_t st);
+float rc_key_value(unsigned key);
+hipError_t launch_rc_splat(const Scene &sc, const RxCond &m, unsigned long long *acc, hipStream_t st);
+hipError_t launch_rc_finish(const RxCond &m, const unsigned long long *acc, hipStream_t st);
+hipError_t launch_rc_coef_perm(const float *src, int64_t K, const RxCond &m, hipStream_t st);
+void release_rxcond(RxCond &m);
 
 bool grow(DevBuf &b, size_t bytes, Allocator *al);
 void release(DevBuf &b);

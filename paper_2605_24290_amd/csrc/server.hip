@@ -312,7 +312,7 @@ extern "C" rxgs_status rxgs_server_start(rxgs_ctx *ctx, const rxgs_server_opts *
         ctx->err = "invalid server options";
         return RXGS_E_INVALID;
     }
-    if (!ctx->scene.valid || (ctx->scene.has_features && !ctx->mlp.valid)) {
+    if (!ctx->scene.valid || (ctx->scene.has_features && !ctx->mlp.valid) || ctx->scene.geometry_only) {
         ctx->err = "server needs an uploaded scene (and MLP)";
         return RXGS_E_STATE;
     }

@@ -72,6 +72,17 @@ class CStageTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", c_int64), ("total_ms", c_double)]
 
 
+class CRxCondDesc(ctypes.Structure):
+    _fields_ = [("basis", c_int32), ("lmax", c_int32), ("channels", c_int32), ("bands", c_int32),
+                ("hidden", c_int32), ("probes", c_int32), ("grid", c_int32), ("reserved", c_int32)]
+
+
+BASIS_FLE = 0
+BASIS_SH = 1
+RXCOND_OCCUPANCY = 0
+RXCOND_BOX = 1
+RXCOND_HIDDEN = 64
+
 ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_int, c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, ctypes.c_size_t, c_int, c_void_p)
 
@@ -81,7 +92,8 @@ EXPORTED = ("rxgs_create", "rxgs_create_with_allocator", "rxgs_destroy", "rxgs_l
             "rxgs_profile_read", "rxgs_server_start", "rxgs_server_submit", "rxgs_server_poll",
             "rxgs_server_cancel", "rxgs_server_stats", "rxgs_server_stop", "rxgs_plan_batch",
             "rxgs_workspace_estimate", "rxgs_set_near_cut", "rxgs_views_redone", "rxgs_render_chunked",
-            "rxgs_view_flags")
+            "rxgs_view_flags", "rxgs_rxcond_param_count", "rxgs_rxcond_upload", "rxgs_render_rxcond",
+            "rxgs_rxcond_export")
 
 _lib = None
 
@@ -136,6 +148,14 @@ def lib():
     L.rxgs_set_near_cut.restype = c_int
     L.rxgs_views_redone.argtypes = [vp]
     L.rxgs_views_redone.restype = c_int64
+    L.rxgs_rxcond_param_count.argtypes = [POINTER(CRxCondDesc)]
+    L.rxgs_rxcond_param_count.restype = c_int64
+    L.rxgs_rxcond_upload.argtypes = [vp, POINTER(CRxCondDesc), vp, vp, c_int, vp]
+    L.rxgs_rxcond_upload.restype = c_int
+    L.rxgs_render_rxcond.argtypes = [vp, c_int, c_int, vp, POINTER(c_int32), c_int, vp, vp, vp, vp, vp, vp, vp]
+    L.rxgs_render_rxcond.restype = c_int
+    L.rxgs_rxcond_export.argtypes = [vp, c_int, vp, c_int64, c_int]
+    L.rxgs_rxcond_export.restype = c_int
     L.rxgs_profile_enable.argtypes = [vp, c_int]
     L.rxgs_profile_read.argtypes = [vp, POINTER(CStageTime), c_int, POINTER(c_int), c_int]
     for name in ("rxgs_create", "rxgs_scene_upload", "rxgs_mlp_upload", "rxgs_saved_create", "rxgs_render",
@@ -314,6 +334,66 @@ class Renderer:
         if want_amp:
             return C, P, S, A
         return C, P, S
+
+    def upload_rxcond(self, model):
+        """Upload the paper's conditioning model (rxgs_rxcond_upload): model has kind
+        (BASIS_FLE / BASIS_SH), lmax, C, F, H, S, G, coeffs (K, L, C, 2) and params (flat)."""
+        self.rxc_desc = CRxCondDesc(int(model.kind), int(model.lmax), int(model.C), int(model.F), int(model.H),
+                                    int(model.S), int(model.G), 0)
+        n = lib().rxgs_rxcond_param_count(byref(self.rxc_desc))
+        if n < 0:
+            raise ValueError("invalid conditioning descriptor")
+        co = _dev_f32(model.coeffs, self.device).reshape(-1)
+        pa = _dev_f32(model.params, self.device).reshape(-1)
+        if pa.numel() != n:
+            raise ValueError(f"the conditioning model needs {n} parameters, got {pa.numel()}")
+        if co.numel() != self.K * (int(model.lmax) + 1) ** 2 * int(model.C) * 2:
+            raise ValueError("coefficients must be K x L x C x 2")
+        self._rxc_keep = (co, pa)
+        _check(lib().rxgs_rxcond_upload(self._ctx, byref(self.rxc_desc), _ptr(co), _ptr(pa), 1, self._stream()),
+               self._ctx)
+        self.rxc_C = int(model.C)
+
+    def render_rxcond(self, rx, tx=None, rx_off=None, mode: str = "tx", saved: Saved | None = None,
+                      want_csum: bool = False, want_amp: bool = False):
+        """Render with the conditioned radiance (rxgs_render_rxcond): (C (N, Ch, 2, H, W),
+        power (N, Ch), csum (N, Ch, 2) or None, amplitude (N, Ch, H, W) or None)."""
+        torch = _torch()
+        rx_t = _dev_f32(rx, self.device).reshape(-1, 3)
+        N = int(rx_t.shape[0])
+        if mode not in ("tx", "rx"):
+            raise ValueError("mode must be 'tx' or 'rx'")
+        m = MODE_TX if mode == "tx" else MODE_RX
+        tx_t, Q, off_arr = None, 0, None
+        if m == MODE_TX:
+            tx_t = _dev_f32(tx, self.device).reshape(-1, 3)
+            Q = int(tx_t.shape[0])
+            if rx_off is None:
+                if Q != 1:
+                    raise ValueError("rx_off is needed with several transmitters")
+                rx_off = [0, N]
+            off_arr = (c_int32 * (Q + 1))(*[int(x) for x in rx_off])
+        H, W, Ch = self.grid.H, self.grid.W, self.rxc_C
+        dev = self.device
+        C = torch.empty((N, Ch, 2, H, W), device=dev, dtype=torch.float32)
+        P = torch.empty((N, Ch), device=dev, dtype=torch.float32)
+        S = torch.empty((N, Ch, 2), device=dev, dtype=torch.float32) if want_csum else None
+        A = torch.empty((N, Ch, H, W), device=dev, dtype=torch.float32) if want_amp else None
+        _check(lib().rxgs_render_rxcond(self._ctx, m, Q, _ptr(tx_t), off_arr, N, _ptr(rx_t), _ptr(C), _ptr(P),
+                                        _ptr(S), _ptr(A), None if saved is None else saved._h, self._stream()),
+               self._ctx)
+        return C, P, S, A
+
+    def rxcond_export(self, what: int):
+        """Occupancy grid (G, G, G) f32 indexed [z, y, x], or the grid box (lo (3,), hi (3,))."""
+        if what == RXCOND_BOX:
+            out = np.zeros(6, dtype=np.float64)
+            _check(lib().rxgs_rxcond_export(self._ctx, what, out.ctypes.data_as(c_void_p), out.nbytes, 0), self._ctx)
+            return out[:3].copy(), out[3:].copy()
+        G = int(self.rxc_desc.grid)
+        out = np.zeros((G, G, G), dtype=np.float32)
+        _check(lib().rxgs_rxcond_export(self._ctx, what, out.ctypes.data_as(c_void_p), out.nbytes, 0), self._ctx)
+        return out
 
     def render_chunked(self, rx, tx=None, rx_off=None, mode: str = "tx", budget_bytes: int = 0, out=None):
         """Coverage map: the receivers streamed through chunks whose workspace fits
