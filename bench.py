@@ -60,8 +60,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target wall time of the oracle sample")
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-rxcond", action="store_true", help="skip the paper's conditioned-radiance workloads")
     ap.add_argument("--no-scale", action="store_true", help="skip the 1M-Gaussian scale workload")
-    ap.add_argument("--serve-queries", type=int, default=400)
+    ap.add_argument("--serve-queries", type=int, default=2000, help="measured queries per arrival rate")
+    ap.add_argument("--serve-warmup", type=int, default=200, help="warm-up queries before the serving runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain copy of this many MiB (counter calibration for profiled runs)")
     return ap.parse_args()
@@ -242,6 +244,61 @@ def scale_part(args):
                         f"(L2 loss, all gradients); coverage map of {N} receivers of one transmitter", **out}
 
 
+def rxcond_part(args):
+    """The paper's own radiance path (FiLM global branch, occupancy local
+    branch, FLE / SH basis) on its inference shape: 32,000 Gaussians in an
+    8 x 6 x 3 m room, 21 receivers, 90 x 360, one transmitter (Table 2's
+    setting; App. E Table 4: lmax 9, F = 6, d = 64, S = 16, 128^3 grid).
+    Fused render of all receivers against the same library called once per
+    receiver; both view modes; the SH backbone (degree 4) and a 26-channel
+    CSI-shaped signal on a 72 x 18 grid beside it."""
+    import torch
+    from paper_2605_24290_amd import rxgs
+    from paper_2605_24290_amd import scenes as S
+
+    dev = torch.device("cuda", 0)
+    out = {}
+    cases = [("fle_l9", S.BASIS_FLE, 9, 1, None), ("sh_l4", S.BASIS_SH, 4, 1, None),
+             ("csi_c26_fle_l4", S.BASIS_FLE, 4, 26, S.Grid(18, 72, 0.0, math.radians(5.0)))]
+    for name, kind, lmax, C, grid in cases:
+        wl = S.make_workload("paper", grid=grid, use_mlp=False)
+        sc = wl.scene
+        m = S.make_rxcond_model(sc.K, kind=kind, lmax=lmax, C=C, F=6, H=64)
+        r = rxgs.Renderer(wl.grid)
+        r.upload_scene(sc.means, sc.log_scales, sc.quats, sc.logits)
+        t0 = time.perf_counter()
+        r.upload_rxcond(m)
+        torch.cuda.synchronize()
+        t_up = time.perf_counter() - t0
+        rx = torch.as_tensor(wl.rx, device=dev)
+        tx = torch.as_tensor(wl.tx, device=dev)
+        N = rx.shape[0]
+        entry = {"gaussians": sc.K, "receivers": N, "channels": C, "basis": "FLE" if kind == S.BASIS_FLE else "SH",
+                 "lmax": lmax, "components": (lmax + 1) ** 2, "grid": [wl.grid.H, wl.grid.W],
+                 "upload_s": t_up}
+        for mode in ("tx", "rx"):
+            ms = timed(lambda: r.render_rxcond(rx, tx=tx, mode=mode), args.steps, args.warmup)
+            r.profile(True)
+            r.profile_read(reset=True)
+            timed(lambda: r.render_rxcond(rx, tx=tx, mode=mode), 3, 0)
+            stages = r.profile_read(reset=True)
+            r.profile(False)
+
+            def loop():
+                for j in range(N):
+                    r.render_rxcond(rx[j:j + 1], tx=tx, mode=mode)
+            ms_loop = timed(loop, 2, 1)
+            entry[mode] = {"ms_per_render": ms, "rx_views_per_s": N * C * 1000.0 / ms,
+                           "per_rx_loop_ms": ms_loop, "fused_speedup": ms_loop / ms,
+                           "stages_ms_per_render": {k: v[1] / 3 for k, v in stages.items()}}
+        r.close()
+        out[name] = entry
+        torch.cuda.empty_cache()
+    return {"workload": "paper inference shape: 32,000 Gaussians (8 x 6 x 3 m), 21 receivers, 1 transmitter; "
+                        "the paper's conditioned radiance; rx_views_per_s counts (receiver, channel) spectra",
+            "paper_h100_ms_all_21_rx": {"GSRF (FLE)": 31.2, "RF-3DGS (SH)": 35.3}, **out}
+
+
 def serving_part(args):
     """Continuous batching on the 200k-Gaussian scene: saturation throughput of
     a burst, then open-loop Poisson arrivals at 0.3 / 0.6 / 0.9 of it."""
@@ -255,7 +312,7 @@ def serving_part(args):
     r.upload_mlp(S.flat_mlp(wl.mlp))
     box = S.PRESETS["c3"].box
     srv = rxgs.Server(r, mode="tx", slots=2, max_rx_per_batch=4096, max_queries_per_batch=64)
-    warm = S.serving_queries(1, 64, box)
+    warm = S.serving_queries(1, args.serve_warmup, box)
     serving.run_burst(srv, warm)
     qs = S.serving_queries(S.BASE_SEED + 3000, args.serve_queries, box)
     sat = serving.run_burst(srv, qs)
@@ -266,7 +323,8 @@ def serving_part(args):
     srv.stop()
     r.close()
     return {"workload": f"c3: {sc.K} Gaussians resident, TX mode, queries of 1-256 receivers (log-uniform), "
-                        f"{args.serve_queries} queries per rate, 2 slots", "saturation": sat,
+                        f"{args.serve_warmup} warm-up queries, then {args.serve_queries} queries per rate, 2 slots",
+            "saturation": sat,
             "rates_x_saturation": rates, "server_stats": st}
 
 
@@ -475,6 +533,8 @@ def main():
         out["train_step"] = train_step_part(args)
     if not args.no_scale:
         out["scale"] = scale_part(args)
+    if not args.no_rxcond:
+        out["rxcond"] = rxcond_part(args)
     if not args.no_serve:
         out["serving"] = serving_part(args)
     if not args.no_cpu_baseline:

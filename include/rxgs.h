@@ -246,6 +246,8 @@ typedef struct {
                                  look-back wait expired and that counted the digits of
                                  their segment's earlier tiles directly instead (exact;
                                  normally 0) */
+    int64_t workspace_bytes;  /* device bytes the render's workspace buffers asked for
+                                 (what rxgs_workspace_estimate bounds, outputs aside) */
 } rxgs_saved_info_t;
 
 rxgs_status rxgs_saved_info(const rxgs_saved *s, rxgs_saved_info_t *out);
@@ -299,21 +301,51 @@ typedef struct {
 
 typedef struct {
     double t_submit;           /* seconds, host monotonic clock */
-    double t_start;            /* batch launched */
+    double t_start;            /* batch launched (the last attempt's) */
     double t_done;             /* results copied to host */
     int32_t batch_queries;     /* queries in the batch that carried it */
     int32_t batch_receivers;
+    int32_t attempts;          /* batches that carried it (2: replayed once after a failed batch) */
+    int32_t reserved;
 } rxgs_ticket_info;
 
 typedef struct {
     int64_t submitted, completed, cancelled, rejected, failed, batches, receivers;
     int64_t queued, in_flight;
     double busy_s;             /* summed wall time of batches on the device */
+    int64_t failed_batches;    /* batches whose launch or device work failed */
+    int64_t replayed;          /* tickets queued again after their batch failed */
+    int64_t peak_slot_bytes;   /* largest device workspace one batch used (buffers it asked for) */
+    int64_t over_estimate;     /* batches whose workspace exceeded the admission estimate */
 } rxgs_server_stats_t;
 
-/* Start the worker on a context with an uploaded scene (and MLP).
+/* Start the worker on a context with an uploaded scene (and MLP).  A batch
+ * whose launch fails (e.g. the allocator returns NULL: E_OOM) or whose device
+ * work reports an error has its slot reset (stream, event and workspace made
+ * again) and its tickets queued again at the front, once; a ticket whose
+ * second batch fails too is retired with that batch's status.  Other tickets
+ * and the worker carry on.
  * Errors: E_INVALID (options), E_STATE (no scene / MLP), E_OOM, E_DEVICE. */
 rxgs_status rxgs_server_start(rxgs_ctx *ctx, const rxgs_server_opts *opts, rxgs_server **out);
+
+/* The same scheduler (admission, continuous batching, retirement, replay)
+ * against a host-only executor instead of the GPU, for tests of the serving
+ * logic without a device: a batch "renders" power_j = tx.x + r_j.x + 2 r_j.y +
+ * 3 r_j.z for each of its receivers after delay_us microseconds; the launch
+ * with index i (0-based, counting every launch) fails with E_OOM when
+ * fail_launch_mask has bit i set (i < 64), and its work reports a device error
+ * when fail_device_mask has bit i set.  K, H and W feed the admission estimate.
+ * want_spectra must be 0. */
+typedef struct {
+    int64_t K;
+    int32_t H, W;
+    int32_t delay_us;
+    int32_t reserved;
+    uint64_t fail_launch_mask;
+    uint64_t fail_device_mask;
+} rxgs_host_executor;
+rxgs_status rxgs_server_start_host(const rxgs_server_opts *opts, const rxgs_host_executor *exec,
+                                   rxgs_server **out);
 /* Queue one query: tx host 3 floats, rx_host n x 3 floats (copied).  Returns
  * a ticket.  Errors: E_INVALID (n < 1, n > max_rx_per_batch, non-finite,
  * workspace estimate above the per-slot budget), E_BUSY (queue full), E_STATE (stopped). */
@@ -323,7 +355,7 @@ rxgs_status rxgs_server_submit(rxgs_server *srv, const float *tx, int32_t n, con
  * (n floats) and, if the server keeps spectra and C_host is not NULL, the
  * n x 2 x H x W spectra, fill info (may be NULL) and retire the ticket.
  * Errors: E_TIMEOUT (still pending), E_CANCELLED, E_INVALID (unknown ticket),
- * E_DEVICE (its batch failed). */
+ * E_OOM or E_DEVICE (its batch failed twice; info is still filled). */
 rxgs_status rxgs_server_poll(rxgs_server *srv, uint64_t ticket, float *power_host, float *C_host,
                              rxgs_ticket_info *info, int32_t timeout_ms);
 /* Cancel a queued ticket (a ticket already on the device completes). */

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 using namespace rxgs;
 
@@ -43,6 +44,7 @@ rxgs_status hip_fail(rxgs_ctx *ctx, hipError_t e, const char *what)
 // a buffer of workspace w (its own allocator, else the context's)
 #define WGROW(ctx, w, buf, bytes)                                                 \
     do {                                                                          \
+        (w).req_bytes += (bytes);                                                 \
         if (!grow((buf), (bytes), (w).al ? (w).al : &(ctx)->alloc))               \
             return fail(ctx, RXGS_E_OOM, (w).al && (w).al->base                   \
                                              ? "scratch region exhausted: " #buf  \
@@ -711,6 +713,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     Workspace &ws = saved ? saved->ws : ctx->ws;
     const bool save = saved && saved->keep;   // keep state for the backward and the exports
     ws.valid = false;
+    ws.req_bytes = 0;
     if (!ws.staged) {
         HIPCHK(ctx, hipEventCreateWithFlags(&ws.staged, hipEventDisableTiming));
         HIPCHK(ctx, hipEventCreateWithFlags(&ws.counted, hipEventDisableTiming));
@@ -820,7 +823,11 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     // (in rows: a view's receivers, and each receiver's channels, are consecutive)
     const bool shared_view = mode == RXGS_MODE_TX || Ch > 1;   // several rows share a view's weights
     int maxr = 1;
-    for (int v = 0; v < V; v++) maxr = std::max(maxr, vnrx[v] * Ch);
+    ws.rx_max = 1;
+    for (int v = 0; v < V; v++) {
+        maxr = std::max(maxr, vnrx[v] * Ch);
+        ws.rx_max = std::max(ws.rx_max, vnrx[v]);
+    }
     ws.R_max = maxr;
     int R = 1;
     if (shared_view)
@@ -1500,6 +1507,7 @@ extern "C" rxgs_status rxgs_saved_info(const rxgs_saved *s, rxgs_saved_info_t *o
         out->n_evaluated_px += (int64_t)h[2 * STAT_SLOTS + i];
         out->n_walked_px += (int64_t)h[3 * STAT_SLOTS + i];
     }
+    out->workspace_bytes = (int64_t)ws.req_bytes;
     out->n_sort_fallbacks = 0;
     const uint32_t *fw[2] = {sort_fallback_word(w.hist, (uint32_t)((size_t)ws.V * ws.Kp), 32, ws.V),
                              sort_fallback_word(w.hist_b, (uint32_t)ws.Dpad, ws.pair_bits, ws.V)};

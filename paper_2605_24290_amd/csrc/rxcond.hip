@@ -233,7 +233,7 @@ __global__ __launch_bounds__(BLOCK) void k_rxcond_local(
     const int4 *__restrict__ items, int nitems, const int *__restrict__ nlive, int64_t Kp,
     const float *__restrict__ occ, int G, RcBox box, const double *__restrict__ tprobe, int S,
     const float *__restrict__ lw1, const float *__restrict__ lb1, const float *__restrict__ w2t,
-    const float *__restrict__ lb2, const float *__restrict__ lw3, const float *__restrict__ lb3, int C,
+    const float *__restrict__ lb2, const float *__restrict__ lw3, const float *__restrict__ lb3, int C, int rpu,
     float4 *__restrict__ rloc)
 {
 #pragma clang fp contract(off)
@@ -262,16 +262,19 @@ __global__ __launch_bounds__(BLOCK) void k_rxcond_local(
     __syncthreads();
     const int lane = threadIdx.x & 63, h = lane >> 5, pl = lane & 31;
     const float invS = 1.f / (float)S;
-    for (int item = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); item < nitems;
-         item += gridDim.x * (BLOCK / 64)) {
+    // one unit = (work item, one of its receivers): rpu units per item
+    const int nunits = nitems * rpu;
+    for (int u = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); u < nunits; u += gridDim.x * (BLOCK / 64)) {
+        const int item = u / rpu, jj = u - item * rpu;
         const int4 it = items[item];
         const int view = it.x, s0 = it.y, j0 = it.z, nj = it.w & 255, nvalid = it.w >> 8;
+        if (jj >= nj) continue;
         const bool valid = pl < nvalid;
         const int64_t s = s0 + pl;
         const int64_t k = min((int64_t)order[(size_t)view * Kp + (valid ? s : s0)], K - 1);
         const float px = soa[k], py = soa[K + k], pz = soa[2 * K + k];
         const double pd[3] = {(double)px, (double)py, (double)pz};
-        for (int jj = 0; jj < nj; jj++) {
+        {
             const int j = j0 + jj;
             const float rxx = rxpos[3 * j], rxy = rxpos[3 * j + 1], rxz = rxpos[3 * j + 2];
             const double rd[3] = {(double)rxx, (double)rxy, (double)rxz};
@@ -356,7 +359,7 @@ __global__ __launch_bounds__(BLOCK) void k_rxcond_eval(
     const float *__restrict__ soa, int64_t K, const float *__restrict__ centres, const uint32_t *__restrict__ order,
     const int4 *__restrict__ items, int nitems, const int *__restrict__ nlive, int64_t Kp,
     const float2 *__restrict__ coef, const float4 *__restrict__ rab, const float4 *__restrict__ rloc,
-    const float4 *__restrict__ ctab, int lmax, int L, int n0, int C, float2 *__restrict__ rad)
+    const float4 *__restrict__ ctab, int lmax, int L, int n0, int C, int rpu, float2 *__restrict__ rad)
 {
     if (nlive) nitems = min(nitems, *nlive);
     __shared__ float4 s_ct[RC_TAB * RC_TAB];
@@ -364,10 +367,12 @@ __global__ __launch_bounds__(BLOCK) void k_rxcond_eval(
     __syncthreads();
     const int lane = threadIdx.x & 63, h = lane >> 5, pl = lane & 31;
     const float SQ2 = 1.41421356237309515f;
-    for (int item = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); item < nitems;
-         item += gridDim.x * (BLOCK / 64)) {
+    const int nunits = nitems * rpu;
+    for (int u = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6); u < nunits; u += gridDim.x * (BLOCK / 64)) {
+        const int item = u / rpu, ju = u - item * rpu;
         const int4 it = items[item];
         const int view = it.x, s0 = it.y, j0 = it.z, nj = it.w & 255, nvalid = it.w >> 8;
+        if (ju >= nj) continue;
         const bool valid = pl < nvalid;
         const int64_t s = s0 + pl;
         const int64_t k = min((int64_t)order[(size_t)view * Kp + (valid ? s : s0)], K - 1);
@@ -382,8 +387,8 @@ __global__ __launch_bounds__(BLOCK) void k_rxcond_eval(
         const float sp = rh > 0.f ? dy / rh : 0.f;
         const float c2 = cp * cp - sp * sp, s2 = 2.f * cp * sp;
         const float2 *crow = coef + (size_t)k * L * C;
-        for (int jj = 0; jj < nj; jj++) {
-            const int j = j0 + jj;
+        {
+            const int j = j0 + ju;
             const float4 *arow = rab + (size_t)j * L * C;
             for (int c0 = 0; c0 < C; c0 += RC_CH_PASS) {
                 const int nc = min(RC_CH_PASS, C - c0);
@@ -581,24 +586,26 @@ hipError_t launch_rxcond_pairs(const Scene &sc, const RxCond &m, Workspace &ws, 
     const int *nlive = far ? far_count(ws) : ws.lazy ? live_count(ws) : nullptr;
     const int nmax = far ? ws.n_items_far : ws.n_items;
     if (nmax <= 0) return hipSuccess;
-    const unsigned blocks = (unsigned)std::min((nmax + 3) / 4, 256 * 8);
+    // a wave per (item, receiver): items carry up to MLP_RG receivers of a view
+    const int rpu = std::max(1, std::min(MLP_RG, ws.rx_max));
+    const unsigned blocks = (unsigned)std::min<int64_t>(((int64_t)nmax * rpu + 3) / 4, 256 * 8);
     const float *P = m.params.as<float>();
     RcBox box = rc_box(m);
     const size_t lds = (size_t)(4 * m.C * RC_H + 4 * m.C) * 4;
     hipLaunchKernelGGL(k_rxcond_local, dim3(blocks), dim3(BLOCK), lds, st, sc.soa.as<float>(), sc.K, ws.rxpos_p,
                        ws.vorder.as<uint32_t>(), items, nmax, nlive, ws.Kp, m.occ.as<float>(), m.G, box,
                        m.tprobe.as<double>(), m.S, P + m.off.l1, P + m.off.lb1, m.w2t.as<float>(), P + m.off.lb2,
-                       P + m.off.l3, P + m.off.lb3, m.C, ws.rloc.as<float4>());
+                       P + m.off.l3, P + m.off.lb3, m.C, rpu, ws.rloc.as<float4>());
     if (m.kind == RXGS_BASIS_FLE)
         hipLaunchKernelGGL(k_rxcond_eval<RXGS_BASIS_FLE>, dim3(blocks), dim3(BLOCK), 0, st, sc.soa.as<float>(), sc.K,
                            ws.centres_p, ws.vorder.as<uint32_t>(), items, nmax, nlive, ws.Kp, m.coef.as<float2>(),
                            ws.rab.as<float4>(), ws.rloc.as<float4>(), m.ctab.as<float4>(), m.lmax, m.L, m.n0, m.C,
-                           ws.rad.as<float2>());
+                           rpu, ws.rad.as<float2>());
     else
         hipLaunchKernelGGL(k_rxcond_eval<RXGS_BASIS_SH>, dim3(blocks), dim3(BLOCK), 0, st, sc.soa.as<float>(), sc.K,
                            ws.centres_p, ws.vorder.as<uint32_t>(), items, nmax, nlive, ws.Kp, m.coef.as<float2>(),
                            ws.rab.as<float4>(), ws.rloc.as<float4>(), m.ctab.as<float4>(), m.lmax, m.L, m.n0, m.C,
-                           ws.rad.as<float2>());
+                           rpu, ws.rad.as<float2>());
     return hipGetLastError();
 }
 

@@ -146,12 +146,14 @@ struct Workspace {
     Allocator *al = nullptr;   // source of its device buffers (nullptr: the context's)
     int rsrc = RSRC_SCENE;     // radiance source of the last render
     int Nrx = 0, Ch = 1;       // receivers and channels (rows N = Nrx x Ch)
+    int rx_max = 1;            // most receivers of one view
     bool use_items = false;    // radiance evaluated per MLP work item (MLP or conditioning model)
     uint64_t rxc_version = 0;
     DevBuf rgam;               // Nrx x 64 receiver term of the conditioning's global layer 1
     DevBuf rab;                // Nrx x L x C float4 global modulation (1 + alpha, beta), walk order
     DevBuf rloc;               // Nrx x Kp x C float4 local modulation (1 + alpha', beta') per sorted position
     bool fixed_host = false;   // h_pinned is a fixed buffer made at set-up (never regrown)
+    size_t req_bytes = 0;      // device bytes the last render's buffers asked for
     // sizes of the last render
     int mode = 0, V = 0, N = 0, Q = 0, R = 1;
     int64_t K = 0, Kp = 0, D = 0, Dpad = 0, nvis_total = 0;

@@ -28,12 +28,16 @@ int64_t round_up64(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 enum TicketState { T_QUEUED = 0, T_RUNNING = 1, T_DONE = 2, T_CANCELLED = 3, T_FAILED = 4 };
 
+constexpr int MAX_ATTEMPTS = 2;   // a ticket rides at most this many batches (one replay)
+
 struct Ticket {
     uint64_t id = 0;
     float tx[3] = {0, 0, 0};
     std::vector<float> rx;
     int n = 0;
     int state = T_QUEUED;
+    int status = RXGS_OK;   // of a failed ticket
+    int attempts = 0;
     double t_submit = 0, t_start = 0, t_done = 0;
     int batch_q = 0, batch_n = 0;
     std::vector<float> power;
@@ -56,6 +60,11 @@ struct Slot {
     std::vector<uint64_t> tickets;
     std::vector<int> offs;   // receiver offset of each ticket in the batch
     int N = 0;
+    int64_t est_bytes = 0;   // admission estimate of the batch
+    // host executor: results and completion of the batch in flight
+    std::vector<float> host_P;
+    double ready_at = 0;
+    bool host_fail = false;
 };
 
 bool pinned_grow(float *&p, size_t &cap, size_t n)
@@ -74,11 +83,30 @@ bool pinned_grow(float *&p, size_t &cap, size_t n)
     return true;
 }
 
+// What runs the batches the scheduler forms: the GPU render, or a host-only
+// stand-in for tests of the scheduling and failure paths.
+struct Executor {
+    virtual ~Executor() = default;
+    virtual rxgs_status init_slot(rxgs_server *s, Slot &sl) = 0;
+    virtual void free_slot(rxgs_server *s, Slot &sl) = 0;
+    // enqueue one batch; on failure nothing of it is left in flight
+    virtual rxgs_status launch(rxgs_server *s, Slot &sl, std::vector<Ticket *> &batch) = 0;
+    // 0 finished, 1 still running, 2 failed
+    virtual int query(Slot &sl) = 0;
+    // results of ticket b of the slot's finished batch
+    virtual void fetch(rxgs_server *s, Slot &sl, size_t b, Ticket &tk) = 0;
+    // device memory the slot's last batch asked for (-1: not tracked)
+    virtual int64_t used_bytes(rxgs_server *s, Slot &sl) = 0;
+};
+
 }  // namespace
 
 struct rxgs_server {
-    rxgs_ctx *ctx = nullptr;
+    rxgs_ctx *ctx = nullptr;   // NULL with the host executor
+    Executor *exec = nullptr;
     rxgs_server_opts opts{};
+    int64_t K = 0;
+    int32_t H = 0, W = 0;
     int64_t slot_budget = 0;
     std::thread worker;
     std::mutex mu;
@@ -111,6 +139,9 @@ extern "C" int64_t rxgs_workspace_estimate(int32_t mode, int32_t Q, int32_t N, i
     b += (mode == RXGS_MODE_TX ? V : N) * P * 8;   // final transmittance, stop index
     b += (int64_t)N * tiles * 12 + V * tiles * 8;  // partial sums, ranges
     b += std::max<int64_t>(K, 1) * (256 + 84) + (int64_t)N * 256;  // MLP layer-1 terms, projection terms
+    b += V * P * (FAR_RECORDS * 8 + 1) + V * tiles;   // far records of the radiance prefix, their counts and tile marks
+    b += VK / MLP_PAIRS * (17 + 16 * ((N + MLP_RG - 1) / MLP_RG)) + ((int64_t)1 << 20);   // work items, block marks,
+                                                                                       // counters and descriptors
     return b;
 }
 
@@ -137,90 +168,207 @@ extern "C" int32_t rxgs_plan_batch(const int32_t *n_rx, int32_t n_queued, int32_
 // ---------------------------------------------------------------------------
 namespace {
 
-// launch one batch on a free slot (called by the worker with the lock released)
-rxgs_status launch_batch(rxgs_server *s, Slot &sl, std::vector<Ticket *> &batch)
+// The GPU executor: one rxgs_render per batch on the slot's stream into its
+// private workspace, results copied back to pinned memory.
+struct GpuExecutor final : Executor {
+    rxgs_status init_slot(rxgs_server *s, Slot &sl) override
+    {
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return RXGS_E_DEVICE;
+        }
+        if (rxgs_saved_create(s->ctx, &sl.saved) != RXGS_OK) return RXGS_E_OOM;
+        sl.saved->keep = false;   // the slot's private workspace; nothing is kept for a backward
+        return RXGS_OK;
+    }
+
+    void free_slot(rxgs_server *s, Slot &sl) override
+    {
+        (void)s;
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        (void)hipGetLastError();
+        if (sl.saved) rxgs_saved_destroy(sl.saved);
+        sl.saved = nullptr;
+        release(sl.d_tx);
+        release(sl.d_rx);
+        release(sl.d_C);
+        release(sl.d_P);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        sl.done = nullptr;
+        sl.stream = nullptr;
+    }
+
+    rxgs_status launch(rxgs_server *s, Slot &sl, std::vector<Ticket *> &batch) override
+    {
+        rxgs_ctx *ctx = s->ctx;
+        const int mode = s->opts.mode;
+        const int Q = (int)batch.size();
+        const int N = sl.N;
+        const size_t P = (size_t)ctx->g.H * ctx->g.W;
+        if (!pinned_grow(sl.h_in, sl.h_in_cap, (size_t)(Q + N) * 3) || !pinned_grow(sl.h_P, sl.h_P_cap, (size_t)N))
+            return RXGS_E_OOM;
+        if (s->opts.want_spectra && !pinned_grow(sl.h_C, sl.h_C_cap, (size_t)N * 2 * P)) return RXGS_E_OOM;
+        std::vector<int32_t> rx_off(Q + 1, 0);
+        for (int q = 0; q < Q; q++) {
+            std::memcpy(sl.h_in + 3 * q, batch[q]->tx, 12);
+            std::memcpy(sl.h_in + 3 * Q + 3 * sl.offs[q], batch[q]->rx.data(), (size_t)batch[q]->n * 12);
+            rx_off[q + 1] = rx_off[q] + batch[q]->n;
+        }
+        rxgs::Allocator *al = &ctx->alloc;
+        if (!grow(sl.d_tx, (size_t)Q * 12, al) || !grow(sl.d_rx, (size_t)N * 12, al) ||
+            !grow(sl.d_P, (size_t)N * 4, al) || !grow(sl.d_C, (size_t)N * 2 * P * 4, al))
+            return RXGS_E_OOM;
+        if (hipMemcpyAsync(sl.d_tx.p, sl.h_in, (size_t)Q * 12, hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
+            hipMemcpyAsync(sl.d_rx.p, sl.h_in + 3 * Q, (size_t)N * 12, hipMemcpyHostToDevice, sl.stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return RXGS_E_DEVICE;
+        }
+        rxgs_status rs = rxgs_render(ctx, mode, Q, sl.d_tx.as<float>(), rx_off.data(), N, sl.d_rx.as<float>(),
+                                     sl.d_C.as<float>(), sl.d_P.as<float>(), nullptr, nullptr, sl.saved, sl.stream);
+        if (rs != RXGS_OK) return rs;
+        if (hipMemcpyAsync(sl.h_P, sl.d_P.p, (size_t)N * 4, hipMemcpyDeviceToHost, sl.stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return RXGS_E_DEVICE;
+        }
+        if (s->opts.want_spectra &&
+            hipMemcpyAsync(sl.h_C, sl.d_C.p, (size_t)N * 2 * P * 4, hipMemcpyDeviceToHost, sl.stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return RXGS_E_DEVICE;
+        }
+        if (hipEventRecord(sl.done, sl.stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return RXGS_E_DEVICE;
+        }
+        return RXGS_OK;
+    }
+
+    int query(Slot &sl) override
+    {
+        const hipError_t q = hipEventQuery(sl.done);
+        if (q == hipErrorNotReady) return 1;
+        if (q == hipSuccess) return 0;
+        (void)hipGetLastError();
+        return 2;
+    }
+
+    void fetch(rxgs_server *s, Slot &sl, size_t b, Ticket &tk) override
+    {
+        const size_t P = (size_t)s->ctx->g.H * s->ctx->g.W;
+        tk.power.assign(sl.h_P + sl.offs[b], sl.h_P + sl.offs[b] + tk.n);
+        if (s->opts.want_spectra)
+            tk.C.assign(sl.h_C + (size_t)sl.offs[b] * 2 * P, sl.h_C + (size_t)(sl.offs[b] + tk.n) * 2 * P);
+    }
+
+    int64_t used_bytes(rxgs_server *s, Slot &sl) override
+    {
+        if (!sl.saved) return -1;
+        const int64_t P = (int64_t)s->H * s->W;
+        // the workspace buffers the render asked for, and the batch's inputs and outputs
+        return (int64_t)sl.saved->ws.req_bytes + (int64_t)sl.tickets.size() * 12 + (int64_t)sl.N * 16 +
+               (int64_t)sl.N * 2 * P * 4;
+    }
+};
+
+// The host executor: every batch "renders" power_j = tx.x + r.x + 2 r.y + 3 r.z
+// per receiver after a fixed delay; launches and completions fail as scripted.
+struct HostExecutor final : Executor {
+    rxgs_host_executor cfg{};
+    int64_t launches = 0;
+
+    rxgs_status init_slot(rxgs_server *, Slot &) override { return RXGS_OK; }
+    void free_slot(rxgs_server *, Slot &sl) override { sl.host_P.clear(); }
+
+    rxgs_status launch(rxgs_server *, Slot &sl, std::vector<Ticket *> &batch) override
+    {
+        const int64_t i = launches++;
+        const uint64_t bit = i < 64 ? (1ull << i) : 0ull;
+        if (cfg.fail_launch_mask & bit) return RXGS_E_OOM;
+        sl.host_P.assign(sl.N, 0.f);
+        for (size_t q = 0; q < batch.size(); q++)
+            for (int j = 0; j < batch[q]->n; j++) {
+                const float *r = batch[q]->rx.data() + 3 * j;
+                sl.host_P[sl.offs[q] + j] = batch[q]->tx[0] + r[0] + 2.f * r[1] + 3.f * r[2];
+            }
+        sl.host_fail = (cfg.fail_device_mask & bit) != 0;
+        sl.ready_at = now_s() + 1e-6 * cfg.delay_us;
+        return RXGS_OK;
+    }
+
+    int query(Slot &sl) override
+    {
+        if (now_s() < sl.ready_at) return 1;
+        return sl.host_fail ? 2 : 0;
+    }
+
+    void fetch(rxgs_server *, Slot &sl, size_t b, Ticket &tk) override
+    {
+        tk.power.assign(sl.host_P.begin() + sl.offs[b], sl.host_P.begin() + sl.offs[b] + tk.n);
+    }
+
+    int64_t used_bytes(rxgs_server *, Slot &) override { return -1; }
+};
+
+// a batch that failed (at launch or on the device): the slot is made again
+// and each of its tickets goes back to the front of the queue, once; a ticket
+// whose second batch fails is retired with the failure
+void batch_failed(rxgs_server *s, Slot &sl, rxgs_status why)
 {
-    rxgs_ctx *ctx = s->ctx;
-    const int mode = s->opts.mode;
-    const int Q = (int)batch.size();
-    int N = 0;
-    sl.offs.clear();
-    for (Ticket *t : batch) {
-        sl.offs.push_back(N);
-        N += t->n;
+    s->st.failed_batches++;
+    s->exec->free_slot(s, sl);
+    if (s->exec->init_slot(s, sl) != RXGS_OK) s->err = "slot could not be made again after a failed batch";
+    const double t = now_s();
+    for (size_t b = sl.tickets.size(); b-- > 0;) {
+        auto it = s->tickets.find(sl.tickets[b]);
+        if (it == s->tickets.end()) continue;
+        Ticket &tk = it->second;
+        if (tk.attempts < MAX_ATTEMPTS && !s->stopping) {
+            tk.state = T_QUEUED;
+            s->queue.push_front(tk.id);
+            s->st.queued++;
+            s->st.replayed++;
+        } else {
+            tk.state = T_FAILED;
+            tk.status = why;
+            tk.t_done = t;
+            s->st.failed++;
+        }
     }
-    sl.N = N;
-    const size_t P = (size_t)ctx->g.H * ctx->g.W;
-    if (!pinned_grow(sl.h_in, sl.h_in_cap, (size_t)(Q + N) * 3) || !pinned_grow(sl.h_P, sl.h_P_cap, (size_t)N))
-        return RXGS_E_OOM;
-    if (s->opts.want_spectra && !pinned_grow(sl.h_C, sl.h_C_cap, (size_t)N * 2 * P)) return RXGS_E_OOM;
-    std::vector<int32_t> rx_off(Q + 1, 0);
-    for (int q = 0; q < Q; q++) {
-        std::memcpy(sl.h_in + 3 * q, batch[q]->tx, 12);
-        std::memcpy(sl.h_in + 3 * Q + 3 * sl.offs[q], batch[q]->rx.data(), (size_t)batch[q]->n * 12);
-        rx_off[q + 1] = rx_off[q] + batch[q]->n;
-    }
-    rxgs::Allocator *al = &s->ctx->alloc;
-    if (!grow(sl.d_tx, (size_t)Q * 12, al) || !grow(sl.d_rx, (size_t)N * 12, al) || !grow(sl.d_P, (size_t)N * 4, al) ||
-        !grow(sl.d_C, (size_t)N * 2 * P * 4, al))
-        return RXGS_E_OOM;
-    if (hipMemcpyAsync(sl.d_tx.p, sl.h_in, (size_t)Q * 12, hipMemcpyHostToDevice, sl.stream) != hipSuccess ||
-        hipMemcpyAsync(sl.d_rx.p, sl.h_in + 3 * Q, (size_t)N * 12, hipMemcpyHostToDevice, sl.stream) != hipSuccess) {
-        (void)hipGetLastError();
-        return RXGS_E_DEVICE;
-    }
-    rxgs_status rs = rxgs_render(ctx, mode, Q, sl.d_tx.as<float>(), rx_off.data(), N, sl.d_rx.as<float>(),
-                                 sl.d_C.as<float>(), sl.d_P.as<float>(), nullptr, nullptr, sl.saved, sl.stream);
-    if (rs != RXGS_OK) return rs;
-    if (hipMemcpyAsync(sl.h_P, sl.d_P.p, (size_t)N * 4, hipMemcpyDeviceToHost, sl.stream) != hipSuccess) {
-        (void)hipGetLastError();
-        return RXGS_E_DEVICE;
-    }
-    if (s->opts.want_spectra &&
-        hipMemcpyAsync(sl.h_C, sl.d_C.p, (size_t)N * 2 * P * 4, hipMemcpyDeviceToHost, sl.stream) != hipSuccess) {
-        (void)hipGetLastError();
-        return RXGS_E_DEVICE;
-    }
-    if (hipEventRecord(sl.done, sl.stream) != hipSuccess) {
-        (void)hipGetLastError();
-        return RXGS_E_DEVICE;
-    }
-    return RXGS_OK;
+    s->st.in_flight -= (int64_t)sl.tickets.size();
+    sl.tickets.clear();
+    sl.busy = false;
+    s->cv_done.notify_all();
 }
 
 void worker_main(rxgs_server *s)
 {
-    (void)hipSetDevice(s->ctx->device);
-    const size_t P = (size_t)s->ctx->g.H * s->ctx->g.W;
+    if (s->ctx) (void)hipSetDevice(s->ctx->device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         // retire finished batches
         bool any_busy = false;
         for (Slot &sl : s->slots) {
             if (!sl.busy) continue;
-            const hipError_t q = hipEventQuery(sl.done);
-            if (q == hipErrorNotReady) {
+            const int q = s->exec->query(sl);
+            if (q == 1) {
                 any_busy = true;
                 continue;
             }
+            if (q == 2) {
+                s->st.busy_s += now_s() - sl.t_launch;
+                batch_failed(s, sl, RXGS_E_DEVICE);
+                continue;
+            }
             const double t = now_s();
-            const bool ok = q == hipSuccess;
-            if (!ok) (void)hipGetLastError();
             for (size_t b = 0; b < sl.tickets.size(); b++) {
                 auto it = s->tickets.find(sl.tickets[b]);
                 if (it == s->tickets.end()) continue;
                 Ticket &tk = it->second;
-                if (ok) {
-                    tk.power.assign(sl.h_P + sl.offs[b], sl.h_P + sl.offs[b] + tk.n);
-                    if (s->opts.want_spectra)
-                        tk.C.assign(sl.h_C + (size_t)sl.offs[b] * 2 * P, sl.h_C + (size_t)(sl.offs[b] + tk.n) * 2 * P);
-                    tk.state = T_DONE;
-                    s->st.completed++;
-                } else {
-                    tk.state = T_FAILED;
-                    s->st.failed++;
-                }
+                s->exec->fetch(s, sl, b, tk);
+                tk.state = T_DONE;
                 tk.t_done = t;
+                s->st.completed++;
             }
             s->st.busy_s += t - sl.t_launch;
             s->st.in_flight -= (int64_t)sl.tickets.size();
@@ -228,7 +376,11 @@ void worker_main(rxgs_server *s)
             sl.busy = false;
             s->cv_done.notify_all();
         }
-        if (s->stopping && !any_busy) break;
+        if (s->stopping && !any_busy) {
+            bool busy_now = false;
+            for (Slot &sl : s->slots) busy_now |= sl.busy;
+            if (!busy_now) break;
+        }
         // launch batches on free slots (continuous batching)
         bool launched = false;
         if (!s->stopping) {
@@ -238,12 +390,13 @@ void worker_main(rxgs_server *s)
                 for (size_t i = 0; i < s->queue.size() && (int)i < s->opts.max_queries_per_batch; i++)
                     ns.push_back(s->tickets[s->queue[i]].n);
                 int64_t bytes = 0;
-                const int take = rxgs_plan_batch(ns.data(), (int32_t)ns.size(), s->opts.mode, s->ctx->scene.K,
-                                                 s->ctx->g.H, s->ctx->g.W, s->slot_budget,
-                                                 s->opts.max_rx_per_batch, s->opts.max_queries_per_batch, &bytes);
+                const int take = rxgs_plan_batch(ns.data(), (int32_t)ns.size(), s->opts.mode, s->K, s->H, s->W,
+                                                 s->slot_budget, s->opts.max_rx_per_batch,
+                                                 s->opts.max_queries_per_batch, &bytes);
                 if (take < 1) break;
                 std::vector<Ticket *> batch;
                 sl.tickets.clear();
+                sl.offs.clear();
                 int nrx = 0;
                 const double t = now_s();
                 for (int i = 0; i < take; i++) {
@@ -251,14 +404,18 @@ void worker_main(rxgs_server *s)
                     s->queue.pop_front();
                     tk.state = T_RUNNING;
                     tk.t_start = t;
+                    tk.attempts++;
                     batch.push_back(&tk);
                     sl.tickets.push_back(tk.id);
+                    sl.offs.push_back(nrx);
                     nrx += tk.n;
                 }
                 for (Ticket *tk : batch) {
                     tk->batch_q = take;
                     tk->batch_n = nrx;
                 }
+                sl.N = nrx;
+                sl.est_bytes = bytes;
                 s->st.queued -= take;
                 s->st.in_flight += take;
                 s->st.batches++;
@@ -267,24 +424,15 @@ void worker_main(rxgs_server *s)
                 sl.t_launch = t;
                 // ticket storage is stable while running (only this thread erases running tickets)
                 lk.unlock();
-                const rxgs_status rs = launch_batch(s, sl, batch);
+                const rxgs_status rs = s->exec->launch(s, sl, batch);
+                const int64_t used = rs == RXGS_OK ? s->exec->used_bytes(s, sl) : -1;
                 lk.lock();
                 if (rs != RXGS_OK) {
-                    s->err = s->ctx->err;
-                    for (uint64_t id : sl.tickets) {
-                        auto it = s->tickets.find(id);
-                        if (it != s->tickets.end()) {
-                            it->second.state = T_FAILED;
-                            it->second.t_done = now_s();
-                        }
-                        s->st.failed++;
-                    }
-                    s->st.in_flight -= (int64_t)sl.tickets.size();
-                    sl.tickets.clear();
-                    sl.busy = false;
-                    (void)hipStreamSynchronize(sl.stream);
-                    (void)hipGetLastError();
-                    s->cv_done.notify_all();
+                    if (s->ctx) s->err = s->ctx->err;
+                    batch_failed(s, sl, rs);
+                } else if (used >= 0) {
+                    s->st.peak_slot_bytes = std::max(s->st.peak_slot_bytes, used);
+                    if (used > sl.est_bytes) s->st.over_estimate++;
                 }
                 launched = true;
             }
@@ -300,15 +448,36 @@ void worker_main(rxgs_server *s)
     s->running = false;
 }
 
+rxgs_status server_options_ok(const rxgs_server_opts *opts)
+{
+    if (opts->max_rx_per_batch < 1 || opts->max_queries_per_batch < 1 || opts->slots < 1 || opts->slots > 8 ||
+        (opts->mode != RXGS_MODE_TX && opts->mode != RXGS_MODE_RX) || opts->queue_capacity < 1 ||
+        opts->mem_budget_bytes < 0)
+        return RXGS_E_INVALID;
+    return RXGS_OK;
+}
+
+// slots made by the executor, then the worker started
+rxgs_status start_worker(rxgs_server *s)
+{
+    s->slot_budget = s->opts.mem_budget_bytes / s->opts.slots;
+    s->slots.resize(s->opts.slots);
+    for (Slot &sl : s->slots) {
+        const rxgs_status rs = s->exec->init_slot(s, sl);
+        if (rs != RXGS_OK) return rs;
+    }
+    s->running = true;
+    s->worker = std::thread(worker_main, s);
+    return RXGS_OK;
+}
+
 }  // namespace
 
 extern "C" rxgs_status rxgs_server_start(rxgs_ctx *ctx, const rxgs_server_opts *opts, rxgs_server **out)
 {
     if (!ctx || !opts || !out) return RXGS_E_INVALID;
     *out = nullptr;
-    if (opts->max_rx_per_batch < 1 || opts->max_queries_per_batch < 1 || opts->slots < 1 || opts->slots > 8 ||
-        (opts->mode != RXGS_MODE_TX && opts->mode != RXGS_MODE_RX) || opts->queue_capacity < 1 ||
-        opts->mem_budget_bytes < 0) {
+    if (server_options_ok(opts) != RXGS_OK) {
         ctx->err = "invalid server options";
         return RXGS_E_INVALID;
     }
@@ -323,31 +492,59 @@ extern "C" rxgs_status rxgs_server_start(rxgs_ctx *ctx, const rxgs_server_opts *
     rxgs_server *s = new (std::nothrow) rxgs_server();
     if (!s) return RXGS_E_OOM;
     s->ctx = ctx;
+    s->exec = new (std::nothrow) GpuExecutor();
+    if (!s->exec) {
+        delete s;
+        return RXGS_E_OOM;
+    }
     s->opts = *opts;
-    int64_t budget = opts->mem_budget_bytes;
-    if (budget == 0) {
+    s->K = ctx->scene.K;
+    s->H = ctx->g.H;
+    s->W = ctx->g.W;
+    if (s->opts.mem_budget_bytes == 0) {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
             (void)hipGetLastError();
             fr = (size_t)8 << 30;
         }
-        budget = (int64_t)(fr / 2);
+        s->opts.mem_budget_bytes = (int64_t)(fr / 2);
     }
-    s->slot_budget = budget / opts->slots;
-    s->slots.resize(opts->slots);
-    for (Slot &sl : s->slots) {
-        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
-            rxgs_saved_create(ctx, &sl.saved) != RXGS_OK) {
-            (void)hipGetLastError();
-            ctx->err = "server slot creation failed";
-            rxgs_server_stop(s);
-            return RXGS_E_DEVICE;
-        }
-        sl.saved->keep = false;   // the slot's private workspace; nothing is kept for a backward
+    const rxgs_status rs = start_worker(s);
+    if (rs != RXGS_OK) {
+        ctx->err = "server slot creation failed";
+        rxgs_server_stop(s);
+        return rs;
     }
-    s->running = true;
-    s->worker = std::thread(worker_main, s);
+    *out = s;
+    return RXGS_OK;
+}
+
+extern "C" rxgs_status rxgs_server_start_host(const rxgs_server_opts *opts, const rxgs_host_executor *exec,
+                                              rxgs_server **out)
+{
+    if (!opts || !exec || !out) return RXGS_E_INVALID;
+    *out = nullptr;
+    if (server_options_ok(opts) != RXGS_OK || opts->want_spectra || opts->mem_budget_bytes <= 0 || exec->K < 0 ||
+        exec->H < 1 || exec->W < 1 || exec->delay_us < 0)
+        return RXGS_E_INVALID;
+    rxgs_server *s = new (std::nothrow) rxgs_server();
+    if (!s) return RXGS_E_OOM;
+    HostExecutor *he = new (std::nothrow) HostExecutor();
+    if (!he) {
+        delete s;
+        return RXGS_E_OOM;
+    }
+    he->cfg = *exec;
+    s->exec = he;
+    s->opts = *opts;
+    s->K = exec->K;
+    s->H = exec->H;
+    s->W = exec->W;
+    const rxgs_status rs = start_worker(s);
+    if (rs != RXGS_OK) {
+        rxgs_server_stop(s);
+        return rs;
+    }
     *out = s;
     return RXGS_OK;
 }
@@ -361,7 +558,7 @@ extern "C" rxgs_status rxgs_server_submit(rxgs_server *s, const float *tx, int32
         if (!std::isfinite(tx[i])) return RXGS_E_INVALID;
     for (int64_t i = 0; i < 3 * (int64_t)n; i++)
         if (!std::isfinite(rx_host[i])) return RXGS_E_INVALID;
-    if (rxgs_workspace_estimate(s->opts.mode, 1, n, s->ctx->scene.K, s->ctx->g.H, s->ctx->g.W) > s->slot_budget) {
+    if (rxgs_workspace_estimate(s->opts.mode, 1, n, s->K, s->H, s->W) > s->slot_budget) {
         std::lock_guard<std::mutex> lk(s->mu);
         s->st.rejected++;
         return RXGS_E_INVALID;
@@ -408,7 +605,7 @@ extern "C" rxgs_status rxgs_server_poll(rxgs_server *s, uint64_t ticket, float *
     Ticket &tk = it->second;
     rxgs_status rs = RXGS_OK;
     if (tk.state == T_CANCELLED) rs = RXGS_E_CANCELLED;
-    else if (tk.state == T_FAILED) rs = RXGS_E_DEVICE;
+    else if (tk.state == T_FAILED) rs = tk.status == RXGS_OK ? RXGS_E_DEVICE : (rxgs_status)tk.status;
     else {
         if (power_host) std::memcpy(power_host, tk.power.data(), tk.power.size() * 4);
         if (C_host && !tk.C.empty()) std::memcpy(C_host, tk.C.data(), tk.C.size() * 4);
@@ -419,6 +616,8 @@ extern "C" rxgs_status rxgs_server_poll(rxgs_server *s, uint64_t ticket, float *
         info->t_done = tk.t_done;
         info->batch_queries = tk.batch_q;
         info->batch_receivers = tk.batch_n;
+        info->attempts = tk.attempts;
+        info->reserved = 0;
     }
     s->tickets.erase(it);
     return rs;
@@ -468,20 +667,14 @@ extern "C" rxgs_status rxgs_server_stop(rxgs_server *s)
         s->cv_done.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
-    (void)hipSetDevice(s->ctx->device);
+    if (s->ctx) (void)hipSetDevice(s->ctx->device);
     for (Slot &sl : s->slots) {
-        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-        if (sl.saved) rxgs_saved_destroy(sl.saved);
-        release(sl.d_tx);
-        release(sl.d_rx);
-        release(sl.d_C);
-        release(sl.d_P);
+        if (s->exec) s->exec->free_slot(s, sl);
         if (sl.h_in) (void)hipHostFree(sl.h_in);
         if (sl.h_P) (void)hipHostFree(sl.h_P);
         if (sl.h_C) (void)hipHostFree(sl.h_C);
-        if (sl.done) (void)hipEventDestroy(sl.done);
-        if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
+    delete s->exec;
     delete s;
     return RXGS_OK;
 }

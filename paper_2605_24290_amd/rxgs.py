@@ -49,7 +49,7 @@ class CSavedInfo(ctypes.Structure):
     _fields_ = [("K", c_int64), ("K_pad", c_int64), ("V", c_int64), ("N", c_int64),
                 ("D", c_int64), ("n_visible", c_int64), ("tiles", c_int64), ("tiles_x", c_int64),
                 ("n_composited_px", c_int64), ("n_composited", c_int64), ("n_evaluated_px", c_int64),
-                ("n_walked_px", c_int64), ("n_sort_fallbacks", c_int64)]
+                ("n_walked_px", c_int64), ("n_sort_fallbacks", c_int64), ("workspace_bytes", c_int64)]
 
 
 class CServerOpts(ctypes.Structure):
@@ -59,13 +59,20 @@ class CServerOpts(ctypes.Structure):
 
 class CTicketInfo(ctypes.Structure):
     _fields_ = [("t_submit", c_double), ("t_start", c_double), ("t_done", c_double),
-                ("batch_queries", c_int32), ("batch_receivers", c_int32)]
+                ("batch_queries", c_int32), ("batch_receivers", c_int32), ("attempts", c_int32),
+                ("reserved", c_int32)]
 
 
 class CServerStats(ctypes.Structure):
     _fields_ = [("submitted", c_int64), ("completed", c_int64), ("cancelled", c_int64), ("rejected", c_int64),
                 ("failed", c_int64), ("batches", c_int64), ("receivers", c_int64), ("queued", c_int64),
-                ("in_flight", c_int64), ("busy_s", c_double)]
+                ("in_flight", c_int64), ("busy_s", c_double), ("failed_batches", c_int64), ("replayed", c_int64),
+                ("peak_slot_bytes", c_int64), ("over_estimate", c_int64)]
+
+
+class CHostExecutor(ctypes.Structure):
+    _fields_ = [("K", c_int64), ("H", c_int32), ("W", c_int32), ("delay_us", c_int32), ("reserved", c_int32),
+                ("fail_launch_mask", ctypes.c_uint64), ("fail_device_mask", ctypes.c_uint64)]
 
 
 class CStageTime(ctypes.Structure):
@@ -126,6 +133,8 @@ def lib():
     L.rxgs_saved_info.argtypes = [vp, POINTER(CSavedInfo)]
     L.rxgs_saved_export.argtypes = [vp, c_int, vp, c_int64, c_int]
     L.rxgs_server_start.argtypes = [vp, POINTER(CServerOpts), POINTER(vp)]
+    L.rxgs_server_start_host.argtypes = [POINTER(CServerOpts), POINTER(CHostExecutor), POINTER(vp)]
+    L.rxgs_server_start_host.restype = c_int
     L.rxgs_server_submit.argtypes = [vp, vp, c_int32, vp, POINTER(ctypes.c_uint64)]
     L.rxgs_server_poll.argtypes = [vp, ctypes.c_uint64, vp, vp, POINTER(CTicketInfo), c_int32]
     L.rxgs_server_cancel.argtypes = [vp, ctypes.c_uint64]
@@ -231,6 +240,8 @@ class TorchAllocator:
 
     def __init__(self):
         self.live = {}          # pointer -> bytes
+        self.fail_next = 0      # test hook: this many coming allocations return NULL
+        self.n_failed = 0
         self.n_alloc = 0
         self.bytes_alloc = 0
         self.n_free = 0
@@ -241,6 +252,10 @@ class TorchAllocator:
         return sum(self.live.values())
 
     def _alloc(self, nbytes, device, user):
+        if self.fail_next > 0:
+            self.fail_next -= 1
+            self.n_failed += 1
+            return None
         try:
             p = _torch().cuda.caching_allocator_alloc(int(nbytes), int(device))
         except Exception:
@@ -490,17 +505,28 @@ class Renderer:
 
 
 class Server:
-    """Continuous-batching server on a Renderer (rxgs_server_*)."""
+    """Continuous-batching server on a Renderer (rxgs_server_*), or, with
+    renderer=None and host_executor given, the same scheduler against the
+    library's host-only executor (rxgs_server_start_host; no GPU)."""
 
-    def __init__(self, renderer: Renderer, mode: str = "tx", max_rx_per_batch: int = 2048,
+    def __init__(self, renderer: Renderer | None, mode: str = "tx", max_rx_per_batch: int = 2048,
                  max_queries_per_batch: int = 64, slots: int = 2, queue_capacity: int = 1 << 20,
-                 want_spectra: bool = False, mem_budget_bytes: int = 0):
+                 want_spectra: bool = False, mem_budget_bytes: int = 0, host_executor: dict | None = None):
         self.renderer = renderer
         self.want_spectra = want_spectra
         o = CServerOpts(mem_budget_bytes, max_rx_per_batch, max_queries_per_batch, slots,
                         MODE_TX if mode == "tx" else MODE_RX, queue_capacity, 1 if want_spectra else 0)
         h = c_void_p()
-        _check(lib().rxgs_server_start(renderer._ctx, byref(o), byref(h)), renderer._ctx)
+        if renderer is None:
+            he = host_executor or {}
+            ex = CHostExecutor(int(he.get("K", 1000)), int(he.get("H", 90)), int(he.get("W", 360)),
+                               int(he.get("delay_us", 200)), 0, int(he.get("fail_launch_mask", 0)),
+                               int(he.get("fail_device_mask", 0)))
+            st = lib().rxgs_server_start_host(byref(o), byref(ex), byref(h))
+            if st != 0:
+                raise RxgsError(st, "host-executor server rejected its options")
+        else:
+            _check(lib().rxgs_server_start(renderer._ctx, byref(o), byref(h)), renderer._ctx)
         self._h = h
         self._n = {}
 
@@ -526,12 +552,15 @@ class Server:
         info = CTicketInfo()
         st = lib().rxgs_server_poll(self._h, ticket, power.ctypes.data_as(c_void_p),
                                     None if C is None else C.ctypes.data_as(c_void_p), byref(info), timeout_ms)
+        d = {f: getattr(info, f) for f, _ in CTicketInfo._fields_}
         if st != 0:
             if st != 6:
                 self._n.pop(ticket, None)
-            raise RxgsError(st, f"ticket {ticket}")
+            err = RxgsError(st, f"ticket {ticket}")
+            err.info = d
+            raise err
         self._n.pop(ticket, None)
-        return power, C, {f: getattr(info, f) for f, _ in CTicketInfo._fields_}
+        return power, C, d
 
     def cancel(self, ticket: int) -> int:
         return lib().rxgs_server_cancel(self._h, ticket)

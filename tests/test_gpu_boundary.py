@@ -17,7 +17,7 @@ import pytest
 from oracle import oracle as O
 from paper_2605_24290_amd import scenes as S
 
-from .parity import compare_spectra, gpu, needs_gpu, oracle_render, renderer_for
+from .parity import FLAG_MARGIN, compare_spectra, gpu, needs_gpu, oracle_render, renderer_for
 
 pytestmark = [gpu, needs_gpu]
 
@@ -47,7 +47,7 @@ def test_amplitude_output_and_gradient(mode):
     ora = oracle_render(wl, mode)
     Co = ora["C"]
     amp_o = np.sqrt(Co[:, 0] ** 2 + Co[:, 1] ** 2 + 1e-8)
-    ok = ora["margin"] >= 1e-4
+    ok = ora["margin"] >= FLAG_MARGIN
     An = A.cpu().numpy()
     for j in range(An.shape[0]):
         err = np.abs(An[j] - amp_o[j]) / amp_o[j].max()

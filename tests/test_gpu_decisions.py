@@ -90,7 +90,12 @@ def test_clamp_stack_forward_and_gradient():
         for f in ("means", "log_scales", "quats", "logits"):
             assert np.abs(gg[f][0]).max() == 0.0, (mode, f, gg[f][0])
         go = O.backward(wl.scene, GRID, centre[None], centre[None], [0], dC.astype(np.float64))
-        _compare(gg, go, FIELDS_DIRECT)
+        # the pixel sits on the stack's axis, where the weight of the second
+        # Gaussian is stationary in its projected position: the exact gradient
+        # of its mean vanishes and both sides hold rounding noise (~1e-9 per
+        # metre against the ~1e-2 a metre of offset would give), so that field
+        # is held to 1e-4 of a 1e-3 floor
+        _compare(gg, go, FIELDS_DIRECT, floor=1e-3)
         saved.close()
         r.close()
 

@@ -34,7 +34,7 @@ pytestmark = [gpu, needs_gpu]
 
 SAMPLE_C1 = [0, 21, 42, 63]
 SAMPLE_C2 = [5, 26]
-MAX_FLAGGED_FULL = 1e-2
+MAX_FLAGGED_FULL = 2e-3
 FIELDS_MLP = ["means", "log_scales", "quats", "logits", "features", "mlp"]
 
 

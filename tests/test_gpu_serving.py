@@ -8,7 +8,9 @@ import pytest
 
 from paper_2605_24290_amd import scenes as S
 
-from .parity import gpu, needs_gpu, renderer_for
+from oracle import oracle as O
+
+from .parity import compare_spectra, gpu, needs_gpu, renderer_for
 
 pytestmark = [gpu, needs_gpu]
 
@@ -42,8 +44,18 @@ def test_alone_equals_mix_and_direct_render(mode):
     C, P, _ = r.render(probe[2], tx=probe[1][None], mode=mode)
     torch.cuda.synchronize()
     assert np.abs(C.cpu().numpy() - C_alone).max() <= 1e-4 * scale
+    # two queries of the mix, rendered alone by the FP64 oracle
+    mixed = [i for i, (_, _, inf) in enumerate(res) if inf["batch_queries"] > 1]
+    picks = sorted(mixed, key=lambda i: qs[i][2].shape[0])[:2]
+    assert len(picks) == 2
+    for i in picks:
+        _, tx_q, rx_q = qs[i]
+        cen, rv = O.views_for(mode, tx_q[None], rx_q)
+        ora = O.render(wl.scene, wl.grid, cen, rx_q, rv, mlp=wl.mlp)
+        compare_spectra(res[i][1], ora)
+        assert np.abs(res[i][0] - ora["power"]).max() <= 1e-4 * np.abs(ora["power"]).max()
     st = srv.stats()
-    assert st["completed"] == 25 and st["failed"] == 0
+    assert st["completed"] == 25 and st["failed"] == 0 and st["over_estimate"] == 0
     srv.stop()
     r.close()
 
@@ -62,6 +74,8 @@ def test_memory_budget_caps_batches_and_cancel():
         assert rxgs.workspace_estimate("tx", info["batch_queries"], info["batch_receivers"], K, H, W) <= budget
     with pytest.raises(rxgs.RxgsError):
         srv.poll(tickets[-1], 1000)
+    st = srv.stats()
+    assert st["over_estimate"] == 0 and 0 < st["peak_slot_bytes"] <= budget
     big = np.zeros((41, 3), np.float32) + 1.0
     with pytest.raises(rxgs.RxgsError):
         srv.submit(qs[0][1], np.concatenate([big] * 100))
@@ -80,5 +94,48 @@ def test_open_loop_reports_percentiles():
         assert math.isfinite(res[k]) and res[k] > 0
     assert res["p99_ms"] >= res["p50_ms"]
     print("[serving]", sat, res)
+    srv.stop()
+    r.close()
+
+
+def test_allocator_failure_fails_one_batch_only():
+    """The caller's allocator returns NULL for the first batch's first device
+    buffer (both the request with slack and the exact one): that batch fails (E_OOM), its slot is made again and its tickets
+    ride the next batch; every result still equals a direct render.  With the
+    allocator failing for good, a query that needs new buffers fails with
+    E_OOM after its replay, and the server serves again once it recovers."""
+    import torch
+    from paper_2605_24290_amd import rxgs
+    wl = S.make_workload("c3", K=20_000, N=1)
+    alloc = rxgs.TorchAllocator()
+    r = rxgs.Renderer(wl.grid, allocator=alloc)
+    sc = wl.scene
+    r.upload_scene(sc.means, sc.log_scales, sc.quats, sc.logits, features=sc.features)
+    r.upload_mlp(S.flat_mlp(wl.mlp))
+    qs = S.serving_queries(31, 12, wl.scene.means.max(axis=0), max_rx=16)
+    srv = rxgs.Server(r, mode="tx", slots=1, max_queries_per_batch=4, want_spectra=True)
+    alloc.fail_next = 2   # a buffer is asked for with 25 % slack, then at its exact size
+    tickets = [srv.submit(q[1], q[2]) for q in qs]
+    res = [srv.poll(t, 60_000) for t in tickets]
+    assert alloc.n_failed == 2
+    assert any(i["attempts"] == 2 for _, _, i in res)
+    for q, (p, C, _) in zip(qs[:3], res[:3]):
+        Cd, Pd, _ = r.render(q[2], tx=q[1][None], mode="tx")
+        torch.cuda.synchronize()
+        assert np.array_equal(Cd.cpu().numpy(), C)
+    st = srv.stats()
+    assert st["failed_batches"] == 1 and st["failed"] == 0 and st["completed"] == 12 and st["replayed"] >= 1
+    # failing for good: a query bigger than any before needs new buffers
+    big = np.concatenate([q[2] for q in qs])[:200]
+    alloc.fail_next = 1 << 30
+    t = srv.submit(qs[0][1], big)
+    with pytest.raises(rxgs.RxgsError) as e:
+        srv.poll(t, 60_000)
+    assert e.value.status == 2 and e.value.info["attempts"] == 2
+    alloc.fail_next = 0
+    p, C, info = srv.poll(srv.submit(qs[0][1], big), 60_000)
+    assert info["attempts"] == 1 and np.isfinite(p).all()
+    st = srv.stats()
+    assert st["failed"] == 1 and st["over_estimate"] == 0
     srv.stop()
     r.close()
