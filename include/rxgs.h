@@ -176,6 +176,26 @@ rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *tx, const i
                         rxgs_saved *saved, void *stream);
 
 /*
+ * rxgs_render for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * arguments without a saved state, the same kernels and results, and no
+ * device or host allocation in the call.  Its workspace is carved, in order,
+ * from a static device array of RXGS_NOALLOC_SCRATCH_BYTES that each GPU the
+ * library runs on holds until the process ends (resolved per device by
+ * rxgs_create, which also makes the call's pinned staging); the region is
+ * rewound at every call.  Every context on a GPU shares that GPU's array, so
+ * calls that overlap on one GPU (other streams, other threads, other
+ * contexts) race; calls on one stream are ordered.  A render whose buffers
+ * exceed the array fails with E_OOM ("scratch region exhausted") before any
+ * output is written (work it had enqueued touched only the array).  The call
+ * synchronises the stream once, like rxgs_render.  Errors: those of
+ * rxgs_render; E_STATE if the context has no such workspace.
+ */
+#define RXGS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+rxgs_status rxgs_render_noalloc(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off, int N,
+                                const float *rx, float *C, float *power, float *csum, float *amp, void *stream);
+
+/*
  * Coverage-map render: the receivers of rxgs_render (same arguments, no saved
  * state) streamed through consecutive chunks, each one rxgs_render call, the
  * largest whose workspace estimate (rxgs_workspace_estimate) fits

@@ -118,6 +118,7 @@ int bits_for(uint64_t n)
 bool ensure_pinned(Workspace &ws, size_t bytes)
 {
     if (ws.h_pinned_cap >= bytes) return true;
+    if (ws.fixed_host) return false;   // made at set-up, never regrown
     if (ws.h_pinned) (void)hipHostFree(ws.h_pinned);
     ws.h_pinned = nullptr;
     ws.h_pinned_cap = 0;
@@ -131,7 +132,8 @@ bool ensure_pinned(Workspace &ws, size_t bytes)
     return true;
 }
 
-void free_workspace(Workspace &ws)
+// every device buffer of a workspace released (carved ones only forgotten)
+void release_buffers(Workspace &ws)
 {
     DevBuf *bufs[] = {&ws.centres, &ws.rxpos,   &ws.desc,   &ws.ext,     &ws.rawkey, &ws.opac,
                       &ws.skey[0], &ws.skey[1], &ws.sval[0], &ws.sval[1], &ws.srec,    &ws.ggeo,
@@ -143,6 +145,11 @@ void free_workspace(Workspace &ws)
                       &ws.items_far, &ws.frec, &ws.fcnt,  &ws.ftile,  &ws.hist_b, &ws.gfeat_tmp, &ws.gmlp_tmp,
                       &ws.rgam,    &ws.rab,     &ws.rloc};
     for (DevBuf *b : bufs) release(*b);
+}
+
+void free_workspace(Workspace &ws)
+{
+    release_buffers(ws);
     if (ws.staged) (void)hipEventDestroy(ws.staged);
     if (ws.counted) (void)hipEventDestroy(ws.counted);
     if (ws.done) (void)hipEventDestroy(ws.done);
@@ -335,6 +342,66 @@ extern "C" const char *rxgs_last_error(const rxgs_ctx *ctx)
     return ctx->err.c_str();
 }
 
+// ============================================================================
+// Scratch of the allocation-free entry point (rxgs_render_noalloc): one
+// static array that every GPU the library runs on holds for the life of the
+// process.  Host code never uses its name as an address: each device's copy
+// is resolved once, with that device current, by hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[RXGS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+constexpr size_t NOALLOC_PINNED = (size_t)1 << 20;   // host staging of the counts and descriptors
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// this device's copy of the scratch array (the device must be current)
+hipError_t scratch_address(int device, void **out)
+{
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+// the allocation-free workspace of a context: carved from the device's
+// scratch array, with its pinned staging and events made here, at set-up
+rxgs_status setup_noalloc(rxgs_ctx *ctx)
+{
+    void *sp = nullptr;
+    hipError_t e = scratch_address(ctx->device, &sp);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipGetSymbolAddress(scratch)");
+    ctx->fixed.base = static_cast<char *>(sp);
+    ctx->fixed.cap = RXGS_NOALLOC_SCRATCH_BYTES;
+    ctx->fixed.used = 0;
+    ctx->fixed.device = ctx->device;
+    rxgs_saved *s = new (std::nothrow) rxgs_saved();
+    if (!s) return fail(ctx, RXGS_E_OOM, "out of host memory");
+    s->ctx = ctx;
+    s->keep = false;
+    s->ws.al = &ctx->fixed;
+    ctx->noalloc = s;
+    Workspace &ws = s->ws;
+    e = hipHostMalloc(&ws.h_pinned, NOALLOC_PINNED, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        ws.h_pinned = nullptr;
+        return hip_fail(ctx, e, "pinned staging of the allocation-free workspace");
+    }
+    ws.h_pinned_cap = NOALLOC_PINNED;
+    ws.fixed_host = true;
+    HIPCHK(ctx, hipEventCreateWithFlags(&ws.staged, hipEventDisableTiming));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ws.counted, hipEventDisableTiming));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ws.done, hipEventDisableTiming));
+    return RXGS_OK;
+}
+}  // namespace
+
 extern "C" rxgs_status rxgs_create(int device, const rxgs_grid *grid, rxgs_ctx **out)
 {
     if (!out) {
@@ -373,6 +440,15 @@ extern "C" rxgs_status rxgs_create(int device, const rxgs_grid *grid, rxgs_ctx *
     g.daz = 2.0 * M_PI / (double)grid->W;
     g.idaz = (double)grid->W / (2.0 * M_PI);
     g.idel = 1.0 / grid->del_el;
+    {
+        DeviceScope ds(device);
+        const rxgs_status rs = setup_noalloc(ctx);
+        if (rs != RXGS_OK) {
+            g_create_err = ctx->err;
+            rxgs_destroy(ctx);
+            return rs;
+        }
+    }
     *out = ctx;
     return RXGS_OK;
 }
@@ -414,6 +490,12 @@ extern "C" void rxgs_destroy(rxgs_ctx *ctx)
     release(ctx->mlp.b1tab);
     release_rxcond(ctx->rxc);
     release(ctx->stage);
+    if (ctx->noalloc) {
+        (void)wait_workspace(ctx->noalloc->ws);
+        free_workspace(ctx->noalloc->ws);
+        delete ctx->noalloc;
+        ctx->noalloc = nullptr;
+    }
     if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
     delete ctx;
 }
@@ -1109,6 +1191,25 @@ extern "C" rxgs_status rxgs_render(rxgs_ctx *ctx, int mode, int Q, const float *
         if (rs != RXGS_OK) return rs;
     }
     return RXGS_OK;
+}
+
+// ============================================================================
+// rxgs_render without allocations: the workspace is carved, in order, from
+// this device's scratch array, rewound at every call; its pinned staging and
+// events were made by rxgs_create.  A render that needs more than the array
+// holds fails with E_OOM ("scratch region exhausted") before writing any output.
+extern "C" rxgs_status rxgs_render_noalloc(rxgs_ctx *ctx, int mode, int Q, const float *tx, const int32_t *rx_off,
+                                           int N, const float *rx, float *C, float *power, float *csum, float *amp,
+                                           void *stream)
+{
+    if (!ctx) return RXGS_E_INVALID;
+    if (!ctx->noalloc || !ctx->fixed.base) return fail(ctx, RXGS_E_STATE, "no allocation-free workspace");
+    Workspace &ws = ctx->noalloc->ws;
+    // the last call's carve is forgotten and the region rewound (its work is
+    // ordered before this call's on one stream; calls that overlap race)
+    release_buffers(ws);
+    ctx->fixed.used = 0;
+    return render_pass(ctx, mode, Q, tx, rx_off, N, rx, C, power, csum, amp, ctx->noalloc, stream, 0xFFFFFFFFu);
 }
 
 // ============================================================================

@@ -292,6 +292,8 @@ struct rxgs_ctx {
     int64_t views_redone = 0;  // views redone over all their entries
     hipStream_t aux = nullptr; // private non-blocking stream of the saved-state queries and exports
     rxgs::Allocator alloc;     // the context's device allocations
+    rxgs::Allocator fixed;     // this device's copy of the static scratch array (rxgs_render_noalloc)
+    rxgs_saved *noalloc = nullptr;   // the allocation-free entry point's workspace, carved from `fixed`
 };
 
 struct rxgs_saved {

@@ -100,7 +100,7 @@ EXPORTED = ("rxgs_create", "rxgs_create_with_allocator", "rxgs_destroy", "rxgs_l
             "rxgs_server_cancel", "rxgs_server_stats", "rxgs_server_stop", "rxgs_plan_batch",
             "rxgs_workspace_estimate", "rxgs_set_near_cut", "rxgs_views_redone", "rxgs_render_chunked",
             "rxgs_view_flags", "rxgs_rxcond_param_count", "rxgs_rxcond_upload", "rxgs_render_rxcond",
-            "rxgs_rxcond_export")
+            "rxgs_rxcond_export", "rxgs_render_noalloc", "rxgs_server_start_host")
 
 _lib = None
 
@@ -157,6 +157,8 @@ def lib():
     L.rxgs_set_near_cut.restype = c_int
     L.rxgs_views_redone.argtypes = [vp]
     L.rxgs_views_redone.restype = c_int64
+    L.rxgs_render_noalloc.argtypes = [vp, c_int, c_int, vp, POINTER(c_int32), c_int, vp, vp, vp, vp, vp, vp]
+    L.rxgs_render_noalloc.restype = c_int
     L.rxgs_rxcond_param_count.argtypes = [POINTER(CRxCondDesc)]
     L.rxgs_rxcond_param_count.restype = c_int64
     L.rxgs_rxcond_upload.argtypes = [vp, POINTER(CRxCondDesc), vp, vp, c_int, vp]
