@@ -433,6 +433,24 @@ rxgs_status rxgs_profile_read(rxgs_ctx *ctx, rxgs_stage_time *out, int max_entri
  */
 rxgs_status rxgs_set_near_cut(rxgs_ctx *ctx, int on);
 
+/*
+ * Deterministic backward (off by default; on at rxgs_create when the
+ * environment variable RXGS_DETERMINISTIC=1).  While on, renders into a saved
+ * state evaluate every visible position's radiance (no radiance prefix) and
+ * keep the pairs' emission order, and rxgs_render_backward on such a state
+ * sums every gradient in a fixed order instead of with float atomics (App. D
+ * accumulates with atomicAdd): the blend backward stores one partial per
+ * (tile-list entry, block of up to 4 receivers), summing its waves in order,
+ * and gathers add them per (view, position) in emission order; the MLP
+ * backward stores its per-Gaussian and per-receiver terms per marked position
+ * block and gathers add them in view and block order; the projection
+ * gradients of each Gaussian are summed over the views in order (FP64).  Two
+ * backwards of the same inputs then give the same bits.  It needs about
+ * (6 + 2 R_max) x 4 B per pair slot and 4 B per (view, Gaussian) more device
+ * memory and one host wait.  Errors: E_INVALID (NULL ctx).
+ */
+rxgs_status rxgs_set_deterministic(rxgs_ctx *ctx, int on);
+
 /* Views redone over all their entries since the context was created, or -1
  * for a NULL ctx. */
 int64_t rxgs_views_redone(const rxgs_ctx *ctx);

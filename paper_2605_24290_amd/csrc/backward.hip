@@ -35,18 +35,32 @@ constexpr float LN2F = 0.69314718055994531f;
 // waves and flushed to global memory once per batch, one entry per thread:
 // global atomics inside the walk stall it (they count against the wave's
 // outstanding-memory budget) and contend across the waves of a tile.
-template <int R>
+// Deterministic variant (DET): each wave adds its entry sums over its 64
+// lanes in a fixed order into its own LDS slots, the four waves' slots are
+// added in order at the flush, and every (tile list entry, receiver block) gets
+// its own partial in global memory (no atomics); a later gather adds the
+// partials of each (view, position) in a fixed order.
+struct DetPartials {
+    float *gP;          // [block of the view][Dpad][8]: (u, v, a, b, c, o) partials per pair slot
+    float *dSP;         // [row of the view][Dpad][2]: dL/ds partials per pair slot
+    int64_t Dpad;
+    const int4 *vinfo;  // per view (first row, rows, visible, -)
+};
+
+template <int R, bool DET>
 __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
     const float4 *__restrict__ srec, const uint32_t *__restrict__ pval, const uint2 *__restrict__ ranges,
     const float2 *__restrict__ rad, const int4 *__restrict__ chunks, int split, int64_t Kp, DevGrid g,
     int tx_mode, const float *__restrict__ C, const float *__restrict__ dC, const float *__restrict__ dP,
     const float *__restrict__ dA, const float *__restrict__ Tfin, const int *__restrict__ nlast, float *__restrict__ dS,
-    float *__restrict__ g2d, uint8_t *__restrict__ live)
+    float *__restrict__ g2d, uint8_t *__restrict__ live, DetPartials det)
 {
+    constexpr int NV = 6 + 2 * R;   // values per entry: six record gradients, then (Re, Im) per receiver
     __shared__ BlendStage st;
     __shared__ float2 s_rad[R][BLOCK];
-    __shared__ float s_acc[6][BLOCK];
-    __shared__ float2 s_dacc[R][BLOCK];
+    __shared__ float s_acc[DET ? 1 : 6][BLOCK];
+    __shared__ float2 s_dacc[DET ? 1 : R][BLOCK];
+    __shared__ float s_accw[DET ? 4 : 1][DET ? NV : 1][BLOCK];
     __shared__ int s_max[4];
 
     const int tile = blockIdx.x;
@@ -103,10 +117,17 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
         const int cnt = end - start;
         __syncthreads();
         uint32_t p = 0;
+        if constexpr (DET) {
 #pragma unroll
-        for (int c = 0; c < 6; c++) s_acc[c][t] = 0.f;
+            for (int w = 0; w < 4; w++)
 #pragma unroll
-        for (int r = 0; r < R; r++) s_dacc[r][t] = make_float2(0.f, 0.f);
+                for (int c = 0; c < NV; c++) s_accw[w][c][t] = 0.f;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 6; c++) s_acc[c][t] = 0.f;
+#pragma unroll
+            for (int r = 0; r < R; r++) s_dacc[r][t] = make_float2(0.f, 0.f);
+        }
         if (t < cnt) {
             p = (uint32_t)min((int64_t)pval[rg.x + start + t], view_end - 1);
             const int64_t s = max((int64_t)p - (int64_t)view * Kp, (int64_t)0);
@@ -167,9 +188,37 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
                 }
             }
             if (__ballot(act) == 0) continue;   // uniform across the wave
+            float vals[6] = {gu, gv, gca, gcb, gcc, glo};
+            if constexpr (DET) {
+                // the wave's sum: its four 16-lane row sums added in order
+                auto wave_total = [&](float x) {
+                    const float v = row_sum(x);
+                    const int b = __float_as_int(v);
+                    return ((__int_as_float(__builtin_amdgcn_readlane(b, 15)) +
+                             __int_as_float(__builtin_amdgcn_readlane(b, 31))) +
+                            __int_as_float(__builtin_amdgcn_readlane(b, 47))) +
+                           __int_as_float(__builtin_amdgcn_readlane(b, 63));
+                };
+#pragma unroll
+                for (int c = 0; c < 6; c++) {
+                    const float v = wave_total(vals[c]);
+                    if (lane == 0) s_accw[wv][c][e] = v;
+                }
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    if (r < nrx) {
+                        const float vx = wave_total(dsr[r].x);
+                        const float vy = wave_total(dsr[r].y);
+                        if (lane == 0) {
+                            s_accw[wv][6 + 2 * r][e] = vx;
+                            s_accw[wv][7 + 2 * r][e] = vy;
+                        }
+                    }
+                }
+                continue;
+            }
             // sums over each 16-lane row, added into the batch's LDS
             // accumulators by the rows' last lanes
-            float vals[6] = {gu, gv, gca, gcb, gcc, glo};
             const bool row_last = (lane & 15) == 15;
 #pragma unroll
             for (int c = 0; c < 6; c++) {
@@ -189,6 +238,36 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
             }
         }
         __syncthreads();
+        if constexpr (DET) {
+            // thread t owns entry t: the four waves' sums in order, stored at
+            // the entry's pair slot for this block of receivers
+            if (t < cnt) {
+                const uint32_t pe = st.p[t];
+                const int64_t d = (int64_t)rg.x + start + t;
+                const int4 vi = det.vinfo[view];
+                const int64_t blk = (j0 - vi.x) / R;
+                float *gp = det.gP + ((size_t)blk * det.Dpad + d) * 8;
+#pragma unroll
+                for (int c = 0; c < 6; c++)
+                    gp[c] = ((s_accw[0][c][t] + s_accw[1][c][t]) + s_accw[2][c][t]) + s_accw[3][c][t];
+                bool any = false;
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    if (r < nrx) {
+                        const float vx = ((s_accw[0][6 + 2 * r][t] + s_accw[1][6 + 2 * r][t]) +
+                                          s_accw[2][6 + 2 * r][t]) + s_accw[3][6 + 2 * r][t];
+                        const float vy = ((s_accw[0][7 + 2 * r][t] + s_accw[1][7 + 2 * r][t]) +
+                                          s_accw[2][7 + 2 * r][t]) + s_accw[3][7 + 2 * r][t];
+                        float *dd = det.dSP + ((size_t)(j0 + r - vi.x) * det.Dpad + d) * 2;
+                        dd[0] = vx;
+                        dd[1] = vy;
+                        any = any || vx != 0.f || vy != 0.f;
+                    }
+                }
+                if (any) live[pe / MLP_PAIRS] = 1;
+            }
+            continue;
+        }
         // flush the batch: thread t owns entry t
         if (t < cnt) {
             const uint32_t pe = st.p[t];
@@ -293,13 +372,26 @@ __global__ __launch_bounds__(BLOCK) void k_live_list(const int4 *__restrict__ it
 //   dL_k += dx1 (registers), dG_j += sum over pairs of dx1 (DPP, atomics)
 //   z2 transposed through LDS to lane = hidden unit, then
 //   dW2 += dz2^T x1 over the 32 pairs (MFMA), db2, dW3, db3 (VALU)
+// Deterministic variant: each live position block has a slot (its rank);
+// the Gaussian term of an item is stored per (slot, receiver group, pair),
+// the receiver term per (slot, row of the view), for fixed-order gathers.
+struct DetMlp {
+    float *dLv;          // [slot][receiver group][32][64]
+    float *dGp;          // [slot][row of the view][64]
+    const int *rank;     // per position block: slot or -1
+    const int4 *vinfo;   // per view (first row, rows, visible, -)
+    int nrg_max, rows_max;
+};
+
+template <bool DET>
 __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
     const float *__restrict__ Lp, const float *__restrict__ Gp, const float *__restrict__ w2a,
     const float *__restrict__ w2b, const float4 *__restrict__ tab, const float *__restrict__ W3,
     const uint32_t *__restrict__ order, const int4 *__restrict__ items, int nitems,
     const int4 *__restrict__ items2, const int *__restrict__ count2, int nsub, int64_t Kp,
     int64_t K, const uint8_t *__restrict__ live, const uint32_t *__restrict__ list, const uint32_t *__restrict__ nlist,
-    const float2 *__restrict__ dS, float *__restrict__ dL, float *__restrict__ dG, float *__restrict__ part)
+    const float2 *__restrict__ dS, float *__restrict__ dL, float *__restrict__ dG, float *__restrict__ part,
+    DetMlp det)
 {
     __shared__ float s_w2a[2 * 32 * 64];
     __shared__ float s_w2b[2 * 32 * 64];
@@ -463,8 +555,15 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
                 const float s0v = half_wave_sum(d0);
                 const float s1v = half_wave_sum(d1);
                 if (pl == 31) {
-                    if (s0v != 0.f) atomicAdd(&dG[(size_t)j * HID + h * 32 + r], s0v);
-                    if (s1v != 0.f) atomicAdd(&dG[(size_t)j * HID + h * 32 + 16 + r], s1v);
+                    if constexpr (DET) {
+                        const int rk = det.rank[((size_t)view * Kp + s0) / MLP_PAIRS];
+                        float *dg = det.dGp + ((size_t)rk * det.rows_max + (j - det.vinfo[view].x)) * HID + h * 32;
+                        dg[r] = s0v;
+                        dg[16 + r] = s1v;
+                    } else {
+                        if (s0v != 0.f) atomicAdd(&dG[(size_t)j * HID + h * 32 + r], s0v);
+                        if (s1v != 0.f) atomicAdd(&dG[(size_t)j * HID + h * 32 + 16 + r], s1v);
+                    }
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -498,10 +597,17 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_bwd(
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
         }
-        if (valid)
+        if constexpr (DET) {
+            const int rk = det.rank[((size_t)view * Kp + s0) / MLP_PAIRS];
+            const int a = (j0 - det.vinfo[view].x) / MLP_RG;
+            float *dl_out = det.dLv + (((size_t)rk * det.nrg_max + a) * MLP_PAIRS + pl) * HID + h * 32;
+#pragma unroll
+            for (int q = 0; q < 32; q++) dl_out[q] = dl[q];
+        } else if (valid) {
 #pragma unroll
             for (int q = 0; q < 32; q++)
                 if (dl[q] != 0.f) atomicAdd(&dL[(size_t)k * HID + h * 32 + q], dl[q]);
+        }
     }
     }
     // per-wave partial sums (natural layouts), reduced in a fixed order later
@@ -700,20 +806,17 @@ __device__ __forceinline__ d3 dsqrt3(d3 a)
     return {s, a.x * k, a.y * k, a.z * k};
 }
 
-__global__ __launch_bounds__(BLOCK) void k_project_bwd(
-    const float *__restrict__ soa, int64_t K, int64_t Kp, const float *__restrict__ centres, int V, DevGrid g,
-    const uint32_t *__restrict__ order, const unsigned long long *__restrict__ counters,
-    const float *__restrict__ g2d, float *__restrict__ gmeans, float *__restrict__ gls, float *__restrict__ gq,
-    float *__restrict__ glogit)
+// Gradients of one (view, Gaussian) record: mean (3), log-scales (3), raw
+// quaternion (4) and opacity logit (1), from the record's 2-D gradients gg
+// (u, v, and the parameters of the blend exponent), in FP64.
+struct ProjGrad {
+    double gp[3], gls[3], gq[4], glogit;
+};
+
+__device__ ProjGrad project_grad(const float *__restrict__ soa, int64_t K, int64_t k, const float *__restrict__ centres,
+                                 int64_t v, const DevGrid &g, const float *__restrict__ gg)
 {
-    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (p >= (int64_t)V * Kp) return;
-    const int64_t v = p / Kp, s = p - v * Kp;
-    if (s >= (int64_t)counters[2 * (size_t)v]) return;
-    const float *gg = g2d + (size_t)p * 8;
     const double g_u = gg[0], g_v = gg[1], g_ca = gg[2], g_cb = gg[3], g_cc = gg[4], g_lo = gg[5];
-    if (g_u == 0 && g_v == 0 && g_ca == 0 && g_cb == 0 && g_cc == 0 && g_lo == 0) return;
-    const int64_t k = min((int64_t)order[p], K - 1);
 
     const double px = soa[k], py = soa[K + k], pz = soa[2 * K + k];
     double s2[3];
@@ -809,15 +912,295 @@ __global__ __launch_bounds__(BLOCK) void k_project_bwd(
     const double gz = 2.0 * (-2.0 * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.0 * z * gR[1][1] +
                              y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
     const double dotq = w * gw + x * gx + y * gy + z * gz;
-    const double gq4[4] = {(gw - w * dotq) / qn, (gx - x * dotq) / qn, (gy - y * dotq) / qn, (gz - z * dotq) / qn};
+    ProjGrad out;
+    for (int a = 0; a < 3; a++) {
+        out.gp[a] = gp[a];
+        out.gls[a] = gls_[a];
+    }
+    out.gq[0] = (gw - w * dotq) / qn;
+    out.gq[1] = (gx - x * dotq) / qn;
+    out.gq[2] = (gy - y * dotq) / qn;
+    out.gq[3] = (gz - z * dotq) / qn;
+    out.glogit = g_o * o * (1.0 - o);
+    return out;
+}
 
+__device__ __forceinline__ bool g2d_zero(const float *gg)
+{
+    return gg[0] == 0.f && gg[1] == 0.f && gg[2] == 0.f && gg[3] == 0.f && gg[4] == 0.f && gg[5] == 0.f;
+}
+
+// per (view, visible Gaussian); float atomics add the views' terms
+__global__ __launch_bounds__(BLOCK) void k_project_bwd(
+    const float *__restrict__ soa, int64_t K, int64_t Kp, const float *__restrict__ centres, int V, DevGrid g,
+    const uint32_t *__restrict__ order, const unsigned long long *__restrict__ counters,
+    const float *__restrict__ g2d, float *__restrict__ gmeans, float *__restrict__ gls, float *__restrict__ gq,
+    float *__restrict__ glogit)
+{
+    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (p >= (int64_t)V * Kp) return;
+    const int64_t v = p / Kp, s = p - v * Kp;
+    if (s >= (int64_t)counters[2 * (size_t)v]) return;
+    const float *gg = g2d + (size_t)p * 8;
+    if (g2d_zero(gg)) return;
+    const int64_t k = min((int64_t)order[p], K - 1);
+    const ProjGrad r = project_grad(soa, K, k, centres, v, g, gg);
     if (gmeans)
-        for (int a = 0; a < 3; a++) atomicAdd(&gmeans[3 * k + a], (float)gp[a]);
+        for (int a = 0; a < 3; a++) atomicAdd(&gmeans[3 * k + a], (float)r.gp[a]);
     if (gls)
-        for (int a = 0; a < 3; a++) atomicAdd(&gls[3 * k + a], (float)gls_[a]);
+        for (int a = 0; a < 3; a++) atomicAdd(&gls[3 * k + a], (float)r.gls[a]);
     if (gq)
-        for (int a = 0; a < 4; a++) atomicAdd(&gq[4 * k + a], (float)gq4[a]);
-    if (glogit) atomicAdd(&glogit[k], (float)(g_o * o * (1.0 - o)));
+        for (int a = 0; a < 4; a++) atomicAdd(&gq[4 * k + a], (float)r.gq[a]);
+    if (glogit) atomicAdd(&glogit[k], (float)r.glogit);
+}
+
+// ============================================================================
+// Deterministic backward (rxgs_set_deterministic): every sum below runs in a
+// fixed order, so two runs give the same bits.
+
+// out = value (overwrite) or out + value (accumulate)
+__device__ __forceinline__ void det_store(float *out, double value, int accum)
+{
+    *out = accum ? (float)((double)*out + value) : (float)value;
+}
+
+// per Gaussian, the views in order (FP64 sums)
+__global__ __launch_bounds__(BLOCK) void k_det_project(
+    const float *__restrict__ soa, int64_t K, int64_t Kp, const float *__restrict__ centres, int V, DevGrid g,
+    const int *__restrict__ oinv, const float *__restrict__ g2d, float *__restrict__ gmeans,
+    float *__restrict__ gls, float *__restrict__ gq, float *__restrict__ glogit, int accum)
+{
+    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= K) return;
+    ProjGrad acc{};
+    for (int v = 0; v < V; v++) {
+        const int s = oinv[(size_t)v * K + k];
+        if (s < 0) continue;
+        const float *gg = g2d + ((size_t)v * Kp + s) * 8;
+        if (g2d_zero(gg)) continue;
+        const ProjGrad r = project_grad(soa, K, k, centres, v, g, gg);
+        for (int a = 0; a < 3; a++) {
+            acc.gp[a] += r.gp[a];
+            acc.gls[a] += r.gls[a];
+        }
+        for (int a = 0; a < 4; a++) acc.gq[a] += r.gq[a];
+        acc.glogit += r.glogit;
+    }
+    if (gmeans)
+        for (int a = 0; a < 3; a++) det_store(&gmeans[3 * k + a], acc.gp[a], accum);
+    if (gls)
+        for (int a = 0; a < 3; a++) det_store(&gls[3 * k + a], acc.gls[a], accum);
+    if (gq)
+        for (int a = 0; a < 4; a++) det_store(&gq[4 * k + a], acc.gq[a], accum);
+    if (glogit) det_store(&glogit[k], acc.glogit, accum);
+}
+
+// sorted position of every (view, Gaussian), -1 where not visible
+__global__ __launch_bounds__(BLOCK) void k_order_inv(const uint32_t *__restrict__ order,
+                                                     const unsigned long long *__restrict__ counters, int V,
+                                                     int64_t K, int64_t Kp, int *__restrict__ oinv)
+{
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= (int64_t)V * Kp) return;
+    const int64_t v = i / Kp, s = i - v * Kp;
+    if (s >= (int64_t)counters[2 * (size_t)v]) return;
+    const int64_t k = order[i];
+    if (k < K) oinv[(size_t)v * K + k] = (int)s;
+}
+
+// emission slot -> sorted slot of every pair: a pair (tile t, position p)
+// was emitted among p's pairs, in tile order, from slot poff[p] of its view
+__global__ __launch_bounds__(BLOCK) void k_pair_inv(const uint32_t *__restrict__ skey, const uint32_t *__restrict__ sval,
+                                                    const uint32_t *__restrict__ ekey, const uint32_t *__restrict__ poff,
+                                                    const int4 *__restrict__ segtab,
+                                                    const uint32_t *__restrict__ pbase,
+                                                    const uint32_t *__restrict__ pcount,
+                                                    const unsigned long long *__restrict__ counters, int64_t Kp,
+                                                    int64_t Dpad, uint32_t *__restrict__ pinv)
+{
+    const int64_t d = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (d >= Dpad) return;
+    const int v = segtab[d / SORT_TILE].z;
+    const int64_t local = d - (int64_t)pbase[v];
+    if (local < 0 || local >= (int64_t)pcount[v]) return;   // padding
+    const uint32_t t = skey[d];
+    const int64_t pg = sval[d];
+    const int64_t s = pg - (int64_t)v * Kp;
+    const uint32_t e0 = poff[pg];
+    const uint32_t e1 = s + 1 < (int64_t)counters[2 * (size_t)v] ? poff[pg + 1] : pcount[v];
+    for (uint32_t e = e0; e < e1; e++)
+        if (ekey[pbase[v] + e] == t) {
+            pinv[pbase[v] + e] = (uint32_t)d;
+            break;
+        }
+}
+
+// per (view, visible position): the record gradients and each row's dL/ds
+// summed over the position's pairs in emission order (and, within a pair, the
+// receiver blocks in order), then the block marks of the MLP backward
+__global__ __launch_bounds__(BLOCK) void k_det_gather(const float *__restrict__ gP, const float *__restrict__ dSP,
+                                                      int64_t Dpad, int Rdet, const uint32_t *__restrict__ pinv,
+                                                      const uint32_t *__restrict__ poff,
+                                                      const uint32_t *__restrict__ pbase,
+                                                      const uint32_t *__restrict__ pcount,
+                                                      const unsigned long long *__restrict__ counters,
+                                                      const int4 *__restrict__ vinfo, int V, int64_t Kp,
+                                                      float *__restrict__ g2d, float *__restrict__ dS,
+                                                      uint8_t *__restrict__ live)
+{
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= (int64_t)V * Kp) return;
+    const int v = (int)(i / Kp);
+    const int64_t s = i - (int64_t)v * Kp;
+    const int64_t nvis = (int64_t)counters[2 * (size_t)v];
+    if (s >= nvis) return;
+    const uint32_t e0 = poff[i], e1 = s + 1 < nvis ? poff[i + 1] : pcount[v];
+    const uint32_t b0 = pbase[v];
+    const int4 vi = vinfo[v];   // (first row, rows, visible, -)
+    const int nblk = (vi.y + Rdet - 1) / Rdet;
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (uint32_t e = e0; e < e1; e++) {
+        const int64_t d = pinv[b0 + e];
+        for (int b = 0; b < nblk; b++) {
+            const float *src = gP + ((size_t)b * Dpad + d) * 8;
+#pragma unroll
+            for (int c = 0; c < 6; c++) acc[c] += src[c];
+        }
+    }
+    float *dst = g2d + (size_t)i * 8;
+#pragma unroll
+    for (int c = 0; c < 6; c++) dst[c] = acc[c];
+    dst[6] = dst[7] = 0.f;
+    bool any = false;
+    for (int r = 0; r < vi.y; r++) {
+        float sx = 0.f, sy = 0.f;
+        for (uint32_t e = e0; e < e1; e++) {
+            const float *src = dSP + ((size_t)r * Dpad + pinv[b0 + e]) * 2;
+            sx += src[0];
+            sy += src[1];
+        }
+        float *out = dS + ((size_t)(vi.x + r) * Kp + s) * 2;
+        out[0] = sx;
+        out[1] = sy;
+        any = any || sx != 0.f || sy != 0.f;
+    }
+    if (any) live[i / MLP_PAIRS] = 1;
+}
+
+// direct radiance: dL/d radiance_k over the rows in order
+__global__ __launch_bounds__(BLOCK) void k_det_rad(const float2 *__restrict__ dS, const int *__restrict__ oinv,
+                                                   const int *__restrict__ rxview, int N, int64_t K, int64_t Kp,
+                                                   float *__restrict__ grad, int accum)
+{
+    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= K) return;
+    double ax = 0.0, ay = 0.0;
+    for (int j = 0; j < N; j++) {
+        const int s = oinv[(size_t)rxview[j] * K + k];
+        if (s < 0) continue;
+        const float2 d = dS[(size_t)j * Kp + s];
+        ax += d.x;
+        ay += d.y;
+    }
+    det_store(&grad[2 * k], ax, accum);
+    det_store(&grad[2 * k + 1], ay, accum);
+}
+
+// ranks of the marked position blocks in index order (-1 unmarked): counts
+// per chunk of 1024 blocks, their exclusive scan (one workgroup), the ranks
+__global__ __launch_bounds__(BLOCK) void k_live_count(const uint8_t *__restrict__ live, int64_t nb,
+                                                      uint32_t *__restrict__ cnt)
+{
+    __shared__ uint32_t s_c[BLOCK / 64];
+    uint32_t c = 0;
+    for (int q = 0; q < 4; q++) {
+        const int64_t b = (int64_t)blockIdx.x * 1024 + q * BLOCK + threadIdx.x;
+        c += (b < nb && live[b]) ? 1u : 0u;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o);
+    if ((threadIdx.x & 63) == 0) s_c[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) cnt[blockIdx.x] = s_c[0] + s_c[1] + s_c[2] + s_c[3];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_counts(uint32_t *__restrict__ cnt, int64_t n,
+                                                       uint32_t *__restrict__ total)
+{
+    if (threadIdx.x != 0) return;
+    uint32_t run = 0;
+    for (int64_t i = 0; i < n; i++) {
+        const uint32_t c = cnt[i];
+        cnt[i] = run;
+        run += c;
+    }
+    *total = run;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_live_rank(const uint8_t *__restrict__ live, int64_t nb,
+                                                     const uint32_t *__restrict__ off, int *__restrict__ rank)
+{
+    __shared__ uint32_t s_w[BLOCK / 64];
+    uint32_t base = off[blockIdx.x];
+    for (int q = 0; q < 4; q++) {
+        const int64_t b = (int64_t)blockIdx.x * 1024 + q * BLOCK + threadIdx.x;
+        const bool lv = b < nb && live[b];
+        const uint64_t m = __ballot(lv);
+        if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t before = 0;
+        for (int w = 0; w < (int)(threadIdx.x >> 6); w++) before += s_w[w];
+        if (b < nb) rank[b] = lv ? (int)(base + before + (uint32_t)count_below(m)) : -1;
+        base += s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        __syncthreads();
+    }
+}
+
+// the MLP backward's Gaussian term, per Gaussian and hidden unit: the views
+// in order, in each the receiver groups in order
+__global__ __launch_bounds__(BLOCK) void k_det_dl(const float *__restrict__ dLv, int nrg_max,
+                                                  const int *__restrict__ oinv, const int *__restrict__ rank,
+                                                  const int4 *__restrict__ vinfo, int V, int64_t K, int64_t Kp,
+                                                  float *__restrict__ dL)
+{
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= K * HID) return;
+    const int64_t k = i / HID;
+    const int u = (int)(i - k * HID);
+    float acc = 0.f;
+    for (int v = 0; v < V; v++) {
+        const int s = oinv[(size_t)v * K + k];
+        if (s < 0) continue;
+        const int rk = rank[((size_t)v * Kp + s) / MLP_PAIRS];
+        if (rk < 0) continue;
+        const int nrg = (vinfo[v].y + MLP_RG - 1) / MLP_RG;
+        for (int a = 0; a < nrg; a++)
+            acc += dLv[(((size_t)rk * nrg_max + a) * MLP_PAIRS + (s % MLP_PAIRS)) * HID + u];
+    }
+    dL[i] = acc;
+}
+
+// ... and its receiver term, per row and hidden unit: the row's marked
+// position blocks in order
+__global__ __launch_bounds__(BLOCK) void k_det_dg(const float *__restrict__ dGp, int rows_max,
+                                                  const int *__restrict__ rank, const int *__restrict__ rxview,
+                                                  const int4 *__restrict__ vinfo,
+                                                  const unsigned long long *__restrict__ counters, int N, int64_t Kp,
+                                                  float *__restrict__ dG)
+{
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= (int64_t)N * HID) return;
+    const int j = (int)(i / HID), u = (int)(i - (int64_t)j * HID);
+    const int v = rxview[j];
+    const int rl = j - vinfo[v].x;
+    const int64_t nb = ((int64_t)counters[2 * (size_t)v] + MLP_PAIRS - 1) / MLP_PAIRS;
+    const int64_t b0 = (int64_t)v * Kp / MLP_PAIRS;
+    float acc = 0.f;
+    for (int64_t b = 0; b < nb; b++) {
+        const int rk = rank[b0 + b];
+        if (rk >= 0) acc += dGp[((size_t)rk * rows_max + rl) * HID + u];
+    }
+    dG[i] = acc;
 }
 
 // ============================================================================
@@ -871,7 +1254,7 @@ hipError_t launch_zero_ranges(const ZeroRanges &z, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int R>
+template <int R, bool DET>
 static hipError_t blend_bwd_launch(Workspace &ws, const float *C, const float *dC, const float *dP, const float *dA,
                                    hipStream_t st)
 {
@@ -880,11 +1263,13 @@ static hipError_t blend_bwd_launch(Workspace &ws, const float *C, const float *d
     const int64_t ny = (int64_t)ws.n_chunks * split;
     if (ny > 65535 || ws.g.tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)ws.g.tiles, (unsigned)ny);
-    hipLaunchKernelGGL(k_blend_bwd<R>, grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
+    const DetPartials det = DET ? DetPartials{ws.gP.as<float>(), ws.dSP.as<float>(), ws.Dpad, ws.d_vinfo}
+                                : DetPartials{nullptr, nullptr, 0, nullptr};
+    hipLaunchKernelGGL((k_blend_bwd<R, DET>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                        ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                        ws.d_chunks, split, ws.Kp, ws.g, ws.mode == RXGS_MODE_TX ? 1 : 0, C, dC, dP, dA,
                        ws.Tfin.as<float>(), ws.nlast.as<int>(), ws.dS.as<float>(), ws.g2d.as<float>(),
-                       ws.live.as<uint8_t>());
+                       ws.live.as<uint8_t>(), det);
     return hipGetLastError();
 }
 
@@ -892,12 +1277,88 @@ hipError_t launch_blend_bwd(Workspace &ws, const float *C, const float *dC, cons
                             hipStream_t st)
 {
     if (ws.n_chunks == 0) return hipSuccess;
-    switch (ws.R) {
-    case 1: return blend_bwd_launch<1>(ws, C, dC, dP, dA, st);
-    case 2: return blend_bwd_launch<2>(ws, C, dC, dP, dA, st);
-    case 4: return blend_bwd_launch<4>(ws, C, dC, dP, dA, st);
-    default: return blend_bwd_launch<8>(ws, C, dC, dP, dA, st);   // 8 and 16
+    if (ws.det) {
+        switch (det_block_rows(ws)) {
+        case 1: return blend_bwd_launch<1, true>(ws, C, dC, dP, dA, st);
+        case 2: return blend_bwd_launch<2, true>(ws, C, dC, dP, dA, st);
+        default: return blend_bwd_launch<4, true>(ws, C, dC, dP, dA, st);
+        }
     }
+    switch (ws.R) {
+    case 1: return blend_bwd_launch<1, false>(ws, C, dC, dP, dA, st);
+    case 2: return blend_bwd_launch<2, false>(ws, C, dC, dP, dA, st);
+    case 4: return blend_bwd_launch<4, false>(ws, C, dC, dP, dA, st);
+    default: return blend_bwd_launch<8, false>(ws, C, dC, dP, dA, st);   // 8 and 16
+    }
+}
+
+// receivers per block of the deterministic blend backward (its per-wave LDS
+// slots hold 6 + 2 R values per entry)
+int det_block_rows(const Workspace &ws) { return std::min(ws.R, 4); }
+
+// the deterministic backward's pair-slot partials, the pair inverse, the
+// per-(view, position) gather and the inverse of the sorted order
+hipError_t launch_det_gather(Workspace &ws, hipStream_t st)
+{
+    const uint32_t *ekey = ws.pair_passes == 1 ? ws.pkey[0].as<uint32_t>() : ws.pkey_em.as<uint32_t>();
+    if (ws.Dpad > 0)
+        hipLaunchKernelGGL(k_pair_inv, dim3(nblk((size_t)ws.Dpad)), dim3(BLOCK), 0, st,
+                           ws.pkey[ws.pairs_buf].as<uint32_t>(), ws.pval[ws.pairs_buf].as<uint32_t>(), ekey,
+                           ws.poff.as<uint32_t>(), ws.d_segtab, ws.d_pbase, ws.d_pcount,
+                           ws.counters.as<unsigned long long>(), ws.Kp, ws.Dpad, ws.pinv.as<uint32_t>());
+    const size_t VK = (size_t)ws.V * ws.Kp;
+    hipLaunchKernelGGL(k_det_gather, dim3(nblk(VK)), dim3(BLOCK), 0, st, ws.gP.as<float>(), ws.dSP.as<float>(),
+                       ws.Dpad, det_block_rows(ws), ws.pinv.as<uint32_t>(), ws.poff.as<uint32_t>(), ws.d_pbase,
+                       ws.d_pcount, ws.counters.as<unsigned long long>(), ws.d_vinfo, ws.V, ws.Kp,
+                       ws.g2d.as<float>(), ws.dS.as<float>(), ws.live.as<uint8_t>());
+    hipLaunchKernelGGL(k_order_inv, dim3(nblk(VK)), dim3(BLOCK), 0, st, ws.vorder.as<uint32_t>(),
+                       ws.counters.as<unsigned long long>(), ws.V, ws.K, ws.Kp, ws.oinv.as<int>());
+    return hipGetLastError();
+}
+
+hipError_t launch_live_rank(Workspace &ws, hipStream_t st)
+{
+    const int64_t nb = (int64_t)ws.V * ws.Kp / MLP_PAIRS;
+    const int64_t nch = (nb + 1023) / 1024;
+    uint32_t *cnt = ws.lcnt.as<uint32_t>();
+    if (nch > 0) {
+        hipLaunchKernelGGL(k_live_count, dim3((unsigned)nch), dim3(BLOCK), 0, st, ws.live.as<uint8_t>(), nb, cnt);
+        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(BLOCK), 0, st, cnt, nch, cnt + nch);
+        hipLaunchKernelGGL(k_live_rank, dim3((unsigned)nch), dim3(BLOCK), 0, st, ws.live.as<uint8_t>(), nb, cnt,
+                           ws.rank.as<int>());
+    }
+    return hipGetLastError();
+}
+
+size_t live_rank_words(const Workspace &ws) { return (size_t)(((int64_t)ws.V * ws.Kp / MLP_PAIRS + 1023) / 1024) + 1; }
+
+hipError_t launch_det_rad(const Scene &sc, Workspace &ws, float *grad, int accum, hipStream_t st)
+{
+    if (!grad || sc.K == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_det_rad, dim3(nblk((size_t)sc.K)), dim3(BLOCK), 0, st, ws.dS.as<float2>(), ws.oinv.as<int>(),
+                       ws.d_rxview, ws.N, sc.K, ws.Kp, grad, accum);
+    return hipGetLastError();
+}
+
+hipError_t launch_det_mlp_gather(Workspace &ws, hipStream_t st)
+{
+    const int nrg_max = (std::min(ws.R_max, 1 << 30) + MLP_RG - 1) / MLP_RG;
+    if (ws.K > 0)
+        hipLaunchKernelGGL(k_det_dl, dim3(nblk((size_t)ws.K * HID)), dim3(BLOCK), 0, st, ws.dLv.as<float>(), nrg_max,
+                           ws.oinv.as<int>(), ws.rank.as<int>(), ws.d_vinfo, ws.V, ws.K, ws.Kp, ws.dL.as<float>());
+    hipLaunchKernelGGL(k_det_dg, dim3(nblk((size_t)ws.N * HID)), dim3(BLOCK), 0, st, ws.dGp.as<float>(), ws.R_max,
+                       ws.rank.as<int>(), ws.d_rxview, ws.d_vinfo, ws.counters.as<unsigned long long>(), ws.N, ws.Kp,
+                       ws.dG.as<float>());
+    return hipGetLastError();
+}
+
+hipError_t launch_det_project(const Scene &sc, Workspace &ws, const rxgs_grads &gr, hipStream_t st)
+{
+    if (sc.K == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_det_project, dim3(nblk((size_t)sc.K)), dim3(BLOCK), 0, st, sc.soa.as<float>(), sc.K, ws.Kp,
+                       ws.centres_p, ws.V, ws.g, ws.oinv.as<int>(), ws.g2d.as<float>(), gr.means, gr.log_scales,
+                       gr.quats, gr.logits, gr.accumulate);
+    return hipGetLastError();
 }
 
 hipError_t launch_rad_bwd(const Scene &sc, Workspace &ws, float *grad, hipStream_t st)
@@ -925,7 +1386,8 @@ hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *g
     const bool far = ws.mpos != 0xFFFFFFFFu;   // the forward evaluated a radiance prefix first
     if (far && (int64_t)ws.n_items + ws.n_items_far >= (1ll << 31)) return hipErrorInvalidValue;
     // virtual items per work item: enough that each holds at most MLPB_RSUB receivers
-    const int nsub = (std::min(ws.R_max, MLP_RG) + MLPB_RSUB - 1) / MLPB_RSUB;
+    // (the deterministic backward keeps whole items: one slot per receiver group)
+    const int nsub = ws.det ? 1 : (std::min(ws.R_max, MLP_RG) + MLPB_RSUB - 1) / MLPB_RSUB;
     const int64_t nall = (int64_t)ws.n_items + (far ? ws.n_items_far : 0);
     if (nall > INT32_MAX / std::max(nsub, 1)) return hipErrorInvalidValue;   // virtual item indices are int
     // the list of live virtual items (in the reduction scratch, first written
@@ -950,13 +1412,25 @@ hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *g
                            ws.n_items, items2, count2, std::max(nsub, 1), ws.Kp, ws.live.as<uint8_t>(), lw,
                            lw + BLOCK, lw + LIST_AT);
     }
-    if (nall > 0)
-        hipLaunchKernelGGL(k_mlp_bwd, dim3((unsigned)(nwaves / 4)), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
+    if (nall > 0 && ws.det) {
+        const DetMlp det{ws.dLv.as<float>(), ws.dGp.as<float>(), ws.rank.as<int>(), ws.d_vinfo,
+                         (ws.R_max + MLP_RG - 1) / MLP_RG, ws.R_max};
+        hipLaunchKernelGGL(k_mlp_bwd<true>, dim3((unsigned)(nwaves / 4)), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
                            ws.Gp.as<float>(), m.w2a.as<float>(), m.w2b.as<float>(), m.tab.as<float4>(), W3,
                            ws.vorder.as<uint32_t>(), ws.items.as<int4>(), ws.n_items, items2, count2,
                            std::max(nsub, 1), ws.Kp, sc.K, ws.live.as<uint8_t>(), ranked ? lw + LIST_AT : nullptr,
                            ranked ? lw + BLOCK : nullptr, ws.dS.as<float2>(), ws.dL.as<float>(),
-                           ws.dG.as<float>(), ws.mpart.as<float>());
+                           ws.dG.as<float>(), ws.mpart.as<float>(), det);
+        const hipError_t e = launch_det_mlp_gather(ws, st);
+        if (e != hipSuccess) return e;
+    } else if (nall > 0) {
+        hipLaunchKernelGGL(k_mlp_bwd<false>, dim3((unsigned)(nwaves / 4)), dim3(BLOCK), 0, st, ws.Lp.as<float>(),
+                           ws.Gp.as<float>(), m.w2a.as<float>(), m.w2b.as<float>(), m.tab.as<float4>(), W3,
+                           ws.vorder.as<uint32_t>(), ws.items.as<int4>(), ws.n_items, items2, count2,
+                           std::max(nsub, 1), ws.Kp, sc.K, ws.live.as<uint8_t>(), ranked ? lw + LIST_AT : nullptr,
+                           ranked ? lw + BLOCK : nullptr, ws.dS.as<float2>(), ws.dL.as<float>(),
+                           ws.dG.as<float>(), ws.mpart.as<float>(), DetMlp{});
+    }
     if (gmlp) {
         if (nall > 0) {
             hipLaunchKernelGGL(k_colsum_groups, dim3(nblk(4096 + 194), RED_GROUPS), dim3(BLOCK), 0, st,

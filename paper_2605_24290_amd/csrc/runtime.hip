@@ -143,7 +143,8 @@ void release_buffers(Workspace &ws)
                       &ws.counters, &ws.hist,   &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
                       &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.mred,   &ws.live,   &ws.items_live, &ws.vflag,
                       &ws.items_far, &ws.frec, &ws.fcnt,  &ws.ftile,  &ws.hist_b, &ws.gfeat_tmp, &ws.gmlp_tmp,
-                      &ws.rgam,    &ws.rab,     &ws.rloc};
+                      &ws.rgam,    &ws.rab,     &ws.rloc,    &ws.pkey_em, &ws.gP,     &ws.dSP,    &ws.pinv,
+                      &ws.oinv,    &ws.rank,    &ws.lcnt,    &ws.dLv,     &ws.dGp};
     for (DevBuf *b : bufs) release(*b);
 }
 
@@ -428,6 +429,10 @@ extern "C" rxgs_status rxgs_create(int device, const rxgs_grid *grid, rxgs_ctx *
     }
     ctx->device = device;
     ctx->alloc.device = device;
+    {
+        const char *e = std::getenv("RXGS_DETERMINISTIC");
+        ctx->deterministic = e && e[0] == '1';
+    }
     ctx->grid = *grid;
     DevGrid &g = ctx->g;
     g.H = grid->H;
@@ -796,6 +801,10 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     const bool save = saved && saved->keep;   // keep state for the backward and the exports
     ws.valid = false;
     ws.req_bytes = 0;
+    // a deterministic backward needs every position's radiance (no prefix,
+    // whose far-position work list is built in arrival order) and the
+    // pairs' emission order
+    ws.det = save && ctx->deterministic && rsrc == RSRC_SCENE;
     if (!ws.staged) {
         HIPCHK(ctx, hipEventCreateWithFlags(&ws.staged, hipEventDisableTiming));
         HIPCHK(ctx, hipEventCreateWithFlags(&ws.counted, hipEventDisableTiming));
@@ -988,7 +997,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     // statistics come from the first pass (weights do not depend on the
     // radiance), the backward reads the radiance of composited entries only,
     // and a radiance export evaluates the rest first.
-    if (ws.use_items && (mode == RXGS_MODE_RX || maxr < PREFIX_MAX_RX))
+    if (ws.use_items && !ws.det && (mode == RXGS_MODE_RX || maxr < PREFIX_MAX_RX))
         for (int v = 0; v < V; v++)
             if ((uint32_t)ws.h_nvis[v] > prefix) ws.mpos = prefix;
     ws.rad_complete = ws.mpos == 0xFFFFFFFFu;
@@ -1093,6 +1102,11 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         // (the emission kernel also clears the pair sort's scratch)
         const int sbits = std::max(bits_for((uint64_t)g.tiles), 1);
         STAGE(ctx, "emit_pairs", launch_emit2(ws, g, sort_ws_bytes((uint32_t)Dpad, sbits, V) / 4, st));
+        ws.pair_passes = (sbits + 7) / 8;
+        if (ws.det && ws.pair_passes > 1) {   // the sort overwrites the emission order
+            WGROW(ctx, ws, ws.pkey_em, (size_t)Dpad * 4);
+            HIPCHK(ctx, hipMemcpyAsync(ws.pkey_em.p, ws.pkey[0].p, (size_t)Dpad * 4, hipMemcpyDeviceToDevice, st));
+        }
         STAGE(ctx, "sort_pairs", sort_pairs_u32(ws.pkey, ws.pval, ws.hist_b, pcur, (uint32_t)Dpad, sbits, V, 0,
                                                 ws.d_segtab, st, true));
         ws.pair_bits = sbits;
@@ -1487,6 +1501,88 @@ extern "C" rxgs_status rxgs_render_chunked(rxgs_ctx *ctx, int mode, int Q, const
 }
 
 // ============================================================================
+// The deterministic backward: the blend backward stores one partial per
+// (pair slot, receiver block) instead of adding atomically; gathers add them
+// per (view, position) in the pairs' emission order, the MLP backward's terms
+// per Gaussian and per receiver in view and block order, and the projection
+// gradients per Gaussian over the views in order.  The outputs are written
+// (or added, accumulate = 1) once each.
+static rxgs_status backward_det(rxgs_ctx *ctx, Workspace &ws, const float *C, const float *dC, const float *dP,
+                                const float *dA, const rxgs_grads &gr, ZeroRanges &zr, hipStream_t st)
+{
+    const Scene &sc = ctx->scene;
+    const int64_t K = ws.K;
+    const bool accum = gr.accumulate == 1;
+    const size_t VK = (size_t)ws.V * ws.Kp;
+    const int Rd = det_block_rows(ws);
+    const size_t nblk = (size_t)(ws.R_max + Rd - 1) / Rd;
+    const size_t Dp = (size_t)std::max<int64_t>(ws.Dpad, 1);
+    zr.n = 0;   // outputs are written, not accumulated into
+    WGROW(ctx, ws, ws.dS, (size_t)ws.N * ws.Kp * 8);
+    WGROW(ctx, ws, ws.g2d, VK * 32);
+    WGROW(ctx, ws, ws.live, VK / MLP_PAIRS + 4);
+    WGROW(ctx, ws, ws.gP, nblk * Dp * 32);
+    WGROW(ctx, ws, ws.dSP, (size_t)ws.R_max * Dp * 8);
+    WGROW(ctx, ws, ws.pinv, Dp * 4);
+    WGROW(ctx, ws, ws.oinv, (size_t)ws.V * std::max<int64_t>(K, 1) * 4);
+    zr.add(ws.live.p, (VK / MLP_PAIRS + 3) / 4);
+    zr.add(ws.gP.p, nblk * Dp * 8);
+    zr.add(ws.dSP.p, (size_t)ws.R_max * Dp * 2);
+    float *gfeat = gr.features, *gmlp = gr.mlp;
+    if (ws.use_mlp) {
+        WGROW(ctx, ws, ws.dL, (size_t)K * HID * 4);
+        WGROW(ctx, ws, ws.dG, (size_t)ws.N * HID * 4);
+        WGROW(ctx, ws, ws.mpart, mlp_part_bytes(ws));
+        WGROW(ctx, ws, ws.w1part, w1b_part_bytes(K));
+        WGROW(ctx, ws, ws.mred, mlp_red_bytes());
+        WGROW(ctx, ws, ws.rank, (VK / MLP_PAIRS + 1) * 4);
+        WGROW(ctx, ws, ws.lcnt, live_rank_words(ws) * 4);
+        if (accum && gfeat) {
+            WGROW(ctx, ws, ws.gfeat_tmp, (size_t)K * FEAT * 4);
+            gfeat = ws.gfeat_tmp.as<float>();
+        }
+        if (accum && gmlp) {
+            WGROW(ctx, ws, ws.gmlp_tmp, (size_t)RXGS_MLP_NPARAM * 4);
+            gmlp = ws.gmlp_tmp.as<float>();
+        }
+    }
+    HIPCHK(ctx, launch_zero_ranges(zr, st));
+    HIPCHK(ctx, launch_fill_u32(ws.oinv.as<uint32_t>(), 0xFFFFFFFFu, (size_t)ws.V * K, st));
+    STAGE(ctx, "blend_bwd", launch_blend_bwd(ws, C, dC, dP, dA, st));
+    STAGE(ctx, "bwd_misc", launch_det_gather(ws, st));
+    if (ws.use_mlp) {
+        // one slot per marked position block, in index order
+        HIPCHK(ctx, launch_live_rank(ws, st));
+        if (!ensure_pinned(ws, 64)) return fail(ctx, RXGS_E_OOM, "pinned allocation failed");
+        const size_t nchunk = live_rank_words(ws) - 1;
+        HIPCHK(ctx, hipMemcpyAsync(ws.h_pinned, ws.lcnt.as<uint32_t>() + nchunk, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+        const size_t nslot = std::max<uint32_t>(*static_cast<uint32_t *>(ws.h_pinned), 1u);
+        const size_t nrg = (size_t)(ws.R_max + MLP_RG - 1) / MLP_RG;
+        WGROW(ctx, ws, ws.dLv, nslot * nrg * MLP_PAIRS * HID * 4);
+        WGROW(ctx, ws, ws.dGp, nslot * (size_t)ws.R_max * HID * 4);
+        HIPCHK(ctx, launch_fill_u32(ws.dGp.as<uint32_t>(), 0u, nslot * (size_t)ws.R_max * HID, st));
+        STAGE(ctx, "mlp_bwd", launch_mlp_bwd(sc, ctx->mlp, ws, gfeat, gmlp, st));
+    } else {
+        STAGE(ctx, "bwd_misc", launch_det_rad(sc, ws, gr.radiance, gr.accumulate, st));
+    }
+    STAGE(ctx, "project_bwd", launch_det_project(sc, ws, gr, st));
+    if (accum && ws.use_mlp) {
+        if (gr.features) HIPCHK(ctx, launch_add_f32(gr.features, gfeat, (size_t)K * FEAT, st));
+        if (gr.mlp) HIPCHK(ctx, launch_add_f32(gr.mlp, gmlp, RXGS_MLP_NPARAM, st));
+    }
+    if (ws.done) HIPCHK(ctx, hipEventRecord(ws.done, st));
+    return RXGS_OK;
+}
+
+extern "C" rxgs_status rxgs_set_deterministic(rxgs_ctx *ctx, int on)
+{
+    if (!ctx) return RXGS_E_INVALID;
+    ctx->deterministic = on != 0;
+    return RXGS_OK;
+}
+
+// ============================================================================
 extern "C" rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *saved, const float *C, const float *dC,
                                             const float *dP, const float *dA, const rxgs_grads *grads, void *stream)
 {
@@ -1527,6 +1623,7 @@ extern "C" rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *sav
         return RXGS_OK;
     }
     const size_t VK = (size_t)ws.V * ws.Kp;
+    if (ws.det) return backward_det(ctx, ws, C, dC, dP, dA, gr, zr, st);
     WGROW(ctx, ws, ws.dS, (size_t)ws.N * ws.Kp * 8);
     WGROW(ctx, ws, ws.g2d, VK * 32);
     WGROW(ctx, ws, ws.live, VK / MLP_PAIRS + 4);

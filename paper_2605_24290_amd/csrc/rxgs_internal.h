@@ -154,6 +154,19 @@ struct Workspace {
     DevBuf rloc;               // Nrx x Kp x C float4 local modulation (1 + alpha', beta') per sorted position
     bool fixed_host = false;   // h_pinned is a fixed buffer made at set-up (never regrown)
     size_t req_bytes = 0;      // device bytes the last render's buffers asked for
+    // deterministic backward (rxgs_set_deterministic): the forward kept every
+    // position's radiance and the emission order of the pairs
+    bool det = false;
+    int pair_passes = 0;       // radix passes of the last pair sort
+    DevBuf pkey_em;            // Dpad u32 tile keys in emission order (pair sorts of 2+ passes)
+    DevBuf gP;                 // [block of a view][Dpad][8] record-gradient partials per pair slot
+    DevBuf dSP;                // [row of a view][Dpad][2] dL/ds partials per pair slot
+    DevBuf pinv;               // Dpad u32: sorted slot of each emitted pair
+    DevBuf oinv;               // V x K int: sorted position of each (view, Gaussian), -1 if not visible
+    DevBuf rank;               // V x Kp / 32 int: slot of each marked position block, -1 unmarked
+    DevBuf lcnt;               // per 1024 blocks: marked-block offsets, then their total
+    DevBuf dLv;                // [slot][receiver group][32][64] Gaussian terms of the MLP backward
+    DevBuf dGp;                // [slot][row of the view][64] receiver terms of the MLP backward
     // sizes of the last render
     int mode = 0, V = 0, N = 0, Q = 0, R = 1;
     int64_t K = 0, Kp = 0, D = 0, Dpad = 0, nvis_total = 0;
@@ -289,6 +302,7 @@ struct rxgs_ctx {
     std::vector<rxgs_saved *> saved;   // live saved states
     rxgs::Profiler prof;
     bool near_cut = false;     // emit each view's nearest entries first (rxgs_set_near_cut)
+    bool deterministic = false;   // saved renders and their backward sum in fixed orders (rxgs_set_deterministic)
     int64_t views_redone = 0;  // views redone over all their entries
     hipStream_t aux = nullptr; // private non-blocking stream of the saved-state queries and exports
     rxgs::Allocator alloc;     // the context's device allocations
@@ -368,6 +382,14 @@ hipError_t launch_add_f32(float *out, const float *add, size_t n, hipStream_t st
 hipError_t launch_rad_bwd(const Scene &sc, Workspace &ws, float *grad, hipStream_t st);
 hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *gfeat, float *gmlp, hipStream_t st);
 hipError_t launch_project_bwd(const Scene &sc, Workspace &ws, const rxgs_grads &gr, hipStream_t st);
+// deterministic backward (backward.hip)
+int det_block_rows(const Workspace &ws);
+hipError_t launch_det_gather(Workspace &ws, hipStream_t st);
+hipError_t launch_live_rank(Workspace &ws, hipStream_t st);
+size_t live_rank_words(const Workspace &ws);
+hipError_t launch_det_rad(const Scene &sc, Workspace &ws, float *grad, int accum, hipStream_t st);
+hipError_t launch_det_mlp_gather(Workspace &ws, hipStream_t st);
+hipError_t launch_det_project(const Scene &sc, Workspace &ws, const rxgs_grads &gr, hipStream_t st);
 size_t mlp_part_bytes(const Workspace &ws);
 unsigned long long *stat_words(Workspace &ws);
 int sort_items_for(uint32_t n);

@@ -100,7 +100,7 @@ EXPORTED = ("rxgs_create", "rxgs_create_with_allocator", "rxgs_destroy", "rxgs_l
             "rxgs_server_cancel", "rxgs_server_stats", "rxgs_server_stop", "rxgs_plan_batch",
             "rxgs_workspace_estimate", "rxgs_set_near_cut", "rxgs_views_redone", "rxgs_render_chunked",
             "rxgs_view_flags", "rxgs_rxcond_param_count", "rxgs_rxcond_upload", "rxgs_render_rxcond",
-            "rxgs_rxcond_export", "rxgs_render_noalloc", "rxgs_server_start_host")
+            "rxgs_rxcond_export", "rxgs_render_noalloc", "rxgs_server_start_host", "rxgs_set_deterministic")
 
 _lib = None
 
@@ -153,6 +153,8 @@ def lib():
     L.rxgs_render_chunked.restype = c_int
     L.rxgs_view_flags.argtypes = [vp, vp, c_int32, POINTER(c_int32)]
     L.rxgs_view_flags.restype = c_int
+    L.rxgs_set_deterministic.argtypes = [vp, c_int]
+    L.rxgs_set_deterministic.restype = c_int
     L.rxgs_set_near_cut.argtypes = [vp, c_int]
     L.rxgs_set_near_cut.restype = c_int
     L.rxgs_views_redone.argtypes = [vp]
@@ -466,6 +468,10 @@ class Renderer:
         _check(lib().rxgs_render_backward(self._ctx, saved._h, _ptr(C.contiguous()), _ptr(dC_t), _ptr(dP_t),
                                           _ptr(dA_t), byref(cg), self._stream()), self._ctx)
         return grads
+
+    def deterministic(self, on: bool = True):
+        """Fixed-order backward sums (rxgs_set_deterministic): bitwise-repeatable gradients."""
+        _check(lib().rxgs_set_deterministic(self._ctx, 1 if on else 0), self._ctx)
 
     def near_cut(self, on: bool = True):
         """Nearest-first emission with the exact fallback (rxgs_set_near_cut; off by default)."""
