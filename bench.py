@@ -42,6 +42,7 @@ SORT_BYTES_PER_KEY_PASS = 16  # read and write one (u32 key, u32 value) per pass
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                             "k_blend_fwd1_c1_rx_traffic.txt")
 SQ_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "c1_rx_sq_counters.txt")
+STATS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "k_blend_fwd1_c1_rx_stats.txt")
 VALU_ISSUE_PEAK = 256 * 2.4e9   # wave64 VALU instructions per second (one per CU per cycle)
 
 
@@ -120,12 +121,16 @@ def gpu_part(args):
         # profiled pass: per-stage event times over the same number of steps
         r.profile(True)
         r.profile_read(reset=True)
+        r.profile_counts(reset=True)
         ms_prof = timed(fused(mode), args.steps, 0)
         stages = r.profile_read(reset=True)
+        counts = r.profile_counts(reset=True)
         r.profile(False)
         entry["ms_per_step_profiled"] = ms_prof
         entry["stages_ms_per_step"] = {k: v[1] / args.steps for k, v in stages.items()}
         entry["stage_launches"] = {k: v[0] for k, v in stages.items()}
+        # MLP work the pair kernels evaluated, counted on the device per render
+        entry["mlp_evaluated"] = {k: v / args.steps for k, v in counts.items()}
         # sizes of one render (visible Gaussians per view, pairs)
         saved = rxgs.Saved(r)
         r.render(rx, tx=tx, mode=mode, saved=saved, out=(C, P))
@@ -140,6 +145,8 @@ def gpu_part(args):
                           "evaluated_px": info["n_evaluated_px"], "walked_px": info["n_walked_px"],
                           "chunks_per_view": 1 if mode == "rx" else -(-N // rpc)}
         saved.close()
+        if mode == args.mode and sc.features is not None:
+            entry["mlp_fp32"] = mlp_fp32_timing(args, wl, rx, tx, C, P, mode)
         if not args.no_loop:
             ms_loop = timed(loop(mode), args.loop_steps, 1)
             entry["per_rx_loop"] = {"ms_per_step": ms_loop, "rx_views_per_s": N * 1000.0 / ms_loop,
@@ -147,6 +154,36 @@ def gpu_part(args):
         res[mode] = entry
     r.close()
     return wl, res
+
+
+def mlp_fp32_timing(args, wl, rx, tx, C, P, mode):
+    """The same render with the pair MLP on FP32 matrix cores throughout
+    (RXGS_MLP_FP32=1 at the MLP upload) instead of split FP16."""
+    from paper_2605_24290_amd import rxgs
+    from paper_2605_24290_amd import scenes as S
+    sc = wl.scene
+    r = rxgs.Renderer(wl.grid)
+    r.upload_scene(sc.means, sc.log_scales, sc.quats, sc.logits, features=sc.features)
+    old = os.environ.get("RXGS_MLP_FP32")
+    os.environ["RXGS_MLP_FP32"] = "1"
+    try:
+        r.upload_mlp(S.flat_mlp(wl.mlp))
+    finally:
+        if old is None:
+            del os.environ["RXGS_MLP_FP32"]
+        else:
+            os.environ["RXGS_MLP_FP32"] = old
+    f = lambda: r.render(rx, tx=tx, mode=mode, out=(C, P))
+    ms = timed(f, args.steps, args.warmup)
+    r.profile(True)
+    r.profile_read(reset=True)
+    timed(f, args.steps, 0)
+    stages = r.profile_read(reset=True)
+    r.profile(False)
+    r.close()
+    st = {k: v[1] / args.steps for k, v in stages.items()}
+    return {"ms_per_step": ms, "rx_views_per_s": rx.shape[0] * 1000.0 / ms,
+            "mlp_pairs_ms": st.get("mlp_pairs", 0.0) + st.get("mlp_far", 0.0)}
 
 
 def train_step_part(args):
@@ -182,6 +219,17 @@ def train_step_part(args):
         r.profile(False)
         out[mode] = {"ms_per_step": ms, "rx_views_per_s": wl.rx.shape[0] * 1000.0 / ms,
                      "stages_ms_per_step": {k: v[1] / 3 for k, v in stages.items()}}
+        # the same step with the fixed-order (bitwise-repeatable) backward
+        r.deterministic(True)
+        ms_det = timed(step, max(3, args.steps // 4), 2)
+        r.profile(True)
+        r.profile_read(reset=True)
+        timed(step, 3, 0)
+        stages = r.profile_read(reset=True)
+        r.profile(False)
+        r.deterministic(False)
+        out[mode]["deterministic"] = {"ms_per_step": ms_det, "vs_atomic": ms_det / ms,
+                                      "stages_ms_per_step": {k: v[1] / 3 for k, v in stages.items()}}
     saved.close()
     r.close()
     return {"workload": f"c2: {sc.K} Gaussians, {wl.rx.shape[0]} receivers, 90x360, MLP, L2 loss, forward + "
@@ -386,18 +434,23 @@ def roofline_for(entry, mode, workload):
         # executed wave64 VALU instructions per launch (SQ_INSTS_VALU of the
         # committed counter run) against the issue peak, over the live launch time
         insts = stored_figure(SQ_FILE, "valu_wave_insts_per_launch", "k_blend_fwd1", workload)
+        # the same work over the kernel's average duration in the committed
+        # rocprofv3 --kernel-trace --stats summary (None once the sources changed)
+        avg_ns = stored_figure(STATS_FILE, "avg_ns_per_launch", "k_blend_fwd1", workload)
+        frac_rp = None if not avg_ns else ops / (avg_ns * 1e-9) / 1e12 / PEAK_VALU_TOPS
         return {"kernel": "k_blend_fwd1", "bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS,
-                "unit": "Tops/s", "frac": ach / PEAK_VALU_TOPS,
+                "unit": "Tops/s", "frac": ach / PEAK_VALU_TOPS, "frac_rocprof": frac_rp,
+                "rocprof_avg_us": None if not avg_ns else avg_ns / 1000.0, "event_avg_us": t_s * 1e6,
                 "traffic": stored_traffic("k_blend_fwd1", workload),
                 "valu_issue_frac": None if insts is None else insts / (VALU_ISSUE_PEAK * t_s),
                 "work": f"{BLEND_OPS_PER_PAIR} lane-ops x {sz['composited']} composited (pixel, Gaussian) pairs"}
     if top == "mlp_pairs":
-        flop = MLP_MFMA_FLOP_PER_PAIR * sz["mlp_pairs"]
+        flop = MLP_MFMA_FLOP_PER_PAIR * mlp_pairs_evaluated(entry)
         ach = flop / t_s / 1e12
         return {"kernel": "k_mlp_pairs", "bound": "mfma", "achieved": ach, "peak": PEAK_FP16_MFMA_TFLOPS,
                 "unit": "TFLOP/s", "frac": ach / PEAK_FP16_MFMA_TFLOPS, "traffic": None,
-                "work": f"{MLP_MFMA_FLOP_PER_PAIR} FP16 MFMA FLOP x {sz['mlp_pairs']} (receiver, visible Gaussian) "
-                        f"pairs ({MLP_FLOP_PER_PAIR} FP32-equivalent)"}
+                "work": f"{MLP_MFMA_FLOP_PER_PAIR} FP16 MFMA FLOP x {mlp_pairs_evaluated(entry)} (receiver, "
+                        f"position) pairs evaluated ({MLP_FLOP_PER_PAIR} FP32-equivalent)"}
     if top == "sort_depth":
         byts = (4 + 4 * SORT_BYTES_PER_KEY_PASS) * sz["sort_keys"]
         ach = byts / t_s / 1e9
@@ -416,6 +469,13 @@ EMIT_RECORD_BYTES = 84 + 56   # per visible entry: order index + projection term
 EMIT_PAIR_BYTES_ENTRY = 20    # per visible entry: box and first pair slot read
 PAIR_BYTES = 8                # per pair: tile and sorted position written
 PAIR_SORT_BYTES = 4 + SORT_BYTES_PER_KEY_PASS   # per pair: histogram read + one 8-bit pass
+
+
+def mlp_pairs_evaluated(entry):
+    """(receiver, position) pairs the pair MLP evaluated per render, counted on
+    the device in the profiled pass (prefix and far launches together)."""
+    ev = entry.get("mlp_evaluated")
+    return int(round(ev["mlp_pairs"])) if ev else entry["sizes"]["mlp_pairs"]
 
 
 def stage_rooflines(entry, mode, K):
@@ -437,12 +497,17 @@ def stage_rooflines(entry, mode, K):
         "emit_pairs": ("hbm", EMIT_PAIR_BYTES_ENTRY * nvis + PAIR_BYTES * D,
                        f"{EMIT_PAIR_BYTES_ENTRY} B per visible entry + {PAIR_BYTES} B per pair"),
         "sort_pairs": ("hbm", PAIR_SORT_BYTES * D, f"{PAIR_SORT_BYTES} B per pair"),
-        "mlp_pairs": ("mfma", MLP_MFMA_FLOP_PER_PAIR * sz["mlp_pairs"],
-                      f"{MLP_MFMA_FLOP_PER_PAIR} FP16 MFMA FLOP per (receiver, visible Gaussian)"),
+        "mlp_pairs": ("mfma", MLP_MFMA_FLOP_PER_PAIR * mlp_pairs_evaluated(entry),
+                      f"{MLP_MFMA_FLOP_PER_PAIR} FP16 MFMA FLOP per (receiver, position) pair evaluated "
+                      "(device count; the far launch's time and pairs included)"),
         "blend_fwd": ("alu", blend_ops, f"{BLEND_OPS_PER_PAIR} lane-ops per composited pair"),
     }
     peak = {"hbm": PEAK_HBM_GBS * 1e9, "mfma": PEAK_FP16_MFMA_TFLOPS * 1e12, "alu": PEAK_VALU_TOPS * 1e12}
     rows, t_roof_sum = {}, 0.0
+    st = dict(st)
+    if "mlp_far" in st and "mlp_pairs" in st:   # the counted pairs cover both launches
+        st["mlp_pairs"] += st.pop("mlp_far")
+        rows["mlp_far"] = {"bound": "included in mlp_pairs"}
     for name, t_ms in st.items():
         if name not in model:
             rows[name] = {"bound": "negligible", "t_us": t_ms * 1e3}
@@ -491,9 +556,33 @@ def cpu_baseline(args, wl, mode):
         dt += time.perf_counter() - t0
         views += n
         reps += 1
+    # one thread: one receiver, repeated for about a third of the time
+    rx1 = wl.rx[:1]
+    cen1, rv1 = O.views_for(mode, wl.tx, rx1)
+    v1, d1 = 0, 0.0
+    while v1 == 0 or d1 < args.cpu_seconds / 3:
+        t0 = time.perf_counter()
+        O.render(wl.scene, wl.grid, cen1, rx1, rv1, mlp=wl.mlp, nthreads=1)
+        d1 += time.perf_counter() - t0
+        v1 += 1
     return {"value": views / dt, "unit": "receiver-views/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{reps} x the first {n} of {wl.rx.shape[0]} receivers, full grid, {mode} mode, FP64 C "
-                      f"oracle, {dt:.1f} s wall"}
+                      f"oracle, {dt:.1f} s wall",
+            "one_thread": {"value": v1 / d1, "unit": "receiver-views/s", "cores": 1,
+                           "sample": f"{v1} x the first receiver, {d1:.1f} s wall"}}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def main():
@@ -519,6 +608,10 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "dtype_note": "FP32 inputs, outputs, projection keys and compositing (FP64 projection terms); the pair "
+                      "MLP's layer 2 and fused layer-1 Gaussian term as split FP16 (hi + lo, three FP16 MFMA "
+                      "products, ~2^-21 relative per product) with FP32 accumulation; fused.mlp_fp32 times the "
+                      "FP32-MFMA variant (RXGS_MLP_FP32=1)",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {wl.scene.K} Gaussians, {wl.rx.shape[0]} receivers, "
                                f"{wl.grid.H}x{wl.grid.W} grid, MLP radiance, {args.mode.upper()}-mode views",

@@ -392,7 +392,16 @@ rxgs_status rxgs_server_stop(rxgs_server *srv);
  */
 int32_t rxgs_plan_batch(const int32_t *n_rx, int32_t n_queued, int32_t mode, int64_t K, int32_t H, int32_t W,
                         int64_t budget_bytes, int32_t max_rx, int32_t max_queries, int64_t *bytes_out);
-/* Workspace estimate of one render (bytes) for Q queries and N receivers. */
+/*
+ * Device bytes of one render of Q queries and N receivers (mode, K Gaussians,
+ * H x W grid): an upper bound of the sum of the render's workspace requests
+ * (rxgs_saved_info.workspace_bytes) plus its inputs and outputs, given at most
+ * RXGS_EST_PAIRS_PER_GAUSSIAN tile pairs per (view, Gaussian) on average,
+ * the one term that depends on the scene (a Gaussian covers more tiles the
+ * nearer it is to the view centre).  The server starts from that ratio and
+ * raises it to 1.25 x the largest one a render has shown.
+ */
+#define RXGS_EST_PAIRS_PER_GAUSSIAN 8.0
 int64_t rxgs_workspace_estimate(int32_t mode, int32_t Q, int32_t N, int64_t K, int32_t H, int32_t W);
 
 /*
@@ -416,6 +425,26 @@ typedef struct {
 
 rxgs_status rxgs_profile_enable(rxgs_ctx *ctx, int on);
 rxgs_status rxgs_profile_read(rxgs_ctx *ctx, rxgs_stage_time *out, int max_entries, int *n_entries, int reset);
+
+/*
+ * Work counts of the profiled renders, counted on the device from the work
+ * lists the kernels consume (Alg. 1 stage 2: the radiance of each receiver
+ * at each sorted position): while profiling is enabled, every launch of the
+ * pair MLP (or of the conditioned radiance) is followed by a small kernel that
+ * adds up its work items.  mlp_items: work items evaluated (one view, 32
+ * sorted positions, up to 16 receivers); mlp_pairs: (receiver, position)
+ * radiance values evaluated; mlp_slots: (receiver, position slot) pairs the
+ * matrix cores process, 32 per (work item, receiver), padding included.
+ * The counts are read on `stream` (the renders' stream; the call waits for
+ * it); `reset` clears them after reading.  Errors: E_INVALID, E_DEVICE.
+ */
+typedef struct {
+    int64_t mlp_items;
+    int64_t mlp_pairs;
+    int64_t mlp_slots;
+} rxgs_work_counts;
+
+rxgs_status rxgs_profile_counts(rxgs_ctx *ctx, rxgs_work_counts *out, int reset, void *stream);
 
 /*
  * Nearest-first emission (off by default).  Compositing stops at a pixel once

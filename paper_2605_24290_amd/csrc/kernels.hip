@@ -2222,6 +2222,43 @@ hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStr
     return hipGetLastError();
 }
 
+// sums over a list of MLP work items (view, s0, first receiver, receivers |
+// valid positions << 8): items, (receiver, position) pairs, 32-slot pairs
+__global__ __launch_bounds__(BLOCK) void k_count_items(const int4 *__restrict__ items, int nmax,
+                                                       const int *__restrict__ nlive, unsigned long long *cnt)
+{
+    const int n = nlive ? min(nmax, *nlive) : nmax;
+    unsigned long long ni = 0, np = 0, ns = 0;
+    for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
+        const int w = items[i].w;
+        ni += 1;
+        np += (unsigned long long)(w & 255) * (unsigned long long)(w >> 8);
+        ns += (unsigned long long)(w & 255) * MLP_PAIRS;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        ni += __shfl_xor(ni, o);
+        np += __shfl_xor(np, o);
+        ns += __shfl_xor(ns, o);
+    }
+    if ((threadIdx.x & 63) == 0 && ni) {
+        atomicAdd(cnt, ni);
+        atomicAdd(cnt + 1, np);
+        atomicAdd(cnt + 2, ns);
+    }
+}
+
+hipError_t launch_count_items(Workspace &ws, bool far, unsigned long long *cnt, hipStream_t st)
+{
+    const int4 *items = far ? ws.items_far.as<int4>() : ws.lazy ? ws.items_live.as<int4>() : ws.items.as<int4>();
+    const int *nlive = far ? far_count(ws) : ws.lazy ? live_count(ws) : nullptr;
+    const int nmax = far ? ws.n_items_far : ws.n_items;
+    if (nmax <= 0 || !cnt) return hipSuccess;
+    hipLaunchKernelGGL(k_count_items, dim3((unsigned)std::min((nmax + BLOCK - 1) / BLOCK, 256)), dim3(BLOCK), 0, st,
+                       items, nmax, nlive, cnt);
+    return hipGetLastError();
+}
+
 template <int R>
 static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st, bool redo)
 {

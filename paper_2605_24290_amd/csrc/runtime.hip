@@ -286,7 +286,30 @@ extern "C" rxgs_status rxgs_profile_enable(rxgs_ctx *ctx, int on)
 {
     if (!ctx) return RXGS_E_INVALID;
     DeviceScope ds(ctx->device);
+    if (on && !ctx->prof.dcount) {
+        void *p = nullptr;
+        if (hipMalloc(&p, 64) != hipSuccess) return fail(ctx, RXGS_E_OOM, "profile counters: device allocation failed");
+        ctx->prof.dcount = static_cast<unsigned long long *>(p);
+        HIPCHK(ctx, hipMemset(p, 0, 64));
+    }
     ctx->prof.on = on != 0;
+    return RXGS_OK;
+}
+
+extern "C" rxgs_status rxgs_profile_counts(rxgs_ctx *ctx, rxgs_work_counts *out, int reset, void *stream)
+{
+    if (!ctx || !out) return RXGS_E_INVALID;
+    DeviceScope ds(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    unsigned long long h[3] = {0, 0, 0};
+    if (ctx->prof.dcount) {
+        HIPCHK(ctx, hipMemcpyAsync(h, ctx->prof.dcount, sizeof h, hipMemcpyDeviceToHost, st));
+        if (reset) HIPCHK(ctx, hipMemsetAsync(ctx->prof.dcount, 0, sizeof h, st));
+        HIPCHK(ctx, hipStreamSynchronize(st));
+    }
+    out->mlp_items = (int64_t)h[0];
+    out->mlp_pairs = (int64_t)h[1];
+    out->mlp_slots = (int64_t)h[2];
     return RXGS_OK;
 }
 
@@ -481,6 +504,7 @@ extern "C" void rxgs_destroy(rxgs_ctx *ctx)
     (void)wait_workspace(ctx->ws);
     if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
     ctx->prof.release_all();
+    if (ctx->prof.dcount) (void)hipFree(ctx->prof.dcount);
     free_workspace(ctx->ws);
     release(ctx->scene.soa);
     release(ctx->scene.rad);
@@ -1124,10 +1148,12 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         // cannot compute it itself
         if (save || !mlp_fused_ok(sc, ctx->mlp)) STAGE(ctx, "mlp_local", launch_mlp_local(sc, ctx->mlp, ws, st));
         STAGE(ctx, "mlp_pairs", launch_mlp_pairs(sc, ctx->mlp, ws, st));
+        if (ctx->prof.on) HIPCHK(ctx, launch_count_items(ws, false, ctx->prof.dcount, st));
     } else if (rxc) {
         if (!ws.items_built) STAGE(ctx, "mlp_items", launch_mlp_items(ws, st));
         if (ws.lazy) STAGE(ctx, "blend_weights", launch_blend_weights(ws, st));
         STAGE(ctx, "rxcond_pairs", launch_rxcond_pairs(sc, ctx->rxc, ws, st, false));
+        if (ctx->prof.on) HIPCHK(ctx, launch_count_items(ws, false, ctx->prof.dcount, st));
     } else {
         STAGE(ctx, "rad_direct", launch_rad_direct(sc, ws, st));
     }
@@ -1143,6 +1169,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         STAGE(ctx, "far_items", launch_far_items(ws, st));
         STAGE(ctx, "mlp_far", rxc ? launch_rxcond_pairs(sc, ctx->rxc, ws, st, true)
                                   : launch_mlp_pairs(sc, ctx->mlp, ws, st, true));
+        if (ctx->prof.on) HIPCHK(ctx, launch_count_items(ws, true, ctx->prof.dcount, st));
         STAGE(ctx, "blend_far", launch_blend_fwd(ws, C, false, st, true));
     }
     STAGE(ctx, "reduce", launch_reduce_outputs(ws, power, csum, st));

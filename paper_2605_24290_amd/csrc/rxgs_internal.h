@@ -270,6 +270,7 @@ struct Profiler {
     std::vector<std::string> names;
     std::vector<int64_t> launches;
     std::vector<double> ms;
+    unsigned long long *dcount = nullptr;   // device: MLP work items, pairs, slots of profiled renders
     int stage_id(const char *name);
     hipEvent_t take();
     void flush();
@@ -366,6 +367,9 @@ hipError_t launch_mlp_global_term(const Mlp &m, Workspace &ws, hipStream_t st);
 hipError_t launch_mlp_items(Workspace &ws, hipStream_t st);
 hipError_t launch_mlp_local(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st);
 hipError_t launch_mlp_pairs(const Scene &sc, const Mlp &m, Workspace &ws, hipStream_t st, bool far = false);
+// adds the work items, pairs and slots of the list the pair kernels of this
+// render consume (the same selection as theirs) to cnt[0..2]
+hipError_t launch_count_items(Workspace &ws, bool far, unsigned long long *cnt, hipStream_t st);
 bool mlp_fused_ok(const Scene &sc, const Mlp &m);
 hipError_t launch_blend_fwd(Workspace &ws, float *C, bool save, hipStream_t st, bool redo = false);
 hipError_t launch_far_items(Workspace &ws, hipStream_t st);

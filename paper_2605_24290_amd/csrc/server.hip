@@ -97,6 +97,8 @@ struct Executor {
     virtual void fetch(rxgs_server *s, Slot &sl, size_t b, Ticket &tk) = 0;
     // device memory the slot's last batch asked for (-1: not tracked)
     virtual int64_t used_bytes(rxgs_server *s, Slot &sl) = 0;
+    // tile pairs per (view, Gaussian) of the slot's last batch (-1: not tracked)
+    virtual double pairs_per_gaussian(Slot &sl) = 0;
 };
 
 }  // namespace
@@ -108,6 +110,9 @@ struct rxgs_server {
     int64_t K = 0;
     int32_t H = 0, W = 0;
     int64_t slot_budget = 0;
+    // tile pairs per (view, Gaussian) the admission estimate assumes: raised
+    // to 1.25 x the largest ratio a render has shown
+    double ppg = RXGS_EST_PAIRS_PER_GAUSSIAN;
     std::thread worker;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -122,32 +127,59 @@ struct rxgs_server {
 };
 
 // ---------------------------------------------------------------------------
-extern "C" int64_t rxgs_workspace_estimate(int32_t mode, int32_t Q, int32_t N, int64_t K, int32_t H, int32_t W)
+namespace {
+
+int bits_of(uint64_t n)
 {
-    if (N <= 0) return 0;
-    const int64_t V = (mode == RXGS_MODE_TX) ? std::max(Q, 1) : N;
-    const int64_t Kp = round_up64(std::max<int64_t>(K, 1), SORT_TILE);
-    const int64_t VK = V * Kp;
-    const int64_t P = (int64_t)H * W;
-    const int64_t tiles = (int64_t)((H + TILE - 1) / TILE) * ((W + TILE - 1) / TILE);
-    const int64_t D_est = 6 * V * std::max<int64_t>(K, 1);
-    int64_t b = VK * 76;                // keys and values (ping-pong), sorted records, boxes, order, pair
-                                        // offsets, sort and emission scratch
-    b += D_est * 16;                    // pair keys and values, ping-pong
-    b += (int64_t)N * Kp * 8;           // radiance
-    b += (int64_t)N * P * 8;            // spectra
-    b += (mode == RXGS_MODE_TX ? V : N) * P * 8;   // final transmittance, stop index
-    b += (int64_t)N * tiles * 12 + V * tiles * 8;  // partial sums, ranges
-    b += std::max<int64_t>(K, 1) * (256 + 84) + (int64_t)N * 256;  // MLP layer-1 terms, projection terms
-    b += V * P * (FAR_RECORDS * 8 + 1) + V * tiles;   // far records of the radiance prefix, their counts and tile marks
-    b += VK / MLP_PAIRS * (17 + 16 * ((N + MLP_RG - 1) / MLP_RG)) + ((int64_t)1 << 20);   // work items, block marks,
-                                                                                       // counters and descriptors
+    int b = 0;
+    while ((1ull << b) < n) b++;
     return b;
 }
 
-extern "C" int32_t rxgs_plan_batch(const int32_t *n_rx, int32_t n_queued, int32_t mode, int64_t K, int32_t H,
-                                   int32_t W, int64_t budget_bytes, int32_t max_rx, int32_t max_queries,
-                                   int64_t *bytes_out)
+// Upper bound of the device bytes one render of Q queries and N receivers asks
+// for (the sum of its workspace buffer requests, as they are made in the
+// render), plus the batch's inputs and outputs, given at most `ppg` tile pairs
+// per (view, Gaussian) on average: the one quantity that depends on the scene.
+int64_t estimate_bytes(int32_t mode, int32_t Q, int32_t N, int64_t K, int32_t H, int32_t W, double ppg)
+{
+    if (N <= 0) return 0;
+    const bool tx = mode == RXGS_MODE_TX;
+    const int64_t V = tx ? std::max(Q, 1) : N;
+    const int64_t K1 = std::max<int64_t>(K, 1);
+    const int64_t Kp = round_up64(K1, SORT_TILE);
+    const int64_t VK = V * Kp;
+    const int64_t P = (int64_t)H * W;
+    const int64_t tiles = (int64_t)((H + TILE - 1) / TILE) * ((W + TILE - 1) / TILE);
+    // tile pairs, each view's segment padded to whole sort units
+    const int64_t Dpad = (int64_t)std::ceil(ppg * (double)V * (double)K1) + V * SORT_TILE;
+    const uint32_t Dsort = (uint32_t)std::min<int64_t>(Dpad, 0xFFFFFFFFll);
+    // MLP work items: per view ceil(visible / 32) x ceil(its receivers / 16),
+    // and the sum over views of ceil(N_v / 16) is at most V + N / 16
+    const int64_t items = (Kp / MLP_PAIRS) * (tx ? V + (N + MLP_RG - 1) / MLP_RG : V);
+    int64_t b = 0;
+    b += 4 * V + 12 * V + 12 * (int64_t)N;   // view flags; view centres and receivers (saved states)
+    b += 72 * VK;                             // depth keys and values (two copies), records, boxes, order, pair offsets
+    b += 84 * K1;                             // projection terms and cull bounds per Gaussian
+    b += 4 * (4 * V + AMAX_SLOTS + 2 * STAT_WORDS + (int64_t)emit_word_count((int)V, Kp) + 16);   // counters
+    b += (int64_t)sort_ws_bytes((uint32_t)std::min<int64_t>(VK, 0xFFFFFFFFll), 32, (int)V);    // depth sort
+    b += 256 * (int64_t)N + 256 * K1;         // MLP layer-1 terms of the receivers and the Gaussians
+    b += 16 * Dpad;                           // pair keys and values, two copies
+    b += (int64_t)sort_ws_bytes(Dsort, std::max(bits_of((uint64_t)tiles), 1), (int)V);   // pair sort
+    b += 12 * V * tiles;                      // tile ranges and tile order
+    b += 8 * (int64_t)N * Kp;                 // radiance
+    b += 8 * (tx ? V : (int64_t)N) * P;       // final transmittance, stop index
+    b += 12 * (int64_t)N * tiles;             // per-tile partial sums
+    b += 3 * 16 * items;                      // work items: all, the live ones, those past the prefix
+    b += 2 * (VK / MLP_PAIRS + 128);          // position-block marks (asked for by both TX paths)
+    b += V * P * (FAR_RECORDS * 8 + 1) + V * tiles;   // far records of the radiance prefix, counts, tile marks
+    b += 4 * Dpad;                            // emission-order pair keys (deterministic saved states)
+    b += 20 * (int64_t)N + 80 * V + 16 * (Dpad / SORT_TILE + 1) + 1024;   // descriptors
+    b += 12 * (int64_t)Q + 16 * (int64_t)N + 8 * (int64_t)N * P;   // transmitters, receivers, power, spectra
+    return b;
+}
+
+int32_t plan_batch(const int32_t *n_rx, int32_t n_queued, int32_t mode, int64_t K, int32_t H, int32_t W,
+                   int64_t budget_bytes, int32_t max_rx, int32_t max_queries, double ppg, int64_t *bytes_out)
 {
     int32_t take = 0;
     int64_t total = 0, bytes = 0;
@@ -155,7 +187,7 @@ extern "C" int32_t rxgs_plan_batch(const int32_t *n_rx, int32_t n_queued, int32_
         for (int32_t i = 0; i < n_queued && i < max_queries; i++) {
             const int64_t t2 = total + n_rx[i];
             if (n_rx[i] < 1 || t2 > max_rx) break;
-            const int64_t b = rxgs_workspace_estimate(mode, i + 1, (int32_t)t2, K, H, W);
+            const int64_t b = estimate_bytes(mode, i + 1, (int32_t)t2, K, H, W, ppg);
             if (b > budget_bytes) break;
             take = i + 1;
             total = t2;
@@ -163,6 +195,21 @@ extern "C" int32_t rxgs_plan_batch(const int32_t *n_rx, int32_t n_queued, int32_
         }
     if (bytes_out) *bytes_out = bytes;
     return take;
+}
+
+}  // namespace
+
+extern "C" int64_t rxgs_workspace_estimate(int32_t mode, int32_t Q, int32_t N, int64_t K, int32_t H, int32_t W)
+{
+    return estimate_bytes(mode, Q, N, K, H, W, RXGS_EST_PAIRS_PER_GAUSSIAN);
+}
+
+extern "C" int32_t rxgs_plan_batch(const int32_t *n_rx, int32_t n_queued, int32_t mode, int64_t K, int32_t H,
+                                   int32_t W, int64_t budget_bytes, int32_t max_rx, int32_t max_queries,
+                                   int64_t *bytes_out)
+{
+    return plan_batch(n_rx, n_queued, mode, K, H, W, budget_bytes, max_rx, max_queries, RXGS_EST_PAIRS_PER_GAUSSIAN,
+                      bytes_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -269,6 +316,12 @@ struct GpuExecutor final : Executor {
         return (int64_t)sl.saved->ws.req_bytes + (int64_t)sl.tickets.size() * 12 + (int64_t)sl.N * 16 +
                (int64_t)sl.N * 2 * P * 4;
     }
+
+    double pairs_per_gaussian(Slot &sl) override
+    {
+        const rxgs::Workspace &w = sl.saved->ws;
+        return (w.V > 0 && w.K > 0) ? (double)w.D / ((double)w.V * (double)w.K) : -1.0;
+    }
 };
 
 // The host executor: every batch "renders" power_j = tx.x + r.x + 2 r.y + 3 r.z
@@ -308,6 +361,7 @@ struct HostExecutor final : Executor {
     }
 
     int64_t used_bytes(rxgs_server *, Slot &) override { return -1; }
+    double pairs_per_gaussian(Slot &) override { return -1.0; }
 };
 
 // a batch that failed (at launch or on the device): the slot is made again
@@ -390,9 +444,9 @@ void worker_main(rxgs_server *s)
                 for (size_t i = 0; i < s->queue.size() && (int)i < s->opts.max_queries_per_batch; i++)
                     ns.push_back(s->tickets[s->queue[i]].n);
                 int64_t bytes = 0;
-                const int take = rxgs_plan_batch(ns.data(), (int32_t)ns.size(), s->opts.mode, s->K, s->H, s->W,
-                                                 s->slot_budget, s->opts.max_rx_per_batch,
-                                                 s->opts.max_queries_per_batch, &bytes);
+                const int take = plan_batch(ns.data(), (int32_t)ns.size(), s->opts.mode, s->K, s->H, s->W,
+                                            s->slot_budget, s->opts.max_rx_per_batch, s->opts.max_queries_per_batch,
+                                            s->ppg, &bytes);
                 if (take < 1) break;
                 std::vector<Ticket *> batch;
                 sl.tickets.clear();
@@ -426,6 +480,7 @@ void worker_main(rxgs_server *s)
                 lk.unlock();
                 const rxgs_status rs = s->exec->launch(s, sl, batch);
                 const int64_t used = rs == RXGS_OK ? s->exec->used_bytes(s, sl) : -1;
+                const double ppg = rs == RXGS_OK ? s->exec->pairs_per_gaussian(sl) : -1.0;
                 lk.lock();
                 if (rs != RXGS_OK) {
                     if (s->ctx) s->err = s->ctx->err;
@@ -434,6 +489,7 @@ void worker_main(rxgs_server *s)
                     s->st.peak_slot_bytes = std::max(s->st.peak_slot_bytes, used);
                     if (used > sl.est_bytes) s->st.over_estimate++;
                 }
+                if (ppg > 0.0) s->ppg = std::max(s->ppg, 1.25 * ppg);
                 launched = true;
             }
         }
@@ -558,7 +614,7 @@ extern "C" rxgs_status rxgs_server_submit(rxgs_server *s, const float *tx, int32
         if (!std::isfinite(tx[i])) return RXGS_E_INVALID;
     for (int64_t i = 0; i < 3 * (int64_t)n; i++)
         if (!std::isfinite(rx_host[i])) return RXGS_E_INVALID;
-    if (rxgs_workspace_estimate(s->opts.mode, 1, n, s->K, s->H, s->W) > s->slot_budget) {
+    if (estimate_bytes(s->opts.mode, 1, n, s->K, s->H, s->W, s->ppg) > s->slot_budget) {
         std::lock_guard<std::mutex> lk(s->mu);
         s->st.rejected++;
         return RXGS_E_INVALID;

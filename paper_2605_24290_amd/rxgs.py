@@ -79,6 +79,10 @@ class CStageTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", c_int64), ("total_ms", c_double)]
 
 
+class CWorkCounts(ctypes.Structure):
+    _fields_ = [("mlp_items", c_int64), ("mlp_pairs", c_int64), ("mlp_slots", c_int64)]
+
+
 class CRxCondDesc(ctypes.Structure):
     _fields_ = [("basis", c_int32), ("lmax", c_int32), ("channels", c_int32), ("bands", c_int32),
                 ("hidden", c_int32), ("probes", c_int32), ("grid", c_int32), ("reserved", c_int32)]
@@ -96,7 +100,7 @@ FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, ctypes.c_size_t, c_int, c_void_p)
 EXPORTED = ("rxgs_create", "rxgs_create_with_allocator", "rxgs_destroy", "rxgs_last_error", "rxgs_scene_upload", "rxgs_mlp_upload",
             "rxgs_saved_create", "rxgs_saved_destroy", "rxgs_render", "rxgs_render_backward",
             "rxgs_saved_info", "rxgs_saved_export", "rxgs_version", "rxgs_profile_enable",
-            "rxgs_profile_read", "rxgs_server_start", "rxgs_server_submit", "rxgs_server_poll",
+            "rxgs_profile_read", "rxgs_profile_counts", "rxgs_server_start", "rxgs_server_submit", "rxgs_server_poll",
             "rxgs_server_cancel", "rxgs_server_stats", "rxgs_server_stop", "rxgs_plan_batch",
             "rxgs_workspace_estimate", "rxgs_set_near_cut", "rxgs_views_redone", "rxgs_render_chunked",
             "rxgs_view_flags", "rxgs_rxcond_param_count", "rxgs_rxcond_upload", "rxgs_render_rxcond",
@@ -171,6 +175,8 @@ def lib():
     L.rxgs_rxcond_export.restype = c_int
     L.rxgs_profile_enable.argtypes = [vp, c_int]
     L.rxgs_profile_read.argtypes = [vp, POINTER(CStageTime), c_int, POINTER(c_int), c_int]
+    L.rxgs_profile_counts.argtypes = [vp, POINTER(CWorkCounts), c_int, vp]
+    L.rxgs_profile_counts.restype = c_int
     for name in ("rxgs_create", "rxgs_scene_upload", "rxgs_mlp_upload", "rxgs_saved_create", "rxgs_render",
                  "rxgs_saved_info", "rxgs_saved_export", "rxgs_profile_enable", "rxgs_profile_read"):
         getattr(L, name).restype = c_int
@@ -499,6 +505,13 @@ class Renderer:
         n = c_int(0)
         _check(lib().rxgs_profile_read(self._ctx, buf, 64, byref(n), 1 if reset else 0), self._ctx)
         return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(min(n.value, 64))}
+
+    def profile_counts(self, reset: bool = True) -> dict:
+        """Device-counted MLP work of the profiled renders since the last reset
+        (rxgs_profile_counts): items, (receiver, position) pairs, 32-slot pairs."""
+        c = CWorkCounts()
+        _check(lib().rxgs_profile_counts(self._ctx, byref(c), 1 if reset else 0, self._stream()), self._ctx)
+        return {"mlp_items": int(c.mlp_items), "mlp_pairs": int(c.mlp_pairs), "mlp_slots": int(c.mlp_slots)}
 
     def close(self):
         if getattr(self, "_ctx", None) is not None:

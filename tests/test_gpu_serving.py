@@ -139,3 +139,35 @@ def test_allocator_failure_fails_one_batch_only():
     assert st["failed"] == 1 and st["over_estimate"] == 0
     srv.stop()
     r.close()
+
+
+@pytest.mark.parametrize("mode", ["tx", "rx"])
+def test_workspace_estimate_bounds_a_render(mode):
+    """rxgs_workspace_estimate bounds the device bytes a render asks for (its
+    workspace requests, as rxgs_saved_info reports them, plus inputs and
+    outputs) on the serving scene at full size, for saved states (which keep
+    what the backward needs) and given the render's own tile-pair ratio."""
+    import torch
+    from paper_2605_24290_amd import rxgs
+    wl = S.make_workload("c3", K=200_000, N=48, Q=3)
+    r = renderer_for(wl)
+    H, W = wl.grid.H, wl.grid.W
+    rx_off = [0, 16, 40, 48]
+    Q = 3 if mode == "tx" else 1
+    saved = rxgs.Saved(r)
+    if mode == "tx":
+        r.render(wl.rx, tx=wl.tx, rx_off=rx_off, mode=mode, saved=saved)
+    else:
+        r.render(wl.rx, tx=wl.tx[:1], mode=mode, saved=saved)
+    torch.cuda.synchronize()
+    info = saved.info()
+    N, K = 48, wl.scene.K
+    io = 12 * Q + 16 * N + 8 * N * H * W
+    est = rxgs.lib().rxgs_workspace_estimate(rxgs.MODE_TX if mode == "tx" else rxgs.MODE_RX, Q, N, K, H, W)
+    ppg = info["D"] / (info["V"] * K)
+    print(f"[estimate] {mode}: asked {info['workspace_bytes'] + io} B, estimate {est} B "
+          f"({est / (info['workspace_bytes'] + io):.2f}x), tile pairs per (view, Gaussian) {ppg:.2f}")
+    assert ppg <= 8.0
+    assert info["workspace_bytes"] + io <= est
+    saved.close()
+    r.close()
