@@ -1268,8 +1268,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3, 3))) v
 // (TX chunks) the walk is bound by broadcasting their radiance from LDS, and
 // the shared per-entry form below serves better (k_blend_fwd_multi).
 
-// entries per staged batch (five workgroups per CU)
-constexpr int NB1 = BLOCK / 2;
+// list entries a wave scans per step (one per lane)
+constexpr int BW_CH = 64;
 
 // Far entries of the radiance prefix path: a lane that composites an entry
 // past the prefix (its radiance not yet evaluated) records (T w, sorted
@@ -1284,151 +1284,29 @@ struct FarState {
     uint8_t *mark;   // per block of MLP_PAIRS sorted positions: a record points into it
 };
 
-template <int NB> struct BlendFwdStage {
-    float4 q[4][NB][2];              // per wave, in list order
-    float4 r0[NB];                   // the batch's records (azimuth shifted near the tile)
-    float4 r1[NB];
-    float2 rad[NB];                  // and radiance
-    uint32_t p[NB];                  // and sorted positions
-    unsigned short list[4][NB];      // per wave: batch index of each entry
-    int len[4];
-    int wcnt[4][4];
-    int ncnt[4][4];                  // per source wave and sub-tile: entries below the position prefix
-    int wide[4];
+// Per wave, the records of the entries of one step of the tile list that can
+// reach its sub-tile, in list order (padded with zero-weight records to a
+// multiple of 4), their sorted positions and their indices in the tile list.
+struct BlendWaveStage {
+    float4 q[4][BW_CH + 4][2];
+    uint32_t p[4][BW_CH + 4];
+    unsigned short idx[4][BW_CH + 4];
 };
 
-// Conservative sub-tile mask of one record (the hardware reciprocal and square
-// root, with a relative margin far above their error): bit w set when the box
-// around the ellipse {E >= log2(1/255)} meets wave w's 8 x 8 sub-tile.
-__device__ __forceinline__ int subtile_mask_fast(const float4 &r0, const float4 &r1, int wide, int tx, int ty)
-{
-    if (wide) return 0xF;
-    float lo = r1.w - (-7.99435343685886f);   // log2 o - log2(1/255)
-    if (!(lo >= -1e-3f)) return 0;
-    lo = fmaxf(lo, 0.f) + 1e-3f;
-    const float muu = -r1.x, muv = -0.5f * r1.y, mvv = -r1.z;
-    const float det = muu * mvv - muv * muv;
-    if (!(det > 0.f)) return 0xF;
-    const float q = lo * __builtin_amdgcn_rcpf(det);
-    const float ru = __builtin_amdgcn_sqrtf(q * mvv) * 1.001f + 0.05f;
-    const float rv = __builtin_amdgcn_sqrtf(q * muu) * 1.001f + 0.05f;
-    const float u = r0.x + r0.y, v = r0.z + r0.w;
-    const float c0 = (float)(tx * TILE), r0f = (float)(ty * TILE);
-    int m = 0;
-#pragma unroll
-    for (int w = 0; w < 4; w++) {
-        const float cl = c0 + 8.f * (float)(w & 1), rl = r0f + 8.f * (float)(w >> 1);
-        const bool hit = (u + ru >= cl) && (u - ru <= cl + 7.f) && (v + rv >= rl) && (v - rv <= rl + 7.f);
-        m |= hit ? (1 << w) : 0;
-    }
-    return m;
-}
-
-// Stage one batch (this thread's entry, if `has`, with its radiance rv).  All
-// threads of the workgroup call it.  First every entry is tested against the
-// four sub-tiles and the per-wave lists are built (ballots and prefix counts);
-// then each wave turns its own list into records, one entry per lane, so no
-// lane computes records for sub-tiles other waves need.  On return st.len,
-// st.wide and the records of every wave are final (lists padded with
-// zero-weight records to a multiple of 4).
-template <int NB>
-__device__ __forceinline__ void stage_fwd(BlendFwdStage<NB> &st, const float4 *__restrict__ srec, uint32_t p, bool has,
-                                          float2 rv, int tx, int ty, const DevGrid &g, float invW, bool nearp)
-{
-    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    int m = 0, wide = 0;
-    const float Wf = (float)g.W, halfW = 0.5f * (float)g.W;
-    if (has) {
-        float4 r0 = srec[2 * (size_t)p];
-        const float4 r1 = srec[2 * (size_t)p + 1];
-        const float tcol = (float)(tx * TILE) + 7.5f;
-        // representative of the azimuth closest to this tile's centre (the
-        // box of a non-wide entry in this tile's list keeps its centre well
-        // inside half a circle of it, so the rounding of the quotient cannot
-        // change the choice)
-        const float sh = rintf((tcol - r0.x) * invW);
-        r0.x = fmaf(sh, Wf, r0.x);
-        wide = fabsf(tcol - (r0.x + r0.y)) >= halfW - 9.0f;
-        m = subtile_mask_fast(r0, r1, wide, tx, ty);
-        st.r0[t] = r0;
-        st.r1[t] = r1;
-        st.rad[t] = rv;
-        st.p[t] = p;
-    }
-    uint64_t bal[4], nbal[4];
-#pragma unroll
-    for (int b = 0; b < 4; b++) {
-        bal[b] = __ballot((m >> b) & 1);
-        nbal[b] = __ballot(((m >> b) & 1) && nearp);
-    }
-    const uint64_t wide_bal = __ballot(wide);
-    if (lane == 0) {
-#pragma unroll
-        for (int b = 0; b < 4; b++) {
-            st.wcnt[w][b] = (int)__popcll(bal[b]);
-            st.ncnt[w][b] = (int)__popcll(nbal[b]);
-        }
-        st.wide[w] = wide_bal ? 1 : 0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < 4; b++) {
-        if ((m >> b) & 1) {
-            int pos = count_below(bal[b]);
-            for (int ww = 0; ww < w; ww++) pos += st.wcnt[ww][b];
-            st.list[b][pos] = (unsigned short)t;
-        }
-    }
-    const bool anywide = (st.wide[0] | st.wide[1] | st.wide[2] | st.wide[3]) != 0;
-    const int n = st.wcnt[0][w] + st.wcnt[1][w] + st.wcnt[2][w] + st.wcnt[3][w];
-    if (lane == 0) st.len[w] = n;
-    __syncthreads();
-    // this wave's records (its sub-tile's centre: colc, rowc)
-    const float colc = (float)(tx * TILE + 8 * (w & 1)) + 3.5f;
-    const float rowc = (float)(ty * TILE + 8 * (w >> 1)) + 3.5f;
-    const int np = (n + 3) & ~3;
-    for (int i = lane; i < np; i += 64) {
-        float4 q0, q1;
-        if (i < n) {
-            const int e = st.list[w][i];
-            const float4 r0 = st.r0[e], r1 = st.r1[e];
-            const float2 re = st.rad[e];
-            const float a = r1.x, bb = r1.y, c = r1.z;
-            const float du0 = (colc - r0.x) - r0.y;
-            const float dv0 = (rowc - r0.z) - r0.w;
-            if (anywide) {
-                q0 = make_float4(du0, dv0, r1.w, a);
-            } else {
-                const float e0 = fmaf(du0, fmaf(a, du0, bb * dv0), fmaf(c * dv0, dv0, r1.w));
-                q0 = make_float4(e0, fmaf(2.f * a, du0, bb * dv0), fmaf(bb, du0, 2.f * c * dv0), a);
-            }
-            q1 = make_float4(bb, c, re.x, re.y);
-        } else {
-            // zero-weight padding: E = -inf in either form (only the constant
-            // term is infinite, so no product of infinity and zero arises)
-            q0 = anywide ? make_float4(0.f, 0.f, -INFINITY, 0.f) : make_float4(-INFINITY, 0.f, 0.f, 0.f);
-            q1 = make_float4(0.f, 0.f, 0.f, 0.f);
-            st.list[w][i] = 0;
-        }
-        st.q[w][i][0] = q0;
-        st.q[w][i][1] = q1;
-    }
-    __syncthreads();
-}
-
-// One wave's walk over its staged list (length n, padded to a multiple of
-// 4, four entries in flight), free of branches per entry: an entry below the
-// alpha threshold, or met after the lane terminated, gets weight 0, which
-// leaves T and the sums unchanged.  WRAP: the list is in the wrapped form.
-// SAVE: track the stop index and the composited count (saved states and
-// statistics only).  DETECT: record every entry at list index i_far or later
-// that the lane composites (FarState).
-template <bool SAVE, bool WRAP, bool DETECT = false, int NB>
-__device__ __forceinline__ void blend_walk1(const BlendFwdStage<NB> &st, int wv, int n, int lbase, float X, float Y,
-                                            float XX, float XY, float YY, float Wf, float halfW, float &T,
-                                            float2 &acc, int &last, uint32_t &ncomp, uint32_t &neval,
-                                            uint32_t &nslot, bool &done, int i_begin = 0, int i_far = 0,
-                                            uint2 *myrec = nullptr, int *fcount = nullptr, uint8_t *mark = nullptr)
+// One wave's walk over its staged records (n real ones, padded to a multiple
+// of 4, four entries in flight), free of branches per entry: an entry below
+// the alpha threshold, or met after the lane terminated, gets weight 0, which
+// leaves T and the sums unchanged.  WRAP: the records are in the wrapped
+// form.  CLAMP: some entry may reach the 0.99 weight cap.  SAVE: track the
+// stop index and the composited count (saved states and statistics only).
+// DETECT: record every entry at index i_far or later that the lane
+// composites (FarState).
+template <bool SAVE, bool WRAP, bool CLAMP, bool DETECT = false>
+__device__ __forceinline__ void blend_walk1(const BlendWaveStage &st, int wv, int n, float X, float Y, float XX,
+                                            float XY, float YY, float Wf, float halfW, float &T, float2 &acc,
+                                            int &last, uint32_t &ncomp, uint32_t &neval, uint32_t &nslot, bool &done,
+                                            int i_begin = 0, int i_far = 0, uint2 *myrec = nullptr,
+                                            int *fcount = nullptr, uint8_t *mark = nullptr)
 {
     for (int i0 = i_begin; i0 < n; i0 += 4) {
 #pragma unroll
@@ -1451,7 +1329,10 @@ __device__ __forceinline__ void blend_walk1(const BlendFwdStage<NB> &st, int wv,
             } else {
                 ex = fmaf(q1.y, YY, fmaf(q1.x, XY, fmaf(q0.w, XX, fmaf(q0.z, Y, fmaf(q0.y, X, q0.x)))));
             }
-            float w = fminf(W_MAX, __builtin_amdgcn_exp2f(ex));
+            // (without CLAMP no entry of the list has log2 o >= log2 0.99, so
+            // the weight is below the cap everywhere)
+            float w = __builtin_amdgcn_exp2f(ex);
+            if (CLAMP) w = fminf(W_MAX, w);
             const bool inc = !done && w >= ALPHA_MIN;
             w = inc ? w : 0.f;
             const float tw = T * w;
@@ -1459,12 +1340,12 @@ __device__ __forceinline__ void blend_walk1(const BlendFwdStage<NB> &st, int wv,
             acc.y = fmaf(tw, q1.w, acc.y);
             T = T - tw;
             if (SAVE) {
-                last = inc ? lbase + (int)st.list[wv][i] : last;
+                last = inc ? (int)st.idx[wv][i] + 1 : last;
                 ncomp += inc ? 1u : 0u;
             }
             if (DETECT && inc && i >= i_far) {
                 if (*fcount < FAR_REC && myrec) {
-                    const uint32_t pe = st.p[st.list[wv][i]];
+                    const uint32_t pe = st.p[wv][i];
                     myrec[*fcount] = make_uint2(__float_as_uint(tw), pe);
                     mark[pe / MLP_PAIRS] = 1;
                 }
@@ -1476,10 +1357,37 @@ __device__ __forceinline__ void blend_walk1(const BlendFwdStage<NB> &st, int wv,
     }
 }
 
+template <bool SAVE, bool WRAP, bool CLAMP>
+__device__ __forceinline__ void blend_walk1_far(const BlendWaveStage &st, int wv, int n, int i_far, float X, float Y,
+                                                float XX, float XY, float YY, float Wf, float halfW, float &T,
+                                                float2 &acc, int &last, uint32_t &ncomp, uint32_t &neval,
+                                                uint32_t &nslot, bool &done, uint2 *myrec, int *fcount, uint8_t *mark)
+{
+    // entries below the position prefix first (the tile list is in depth
+    // order), then the rest with the far-entry records
+    const int i4 = i_far & ~3;
+    blend_walk1<SAVE, WRAP, CLAMP>(st, wv, min(n, i4), X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
+                                   nslot, done);
+    if (i4 < n && __any(!done))
+        blend_walk1<SAVE, WRAP, CLAMP, true>(st, wv, n, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
+                                             nslot, done, i4, i_far, myrec, fcount, mark);
+}
+
 // SECOND: the prefix path's second launch (its own instantiation, so that
 // profiles tell the two launches apart).
+//
+// Each wave walks its 8 x 8 sub-tile on its own, with no workgroup barrier
+// until the end: per step, lane l takes entry l of the next 64 of the tile
+// list and tests the entry's binning box (the box the tile binning used, so
+// every pixel the entry can reach lies in it) against the wave's sub-tile;
+// the lanes of the entries that hit build their records (exponent as the
+// quadratic around the sub-tile centre, or the wrapped form when an entry
+// of the step spans more than half the azimuth circle) into the wave's LDS
+// slice in list order (ballot and lane count), and the wave walks them.  A
+// wave stops at the first step after all its lanes terminated.
 template <bool SAVE, bool SECOND = false>
 __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__ srec,
+                                                      const float4 *__restrict__ sbox,
                                                       const uint32_t *__restrict__ pval,
                                                       const uint2 *__restrict__ ranges,
                                                       const float2 *__restrict__ rad,
@@ -1487,13 +1395,13 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
                                                       float *__restrict__ C, float *__restrict__ Tfin,
                                                       int *__restrict__ nlast, float *__restrict__ part,
                                                       unsigned long long *__restrict__ stats,
-                                                     const uint32_t *__restrict__ torder,
-                                                     uint32_t *__restrict__ vflag, uint32_t mpos, FarState fs)
+                                                      const uint32_t *__restrict__ torder,
+                                                      uint32_t *__restrict__ vflag, uint32_t mpos, FarState fs)
 {
-    constexpr int NB = NB1;
     constexpr bool redo = SECOND;
-    __shared__ BlendFwdStage<NB> st;
+    __shared__ BlendWaveStage st;
     __shared__ float s_red[4][3];
+    __shared__ uint32_t s_cnt[3][4];
 
     // grid: (chunk, rank of the tile in its view's longest-first order)
     const int4 ch = chunks[blockIdx.x];
@@ -1518,6 +1426,11 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
     const float Wf = (float)g.W, halfW = 0.5f * (float)g.W, invW = 1.0f / (float)g.W;
     const uint2 rg = ranges[(size_t)view * g.tiles + tile];
     const int64_t view_end = ((int64_t)view + 1) * Kp;
+    // this wave's sub-tile: first column and row, centre; the tile's centre column
+    const float cl = (float)(tx * TILE + 8 * (wv & 1)), rl = (float)(ty * TILE + 8 * (wv >> 1));
+    const float colc = cl + 3.5f, rowc = rl + 3.5f;
+    const float tcol = (float)(tx * TILE) + 7.5f;
+    const float allcols = 0.5f * (float)(g.W - TILE - 2);   // a box this wide takes every tile column
 
     float T = 1.f;
     float2 acc = make_float2(0.f, 0.f);
@@ -1547,43 +1460,103 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
             }
         }
     }
-    for (uint32_t base = rg.x; !deferred && base < rg.y; base += NB) {
-        const uint32_t cnt = min((uint32_t)NB, rg.y - base);
-        __syncthreads();
+    for (uint32_t base = rg.x; !deferred && base < rg.y; base += BW_CH) {
+        if (__all(done)) break;   // uniform across the wave
+        const uint32_t i = base + (uint32_t)lane;
         uint32_t p = 0;
-        float2 rv = make_float2(0.f, 0.f);
-        bool nearp = true;
-        if ((uint32_t)t < cnt) {
-            p = min(pval[base + t], (uint32_t)(view_end - 1));
-            const int64_t s = max((int64_t)p - (int64_t)view * Kp, (int64_t)0);
-            nearp = s < (int64_t)mpos;
-            if (nearp) rv = rad[(size_t)j0 * Kp + s];
+        bool hit = false, wide = false;
+        if (i < rg.y) {
+            p = min(pval[i], (uint32_t)(view_end - 1));
+            const float4 b = sbox[p];   // (u, v, padded half-extents)
+            const float u = fmaf(rintf((tcol - b.x) * invW), Wf, b.x);   // azimuth nearest the tile
+            wide = fabsf(tcol - u) >= halfW - 9.0f;
+            const bool colhit = b.z >= allcols || (u + b.z >= cl && u - b.z <= cl + 7.f);
+            const bool rowhit = b.y + b.w >= rl && b.y - b.w <= rl + 7.f;
+            hit = wide || (colhit && rowhit);
         }
-        stage_fwd<NB>(st, srec, p, (uint32_t)t < cnt, rv, tx, ty, g, invW, nearp);
-        if (__any(!done)) {
-            const int n = __builtin_amdgcn_readfirstlane(st.len[wv]);
-            const int lbase = (int)(base - rg.x) + 1;
-            // list entries below the position prefix come first (the tile list is in depth order)
-            const int i_far = __builtin_amdgcn_readfirstlane(st.ncnt[0][wv] + st.ncnt[1][wv] + st.ncnt[2][wv] +
-                                                             st.ncnt[3][wv]);
-            const int i4 = i_far & ~3;
-            const bool wide = st.wide[0] | st.wide[1] | st.wide[2] | st.wide[3];
-            if (wide)
-                blend_walk1<SAVE, true>(st, wv, min(n, i4), lbase, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp,
-                                        neval, nslot, done);
-            else
-                blend_walk1<SAVE, false>(st, wv, min(n, i4), lbase, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp,
-                                         neval, nslot, done);
-            if (i4 < n && __any(!done)) {
-                if (wide)
-                    blend_walk1<SAVE, true, true>(st, wv, n, lbase, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp,
-                                                  neval, nslot, done, i4, i_far, myrec, &fcount, fs.mark);
-                else
-                    blend_walk1<SAVE, false, true>(st, wv, n, lbase, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp,
-                                                   neval, nslot, done, i4, i_far, myrec, &fcount, fs.mark);
+        const int64_t s = (int64_t)p - (int64_t)view * Kp;
+        const bool nearp = s < (int64_t)mpos;
+        const uint64_t hb = __ballot(hit);
+        const int n = __popcll(hb);
+        if (n == 0) continue;
+        const bool anywide = __ballot(hit && wide) != 0;
+        const int n_near = __popcll(__ballot(hit && nearp));
+        // log2 o of some entry at or above log2 0.99 (the weight cap may apply)
+        bool capped = false;
+        if (hit) {
+            const int pos = count_below(hb);
+            float4 r0 = srec[2 * (size_t)p];
+            const float4 r1 = srec[2 * (size_t)p + 1];
+            const float2 re = nearp ? rad[(size_t)j0 * Kp + s] : make_float2(0.f, 0.f);
+            // representative of the azimuth closest to the tile's centre
+            r0.x = fmaf(rintf((tcol - r0.x) * invW), Wf, r0.x);
+            const float a = r1.x, bb = r1.y, c = r1.z;
+            const float du0 = (colc - r0.x) - r0.y;
+            const float dv0 = (rowc - r0.z) - r0.w;
+            float4 q0;
+            if (anywide) {
+                q0 = make_float4(du0, dv0, r1.w, a);
+            } else {
+                const float e0 = fmaf(du0, fmaf(a, du0, bb * dv0), fmaf(c * dv0, dv0, r1.w));
+                q0 = make_float4(e0, fmaf(2.f * a, du0, bb * dv0), fmaf(bb, du0, 2.f * c * dv0), a);
             }
+            capped = r1.w >= LOG2_W_MAX;
+            st.q[wv][pos][0] = q0;
+            st.q[wv][pos][1] = make_float4(bb, c, re.x, re.y);
+            st.p[wv][pos] = p;
+            if (SAVE) st.idx[wv][pos] = (unsigned short)(i - rg.x);
         }
-        if (__syncthreads_and(done ? 1 : 0)) break;
+        const bool clamp = __ballot(capped) != 0;
+        // zero-weight padding to a multiple of 4: E = -inf in either form
+        // (only the constant term is infinite, so no product of infinity and
+        // zero arises)
+        const int np = (n + 3) & ~3;
+        if (lane >= n && lane < np) {
+            st.q[wv][lane][0] = anywide ? make_float4(0.f, 0.f, -INFINITY, 0.f) : make_float4(-INFINITY, 0.f, 0.f, 0.f);
+            st.q[wv][lane][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            st.p[wv][lane] = 0;
+            if (SAVE) st.idx[wv][lane] = 0;
+        }
+        // the wave reads what its own lanes wrote (LDS operations of one wave
+        // complete in order)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (n_near < n) {
+            if (anywide) {
+                if (clamp)
+                    blend_walk1_far<SAVE, true, true>(st, wv, n, n_near, X, Y, XX, XY, YY, Wf, halfW, T, acc, last,
+                                                      ncomp, neval, nslot, done, myrec, &fcount, fs.mark);
+                else
+                    blend_walk1_far<SAVE, true, false>(st, wv, n, n_near, X, Y, XX, XY, YY, Wf, halfW, T, acc, last,
+                                                       ncomp, neval, nslot, done, myrec, &fcount, fs.mark);
+            } else {
+                if (clamp)
+                    blend_walk1_far<SAVE, false, true>(st, wv, n, n_near, X, Y, XX, XY, YY, Wf, halfW, T, acc, last,
+                                                       ncomp, neval, nslot, done, myrec, &fcount, fs.mark);
+                else
+                    blend_walk1_far<SAVE, false, false>(st, wv, n, n_near, X, Y, XX, XY, YY, Wf, halfW, T, acc, last,
+                                                        ncomp, neval, nslot, done, myrec, &fcount, fs.mark);
+            }
+        } else if (anywide) {
+            if (clamp)
+                blend_walk1<SAVE, true, true>(st, wv, n, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
+                                              nslot, done);
+            else
+                blend_walk1<SAVE, true, false>(st, wv, n, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
+                                               nslot, done);
+        } else {
+            if (clamp)
+                blend_walk1<SAVE, false, true>(st, wv, n, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
+                                               nslot, done);
+            else
+                blend_walk1<SAVE, false, false>(st, wv, n, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
+                                                nslot, done);
+        }
+        // the next step overwrites the slice only after this walk read it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (!redo) {
         // a pixel still open at the end of a view's truncated list: the view is redone in full
@@ -1622,9 +1595,9 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
     if (SAVE) {
         const uint32_t nc = wave_sum_u32(ncomp), ne = wave_sum_u32(neval), ns = wave_sum_u32(nslot);
         if (lane == 0) {
-            st.wcnt[0][wv] = (int)nc;
-            st.wcnt[1][wv] = (int)ne;
-            st.wcnt[2][wv] = (int)ns;
+            s_cnt[0][wv] = nc;
+            s_cnt[1][wv] = ne;
+            s_cnt[2][wv] = ns;
         }
     }
     __syncthreads();
@@ -1639,7 +1612,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
         unsigned long long n[3];
 #pragma unroll
         for (int c = 0; c < 3; c++)
-            n[c] = (unsigned long long)st.wcnt[c][0] + st.wcnt[c][1] + st.wcnt[c][2] + st.wcnt[c][3];
+            n[c] = (unsigned long long)s_cnt[c][0] + s_cnt[c][1] + s_cnt[c][2] + s_cnt[c][3];
         if (n[0]) {
             atomicAdd(stats + slot, n[0]);
             atomicAdd(stats + STAT_SLOTS + slot, n[0] * (unsigned long long)nrx);
@@ -2271,17 +2244,17 @@ static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st, boo
     if constexpr (R == 1) {
         if (save)
             hipLaunchKernelGGL((k_blend_fwd1<true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
-                               ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
+                               ws.sbox.as<float4>(), ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
                                ws.part.as<float>(), stat_words(ws), tord, ws.vflag.as<uint32_t>(), mpos, fs);
         else if (redo)
             hipLaunchKernelGGL((k_blend_fwd1<false, true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
-                               ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
+                               ws.sbox.as<float4>(), ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord,
                                ws.vflag.as<uint32_t>(), mpos, fs);
         else
             hipLaunchKernelGGL((k_blend_fwd1<false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
-                               ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
+                               ws.sbox.as<float4>(), ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord,
                                ws.vflag.as<uint32_t>(), mpos, fs);
     } else {

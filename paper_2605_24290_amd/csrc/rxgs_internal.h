@@ -38,6 +38,10 @@ constexpr int EM2_CHUNK = BLOCK * EM2_PER;
 // Method constants (Alg. 1 compositing and the readings of its unstated values).
 constexpr float ALPHA_MIN = 1.0f / 255.0f;   // skip threshold on the blend weight
 constexpr float W_MAX = 0.99f;               // blend weight clamp
+// log2 o at or above which an entry's blend weight may reach the clamp: its
+// exponent peaks at log2 o, and this sits 0.035 below log2 0.99 (= -0.0145),
+// far above the FP32 error of the exponent
+constexpr float LOG2_W_MAX = -0.05f;
 constexpr float T_EPS = 1e-4f;               // early-termination transmittance
 constexpr double DILATE = 0.3;               // px^2 added to the projected covariance
 constexpr float NEAR2 = 0.04f;               // cull Gaussians closer than 0.2 m
