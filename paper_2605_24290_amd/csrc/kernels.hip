@@ -1288,77 +1288,101 @@ struct FarState {
 // reach its sub-tile, in list order (padded with zero-weight records to a
 // multiple of 4), their sorted positions and their indices in the tile list.
 struct BlendWaveStage {
-    float4 q[4][BW_CH + 4][2];
-    uint32_t p[4][BW_CH + 4];
-    unsigned short idx[4][BW_CH + 4];
+    float4 q[1][BW_CH + 4][2];           // (E0, gx, gy, a), (b, c, radiance)
+    float4 qw[1][BW_CH + 4];             // offset form: (du0, dv0, log2 o, -)
+    uint32_t p[1][BW_CH + 4];
+    unsigned short idx[1][BW_CH + 4];
+    uint32_t wf[1][(BW_CH + 4) / 4];     // one byte per entry: it needs the wrapped form
 };
 
-// One wave's walk over its staged records (n real ones, padded to a multiple
-// of 4, four entries in flight), free of branches per entry: an entry below
+// Four entries of one wave's walk, free of branches per entry: an entry below
 // the alpha threshold, or met after the lane terminated, gets weight 0, which
-// leaves T and the sums unchanged.  WRAP: the records are in the wrapped
-// form.  CLAMP: some entry may reach the 0.99 weight cap.  SAVE: track the
-// stop index and the composited count (saved states and statistics only).
-// DETECT: record every entry at index i_far or later that the lane
-// composites (FarState).
-template <bool SAVE, bool WRAP, bool CLAMP, bool DETECT = false>
-__device__ __forceinline__ void blend_walk1(const BlendWaveStage &st, int wv, int n, float X, float Y, float XX,
-                                            float XY, float YY, float Wf, float halfW, float &T, float2 &acc,
-                                            int &last, uint32_t &ncomp, uint32_t &neval, uint32_t &nslot, bool &done,
-                                            int i_begin = 0, int i_far = 0, uint2 *myrec = nullptr,
-                                            int *fcount = nullptr, uint8_t *mark = nullptr)
+// leaves T and the sums unchanged.  WRAP: the offset form, each pixel's
+// azimuth offset wrapped into [-W/2, W/2); else the quadratic form.  CLAMP:
+// some entry may reach the 0.99 weight cap.  SAVE: track the stop index and
+// the composited count (saved states and statistics only).  DETECT: record
+// every entry at index i_far or later that the lane composites (FarState).
+template <bool SAVE, bool WRAP, bool CLAMP, bool DETECT>
+__device__ __forceinline__ void blend_group4(const BlendWaveStage &st, int wv, int i0, int n, float X, float Y,
+                                             float XX, float XY, float YY, float Wf, float halfW, float &T,
+                                             float2 &acc, int &last, uint32_t &ncomp, uint32_t &neval,
+                                             uint32_t &nslot, bool &done, int i_far, uint2 *myrec, int *fcount,
+                                             uint8_t *mark)
+{
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int i = i0 + k;
+        if (SAVE) {
+            const bool real = i < n;
+            neval += (real && !done) ? 1u : 0u;
+            nslot += real ? 1u : 0u;
+        }
+        const float4 q0 = st.q[wv][i][0];
+        const float4 q1 = st.q[wv][i][1];
+        float ex;
+        if (WRAP) {
+            const float4 qw = st.qw[wv][i];
+            float du = qw.x + X;
+            du = du >= halfW ? du - Wf : du;
+            du = du < -halfW ? du + Wf : du;
+            const float dv = qw.y + Y;
+            ex = fmaf(du, fmaf(q0.w, du, q1.x * dv), fmaf(q1.y * dv, dv, qw.z));
+        } else {
+            ex = fmaf(q1.y, YY, fmaf(q1.x, XY, fmaf(q0.w, XX, fmaf(q0.z, Y, fmaf(q0.y, X, q0.x)))));
+        }
+        // (without CLAMP no entry of the list has log2 o >= LOG2_W_MAX, so the
+        // weight is below the cap everywhere)
+        float w = __builtin_amdgcn_exp2f(ex);
+        if (CLAMP) w = fminf(W_MAX, w);
+        const bool inc = !done && w >= ALPHA_MIN;
+        w = inc ? w : 0.f;
+        const float tw = T * w;
+        acc.x = fmaf(tw, q1.z, acc.x);
+        acc.y = fmaf(tw, q1.w, acc.y);
+        T = T - tw;
+        if (SAVE) {
+            last = inc ? (int)st.idx[wv][i] + 1 : last;
+            ncomp += inc ? 1u : 0u;
+        }
+        if (DETECT && inc && i >= i_far) {
+            if (*fcount < FAR_REC && myrec) {
+                const uint32_t pe = st.p[wv][i];
+                myrec[*fcount] = make_uint2(__float_as_uint(tw), pe);
+                mark[pe / MLP_PAIRS] = 1;
+            }
+            ++*fcount;
+        }
+        done = done || T < T_EPS;
+    }
+}
+
+// One wave's walk over its staged records (n real ones, padded to a multiple
+// of 4), four entries in flight.  MIXED: some entry needs the wrapped form
+// (bit i of wmask for record i); each group of four that holds one is
+// evaluated in the offset form, the others in the quadratic form (a branch
+// uniform across the wave).
+template <bool SAVE, bool MIXED, bool CLAMP, bool DETECT = false>
+__device__ __forceinline__ void blend_walk1(const BlendWaveStage &st, int wv, int n, uint64_t wmask, float X, float Y,
+                                            float XX, float XY, float YY, float Wf, float halfW, float &T,
+                                            float2 &acc, int &last, uint32_t &ncomp, uint32_t &neval,
+                                            uint32_t &nslot, bool &done, int i_begin = 0, int i_far = 0,
+                                            uint2 *myrec = nullptr, int *fcount = nullptr, uint8_t *mark = nullptr)
 {
     for (int i0 = i_begin; i0 < n; i0 += 4) {
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const int i = i0 + k;
-            if (SAVE) {
-                const bool real = i < n;
-                neval += (real && !done) ? 1u : 0u;
-                nslot += real ? 1u : 0u;
-            }
-            const float4 q0 = st.q[wv][i][0];
-            const float4 q1 = st.q[wv][i][1];
-            float ex;
-            if (WRAP) {
-                float du = q0.x + X;
-                du = du >= halfW ? du - Wf : du;
-                du = du < -halfW ? du + Wf : du;
-                const float dv = q0.y + Y;
-                ex = fmaf(du, fmaf(q0.w, du, q1.x * dv), fmaf(q1.y * dv, dv, q0.z));
-            } else {
-                ex = fmaf(q1.y, YY, fmaf(q1.x, XY, fmaf(q0.w, XX, fmaf(q0.z, Y, fmaf(q0.y, X, q0.x)))));
-            }
-            // (without CLAMP no entry of the list has log2 o >= log2 0.99, so
-            // the weight is below the cap everywhere)
-            float w = __builtin_amdgcn_exp2f(ex);
-            if (CLAMP) w = fminf(W_MAX, w);
-            const bool inc = !done && w >= ALPHA_MIN;
-            w = inc ? w : 0.f;
-            const float tw = T * w;
-            acc.x = fmaf(tw, q1.z, acc.x);
-            acc.y = fmaf(tw, q1.w, acc.y);
-            T = T - tw;
-            if (SAVE) {
-                last = inc ? (int)st.idx[wv][i] + 1 : last;
-                ncomp += inc ? 1u : 0u;
-            }
-            if (DETECT && inc && i >= i_far) {
-                if (*fcount < FAR_REC && myrec) {
-                    const uint32_t pe = st.p[wv][i];
-                    myrec[*fcount] = make_uint2(__float_as_uint(tw), pe);
-                    mark[pe / MLP_PAIRS] = 1;
-                }
-                ++*fcount;
-            }
-            done = done || T < T_EPS;
-        }
+        const bool wrap = MIXED && ((wmask >> i0) & 0xFull) != 0;
+        if (wrap)
+            blend_group4<SAVE, true, CLAMP, DETECT>(st, wv, i0, n, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp,
+                                                    neval, nslot, done, i_far, myrec, fcount, mark);
+        else
+            blend_group4<SAVE, false, CLAMP, DETECT>(st, wv, i0, n, X, Y, XX, XY, YY, Wf, halfW, T, acc, last,
+                                                     ncomp, neval, nslot, done, i_far, myrec, fcount, mark);
         if (__all(done)) break;
     }
 }
 
-template <bool SAVE, bool WRAP, bool CLAMP>
-__device__ __forceinline__ void blend_walk1_far(const BlendWaveStage &st, int wv, int n, int i_far, float X, float Y,
+template <bool SAVE, bool MIXED, bool CLAMP>
+__device__ __forceinline__ void blend_walk1_far(const BlendWaveStage &st, int wv, int n, uint64_t wmask, int i_far, float X,
+                                                float Y,
                                                 float XX, float XY, float YY, float Wf, float halfW, float &T,
                                                 float2 &acc, int &last, uint32_t &ncomp, uint32_t &neval,
                                                 uint32_t &nslot, bool &done, uint2 *myrec, int *fcount, uint8_t *mark)
@@ -1366,27 +1390,31 @@ __device__ __forceinline__ void blend_walk1_far(const BlendWaveStage &st, int wv
     // entries below the position prefix first (the tile list is in depth
     // order), then the rest with the far-entry records
     const int i4 = i_far & ~3;
-    blend_walk1<SAVE, WRAP, CLAMP>(st, wv, min(n, i4), X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
+    blend_walk1<SAVE, MIXED, CLAMP>(st, wv, min(n, i4), wmask, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
                                    nslot, done);
     if (i4 < n && __any(!done))
-        blend_walk1<SAVE, WRAP, CLAMP, true>(st, wv, n, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
+        blend_walk1<SAVE, MIXED, CLAMP, true>(st, wv, n, wmask, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
                                              nslot, done, i4, i_far, myrec, fcount, mark);
 }
 
 // SECOND: the prefix path's second launch (its own instantiation, so that
 // profiles tell the two launches apart).
 //
-// Each wave walks its 8 x 8 sub-tile on its own, with no workgroup barrier
-// until the end: per step, lane l takes entry l of the next 64 of the tile
+// One wave per workgroup, each an 8 x 8 sub-tile of a tile (four workgroups
+// per tile and receiver chunk), so a wave whose pixels stop early leaves at
+// once: per step, lane l takes entry l of the next 64 of the tile
 // list and tests the entry's binning box (the box the tile binning used, so
 // every pixel the entry can reach lies in it) against the wave's sub-tile;
 // the lanes of the entries that hit build their records (exponent as the
 // quadratic around the sub-tile centre, or the wrapped form when an entry
-// of the step spans more than half the azimuth circle) into the wave's LDS
+// of the step spans nearly the whole azimuth circle and is centred near the
+// sub-tile's antipode, where pixel offsets cross the seam) into the wave's LDS
 // slice in list order (ballot and lane count), and the wave walks them.  A
 // wave stops at the first step after all its lanes terminated.
+constexpr int BLEND1_THREADS = 64;
+
 template <bool SAVE, bool SECOND = false>
-__global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__ srec,
+__global__ __launch_bounds__(BLEND1_THREADS) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_blend_fwd1(const float4 *__restrict__ srec,
                                                       const float4 *__restrict__ sbox,
                                                       const uint32_t *__restrict__ pval,
                                                       const uint2 *__restrict__ ranges,
@@ -1400,36 +1428,36 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
 {
     constexpr bool redo = SECOND;
     __shared__ BlendWaveStage st;
-    __shared__ float s_red[4][3];
-    __shared__ uint32_t s_cnt[3][4];
 
-    // grid: (chunk, rank of the tile in its view's longest-first order)
+    // grid: (chunk, 4 x rank of the tile in its view's longest-first order +
+    // sub-tile)
     const int4 ch = chunks[blockIdx.x];
-    const int tile = torder ? (int)torder[(size_t)ch.x * g.tiles + blockIdx.y] : (int)blockIdx.y;
+    const int sub = (int)(blockIdx.y & 3u), rank = (int)(blockIdx.y >> 2);
+    const int tile = torder ? (int)torder[(size_t)ch.x * g.tiles + rank] : rank;
+    const size_t tsub = ((size_t)ch.x * g.tiles + tile) * 4 + sub;   // (view, tile, sub-tile)
     // second launch of the prefix path: blend views that overflowed their
-    // records again, add the recorded far entries in tiles that have some,
-    // nothing elsewhere (uniform over the block, before any barrier)
+    // records again, add the recorded far entries in sub-tiles that have
+    // some, nothing elsewhere
     bool deferred = false;
     if (redo) {
         if (!(vflag[ch.x] & 4u)) {
-            if (!fs.tile[(size_t)ch.x * g.tiles + tile]) return;
+            if (!fs.tile[tsub]) return;
             deferred = true;
         }
     }
     const int view = ch.x, j0 = ch.y, nrx = ch.z, tslot = ch.w;
     const int ty = tile / g.tiles_x, tx = tile - ty * g.tiles_x;
-    const int t = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
-    const int row = ty * TILE + 8 * (wv >> 1) + (lane >> 3), col = tx * TILE + 8 * (wv & 1) + (lane & 7);
+    const int lane = threadIdx.x, wv = 0;
+    const int row = ty * TILE + 8 * (sub >> 1) + (lane >> 3), col = tx * TILE + 8 * (sub & 1) + (lane & 7);
     const bool inside = row < g.H && col < g.W;
     const float X = (float)(lane & 7) - 3.5f, Y = (float)(lane >> 3) - 3.5f;
     const float XX = X * X, XY = X * Y, YY = Y * Y;
     const float Wf = (float)g.W, halfW = 0.5f * (float)g.W, invW = 1.0f / (float)g.W;
     const uint2 rg = ranges[(size_t)view * g.tiles + tile];
     const int64_t view_end = ((int64_t)view + 1) * Kp;
-    // this wave's sub-tile: first column and row, centre; the tile's centre column
-    const float cl = (float)(tx * TILE + 8 * (wv & 1)), rl = (float)(ty * TILE + 8 * (wv >> 1));
+    // this wave's sub-tile: first column and row, centre
+    const float cl = (float)(tx * TILE + 8 * (sub & 1)), rl = (float)(ty * TILE + 8 * (sub >> 1));
     const float colc = cl + 3.5f, rowc = rl + 3.5f;
-    const float tcol = (float)(tx * TILE) + 7.5f;
     const float allcols = 0.5f * (float)(g.W - TILE - 2);   // a box this wide takes every tile column
 
     float T = 1.f;
@@ -1468,11 +1496,18 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
         if (i < rg.y) {
             p = min(pval[i], (uint32_t)(view_end - 1));
             const float4 b = sbox[p];   // (u, v, padded half-extents)
-            const float u = fmaf(rintf((tcol - b.x) * invW), Wf, b.x);   // azimuth nearest the tile
-            wide = fabsf(tcol - u) >= halfW - 9.0f;
+            // the azimuth representative nearest the sub-tile's centre: no
+            // other one can reach the sub-tile unless the box spans nearly
+            // the whole circle (then it takes every column)
+            const float u = fmaf(rintf((colc - b.x) * invW), Wf, b.x);
             const bool colhit = b.z >= allcols || (u + b.z >= cl && u - b.z <= cl + 7.f);
             const bool rowhit = b.y + b.w >= rl && b.y - b.w <= rl + 7.f;
-            hit = wide || (colhit && rowhit);
+            hit = colhit && rowhit;
+            // pixel offsets (u within 3.5 px of the sub-tile's centre) cross
+            // the +-W/2 seam only for a centre within 4 px of the antipode,
+            // and matter there only for a box reaching that far: such an
+            // entry needs the wrapped form
+            wide = fabsf(colc - u) > halfW - 4.0f && b.z > halfW - 5.0f;
         }
         const int64_t s = (int64_t)p - (int64_t)view * Kp;
         const bool nearp = s < (int64_t)mpos;
@@ -1488,21 +1523,19 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
             float4 r0 = srec[2 * (size_t)p];
             const float4 r1 = srec[2 * (size_t)p + 1];
             const float2 re = nearp ? rad[(size_t)j0 * Kp + s] : make_float2(0.f, 0.f);
-            // representative of the azimuth closest to the tile's centre
-            r0.x = fmaf(rintf((tcol - r0.x) * invW), Wf, r0.x);
+            // representative of the azimuth closest to the sub-tile's centre
+            r0.x = fmaf(rintf((colc - r0.x) * invW), Wf, r0.x);
             const float a = r1.x, bb = r1.y, c = r1.z;
             const float du0 = (colc - r0.x) - r0.y;
             const float dv0 = (rowc - r0.z) - r0.w;
-            float4 q0;
-            if (anywide) {
-                q0 = make_float4(du0, dv0, r1.w, a);
-            } else {
-                const float e0 = fmaf(du0, fmaf(a, du0, bb * dv0), fmaf(c * dv0, dv0, r1.w));
-                q0 = make_float4(e0, fmaf(2.f * a, du0, bb * dv0), fmaf(bb, du0, 2.f * c * dv0), a);
-            }
+            const float e0 = fmaf(du0, fmaf(a, du0, bb * dv0), fmaf(c * dv0, dv0, r1.w));
             capped = r1.w >= LOG2_W_MAX;
-            st.q[wv][pos][0] = q0;
+            st.q[wv][pos][0] = make_float4(e0, fmaf(2.f * a, du0, bb * dv0), fmaf(bb, du0, 2.f * c * dv0), a);
             st.q[wv][pos][1] = make_float4(bb, c, re.x, re.y);
+            if (anywide) {
+                st.qw[wv][pos] = make_float4(du0, dv0, r1.w, 0.f);
+                reinterpret_cast<unsigned char *>(st.wf[wv])[pos] = wide ? 1 : 0;
+            }
             st.p[wv][pos] = p;
             if (SAVE) st.idx[wv][pos] = (unsigned short)(i - rg.x);
         }
@@ -1512,8 +1545,12 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
         // zero arises)
         const int np = (n + 3) & ~3;
         if (lane >= n && lane < np) {
-            st.q[wv][lane][0] = anywide ? make_float4(0.f, 0.f, -INFINITY, 0.f) : make_float4(-INFINITY, 0.f, 0.f, 0.f);
+            st.q[wv][lane][0] = make_float4(-INFINITY, 0.f, 0.f, 0.f);
             st.q[wv][lane][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (anywide) {
+                st.qw[wv][lane] = make_float4(0.f, 0.f, -INFINITY, 0.f);
+                reinterpret_cast<unsigned char *>(st.wf[wv])[lane] = 0;
+            }
             st.p[wv][lane] = 0;
             if (SAVE) st.idx[wv][lane] = 0;
         }
@@ -1522,35 +1559,37 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // records that need the wrapped form, by position
+        const uint64_t wmask = anywide ? __ballot(reinterpret_cast<const unsigned char *>(st.wf[wv])[lane] != 0) : 0ull;
         if (n_near < n) {
             if (anywide) {
                 if (clamp)
-                    blend_walk1_far<SAVE, true, true>(st, wv, n, n_near, X, Y, XX, XY, YY, Wf, halfW, T, acc, last,
+                    blend_walk1_far<SAVE, true, true>(st, wv, n, wmask, n_near, X, Y, XX, XY, YY, Wf, halfW, T, acc, last,
                                                       ncomp, neval, nslot, done, myrec, &fcount, fs.mark);
                 else
-                    blend_walk1_far<SAVE, true, false>(st, wv, n, n_near, X, Y, XX, XY, YY, Wf, halfW, T, acc, last,
+                    blend_walk1_far<SAVE, true, false>(st, wv, n, wmask, n_near, X, Y, XX, XY, YY, Wf, halfW, T, acc, last,
                                                        ncomp, neval, nslot, done, myrec, &fcount, fs.mark);
             } else {
                 if (clamp)
-                    blend_walk1_far<SAVE, false, true>(st, wv, n, n_near, X, Y, XX, XY, YY, Wf, halfW, T, acc, last,
+                    blend_walk1_far<SAVE, false, true>(st, wv, n, wmask, n_near, X, Y, XX, XY, YY, Wf, halfW, T, acc, last,
                                                        ncomp, neval, nslot, done, myrec, &fcount, fs.mark);
                 else
-                    blend_walk1_far<SAVE, false, false>(st, wv, n, n_near, X, Y, XX, XY, YY, Wf, halfW, T, acc, last,
+                    blend_walk1_far<SAVE, false, false>(st, wv, n, wmask, n_near, X, Y, XX, XY, YY, Wf, halfW, T, acc, last,
                                                         ncomp, neval, nslot, done, myrec, &fcount, fs.mark);
             }
         } else if (anywide) {
             if (clamp)
-                blend_walk1<SAVE, true, true>(st, wv, n, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
+                blend_walk1<SAVE, true, true>(st, wv, n, wmask, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
                                               nslot, done);
             else
-                blend_walk1<SAVE, true, false>(st, wv, n, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
+                blend_walk1<SAVE, true, false>(st, wv, n, wmask, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
                                                nslot, done);
         } else {
             if (clamp)
-                blend_walk1<SAVE, false, true>(st, wv, n, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
+                blend_walk1<SAVE, false, true>(st, wv, n, wmask, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
                                                nslot, done);
             else
-                blend_walk1<SAVE, false, false>(st, wv, n, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
+                blend_walk1<SAVE, false, false>(st, wv, n, wmask, X, Y, XX, XY, YY, Wf, halfW, T, acc, last, ncomp, neval,
                                                 nslot, done);
         }
         // the next step overwrites the slice only after this walk read it
@@ -1560,14 +1599,14 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
     }
     if (!redo) {
         // a pixel still open at the end of a view's truncated list: the view is redone in full
-        if (__syncthreads_or(inside && !done) && t == 0 && (vflag[view] & 1u)) atomicOr(vflag + view, 2u);
+        if (__any(inside && !done) && lane == 0 && (vflag[view] & 1u)) atomicOr(vflag + view, 2u);
         if (mpos != 0xFFFFFFFFu) {
             // entries past the prefix composited here: records kept (8), or too many (4)
             if (inside) fs.cnt[(size_t)view * P + pix] = (uint8_t)min(fcount, 255);
-            const int any_rec = __syncthreads_or(fcount > 0 && fcount <= FAR_REC);
-            const int any_ovf = __syncthreads_or(fcount > FAR_REC);
-            if (t == 0) {
-                fs.tile[(size_t)view * g.tiles + tile] = any_rec ? 1 : 0;
+            const bool any_rec = __any(fcount > 0 && fcount <= FAR_REC);
+            const bool any_ovf = __any(fcount > FAR_REC);
+            if (lane == 0) {
+                fs.tile[tsub] = any_rec ? 1 : 0;
                 if (any_ovf || any_rec) atomicOr(vflag + view, any_ovf ? 12u : 8u);
             }
         }
@@ -1581,45 +1620,34 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd1(const float4 *__restrict__
             nlast[(size_t)tslot * P + pix] = last;
         }
     }
-    // per-tile partial sums: power, Re, Im (fixed-order reduction)
+    // per-sub-tile partial sums: power, Re, Im (the reduction adds the four
+    // sub-tiles of a tile in order, then the tiles)
     {
-        const float pw = wave_sum_f32(acc.x * acc.x + acc.y * acc.y);
+        // (one explicit FMA, so every instantiation rounds the power alike)
+        const float pw = wave_sum_f32(fmaf(acc.x, acc.x, acc.y * acc.y));
         const float sr = wave_sum_f32(acc.x);
         const float si = wave_sum_f32(acc.y);
-        if (lane == 0) {
-            s_red[wv][0] = pw;
-            s_red[wv][1] = sr;
-            s_red[wv][2] = si;
+        if (lane == 0 && nrx > 0) {
+            float *pp = part + (((size_t)j0 * g.tiles + tile) * 4 + sub) * 3;
+            pp[0] = pw;
+            pp[1] = sr;
+            pp[2] = si;
         }
-    }
-    if (SAVE) {
-        const uint32_t nc = wave_sum_u32(ncomp), ne = wave_sum_u32(neval), ns = wave_sum_u32(nslot);
-        if (lane == 0) {
-            s_cnt[0][wv] = nc;
-            s_cnt[1][wv] = ne;
-            s_cnt[2][wv] = ns;
-        }
-    }
-    __syncthreads();
-    if (t < 3 && nrx > 0) {
-        const float v = ((s_red[0][t] + s_red[1][t]) + s_red[2][t]) + s_red[3][t];
-        part[((size_t)j0 * g.tiles + tile) * 3 + t] = v;
     }
     // composited (pixel, entry) pairs: per chunk pixel and per receiver pixel,
     // spread over STAT_SLOTS counters
-    if (SAVE && t == 0) {
-        const unsigned slot = (blockIdx.x + blockIdx.y * gridDim.x) % STAT_SLOTS;
-        unsigned long long n[3];
-#pragma unroll
-        for (int c = 0; c < 3; c++)
-            n[c] = (unsigned long long)s_cnt[c][0] + s_cnt[c][1] + s_cnt[c][2] + s_cnt[c][3];
-        if (n[0]) {
-            atomicAdd(stats + slot, n[0]);
-            atomicAdd(stats + STAT_SLOTS + slot, n[0] * (unsigned long long)nrx);
-        }
-        if (n[2]) {
-            atomicAdd(stats + 2 * STAT_SLOTS + slot, n[1]);
-            atomicAdd(stats + 3 * STAT_SLOTS + slot, n[2]);
+    if (SAVE) {
+        const uint32_t nc = wave_sum_u32(ncomp), ne = wave_sum_u32(neval), ns = wave_sum_u32(nslot);
+        if (lane == 0) {
+            const unsigned slot = (blockIdx.x + blockIdx.y * gridDim.x) % STAT_SLOTS;
+            if (nc) {
+                atomicAdd(stats + slot, (unsigned long long)nc);
+                atomicAdd(stats + STAT_SLOTS + slot, (unsigned long long)nc * (unsigned long long)nrx);
+            }
+            if (ns) {
+                atomicAdd(stats + 2 * STAT_SLOTS + slot, (unsigned long long)ne);
+                atomicAdd(stats + 3 * STAT_SLOTS + slot, (unsigned long long)ns);
+            }
         }
     }
 }
@@ -1845,7 +1873,7 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restr
     // per-tile partial sums: power, Re, Im (fixed-order reduction)
 #pragma unroll
     for (int r = 0; r < R; r++) {
-        const float pw = wave_sum_f32(acc[r].x * acc[r].x + acc[r].y * acc[r].y);
+        const float pw = wave_sum_f32(fmaf(acc[r].x, acc[r].x, acc[r].y * acc[r].y));
         const float sr = wave_sum_f32(acc[r].x);
         const float si = wave_sum_f32(acc[r].y);
         if (lane == 0) {
@@ -1891,7 +1919,9 @@ __global__ __launch_bounds__(BLOCK) void k_blend_fwd_multi(const float4 *__restr
 
 // one wave per receiver; lanes take tiles in a fixed stride, then a fixed
 // butterfly, so the result does not depend on scheduling
-__global__ __launch_bounds__(BLOCK) void k_reduce_out(const float *__restrict__ part, int N, int tiles,
+// part: per (row, tile) nsub partials of (power, Re, Im), the sub-tiles of a
+// tile in order
+__global__ __launch_bounds__(BLOCK) void k_reduce_out(const float *__restrict__ part, int N, int tiles, int nsub,
                                                       float *__restrict__ power, float *__restrict__ csum)
 {
     const int j = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
@@ -1899,10 +1929,12 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_out(const float *__restrict__ 
     if (j >= N) return;
     double pw = 0, sr = 0, si = 0;
     for (int t = lane; t < tiles; t += 64) {
-        const float *p = part + ((size_t)j * tiles + t) * 3;
-        pw += p[0];
-        sr += p[1];
-        si += p[2];
+        const float *p = part + ((size_t)j * tiles + t) * nsub * 3;
+        for (int q = 0; q < nsub; q++) {
+            pw += p[3 * q];
+            sr += p[3 * q + 1];
+            si += p[3 * q + 2];
+        }
     }
     for (int off = 32; off > 0; off >>= 1) {
         pw += __shfl_xor(pw, off);
@@ -2242,18 +2274,20 @@ static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st, boo
     dim3 grid((unsigned)ws.n_chunks, (unsigned)ws.g.tiles);
     const uint32_t *tord = ws.tiles_ordered ? ws.torder.as<uint32_t>() : nullptr;
     if constexpr (R == 1) {
+        grid.y = (unsigned)ws.g.tiles * 4;   // one workgroup per sub-tile
+        const dim3 blk(BLEND1_THREADS);
         if (save)
-            hipLaunchKernelGGL((k_blend_fwd1<true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
+            hipLaunchKernelGGL((k_blend_fwd1<true>), grid, blk, 0, st, ws.srec.as<float4>(),
                                ws.sbox.as<float4>(), ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, ws.Tfin.as<float>(), ws.nlast.as<int>(),
                                ws.part.as<float>(), stat_words(ws), tord, ws.vflag.as<uint32_t>(), mpos, fs);
         else if (redo)
-            hipLaunchKernelGGL((k_blend_fwd1<false, true>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
+            hipLaunchKernelGGL((k_blend_fwd1<false, true>), grid, blk, 0, st, ws.srec.as<float4>(),
                                ws.sbox.as<float4>(), ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord,
                                ws.vflag.as<uint32_t>(), mpos, fs);
         else
-            hipLaunchKernelGGL((k_blend_fwd1<false>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
+            hipLaunchKernelGGL((k_blend_fwd1<false>), grid, blk, 0, st, ws.srec.as<float4>(),
                                ws.sbox.as<float4>(), ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                                ws.d_chunks, ws.Kp, ws.g, C, nullptr, nullptr, ws.part.as<float>(), nullptr, tord,
                                ws.vflag.as<uint32_t>(), mpos, fs);
@@ -2281,7 +2315,8 @@ static void blend_launch(Workspace &ws, float *C, bool save, hipStream_t st, boo
 hipError_t launch_blend_fwd(Workspace &ws, float *C, bool save, hipStream_t st, bool redo)
 {
     if (ws.n_chunks == 0) return hipSuccess;
-    if (ws.g.tiles > 65535) return hipErrorInvalidConfiguration;   // grid y limit
+    // grid y limit (one workgroup per sub-tile with one receiver per chunk)
+    if ((int64_t)ws.g.tiles * (ws.R == 1 ? 4 : 1) > 65535) return hipErrorInvalidConfiguration;
     switch (ws.R) {
     case 1: blend_launch<1>(ws, C, save, st, redo); break;
     case 2: blend_launch<2>(ws, C, save, st, redo); break;
@@ -2454,7 +2489,7 @@ hipError_t launch_reduce_outputs(Workspace &ws, float *power, float *csum, hipSt
 {
     if (ws.N == 0 || (!power && !csum)) return hipSuccess;
     hipLaunchKernelGGL(k_reduce_out, dim3((unsigned)((ws.N + 3) / 4)), dim3(BLOCK), 0, st, ws.part.as<float>(), ws.N,
-                       ws.g.tiles, power, csum);
+                       ws.g.tiles, ws.R == 1 ? 4 : 1, power, csum);
     return hipGetLastError();
 }
 

@@ -1066,7 +1066,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     WGROW(ctx, ws, ws.rad, (size_t)NR * Kp * 8);
     WGROW(ctx, ws, ws.Tfin, (size_t)ws.n_tslots * P * 4);
     WGROW(ctx, ws, ws.nlast, (size_t)ws.n_tslots * P * 4);
-    WGROW(ctx, ws, ws.part, (size_t)NR * g.tiles * 12);
+    WGROW(ctx, ws, ws.part, (size_t)NR * g.tiles * 48);   // per sub-tile with one receiver per chunk
     if (ws.use_mlp) WGROW(ctx, ws, ws.Lp, (size_t)std::max<int64_t>(K, 1) * HID * 4);
     if (ws.use_items) WGROW(ctx, ws, ws.items, (size_t)std::max(ws.n_items, 1) * 16);
     if (rxc) WGROW(ctx, ws, ws.rloc, (size_t)N * Kp * Ch * 16);
@@ -1078,7 +1078,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         WGROW(ctx, ws, ws.items_far, (size_t)std::max(ws.n_items_far, 1) * 16);
         WGROW(ctx, ws, ws.frec, (size_t)V * P * FAR_RECORDS * 8);
         WGROW(ctx, ws, ws.fcnt, (size_t)V * P);
-        WGROW(ctx, ws, ws.ftile, (size_t)V * g.tiles);
+        WGROW(ctx, ws, ws.ftile, (size_t)V * g.tiles * 4);
         WGROW(ctx, ws, ws.live, live_count_offset(ws) + 64);   // marks of the blocks records point into
     }
 

@@ -168,10 +168,10 @@ int64_t estimate_bytes(int32_t mode, int32_t Q, int32_t N, int64_t K, int32_t H,
     b += 12 * V * tiles;                      // tile ranges and tile order
     b += 8 * (int64_t)N * Kp;                 // radiance
     b += 8 * (tx ? V : (int64_t)N) * P;       // final transmittance, stop index
-    b += 12 * (int64_t)N * tiles;             // per-tile partial sums
+    b += 48 * (int64_t)N * tiles;             // per-sub-tile partial sums
     b += 3 * 16 * items;                      // work items: all, the live ones, those past the prefix
     b += 2 * (VK / MLP_PAIRS + 128);          // position-block marks (asked for by both TX paths)
-    b += V * P * (FAR_RECORDS * 8 + 1) + V * tiles;   // far records of the radiance prefix, counts, tile marks
+    b += V * P * (FAR_RECORDS * 8 + 1) + 4 * V * tiles;   // far records of the radiance prefix, counts, sub-tile marks
     b += 4 * Dpad;                            // emission-order pair keys (deterministic saved states)
     b += 20 * (int64_t)N + 80 * V + 16 * (Dpad / SORT_TILE + 1) + 1024;   // descriptors
     b += 12 * (int64_t)Q + 16 * (int64_t)N + 8 * (int64_t)N * P;   // transmitters, receivers, power, spectra
