@@ -288,11 +288,16 @@ rxgs_status rxgs_saved_info(const rxgs_saved *s, rxgs_saved_info_t *out);
  *                         rxgs_view_flags, evaluates the rest first, on the device)
  *   RXGS_EXPORT_TFINAL    S x H x W f32: final transmittance (S = V in TX mode, N in RX)
  *   RXGS_EXPORT_NLAST     S x H x W i32: entries of the tile list consumed
+ *   RXGS_EXPORT_RECORDS   V x K_pad x 8 f32: the blend record at each sorted position
+ *                         s < NVIS[v] (Alg. 1 stage 1 output): floor u, u - floor u,
+ *                         floor v, v - floor v, then -log2(e)/2 a, -log2(e) b,
+ *                         -log2(e)/2 c (the conic, inverse of the projected
+ *                         covariance) and log2 o
  * `bytes` must be at least the size above; E_INVALID otherwise. */
 enum {
     RXGS_EXPORT_BIN = 0, RXGS_EXPORT_KEYS = 1, RXGS_EXPORT_OPACITY = 2, RXGS_EXPORT_ORDER = 3,
     RXGS_EXPORT_NVIS = 4, RXGS_EXPORT_PAIRS = 5, RXGS_EXPORT_RANGES = 6,
-    RXGS_EXPORT_RADIANCE = 7, RXGS_EXPORT_TFINAL = 8, RXGS_EXPORT_NLAST = 9
+    RXGS_EXPORT_RADIANCE = 7, RXGS_EXPORT_TFINAL = 8, RXGS_EXPORT_NLAST = 9, RXGS_EXPORT_RECORDS = 10
 };
 rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *dst, int64_t bytes, int dst_on_device);
 

@@ -1413,8 +1413,10 @@ __device__ __forceinline__ void blend_walk1_far(const BlendWaveStage &st, int wv
 // wave stops at the first step after all its lanes terminated.
 constexpr int BLEND1_THREADS = 64;
 
+// (seven waves per SIMD; six for the saving instantiation, whose counters
+// would not fit in registers)
 template <bool SAVE, bool SECOND = false>
-__global__ __launch_bounds__(BLEND1_THREADS) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_blend_fwd1(const float4 *__restrict__ srec,
+__global__ __launch_bounds__(BLEND1_THREADS) __attribute__((amdgpu_waves_per_eu(SAVE ? 6 : 7, 8))) void k_blend_fwd1(const float4 *__restrict__ srec,
                                                       const float4 *__restrict__ sbox,
                                                       const uint32_t *__restrict__ pval,
                                                       const uint2 *__restrict__ ranges,

@@ -1788,6 +1788,7 @@ extern "C" rxgs_status rxgs_saved_export(const rxgs_saved *s, int what, void *ds
     case RXGS_EXPORT_RADIANCE: src = ws.rad.p; n = (size_t)ws.N * ws.Kp * 8; break;
     case RXGS_EXPORT_TFINAL: src = ws.Tfin.p; n = (size_t)ws.n_tslots * P * 4; break;
     case RXGS_EXPORT_NLAST: src = ws.nlast.p; n = (size_t)ws.n_tslots * P * 4; break;
+    case RXGS_EXPORT_RECORDS: src = ws.srec.p; n = VK * 32; break;
     default: return fail(ctx, RXGS_E_INVALID, "unknown export");
     }
     if ((size_t)bytes < n) return fail(ctx, RXGS_E_INVALID, "destination too small");

@@ -22,7 +22,7 @@ FEAT_DIM = 32
 TILE = 16
 
 EXPORT_BIN, EXPORT_KEYS, EXPORT_OPACITY, EXPORT_ORDER, EXPORT_NVIS, EXPORT_PAIRS, \
-    EXPORT_RANGES, EXPORT_RADIANCE, EXPORT_TFINAL, EXPORT_NLAST = range(10)
+    EXPORT_RANGES, EXPORT_RADIANCE, EXPORT_TFINAL, EXPORT_NLAST, EXPORT_RECORDS = range(11)
 
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_OOM", 3: "E_DEVICE", 4: "E_STATE", 5: "E_BUSY",
           6: "E_TIMEOUT", 7: "E_CANCELLED"}

@@ -52,11 +52,32 @@ def _check_binning(r, saved, wl, mode):
     kb, near, pr = O.project(wl.scene, wl.grid, cen)
     diff = np.argwhere(keys != kb)
     assert diff.size == 0, (diff[:5], keys[tuple(diff[:5].T)], kb[tuple(diff[:5].T)])
-    # records within tolerance of the FP64 projection (visible ones)
+    # binning boxes within tolerance of the FP64 projection (visible ones):
+    # centre, and the padded half-extents of the ellipse q <= 2 ln(255 o)
+    # (R6: x 1.0001 + 0.01 px) from the oracle's projected covariance
     vis = ~near & (op >= np.float32(1 / 255))
     assert np.abs(ext[..., 0][vis] - pr[..., 0][vis]).max() < 1e-4 * wl.grid.W
     assert np.abs(ext[..., 1][vis] - pr[..., 1][vis]).max() < 1e-3
     assert np.abs(op[~near] - pr[..., 5][~near]).max() < 1e-6
+    qmax = 2.0 * np.log(op.astype(np.float64) * 255.0)
+    for ax, cov in ((2, 6), (3, 8)):
+        want = np.sqrt(np.maximum(qmax * pr[..., cov], 0.0)) * 1.0001 + 0.01
+        err = np.abs(ext[..., ax].astype(np.float64) - want)[vis]
+        assert (err <= 2e-6 * want[vis] + 1e-5).all(), (ax, err.max())
+    # the blend records at each sorted position: pixel position to 1e-5 px,
+    # conic to 1e-5 of its largest coefficient, log2 opacity
+    rec = saved.export(rxgs.EXPORT_RECORDS, np.float32, (V, Kp, 8)).astype(np.float64)
+    l2e = 1.4426950408889634
+    for v in range(V):
+        n = int(nvis[v])
+        k = order[v, :n]
+        assert np.abs(rec[v, :n, 0] + rec[v, :n, 1] - pr[v, k, 0]).max(initial=0) <= 1e-5
+        assert np.abs(rec[v, :n, 2] + rec[v, :n, 3] - pr[v, k, 1]).max(initial=0) <= 1e-5
+        conic = np.stack([rec[v, :n, 4] / (-0.5 * l2e), rec[v, :n, 5] / -l2e, rec[v, :n, 6] / (-0.5 * l2e)], axis=1)
+        ref = pr[v, k, 2:5]
+        scale = np.maximum(np.abs(ref[:, 0]), np.abs(ref[:, 2]))[:, None]
+        assert (np.abs(conic - ref) <= 1e-5 * scale).all(), np.abs((conic - ref) / scale).max()
+        assert np.abs(rec[v, :n, 7] - np.log2(pr[v, k, 5])).max(initial=0) <= 1e-6
     # pairs and order bit-exact against the oracle's integer binning
     seg, kk = O.bin_records(ext[..., 0], ext[..., 1], ext[..., 2], ext[..., 3], op, keys, wl.grid)
     assert seg.size == D
