@@ -470,12 +470,12 @@ rxgs_status rxgs_set_near_cut(rxgs_ctx *ctx, int on);
 /*
  * Deterministic backward (off by default; on at rxgs_create when the
  * environment variable RXGS_DETERMINISTIC=1).  While on, renders into a saved
- * state evaluate every visible position's radiance (no radiance prefix) and
- * keep the pairs' emission order, and rxgs_render_backward on such a state
- * sums every gradient in a fixed order instead of with float atomics (App. D
- * accumulates with atomicAdd): the blend backward stores one partial per
- * (tile-list entry, block of up to 4 receivers), summing its waves in order,
- * and gathers add them per (view, position) in emission order; the MLP
+ * state evaluate every visible position's radiance (no radiance prefix), and
+ * rxgs_render_backward on such a state sums every gradient in a fixed order
+ * instead of with float atomics (App. D accumulates with atomicAdd): the
+ * blend backward stores one partial per (pair, block of up to 4 receivers) at
+ * the pair's emission slot, summing its waves in order, and gathers add them
+ * per (view, position) and per (row, position) in emission order; the MLP
  * backward stores its per-Gaussian and per-receiver terms per marked position
  * block and gathers add them in view and block order; the projection
  * gradients of each Gaussian are summed over the views in order (FP64).  Two

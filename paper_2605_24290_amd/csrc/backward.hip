@@ -37,14 +37,19 @@ constexpr float LN2F = 0.69314718055994531f;
 // outstanding-memory budget) and contend across the waves of a tile.
 // Deterministic variant (DET): each wave adds its entry sums over its 64
 // lanes in a fixed order into its own LDS slots, the four waves' slots are
-// added in order at the flush, and every (tile list entry, receiver block) gets
-// its own partial in global memory (no atomics); a later gather adds the
-// partials of each (view, position) in a fixed order.
+// added in order at the flush, and every (pair, receiver block) gets its own
+// partial in global memory (no atomics), stored at the pair's emission slot
+// (its position's first slot plus the tile's index in the position's tile
+// enumeration), so a later gather adds each position's partials from one
+// contiguous range, in emission order.
 struct DetPartials {
-    float *gP;          // [block of the view][Dpad][8]: (u, v, a, b, c, o) partials per pair slot
-    float *dSP;         // [row of the view][Dpad][2]: dL/ds partials per pair slot
+    float *gP;          // [block of the view][Dpad][8]: (u, v, a, b, c, o) partials per pair, emission slot
+    float *dSP;         // [row of the view][Dpad][2]: dL/ds partials per pair, emission slot
     int64_t Dpad;
     const int4 *vinfo;  // per view (first row, rows, visible, -)
+    const float4 *sbox; // binning box of each sorted position
+    const uint32_t *poff;   // first pair slot of each sorted position within its view
+    const uint32_t *pbase;  // first pair slot of each view
 };
 
 template <int R, bool DET>
@@ -243,7 +248,12 @@ __global__ __launch_bounds__(BLOCK) void k_blend_bwd(
             // the entry's pair slot for this block of receivers
             if (t < cnt) {
                 const uint32_t pe = st.p[t];
-                const int64_t d = (int64_t)rg.x + start + t;
+                // the pair's emission slot
+                const float4 b = det.sbox[pe];
+                int ty0, ty1, a0, a1, b0, b1;
+                (void)tile_rows(b.y, b.w, g.H, ty0, ty1);
+                (void)tile_cols(b.x, b.z, g.W, g.tiles_x, a0, a1, b0, b1);
+                const int64_t d = (int64_t)det.pbase[view] + det.poff[pe] + tile_rank(ty, tx, ty0, a0, a1, b0, b1);
                 const int4 vi = det.vinfo[view];
                 const int64_t blk = (j0 - vi.x) / R;
                 float *gp = det.gP + ((size_t)blk * det.Dpad + d) * 8;
@@ -1008,45 +1018,16 @@ __global__ __launch_bounds__(BLOCK) void k_order_inv(const uint32_t *__restrict_
     if (k < K) oinv[(size_t)v * K + k] = (int)s;
 }
 
-// emission slot -> sorted slot of every pair: a pair (tile t, position p)
-// was emitted among p's pairs, in tile order, from slot poff[p] of its view
-__global__ __launch_bounds__(BLOCK) void k_pair_inv(const uint32_t *__restrict__ skey, const uint32_t *__restrict__ sval,
-                                                    const uint32_t *__restrict__ ekey, const uint32_t *__restrict__ poff,
-                                                    const int4 *__restrict__ segtab,
-                                                    const uint32_t *__restrict__ pbase,
-                                                    const uint32_t *__restrict__ pcount,
-                                                    const unsigned long long *__restrict__ counters, int64_t Kp,
-                                                    int64_t Dpad, uint32_t *__restrict__ pinv)
-{
-    const int64_t d = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (d >= Dpad) return;
-    const int v = segtab[d / SORT_TILE].z;
-    const int64_t local = d - (int64_t)pbase[v];
-    if (local < 0 || local >= (int64_t)pcount[v]) return;   // padding
-    const uint32_t t = skey[d];
-    const int64_t pg = sval[d];
-    const int64_t s = pg - (int64_t)v * Kp;
-    const uint32_t e0 = poff[pg];
-    const uint32_t e1 = s + 1 < (int64_t)counters[2 * (size_t)v] ? poff[pg + 1] : pcount[v];
-    for (uint32_t e = e0; e < e1; e++)
-        if (ekey[pbase[v] + e] == t) {
-            pinv[pbase[v] + e] = (uint32_t)d;
-            break;
-        }
-}
-
-// per (view, visible position): the record gradients and each row's dL/ds
-// summed over the position's pairs in emission order (and, within a pair, the
-// receiver blocks in order), then the block marks of the MLP backward
-__global__ __launch_bounds__(BLOCK) void k_det_gather(const float *__restrict__ gP, const float *__restrict__ dSP,
-                                                      int64_t Dpad, int Rdet, const uint32_t *__restrict__ pinv,
+// per (view, visible position): the record gradients summed over the
+// position's pairs in emission order (and, within a pair, the receiver blocks
+// in order)
+__global__ __launch_bounds__(BLOCK) void k_det_gather(const float *__restrict__ gP, int64_t Dpad, int Rdet,
                                                       const uint32_t *__restrict__ poff,
                                                       const uint32_t *__restrict__ pbase,
                                                       const uint32_t *__restrict__ pcount,
                                                       const unsigned long long *__restrict__ counters,
                                                       const int4 *__restrict__ vinfo, int V, int64_t Kp,
-                                                      float *__restrict__ g2d, float *__restrict__ dS,
-                                                      uint8_t *__restrict__ live)
+                                                      float *__restrict__ g2d)
 {
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (i >= (int64_t)V * Kp) return;
@@ -1055,36 +1036,55 @@ __global__ __launch_bounds__(BLOCK) void k_det_gather(const float *__restrict__ 
     const int64_t nvis = (int64_t)counters[2 * (size_t)v];
     if (s >= nvis) return;
     const uint32_t e0 = poff[i], e1 = s + 1 < nvis ? poff[i + 1] : pcount[v];
-    const uint32_t b0 = pbase[v];
-    const int4 vi = vinfo[v];   // (first row, rows, visible, -)
-    const int nblk = (vi.y + Rdet - 1) / Rdet;
+    const size_t b0 = pbase[v];
+    const int nblk = (vinfo[v].y + Rdet - 1) / Rdet;
     float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (uint32_t e = e0; e < e1; e++) {
-        const int64_t d = pinv[b0 + e];
         for (int b = 0; b < nblk; b++) {
-            const float *src = gP + ((size_t)b * Dpad + d) * 8;
-#pragma unroll
-            for (int c = 0; c < 6; c++) acc[c] += src[c];
+            const float4 *src = reinterpret_cast<const float4 *>(gP + ((size_t)b * Dpad + b0 + e) * 8);
+            const float4 x = src[0], y = src[1];
+            acc[0] += x.x;
+            acc[1] += x.y;
+            acc[2] += x.z;
+            acc[3] += x.w;
+            acc[4] += y.x;
+            acc[5] += y.y;
         }
     }
-    float *dst = g2d + (size_t)i * 8;
-#pragma unroll
-    for (int c = 0; c < 6; c++) dst[c] = acc[c];
-    dst[6] = dst[7] = 0.f;
-    bool any = false;
-    for (int r = 0; r < vi.y; r++) {
+    float4 *dst = reinterpret_cast<float4 *>(g2d + (size_t)i * 8);
+    dst[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    dst[1] = make_float4(acc[4], acc[5], 0.f, 0.f);
+}
+
+// per (row, sorted position of the row's view): dL/ds summed over the
+// position's pairs in emission order; marks the position blocks with a
+// nonzero dL/ds for the MLP backward
+__global__ __launch_bounds__(BLOCK) void k_det_gather_ds(const float *__restrict__ dSP, int64_t Dpad,
+                                                         const uint32_t *__restrict__ poff,
+                                                         const uint32_t *__restrict__ pbase,
+                                                         const uint32_t *__restrict__ pcount,
+                                                         const unsigned long long *__restrict__ counters,
+                                                         const int4 *__restrict__ vinfo,
+                                                         const int *__restrict__ rxview, int64_t Kp,
+                                                         float *__restrict__ dS, uint8_t *__restrict__ live)
+{
+    const int j = blockIdx.y;
+    const int v = rxview[j];
+    const int64_t nvis = (int64_t)counters[2 * (size_t)v];
+    const int rl = j - vinfo[v].x;
+    const size_t b0 = pbase[v];
+    for (int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x; s < nvis; s += (int64_t)gridDim.x * BLOCK) {
+        const size_t i = (size_t)v * Kp + s;
+        const uint32_t e0 = poff[i], e1 = s + 1 < nvis ? poff[i + 1] : pcount[v];
         float sx = 0.f, sy = 0.f;
         for (uint32_t e = e0; e < e1; e++) {
-            const float *src = dSP + ((size_t)r * Dpad + pinv[b0 + e]) * 2;
-            sx += src[0];
-            sy += src[1];
+            const float2 d = *reinterpret_cast<const float2 *>(dSP + ((size_t)rl * Dpad + b0 + e) * 2);
+            sx += d.x;
+            sy += d.y;
         }
-        float *out = dS + ((size_t)(vi.x + r) * Kp + s) * 2;
-        out[0] = sx;
-        out[1] = sy;
-        any = any || sx != 0.f || sy != 0.f;
+        *reinterpret_cast<float2 *>(dS + ((size_t)j * Kp + s) * 2) = make_float2(sx, sy);
+        if (sx != 0.f || sy != 0.f) live[i / MLP_PAIRS] = 1;
     }
-    if (any) live[i / MLP_PAIRS] = 1;
 }
 
 // direct radiance: dL/d radiance_k over the rows in order
@@ -1180,27 +1180,36 @@ __global__ __launch_bounds__(BLOCK) void k_det_dl(const float *__restrict__ dLv,
     dL[i] = acc;
 }
 
-// ... and its receiver term, per row and hidden unit: the row's marked
-// position blocks in order
+// ... and its receiver term, per row (one wave, lane = hidden unit): the
+// row's marked position blocks in increasing order (64 ranks read at a time,
+// the live ones walked through the ballot mask from its lowest bit)
 __global__ __launch_bounds__(BLOCK) void k_det_dg(const float *__restrict__ dGp, int rows_max,
                                                   const int *__restrict__ rank, const int *__restrict__ rxview,
                                                   const int4 *__restrict__ vinfo,
                                                   const unsigned long long *__restrict__ counters, int N, int64_t Kp,
                                                   float *__restrict__ dG)
 {
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (i >= (int64_t)N * HID) return;
-    const int j = (int)(i / HID), u = (int)(i - (int64_t)j * HID);
+    static_assert(HID == 64, "one lane per hidden unit");
+    const int j = blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (j >= N) return;   // uniform across the wave
     const int v = rxview[j];
     const int rl = j - vinfo[v].x;
     const int64_t nb = ((int64_t)counters[2 * (size_t)v] + MLP_PAIRS - 1) / MLP_PAIRS;
     const int64_t b0 = (int64_t)v * Kp / MLP_PAIRS;
     float acc = 0.f;
-    for (int64_t b = 0; b < nb; b++) {
-        const int rk = rank[b0 + b];
-        if (rk >= 0) acc += dGp[((size_t)rk * rows_max + rl) * HID + u];
+    for (int64_t c = 0; c < nb; c += 64) {
+        const int64_t b = c + lane;
+        const int rk = b < nb ? rank[b0 + b] : -1;
+        uint64_t m = __ballot(rk >= 0);
+        while (m) {
+            const int l = (int)__builtin_ctzll(m);
+            m &= m - 1;
+            const int r = __builtin_amdgcn_readlane(rk, l);
+            acc += dGp[((size_t)r * rows_max + rl) * HID + lane];
+        }
     }
-    dG[i] = acc;
+    dG[(size_t)j * HID + lane] = acc;
 }
 
 // ============================================================================
@@ -1263,8 +1272,9 @@ static hipError_t blend_bwd_launch(Workspace &ws, const float *C, const float *d
     const int64_t ny = (int64_t)ws.n_chunks * split;
     if (ny > 65535 || ws.g.tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)ws.g.tiles, (unsigned)ny);
-    const DetPartials det = DET ? DetPartials{ws.gP.as<float>(), ws.dSP.as<float>(), ws.Dpad, ws.d_vinfo}
-                                : DetPartials{nullptr, nullptr, 0, nullptr};
+    const DetPartials det = DET ? DetPartials{ws.gP.as<float>(), ws.dSP.as<float>(), ws.Dpad, ws.d_vinfo,
+                                              ws.sbox.as<float4>(), ws.poff.as<uint32_t>(), ws.d_pbase}
+                                : DetPartials{nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr};
     hipLaunchKernelGGL((k_blend_bwd<R, DET>), grid, dim3(BLOCK), 0, st, ws.srec.as<float4>(),
                        ws.pval[ws.pairs_buf].as<uint32_t>(), ws.ranges.as<uint2>(), ws.rad.as<float2>(),
                        ws.d_chunks, split, ws.Kp, ws.g, ws.mode == RXGS_MODE_TX ? 1 : 0, C, dC, dP, dA,
@@ -1296,23 +1306,22 @@ hipError_t launch_blend_bwd(Workspace &ws, const float *C, const float *dC, cons
 // slots hold 6 + 2 R values per entry)
 int det_block_rows(const Workspace &ws) { return std::min(ws.R, 4); }
 
-// the deterministic backward's pair-slot partials, the pair inverse, the
-// per-(view, position) gather and the inverse of the sorted order
+// the deterministic backward's gathers of the pair partials per (view,
+// position) and per (row, position), and the inverse of the sorted order
 hipError_t launch_det_gather(Workspace &ws, hipStream_t st)
 {
-    const uint32_t *ekey = ws.pair_passes == 1 ? ws.pkey[0].as<uint32_t>() : ws.pkey_em.as<uint32_t>();
-    if (ws.Dpad > 0)
-        hipLaunchKernelGGL(k_pair_inv, dim3(nblk((size_t)ws.Dpad)), dim3(BLOCK), 0, st,
-                           ws.pkey[ws.pairs_buf].as<uint32_t>(), ws.pval[ws.pairs_buf].as<uint32_t>(), ekey,
-                           ws.poff.as<uint32_t>(), ws.d_segtab, ws.d_pbase, ws.d_pcount,
-                           ws.counters.as<unsigned long long>(), ws.Kp, ws.Dpad, ws.pinv.as<uint32_t>());
     const size_t VK = (size_t)ws.V * ws.Kp;
-    hipLaunchKernelGGL(k_det_gather, dim3(nblk(VK)), dim3(BLOCK), 0, st, ws.gP.as<float>(), ws.dSP.as<float>(),
-                       ws.Dpad, det_block_rows(ws), ws.pinv.as<uint32_t>(), ws.poff.as<uint32_t>(), ws.d_pbase,
-                       ws.d_pcount, ws.counters.as<unsigned long long>(), ws.d_vinfo, ws.V, ws.Kp,
-                       ws.g2d.as<float>(), ws.dS.as<float>(), ws.live.as<uint8_t>());
-    hipLaunchKernelGGL(k_order_inv, dim3(nblk(VK)), dim3(BLOCK), 0, st, ws.vorder.as<uint32_t>(),
-                       ws.counters.as<unsigned long long>(), ws.V, ws.K, ws.Kp, ws.oinv.as<int>());
+    const unsigned long long *cnt = ws.counters.as<unsigned long long>();
+    hipLaunchKernelGGL(k_det_gather, dim3(nblk(VK)), dim3(BLOCK), 0, st, ws.gP.as<float>(), ws.Dpad,
+                       det_block_rows(ws), ws.poff.as<uint32_t>(), ws.d_pbase, ws.d_pcount, cnt, ws.d_vinfo, ws.V,
+                       ws.Kp, ws.g2d.as<float>());
+    if (ws.N > 65535) return hipErrorInvalidConfiguration;
+    const unsigned bx = (unsigned)std::min<size_t>(nblk((size_t)ws.Kp), 64);
+    hipLaunchKernelGGL(k_det_gather_ds, dim3(bx, (unsigned)ws.N), dim3(BLOCK), 0, st, ws.dSP.as<float>(), ws.Dpad,
+                       ws.poff.as<uint32_t>(), ws.d_pbase, ws.d_pcount, cnt, ws.d_vinfo, ws.d_rxview, ws.Kp,
+                       ws.dS.as<float>(), ws.live.as<uint8_t>());
+    hipLaunchKernelGGL(k_order_inv, dim3(nblk(VK)), dim3(BLOCK), 0, st, ws.vorder.as<uint32_t>(), cnt, ws.V, ws.K,
+                       ws.Kp, ws.oinv.as<int>());
     return hipGetLastError();
 }
 

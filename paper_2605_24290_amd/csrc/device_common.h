@@ -38,6 +38,56 @@ __host__ __device__ __forceinline__ int hid_pos(int d)
     return h * 32 + t;
 }
 
+// tile coverage of one record, FP32 rules (rows clamped to the grid, columns
+// modulo W; a box spanning nearly the full circle takes every tile column)
+__device__ __forceinline__ int tile_rows(float v, float rvp, int H, int &ty0, int &ty1)
+{
+    float lo = fmaxf(__fsub_rn(v, rvp), 0.0f);
+    float hi = fminf(__fadd_rn(v, rvp), (float)(H - 1));
+    int i0 = (int)ceilf(lo), i1 = (int)floorf(hi);
+    if (i0 > i1) return 0;
+    ty0 = i0 / TILE;
+    ty1 = i1 / TILE;
+    return ty1 - ty0 + 1;
+}
+
+__device__ __forceinline__ int tile_cols(float u, float rup, int W, int tiles_x, int &a0, int &a1, int &b0,
+                                         int &b1)
+{
+    b0 = 0;
+    b1 = -1;
+    if (rup >= 0.5f * (float)(W - TILE - 2)) {
+        a0 = 0;
+        a1 = tiles_x - 1;
+        return tiles_x;
+    }
+    int c0 = (int)ceilf(__fsub_rn(u, rup)), c1 = (int)floorf(__fadd_rn(u, rup));
+    if (c0 > c1) return 0;
+    // c0 mod W; c0 lies in (-W, W) for every box on the grid, other values
+    // take the general form
+    int m = c0 < 0 ? c0 + W : c0;
+    if ((unsigned)m >= (unsigned)W) m = ((c0 % W) + W) % W;
+    int e = m + (c1 - c0);
+    a0 = m / TILE;
+    if (e < W) {
+        a1 = e / TILE;
+    } else {
+        a1 = (W - 1) / TILE;
+        b1 = (e - W) / TILE;
+    }
+    return (a1 - a0 + 1) + (b1 - b0 + 1);
+}
+
+// index of tile (ty, tx) in the enumeration the pair emission uses for a
+// record covering rows ty0.. and the column ranges a0..a1, b0..b1: row-major,
+// the first column range before the second
+__device__ __forceinline__ int tile_rank(int ty, int tx, int ty0, int a0, int a1, int b0, int b1)
+{
+    const int na = a1 - a0 + 1, nc = na + (b1 - b0 + 1);
+    const int cx = (tx >= a0 && tx <= a1) ? tx - a0 : na + (tx - b0);
+    return (ty - ty0) * nc + cx;
+}
+
 // DPP move (row_shr, row_bcast, ...) with masked-off or out-of-row lanes reading 0
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_shift(float x)

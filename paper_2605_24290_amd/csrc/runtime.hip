@@ -143,7 +143,7 @@ void release_buffers(Workspace &ws)
                       &ws.counters, &ws.hist,   &ws.nvis_d, &ws.dS,    &ws.g2d,    &ws.dL,
                       &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.mred,   &ws.live,   &ws.items_live, &ws.vflag,
                       &ws.items_far, &ws.frec, &ws.fcnt,  &ws.ftile,  &ws.hist_b, &ws.gfeat_tmp, &ws.gmlp_tmp,
-                      &ws.rgam,    &ws.rab,     &ws.rloc,    &ws.pkey_em, &ws.gP,     &ws.dSP,    &ws.pinv,
+                      &ws.rgam,    &ws.rab,     &ws.rloc,    &ws.gP,     &ws.dSP,
                       &ws.oinv,    &ws.rank,    &ws.lcnt,    &ws.dLv,     &ws.dGp};
     for (DevBuf *b : bufs) release(*b);
 }
@@ -826,8 +826,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     ws.valid = false;
     ws.req_bytes = 0;
     // a deterministic backward needs every position's radiance (no prefix,
-    // whose far-position work list is built in arrival order) and the
-    // pairs' emission order
+    // whose far-position work list is built in arrival order)
     ws.det = save && ctx->deterministic && rsrc == RSRC_SCENE;
     if (!ws.staged) {
         HIPCHK(ctx, hipEventCreateWithFlags(&ws.staged, hipEventDisableTiming));
@@ -1126,11 +1125,6 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
         // (the emission kernel also clears the pair sort's scratch)
         const int sbits = std::max(bits_for((uint64_t)g.tiles), 1);
         STAGE(ctx, "emit_pairs", launch_emit2(ws, g, sort_ws_bytes((uint32_t)Dpad, sbits, V) / 4, st));
-        ws.pair_passes = (sbits + 7) / 8;
-        if (ws.det && ws.pair_passes > 1) {   // the sort overwrites the emission order
-            WGROW(ctx, ws, ws.pkey_em, (size_t)Dpad * 4);
-            HIPCHK(ctx, hipMemcpyAsync(ws.pkey_em.p, ws.pkey[0].p, (size_t)Dpad * 4, hipMemcpyDeviceToDevice, st));
-        }
         STAGE(ctx, "sort_pairs", sort_pairs_u32(ws.pkey, ws.pval, ws.hist_b, pcur, (uint32_t)Dpad, sbits, V, 0,
                                                 ws.d_segtab, st, true));
         ws.pair_bits = sbits;
@@ -1529,8 +1523,9 @@ extern "C" rxgs_status rxgs_render_chunked(rxgs_ctx *ctx, int mode, int Q, const
 
 // ============================================================================
 // The deterministic backward: the blend backward stores one partial per
-// (pair slot, receiver block) instead of adding atomically; gathers add them
-// per (view, position) in the pairs' emission order, the MLP backward's terms
+// (pair, receiver block) at the pair's emission slot instead of adding
+// atomically; gathers add them per (view, position) and per (row, position)
+// in emission order, the MLP backward's terms
 // per Gaussian and per receiver in view and block order, and the projection
 // gradients per Gaussian over the views in order.  The outputs are written
 // (or added, accumulate = 1) once each.
@@ -1550,7 +1545,6 @@ static rxgs_status backward_det(rxgs_ctx *ctx, Workspace &ws, const float *C, co
     WGROW(ctx, ws, ws.live, VK / MLP_PAIRS + 4);
     WGROW(ctx, ws, ws.gP, nblk * Dp * 32);
     WGROW(ctx, ws, ws.dSP, (size_t)ws.R_max * Dp * 8);
-    WGROW(ctx, ws, ws.pinv, Dp * 4);
     WGROW(ctx, ws, ws.oinv, (size_t)ws.V * std::max<int64_t>(K, 1) * 4);
     zr.add(ws.live.p, (VK / MLP_PAIRS + 3) / 4);
     zr.add(ws.gP.p, nblk * Dp * 8);

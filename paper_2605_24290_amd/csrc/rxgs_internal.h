@@ -161,11 +161,8 @@ struct Workspace {
     // deterministic backward (rxgs_set_deterministic): the forward kept every
     // position's radiance and the emission order of the pairs
     bool det = false;
-    int pair_passes = 0;       // radix passes of the last pair sort
-    DevBuf pkey_em;            // Dpad u32 tile keys in emission order (pair sorts of 2+ passes)
     DevBuf gP;                 // [block of a view][Dpad][8] record-gradient partials per pair slot
     DevBuf dSP;                // [row of a view][Dpad][2] dL/ds partials per pair slot
-    DevBuf pinv;               // Dpad u32: sorted slot of each emitted pair
     DevBuf oinv;               // V x K int: sorted position of each (view, Gaussian), -1 if not visible
     DevBuf rank;               // V x Kp / 32 int: slot of each marked position block, -1 unmarked
     DevBuf lcnt;               // per 1024 blocks: marked-block offsets, then their total
