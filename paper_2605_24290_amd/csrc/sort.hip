@@ -113,39 +113,44 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict_
     __shared__ uint32_t s_loc[256];     // tile-local start of each digit
     __shared__ uint32_t s_glob[256];    // output start of each digit for this tile
     __shared__ uint32_t s_w[4];
-    __shared__ uint32_t s_tile;
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int shift = 8 * pass;
-    // the workgroup's segment follows from its index (segments are runs of
-    // whole tiles); its tile inside the segment comes from the segment's own
-    // ticket, so waits only go to tiles that took smaller tickets
+    (void)ticket;
+    // the workgroup's tile is its index, and its segment follows from it
+    // (segments are runs of whole tiles); workgroups are dispatched in index
+    // order, so a look-back waits only for tiles already dispatched (and the
+    // wait is bounded in any case)
+    const uint32_t tile = blockIdx.x;
     uint32_t seg, first;
-    tile_segment(blockIdx.x, sm, seg, first);
-    if (t == 0) s_tile = first + atomicAdd(ticket + (size_t)seg * TICKET_STRIDE, 1u);
+    tile_segment(tile, sm, seg, first);
+    const size_t tile0 = (size_t)tile * TILEN, seg0 = (size_t)first * TILEN;
+    const size_t base = tile0 + (size_t)w * WCH;
+    // the tile's keys, loaded first so that their latency overlaps the scan
+    // of the segment's digit totals (positions past the segment's surviving
+    // prefix are dropped below)
+    const size_t lim0 = min((size_t)n, tile0 + TILEN);
+    uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; r++) {
+        const size_t idx = base + (size_t)r * 64 + lane;
+        const bool in = idx < lim0;
+        key[r] = in ? kin[idx] : SORT_DROP;
+        val[r] = in ? vin[idx] : 0u;
+    }
 #pragma unroll
     for (int ww = 0; ww < 4; ww++) s_wc[ww][t] = 0;
-    __syncthreads();
-    const uint32_t tile = s_tile;
     // digit starts in the segment (from its digit totals) and its surviving count
     uint32_t seg_n;
     const uint32_t dbase = block_exclusive_scan(hist[((size_t)seg * passes + pass) * 256 + t], seg_n, s_w);
     // input positions of this tile that hold keys: all (first pass), or the
     // part of the segment's surviving prefix inside the tile (later passes)
-    const size_t tile0 = (size_t)tile * TILEN, seg0 = (size_t)first * TILEN;
-    size_t lim = min((size_t)n, tile0 + TILEN);
+    size_t lim = lim0;
     if (pass > 0) {
         lim = min(lim, seg0 + seg_n);
         if (tile0 >= lim) return;   // uniform; later tiles of the segment are empty too
-    }
-    const size_t base = tile0 + (size_t)w * WCH;
-
-    uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
 #pragma unroll
-    for (int r = 0; r < ITEMS; r++) {
-        const size_t idx = base + (size_t)r * 64 + lane;
-        const bool in = idx < lim;
-        key[r] = in ? kin[idx] : SORT_DROP;
-        val[r] = in ? vin[idx] : 0u;
+        for (int r = 0; r < ITEMS; r++)
+            if (base + (size_t)r * 64 + lane >= lim) key[r] = SORT_DROP;
     }
     // stable rank inside the wave's chunk: the keys of one round are matched by
     // digit; a digit's running count is read by all its lanes, then advanced by
