@@ -99,11 +99,18 @@ __device__ __forceinline__ void gauss_geo(const float *__restrict__ soa, int64_t
     }
 }
 
-// the view-independent part of every Gaussian, computed once per render and
-// read back by the key and emission kernels (80 bytes per Gaussian)
+// the view-independent part of every Gaussian, computed once per render (in
+// FP64) and read back by the key and emission kernels, 48 bytes per Gaussian:
+// position and opacity, then the 3-D covariance, the squared-distance bound
+// of the support and log2 opacity rounded to FP32.  The emission gathers these
+// terms in depth order; the FP32 rounding (a relative 6e-8) moves the
+// projected conic and the binning extents by about 1e-7 relative, far below
+// their FP32 storage in the blend record, and the backward differentiates
+// the FP64 terms it recomputes from the parameters.
 struct alignas(16) GaussGeoPacked {
-    double S00, S01, S02, S11, S12, S22, qmax, lo2;
     float px, py, pz, o32;
+    float S00, S01, S02, S11;
+    float S12, S22, qmax, lo2;
 };
 
 // Also the cull bound of each Gaussian, qcull >= q_max trace(Sigma) (rounded
@@ -117,21 +124,21 @@ __global__ __launch_bounds__(BLOCK) void k_gauss_prep(const float *__restrict__ 
     GaussGeo G;
     gauss_geo(soa, K, k, G);
     GaussGeoPacked o;
-    o.S00 = G.S00; o.S01 = G.S01; o.S02 = G.S02; o.S11 = G.S11; o.S12 = G.S12; o.S22 = G.S22;
-    o.qmax = G.qmax; o.lo2 = G.lo2;
     o.px = G.px; o.py = G.py; o.pz = G.pz; o.o32 = G.o32;
+    o.S00 = (float)G.S00; o.S01 = (float)G.S01; o.S02 = (float)G.S02;
+    o.S11 = (float)G.S11; o.S12 = (float)G.S12; o.S22 = (float)G.S22;
+    o.qmax = (float)G.qmax; o.lo2 = (float)G.lo2;
     out[k] = o;
     qcull[k] = (float)(G.qmax * (G.S00 + G.S11 + G.S22) * (1.0 + 1e-6));
 }
 
 __device__ __forceinline__ void gauss_geo_load(const GaussGeoPacked *__restrict__ gg, int64_t k, GaussGeo &G)
 {
-    const double2 *d = reinterpret_cast<const double2 *>(gg + k);
-    const double2 a = d[0], b = d[1], c = d[2], e = d[3];
-    const float4 f = *reinterpret_cast<const float4 *>(d + 4);
-    G.S00 = a.x; G.S01 = a.y; G.S02 = b.x; G.S11 = b.y; G.S12 = c.x; G.S22 = c.y;
-    G.qmax = e.x; G.lo2 = e.y;
+    const float4 *d = reinterpret_cast<const float4 *>(gg + k);
+    const float4 f = d[0], a = d[1], b = d[2];
     G.px = f.x; G.py = f.y; G.pz = f.z; G.o32 = f.w;
+    G.S00 = a.x; G.S01 = a.y; G.S02 = a.z; G.S11 = a.w; G.S12 = b.x; G.S22 = b.y;
+    G.qmax = b.z; G.lo2 = b.w;
 }
 
 // view part: FP32 depth key, grid position, projected covariance (A, B; B, C)
@@ -255,7 +262,7 @@ __global__ __launch_bounds__(BLOCK) void k_project(
             gauss_geo_load(gg, k, G);
             po = make_float4(G.px, G.py, G.pz, G.o32);
         } else {
-            po = *reinterpret_cast<const float4 *>(reinterpret_cast<const double2 *>(gg + k) + 4);
+            po = *reinterpret_cast<const float4 *>(gg + k);
         }
         qc = qcull[k];
     }

@@ -872,7 +872,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     WGROW(ctx, ws, ws.sbox, VK * 16);
     WGROW(ctx, ws, ws.vorder, VK * 4);
     WGROW(ctx, ws, ws.poff, VK * 4);
-    WGROW(ctx, ws, ws.ggeo, (size_t)std::max<int64_t>(K, 1) * 80);
+    WGROW(ctx, ws, ws.ggeo, (size_t)std::max<int64_t>(K, 1) * 48);
     WGROW(ctx, ws, ws.qcull, (size_t)std::max<int64_t>(K, 1) * 4);
     // per view (visible count, pair count); slots for the largest |layer-1
     // term| of the receivers and of the Gaussians (FP32 bits); render

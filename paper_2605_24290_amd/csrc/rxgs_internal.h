@@ -187,7 +187,7 @@ struct Workspace {
     DevBuf skey[2];   // V x Kp u32 sort keys (ping-pong)
     DevBuf sval[2];   // V x Kp u32 sort values
     int sorted_buf = 0;
-    DevBuf ggeo;      // K x 80 B view-independent projection terms of every Gaussian
+    DevBuf ggeo;      // K x 48 B view-independent projection terms of every Gaussian
     DevBuf qcull;     // K f32 elevation-cull bound of every Gaussian
     DevBuf srec;      // V x Kp x 2 float4 blend records of the visible entries in depth order
     DevBuf sbox;      // V x Kp float4 binning boxes (u, v, rup, rvp), same order

@@ -159,7 +159,7 @@ int64_t estimate_bytes(int32_t mode, int32_t Q, int32_t N, int64_t K, int32_t H,
     int64_t b = 0;
     b += 4 * V + 12 * V + 12 * (int64_t)N;   // view flags; view centres and receivers (saved states)
     b += 72 * VK;                             // depth keys and values (two copies), records, boxes, order, pair offsets
-    b += 84 * K1;                             // projection terms and cull bounds per Gaussian
+    b += 52 * K1;                             // projection terms and cull bounds per Gaussian
     b += 4 * (4 * V + AMAX_SLOTS + 2 * STAT_WORDS + (int64_t)emit_word_count((int)V, Kp) + 16);   // counters
     b += (int64_t)sort_ws_bytes((uint32_t)std::min<int64_t>(VK, 0xFFFFFFFFll), 32, (int)V);    // depth sort
     b += 256 * (int64_t)N + 256 * K1;         // MLP layer-1 terms of the receivers and the Gaussians
