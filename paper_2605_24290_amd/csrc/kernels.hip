@@ -361,15 +361,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
     const uint32_t *__restrict__ order, const uint32_t *__restrict__ hist, int passes, int cpv,
     float4 *__restrict__ srec, float4 *__restrict__ sbox, uint32_t *__restrict__ vorder, uint32_t *__restrict__ poff,
     unsigned long long *__restrict__ counters, unsigned long long *status, uint32_t *tickets, uint32_t *err,
-    uint32_t limit, uint32_t *__restrict__ vflag)
+    uint32_t limit, uint32_t *__restrict__ vflag, uint32_t *__restrict__ bcnt, uint4 *__restrict__ binfo)
 {
     constexpr int NW = NT / 64;
     __shared__ uint2 s_w2[NW];
     __shared__ uint32_t s_chunk, s_vbase, s_pbase;
+    __shared__ int s_d[BIN_DIFF_WORDS];
     constexpr int EM1_CHUNK = NT * EM1_PER;
     const int t = threadIdx.x;
     const int v = (int)(blockIdx.x / (unsigned)cpv);
+    const int dw = g.tiles_x + 1;   // row stride of the per-tile difference counts
     if (t == 0) s_chunk = atomicAdd(tickets + (size_t)v * EM_TICKET_STRIDE, 1u);
+    if (bcnt)
+        for (int i = t; i < g.tiles_y * dw; i += NT) s_d[i] = 0;
     // entries the depth sort kept for this view: the sum of its digit totals
     uint2 seg2;
     (void)block_exclusive_scan2<NW>(t < 256 ? hist[((size_t)v * passes) * 256 + t] : 0u, 0u, seg2, s_w2);
@@ -406,8 +410,35 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
         }
         npairs += nt[j];
     }
+    if (bcnt) {
+        // this chunk's pairs per tile: +1 / -1 at the ends of each covered
+        // column run, row by row, then a prefix along each row
+#pragma unroll
+        for (int j = 0; j < EM1_PER; j++) {
+            if (!nt[j]) continue;
+            int ty0, ty1, a0, a1, b0, b1;
+            (void)tile_rows(box[j].y, box[j].w, g.H, ty0, ty1);
+            (void)tile_cols(box[j].x, box[j].z, g.W, g.tiles_x, a0, a1, b0, b1);
+            for (int ty = ty0; ty <= ty1; ty++) {
+                int *d = s_d + ty * dw;
+                atomicAdd(d + a0, 1);
+                atomicAdd(d + a1 + 1, -1);
+                if (b1 >= b0) {
+                    atomicAdd(d + b0, 1);
+                    atomicAdd(d + b1 + 1, -1);
+                }
+            }
+        }
+    }
+    // (the scan's first barrier orders the counts above before the reads below)
     uint2 tot;
     const uint2 pre = block_exclusive_scan2<NW>(nvis, npairs, tot, s_w2);
+    if (bcnt && t < g.tiles) {
+        const int ty = t / g.tiles_x, tx = t - ty * g.tiles_x;
+        int c = 0;
+        for (int x = 0; x <= tx; x++) c += s_d[ty * dw + x];
+        bcnt[((size_t)v * cpv + chunk) * 256 + t] = (uint32_t)c;
+    }
     if (t < 64) {
         uint32_t evis = 0;
         uint64_t epairs = 0;
@@ -475,6 +506,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
         counters[2 * (size_t)v] = s_vbase + tot.x;
         counters[2 * (size_t)v + 1] = (uint64_t)s_pbase + tot.y;
     }
+    if (binfo && t == 0) binfo[(size_t)v * cpv + chunk] = make_uint4(s_vbase, tot.x, s_pbase, tot.y);
 }
 
 // Emission, part 2 (after the counts are known): one (local tile id, sorted
@@ -587,6 +619,249 @@ __global__ __launch_bounds__(BLOCK) void k_emit2(const float4 *__restrict__ sbox
         const uint32_t pend = pb + (uint32_t)(((uint64_t)pcount[v] + SORT_TILE - 1) / SORT_TILE * SORT_TILE);
         for (uint32_t o = seg_end + t; o < pend; o += BLOCK) pkey[o] = 0xFFFFFFFFu;
     }
+}
+
+// Direct binning (grids of at most BIN_MAX_TILES tiles): each tile's list is
+// written in its final place, in depth order, without a sort of the pairs.
+// The first emission counts each chunk's pairs per tile.  Per view,
+// k_bin_scan turns those counts into each chunk's start inside every tile's
+// list (the counts of the view's earlier chunks) and the view's list
+// lengths.  k_bin_pairs then places the pairs in units of BIN_WIN pair slots
+// of one chunk (the slots of a chunk are its entries' covered tiles, entry
+// by entry in depth order, each entry's tiles row by row): a tile's list
+// starts at the view's segment start plus the lengths of the lists of lower
+// tiles, a chunk's pairs of that tile follow the earlier chunks', and a
+// unit's follow the chunk's slots before the unit.  Inside a unit the pairs
+// keep slot order (an entry covers a tile at most once, so this is depth
+// order).  The result is the stable sort of the emitted pairs by tile.
+//
+// One workgroup per view.  Per tile (one thread each): each live chunk's
+// count becomes the count of the view's earlier chunks (chunks read 16 at a
+// time) and the total is the tile's list length.  Per live chunk: the index
+// of its first unit within the view (exclusive prefix, nlive + 1 words).
+__global__ __launch_bounds__(BLOCK) void k_bin_scan(const uint32_t *__restrict__ hist, int passes, uint32_t limit,
+                                                    int cpv, int chunk, int tiles, const uint4 *__restrict__ binfo,
+                                                    uint32_t *__restrict__ bcnt, uint32_t *__restrict__ btot,
+                                                    uint32_t *__restrict__ blive, uint32_t *__restrict__ bunit)
+{
+    __shared__ uint32_t s_w[4];
+    const int v = blockIdx.x, t = threadIdx.x;
+    // live chunks of the view: those holding some of its kept entries
+    uint32_t kept;
+    (void)block_exclusive_scan(hist[((size_t)v * passes) * 256 + t], kept, s_w);
+    const uint32_t nlive = (min(kept, limit) + (uint32_t)chunk - 1) / (uint32_t)chunk;
+    if (t == 0) blive[v] = nlive;
+    uint32_t *wp = bunit + (size_t)v * (cpv + 1);
+    uint32_t ubase = 0;
+    for (uint32_t j0 = 0; j0 < nlive; j0 += BLOCK) {   // uniform
+        const uint32_t j = j0 + t;
+        const uint32_t n = j < nlive ? (binfo[(size_t)v * cpv + j].w + BIN_WIN - 1) / BIN_WIN : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(n, tot, s_w);
+        if (j < nlive) wp[j] = ubase + ex;
+        ubase += tot;
+    }
+    if (t == 0) wp[nlive] = ubase;
+    if (t >= tiles) return;
+    uint32_t run = 0;
+    uint32_t *col = bcnt + (size_t)v * cpv * 256 + t;
+    for (uint32_t j0 = 0; j0 < nlive; j0 += 16) {
+        uint32_t c[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) c[q] = j0 + q < nlive ? col[(size_t)(j0 + q) * 256] : 0u;
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            if (j0 + q < nlive) col[(size_t)(j0 + q) * 256] = run;
+            run += c[q];
+        }
+    }
+    btot[(size_t)v * 256 + t] = run;
+}
+
+// +1 / -1 at the ends of the column runs [a0, a1] and [b0, b1] of tile row ty
+__device__ __forceinline__ void bin_diff_row(int *s_d, int dw, int ty, int a0, int a1, int b0, int b1)
+{
+    int *d = s_d + ty * dw;
+    atomicAdd(d + a0, 1);
+    atomicAdd(d + a1 + 1, -1);
+    if (b1 >= b0) {
+        atomicAdd(d + b0, 1);
+        atomicAdd(d + b1 + 1, -1);
+    }
+}
+
+// One workgroup per unit.  The chunk's entries' first slots go to LDS; the
+// slots before the unit are counted per tile (difference counts of whole
+// entries, and of the first rows and columns of the entry the unit starts
+// in); the unit's slots get their tile and entry in LDS tables.  Each wave
+// ranks a contiguous part of the unit by tile (eight ballots match equal
+// tiles; a per-wave count per tile in LDS), then the waves' counts give each
+// wave its start in every tile's list.
+__global__ __launch_bounds__(BLOCK) void k_bin_pairs(const float4 *__restrict__ sbox,
+                                                     const uint32_t *__restrict__ poff, int64_t Kp, DevGrid g,
+                                                     int cpv, int V, const uint32_t *__restrict__ uoff,
+                                                     const uint4 *__restrict__ binfo,
+                                                     const uint32_t *__restrict__ bcnt,
+                                                     const uint32_t *__restrict__ btot,
+                                                     const uint32_t *__restrict__ blive,
+                                                     const uint32_t *__restrict__ bunit,
+                                                     const uint32_t *__restrict__ pbase,
+                                                     const uint32_t *__restrict__ pcount, uint32_t *__restrict__ pval)
+{
+    __shared__ uint32_t s_off[BIN_CHUNK_MAX];     // first slot of each entry of the chunk (chunk-relative)
+    __shared__ unsigned short s_own[BIN_WIN];     // entry (index in the chunk) of each slot of the unit
+    __shared__ unsigned char s_tile[BIN_WIN];     // tile of each slot of the unit
+    __shared__ int s_d[BIN_DIFF_WORDS];           // difference counts of the chunk's slots before the unit
+    __shared__ uint32_t s_wc[4][256];             // per wave: its pairs per tile
+    __shared__ uint32_t s_ws[4][256];             // per wave: its start in each tile's list
+    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_probe, s_j, s_ea, s_eb;
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    // the view of this unit: the number of views after the first whose units
+    // start at or before it (uoff is non-decreasing)
+    uint32_t cnt = 0;
+    for (int i = 1 + t; i < V; i += BLOCK) cnt += uoff[i] <= blockIdx.x ? 1u : 0u;
+    uint32_t vcount;
+    (void)block_exclusive_scan(cnt, vcount, s_w);
+    const int v = (int)vcount;
+    const uint32_t u = blockIdx.x - uoff[v];
+    const uint32_t nl = blive[v];
+    const uint32_t *wp = bunit + (size_t)v * (cpv + 1);
+    if (u >= wp[nl]) return;   // uniform: past the view's units
+    // its chunk j (wp[j] <= u < wp[j + 1]): every stride-th chunk probed,
+    // then the chunks of the bracket
+    const uint32_t stride = (nl + BLOCK - 1) / BLOCK;
+    if (t == 0) s_probe = 0;
+    __syncthreads();
+    {
+        const uint32_t c = (uint32_t)t * stride;
+        if (c < nl && wp[c] <= u) atomicMax(&s_probe, c);
+    }
+    __syncthreads();
+    for (uint32_t c = s_probe + t; c < min(nl, s_probe + stride); c += BLOCK)
+        if (wp[c] <= u && u < wp[c + 1]) s_j = c;
+    const int dw = g.tiles_x + 1;
+    for (int i = t; i < g.tiles_y * dw; i += BLOCK) s_d[i] = 0;
+#pragma unroll
+    for (int ww = 0; ww < 4; ww++) s_wc[ww][t] = 0;
+    __syncthreads();
+    const uint32_t j = s_j;
+    const uint4 bi = binfo[(size_t)v * cpv + j];
+    const uint32_t nvis = bi.y, pj = bi.w;
+    const uint32_t s0 = (u - wp[j]) * BIN_WIN, s1 = min(pj, s0 + (uint32_t)BIN_WIN);
+    const size_t row = (size_t)v * Kp + bi.x;
+    for (uint32_t e = t; e < nvis; e += BLOCK) s_off[e] = poff[row + e] - bi.z;
+    __syncthreads();
+    // the entries holding the unit's first and last slots
+    for (uint32_t e = t; e < nvis; e += BLOCK) {
+        const uint32_t o0 = s_off[e], o1 = e + 1 < nvis ? s_off[e + 1] : pj;
+        if (o0 <= s0 && s0 < o1) s_ea = e;
+        if (o0 <= s1 - 1 && s1 - 1 < o1) s_eb = e;
+    }
+    __syncthreads();
+    const uint32_t ea = s_ea, eb = s_eb;
+    // slots before the unit: whole entries before ea, and the first k slots of ea
+    for (uint32_t e = t; e <= ea; e += BLOCK) {
+        const float4 bx = sbox[row + e];
+        int ty0, ty1, a0, a1, b0, b1;
+        (void)tile_rows(bx.y, bx.w, g.H, ty0, ty1);
+        (void)tile_cols(bx.x, bx.z, g.W, g.tiles_x, a0, a1, b0, b1);
+        if (e < ea) {
+            for (int ty = ty0; ty <= ty1; ty++) bin_diff_row(s_d, dw, ty, a0, a1, b0, b1);
+        } else {
+            const int na = a1 - a0 + 1, nc = na + (b1 - b0 + 1);
+            const int k = (int)(s0 - s_off[e]);
+            const int full = k / nc, q = k - full * nc;
+            for (int ty = ty0; ty < ty0 + full; ty++) bin_diff_row(s_d, dw, ty, a0, a1, b0, b1);
+            if (q > 0) {   // the first q columns of the next row, in slot order
+                if (q <= na) bin_diff_row(s_d, dw, ty0 + full, a0, a0 + q - 1, 0, -1);
+                else bin_diff_row(s_d, dw, ty0 + full, a0, a1, b0, b0 + (q - na) - 1);
+            }
+        }
+    }
+    // the unit's slots: tile and entry of each
+    for (uint32_t e = ea + t; e <= eb; e += BLOCK) {
+        const float4 bx = sbox[row + e];
+        int ty0, ty1, a0, a1, b0, b1;
+        (void)tile_rows(bx.y, bx.w, g.H, ty0, ty1);
+        (void)tile_cols(bx.x, bx.z, g.W, g.tiles_x, a0, a1, b0, b1);
+        const int na = a1 - a0 + 1, nc = na + (b1 - b0 + 1);
+        const uint32_t o0 = s_off[e], o1 = e + 1 < nvis ? s_off[e + 1] : pj;
+        const uint32_t x0 = max(o0, s0), x1 = min(o1, s1);
+        const int k0 = (int)(x0 - o0);
+        int ty = ty0 + k0 / nc, q = k0 % nc;
+        for (uint32_t x = x0; x < x1; x++) {
+            const int tx = q < na ? a0 + q : b0 + (q - na);
+            s_tile[x - s0] = (unsigned char)(ty * g.tiles_x + tx);
+            s_own[x - s0] = (unsigned short)e;
+            if (++q == nc) {
+                q = 0;
+                ty++;
+            }
+        }
+    }
+    // start of each tile's run for this unit (the scan's barriers also order
+    // the tables above before their reads)
+    uint32_t start;
+    {
+        const uint32_t c = t < g.tiles ? btot[(size_t)v * 256 + t] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_exclusive_scan(c, total, s_w);
+        start = pbase[v] + ex;
+        if (t < g.tiles) {
+            const int ty = t / g.tiles_x, tx = t - ty * g.tiles_x;
+            int before = 0;
+            for (int x = 0; x <= tx; x++) before += s_d[ty * dw + x];
+            start += bcnt[((size_t)v * cpv + j) * 256 + t] + (uint32_t)before;
+        }
+    }
+    // wave w ranks slots [wb, wb + per) of the unit, 64 per round
+    const uint32_t n = s1 - s0;
+    const uint32_t per = (n + 4 * 64 - 1) / (4 * 64) * 64;
+    const uint32_t wb = (uint32_t)w * per;
+    uint32_t key[BIN_WIN / 256], rk[BIN_WIN / 256], val[BIN_WIN / 256];
+#pragma unroll
+    for (int r = 0; r < BIN_WIN / 256; r++) {
+        key[r] = 0xFFFFFFFFu;
+        rk[r] = 0;
+        val[r] = 0;
+        if ((uint32_t)r * 64 >= per) continue;   // uniform
+        const uint32_t i = wb + (uint32_t)r * 64 + lane;
+        const bool valid = i < n;
+        const uint32_t d = valid ? (uint32_t)s_tile[i] : 0u;
+        if (valid) {
+            key[r] = d;
+            val[r] = (uint32_t)(row + s_own[i]);
+        }
+        // lanes of this round with the same tile
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int bt = 0; bt < 8; bt++) {
+            const uint32_t bit = (d >> bt) & 1u;
+            const uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        const uint32_t below = (uint32_t)count_below(m);
+        const uint32_t before = valid ? s_wc[w][d] : 0u;
+        rk[r] = before + below;
+        if (valid && below == 0) s_wc[w][d] = before + (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    {
+        const uint32_t c0w = s_wc[0][t], c1w = s_wc[1][t], c2w = s_wc[2][t];
+        s_ws[0][t] = start;
+        s_ws[1][t] = start + c0w;
+        s_ws[2][t] = start + c0w + c1w;
+        s_ws[3][t] = start + c0w + c1w + c2w;
+    }
+    __syncthreads();
+    const uint32_t seg_end = pbase[v] + pcount[v];
+#pragma unroll
+    for (int r = 0; r < BIN_WIN / 256; r++)
+        if (key[r] != 0xFFFFFFFFu) {
+            const uint32_t o = s_ws[w][key[r]] + rk[r];
+            if (o < seg_end) pval[o] = val[r];
+        }
 }
 
 // One workgroup per view: the pair sort's digit totals of the view are its
@@ -2038,16 +2313,67 @@ size_t emit_word_count(int V, int64_t Kp)
     return EM_TICKET_STRIDE + (size_t)V * EM_TICKET_STRIDE + 2 * (size_t)V * (size_t)((Kp + BLOCK - 1) / BLOCK);
 }
 
+// chunks of 1024 entries (512 threads, 2 per thread) when there are many,
+// which amortises each chunk's look-back; 256 (1 per thread) for small
+// launches, which keeps the chain of chunks short
+void emit1_chunking(Workspace &ws)
+{
+    const int64_t per_view = std::min<int64_t>(ws.Kp, ws.limit);
+    const bool wide = (size_t)ws.V * (size_t)(per_view / (4 * BLOCK)) >= 1024;
+    ws.em_chunk = wide ? 4 * BLOCK : BLOCK;
+    ws.em_cpv = (int)((per_view + ws.em_chunk - 1) / ws.em_chunk);
+}
+
+size_t bins_bytes(int V, int cpv)
+{
+    const size_t vc = (size_t)V * cpv;
+    return (vc * 256 + vc * 4 + (size_t)V * 256 + (size_t)V + (size_t)V * (cpv + 1)) * 4;
+}
+
+namespace {
+struct BinPtrs {
+    uint32_t *cnt, *tot, *live, *unit;
+    uint4 *info;
+};
+BinPtrs bin_ptrs(Workspace &ws)
+{
+    BinPtrs b;
+    const size_t vc = (size_t)ws.V * ws.em_cpv;
+    b.cnt = ws.bins.as<uint32_t>();
+    b.info = reinterpret_cast<uint4 *>(b.cnt + vc * 256);
+    b.tot = b.cnt + vc * 256 + vc * 4;
+    b.live = b.tot + (size_t)ws.V * 256;
+    b.unit = b.live + ws.V;
+    return b;
+}
+}  // namespace
+
+hipError_t launch_bin_scan(Workspace &ws, const DevGrid &g, hipStream_t st)
+{
+    const BinPtrs b = bin_ptrs(ws);
+    hipLaunchKernelGGL(k_bin_scan, dim3((unsigned)ws.V), dim3(BLOCK), 0, st, ws.hist.as<uint32_t>(), 4, ws.limit,
+                       ws.em_cpv, ws.em_chunk, g.tiles, b.info, b.cnt, b.tot, b.live, b.unit);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_pairs(Workspace &ws, const DevGrid &g, hipStream_t st)
+{
+    if (ws.n_emit_chunks == 0) return hipSuccess;
+    if (ws.em_chunk > BIN_CHUNK_MAX) return hipErrorInvalidValue;
+    const BinPtrs b = bin_ptrs(ws);
+    hipLaunchKernelGGL(k_bin_pairs, dim3((unsigned)ws.n_emit_chunks), dim3(BLOCK), 0, st, ws.sbox.as<float4>(),
+                       ws.poff.as<uint32_t>(), ws.Kp, g, ws.em_cpv, ws.V, ws.d_chunk_off, b.info, b.cnt, b.tot,
+                       b.live, b.unit, ws.d_pbase, ws.d_pcount, ws.pval[0].as<uint32_t>());
+    return hipGetLastError();
+}
+
 hipError_t launch_emit1(const Scene &sc, Workspace &ws, const DevGrid &g, hipStream_t st)
 {
     uint32_t *ew = emit_words(ws);
-    // chunks of 1024 entries (512 threads, 2 per thread) when there are many,
-    // which amortises each chunk's look-back; 256 (1 per thread) for small
-    // launches, which keeps the chain of chunks short
-    const int64_t per_view = std::min<int64_t>(ws.Kp, ws.limit);
-    const bool wide = (size_t)ws.V * (size_t)(per_view / (4 * BLOCK)) >= 1024;
-    const int chunk = wide ? 4 * BLOCK : BLOCK;
-    const int cpv = (int)((per_view + chunk - 1) / chunk);
+    emit1_chunking(ws);
+    const bool wide = ws.em_chunk == 4 * BLOCK;
+    const int cpv = ws.em_cpv;
+    const BinPtrs b = ws.direct_bins ? bin_ptrs(ws) : BinPtrs{nullptr, nullptr, nullptr, nullptr, nullptr};
     auto kern = wide ? k_emit1<2, 2 * BLOCK> : k_emit1<1, BLOCK>;
     hipLaunchKernelGGL(kern, dim3((unsigned)(ws.V * cpv)), dim3(wide ? 2 * BLOCK : BLOCK), 0, st,
                        ws.ggeo.as<GaussGeoPacked>(), sc.K, ws.Kp, ws.centres_p, g,
@@ -2055,7 +2381,7 @@ hipError_t launch_emit1(const Scene &sc, Workspace &ws, const DevGrid &g, hipStr
                        ws.sbox.as<float4>(), ws.vorder.as<uint32_t>(), ws.poff.as<uint32_t>(),
                        ws.counters.as<unsigned long long>(),
                        reinterpret_cast<unsigned long long *>(ew + EM_TICKET_STRIDE + (size_t)ws.V * EM_TICKET_STRIDE),
-                       ew + EM_TICKET_STRIDE, ew, ws.limit, ws.vflag.as<uint32_t>());
+                       ew + EM_TICKET_STRIDE, ew, ws.limit, ws.vflag.as<uint32_t>(), b.cnt, b.info);
     return hipGetLastError();
 }
 
@@ -2078,7 +2404,9 @@ hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st)
         // work items in the same launch
         const unsigned nbi = ws.use_items ? (unsigned)nblk((size_t)ws.n_items) : 0u;
         if (nbi > 0 && ws.items.cap < (size_t)ws.n_items * 16) return hipErrorInvalidValue;   // not allocated
-        hipLaunchKernelGGL(k_ranges_items, dim3((unsigned)ws.V + nbi), dim3(BLOCK), 0, st, ws.hist_b.as<uint32_t>(),
+        // (the list lengths: the direct binning's per-view totals, or the pair sort's digit totals)
+        const uint32_t *lens = ws.direct_bins ? bin_ptrs(ws).tot : ws.hist_b.as<uint32_t>();
+        hipLaunchKernelGGL(k_ranges_items, dim3((unsigned)ws.V + nbi), dim3(BLOCK), 0, st, lens,
                            ws.d_pbase, ws.d_pcount, g.tiles, ws.ranges.as<uint2>(), ws.torder.as<uint32_t>(),
                            ws.d_item_off, ws.d_vinfo, ws.V, ws.n_items, ws.items.as<int4>());
         ws.tiles_ordered = true;

@@ -144,7 +144,7 @@ void release_buffers(Workspace &ws)
                       &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.mred,   &ws.live,   &ws.items_live, &ws.vflag,
                       &ws.items_far, &ws.frec, &ws.fcnt,  &ws.ftile,  &ws.hist_b, &ws.gfeat_tmp, &ws.gmlp_tmp,
                       &ws.rgam,    &ws.rab,     &ws.rloc,    &ws.gP,     &ws.dSP,
-                      &ws.oinv,    &ws.rank,    &ws.lcnt,    &ws.dLv,     &ws.dGp};
+                      &ws.oinv,    &ws.rank,    &ws.lcnt,    &ws.dLv,     &ws.dGp,    &ws.bins};
     for (DevBuf *b : bufs) release(*b);
 }
 
@@ -455,6 +455,8 @@ extern "C" rxgs_status rxgs_create(int device, const rxgs_grid *grid, rxgs_ctx *
     {
         const char *e = std::getenv("RXGS_DETERMINISTIC");
         ctx->deterministic = e && e[0] == '1';
+        const char *ps = std::getenv("RXGS_PAIR_SORT");
+        ctx->pair_sort = ps && ps[0] == '1';
     }
     ctx->grid = *grid;
     DevGrid &g = ctx->g;
@@ -881,6 +883,11 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     const size_t cnt_words = (size_t)4 * V + AMAX_SLOTS + 2 * STAT_WORDS + emit_words_n + 16;   // + far-item count
     WGROW(ctx, ws, ws.counters, cnt_words * 4);
     WGROW(ctx, ws, ws.hist, sort_ws_bytes((uint32_t)VK, 32, V));
+    // grids of at most BIN_MAX_TILES tiles: the first emission counts its
+    // pairs per tile and the pairs are placed in their tile lists directly
+    ws.direct_bins = g.tiles <= BIN_MAX_TILES && !ctx->pair_sort;
+    emit1_chunking(ws);
+    if (ws.direct_bins) WGROW(ctx, ws, ws.bins, bins_bytes(V, ws.em_cpv));
 
     if (save) {
         HIPCHK(ctx, hipMemcpyAsync(ws.centres.p, mode == RXGS_MODE_TX ? tx : rx, (size_t)V * 12,
@@ -913,6 +920,8 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     const uint32_t *h_err = static_cast<const uint32_t *>(ws.h_pinned) + (head_bytes / 4 - 1);
     HIPCHK(ctx, hipMemcpyAsync(h_cnt, ws.counters.p, head_bytes, hipMemcpyDeviceToHost, st));
     HIPCHK(ctx, hipEventRecord(ws.counted, st));
+    // each chunk's start in every tile list, and the views' list lengths
+    if (ws.direct_bins) STAGE(ctx, "bin_scan", launch_bin_scan(ws, g, st));
     // the receivers' layer-1 term depends on nothing above: it runs while the
     // host waits for the counts
     if (ws.use_mlp) {
@@ -1048,18 +1057,26 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     ws.n_items = (int)item_off[V];
     if (nfar >= (1ll << 31)) return fail(ctx, RXGS_E_INVALID, "too many MLP work items");
     ws.n_items_far = (int)nfar;
-    // pair-emission chunks: EM2_CHUNK visible entries of one view each
+    // pair-emission chunks: EM2_CHUNK visible entries of one view each; or,
+    // with direct binning, the placement units of each view: at most one per
+    // BIN_WIN of its pairs plus one per chunk of the first emission
     std::vector<uint32_t> chunk_off(V + 1, 0);
-    for (int v = 0; v < V; v++)
-        chunk_off[v + 1] = chunk_off[v] + (uint32_t)((ws.h_nvis[v] + EM2_CHUNK - 1) / EM2_CHUNK);
+    for (int v = 0; v < V; v++) {
+        const uint64_t n = ws.direct_bins ? (ws.h_pcount[v] + (uint64_t)BIN_WIN - 1) / BIN_WIN + (uint64_t)ws.em_cpv
+                                          : (uint64_t)((ws.h_nvis[v] + EM2_CHUNK - 1) / EM2_CHUNK);
+        if ((uint64_t)chunk_off[v] + n >= (1ull << 31)) return fail(ctx, RXGS_E_INVALID, "too many pair-emission chunks");
+        chunk_off[v + 1] = chunk_off[v] + (uint32_t)n;
+    }
     ws.n_emit_chunks = (int)chunk_off[V];
 
     const size_t P = (size_t)g.H * g.W;
-    WGROW(ctx, ws, ws.pkey[0], std::max<uint64_t>(Dpad, 1) * 4);
-    WGROW(ctx, ws, ws.pkey[1], std::max<uint64_t>(Dpad, 1) * 4);
     WGROW(ctx, ws, ws.pval[0], std::max<uint64_t>(Dpad, 1) * 4);
-    WGROW(ctx, ws, ws.pval[1], std::max<uint64_t>(Dpad, 1) * 4);
-    WGROW(ctx, ws, ws.hist_b, sort_ws_bytes((uint32_t)Dpad, std::max(bits_for((uint64_t)g.tiles), 1), V));
+    if (!ws.direct_bins) {
+        WGROW(ctx, ws, ws.pkey[0], std::max<uint64_t>(Dpad, 1) * 4);
+        WGROW(ctx, ws, ws.pkey[1], std::max<uint64_t>(Dpad, 1) * 4);
+        WGROW(ctx, ws, ws.pval[1], std::max<uint64_t>(Dpad, 1) * 4);
+        WGROW(ctx, ws, ws.hist_b, sort_ws_bytes((uint32_t)Dpad, std::max(bits_for((uint64_t)g.tiles), 1), V));
+    }
     WGROW(ctx, ws, ws.ranges, (size_t)V * g.tiles * 8);
     WGROW(ctx, ws, ws.torder, (size_t)V * g.tiles * 4);
     WGROW(ctx, ws, ws.rad, (size_t)NR * Kp * 8);
@@ -1119,9 +1136,13 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     HIPCHK(ctx, hipMemcpyAsync(dd, hp, stage_bytes, hipMemcpyHostToDevice, st));
     HIPCHK(ctx, hipEventRecord(ws.staged, st));
 
-    // pairs: emit in depth order, stable sort by (view, tile), tile ranges
+    // pairs: placed in their tile lists directly, or emitted in depth order
+    // and stably sorted by (view, tile); then the tile ranges
     int pcur = 0;
-    if (D > 0) {
+    if (D > 0 && ws.direct_bins) {
+        STAGE(ctx, "emit_pairs", launch_bin_pairs(ws, g, st));
+        ws.pair_bits = 0;
+    } else if (D > 0) {
         // (the emission kernel also clears the pair sort's scratch)
         const int sbits = std::max(bits_for((uint64_t)g.tiles), 1);
         STAGE(ctx, "emit_pairs", launch_emit2(ws, g, sort_ws_bytes((uint32_t)Dpad, sbits, V) / 4, st));

@@ -34,6 +34,10 @@ constexpr int STAT_WORDS = 4 * STAT_SLOTS;   // four statistics, u64 each
 constexpr uint32_t SMALL_SORT = 1u << 20;  // sorts up to this length use 1024-key blocks
 constexpr int EM2_PER = 1;               // pair emission: 256-entry sub-chunks per workgroup
 constexpr int EM2_CHUNK = BLOCK * EM2_PER;
+constexpr int BIN_MAX_TILES = 255;       // grids up to this many tiles place their pairs without a pair sort
+constexpr int BIN_DIFF_WORDS = 512;      // LDS words of the per-tile difference counts (tiles_y x (tiles_x + 1))
+constexpr int BIN_WIN = 2048;            // pair slots per placement unit of the direct binning
+constexpr int BIN_CHUNK_MAX = 1024;      // most entries of a chunk of the first emission
 
 // Method constants (Alg. 1 compositing and the readings of its unstated values).
 constexpr float ALPHA_MIN = 1.0f / 255.0f;   // skip threshold on the blend weight
@@ -225,6 +229,13 @@ struct Workspace {
                       // activation bounds, render statistics and the emission's look-back words
     DevBuf hist;      // radix sort scratch (depth sort)
     DevBuf hist_b;    // radix sort scratch (pair sort); per-view tile counts at its start
+    // direct binning (at most BIN_MAX_TILES tiles): per chunk of the first
+    // emission its pairs per tile (then its start in each tile's list), per
+    // chunk (first visible entry, visible entries), per view its list
+    // lengths and its live chunks
+    DevBuf bins;
+    bool direct_bins = false;
+    int em_cpv = 0, em_chunk = 0;   // chunks of the first emission per view, kept entries per chunk
     DevBuf nvis_d;    // V int
     // backward scratch
     DevBuf dS;        // N x Kp float2
@@ -305,6 +316,7 @@ struct rxgs_ctx {
     rxgs::Profiler prof;
     bool near_cut = false;     // emit each view's nearest entries first (rxgs_set_near_cut)
     bool deterministic = false;   // saved renders and their backward sum in fixed orders (rxgs_set_deterministic)
+    bool pair_sort = false;       // bin through the pair sort on every grid (RXGS_PAIR_SORT=1), not only large ones
     int64_t views_redone = 0;  // views redone over all their entries
     hipStream_t aux = nullptr; // private non-blocking stream of the saved-state queries and exports
     rxgs::Allocator alloc;     // the context's device allocations
@@ -360,6 +372,12 @@ size_t sort_ws_bytes(uint32_t n, int bits, int nseg);
 uint32_t *sort_fallback_word(DevBuf &wsb, uint32_t n, int bits, int nseg);
 hipError_t launch_emit1(const Scene &sc, Workspace &ws, const DevGrid &g, hipStream_t st);
 hipError_t launch_emit2(Workspace &ws, const DevGrid &g, size_t sort_words, hipStream_t st);
+// direct binning: the first emission's chunking (sets em_cpv, em_chunk), the
+// bytes of the bins buffer, the per-view scan and the placement of the pairs
+void emit1_chunking(Workspace &ws);
+size_t bins_bytes(int V, int cpv);
+hipError_t launch_bin_scan(Workspace &ws, const DevGrid &g, hipStream_t st);
+hipError_t launch_bin_pairs(Workspace &ws, const DevGrid &g, hipStream_t st);
 uint32_t *emit_words(Workspace &ws);
 size_t emit_word_count(int V, int64_t Kp);
 hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st);

@@ -173,6 +173,7 @@ int64_t estimate_bytes(int32_t mode, int32_t Q, int32_t N, int64_t K, int32_t H,
     b += 2 * (VK / MLP_PAIRS + 128);          // position-block marks (asked for by both TX paths)
     b += V * P * (FAR_RECORDS * 8 + 1) + 4 * V * tiles;   // far records of the radiance prefix, counts, sub-tile marks
     b += 4 * Dpad;                            // emission-order pair keys (deterministic saved states)
+    b += 4 * VK + VK / 12 + 1040 * V + 64;    // direct binning: per-chunk tile counts, extents and units
     b += 20 * (int64_t)N + 80 * V + 16 * (Dpad / SORT_TILE + 1) + 1024;   // descriptors
     b += 12 * (int64_t)Q + 16 * (int64_t)N + 8 * (int64_t)N * P;   // transmitters, receivers, power, spectra
     return b;
