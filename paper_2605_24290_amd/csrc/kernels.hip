@@ -690,13 +690,33 @@ __device__ __forceinline__ void bin_diff_row(int *s_d, int dw, int ty, int a0, i
     }
 }
 
+// Lanes of a wave whose 8-bit keys equal this lane's, among the lanes in
+// `m`: eight ballots, one per key bit; a lane keeps the lanes whose bit
+// agrees with its own (m & (bb xnor own bit), one three-input bit operation
+// per 32-lane half; truth table 0x90 over (m, bb, own bit)).
+__device__ __forceinline__ uint64_t match_key8(uint32_t d, uint64_t m)
+{
+    uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+#pragma unroll
+    for (int bt = 0; bt < 8; bt++) {
+        const uint32_t own = (uint32_t)(((int32_t)(d << (31 - bt))) >> 31);   // all ones if bit bt is set
+        const uint64_t bb = __ballot(own != 0u);
+        lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)bb, own, 0x90);
+        hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(bb >> 32), own, 0x90);
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // One workgroup per unit.  The chunk's entries' first slots go to LDS; the
 // slots before the unit are counted per tile (difference counts of whole
 // entries, and of the first rows and columns of the entry the unit starts
-// in); the unit's slots get their tile and entry in LDS tables.  Each wave
-// ranks a contiguous part of the unit by tile (eight ballots match equal
-// tiles; a per-wave count per tile in LDS), then the waves' counts give each
-// wave its start in every tile's list.
+// in); the unit's entries leave their tile rectangles in LDS and mark where
+// they start in a bitmap of the unit's slots.  Each wave then takes a
+// contiguous part of the unit 64 slots at a time: a slot's entry is the
+// number of marks up to it, its tile follows from its rank inside that
+// entry's rectangle; the wave ranks its slots by tile (match_key8 and a
+// per-wave count per tile in LDS), and the waves' counts give each wave its
+// start in every tile's list.
 __global__ __launch_bounds__(BLOCK) void k_bin_pairs(const float4 *__restrict__ sbox,
                                                      const uint32_t *__restrict__ poff, int64_t Kp, DevGrid g,
                                                      int cpv, int V, const uint32_t *__restrict__ uoff,
@@ -709,11 +729,11 @@ __global__ __launch_bounds__(BLOCK) void k_bin_pairs(const float4 *__restrict__ 
                                                      const uint32_t *__restrict__ pcount, uint32_t *__restrict__ pval)
 {
     __shared__ uint32_t s_off[BIN_CHUNK_MAX];     // first slot of each entry of the chunk (chunk-relative)
-    __shared__ unsigned short s_own[BIN_WIN];     // entry (index in the chunk) of each slot of the unit
-    __shared__ unsigned char s_tile[BIN_WIN];     // tile of each slot of the unit
+    __shared__ uint32_t s_rect[BIN_CHUNK_MAX];    // per entry of the unit: ty0, a0, columns in range a, columns
+    __shared__ uint32_t s_mark[BIN_WIN / 32];     // slots of the unit where an entry after the first starts
+    __shared__ uint32_t s_mpre[BIN_WIN / 32];     // marks in the words before each word
     __shared__ int s_d[BIN_DIFF_WORDS];           // difference counts of the chunk's slots before the unit
-    __shared__ uint32_t s_wc[4][256];             // per wave: its pairs per tile
-    __shared__ uint32_t s_ws[4][256];             // per wave: its start in each tile's list
+    __shared__ uint32_t s_wc[4][256];             // per wave: its pairs per tile, then its start in each list
     __shared__ uint32_t s_w[4];
     __shared__ uint32_t s_probe, s_j, s_ea, s_eb;
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
@@ -732,6 +752,7 @@ __global__ __launch_bounds__(BLOCK) void k_bin_pairs(const float4 *__restrict__ 
     // then the chunks of the bracket
     const uint32_t stride = (nl + BLOCK - 1) / BLOCK;
     if (t == 0) s_probe = 0;
+    if (t < BIN_WIN / 32) s_mark[t] = 0;
     __syncthreads();
     {
         const uint32_t c = (uint32_t)t * stride;
@@ -760,45 +781,39 @@ __global__ __launch_bounds__(BLOCK) void k_bin_pairs(const float4 *__restrict__ 
     }
     __syncthreads();
     const uint32_t ea = s_ea, eb = s_eb;
-    // slots before the unit: whole entries before ea, and the first k slots of ea
-    for (uint32_t e = t; e <= ea; e += BLOCK) {
-        const float4 bx = sbox[row + e];
-        int ty0, ty1, a0, a1, b0, b1;
-        (void)tile_rows(bx.y, bx.w, g.H, ty0, ty1);
-        (void)tile_cols(bx.x, bx.z, g.W, g.tiles_x, a0, a1, b0, b1);
-        if (e < ea) {
-            for (int ty = ty0; ty <= ty1; ty++) bin_diff_row(s_d, dw, ty, a0, a1, b0, b1);
-        } else {
-            const int na = a1 - a0 + 1, nc = na + (b1 - b0 + 1);
-            const int k = (int)(s0 - s_off[e]);
-            const int full = k / nc, q = k - full * nc;
-            for (int ty = ty0; ty < ty0 + full; ty++) bin_diff_row(s_d, dw, ty, a0, a1, b0, b1);
-            if (q > 0) {   // the first q columns of the next row, in slot order
-                if (q <= na) bin_diff_row(s_d, dw, ty0 + full, a0, a0 + q - 1, 0, -1);
-                else bin_diff_row(s_d, dw, ty0 + full, a0, a1, b0, b0 + (q - na) - 1);
-            }
-        }
+    // the boxes of entries 0 .. eb (at most four per thread, loaded together)
+    constexpr int EPT = BIN_CHUNK_MAX / BLOCK;
+    float4 bx[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; q++) {
+        const uint32_t e = (uint32_t)t + (uint32_t)q * BLOCK;
+        bx[q] = e <= eb ? sbox[row + e] : make_float4(0.f, 0.f, -1.f, -1.f);
     }
-    // the unit's slots: tile and entry of each
-    for (uint32_t e = ea + t; e <= eb; e += BLOCK) {
-        const float4 bx = sbox[row + e];
+#pragma unroll
+    for (int q = 0; q < EPT; q++) {
+        const uint32_t e = (uint32_t)t + (uint32_t)q * BLOCK;
+        if (e > eb) continue;
         int ty0, ty1, a0, a1, b0, b1;
-        (void)tile_rows(bx.y, bx.w, g.H, ty0, ty1);
-        (void)tile_cols(bx.x, bx.z, g.W, g.tiles_x, a0, a1, b0, b1);
+        (void)tile_rows(bx[q].y, bx[q].w, g.H, ty0, ty1);
+        (void)tile_cols(bx[q].x, bx[q].z, g.W, g.tiles_x, a0, a1, b0, b1);
         const int na = a1 - a0 + 1, nc = na + (b1 - b0 + 1);
-        const uint32_t o0 = s_off[e], o1 = e + 1 < nvis ? s_off[e + 1] : pj;
-        const uint32_t x0 = max(o0, s0), x1 = min(o1, s1);
-        const int k0 = (int)(x0 - o0);
-        int ty = ty0 + k0 / nc, q = k0 % nc;
-        for (uint32_t x = x0; x < x1; x++) {
-            const int tx = q < na ? a0 + q : b0 + (q - na);
-            s_tile[x - s0] = (unsigned char)(ty * g.tiles_x + tx);
-            s_own[x - s0] = (unsigned short)e;
-            if (++q == nc) {
-                q = 0;
-                ty++;
-            }
+        if (e < ea) {   // slots before the unit: all of this entry's
+            for (int ty = ty0; ty <= ty1; ty++) bin_diff_row(s_d, dw, ty, a0, a1, b0, b1);
+            continue;
         }
+        if (e == ea) {   // its first k slots: whole rows, then the first q columns of the next
+            const int k = (int)(s0 - s_off[e]);
+            const int full = k / nc, qq = k - full * nc;
+            for (int ty = ty0; ty < ty0 + full; ty++) bin_diff_row(s_d, dw, ty, a0, a1, b0, b1);
+            if (qq > 0) {
+                if (qq <= na) bin_diff_row(s_d, dw, ty0 + full, a0, a0 + qq - 1, 0, -1);
+                else bin_diff_row(s_d, dw, ty0 + full, a0, a1, b0, b0 + (qq - na) - 1);
+            }
+        } else {
+            const uint32_t x = s_off[e] - s0;   // inside the unit
+            atomicOr(&s_mark[x >> 5], 1u << (x & 31));
+        }
+        s_rect[e - ea] = (uint32_t)ty0 | ((uint32_t)a0 << 8) | ((uint32_t)na << 16) | ((uint32_t)nc << 24);
     }
     // start of each tile's run for this unit (the scan's barriers also order
     // the tables above before their reads)
@@ -814,8 +829,18 @@ __global__ __launch_bounds__(BLOCK) void k_bin_pairs(const float4 *__restrict__ 
             for (int x = 0; x <= tx; x++) before += s_d[ty * dw + x];
             start += bcnt[((size_t)v * cpv + j) * 256 + t] + (uint32_t)before;
         }
+        if (t < BIN_WIN / 32) {   // marks before each word: one wave's scan of the 64 word counts
+            const uint32_t c1 = (uint32_t)__popc(s_mark[t]);
+            uint32_t x = c1;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(x, off);
+                if (t >= off) x += y;
+            }
+            s_mpre[t] = x - c1;
+        }
     }
-    // wave w ranks slots [wb, wb + per) of the unit, 64 per round
+    __syncthreads();
+    // wave w takes slots [wb, wb + per) of the unit, 64 per round
     const uint32_t n = s1 - s0;
     const uint32_t per = (n + 4 * 64 - 1) / (4 * 64) * 64;
     const uint32_t wb = (uint32_t)w * per;
@@ -828,19 +853,32 @@ __global__ __launch_bounds__(BLOCK) void k_bin_pairs(const float4 *__restrict__ 
         if ((uint32_t)r * 64 >= per) continue;   // uniform
         const uint32_t i = wb + (uint32_t)r * 64 + lane;
         const bool valid = i < n;
-        const uint32_t d = valid ? (uint32_t)s_tile[i] : 0u;
+        uint32_t d = 0;
         if (valid) {
+            // entry: ea plus the marks at or before slot i
+            const uint32_t wd = i >> 5;
+            const uint32_t el = s_mpre[wd] + (uint32_t)__popc(s_mark[wd] & ((2u << (i & 31)) - 1u));
+            const uint32_t rc = s_rect[el];
+            const uint32_t e = ea + el;
+            const int nc = (int)(rc >> 24), na = (int)((rc >> 16) & 255u);
+            const int kk = (int)(s0 + i - s_off[e]);
+            // kk / nc through the reciprocal (exact after the correction: kk < 2^24)
+            int rw = (int)((float)kk * __builtin_amdgcn_rcpf((float)nc));
+            int cc = kk - rw * nc;
+            if (cc < 0) {
+                rw--;
+                cc += nc;
+            } else if (cc >= nc) {
+                rw++;
+                cc -= nc;
+            }
+            const int ty = (int)(rc & 255u) + rw;
+            const int tx = cc < na ? (int)((rc >> 8) & 255u) + cc : cc - na;   // the second run starts at column 0
+            d = (uint32_t)(ty * g.tiles_x + tx);
             key[r] = d;
-            val[r] = (uint32_t)(row + s_own[i]);
+            val[r] = (uint32_t)(row + e);
         }
-        // lanes of this round with the same tile
-        uint64_t m = __ballot(valid);
-#pragma unroll
-        for (int bt = 0; bt < 8; bt++) {
-            const uint32_t bit = (d >> bt) & 1u;
-            const uint64_t bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
-        }
+        const uint64_t m = match_key8(d, __ballot(valid));
         const uint32_t below = (uint32_t)count_below(m);
         const uint32_t before = valid ? s_wc[w][d] : 0u;
         rk[r] = before + below;
@@ -849,17 +887,17 @@ __global__ __launch_bounds__(BLOCK) void k_bin_pairs(const float4 *__restrict__ 
     __syncthreads();
     {
         const uint32_t c0w = s_wc[0][t], c1w = s_wc[1][t], c2w = s_wc[2][t];
-        s_ws[0][t] = start;
-        s_ws[1][t] = start + c0w;
-        s_ws[2][t] = start + c0w + c1w;
-        s_ws[3][t] = start + c0w + c1w + c2w;
+        s_wc[0][t] = start;
+        s_wc[1][t] = start + c0w;
+        s_wc[2][t] = start + c0w + c1w;
+        s_wc[3][t] = start + c0w + c1w + c2w;
     }
     __syncthreads();
     const uint32_t seg_end = pbase[v] + pcount[v];
 #pragma unroll
     for (int r = 0; r < BIN_WIN / 256; r++)
         if (key[r] != 0xFFFFFFFFu) {
-            const uint32_t o = s_ws[w][key[r]] + rk[r];
+            const uint32_t o = s_wc[w][key[r]] + rk[r];
             if (o < seg_end) pval[o] = val[r];
         }
 }
