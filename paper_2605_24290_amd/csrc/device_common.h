@@ -13,6 +13,23 @@ __device__ __forceinline__ int count_below(uint64_t m)
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Lanes of a wave whose 8-bit keys equal this lane's, among the lanes in
+// `m`: eight ballots, one per key bit; a lane keeps the lanes whose bit
+// agrees with its own (m & (bb xnor own bit), one three-input bit operation
+// per 32-lane half; truth table 0x90 over (m, bb, own bit)).
+__device__ __forceinline__ uint64_t match_key8(uint32_t d, uint64_t m)
+{
+    uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+#pragma unroll
+    for (int bt = 0; bt < 8; bt++) {
+        const uint32_t own = (uint32_t)(((int32_t)(d << (31 - bt))) >> 31);   // all ones if bit bt is set
+        const uint64_t bb = __ballot(own != 0u);
+        lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)bb, own, 0x90);
+        hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(bb >> 32), own, 0x90);
+    }
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Blend exponent of one (pixel, record): log2 of o exp(-q/2), with the record
 // holding (-a/2, -b, -c/2) log2(e) and log2(o).  Written with explicit fmaf so
 // that the forward and the backward evaluate bit-identical weights.

@@ -116,9 +116,19 @@ struct alignas(16) GaussGeoPacked {
 // Also the cull bound of each Gaussian, qcull >= q_max trace(Sigma) (rounded
 // up): the vertical variance of any projection is at most
 // lambda_max(Sigma) / (rho^2 del^2) + 0.3 px^2 <= trace(Sigma) / (rho^2 del^2) + 0.3.
+// It also clears the render's counters and the depth sort's scratch (both
+// first used by later kernels of the stream).
 __global__ __launch_bounds__(BLOCK) void k_gauss_prep(const float *__restrict__ soa, int64_t K,
-                                                      GaussGeoPacked *__restrict__ out, float *__restrict__ qcull)
+                                                      GaussGeoPacked *__restrict__ out, float *__restrict__ qcull,
+                                                      uint32_t *__restrict__ z0, size_t n0, uint32_t *__restrict__ z1,
+                                                      size_t n1)
 {
+    {
+        const size_t stride = (size_t)gridDim.x * BLOCK;
+        const size_t i0 = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+        for (size_t i = i0; i < n0; i += stride) z0[i] = 0u;
+        for (size_t i = i0; i < n1; i += stride) z1[i] = 0u;
+    }
     const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (k >= K) return;
     GaussGeo G;
@@ -228,13 +238,66 @@ __device__ __forceinline__ bool maybe_on_grid(float dxf, float dyf, float dzf, f
     return !(vv + R < -0.01f || vv - R > (float)(g.H - 1) + 0.01f);
 }
 
+// Depth keys of one view's tile of PER x BLOCK Gaussians (PER per thread,
+// strided so that loads and stores are coalesced), with the culls of
+// k_project, and the tile's contribution to the depth sort's digit totals:
+// per-wave LDS counts of all four 8-bit digits of the kept keys, summed and
+// added to the view's totals with one atomic per nonzero count.  Many views:
+// tiles of 2048 (fewer atomics); few: tiles of 256 (enough workgroups).
+template <int PER>
+__global__ __launch_bounds__(BLOCK) void k_keys(const GaussGeoPacked *__restrict__ gg,
+                                                const float *__restrict__ qcull, int64_t K, int64_t Kp,
+                                                const float *__restrict__ centres, DevGrid g,
+                                                uint32_t *__restrict__ skey, uint32_t *__restrict__ sval,
+                                                uint32_t *__restrict__ hist)
+{
+    constexpr int KEY_TILE = PER * BLOCK;
+    __shared__ uint32_t h[4][4][256];   // [digit position][wave][digit]
+    const int t = threadIdx.x, w = t >> 6;
+    const int64_t tiles = Kp / KEY_TILE;
+    const int v = (int)(blockIdx.x / (uint64_t)tiles);
+    const int64_t k0 = (int64_t)(blockIdx.x - (uint64_t)v * (uint64_t)tiles) * KEY_TILE;
+#pragma unroll
+    for (int p = 0; p < 4; p++)
+#pragma unroll
+        for (int ww = 0; ww < 4; ww++) h[p][ww][t] = 0;
+    const float cx = centres[3 * v], cy = centres[3 * v + 1], cz = centres[3 * v + 2];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+        const int64_t k = k0 + r * BLOCK + t;
+        uint32_t key = 0xFFFFFFFFu;
+        if (k < K) {
+            const float4 po = *reinterpret_cast<const float4 *>(gg + k);
+            const float qc = qcull[k];
+            const float dxf = __fsub_rn(po.x, cx), dyf = __fsub_rn(po.y, cy), dzf = __fsub_rn(po.z, cz);
+            const float kf = depth_key(dxf, dyf, dzf);
+            if (!(kf < NEAR2) && po.w >= ALPHA_MIN && maybe_on_grid(dxf, dyf, dzf, kf, qc, g))
+                key = __float_as_uint(kf);
+        }
+        const size_t i = (size_t)v * Kp + k;
+        skey[i] = key;
+        sval[i] = (uint32_t)k;
+        if (key != 0xFFFFFFFFu)
+#pragma unroll
+            for (int p = 0; p < 4; p++) atomicAdd(&h[p][w][(key >> (8 * p)) & 255u], 1u);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 4; p++) {
+        const uint32_t c = h[p][0][t] + h[p][1][t] + h[p][2][t] + h[p][3][t];
+        if (c) atomicAdd(&hist[((size_t)v * 4 + p) * 256 + t], c);
+    }
+}
+
 // Depth keys of every (view, Gaussian): one thread per Gaussian (coalesced
 // loads), looping over a chunk of views.  A key is dropped (0xFFFFFFFF) when
 // the Gaussian is too near (FP32 key below 0.2^2 m^2), too faint (opacity
 // below 1/255) or surely off the grid's rows; the emission kernel applies the
 // exact test to the rest.  SAVE: the exact binning boxes, raw keys and
 // opacities are written for export; KEYS = false: only those (a saved
-// state's export, computed when first asked for).
+// state's export, computed when first asked for; a render's keys come from
+// k_keys, which applies the same culls).
 template <bool SAVE, bool KEYS = true>
 __global__ __launch_bounds__(BLOCK) void k_project(
     const GaussGeoPacked *__restrict__ gg, const float *__restrict__ qcull, int64_t K, int64_t Kp,
@@ -688,23 +751,6 @@ __device__ __forceinline__ void bin_diff_row(int *s_d, int dw, int ty, int a0, i
         atomicAdd(d + b0, 1);
         atomicAdd(d + b1 + 1, -1);
     }
-}
-
-// Lanes of a wave whose 8-bit keys equal this lane's, among the lanes in
-// `m`: eight ballots, one per key bit; a lane keeps the lanes whose bit
-// agrees with its own (m & (bb xnor own bit), one three-input bit operation
-// per 32-lane half; truth table 0x90 over (m, bb, own bit)).
-__device__ __forceinline__ uint64_t match_key8(uint32_t d, uint64_t m)
-{
-    uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
-#pragma unroll
-    for (int bt = 0; bt < 8; bt++) {
-        const uint32_t own = (uint32_t)(((int32_t)(d << (31 - bt))) >> 31);   // all ones if bit bt is set
-        const uint64_t bb = __ballot(own != 0u);
-        lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)bb, own, 0x90);
-        hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(bb >> 32), own, 0x90);
-    }
-    return ((uint64_t)hi << 32) | lo;
 }
 
 // One workgroup per unit.  The chunk's entries' first slots go to LDS; the
@@ -2317,24 +2363,20 @@ hipError_t launch_project_exports(Workspace &ws, hipStream_t st)
 }
 
 hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t Kp, const DevGrid &g,
-                          Workspace &ws, bool keep_boxes, size_t counter_words, size_t sort_words, hipStream_t st)
+                          Workspace &ws, size_t counter_words, size_t sort_words, hipStream_t st)
 {
-    if (sc.K > 0)
-        hipLaunchKernelGGL(k_gauss_prep, dim3((unsigned)((sc.K + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st,
-                           sc.soa.as<float>(), sc.K, ws.ggeo.as<GaussGeoPacked>(), ws.qcull.as<float>());
-    const int vchunk = V <= 4 ? 1 : 4;
-    dim3 grid((unsigned)(Kp / BLOCK), (unsigned)((V + vchunk - 1) / vchunk));
-    if (keep_boxes)
-        hipLaunchKernelGGL(k_project<true>, grid, dim3(BLOCK), 0, st, ws.ggeo.as<GaussGeoPacked>(),
-                           ws.qcull.as<float>(), sc.K, Kp, centres, V, vchunk, g, ws.skey[0].as<uint32_t>(),
-                           ws.sval[0].as<uint32_t>(), ws.ext.as<float4>(), ws.rawkey.as<uint32_t>(),
-                           ws.opac.as<float>(), ws.counters.as<uint32_t>(), counter_words, ws.hist.as<uint32_t>(),
-                           sort_words);
-    else
-        hipLaunchKernelGGL(k_project<false>, grid, dim3(BLOCK), 0, st, ws.ggeo.as<GaussGeoPacked>(),
-                           ws.qcull.as<float>(), sc.K, Kp, centres, V, vchunk, g, ws.skey[0].as<uint32_t>(),
-                           ws.sval[0].as<uint32_t>(), nullptr, nullptr, nullptr, ws.counters.as<uint32_t>(),
-                           counter_words, ws.hist.as<uint32_t>(), sort_words);
+    if (Kp % (8 * BLOCK) != 0) return hipErrorInvalidValue;
+    // (the clears need a grid even without Gaussians)
+    const unsigned nb = (unsigned)std::max<int64_t>((sc.K + BLOCK - 1) / BLOCK, 64);
+    hipLaunchKernelGGL(k_gauss_prep, dim3(nb), dim3(BLOCK), 0, st, sc.soa.as<float>(), sc.K,
+                       ws.ggeo.as<GaussGeoPacked>(), ws.qcull.as<float>(), ws.counters.as<uint32_t>(), counter_words,
+                       ws.hist.as<uint32_t>(), sort_words);
+    if (V == 0 || Kp == 0) return hipGetLastError();
+    const bool wide = (uint64_t)V * (uint64_t)(Kp / (8 * BLOCK)) >= 1024;
+    const int per = wide ? 8 : 1;
+    hipLaunchKernelGGL(wide ? k_keys<8> : k_keys<1>, dim3((unsigned)((uint64_t)V * (uint64_t)(Kp / (per * BLOCK)))),
+                       dim3(BLOCK), 0, st, ws.ggeo.as<GaussGeoPacked>(), ws.qcull.as<float>(), sc.K, Kp, centres, g,
+                       ws.skey[0].as<uint32_t>(), ws.sval[0].as<uint32_t>(), ws.hist.as<uint32_t>());
     return hipGetLastError();
 }
 

@@ -904,13 +904,14 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     // then the exact projection in depth order, which compacts the visible
     // entries and counts them and their pairs; the host waits only for those
     // counts
-    // (the key kernel also clears the counters and the depth sort's scratch)
+    // (the projection-terms kernel also clears the counters and the depth
+    // sort's scratch; the key kernel adds the keys' digits to the sort's totals)
     const size_t depth_sort_words = sort_ws_bytes((uint32_t)VK, 32, V) / 4;
     STAGE(ctx, "project",
-          launch_project(sc, ws.centres_p, V, Kp, g, ws, false, cnt_words, depth_sort_words, st));
+          launch_project(sc, ws.centres_p, V, Kp, g, ws, cnt_words, depth_sort_words, st));
     int cur = 0;
     STAGE(ctx, "sort_depth",
-          sort_pairs_u32(ws.skey, ws.sval, ws.hist, cur, (uint32_t)VK, 32, V, Kp, nullptr, st, true));
+          sort_pairs_u32(ws.skey, ws.sval, ws.hist, cur, (uint32_t)VK, 32, V, Kp, nullptr, st, true, true));
     ws.sorted_buf = cur;
     STAGE(ctx, "emit_records", launch_emit1(sc, ws, g, st));
     // one copy: the per-view counts up to and including the emission's error word

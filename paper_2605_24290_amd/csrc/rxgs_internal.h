@@ -335,8 +335,10 @@ struct rxgs_saved {
 namespace rxgs {
 
 // ---- launch wrappers (kernels.hip) ----
+// view-independent projection terms (which also clear the counters and the
+// depth sort's scratch), then the depth keys and the sort's digit totals
 hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t Kp, const DevGrid &g,
-                          Workspace &ws, bool keep_boxes, size_t counter_words, size_t sort_words, hipStream_t st);
+                          Workspace &ws, size_t counter_words, size_t sort_words, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t st);
 // a saved state's binning boxes, raw keys and opacities, from its own centres
 hipError_t launch_project_exports(Workspace &ws, hipStream_t st);
@@ -363,9 +365,11 @@ hipError_t launch_zero_visible(uint32_t *p, int64_t Kp, int wpr, const unsigned 
 // `bits` key bits; segments of seg_len keys (a multiple of 4096), or given per
 // 4096-key unit by segtab; wsb holds sort_ws_bytes(n, bits, nseg) bytes and
 // keeps the per-segment digit totals at its start; zeroed: the caller has
-// cleared those bytes already on this stream
+// cleared those bytes already on this stream; counted: the caller has also
+// added every key's digits to those totals (the histogram pass is skipped)
 hipError_t sort_pairs_u32(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
-                          int64_t seg_len, const int4 *segtab, hipStream_t st, bool zeroed = false);
+                          int64_t seg_len, const int4 *segtab, hipStream_t st, bool zeroed = false,
+                          bool counted = false);
 size_t sort_ws_bytes(uint32_t n, int bits, int nseg);
 // the sort's counter of look-back waits that expired and took the direct count
 // (inside wsb; zeroed with the rest of the scratch)

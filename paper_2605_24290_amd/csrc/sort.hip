@@ -159,13 +159,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict_
     for (int r = 0; r < ITEMS; r++) {
         const bool valid = key[r] != SORT_DROP;
         const uint32_t d = (key[r] >> shift) & 255u;
-        uint64_t m = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; b++) {
-            const uint32_t bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
-        }
+        const uint64_t m = match_key8(d, __ballot(valid));
         const uint32_t below = (uint32_t)count_below(m);
         const uint32_t before = s_wc[w][d];
         rank[r] = before + below;
@@ -283,7 +277,7 @@ int sort_spin_limit()
 
 template <int ITEMS>
 hipError_t sort_run(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
-                    int64_t seg_len, const int4 *segtab, bool zeroed, hipStream_t st)
+                    int64_t seg_len, const int4 *segtab, bool zeroed, bool counted, hipStream_t st)
 {
     constexpr uint32_t TILEN = BLOCK * ITEMS;
     const uint32_t ntiles = (n + TILEN - 1) / TILEN;
@@ -302,8 +296,9 @@ hipError_t sort_run(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t 
         hipError_t e = launch_fill_u32(hist, 0u, words, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_sort_hist<ITEMS>, dim3(ntiles), dim3(BLOCK), 0, st, keys[cur].as<uint32_t>(), n, passes, sm,
-                       hist);
+    if (!counted)
+        hipLaunchKernelGGL(k_sort_hist<ITEMS>, dim3(ntiles), dim3(BLOCK), 0, st, keys[cur].as<uint32_t>(), n, passes,
+                           sm, hist);
     const int spin_max = sort_spin_limit();
     for (int p = 0; p < passes; p++) {
         hipLaunchKernelGGL(k_sort_pass<ITEMS>, dim3(ntiles), dim3(BLOCK), 0, st, keys[cur].as<uint32_t>(),
@@ -339,12 +334,13 @@ size_t sort_ws_bytes(uint32_t n, int bits, int nseg)
 }
 
 hipError_t sort_pairs_u32(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
-                          int64_t seg_len, const int4 *segtab, hipStream_t st, bool zeroed)
+                          int64_t seg_len, const int4 *segtab, hipStream_t st, bool zeroed, bool counted)
 {
     if (n == 0 || bits <= 0) return hipSuccess;
-    if (bits > 32 || nseg <= 0) return hipErrorInvalidValue;
-    if (sort_items_for(n) == 4) return sort_run<4>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, zeroed, st);
-    return sort_run<16>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, zeroed, st);
+    if (bits > 32 || nseg <= 0 || (counted && !zeroed)) return hipErrorInvalidValue;
+    if (sort_items_for(n) == 4)
+        return sort_run<4>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, zeroed, counted, st);
+    return sort_run<16>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, zeroed, counted, st);
 }
 
 }  // namespace rxgs
