@@ -417,7 +417,7 @@ def stored_traffic(kernel: str, workload: str):
     return stored_figure(TRAFFIC_FILE, "hbm_bytes_per_launch", kernel, workload)
 
 
-def roofline_for(entry, mode, workload):
+def roofline_for(entry, mode, workload, K=0):
     """Roofline entry of the stage with the largest time share; the time is the
     stage's average from HIP events the library records on the launch stream."""
     st = entry["stages_ms_per_step"]
@@ -451,14 +451,19 @@ def roofline_for(entry, mode, workload):
                 "unit": "TFLOP/s", "frac": ach / PEAK_FP16_MFMA_TFLOPS, "traffic": None,
                 "work": f"{MLP_MFMA_FLOP_PER_PAIR} FP16 MFMA FLOP x {mlp_pairs_evaluated(entry)} (receiver, "
                         f"position) pairs evaluated ({MLP_FLOP_PER_PAIR} FP32-equivalent)"}
-    if top == "sort_depth":
-        byts = (4 + 4 * SORT_BYTES_PER_KEY_PASS) * sz["sort_keys"]
-        ach = byts / t_s / 1e9
-        return {"kernel": "radix sort (histogram + 4 passes)", "bound": "hbm", "achieved": ach,
-                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": None,
-                "work": f"68 B x {sz['sort_keys']} keys"}
+    # any other stage: its HBM roofline from the per-stage model
+    row = stage_rooflines(entry, mode, K)["stages"].get(top, {})
+    if row.get("bound") == "hbm":
+        ach = row["work"] / t_s / 1e9
+        return {"kernel": STAGE_KERNELS.get(top, top), "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": ach / PEAK_HBM_GBS, "traffic": None, "work": row["work_model"]}
     return {"kernel": top, "bound": "unknown", "achieved": None, "peak": None, "unit": None, "frac": None,
             "traffic": None}
+
+
+# the kernels behind the stage names
+STAGE_KERNELS = {"project": "k_gauss_prep + k_keys", "sort_depth": "k_sort_pass (4 passes)",
+                 "emit_records": "k_emit1", "emit_pairs": "k_bin_pairs (or k_emit2)", "sort_pairs": "k_sort_pass"}
 
 
 # Algorithmic work per stage of one render (bytes that must cross HBM, lane-ops,
@@ -467,7 +472,8 @@ def roofline_for(entry, mode, workload):
 EMIT_RECORD_BYTES = 84 + 56   # per visible entry: order index + projection terms read; record,
                               # box, index and pair slot written
 EMIT_PAIR_BYTES_ENTRY = 20    # per visible entry: box and first pair slot read
-PAIR_BYTES = 8                # per pair: tile and sorted position written
+PAIR_BYTES = 8                # per pair: tile and sorted position written (emission before a pair sort)
+BIN_PAIR_BYTES = 4            # per pair: sorted position written in its tile list (direct binning)
 PAIR_SORT_BYTES = 4 + SORT_BYTES_PER_KEY_PASS   # per pair: histogram read + one 8-bit pass
 
 
@@ -492,10 +498,14 @@ def stage_rooflines(entry, mode, K):
         blend_ops = BLEND_OPS_PER_PAIR * per_view + BLEND_OPS_PER_EXTRA_RX * (sz["composited"] - per_view)
     model = {
         "project": ("hbm", 44 * K + 8 * VK, "44 B per Gaussian read, 8 B per (view, Gaussian) key written"),
-        "sort_depth": ("hbm", (4 + 4 * SORT_BYTES_PER_KEY_PASS) * VK, "68 B per (view, Gaussian) key"),
+        "sort_depth": ("hbm", 4 * SORT_BYTES_PER_KEY_PASS * VK,
+                       f"{4 * SORT_BYTES_PER_KEY_PASS} B per (view, Gaussian) key (4 passes)"),
         "emit_records": ("hbm", EMIT_RECORD_BYTES * nvis, f"{EMIT_RECORD_BYTES} B per visible entry"),
-        "emit_pairs": ("hbm", EMIT_PAIR_BYTES_ENTRY * nvis + PAIR_BYTES * D,
-                       f"{EMIT_PAIR_BYTES_ENTRY} B per visible entry + {PAIR_BYTES} B per pair"),
+        "emit_pairs": (("hbm", EMIT_PAIR_BYTES_ENTRY * nvis + PAIR_BYTES * D,
+                        f"{EMIT_PAIR_BYTES_ENTRY} B per visible entry + {PAIR_BYTES} B per pair")
+                       if "sort_pairs" in st else
+                       ("hbm", EMIT_PAIR_BYTES_ENTRY * nvis + BIN_PAIR_BYTES * D,
+                        f"{EMIT_PAIR_BYTES_ENTRY} B per visible entry + {BIN_PAIR_BYTES} B per pair (direct binning)")),
         "sort_pairs": ("hbm", PAIR_SORT_BYTES * D, f"{PAIR_SORT_BYTES} B per pair"),
         "mlp_pairs": ("mfma", MLP_MFMA_FLOP_PER_PAIR * mlp_pairs_evaluated(entry),
                       f"{MLP_MFMA_FLOP_PER_PAIR} FP16 MFMA FLOP per (receiver, position) pair evaluated "
@@ -619,7 +629,7 @@ def main():
                    "mode": args.mode},
         "fused": head,
         "other_modes": {k: v for k, v in res.items() if k != args.mode},
-        "roofline": roofline_for(head, args.mode, workload),
+        "roofline": roofline_for(head, args.mode, workload, wl.scene.K),
         "stage_roofline": stage_rooflines(head, args.mode, wl.scene.K),
     }
     if not args.no_train:
