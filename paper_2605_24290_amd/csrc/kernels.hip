@@ -364,10 +364,12 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, size_t n)
 }
 
 // Emission, part 1 (after the depth sort): the exact projection of every kept
-// entry in depth order.  A workgroup takes the next chunk of 256 x PER sorted
-// entries of its view from the view's ticket (PER consecutive entries per
-// thread: 4 when there are many chunks, which amortises each chunk's
-// look-back; 1 for small launches, which keeps the chain of chunks short), evaluates them (FP64, the same code as the key kernel's exports)
+// entry in depth order.  The workgroup of index i takes chunk i of its view
+// (NT x PER sorted entries, PER consecutive ones per thread; 1024 when there
+// are many chunks, which amortises each chunk's look-back, 256 for small
+// launches, which keeps the chain of chunks short); it loads its entries'
+// Gaussian indices before it knows how many the sort kept (the depth sort's
+// first pass left that count per view), evaluates them (FP64, the same code as the key kernel's exports)
 // and compacts the visible ones (at least one tile covered): their depth rank
 // among the view's visible Gaussians and their first pair slot come from one
 // workgroup scan of the per-thread (visible, pairs) counts plus a
@@ -379,7 +381,6 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, size_t n)
 // a view) set bits of the error word, which the host checks.
 constexpr uint64_t EM_AGG = 1ull << 62, EM_PRE = 1ull << 63;
 constexpr int EM_SPIN_MAX = 1 << 20;
-constexpr int EM_TICKET_STRIDE = 32;   // one ticket counter per view, 128 bytes apart
 
 __device__ __forceinline__ uint64_t em_pack(uint64_t flag, uint32_t vis, uint32_t pairs)
 {
@@ -421,38 +422,43 @@ __device__ __forceinline__ uint2 block_exclusive_scan2(uint32_t x, uint32_t y, u
 template <int EM1_PER, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_emit1(
     const GaussGeoPacked *__restrict__ gg, int64_t K, int64_t Kp, const float *__restrict__ centres, DevGrid g,
-    const uint32_t *__restrict__ order, const uint32_t *__restrict__ hist, int passes, int cpv,
+    const uint32_t *__restrict__ order, const uint32_t *__restrict__ kept, int cpv,
     float4 *__restrict__ srec, float4 *__restrict__ sbox, uint32_t *__restrict__ vorder, uint32_t *__restrict__ poff,
-    unsigned long long *__restrict__ counters, unsigned long long *status, uint32_t *tickets, uint32_t *err,
+    unsigned long long *__restrict__ counters, unsigned long long *status, uint32_t *err,
     uint32_t limit, uint32_t *__restrict__ vflag, uint32_t *__restrict__ bcnt, uint4 *__restrict__ binfo)
 {
     constexpr int NW = NT / 64;
     __shared__ uint2 s_w2[NW];
-    __shared__ uint32_t s_chunk, s_vbase, s_pbase;
+    __shared__ uint32_t s_vbase, s_pbase;
     __shared__ int s_d[BIN_DIFF_WORDS];
     constexpr int EM1_CHUNK = NT * EM1_PER;
     const int t = threadIdx.x;
     const int v = (int)(blockIdx.x / (unsigned)cpv);
+    const uint32_t chunk = blockIdx.x - (uint32_t)v * (uint32_t)cpv;
     const int dw = g.tiles_x + 1;   // row stride of the per-tile difference counts
-    if (t == 0) s_chunk = atomicAdd(tickets + (size_t)v * EM_TICKET_STRIDE, 1u);
-    if (bcnt)
-        for (int i = t; i < g.tiles_y * dw; i += NT) s_d[i] = 0;
-    // entries the depth sort kept for this view: the sum of its digit totals
-    uint2 seg2;
-    (void)block_exclusive_scan2<NW>(t < 256 ? hist[((size_t)v * passes) * 256 + t] : 0u, 0u, seg2, s_w2);
-    // only the nearest `limit` of them are emitted; record whether that cut any
-    const uint32_t seg_n = min(seg2.x, limit);
-    const uint32_t chunk = s_chunk;
-    if (t == 0 && chunk == 0) vflag[v] = seg2.x > limit ? 1u : 0u;
     const int64_t s0 = (int64_t)chunk * EM1_CHUNK;
-    // uniform; chunks with higher tickets of this view are past the end too
-    if (s0 >= (int64_t)seg_n) return;
     const int64_t sb = s0 + (int64_t)t * EM1_PER;
-    const float cx = centres[3 * v], cy = centres[3 * v + 1], cz = centres[3 * v + 2];
+    // the chunk's sorted Gaussian indices, loaded before the kept count is
+    // known (positions past it are dropped below; the index is clamped before use)
     uint32_t kk[EM1_PER], nt[EM1_PER];
-    float4 r0[EM1_PER], r1[EM1_PER], box[EM1_PER];
 #pragma unroll
-    for (int j = 0; j < EM1_PER; j++) kk[j] = sb + j < (int64_t)seg_n ? order[(size_t)v * Kp + sb + j] : 0xFFFFFFFFu;
+    for (int j = 0; j < EM1_PER; j++) kk[j] = sb + j < Kp ? order[(size_t)v * Kp + sb + j] : 0xFFFFFFFFu;
+    // entries the depth sort kept for this view; only the nearest `limit` of
+    // them are emitted: record whether that cut any
+    const uint32_t kv = kept[(size_t)v * KEPT_STRIDE];
+    const uint32_t seg_n = min(kv, limit);
+    if (t == 0 && chunk == 0) vflag[v] = kv > limit ? 1u : 0u;
+    // uniform; the view's later chunks are past the end too
+    if (s0 >= (int64_t)seg_n) return;
+    if (bcnt) {
+        for (int i = t; i < g.tiles_y * dw; i += NT) s_d[i] = 0;
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < EM1_PER; j++)
+        if (sb + j >= (int64_t)seg_n) kk[j] = 0xFFFFFFFFu;
+    const float cx = centres[3 * v], cy = centres[3 * v + 1], cz = centres[3 * v + 2];
+    float4 r0[EM1_PER], r1[EM1_PER], box[EM1_PER];
     uint32_t nvis = 0, npairs = 0;
 #pragma unroll
     for (int j = 0; j < EM1_PER; j++) {
@@ -699,9 +705,12 @@ __global__ __launch_bounds__(BLOCK) void k_emit2(const float4 *__restrict__ sbox
 // order).  The result is the stable sort of the emitted pairs by tile.
 //
 // One workgroup per view.  Per tile (one thread each): each live chunk's
-// count becomes the count of the view's earlier chunks (chunks read 16 at a
-// time) and the total is the tile's list length.  Per live chunk: the index
+// count becomes the count of the view's earlier chunks (chunks read
+// BIN_SCAN_BATCH at a time, all in flight together) and the total is the
+// tile's list length.  Per live chunk: the index
 // of its first unit within the view (exclusive prefix, nlive + 1 words).
+constexpr int BIN_SCAN_BATCH = 16;
+
 __global__ __launch_bounds__(BLOCK) void k_bin_scan(const uint32_t *__restrict__ hist, int passes, uint32_t limit,
                                                     int cpv, int chunk, int tiles, const uint4 *__restrict__ binfo,
                                                     uint32_t *__restrict__ bcnt, uint32_t *__restrict__ btot,
@@ -728,12 +737,12 @@ __global__ __launch_bounds__(BLOCK) void k_bin_scan(const uint32_t *__restrict__
     if (t >= tiles) return;
     uint32_t run = 0;
     uint32_t *col = bcnt + (size_t)v * cpv * 256 + t;
-    for (uint32_t j0 = 0; j0 < nlive; j0 += 16) {
-        uint32_t c[16];
+    for (uint32_t j0 = 0; j0 < nlive; j0 += BIN_SCAN_BATCH) {
+        uint32_t c[BIN_SCAN_BATCH];
 #pragma unroll
-        for (int q = 0; q < 16; q++) c[q] = j0 + q < nlive ? col[(size_t)(j0 + q) * 256] : 0u;
+        for (int q = 0; q < BIN_SCAN_BATCH; q++) c[q] = j0 + q < nlive ? col[(size_t)(j0 + q) * 256] : 0u;
 #pragma unroll
-        for (int q = 0; q < 16; q++) {
+        for (int q = 0; q < BIN_SCAN_BATCH; q++) {
             if (j0 + q < nlive) col[(size_t)(j0 + q) * 256] = run;
             run += c[q];
         }
@@ -2380,9 +2389,10 @@ hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t 
     return hipGetLastError();
 }
 
-// the emission's error word, per-view tickets and per-chunk 64-bit look-back
-// status, after the render statistics in the counters buffer (the offset is
-// even, so the status words are 8-byte aligned)
+// the emission's error word, per view the depth sort's kept count (KEPT_STRIDE
+// words apart) and per-chunk 64-bit look-back status, after the render
+// statistics in the counters buffer (the offset is even, so the status words
+// are 8-byte aligned)
 uint32_t *emit_words(Workspace &ws)
 {
     return ws.counters.as<uint32_t>() + (size_t)4 * ws.V + AMAX_SLOTS + 2 * STAT_WORDS;
@@ -2390,7 +2400,7 @@ uint32_t *emit_words(Workspace &ws)
 
 size_t emit_word_count(int V, int64_t Kp)
 {
-    return EM_TICKET_STRIDE + (size_t)V * EM_TICKET_STRIDE + 2 * (size_t)V * (size_t)((Kp + BLOCK - 1) / BLOCK);
+    return KEPT_STRIDE + (size_t)V * KEPT_STRIDE + 2 * (size_t)V * (size_t)((Kp + BLOCK - 1) / BLOCK);
 }
 
 // chunks of 1024 entries (512 threads, 2 per thread) when there are many,
@@ -2457,11 +2467,11 @@ hipError_t launch_emit1(const Scene &sc, Workspace &ws, const DevGrid &g, hipStr
     auto kern = wide ? k_emit1<2, 2 * BLOCK> : k_emit1<1, BLOCK>;
     hipLaunchKernelGGL(kern, dim3((unsigned)(ws.V * cpv)), dim3(wide ? 2 * BLOCK : BLOCK), 0, st,
                        ws.ggeo.as<GaussGeoPacked>(), sc.K, ws.Kp, ws.centres_p, g,
-                       ws.sval[ws.sorted_buf].as<uint32_t>(), ws.hist.as<uint32_t>(), 4, cpv, ws.srec.as<float4>(),
+                       ws.sval[ws.sorted_buf].as<uint32_t>(), ew + KEPT_STRIDE, cpv, ws.srec.as<float4>(),
                        ws.sbox.as<float4>(), ws.vorder.as<uint32_t>(), ws.poff.as<uint32_t>(),
                        ws.counters.as<unsigned long long>(),
-                       reinterpret_cast<unsigned long long *>(ew + EM_TICKET_STRIDE + (size_t)ws.V * EM_TICKET_STRIDE),
-                       ew + EM_TICKET_STRIDE, ew, ws.limit, ws.vflag.as<uint32_t>(), b.cnt, b.info);
+                       reinterpret_cast<unsigned long long *>(ew + KEPT_STRIDE + (size_t)ws.V * KEPT_STRIDE), ew,
+                       ws.limit, ws.vflag.as<uint32_t>(), b.cnt, b.info);
     return hipGetLastError();
 }
 

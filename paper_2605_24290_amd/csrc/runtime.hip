@@ -911,7 +911,8 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
           launch_project(sc, ws.centres_p, V, Kp, g, ws, cnt_words, depth_sort_words, st));
     int cur = 0;
     STAGE(ctx, "sort_depth",
-          sort_pairs_u32(ws.skey, ws.sval, ws.hist, cur, (uint32_t)VK, 32, V, Kp, nullptr, st, true, true));
+          sort_pairs_u32(ws.skey, ws.sval, ws.hist, cur, (uint32_t)VK, 32, V, Kp, nullptr, st, true, true,
+                         emit_words(ws) + KEPT_STRIDE));
     ws.sorted_buf = cur;
     STAGE(ctx, "emit_records", launch_emit1(sc, ws, g, st));
     // one copy: the per-view counts up to and including the emission's error word

@@ -36,6 +36,7 @@ constexpr int EM2_PER = 1;               // pair emission: 256-entry sub-chunks 
 constexpr int EM2_CHUNK = BLOCK * EM2_PER;
 constexpr int BIN_MAX_TILES = 255;       // grids up to this many tiles place their pairs without a pair sort
 constexpr int BIN_DIFF_WORDS = 512;      // LDS words of the per-tile difference counts (tiles_y x (tiles_x + 1))
+constexpr int KEPT_STRIDE = 32;          // words between the per-view kept counts the depth sort leaves
 constexpr int BIN_WIN = 2048;            // pair slots per placement unit of the direct binning
 constexpr int BIN_CHUNK_MAX = 1024;      // most entries of a chunk of the first emission
 
@@ -366,10 +367,12 @@ hipError_t launch_zero_visible(uint32_t *p, int64_t Kp, int wpr, const unsigned 
 // 4096-key unit by segtab; wsb holds sort_ws_bytes(n, bits, nseg) bytes and
 // keeps the per-segment digit totals at its start; zeroed: the caller has
 // cleared those bytes already on this stream; counted: the caller has also
-// added every key's digits to those totals (the histogram pass is skipped)
+// added every key's digits to those totals (the histogram pass is skipped);
+// seg_kept: the first pass writes each segment's surviving key count there
+// (KEPT_STRIDE words apart)
 hipError_t sort_pairs_u32(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
                           int64_t seg_len, const int4 *segtab, hipStream_t st, bool zeroed = false,
-                          bool counted = false);
+                          bool counted = false, uint32_t *seg_kept = nullptr);
 size_t sort_ws_bytes(uint32_t n, int bits, int nseg);
 // the sort's counter of look-back waits that expired and took the direct count
 // (inside wsb; zeroed with the rest of the scratch)

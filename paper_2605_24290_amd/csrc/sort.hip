@@ -3,13 +3,12 @@
 //
 // The keys are split into independent segments (one per view: the per-view
 // depth sort, and the per-view padded pair lists).  One histogram kernel reads
-// every key once and counts all digits of all passes per segment.  Each pass
-// is then a single kernel: a workgroup takes the next 4096-key tile of its
-// segment in order from the segment's atomic ticket (one counter per segment,
-// so tickets of different segments do not serialise on one address), ranks
-// its keys stably, publishes its per-digit counts and obtains the counts of
-// the earlier tiles of its segment by decoupled look-back, and writes its
-// keys digit run by digit run.  Ranking is wave
+// every key once and counts all digits of all passes per segment (or the
+// caller has counted them while writing the keys).  Each pass is then a
+// single kernel: the workgroup of index i takes tile i (4096 keys; segments
+// are runs of whole tiles), ranks its keys stably, publishes its per-digit
+// counts and obtains the counts of the earlier tiles of its segment by
+// decoupled look-back, and writes its keys digit run by digit run.  Ranking is wave
 // synchronous: each wave owns a contiguous quarter of the tile, takes its keys
 // 64 at a time in index order, matches equal digits with 8 ballots and keeps
 // running per-digit counts in LDS, so the only workgroup barriers are the ones
@@ -21,10 +20,9 @@
 // the segment's start, and the later passes only touch that prefix (the
 // segment's surviving count is the sum of its digit totals).
 //
-// Look-back progress: a workgroup only waits for tiles with a smaller ticket,
-// whose workgroups took their tickets earlier and are therefore resident; they
-// publish their aggregates before waiting themselves, so every wait ends.  A
-// wait is still bounded: on expiry the workgroup counts the digit totals of
+// Look-back progress: a workgroup only waits for tiles with a smaller index,
+// whose workgroups were dispatched earlier; they publish their aggregates
+// before waiting themselves, so every wait ends.  A wait is still bounded: on expiry the workgroup counts the digit totals of
 // the segment's earlier tiles directly from their input keys (exact, slow),
 // publishes them like a look-back result and adds one to the sort's
 // fallback counter, so the order is right either way.
@@ -40,7 +38,6 @@ constexpr uint32_t LB_AGG = 1u << 30;    // status word: aggregate of this tile 
 constexpr uint32_t LB_PRE = 1u << 31;    // status word: inclusive prefix up to this tile
 constexpr uint32_t LB_MASK = LB_AGG - 1;
 constexpr uint32_t SORT_DROP = 0xFFFFFFFFu;   // dropped key
-constexpr int TICKET_STRIDE = 32;             // one ticket counter per 128-byte line
 
 struct SortSeg {
     uint32_t seg_blocks;   // uniform segments of this many tiles (0: table or one segment)
@@ -103,7 +100,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict_
                                                      uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                      uint32_t n, int pass, int passes, SortSeg sm,
                                                      const uint32_t *__restrict__ hist, uint32_t *status,
-                                                     uint32_t *ticket, uint32_t *err, int spin_max)
+                                                     uint32_t *seg_kept, uint32_t *err, int spin_max)
 {
     constexpr int TILEN = BLOCK * ITEMS;
     constexpr int WCH = 64 * ITEMS;   // keys per wave
@@ -115,7 +112,6 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict_
     __shared__ uint32_t s_w[4];
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     const int shift = 8 * pass;
-    (void)ticket;
     // the workgroup's tile is its index, and its segment follows from it
     // (segments are runs of whole tiles); workgroups are dispatched in index
     // order, so a look-back waits only for tiles already dispatched (and the
@@ -142,6 +138,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict_
     // digit starts in the segment (from its digit totals) and its surviving count
     uint32_t seg_n;
     const uint32_t dbase = block_exclusive_scan(hist[((size_t)seg * passes + pass) * 256 + t], seg_n, s_w);
+    if (pass == 0 && seg_kept && tile == first && t == 0) seg_kept[(size_t)seg * KEPT_STRIDE] = seg_n;
     // input positions of this tile that hold keys: all (first pass), or the
     // part of the segment's surviving prefix inside the tile (later passes)
     size_t lim = lim0;
@@ -277,7 +274,8 @@ int sort_spin_limit()
 
 template <int ITEMS>
 hipError_t sort_run(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
-                    int64_t seg_len, const int4 *segtab, bool zeroed, bool counted, hipStream_t st)
+                    int64_t seg_len, const int4 *segtab, bool zeroed, bool counted, uint32_t *seg_kept,
+                    hipStream_t st)
 {
     constexpr uint32_t TILEN = BLOCK * ITEMS;
     const uint32_t ntiles = (n + TILEN - 1) / TILEN;
@@ -290,8 +288,7 @@ hipError_t sort_run(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t 
     if (wsb.cap < words * 4) return hipErrorOutOfMemory;
     uint32_t *hist = wsb.as<uint32_t>();
     uint32_t *status = hist + (size_t)nseg * passes * 256;
-    uint32_t *tickets = status + (size_t)passes * ntiles * 256;   // [pass][segment], TICKET_STRIDE apart
-    uint32_t *err = tickets + (size_t)passes * nseg * TICKET_STRIDE;
+    uint32_t *err = status + (size_t)passes * ntiles * 256;
     if (!zeroed) {
         hipError_t e = launch_fill_u32(hist, 0u, words, st);
         if (e != hipSuccess) return e;
@@ -303,8 +300,7 @@ hipError_t sort_run(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t 
     for (int p = 0; p < passes; p++) {
         hipLaunchKernelGGL(k_sort_pass<ITEMS>, dim3(ntiles), dim3(BLOCK), 0, st, keys[cur].as<uint32_t>(),
                            vals[cur].as<uint32_t>(), keys[cur ^ 1].as<uint32_t>(), vals[cur ^ 1].as<uint32_t>(), n, p,
-                           passes, sm, hist, status + (size_t)p * ntiles * 256,
-                           tickets + (size_t)p * nseg * TICKET_STRIDE, err, spin_max);
+                           passes, sm, hist, status + (size_t)p * ntiles * 256, seg_kept, err, spin_max);
         cur ^= 1;
     }
     return hipGetLastError();
@@ -320,8 +316,7 @@ uint32_t *sort_fallback_word(DevBuf &wsb, uint32_t n, int bits, int nseg)
     const uint32_t tilen = BLOCK * (uint32_t)sort_items_for(n);
     const size_t ntiles = (n + tilen - 1) / tilen;
     const size_t passes = (size_t)(bits + 7) / 8;
-    return wsb.as<uint32_t>() + (size_t)nseg * passes * 256 + passes * ntiles * 256 +
-           passes * (size_t)nseg * TICKET_STRIDE;
+    return wsb.as<uint32_t>() + (size_t)nseg * passes * 256 + passes * ntiles * 256;
 }
 
 size_t sort_ws_bytes(uint32_t n, int bits, int nseg)
@@ -329,18 +324,18 @@ size_t sort_ws_bytes(uint32_t n, int bits, int nseg)
     const uint32_t tilen = BLOCK * (uint32_t)sort_items_for(n);
     const size_t ntiles = (n + tilen - 1) / tilen;
     const size_t passes = (size_t)(std::max(bits, 1) + 7) / 8;
-    return ((size_t)std::max(nseg, 1) * passes * 256 + passes * ntiles * 256 +
-            passes * (size_t)std::max(nseg, 1) * TICKET_STRIDE + 64) * 4;
+    return ((size_t)std::max(nseg, 1) * passes * 256 + passes * ntiles * 256 + 64) * 4;
 }
 
 hipError_t sort_pairs_u32(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
-                          int64_t seg_len, const int4 *segtab, hipStream_t st, bool zeroed, bool counted)
+                          int64_t seg_len, const int4 *segtab, hipStream_t st, bool zeroed, bool counted,
+                          uint32_t *seg_kept)
 {
     if (n == 0 || bits <= 0) return hipSuccess;
     if (bits > 32 || nseg <= 0 || (counted && !zeroed)) return hipErrorInvalidValue;
     if (sort_items_for(n) == 4)
-        return sort_run<4>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, zeroed, counted, st);
-    return sort_run<16>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, zeroed, counted, st);
+        return sort_run<4>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, zeroed, counted, seg_kept, st);
+    return sort_run<16>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, zeroed, counted, seg_kept, st);
 }
 
 }  // namespace rxgs
