@@ -242,14 +242,15 @@ __device__ __forceinline__ bool maybe_on_grid(float dxf, float dyf, float dzf, f
 // strided so that loads and stores are coalesced), with the culls of
 // k_project, and the tile's contribution to the depth sort's digit totals:
 // per-wave LDS counts of all four 8-bit digits of the kept keys, summed and
-// added to the view's totals with one atomic per nonzero count.  Many views:
+// added to the view's totals with one atomic per nonzero count (the values,
+// the Gaussian indices, are not written: the sort's first pass takes each
+// key's index in its view's segment).  Many views:
 // tiles of 2048 (fewer atomics); few: tiles of 256 (enough workgroups).
 template <int PER>
 __global__ __launch_bounds__(BLOCK) void k_keys(const GaussGeoPacked *__restrict__ gg,
                                                 const float *__restrict__ qcull, int64_t K, int64_t Kp,
                                                 const float *__restrict__ centres, DevGrid g,
-                                                uint32_t *__restrict__ skey, uint32_t *__restrict__ sval,
-                                                uint32_t *__restrict__ hist)
+                                                uint32_t *__restrict__ skey, uint32_t *__restrict__ hist)
 {
     constexpr int KEY_TILE = PER * BLOCK;
     __shared__ uint32_t h[4][4][256];   // [digit position][wave][digit]
@@ -275,9 +276,7 @@ __global__ __launch_bounds__(BLOCK) void k_keys(const GaussGeoPacked *__restrict
             if (!(kf < NEAR2) && po.w >= ALPHA_MIN && maybe_on_grid(dxf, dyf, dzf, kf, qc, g))
                 key = __float_as_uint(kf);
         }
-        const size_t i = (size_t)v * Kp + k;
-        skey[i] = key;
-        sval[i] = (uint32_t)k;
+        skey[(size_t)v * Kp + k] = key;   // (its value, k, is the sort's index in the view's segment)
         if (key != 0xFFFFFFFFu)
 #pragma unroll
             for (int p = 0; p < 4; p++) atomicAdd(&h[p][w][(key >> (8 * p)) & 255u], 1u);
@@ -2385,7 +2384,7 @@ hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t 
     const int per = wide ? 8 : 1;
     hipLaunchKernelGGL(wide ? k_keys<8> : k_keys<1>, dim3((unsigned)((uint64_t)V * (uint64_t)(Kp / (per * BLOCK)))),
                        dim3(BLOCK), 0, st, ws.ggeo.as<GaussGeoPacked>(), ws.qcull.as<float>(), sc.K, Kp, centres, g,
-                       ws.skey[0].as<uint32_t>(), ws.sval[0].as<uint32_t>(), ws.hist.as<uint32_t>());
+                       ws.skey[0].as<uint32_t>(), ws.hist.as<uint32_t>());
     return hipGetLastError();
 }
 

@@ -912,7 +912,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     int cur = 0;
     STAGE(ctx, "sort_depth",
           sort_pairs_u32(ws.skey, ws.sval, ws.hist, cur, (uint32_t)VK, 32, V, Kp, nullptr, st, true, true,
-                         emit_words(ws) + KEPT_STRIDE));
+                         emit_words(ws) + KEPT_STRIDE, SORT_VALS_INDEX | SORT_VALS_ONLY));
     ws.sorted_buf = cur;
     STAGE(ctx, "emit_records", launch_emit1(sc, ws, g, st));
     // one copy: the per-view counts up to and including the emission's error word

@@ -37,6 +37,8 @@ constexpr int EM2_CHUNK = BLOCK * EM2_PER;
 constexpr int BIN_MAX_TILES = 255;       // grids up to this many tiles place their pairs without a pair sort
 constexpr int BIN_DIFF_WORDS = 512;      // LDS words of the per-tile difference counts (tiles_y x (tiles_x + 1))
 constexpr int KEPT_STRIDE = 32;          // words between the per-view kept counts the depth sort leaves
+constexpr int SORT_VALS_INDEX = 1;       // sort flag: a key's value is its index in its segment (not read)
+constexpr int SORT_VALS_ONLY = 2;        // sort flag: the sorted keys are not needed (last pass writes values only)
 constexpr int BIN_WIN = 2048;            // pair slots per placement unit of the direct binning
 constexpr int BIN_CHUNK_MAX = 1024;      // most entries of a chunk of the first emission
 
@@ -372,7 +374,7 @@ hipError_t launch_zero_visible(uint32_t *p, int64_t Kp, int wpr, const unsigned 
 // (KEPT_STRIDE words apart)
 hipError_t sort_pairs_u32(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
                           int64_t seg_len, const int4 *segtab, hipStream_t st, bool zeroed = false,
-                          bool counted = false, uint32_t *seg_kept = nullptr);
+                          bool counted = false, uint32_t *seg_kept = nullptr, int flags = 0);
 size_t sort_ws_bytes(uint32_t n, int bits, int nseg);
 // the sort's counter of look-back waits that expired and took the direct count
 // (inside wsb; zeroed with the rest of the scratch)

@@ -98,7 +98,7 @@ template <int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict__ kin,
                                                      const uint32_t *__restrict__ vin,
                                                      uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
-                                                     uint32_t n, int pass, int passes, SortSeg sm,
+                                                     uint32_t n, int pass, int passes, SortSeg sm, int flags,
                                                      const uint32_t *__restrict__ hist, uint32_t *status,
                                                      uint32_t *seg_kept, uint32_t *err, int spin_max)
 {
@@ -131,7 +131,8 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict_
         const size_t idx = base + (size_t)r * 64 + lane;
         const bool in = idx < lim0;
         key[r] = in ? kin[idx] : SORT_DROP;
-        val[r] = in ? vin[idx] : 0u;
+        // (first pass with SORT_VALS_INDEX: a key's value is its index in its segment)
+        val[r] = !in ? 0u : (pass == 0 && (flags & SORT_VALS_INDEX)) ? (uint32_t)(idx - seg0) : vin[idx];
     }
 #pragma unroll
     for (int ww = 0; ww < 4; ww++) s_wc[ww][t] = 0;
@@ -255,7 +256,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint32_t *__restrict_
         const uint32_t d = (k >> shift) & 255u;
         const uint32_t o = s_glob[d] + (i - s_loc[d]);
         if (o < n) {
-            kout[o] = k;
+            if (pass + 1 < passes || !(flags & SORT_VALS_ONLY)) kout[o] = k;
             vout[o] = s_val[i];
         }
     }
@@ -275,7 +276,7 @@ int sort_spin_limit()
 template <int ITEMS>
 hipError_t sort_run(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
                     int64_t seg_len, const int4 *segtab, bool zeroed, bool counted, uint32_t *seg_kept,
-                    hipStream_t st)
+                    int flags, hipStream_t st)
 {
     constexpr uint32_t TILEN = BLOCK * ITEMS;
     const uint32_t ntiles = (n + TILEN - 1) / TILEN;
@@ -300,7 +301,7 @@ hipError_t sort_run(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t 
     for (int p = 0; p < passes; p++) {
         hipLaunchKernelGGL(k_sort_pass<ITEMS>, dim3(ntiles), dim3(BLOCK), 0, st, keys[cur].as<uint32_t>(),
                            vals[cur].as<uint32_t>(), keys[cur ^ 1].as<uint32_t>(), vals[cur ^ 1].as<uint32_t>(), n, p,
-                           passes, sm, hist, status + (size_t)p * ntiles * 256, seg_kept, err, spin_max);
+                           passes, sm, flags, hist, status + (size_t)p * ntiles * 256, seg_kept, err, spin_max);
         cur ^= 1;
     }
     return hipGetLastError();
@@ -329,13 +330,14 @@ size_t sort_ws_bytes(uint32_t n, int bits, int nseg)
 
 hipError_t sort_pairs_u32(DevBuf *keys, DevBuf *vals, DevBuf &wsb, int &cur, uint32_t n, int bits, int nseg,
                           int64_t seg_len, const int4 *segtab, hipStream_t st, bool zeroed, bool counted,
-                          uint32_t *seg_kept)
+                          uint32_t *seg_kept, int flags)
 {
     if (n == 0 || bits <= 0) return hipSuccess;
     if (bits > 32 || nseg <= 0 || (counted && !zeroed)) return hipErrorInvalidValue;
     if (sort_items_for(n) == 4)
-        return sort_run<4>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, zeroed, counted, seg_kept, st);
-    return sort_run<16>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, zeroed, counted, seg_kept, st);
+        return sort_run<4>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, zeroed, counted, seg_kept, flags,
+                           st);
+    return sort_run<16>(keys, vals, wsb, cur, n, bits, nseg, seg_len, segtab, zeroed, counted, seg_kept, flags, st);
 }
 
 }  // namespace rxgs
