@@ -706,12 +706,14 @@ __global__ __launch_bounds__(BLOCK) void k_emit2(const float4 *__restrict__ sbox
 // One workgroup per view.  Per tile (one thread each): each live chunk's
 // count becomes the count of the view's earlier chunks (chunks read
 // BIN_SCAN_BATCH at a time, all in flight together) and the total is the
-// tile's list length.  Per live chunk: the index
-// of its first unit within the view (exclusive prefix, nlive + 1 words).
+// tile's list length.  Per live chunk: the index of its first group of
+// units (up to `group` units, one workgroup of k_bin_pairs) within the view
+// (exclusive prefix, nlive + 1 words).
 constexpr int BIN_SCAN_BATCH = 16;
 
 __global__ __launch_bounds__(BLOCK) void k_bin_scan(const uint32_t *__restrict__ hist, int passes, uint32_t limit,
-                                                    int cpv, int chunk, int tiles, const uint4 *__restrict__ binfo,
+                                                    int cpv, int chunk, int tiles, int group,
+                                                    const uint4 *__restrict__ binfo,
                                                     uint32_t *__restrict__ bcnt, uint32_t *__restrict__ btot,
                                                     uint32_t *__restrict__ blive, uint32_t *__restrict__ bunit)
 {
@@ -726,7 +728,8 @@ __global__ __launch_bounds__(BLOCK) void k_bin_scan(const uint32_t *__restrict__
     uint32_t ubase = 0;
     for (uint32_t j0 = 0; j0 < nlive; j0 += BLOCK) {   // uniform
         const uint32_t j = j0 + t;
-        const uint32_t n = j < nlive ? (binfo[(size_t)v * cpv + j].w + BIN_WIN - 1) / BIN_WIN : 0u;
+        const uint32_t n = j < nlive ? (binfo[(size_t)v * cpv + j].w + BIN_WIN * group - 1) / (BIN_WIN * group)
+                                     : 0u;
         uint32_t tot;
         const uint32_t ex = block_exclusive_scan(n, tot, s_w);
         if (j < nlive) wp[j] = ubase + ex;
@@ -761,19 +764,23 @@ __device__ __forceinline__ void bin_diff_row(int *s_d, int dw, int ty, int a0, i
     }
 }
 
-// One workgroup per unit.  The chunk's entries' first slots go to LDS; the
-// slots before the unit are counted per tile (difference counts of whole
-// entries, and of the first rows and columns of the entry the unit starts
-// in); the unit's entries leave their tile rectangles in LDS and mark where
-// they start in a bitmap of the unit's slots.  Each wave then takes a
-// contiguous part of the unit 64 slots at a time: a slot's entry is the
+// One workgroup per group of up to `group` consecutive units of one chunk
+// (heavy chunks, the nearest entries of a view, spread over several; groups
+// of one unit when there are few chunks, so heavy chunks spread widely).  The
+// chunk's entries' first slots go to LDS; the slots before the group are
+// counted per tile (difference counts of whole entries, and of the first rows
+// and columns of the entry the group starts in); the group's entries leave
+// their tile rectangles in LDS.  Per unit, the entries that start inside it
+// are marked in a bitmap of its slots, and each wave takes a contiguous part
+// of the unit 64 slots at a time: a slot's entry is the
 // number of marks up to it, its tile follows from its rank inside that
 // entry's rectangle; the wave ranks its slots by tile (match_key8 and a
 // per-wave count per tile in LDS), and the waves' counts give each wave its
-// start in every tile's list.
+// start in every tile's list; the unit's counts advance the starts for the
+// next unit.
 __global__ __launch_bounds__(BLOCK) void k_bin_pairs(const float4 *__restrict__ sbox,
                                                      const uint32_t *__restrict__ poff, int64_t Kp, DevGrid g,
-                                                     int cpv, int V, const uint32_t *__restrict__ uoff,
+                                                     int cpv, int V, int group, const uint32_t *__restrict__ uoff,
                                                      const uint4 *__restrict__ binfo,
                                                      const uint32_t *__restrict__ bcnt,
                                                      const uint32_t *__restrict__ btot,
@@ -783,15 +790,15 @@ __global__ __launch_bounds__(BLOCK) void k_bin_pairs(const float4 *__restrict__ 
                                                      const uint32_t *__restrict__ pcount, uint32_t *__restrict__ pval)
 {
     __shared__ uint32_t s_off[BIN_CHUNK_MAX];     // first slot of each entry of the chunk (chunk-relative)
-    __shared__ uint32_t s_rect[BIN_CHUNK_MAX];    // per entry of the unit: ty0, a0, columns in range a, columns
+    __shared__ uint32_t s_rect[BIN_CHUNK_MAX];    // per entry of the units: ty0, a0, columns in range a, columns
     __shared__ uint32_t s_mark[BIN_WIN / 32];     // slots of the unit where an entry after the first starts
     __shared__ uint32_t s_mpre[BIN_WIN / 32];     // marks in the words before each word
     __shared__ int s_d[BIN_DIFF_WORDS];           // difference counts of the chunk's slots before the unit
     __shared__ uint32_t s_wc[4][256];             // per wave: its pairs per tile, then its start in each list
     __shared__ uint32_t s_w[4];
-    __shared__ uint32_t s_probe, s_j, s_ea, s_eb;
+    __shared__ uint32_t s_probe, s_j, s_ea, s_eb, s_ej;
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    // the view of this unit: the number of views after the first whose units
+    // the view of this group of units: the number of views after the first whose units
     // start at or before it (uoff is non-decreasing)
     uint32_t cnt = 0;
     for (int i = 1 + t; i < V; i += BLOCK) cnt += uoff[i] <= blockIdx.x ? 1u : 0u;
@@ -823,15 +830,18 @@ __global__ __launch_bounds__(BLOCK) void k_bin_pairs(const float4 *__restrict__ 
     const uint32_t j = s_j;
     const uint4 bi = binfo[(size_t)v * cpv + j];
     const uint32_t nvis = bi.y, pj = bi.w;
-    const uint32_t s0 = (u - wp[j]) * BIN_WIN, s1 = min(pj, s0 + (uint32_t)BIN_WIN);
+    // this workgroup's units of the chunk and their slots
+    const uint32_t nu = (pj + BIN_WIN - 1) / BIN_WIN;
+    const uint32_t ua = (u - wp[j]) * (uint32_t)group, ub = min(nu, ua + (uint32_t)group);
+    const uint32_t sa = ua * BIN_WIN, sz = min(pj, ub * BIN_WIN);
     const size_t row = (size_t)v * Kp + bi.x;
     for (uint32_t e = t; e < nvis; e += BLOCK) s_off[e] = poff[row + e] - bi.z;
     __syncthreads();
-    // the entries holding the unit's first and last slots
+    // the entries holding the first and the last of these slots
     for (uint32_t e = t; e < nvis; e += BLOCK) {
         const uint32_t o0 = s_off[e], o1 = e + 1 < nvis ? s_off[e + 1] : pj;
-        if (o0 <= s0 && s0 < o1) s_ea = e;
-        if (o0 <= s1 - 1 && s1 - 1 < o1) s_eb = e;
+        if (o0 <= sa && sa < o1) s_ea = e;
+        if (o0 <= sz - 1 && sz - 1 < o1) s_eb = e;
     }
     __syncthreads();
     const uint32_t ea = s_ea, eb = s_eb;
@@ -851,26 +861,23 @@ __global__ __launch_bounds__(BLOCK) void k_bin_pairs(const float4 *__restrict__ 
         (void)tile_rows(bx[q].y, bx[q].w, g.H, ty0, ty1);
         (void)tile_cols(bx[q].x, bx[q].z, g.W, g.tiles_x, a0, a1, b0, b1);
         const int na = a1 - a0 + 1, nc = na + (b1 - b0 + 1);
-        if (e < ea) {   // slots before the unit: all of this entry's
+        if (e < ea) {   // slots before the first unit: all of this entry's
             for (int ty = ty0; ty <= ty1; ty++) bin_diff_row(s_d, dw, ty, a0, a1, b0, b1);
             continue;
         }
         if (e == ea) {   // its first k slots: whole rows, then the first q columns of the next
-            const int k = (int)(s0 - s_off[e]);
+            const int k = (int)(sa - s_off[e]);
             const int full = k / nc, qq = k - full * nc;
             for (int ty = ty0; ty < ty0 + full; ty++) bin_diff_row(s_d, dw, ty, a0, a1, b0, b1);
             if (qq > 0) {
                 if (qq <= na) bin_diff_row(s_d, dw, ty0 + full, a0, a0 + qq - 1, 0, -1);
                 else bin_diff_row(s_d, dw, ty0 + full, a0, a1, b0, b0 + (qq - na) - 1);
             }
-        } else {
-            const uint32_t x = s_off[e] - s0;   // inside the unit
-            atomicOr(&s_mark[x >> 5], 1u << (x & 31));
         }
-        s_rect[e - ea] = (uint32_t)ty0 | ((uint32_t)a0 << 8) | ((uint32_t)na << 16) | ((uint32_t)nc << 24);
+        s_rect[e] = (uint32_t)ty0 | ((uint32_t)a0 << 8) | ((uint32_t)na << 16) | ((uint32_t)nc << 24);
     }
-    // start of each tile's run for this unit (the scan's barriers also order
-    // the tables above before their reads)
+    // start of each tile's run for the first unit (the scan's barriers also
+    // order the tables above before their reads)
     uint32_t start;
     {
         const uint32_t c = t < g.tiles ? btot[(size_t)v * 256 + t] : 0u;
@@ -883,6 +890,23 @@ __global__ __launch_bounds__(BLOCK) void k_bin_pairs(const float4 *__restrict__ 
             for (int x = 0; x <= tx; x++) before += s_d[ty * dw + x];
             start += bcnt[((size_t)v * cpv + j) * 256 + t] + (uint32_t)before;
         }
+    }
+    const uint32_t seg_end = pbase[v] + pcount[v];
+    for (uint32_t uk = ua; uk < ub; uk++) {   // uniform
+        const uint32_t s0 = uk * BIN_WIN, s1 = min(pj, s0 + (uint32_t)BIN_WIN);
+        // (the previous unit's scatter has read the starts)
+        __syncthreads();
+        if (t < BIN_WIN / 32) s_mark[t] = 0;
+#pragma unroll
+        for (int ww = 0; ww < 4; ww++) s_wc[ww][t] = 0;
+        __syncthreads();
+        // the entry holding slot s0, and a mark where each later entry starts
+        for (uint32_t e = ea + t; e <= eb; e += BLOCK) {
+            const uint32_t o0 = s_off[e], o1 = e + 1 < nvis ? s_off[e + 1] : pj;
+            if (o0 <= s0 && s0 < o1) s_ej = e;
+            if (s0 < o0 && o0 < s1) atomicOr(&s_mark[(o0 - s0) >> 5], 1u << ((o0 - s0) & 31));
+        }
+        __syncthreads();
         if (t < BIN_WIN / 32) {   // marks before each word: one wave's scan of the 64 word counts
             const uint32_t c1 = (uint32_t)__popc(s_mark[t]);
             uint32_t x = c1;
@@ -892,68 +916,68 @@ __global__ __launch_bounds__(BLOCK) void k_bin_pairs(const float4 *__restrict__ 
             }
             s_mpre[t] = x - c1;
         }
-    }
-    __syncthreads();
-    // wave w takes slots [wb, wb + per) of the unit, 64 per round
-    const uint32_t n = s1 - s0;
-    const uint32_t per = (n + 4 * 64 - 1) / (4 * 64) * 64;
-    const uint32_t wb = (uint32_t)w * per;
-    uint32_t key[BIN_WIN / 256], rk[BIN_WIN / 256], val[BIN_WIN / 256];
+        __syncthreads();
+        const uint32_t ej = s_ej;
+        // wave w takes slots [wb, wb + per) of the unit, 64 per round
+        const uint32_t n = s1 - s0;
+        const uint32_t per = (n + 4 * 64 - 1) / (4 * 64) * 64;
+        const uint32_t wb = (uint32_t)w * per;
+        uint32_t key[BIN_WIN / 256], rk[BIN_WIN / 256], val[BIN_WIN / 256];
 #pragma unroll
-    for (int r = 0; r < BIN_WIN / 256; r++) {
-        key[r] = 0xFFFFFFFFu;
-        rk[r] = 0;
-        val[r] = 0;
-        if ((uint32_t)r * 64 >= per) continue;   // uniform
-        const uint32_t i = wb + (uint32_t)r * 64 + lane;
-        const bool valid = i < n;
-        uint32_t d = 0;
-        if (valid) {
-            // entry: ea plus the marks at or before slot i
-            const uint32_t wd = i >> 5;
-            const uint32_t el = s_mpre[wd] + (uint32_t)__popc(s_mark[wd] & ((2u << (i & 31)) - 1u));
-            const uint32_t rc = s_rect[el];
-            const uint32_t e = ea + el;
-            const int nc = (int)(rc >> 24), na = (int)((rc >> 16) & 255u);
-            const int kk = (int)(s0 + i - s_off[e]);
-            // kk / nc through the reciprocal (exact after the correction: kk < 2^24)
-            int rw = (int)((float)kk * __builtin_amdgcn_rcpf((float)nc));
-            int cc = kk - rw * nc;
-            if (cc < 0) {
-                rw--;
-                cc += nc;
-            } else if (cc >= nc) {
-                rw++;
-                cc -= nc;
+        for (int r = 0; r < BIN_WIN / 256; r++) {
+            key[r] = 0xFFFFFFFFu;
+            rk[r] = 0;
+            val[r] = 0;
+            if ((uint32_t)r * 64 >= per) continue;   // uniform
+            const uint32_t i = wb + (uint32_t)r * 64 + lane;
+            const bool valid = i < n;
+            uint32_t d = 0;
+            if (valid) {
+                // entry: the one holding s0 plus the marks at or before slot i
+                const uint32_t wd = i >> 5;
+                const uint32_t e = ej + s_mpre[wd] + (uint32_t)__popc(s_mark[wd] & ((2u << (i & 31)) - 1u));
+                const uint32_t rc = s_rect[e];
+                const int nc = (int)(rc >> 24), na = (int)((rc >> 16) & 255u);
+                const int kk = (int)(s0 + i - s_off[e]);
+                // kk / nc through the reciprocal (exact after the correction: kk < 2^24)
+                int rw = (int)((float)kk * __builtin_amdgcn_rcpf((float)nc));
+                int cc = kk - rw * nc;
+                if (cc < 0) {
+                    rw--;
+                    cc += nc;
+                } else if (cc >= nc) {
+                    rw++;
+                    cc -= nc;
+                }
+                const int ty = (int)(rc & 255u) + rw;
+                const int tx = cc < na ? (int)((rc >> 8) & 255u) + cc : cc - na;   // the second run starts at column 0
+                d = (uint32_t)(ty * g.tiles_x + tx);
+                key[r] = d;
+                val[r] = (uint32_t)(row + e);
             }
-            const int ty = (int)(rc & 255u) + rw;
-            const int tx = cc < na ? (int)((rc >> 8) & 255u) + cc : cc - na;   // the second run starts at column 0
-            d = (uint32_t)(ty * g.tiles_x + tx);
-            key[r] = d;
-            val[r] = (uint32_t)(row + e);
+            const uint64_t m = match_key8(d, __ballot(valid));
+            const uint32_t below = (uint32_t)count_below(m);
+            const uint32_t before = valid ? s_wc[w][d] : 0u;
+            rk[r] = before + below;
+            if (valid && below == 0) s_wc[w][d] = before + (uint32_t)__popcll(m);
         }
-        const uint64_t m = match_key8(d, __ballot(valid));
-        const uint32_t below = (uint32_t)count_below(m);
-        const uint32_t before = valid ? s_wc[w][d] : 0u;
-        rk[r] = before + below;
-        if (valid && below == 0) s_wc[w][d] = before + (uint32_t)__popcll(m);
-    }
-    __syncthreads();
-    {
-        const uint32_t c0w = s_wc[0][t], c1w = s_wc[1][t], c2w = s_wc[2][t];
-        s_wc[0][t] = start;
-        s_wc[1][t] = start + c0w;
-        s_wc[2][t] = start + c0w + c1w;
-        s_wc[3][t] = start + c0w + c1w + c2w;
-    }
-    __syncthreads();
-    const uint32_t seg_end = pbase[v] + pcount[v];
+        __syncthreads();
+        {
+            const uint32_t c0w = s_wc[0][t], c1w = s_wc[1][t], c2w = s_wc[2][t], c3w = s_wc[3][t];
+            s_wc[0][t] = start;
+            s_wc[1][t] = start + c0w;
+            s_wc[2][t] = start + c0w + c1w;
+            s_wc[3][t] = start + c0w + c1w + c2w;
+            start += c0w + c1w + c2w + c3w;   // the next unit's start
+        }
+        __syncthreads();
 #pragma unroll
-    for (int r = 0; r < BIN_WIN / 256; r++)
-        if (key[r] != 0xFFFFFFFFu) {
-            const uint32_t o = s_wc[w][key[r]] + rk[r];
-            if (o < seg_end) pval[o] = val[r];
-        }
+        for (int r = 0; r < BIN_WIN / 256; r++)
+            if (key[r] != 0xFFFFFFFFu) {
+                const uint32_t o = s_wc[w][key[r]] + rk[r];
+                if (o < seg_end) pval[o] = val[r];
+            }
+    }
 }
 
 // One workgroup per view: the pair sort's digit totals of the view are its
@@ -2411,6 +2435,9 @@ void emit1_chunking(Workspace &ws)
     const bool wide = (size_t)ws.V * (size_t)(per_view / (4 * BLOCK)) >= 1024;
     ws.em_chunk = wide ? 4 * BLOCK : BLOCK;
     ws.em_cpv = (int)((per_view + ws.em_chunk - 1) / ws.em_chunk);
+    // placement units per workgroup of k_bin_pairs: four when there are many
+    // chunks (fewer set-ups), else one (more workgroups for the heavy chunks)
+    ws.bin_group = (size_t)ws.V * (size_t)ws.em_cpv >= 2048 ? BIN_GROUP : 1;
 }
 
 size_t bins_bytes(int V, int cpv)
@@ -2441,7 +2468,7 @@ hipError_t launch_bin_scan(Workspace &ws, const DevGrid &g, hipStream_t st)
 {
     const BinPtrs b = bin_ptrs(ws);
     hipLaunchKernelGGL(k_bin_scan, dim3((unsigned)ws.V), dim3(BLOCK), 0, st, ws.hist.as<uint32_t>(), 4, ws.limit,
-                       ws.em_cpv, ws.em_chunk, g.tiles, b.info, b.cnt, b.tot, b.live, b.unit);
+                       ws.em_cpv, ws.em_chunk, g.tiles, ws.bin_group, b.info, b.cnt, b.tot, b.live, b.unit);
     return hipGetLastError();
 }
 
@@ -2451,7 +2478,8 @@ hipError_t launch_bin_pairs(Workspace &ws, const DevGrid &g, hipStream_t st)
     if (ws.em_chunk > BIN_CHUNK_MAX) return hipErrorInvalidValue;
     const BinPtrs b = bin_ptrs(ws);
     hipLaunchKernelGGL(k_bin_pairs, dim3((unsigned)ws.n_emit_chunks), dim3(BLOCK), 0, st, ws.sbox.as<float4>(),
-                       ws.poff.as<uint32_t>(), ws.Kp, g, ws.em_cpv, ws.V, ws.d_chunk_off, b.info, b.cnt, b.tot,
+                       ws.poff.as<uint32_t>(), ws.Kp, g, ws.em_cpv, ws.V, ws.bin_group, ws.d_chunk_off, b.info, b.cnt,
+                       b.tot,
                        b.live, b.unit, ws.d_pbase, ws.d_pcount, ws.pval[0].as<uint32_t>());
     return hipGetLastError();
 }

@@ -1060,11 +1060,13 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     if (nfar >= (1ll << 31)) return fail(ctx, RXGS_E_INVALID, "too many MLP work items");
     ws.n_items_far = (int)nfar;
     // pair-emission chunks: EM2_CHUNK visible entries of one view each; or,
-    // with direct binning, the placement units of each view: at most one per
-    // BIN_WIN of its pairs plus one per chunk of the first emission
+    // with direct binning, the workgroups placing each view's pairs (groups of
+    // up to bin_group units of BIN_WIN pair slots of one chunk): at most one
+    // per BIN_WIN x bin_group of its pairs plus one per chunk of the first emission
     std::vector<uint32_t> chunk_off(V + 1, 0);
     for (int v = 0; v < V; v++) {
-        const uint64_t n = ws.direct_bins ? (ws.h_pcount[v] + (uint64_t)BIN_WIN - 1) / BIN_WIN + (uint64_t)ws.em_cpv
+        const uint64_t gs = (uint64_t)BIN_WIN * (uint64_t)ws.bin_group;
+        const uint64_t n = ws.direct_bins ? (ws.h_pcount[v] + gs - 1) / gs + (uint64_t)ws.em_cpv
                                           : (uint64_t)((ws.h_nvis[v] + EM2_CHUNK - 1) / EM2_CHUNK);
         if ((uint64_t)chunk_off[v] + n >= (1ull << 31)) return fail(ctx, RXGS_E_INVALID, "too many pair-emission chunks");
         chunk_off[v + 1] = chunk_off[v] + (uint32_t)n;
