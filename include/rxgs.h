@@ -76,7 +76,11 @@ enum { RXGS_MODE_TX = 0, RXGS_MODE_RX = 1 };
 #define RXGS_TILE 16
 
 /* Create a context on HIP device `device` for one angular grid.  Its device
- * buffers come from hipMalloc.  Errors: E_INVALID (grid), E_DEVICE. */
+ * buffers come from hipMalloc.  Grids of at most 255 tiles place each tile
+ * pair in its depth-ordered tile list directly; larger grids, or any grid
+ * when the environment variable RXGS_PAIR_SORT=1 is set at creation, emit the
+ * pairs in depth order and sort them stably by tile (the same lists).
+ * Errors: E_INVALID (grid), E_DEVICE. */
 rxgs_status rxgs_create(int device, const rxgs_grid *grid, rxgs_ctx **out);
 
 /* Caller-supplied device allocator (e.g. a framework's caching allocator).
