@@ -1125,15 +1125,18 @@ __global__ __launch_bounds__(BLOCK) void k_mlp_global(const float *__restrict__ 
 }
 
 // The tile ranges (one workgroup per view) and the MLP work
-// items (the workgroups after them) in one launch.
+// items (the workgroups after them) in one launch; also clears a buffer.
 __global__ __launch_bounds__(BLOCK) void k_ranges_items(const uint32_t *__restrict__ hist,
                                                         const uint32_t *__restrict__ pbase,
                                                         const uint32_t *__restrict__ pcount, int tiles,
                                                         uint2 *__restrict__ ranges, uint32_t *__restrict__ torder,
                                                         const uint32_t *__restrict__ item_off,
                                                         const int4 *__restrict__ vinfo, int V, int nitems,
-                                                        int4 *__restrict__ items)
+                                                        int4 *__restrict__ items, uint32_t *__restrict__ z,
+                                                        size_t nz)
 {
+    // clears z (the position-block marks of the radiance prefix path)
+    for (size_t k = (size_t)blockIdx.x * BLOCK + threadIdx.x; k < nz; k += (size_t)gridDim.x * BLOCK) z[k] = 0u;
     if ((int)blockIdx.x < V) {
         ranges_of_view(blockIdx.x, hist, pbase, pcount, tiles, ranges, torder);
         return;
@@ -2523,14 +2526,19 @@ hipError_t launch_ranges(Workspace &ws, const DevGrid &g, hipStream_t st)
         if (nbi > 0 && ws.items.cap < (size_t)ws.n_items * 16) return hipErrorInvalidValue;   // not allocated
         // (the list lengths: the direct binning's per-view totals, or the pair sort's digit totals)
         const uint32_t *lens = ws.direct_bins ? bin_ptrs(ws).tot : ws.hist_b.as<uint32_t>();
+        // the radiance prefix path's position-block marks are cleared here too
+        ws.live_cleared = ws.mpos != 0xFFFFFFFFu;
         hipLaunchKernelGGL(k_ranges_items, dim3((unsigned)ws.V + nbi), dim3(BLOCK), 0, st, lens,
                            ws.d_pbase, ws.d_pcount, g.tiles, ws.ranges.as<uint2>(), ws.torder.as<uint32_t>(),
-                           ws.d_item_off, ws.d_vinfo, ws.V, ws.n_items, ws.items.as<int4>());
+                           ws.d_item_off, ws.d_vinfo, ws.V, ws.n_items, ws.items.as<int4>(),
+                           ws.live_cleared ? ws.live.as<uint32_t>() : nullptr,
+                           ws.live_cleared ? (live_count_offset(ws) + 3) / 4 : (size_t)0);
         ws.tiles_ordered = true;
         ws.items_built = nbi > 0;
         return hipGetLastError();
     }
     ws.tiles_ordered = false;
+    ws.live_cleared = false;
     hipError_t e = launch_fill_u32(ws.ranges.as<uint32_t>(), 0u, nr * 2, st);
     if (e != hipSuccess || ws.Dpad == 0) return e;
     hipLaunchKernelGGL(k_ranges, dim3(nblk((size_t)ws.Dpad)), dim3(BLOCK), 0, st,

@@ -1178,7 +1178,7 @@ static rxgs_status render_pass(rxgs_ctx *ctx, int mode, int Q, const float *tx, 
     }
 
     // stage 3: compositing, then the per-receiver reductions
-    if (ws.mpos != 0xFFFFFFFFu)
+    if (ws.mpos != 0xFFFFFFFFu && !ws.live_cleared)
         HIPCHK(ctx, launch_fill_u32(ws.live.as<uint32_t>(), 0u, (live_count_offset(ws) + 3) / 4, st));
     STAGE(ctx, "blend_fwd", launch_blend_fwd(ws, C, save, st));
     if (ws.mpos != 0xFFFFFFFFu) {

@@ -241,6 +241,7 @@ struct Workspace {
     bool direct_bins = false;
     int em_cpv = 0, em_chunk = 0;   // chunks of the first emission per view, kept entries per chunk
     int bin_group = 1;              // placement units per workgroup of the direct binning
+    bool live_cleared = false;      // the ranges launch cleared the prefix path's position-block marks
     DevBuf nvis_d;    // V int
     // backward scratch
     DevBuf dS;        // N x Kp float2
