@@ -478,35 +478,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
         }
         npairs += nt[j];
     }
-    if (bcnt) {
-        // this chunk's pairs per tile: +1 / -1 at the ends of each covered
-        // column run, row by row, then a prefix along each row
-#pragma unroll
-        for (int j = 0; j < EM1_PER; j++) {
-            if (!nt[j]) continue;
-            int ty0, ty1, a0, a1, b0, b1;
-            (void)tile_rows(box[j].y, box[j].w, g.H, ty0, ty1);
-            (void)tile_cols(box[j].x, box[j].z, g.W, g.tiles_x, a0, a1, b0, b1);
-            for (int ty = ty0; ty <= ty1; ty++) {
-                int *d = s_d + ty * dw;
-                atomicAdd(d + a0, 1);
-                atomicAdd(d + a1 + 1, -1);
-                if (b1 >= b0) {
-                    atomicAdd(d + b0, 1);
-                    atomicAdd(d + b1 + 1, -1);
-                }
-            }
-        }
-    }
-    // (the scan's first barrier orders the counts above before the reads below)
     uint2 tot;
     const uint2 pre = block_exclusive_scan2<NW>(nvis, npairs, tot, s_w2);
-    if (bcnt && t < g.tiles) {
-        const int ty = t / g.tiles_x, tx = t - ty * g.tiles_x;
-        int c = 0;
-        for (int x = 0; x <= tx; x++) c += s_d[ty * dw + x];
-        bcnt[((size_t)v * cpv + chunk) * 256 + t] = (uint32_t)c;
-    }
     if (t < 64) {
         uint32_t evis = 0;
         uint64_t epairs = 0;
@@ -555,7 +528,34 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
             s_pbase = (uint32_t)epairs;
         }
     }
+    if (bcnt) {
+        // this chunk's pairs per tile (while wave 0 looks back): +1 / -1 at
+        // the ends of each covered column run, row by row, then a prefix
+        // along each row
+#pragma unroll
+        for (int j = 0; j < EM1_PER; j++) {
+            if (!nt[j]) continue;
+            int ty0, ty1, a0, a1, b0, b1;
+            (void)tile_rows(box[j].y, box[j].w, g.H, ty0, ty1);
+            (void)tile_cols(box[j].x, box[j].z, g.W, g.tiles_x, a0, a1, b0, b1);
+            for (int ty = ty0; ty <= ty1; ty++) {
+                int *d = s_d + ty * dw;
+                atomicAdd(d + a0, 1);
+                atomicAdd(d + a1 + 1, -1);
+                if (b1 >= b0) {
+                    atomicAdd(d + b0, 1);
+                    atomicAdd(d + b1 + 1, -1);
+                }
+            }
+        }
+    }
     __syncthreads();
+    if (bcnt && t < g.tiles) {
+        const int ty = t / g.tiles_x, tx = t - ty * g.tiles_x;
+        int c = 0;
+        for (int x = 0; x <= tx; x++) c += s_d[ty * dw + x];
+        bcnt[((size_t)v * cpv + chunk) * 256 + t] = (uint32_t)c;
+    }
     size_t q = (size_t)v * Kp + s_vbase + pre.x;
     uint32_t po = s_pbase + pre.y;
 #pragma unroll
