@@ -363,8 +363,11 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, size_t n)
 }
 
 // Emission, part 1 (after the depth sort): the exact projection of every kept
-// entry in depth order.  The workgroup of index i takes chunk i of its view
-// (NT x PER sorted entries, PER consecutive ones per thread; 1024 when there
+// entry in depth order.  Workgroups take the views' chunks chunk by chunk
+// (workgroup i: chunk i / V of view i mod V, so that the workgroups resident
+// together hold the first chunks of many views, and a later chunk's
+// look-back mostly finds its predecessors done), each of NT x PER sorted
+// entries (PER consecutive ones per thread; 1024 when there
 // are many chunks, which amortises each chunk's look-back, 256 for small
 // launches, which keeps the chain of chunks short); it loads its entries'
 // Gaussian indices before it knows how many the sort kept (the depth sort's
@@ -432,8 +435,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
     __shared__ int s_d[BIN_DIFF_WORDS];
     constexpr int EM1_CHUNK = NT * EM1_PER;
     const int t = threadIdx.x;
-    const int v = (int)(blockIdx.x / (unsigned)cpv);
-    const uint32_t chunk = blockIdx.x - (uint32_t)v * (uint32_t)cpv;
+    const uint32_t nviews = gridDim.x / (unsigned)cpv;
+    const uint32_t chunk = blockIdx.x / nviews;
+    const int v = (int)(blockIdx.x - chunk * nviews);
     const int dw = g.tiles_x + 1;   // row stride of the per-tile difference counts
     const int64_t s0 = (int64_t)chunk * EM1_CHUNK;
     const int64_t sb = s0 + (int64_t)t * EM1_PER;
