@@ -709,11 +709,11 @@ __global__ __launch_bounds__(BLOCK) void k_emit2(const float4 *__restrict__ sbox
 //
 // One workgroup per view.  Per tile (one thread each): each live chunk's
 // count becomes the count of the view's earlier chunks (chunks read
-// BIN_SCAN_BATCH at a time, all in flight together) and the total is the
-// tile's list length.  Per live chunk: the index of its first group of
+// BIN_SCAN_WIDE, then BIN_SCAN_BATCH at a time, all in flight together) and
+// the total is the tile's list length.  Per live chunk: the index of its first group of
 // units (up to `group` units, one workgroup of k_bin_pairs) within the view
 // (exclusive prefix, nlive + 1 words).
-constexpr int BIN_SCAN_BATCH = 16;
+constexpr int BIN_SCAN_BATCH = 16, BIN_SCAN_WIDE = 64;
 
 __global__ __launch_bounds__(BLOCK) void k_bin_scan(const uint32_t *__restrict__ hist, int passes, uint32_t limit,
                                                     int cpv, int chunk, int tiles, int group,
@@ -743,7 +743,19 @@ __global__ __launch_bounds__(BLOCK) void k_bin_scan(const uint32_t *__restrict__
     if (t >= tiles) return;
     uint32_t run = 0;
     uint32_t *col = bcnt + (size_t)v * cpv * 256 + t;
-    for (uint32_t j0 = 0; j0 < nlive; j0 += BIN_SCAN_BATCH) {
+    uint32_t j0 = 0;
+    // whole batches of BIN_SCAN_WIDE chunks (no per-chunk bound tests), then the rest
+    for (; j0 + BIN_SCAN_WIDE <= nlive; j0 += BIN_SCAN_WIDE) {
+        uint32_t c[BIN_SCAN_WIDE];
+#pragma unroll
+        for (int q = 0; q < BIN_SCAN_WIDE; q++) c[q] = col[(size_t)(j0 + q) * 256];
+#pragma unroll
+        for (int q = 0; q < BIN_SCAN_WIDE; q++) {
+            col[(size_t)(j0 + q) * 256] = run;
+            run += c[q];
+        }
+    }
+    for (; j0 < nlive; j0 += BIN_SCAN_BATCH) {
         uint32_t c[BIN_SCAN_BATCH];
 #pragma unroll
         for (int q = 0; q < BIN_SCAN_BATCH; q++) c[q] = j0 + q < nlive ? col[(size_t)(j0 + q) * 256] : 0u;
