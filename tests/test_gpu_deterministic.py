@@ -5,8 +5,8 @@ FP64 oracle's reverse mode within 1e-4 (per tensor, max error over max) and
 the float-atomic backward within 1e-5; the accumulating form adds.  Cases:
 direct radiance in both view modes, the training step's MLP subset, a TX view
 of 20 receivers (blocks of 4 receivers, two receiver groups per work item),
-several transmitters, and a grid of more than 255 tiles (two-pass pair sort:
-the emission order is kept aside)."""
+several transmitters, and a grid of more than 255 tiles (pairs sorted by
+tile in two passes instead of placed directly)."""
 import math
 
 import numpy as np
@@ -96,9 +96,11 @@ def test_deterministic_many_receivers_and_transmitters():
 
 
 def test_deterministic_two_pass_pair_sort():
-    """A 4 deg x 1 deg grid of 23 x 45 = 1035 tiles: the pair sort takes two
-    passes and overwrites the emission order, which the deterministic
-    forward keeps aside."""
+    """A 4 deg x 1 deg grid of 23 x 45 = 1035 tiles: the pairs are emitted
+    and sorted by tile in two passes (grids over 255 tiles), and the
+    deterministic backward's partials sit at the pairs' emission slots, which
+    it derives from each entry's first slot and the tile's rank in its
+    rectangle, whatever order the sort left."""
     grid = S.Grid(90, 720, 0.0, math.pi / 180)
     wl = S.make_workload("c1", K=800, N=2, grid=grid)
     rng = np.random.default_rng(24)
