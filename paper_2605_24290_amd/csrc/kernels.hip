@@ -238,54 +238,71 @@ __device__ __forceinline__ bool maybe_on_grid(float dxf, float dyf, float dzf, f
     return !(vv + R < -0.01f || vv - R > (float)(g.H - 1) + 0.01f);
 }
 
-// Depth keys of one view's tile of PER x BLOCK Gaussians (PER per thread,
-// strided so that loads and stores are coalesced), with the culls of
-// k_project, and the tile's contribution to the depth sort's digit totals:
-// per-wave LDS counts of all four 8-bit digits of the kept keys, summed and
-// added to the view's totals with one atomic per nonzero count (the values,
-// the Gaussian indices, are not written: the sort's first pass takes each
-// key's index in its view's segment).  Many views:
-// tiles of 2048 (fewer atomics); few: tiles of 256 (enough workgroups).
-template <int PER>
+// Depth keys of VPW views' tile of PER x BLOCK Gaussians (PER per thread,
+// strided so that loads and stores are coalesced; each Gaussian's terms are
+// read once for the VPW views), with the culls of k_project, and the tile's
+// contribution to the depth sort's digit totals: LDS counts of all four 8-bit
+// digits of the kept keys per view, added to the view's totals with one
+// atomic per nonzero count (the values, the Gaussian indices, are not
+// written: the sort's first pass takes each key's index in its view's
+// segment).  Many views: tiles of 2048 (fewer atomics), four views per
+// workgroup for large scenes (whose per-Gaussian terms do not stay in L2);
+// few views: tiles of 256 (enough workgroups).
+template <int PER, int VPW>
 __global__ __launch_bounds__(BLOCK) void k_keys(const GaussGeoPacked *__restrict__ gg,
                                                 const float *__restrict__ qcull, int64_t K, int64_t Kp,
-                                                const float *__restrict__ centres, DevGrid g,
+                                                const float *__restrict__ centres, DevGrid g, int V,
                                                 uint32_t *__restrict__ skey, uint32_t *__restrict__ hist)
 {
     constexpr int KEY_TILE = PER * BLOCK;
-    __shared__ uint32_t h[4][4][256];   // [digit position][wave][digit]
-    const int t = threadIdx.x, w = t >> 6;
+    __shared__ uint32_t h[VPW][4][256];   // [view][digit position][digit]
+    const int t = threadIdx.x;
     const int64_t tiles = Kp / KEY_TILE;
-    const int v = (int)(blockIdx.x / (uint64_t)tiles);
-    const int64_t k0 = (int64_t)(blockIdx.x - (uint64_t)v * (uint64_t)tiles) * KEY_TILE;
+    const int vg = (int)(blockIdx.x / (uint64_t)tiles);
+    const int64_t k0 = (int64_t)(blockIdx.x - (uint64_t)vg * (uint64_t)tiles) * KEY_TILE;
+    const int v0 = vg * VPW;
 #pragma unroll
-    for (int p = 0; p < 4; p++)
+    for (int vv = 0; vv < VPW; vv++)
 #pragma unroll
-        for (int ww = 0; ww < 4; ww++) h[p][ww][t] = 0;
-    const float cx = centres[3 * v], cy = centres[3 * v + 1], cz = centres[3 * v + 2];
+        for (int p = 0; p < 4; p++) h[vv][p][t] = 0;
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < PER; r++) {
         const int64_t k = k0 + r * BLOCK + t;
-        uint32_t key = 0xFFFFFFFFu;
+        float4 po = make_float4(0.f, 0.f, 0.f, 0.f);
+        float qc = 0.f;
         if (k < K) {
-            const float4 po = *reinterpret_cast<const float4 *>(gg + k);
-            const float qc = qcull[k];
-            const float dxf = __fsub_rn(po.x, cx), dyf = __fsub_rn(po.y, cy), dzf = __fsub_rn(po.z, cz);
-            const float kf = depth_key(dxf, dyf, dzf);
-            if (!(kf < NEAR2) && po.w >= ALPHA_MIN && maybe_on_grid(dxf, dyf, dzf, kf, qc, g))
-                key = __float_as_uint(kf);
+            po = *reinterpret_cast<const float4 *>(gg + k);
+            qc = qcull[k];
         }
-        skey[(size_t)v * Kp + k] = key;   // (its value, k, is the sort's index in the view's segment)
-        if (key != 0xFFFFFFFFu)
 #pragma unroll
-            for (int p = 0; p < 4; p++) atomicAdd(&h[p][w][(key >> (8 * p)) & 255u], 1u);
+        for (int vv = 0; vv < VPW; vv++) {
+            const int v = v0 + vv;
+            if (v >= V) break;
+            uint32_t key = 0xFFFFFFFFu;
+            if (k < K) {
+                const float cx = centres[3 * v], cy = centres[3 * v + 1], cz = centres[3 * v + 2];
+                const float dxf = __fsub_rn(po.x, cx), dyf = __fsub_rn(po.y, cy), dzf = __fsub_rn(po.z, cz);
+                const float kf = depth_key(dxf, dyf, dzf);
+                if (!(kf < NEAR2) && po.w >= ALPHA_MIN && maybe_on_grid(dxf, dyf, dzf, kf, qc, g))
+                    key = __float_as_uint(kf);
+            }
+            skey[(size_t)v * Kp + k] = key;
+            if (key != 0xFFFFFFFFu)
+#pragma unroll
+                for (int p = 0; p < 4; p++) atomicAdd(&h[vv][p][(key >> (8 * p)) & 255u], 1u);
+        }
     }
     __syncthreads();
 #pragma unroll
-    for (int p = 0; p < 4; p++) {
-        const uint32_t c = h[p][0][t] + h[p][1][t] + h[p][2][t] + h[p][3][t];
-        if (c) atomicAdd(&hist[((size_t)v * 4 + p) * 256 + t], c);
+    for (int vv = 0; vv < VPW; vv++) {
+        const int v = v0 + vv;
+        if (v >= V) break;
+#pragma unroll
+        for (int p = 0; p < 4; p++) {
+            const uint32_t c = h[vv][p][t];
+            if (c) atomicAdd(&hist[((size_t)v * 4 + p) * 256 + t], c);
+        }
     }
 }
 
@@ -2413,6 +2430,9 @@ hipError_t launch_project_exports(Workspace &ws, hipStream_t st)
     return hipGetLastError();
 }
 
+// scenes from this many (padded) Gaussians take four views per key workgroup
+constexpr int64_t KEYS_BIG_SCENE = 1 << 18;
+
 hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t Kp, const DevGrid &g,
                           Workspace &ws, size_t counter_words, size_t sort_words, hipStream_t st)
 {
@@ -2424,10 +2444,12 @@ hipError_t launch_project(const Scene &sc, const float *centres, int V, int64_t 
                        ws.hist.as<uint32_t>(), sort_words);
     if (V == 0 || Kp == 0) return hipGetLastError();
     const bool wide = (uint64_t)V * (uint64_t)(Kp / (8 * BLOCK)) >= 1024;
-    const int per = wide ? 8 : 1;
-    hipLaunchKernelGGL(wide ? k_keys<8> : k_keys<1>, dim3((unsigned)((uint64_t)V * (uint64_t)(Kp / (per * BLOCK)))),
+    const bool big = wide && V >= 4 && Kp >= KEYS_BIG_SCENE;
+    const int per = wide ? 8 : 1, vpw = big ? 4 : 1;
+    auto kern = big ? k_keys<8, 4> : wide ? k_keys<8, 1> : k_keys<1, 1>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)((uint64_t)((V + vpw - 1) / vpw) * (uint64_t)(Kp / (per * BLOCK)))),
                        dim3(BLOCK), 0, st, ws.ggeo.as<GaussGeoPacked>(), ws.qcull.as<float>(), sc.K, Kp, centres, g,
-                       ws.skey[0].as<uint32_t>(), ws.hist.as<uint32_t>());
+                       V, ws.skey[0].as<uint32_t>(), ws.hist.as<uint32_t>());
     return hipGetLastError();
 }
 
@@ -2454,7 +2476,7 @@ void emit1_chunking(Workspace &ws)
     const bool wide = (size_t)ws.V * (size_t)(per_view / (4 * BLOCK)) >= 1024;
     ws.em_chunk = wide ? 4 * BLOCK : BLOCK;
     ws.em_cpv = (int)((per_view + ws.em_chunk - 1) / ws.em_chunk);
-    // placement units per workgroup of k_bin_pairs: four when there are many
+    // placement units per workgroup of k_bin_pairs: BIN_GROUP when there are many
     // chunks (fewer set-ups), else one (more workgroups for the heavy chunks)
     ws.bin_group = (size_t)ws.V * (size_t)ws.em_cpv >= 2048 ? BIN_GROUP : 1;
 }

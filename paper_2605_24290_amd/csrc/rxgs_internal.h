@@ -41,7 +41,7 @@ constexpr int SORT_VALS_INDEX = 1;       // sort flag: a key's value is its inde
 constexpr int SORT_VALS_ONLY = 2;        // sort flag: the sorted keys are not needed (last pass writes values only)
 constexpr int BIN_WIN = 2048;            // pair slots per placement unit of the direct binning
 constexpr int BIN_CHUNK_MAX = 1024;      // most entries of a chunk of the first emission
-constexpr int BIN_GROUP = 4;             // placement units of one chunk per workgroup (renders with many chunks)
+constexpr int BIN_GROUP = 2;             // placement units of one chunk per workgroup (renders with many chunks)
 
 // Method constants (Alg. 1 compositing and the readings of its unstated values).
 constexpr float ALPHA_MIN = 1.0f / 255.0f;   // skip threshold on the blend weight
