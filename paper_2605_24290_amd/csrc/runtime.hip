@@ -132,6 +132,16 @@ bool ensure_pinned(Workspace &ws, size_t bytes)
     return true;
 }
 
+// Size (bytes of the 2-D record gradients) above which the backward clears
+// its per-position accumulators at visible positions only (256 MiB);
+// RXGS_ZERO_VISIBLE_MIN overrides it (0: always), so that tests can take
+// that path on small scenes.
+size_t zero_visible_min()
+{
+    const char *e = std::getenv("RXGS_ZERO_VISIBLE_MIN");
+    return (e && e[0]) ? (size_t)std::strtoull(e, nullptr, 10) : ((size_t)256 << 20);
+}
+
 // every device buffer of a workspace released (carved ones only forgotten)
 void release_buffers(Workspace &ws)
 {
@@ -1675,7 +1685,7 @@ extern "C" rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *sav
     WGROW(ctx, ws, ws.live, VK / MLP_PAIRS + 4);
     // dL/ds and the 2-D record gradients are written and read at visible
     // positions only; when they are large, only those are cleared
-    const bool rows = VK * 32 > ((size_t)256 << 20) && ws.N <= 65535 && ws.V <= 65535;
+    const bool rows = VK * 32 > zero_visible_min() && ws.N <= 65535 && ws.V <= 65535;
     if (rows) {
         const unsigned long long *cnt = ws.counters.as<unsigned long long>();
         HIPCHK(ctx, launch_zero_visible(ws.dS.as<uint32_t>(), ws.Kp, 2, cnt, ws.d_rxview, ws.N, st));

@@ -128,6 +128,41 @@ def test_backward_radiance_prefix_far_entries(mode):
     _compare(gg, go, FIELDS_MLP)
 
 
+@pytest.mark.parametrize("mode", ["tx", "rx"])
+def test_backward_visible_only_clearing_two_backwards(mode, monkeypatch):
+    """Large backwards clear their per-(view or receiver, position) gradient
+    accumulators at visible positions only (RXGS_ZERO_VISIBLE_MIN=0 takes that
+    path here).  Two backwards with different dC on one saved state, with
+    several receivers per TX view (rows map to views through the receiver
+    table): the second must match the oracle's reverse mode for its own dC,
+    so nothing of the first may survive in the accumulators."""
+    import torch
+    from paper_2605_24290_amd import rxgs
+    monkeypatch.setenv("RXGS_ZERO_VISIBLE_MIN", "0")
+    grid = S.Grid(45, 90, -math.pi / 2, math.pi / 45)
+    wl = S.make_workload("c1", K=800, N=6, Q=2, grid=grid)
+    rx_off = [0, 4, 6] if mode == "tx" else None
+    r = renderer_for(wl)
+    saved = rxgs.Saved(r)
+    C, P, _ = r.render(wl.rx, tx=wl.tx, rx_off=rx_off, mode=mode, saved=saved)
+    rng = np.random.default_rng(41)
+    dC1 = rng.normal(size=(6, 2, grid.H, grid.W)).astype(np.float32)
+    dC2 = rng.normal(size=(6, 2, grid.H, grid.W)).astype(np.float32)
+    r.backward(saved, C, torch.as_tensor(dC1, device=C.device))
+    g = r.backward(saved, C, torch.as_tensor(dC2, device=C.device))
+    torch.cuda.synchronize()
+    gg = {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
+    saved.close()
+    r.close()
+    if mode == "tx":
+        cen = wl.tx.astype(np.float64)
+        rv = np.array([0, 0, 0, 0, 1, 1], dtype=np.int32)
+    else:
+        cen, rv = O.views_for(mode, wl.tx, wl.rx)
+    go = O.backward(wl.scene, wl.grid, cen, wl.rx, rv, dC2, None, mlp=wl.mlp)
+    _compare(gg, go, FIELDS_MLP)
+
+
 def test_gpu_gradient_matches_fp64_central_differences():
     """GPU gradient of L = sum(dC * C) against FP64 central differences (step
     1e-6) of the oracle's forward on exactly 64 random parameters of the
