@@ -4,17 +4,20 @@
 // index added to the sort key):
 //   k_gauss_prep   stage 1: view-independent projection terms of every
 //                  Gaussian (covariance, opacity, cut-off).
-//   k_project      stage 1: per (view, Gaussian) FP32 depth key with the
-//                  near, opacity and conservative elevation culls.  [HBM]
+//   k_keys         stage 1: per (view, Gaussian) FP32 depth key with the
+//                  near, opacity and conservative elevation culls, and the
+//                  depth sort's digit totals.                       [HBM]
 //   radix sort     stage 1: per-view stable sort of the depth keys (one
 //                  segment per view), 4 passes of 8 bits (sort.hip). [HBM]
 //   k_emit1        stage 1: exact FP64 projection of the kept entries in
 //                  depth order; visible ones compacted into blend
-//                  records, boxes and pair offsets.                 [ALU]
-//   k_emit2        one (local tile, sorted position) pair per covered tile,
-//                  emitted in depth order into the view's segment.  [HBM]
-//   radix sort     stable 8-bit sort of each view's pairs by tile, so each
-//                  tile's list stays in depth order.                [HBM]
+//                  records, boxes and pair offsets; per chunk its pairs
+//                  per tile.                                        [ALU]
+//   k_bin_scan,    grids of at most 255 tiles: each chunk's start in every
+//   k_bin_pairs    tile list, then each (tile, sorted position) pair placed
+//                  directly in its tile list, in depth order.       [ALU]
+//   k_emit2 and    larger grids: the pairs emitted in depth order into the
+//   radix sort     view's segment, then stably sorted by tile.      [HBM]
 //   k_ranges_items [start, end) of each tile's list (and the MLP work items).
 //   k_mlp_*        stage 2: receiver term and Gaussian term of the MLP's first
 //                  layer, then the per-(receiver, Gaussian) layers on split
@@ -598,10 +601,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
     if (binfo && t == 0) binfo[(size_t)v * cpv + chunk] = make_uint4(s_vbase, tot.x, s_pbase, tot.y);
 }
 
-// Emission, part 2 (after the counts are known): one (local tile id, sorted
-// position) pair per covered tile of every visible entry, in depth order,
-// into the view's segment of the pair arrays (segments start at multiples of
-// 4096 so the pair sort can treat each view on its own).  One workgroup per
+// Emission, part 2 for grids of more than BIN_MAX_TILES tiles (after the
+// counts are known): one (local tile id, sorted position) pair per covered
+// tile of every visible entry, in depth order, into the view's segment of the
+// pair arrays (segments start at multiples of 4096 so the pair sort can treat
+// each view on its own).  One workgroup per
 // EM2_CHUNK visible entries of a view, taken 256 at a time; the first pair
 // slots come from part 1, and for each window of 2048 output slots an LDS
 // table records which entry owns each slot, so consecutive threads write
@@ -1013,11 +1017,11 @@ __global__ __launch_bounds__(BLOCK) void k_bin_pairs(const float4 *__restrict__ 
     }
 }
 
-// One workgroup per view: the pair sort's digit totals of the view are its
-// per-tile list lengths; their exclusive scan from the view's segment start
-// gives the lists' positions.  A view without pairs has empty lists (its
-// totals are not read: the sort, and the clearing of its scratch, is skipped
-// when a render has no pairs at all).  Also the view's tiles ordered by list
+// One workgroup per view: the view's per-tile list lengths (the direct
+// binning's totals, or the pair sort's digit totals); their exclusive scan
+// from the view's segment start gives the lists' positions.  A view without
+// pairs has empty lists (its totals are not read: they are not written when
+// a render has no pairs at all).  Also the view's tiles ordered by list
 // length, longest first (ties by tile index): the blend starts the longest
 // lists of every view first, which shortens the tail of its grid.
 __device__ __forceinline__ void ranges_of_view(int v, const uint32_t *__restrict__ hist,
