@@ -816,33 +816,59 @@ __device__ __forceinline__ d3 dsqrt3(d3 a)
     return {s, a.x * k, a.y * k, a.z * k};
 }
 
-// Gradients of one (view, Gaussian) record: mean (3), log-scales (3), raw
-// quaternion (4) and opacity logit (1), from the record's 2-D gradients gg
-// (u, v, and the parameters of the blend exponent), in FP64.
-struct ProjGrad {
-    double gp[3], gls[3], gq[4], glogit;
+// The projection backward in three parts, all in FP64: the terms of a
+// Gaussian that every view shares (gauss_terms), what one (view, Gaussian)
+// record passes back (view_grad), and the rest of the chain from the
+// covariance and opacity to the log-scales, raw quaternion and opacity logit
+// (cov_grad).  The last part is linear in its inputs for a fixed Gaussian, so
+// the views' terms are summed first and it runs once per Gaussian.
+// per-Gaussian terms read by every view: covariance upper triangle (00, 01,
+// 02, 11, 12, 22) and the mean
+struct __align__(16) ProjTerm {
+    double S[6];
+    float4 pos;
+};
+static_assert(sizeof(ProjTerm) == PROJ_TERM_BYTES, "ProjTerm layout");
+
+struct GaussTerms {
+    double R[3][3], s2[3], S[3][3];
+    double w, x, y, z, qn, o;
 };
 
-__device__ ProjGrad project_grad(const float *__restrict__ soa, int64_t K, int64_t k, const float *__restrict__ centres,
-                                 int64_t v, const DevGrid &g, const float *__restrict__ gg)
+// rotation of the normalised quaternion, squared scales, S = R diag(s2) R^T,
+// opacity
+__device__ GaussTerms gauss_terms(const float *__restrict__ soa, int64_t K, int64_t k)
 {
-    const double g_u = gg[0], g_v = gg[1], g_ca = gg[2], g_cb = gg[3], g_cc = gg[4], g_lo = gg[5];
-
-    const double px = soa[k], py = soa[K + k], pz = soa[2 * K + k];
-    double s2[3];
-    for (int a = 0; a < 3; a++) s2[a] = exp(2.0 * (double)soa[(3 + a) * K + k]);
+    GaussTerms t;
+    for (int a = 0; a < 3; a++) t.s2[a] = exp(2.0 * (double)soa[(3 + a) * K + k]);
     const double q0 = soa[6 * K + k], q1 = soa[7 * K + k], q2 = soa[8 * K + k], q3 = soa[9 * K + k];
-    const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
-    const double w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
-    double R[3][3];
-    R[0][0] = 1.0 - 2.0 * (y * y + z * z); R[0][1] = 2.0 * (x * y - w * z); R[0][2] = 2.0 * (x * z + w * y);
-    R[1][0] = 2.0 * (x * y + w * z); R[1][1] = 1.0 - 2.0 * (x * x + z * z); R[1][2] = 2.0 * (y * z - w * x);
-    R[2][0] = 2.0 * (x * z - w * y); R[2][1] = 2.0 * (y * z + w * x); R[2][2] = 1.0 - 2.0 * (x * x + y * y);
-    double S[3][3];
+    t.qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    const double w = q0 / t.qn, x = q1 / t.qn, y = q2 / t.qn, z = q3 / t.qn;
+    t.w = w, t.x = x, t.y = y, t.z = z;
+    t.R[0][0] = 1.0 - 2.0 * (y * y + z * z); t.R[0][1] = 2.0 * (x * y - w * z); t.R[0][2] = 2.0 * (x * z + w * y);
+    t.R[1][0] = 2.0 * (x * y + w * z); t.R[1][1] = 1.0 - 2.0 * (x * x + z * z); t.R[1][2] = 2.0 * (y * z - w * x);
+    t.R[2][0] = 2.0 * (x * z - w * y); t.R[2][1] = 2.0 * (y * z + w * x); t.R[2][2] = 1.0 - 2.0 * (x * x + y * y);
     for (int a = 0; a < 3; a++)
-        for (int b = 0; b < 3; b++) S[a][b] = R[a][0] * s2[0] * R[b][0] + R[a][1] * s2[1] * R[b][1] + R[a][2] * s2[2] * R[b][2];
-    const double o = 1.0 / (1.0 + exp(-(double)soa[10 * K + k]));
+        for (int b = 0; b < 3; b++)
+            t.S[a][b] = t.R[a][0] * t.s2[0] * t.R[b][0] + t.R[a][1] * t.s2[1] * t.R[b][1] +
+                        t.R[a][2] * t.s2[2] * t.R[b][2];
+    t.o = 1.0 / (1.0 + exp(-(double)soa[10 * K + k]));
+    return t;
+}
 
+// What one (view, Gaussian) record passes back, from its 2-D gradients gg (u,
+// v, and the parameters of the blend exponent): to the mean (gp), to the
+// covariance as Gs = dL/dS + (dL/dS)^T (entries 00, 01, 02, 11, 12, 22), and
+// to the exponent's log2-opacity term (glo).
+struct ViewGrad {
+    double gp[3], Gs[6], glo;
+};
+
+__device__ ViewGrad view_grad(double px, double py, double pz, const double (&S)[3][3],
+                              const float *__restrict__ centres, int64_t v, const DevGrid &g,
+                              const float *__restrict__ gg)
+{
+    const double g_u = gg[0], g_v = gg[1], g_ca = gg[2], g_cb = gg[3], g_cc = gg[4];
     const double cx = centres[3 * v], cy = centres[3 * v + 1], cz = centres[3 * v + 2];
     const d3 dx = D3(px - cx, 1, 0, 0), dy = D3(py - cy, 0, 1, 0), dz = D3(pz - cz, 0, 0, 1);
     d3 hh = dx * dx + dy * dy;
@@ -871,10 +897,9 @@ __device__ ProjGrad project_grad(const float *__restrict__ soa, int64_t K, int64
     const double Cc = mv[0].v * Smv[0] + mv[1].v * Smv[1] + mv[2].v * Smv[2] + DILATE;
     const double det = A * Cc - B * B, id2 = 1.0 / (det * det);
 
-    // record parameters (ca, cb, cc, lo) -> conic (a, b, c) and opacity
+    // record parameters (ca, cb, cc) -> conic (a, b, c)
     constexpr double L2E = 1.4426950408889634;
     const double g_a = -0.5 * L2E * g_ca, g_b = -L2E * g_cb, g_c = -0.5 * L2E * g_cc;
-    const double g_o = g_lo / (o * 0.69314718055994531);
     // conic = inverse of [[A, B], [B, Cc]]
     const double g_A = (-Cc * Cc * g_a + B * Cc * g_b - B * B * g_c) * id2;
     const double g_B = (2.0 * B * Cc * g_a - (A * Cc + B * B) * g_b + 2.0 * A * B * g_c) * id2;
@@ -885,33 +910,49 @@ __device__ ProjGrad project_grad(const float *__restrict__ soa, int64_t K, int64
         g_mu[a] = 2.0 * g_A * Smu[a] + g_B * Smv[a];
         g_mv[a] = 2.0 * g_C * Smv[a] + g_B * Smu[a];
     }
-    double gp[3] = {0, 0, 0};
+    ViewGrad out;
+    for (int a = 0; a < 3; a++) out.gp[a] = 0.0;
     for (int a = 0; a < 3; a++) {
         const double wu = g_mu[a], wvv = g_mv[a];
-        gp[0] += wu * mu[a].x + wvv * mv[a].x;
-        gp[1] += wu * mu[a].y + wvv * mv[a].y;
-        gp[2] += wu * mu[a].z + wvv * mv[a].z;
+        out.gp[0] += wu * mu[a].x + wvv * mv[a].x;
+        out.gp[1] += wu * mu[a].y + wvv * mv[a].y;
+        out.gp[2] += wu * mu[a].z + wvv * mv[a].z;
     }
-    for (int a = 0; a < 3; a++) gp[a] += g_u * mu[a].v + g_v * mv[a].v;
-    // covariance: gS = g_A mu mu^T + g_B mu mv^T + g_C mv mv^T
-    double gS[3][3];
+    for (int a = 0; a < 3; a++) out.gp[a] += g_u * mu[a].v + g_v * mv[a].v;
+    // dL/dS = g_A mu mu^T + g_B mu mv^T + g_C mv mv^T, plus its transpose
+    int e = 0;
     for (int a = 0; a < 3; a++)
-        for (int b = 0; b < 3; b++)
-            gS[a][b] = g_A * mu[a].v * mu[b].v + g_B * mu[a].v * mv[b].v + g_C * mv[a].v * mv[b].v;
-    // Sigma = R diag(s2) R^T
+        for (int b = a; b < 3; b++)
+            out.Gs[e++] = 2.0 * g_A * mu[a].v * mu[b].v + g_B * (mu[a].v * mv[b].v + mu[b].v * mv[a].v) +
+                          2.0 * g_C * mv[a].v * mv[b].v;
+    out.glo = gg[5];
+    return out;
+}
+
+struct CovGrad {
+    double gls[3], gq[4], glogit;
+};
+
+// from a Gaussian's (summed) Gs and glo: S = R diag(s2) R^T back to the
+// log-scales and the raw quaternion, the log2-opacity term back to the logit
+__device__ CovGrad cov_grad(const GaussTerms &t, const double (&G6)[6], double glo)
+{
+    const double Gs[3][3] = {{G6[0], G6[1], G6[2]}, {G6[1], G6[3], G6[4]}, {G6[2], G6[4], G6[5]}};
+    const double(&R)[3][3] = t.R;
+    const double w = t.w, x = t.x, y = t.y, z = t.z;
     double gR[3][3];
     for (int a = 0; a < 3; a++)
         for (int b = 0; b < 3; b++) {
             double acc = 0.0;
-            for (int c = 0; c < 3; c++) acc += (gS[a][c] + gS[c][a]) * R[c][b];
-            gR[a][b] = acc * s2[b];
+            for (int c = 0; c < 3; c++) acc += Gs[a][c] * R[c][b];
+            gR[a][b] = acc * t.s2[b];
         }
-    double gls_[3];
+    CovGrad out;
     for (int b = 0; b < 3; b++) {
         double acc = 0.0;
         for (int a = 0; a < 3; a++)
-            for (int c = 0; c < 3; c++) acc += R[a][b] * gS[a][c] * R[c][b];
-        gls_[b] = acc * 2.0 * s2[b];
+            for (int c = 0; c < 3; c++) acc += R[a][b] * Gs[a][c] * R[c][b];
+        out.gls[b] = acc * t.s2[b];   // d s2 / d log-scale = 2 s2; Gs holds dL/dS twice
     }
     // rotation from the normalised quaternion (w, x, y, z)
     const double gw = 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
@@ -922,16 +963,12 @@ __device__ ProjGrad project_grad(const float *__restrict__ soa, int64_t K, int64
     const double gz = 2.0 * (-2.0 * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.0 * z * gR[1][1] +
                              y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
     const double dotq = w * gw + x * gx + y * gy + z * gz;
-    ProjGrad out;
-    for (int a = 0; a < 3; a++) {
-        out.gp[a] = gp[a];
-        out.gls[a] = gls_[a];
-    }
-    out.gq[0] = (gw - w * dotq) / qn;
-    out.gq[1] = (gx - x * dotq) / qn;
-    out.gq[2] = (gy - y * dotq) / qn;
-    out.gq[3] = (gz - z * dotq) / qn;
-    out.glogit = g_o * o * (1.0 - o);
+    out.gq[0] = (gw - w * dotq) / t.qn;
+    out.gq[1] = (gx - x * dotq) / t.qn;
+    out.gq[2] = (gy - y * dotq) / t.qn;
+    out.gq[3] = (gz - z * dotq) / t.qn;
+    // log2 o = log2(sigmoid(logit)): d/dlogit = (1 - o) / ln 2
+    out.glogit = glo * (1.0 - t.o) / 0.69314718055994531;
     return out;
 }
 
@@ -940,12 +977,27 @@ __device__ __forceinline__ bool g2d_zero(const float *gg)
     return gg[0] == 0.f && gg[1] == 0.f && gg[2] == 0.f && gg[3] == 0.f && gg[4] == 0.f && gg[5] == 0.f;
 }
 
-// per (view, visible Gaussian); float atomics add the views' terms
+// per Gaussian: its mean and covariance (upper triangle), read by every view
+__global__ __launch_bounds__(BLOCK) void k_proj_terms(const float *__restrict__ soa, int64_t K,
+                                                      ProjTerm *__restrict__ pt)
+{
+    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= K) return;
+    const GaussTerms t = gauss_terms(soa, K, k);
+    ProjTerm p;
+    p.S[0] = t.S[0][0], p.S[1] = t.S[0][1], p.S[2] = t.S[0][2];
+    p.S[3] = t.S[1][1], p.S[4] = t.S[1][2], p.S[5] = t.S[2][2];
+    p.pos = make_float4(soa[k], soa[K + k], soa[2 * K + k], 0.f);
+    pt[k] = p;
+}
+
+// per (view, visible Gaussian); float atomics add the views' terms: mean
+// gradients to their output, Gs and glo per Gaussian (pacc, PACC_STRIDE
+// floats each) for k_project_fin
 __global__ __launch_bounds__(BLOCK) void k_project_bwd(
-    const float *__restrict__ soa, int64_t K, int64_t Kp, const float *__restrict__ centres, int V, DevGrid g,
+    const ProjTerm *__restrict__ pt, int64_t K, int64_t Kp, const float *__restrict__ centres, int V, DevGrid g,
     const uint32_t *__restrict__ order, const unsigned long long *__restrict__ counters,
-    const float *__restrict__ g2d, float *__restrict__ gmeans, float *__restrict__ gls, float *__restrict__ gq,
-    float *__restrict__ glogit)
+    const float *__restrict__ g2d, float *__restrict__ gmeans, float *__restrict__ pacc)
 {
     const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (p >= (int64_t)V * Kp) return;
@@ -954,14 +1006,37 @@ __global__ __launch_bounds__(BLOCK) void k_project_bwd(
     const float *gg = g2d + (size_t)p * 8;
     if (g2d_zero(gg)) return;
     const int64_t k = min((int64_t)order[p], K - 1);
-    const ProjGrad r = project_grad(soa, K, k, centres, v, g, gg);
+    const ProjTerm q = pt[k];
+    const double S[3][3] = {{q.S[0], q.S[1], q.S[2]}, {q.S[1], q.S[3], q.S[4]}, {q.S[2], q.S[4], q.S[5]}};
+    const ViewGrad r = view_grad(q.pos.x, q.pos.y, q.pos.z, S, centres, v, g, gg);
     if (gmeans)
         for (int a = 0; a < 3; a++) atomicAdd(&gmeans[3 * k + a], (float)r.gp[a]);
+    if (pacc) {
+        float *acc = pacc + (size_t)k * PACC_STRIDE;
+        for (int a = 0; a < 6; a++) atomicAdd(&acc[a], (float)r.Gs[a]);
+        atomicAdd(&acc[6], (float)r.glo);
+    }
+}
+
+// per Gaussian: the summed Gs and glo through the rest of the chain, added to
+// the outputs
+__global__ __launch_bounds__(BLOCK) void k_project_fin(const float *__restrict__ soa, int64_t K,
+                                                       const float *__restrict__ pacc, float *__restrict__ gls,
+                                                       float *__restrict__ gq, float *__restrict__ glogit)
+{
+    const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (k >= K) return;
+    const float *acc = pacc + (size_t)k * PACC_STRIDE;
+    const double G6[6] = {acc[0], acc[1], acc[2], acc[3], acc[4], acc[5]};
+    const double glo = acc[6];
+    if (G6[0] == 0.0 && G6[1] == 0.0 && G6[2] == 0.0 && G6[3] == 0.0 && G6[4] == 0.0 && G6[5] == 0.0 && glo == 0.0)
+        return;   // no view passed anything back
+    const CovGrad c = cov_grad(gauss_terms(soa, K, k), G6, glo);
     if (gls)
-        for (int a = 0; a < 3; a++) atomicAdd(&gls[3 * k + a], (float)r.gls[a]);
+        for (int a = 0; a < 3; a++) gls[3 * k + a] += (float)c.gls[a];
     if (gq)
-        for (int a = 0; a < 4; a++) atomicAdd(&gq[4 * k + a], (float)r.gq[a]);
-    if (glogit) atomicAdd(&glogit[k], (float)r.glogit);
+        for (int a = 0; a < 4; a++) gq[4 * k + a] += (float)c.gq[a];
+    if (glogit) glogit[k] += (float)c.glogit;
 }
 
 // ============================================================================
@@ -974,7 +1049,7 @@ __device__ __forceinline__ void det_store(float *out, double value, int accum)
     *out = accum ? (float)((double)*out + value) : (float)value;
 }
 
-// per Gaussian, the views in order (FP64 sums)
+// per Gaussian, the views in order (FP64 sums), then the rest of the chain
 __global__ __launch_bounds__(BLOCK) void k_det_project(
     const float *__restrict__ soa, int64_t K, int64_t Kp, const float *__restrict__ centres, int V, DevGrid g,
     const int *__restrict__ oinv, const float *__restrict__ g2d, float *__restrict__ gmeans,
@@ -982,27 +1057,27 @@ __global__ __launch_bounds__(BLOCK) void k_det_project(
 {
     const int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (k >= K) return;
-    ProjGrad acc{};
+    const GaussTerms t = gauss_terms(soa, K, k);
+    const double px = soa[k], py = soa[K + k], pz = soa[2 * K + k];
+    double gp[3] = {0.0, 0.0, 0.0}, G6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, glo = 0.0;
     for (int v = 0; v < V; v++) {
         const int s = oinv[(size_t)v * K + k];
         if (s < 0) continue;
         const float *gg = g2d + ((size_t)v * Kp + s) * 8;
         if (g2d_zero(gg)) continue;
-        const ProjGrad r = project_grad(soa, K, k, centres, v, g, gg);
-        for (int a = 0; a < 3; a++) {
-            acc.gp[a] += r.gp[a];
-            acc.gls[a] += r.gls[a];
-        }
-        for (int a = 0; a < 4; a++) acc.gq[a] += r.gq[a];
-        acc.glogit += r.glogit;
+        const ViewGrad r = view_grad(px, py, pz, t.S, centres, v, g, gg);
+        for (int a = 0; a < 3; a++) gp[a] += r.gp[a];
+        for (int a = 0; a < 6; a++) G6[a] += r.Gs[a];
+        glo += r.glo;
     }
+    const CovGrad c = cov_grad(t, G6, glo);
     if (gmeans)
-        for (int a = 0; a < 3; a++) det_store(&gmeans[3 * k + a], acc.gp[a], accum);
+        for (int a = 0; a < 3; a++) det_store(&gmeans[3 * k + a], gp[a], accum);
     if (gls)
-        for (int a = 0; a < 3; a++) det_store(&gls[3 * k + a], acc.gls[a], accum);
+        for (int a = 0; a < 3; a++) det_store(&gls[3 * k + a], c.gls[a], accum);
     if (gq)
-        for (int a = 0; a < 4; a++) det_store(&gq[4 * k + a], acc.gq[a], accum);
-    if (glogit) det_store(&glogit[k], acc.glogit, accum);
+        for (int a = 0; a < 4; a++) det_store(&gq[4 * k + a], c.gq[a], accum);
+    if (glogit) det_store(&glogit[k], c.glogit, accum);
 }
 
 // sorted position of every (view, Gaussian), -1 where not visible
@@ -1477,10 +1552,16 @@ hipError_t launch_project_bwd(const Scene &sc, Workspace &ws, const rxgs_grads &
 {
     const int64_t n = (int64_t)ws.V * ws.Kp;
     if (sc.K == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_project_bwd, dim3(nblk(n)), dim3(BLOCK), 0, st, sc.soa.as<float>(), sc.K, ws.Kp,
-                       ws.centres_p, ws.V, ws.g, ws.vorder.as<uint32_t>(),
-                       ws.counters.as<unsigned long long>(), ws.g2d.as<float>(), gr.means, gr.log_scales, gr.quats,
-                       gr.logits);
+    // the covariance and opacity part of the chain is wanted (pacc cleared beforehand)
+    const bool cov = gr.log_scales || gr.quats || gr.logits;
+    hipLaunchKernelGGL(k_proj_terms, dim3(nblk(sc.K)), dim3(BLOCK), 0, st, sc.soa.as<float>(), sc.K,
+                       ws.pterm.as<ProjTerm>());
+    hipLaunchKernelGGL(k_project_bwd, dim3(nblk(n)), dim3(BLOCK), 0, st, ws.pterm.as<ProjTerm>(), sc.K, ws.Kp,
+                       ws.centres_p, ws.V, ws.g, ws.vorder.as<uint32_t>(), ws.counters.as<unsigned long long>(),
+                       ws.g2d.as<float>(), gr.means, cov ? ws.pacc.as<float>() : nullptr);
+    if (cov)
+        hipLaunchKernelGGL(k_project_fin, dim3(nblk(sc.K)), dim3(BLOCK), 0, st, sc.soa.as<float>(), sc.K,
+                           ws.pacc.as<float>(), gr.log_scales, gr.quats, gr.logits);
     return hipGetLastError();
 }
 

@@ -154,7 +154,8 @@ void release_buffers(Workspace &ws)
                       &ws.dG,      &ws.mpart,   &ws.w1part,  &ws.mred,   &ws.live,   &ws.items_live, &ws.vflag,
                       &ws.items_far, &ws.frec, &ws.fcnt,  &ws.ftile,  &ws.hist_b, &ws.gfeat_tmp, &ws.gmlp_tmp,
                       &ws.rgam,    &ws.rab,     &ws.rloc,    &ws.gP,     &ws.dSP,
-                      &ws.oinv,    &ws.rank,    &ws.lcnt,    &ws.dLv,     &ws.dGp,    &ws.bins};
+                      &ws.oinv,    &ws.rank,    &ws.lcnt,    &ws.dLv,     &ws.dGp,    &ws.bins,
+                      &ws.pterm,   &ws.pacc};
     for (DevBuf *b : bufs) release(*b);
 }
 
@@ -1695,6 +1696,9 @@ extern "C" rxgs_status rxgs_render_backward(rxgs_ctx *ctx, const rxgs_saved *sav
         zr.add(ws.g2d.p, VK * 8);
     }
     zr.add(ws.live.p, (VK / MLP_PAIRS + 3) / 4);
+    WGROW(ctx, ws, ws.pterm, (size_t)K * PROJ_TERM_BYTES);
+    WGROW(ctx, ws, ws.pacc, (size_t)K * PACC_STRIDE * 4);
+    zr.add(ws.pacc.p, (size_t)K * PACC_STRIDE);
     if (ws.use_mlp) {
         WGROW(ctx, ws, ws.dL, (size_t)K * HID * 4);
         WGROW(ctx, ws, ws.dG, (size_t)ws.N * HID * 4);

@@ -254,6 +254,8 @@ struct Workspace {
     DevBuf gfeat_tmp; // K x 32 feature gradients before they are added (accumulating backward)
     DevBuf gmlp_tmp;  // MLP gradients before they are added (accumulating backward)
     DevBuf live;      // per (view, 32 sorted positions): composited (lazy forward) or some dL/ds nonzero (backward)
+    DevBuf pterm;     // K x PROJ_TERM_BYTES: per-Gaussian terms of the projection backward
+    DevBuf pacc;      // K x PACC_STRIDE floats: per-Gaussian sums of the projection backward
     DevBuf items_live;   // MLP work items of the live blocks (lazy forward)
     bool lazy = false;   // this render evaluates the pair MLP on live blocks only
     uint32_t limit = 0xFFFFFFFFu;   // depth-sorted entries emitted per view (the nearest)
@@ -416,6 +418,8 @@ hipError_t launch_amplitude(const float *C, float *amp, int N, size_t P, hipStre
 hipError_t launch_add_f32(float *out, const float *add, size_t n, hipStream_t st);
 hipError_t launch_rad_bwd(const Scene &sc, Workspace &ws, float *grad, hipStream_t st);
 hipError_t launch_mlp_bwd(const Scene &sc, const Mlp &m, Workspace &ws, float *gfeat, float *gmlp, hipStream_t st);
+constexpr int PROJ_TERM_BYTES = 64;   // covariance upper triangle (6 doubles) and the mean (float4)
+constexpr int PACC_STRIDE = 8;        // covariance terms (6), log2-opacity term, padding
 hipError_t launch_project_bwd(const Scene &sc, Workspace &ws, const rxgs_grads &gr, hipStream_t st);
 // deterministic backward (backward.hip)
 int det_block_rows(const Workspace &ws);
